@@ -1,0 +1,193 @@
+/*
+ * lv.h - C ABI of the MI355X (gfx950) Louvain local-moving library.
+ *
+ * Method: F. Li, Z. Du, D. A. Bader, "Designing Parallel Algorithms for
+ * Community Detection using Arachne" (arXiv 2507.06471): Louvain = local
+ * moving (Algorithm 2, gain of Equation 1) alternating with aggregation
+ * (Algorithm 3), and label propagation (Algorithm 1) as a second mode of the
+ * same neighbour-aggregation step.  Modularity as in Section II-C.
+ *
+ * Deterministic semantics implemented by every entry point:
+ *   - integer edge weights >= 1; a loop (v, v, w) counts twice in the weighted
+ *     degree (Section II-A), so it enters the method as A_vv = 2w;
+ *   - synchronous sweeps: every vertex decides against the previous sweep's
+ *     labels and community volumes;
+ *   - each vertex takes the best neighbouring community (ties to the smallest
+ *     id) by the exact integer score  M*W_i(C) - k_i*Sigma_tot(C)  (Louvain; the
+ *     gain of Equation 1 is 2*(score - stay)/M^2) or W_i(C) (LPA), and moves
+ *     only if it beats staying and lies in the sweep's direction: odd sweeps
+ *     allow only moves to smaller community ids, even sweeps only to larger;
+ *   - a level ends after two consecutive sweeps with no move (LPA: with at
+ *     most lpa_threshold moves) or after max_sweeps sweeps;
+ *   - communities are renumbered by their smallest member vertex id;
+ *   - a Louvain level is kept only if it raises modularity (Section III-B,
+ *     "until no further improvement"), at most max_levels levels.
+ * Every decision is integer arithmetic (int64 products of values < 2^31), so
+ * results do not depend on tuning, scheduling or batching.
+ *
+ * Conventions for all calls:
+ *   - every call returns an lv_status; out-parameters are written only on
+ *     LV_OK; the library never aborts or prints; lv_last_error() gives a
+ *     thread-local detail string for the last failure on the calling thread;
+ *   - the caller owns every buffer it passes; inputs need to live only for the
+ *     duration of the call; handles are library-owned until *_destroy;
+ *   - LV_MEM_HOST / LV_MEM_DEVICE says where a caller buffer lives; device
+ *     buffers must be hipMalloc'd memory of the current device;
+ *   - a graph handle is bound to one HIP stream and must be used by one host
+ *     thread at a time; calls are synchronous unless stated otherwise.
+ */
+#ifndef LV_H
+#define LV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum lv_status {
+    LV_OK = 0,
+    LV_E_ARG = 1,        /* null pointer, negative size, bad parameter value          */
+    LV_E_CSR = 2,        /* offsets not monotone / not ending at nnz, index out of
+                            range, or a row not strictly increasing                   */
+    LV_E_ASYMMETRIC = 3, /* entry (i,j,w) without a matching (j,i,w)                  */
+    LV_E_WEIGHT = 4,     /* a weight < 1                                              */
+    LV_E_OVERFLOW = 5,   /* total volume M = sum_i k_i >= 2^31, or nnz >= 2^31        */
+    LV_E_NOMEM = 6,      /* device allocation failed; the handle stays usable         */
+    LV_E_HIP = 7,        /* a HIP runtime call failed                                 */
+    LV_E_BUSY = 8,       /* server queue full                                         */
+    LV_E_TOO_LARGE = 9,  /* job exceeds the server's device-memory budget             */
+    LV_E_CANCELLED = 10, /* job cancelled before it ran                               */
+    LV_E_STATE = 11,     /* call not valid in the object's current state              */
+    LV_E_NOT_FOUND = 12  /* unknown ticket or level                                   */
+} lv_status;
+
+typedef enum lv_memkind { LV_MEM_HOST = 0, LV_MEM_DEVICE = 1 } lv_memkind;
+
+/* lv_graph_create_csr flags */
+#define LV_VALIDATE 1u /* check CSR shape, sortedness, symmetry and weights on the device */
+
+/* lv_params.flags */
+#define LV_TIMING 1u      /* record per-kernel HIP event times (see lv_level_info)          */
+#define LV_KEEP_GRAPHS 2u /* lv_louvain keeps every coarse graph for lv_result_level_graph */
+
+typedef struct lv_graph lv_graph;   /* device-resident CSR + workspace, library-owned */
+typedef struct lv_result lv_result; /* per-level labels and statistics, library-owned */
+
+/*
+ * Scheduling knobs.  They choose which kernel handles a vertex (by its number
+ * of CSR entries L) and the LDS table sizes; they never change results.
+ * Zero fields take the built-in defaults.
+ */
+typedef struct lv_tuning {
+    int32_t sub_max;   /* L <= sub_max: a sub-wave group per vertex (power of 2, 2..64)  */
+    int32_t wave_max;  /* L <= wave_max: one wavefront per vertex                          */
+    int32_t block_max; /* L <= block_max: one workgroup per vertex, LDS table              */
+                       /* L >  block_max: several workgroups per vertex, global table      */
+    int32_t hub_chunk; /* CSR entries per workgroup on the global-table path               */
+} lv_tuning;
+
+typedef struct lv_params {
+    int32_t max_sweeps;    /* sweeps per level, default 20 (Alg. 2 maxIteration)          */
+    int32_t max_levels;    /* accepted Louvain levels, default 32                         */
+    int64_t lpa_threshold; /* LPA stops after two sweeps with <= this many moves (Alg. 1) */
+    uint32_t flags;        /* LV_TIMING                                                    */
+    const lv_tuning* tuning; /* NULL = built-in defaults                                   */
+} lv_params;
+
+#define LV_KERNEL_SLOTS 12
+
+/* Per-level statistics; times are milliseconds from HIP events (LV_TIMING). */
+typedef struct lv_level_info {
+    int32_t n;          /* vertices of this level's graph                        */
+    int32_t n_next;     /* communities after renumbering                          */
+    int64_t nnz;        /* CSR entries of this level's graph                      */
+    int32_t sweeps;     /* sweeps run                                             */
+    int32_t accepted;   /* 1 if the level raised modularity and was kept          */
+    int64_t q_start;    /* Q_int of the singleton partition of this level         */
+    int64_t q_end;      /* Q_int of the level's partition (= singletons of next)  */
+    double move_ms;     /* summed duration of the move kernels (all sweeps)       */
+    double sweep_ms;    /* whole local-moving phase (moves + commits)             */
+    double renumber_ms;
+    double aggregate_ms;
+    int64_t move_launches; /* number of move-kernel launches                       */
+    int64_t move_bytes;    /* algorithmic bytes of the move kernels, all sweeps    */
+    /* Per move kernel (LV_TIMING): slot 2*(class-1) + (1 for the first sweep
+       of a level, where every community is a single vertex); classes 1..5 =
+       8-lane, 32-lane, wavefront, 256- and 512-thread workgroup tables, 6 =
+       global table (hubs, its two or three kernels together).  Bytes count each array element a kernel needs once:
+       indices (and weights) of its rows, and 20 bytes per vertex (vertex list,
+       row offset, label, degree, own community volume). */
+    double kern_ms[LV_KERNEL_SLOTS];
+    int64_t kern_launches[LV_KERNEL_SLOTS];
+    int64_t kern_bytes[LV_KERNEL_SLOTS];
+} lv_level_info;
+
+void lv_params_default(lv_params* p);
+const char* lv_status_str(lv_status s);
+const char* lv_last_error(void);
+
+/*
+ * Create a device-resident graph from a symmetric CSR (Section II-A graph
+ * model).  offsets int32[n+1] (offsets[0] = 0, non-decreasing, offsets[n] =
+ * nnz); indices int32[nnz] in [0,n), strictly increasing within each row;
+ * weights int32[nnz] >= 1, or NULL for unit weights; a diagonal entry is a
+ * loop.  All three arrays live in `kind` memory.  The library copies them;
+ * `stream` (a hipStream_t, NULL = a library-created stream) is used for all
+ * work on this graph.  With LV_VALIDATE the layout, symmetry and weights are
+ * checked (LV_E_CSR, LV_E_ASYMMETRIC, LV_E_WEIGHT); the volume bound is
+ * always checked (LV_E_OVERFLOW).
+ */
+lv_status lv_graph_create_csr(int32_t n, const int32_t* offsets, const int32_t* indices,
+                              const int32_t* weights, lv_memkind kind, uint32_t flags, void* stream,
+                              lv_graph** out);
+lv_status lv_graph_destroy(lv_graph* g);
+/* n, nnz and total volume M = sum of weighted degrees (loops counted twice). */
+lv_status lv_graph_info(const lv_graph* g, int32_t* n, int64_t* nnz, int64_t* volume);
+
+/*
+ * Multi-level Louvain (Algorithm 3 driving Algorithm 2).  params NULL =
+ * defaults.  The result keeps every attempted level's statistics and every
+ * accepted level's labels on the device.
+ */
+lv_status lv_louvain(lv_graph* g, const lv_params* params, lv_result** out);
+/* accepted levels, attempted levels (attempted = accepted + 1 unless max_levels hit) */
+lv_status lv_result_num_levels(const lv_result* r, int32_t* accepted, int32_t* attempted);
+lv_status lv_result_level_info(const lv_result* r, int32_t level, lv_level_info* out);
+/* per-sweep mover counts of an attempted level; writes min(cap, sweeps) values */
+lv_status lv_result_level_moves(const lv_result* r, int32_t level, int64_t* moves, int32_t cap);
+/* labels int32[n_level] of an accepted level: vertex of level l -> vertex of level l+1 */
+lv_status lv_result_level_labels(const lv_result* r, int32_t level, int32_t* labels, lv_memkind kind);
+/*
+ * Coarse graph produced by accepted level `level` (the Aggregation of
+ * Algorithm 3: A' = S^T A S with merged parallel edges and the community's
+ * internal weight on the diagonal, already counted twice like a loop), as a
+ * CSR with sorted columns: offsets int32[n_next+1], indices/weights int32[nnz].
+ * Needs LV_KEEP_GRAPHS (else LV_E_STATE).  Any of the three buffers may be
+ * NULL; *nnz is always written.
+ */
+lv_status lv_result_level_graph(const lv_result* r, int32_t level, int32_t* offsets, int32_t* indices,
+                                int32_t* weights, int64_t* nnz, lv_memkind kind);
+/* labels int32[n] of the input vertices after all accepted levels (singletons if none) */
+lv_status lv_result_final_labels(const lv_result* r, int32_t* labels, lv_memkind kind);
+/* Q_int, M and Q = (double)Q_int / ((double)M * (double)M) of the final partition */
+lv_status lv_result_modularity(const lv_result* r, int64_t* q_int, int64_t* m, double* q);
+lv_status lv_result_destroy(lv_result* r);
+
+/*
+ * Label propagation (Algorithm 1) as one level of synchronous sweeps with the
+ * LPA score, then renumbering.  labels int32[n] in `kind` memory; info may be
+ * NULL (then only labels are written); moves_out (may be NULL) receives up to
+ * moves_cap per-sweep mover counts.
+ */
+lv_status lv_lpa(lv_graph* g, const lv_params* params, int32_t* labels, lv_memkind kind,
+                 lv_level_info* info, int64_t* moves_out, int32_t moves_cap);
+
+/* Modularity (Section II-C) of any labels int32[n] with values in [0, n). */
+lv_status lv_modularity(lv_graph* g, const int32_t* labels, lv_memkind kind, int64_t* q_int,
+                        int64_t* m, double* q);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LV_H */

@@ -1,0 +1,315 @@
+"""Python binding of the MI355X Louvain library (``liblv.so``, C ABI in include/lv.h).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+The ``lv_*`` functions mirror the C entry points one to one; ``Graph``,
+``louvain``, ``lpa`` and ``modularity`` are small conveniences over them.
+Device buffers may be passed as torch CUDA tensors (PyTorch is used for device
+memory and streams only); host buffers as numpy arrays.
+
+There is no fallback: if ``liblv.so`` is missing or fails to load, every call
+raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblv.so")
+
+LV_OK = 0
+STATUS_NAMES = {
+    0: "LV_OK", 1: "LV_E_ARG", 2: "LV_E_CSR", 3: "LV_E_ASYMMETRIC", 4: "LV_E_WEIGHT",
+    5: "LV_E_OVERFLOW", 6: "LV_E_NOMEM", 7: "LV_E_HIP", 8: "LV_E_BUSY", 9: "LV_E_TOO_LARGE",
+    10: "LV_E_CANCELLED", 11: "LV_E_STATE", 12: "LV_E_NOT_FOUND",
+}
+LV_MEM_HOST, LV_MEM_DEVICE = 0, 1
+LV_VALIDATE = 1
+LV_TIMING = 1
+LV_KEEP_GRAPHS = 2
+KERNEL_SLOTS = 12
+# kernel slot -> name (slot = 2*(class-1) + first-sweep flag)
+KERNEL_NAMES = [f"{c}{'/first' if f else ''}" for c in ("g8", "g32", "wave", "block256", "block512", "hub")
+                for f in (0, 1)]
+
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_vp = ctypes.c_void_p
+
+
+class lv_tuning(ctypes.Structure):
+    _fields_ = [("sub_max", ctypes.c_int32), ("wave_max", ctypes.c_int32),
+                ("block_max", ctypes.c_int32), ("hub_chunk", ctypes.c_int32)]
+
+
+class lv_params(ctypes.Structure):
+    _fields_ = [("max_sweeps", ctypes.c_int32), ("max_levels", ctypes.c_int32),
+                ("lpa_threshold", ctypes.c_int64), ("flags", ctypes.c_uint32),
+                ("tuning", ctypes.POINTER(lv_tuning))]
+
+
+class lv_level_info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("n_next", ctypes.c_int32), ("nnz", ctypes.c_int64),
+                ("sweeps", ctypes.c_int32), ("accepted", ctypes.c_int32),
+                ("q_start", ctypes.c_int64), ("q_end", ctypes.c_int64),
+                ("move_ms", ctypes.c_double), ("sweep_ms", ctypes.c_double),
+                ("renumber_ms", ctypes.c_double), ("aggregate_ms", ctypes.c_double),
+                ("move_launches", ctypes.c_int64), ("move_bytes", ctypes.c_int64),
+                ("kern_ms", ctypes.c_double * KERNEL_SLOTS), ("kern_launches", ctypes.c_int64 * KERNEL_SLOTS),
+                ("kern_bytes", ctypes.c_int64 * KERNEL_SLOTS)]
+
+    def as_dict(self) -> dict:
+        out = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            out[name] = list(v) if name.startswith("kern_") else v
+        return out
+
+
+# name -> (restype, argtypes); every entry point declared in include/lv.h
+SIGNATURES = {
+    "lv_params_default": (None, [ctypes.POINTER(lv_params)]),
+    "lv_status_str": (ctypes.c_char_p, [ctypes.c_int]),
+    "lv_last_error": (ctypes.c_char_p, []),
+    "lv_graph_create_csr": (ctypes.c_int, [ctypes.c_int32, _vp, _vp, _vp, ctypes.c_int, ctypes.c_uint32, _vp,
+                                           ctypes.POINTER(_vp)]),
+    "lv_graph_destroy": (ctypes.c_int, [_vp]),
+    "lv_graph_info": (ctypes.c_int, [_vp, _i32p, _i64p, _i64p]),
+    "lv_louvain": (ctypes.c_int, [_vp, ctypes.POINTER(lv_params), ctypes.POINTER(_vp)]),
+    "lv_result_num_levels": (ctypes.c_int, [_vp, _i32p, _i32p]),
+    "lv_result_level_info": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.POINTER(lv_level_info)]),
+    "lv_result_level_moves": (ctypes.c_int, [_vp, ctypes.c_int32, _i64p, ctypes.c_int32]),
+    "lv_result_level_labels": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, ctypes.c_int]),
+    "lv_result_level_graph": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, _vp, _vp, _i64p, ctypes.c_int]),
+    "lv_result_final_labels": (ctypes.c_int, [_vp, _vp, ctypes.c_int]),
+    "lv_result_modularity": (ctypes.c_int, [_vp, _i64p, _i64p, ctypes.POINTER(ctypes.c_double)]),
+    "lv_result_destroy": (ctypes.c_int, [_vp]),
+    "lv_lpa": (ctypes.c_int, [_vp, ctypes.POINTER(lv_params), _vp, ctypes.c_int,
+                              ctypes.POINTER(lv_level_info), _i64p, ctypes.c_int32]),
+    "lv_modularity": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _i64p, _i64p, ctypes.POINTER(ctypes.c_double)]),
+}
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load liblv.so and declare its signatures.  Raises if it is missing.
+
+    When PyTorch is installed it is imported first: its wheel ships its own HIP
+    runtime under the same soname (libamdhip64.so.7), and loading torch first
+    makes liblv bind to that one, so a process never holds two HIP runtimes
+    (the second one would not see the GPU).  LV_NO_TORCH=1 skips this.
+    """
+    global _lib
+    if _lib is None:
+        if os.environ.get("LV_NO_TORCH") != "1":
+            try:
+                import torch  # noqa: F401
+            except ImportError:
+                pass
+        if not os.path.exists(path):
+            raise ImportError(f"{path} is not built; run paper_2507_06471_amd/build.py "
+                              "(or __graft_entry__.build())")
+        lib = ctypes.CDLL(path)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+class LvError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        lib = load_library()
+        detail = lib.lv_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)} ({detail})")
+        self.status = status
+
+
+def _check(status: int, where: str):
+    if status != LV_OK:
+        raise LvError(status, where)
+
+
+def _ptr(buf):
+    """(address, memkind) of a numpy array or torch tensor (None -> (None, host))."""
+    if buf is None:
+        return None, LV_MEM_HOST
+    if isinstance(buf, np.ndarray):
+        assert buf.dtype == np.int32 and buf.flags.c_contiguous, "int32 contiguous arrays only"
+        return buf.ctypes.data, LV_MEM_HOST
+    # torch tensor
+    import torch
+
+    assert buf.dtype == torch.int32 and buf.is_contiguous(), "int32 contiguous tensors only"
+    return buf.data_ptr(), (LV_MEM_DEVICE if buf.is_cuda else LV_MEM_HOST)
+
+
+def make_params(max_sweeps: int = 20, max_levels: int = 32, lpa_threshold: int = 0, flags: int = 0,
+                tuning: Optional[dict] = None):
+    p = lv_params()
+    load_library().lv_params_default(ctypes.byref(p))
+    p.max_sweeps, p.max_levels, p.lpa_threshold, p.flags = max_sweeps, max_levels, lpa_threshold, flags
+    keep = None
+    if tuning:
+        keep = lv_tuning(**tuning)
+        p.tuning = ctypes.pointer(keep)
+    return p, keep
+
+
+class Graph:
+    """Device-resident graph handle (lv_graph_create_csr / lv_graph_destroy)."""
+
+    def __init__(self, n: int, offsets, indices, weights=None, validate: bool = True, stream: int = 0):
+        lib = load_library()
+        po, ko = _ptr(offsets)
+        pi, ki = _ptr(indices)
+        pw, kw = _ptr(weights)
+        kinds = {ko, ki} | ({kw} if weights is not None else set())
+        if len(kinds) != 1:
+            raise ValueError("offsets, indices and weights must live in the same memory")
+        h = _vp()
+        st = lib.lv_graph_create_csr(int(n), po, pi, pw, ko, LV_VALIDATE if validate else 0,
+                                     stream or None, ctypes.byref(h))
+        _check(st, "lv_graph_create_csr")
+        self._h = h
+        self.n = int(n)
+        nn, nnz, vol = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib.lv_graph_info(h, ctypes.byref(nn), ctypes.byref(nnz), ctypes.byref(vol)), "lv_graph_info")
+        self.nnz = nnz.value
+        self.volume = vol.value
+
+    @classmethod
+    def from_csr(cls, g, validate: bool = True, device: bool = False):
+        """From a ``graphgen.CSR``-like object (n, offsets, indices, weights)."""
+        off = np.ascontiguousarray(g.offsets, dtype=np.int32)
+        idx = np.ascontiguousarray(g.indices, dtype=np.int32)
+        w = None if g.weights is None else np.ascontiguousarray(g.weights, dtype=np.int32)
+        if device:
+            import torch
+
+            off, idx = torch.from_numpy(off).cuda(), torch.from_numpy(idx).cuda()
+            w = None if w is None else torch.from_numpy(w).cuda()
+            torch.cuda.synchronize()
+        return cls(g.n, off, idx, w, validate=validate)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().lv_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+@dataclass
+class LevelResult:
+    info: dict
+    moves: List[int]
+    labels: Optional[np.ndarray] = None
+    graph: Optional[tuple] = None  # (offsets, indices, weights) when kept
+
+
+@dataclass
+class LouvainResult:
+    q_int: int
+    M: int
+    q: float
+    final_labels: np.ndarray
+    levels: List[LevelResult] = field(default_factory=list)  # every attempted level
+
+    @property
+    def accepted(self) -> List[LevelResult]:
+        return [lv for lv in self.levels if lv.info["accepted"]]
+
+
+def louvain(graph: Graph, max_sweeps: int = 20, max_levels: int = 32, timing: bool = False,
+            keep_graphs: bool = False, tuning: Optional[dict] = None) -> LouvainResult:
+    """lv_louvain + result accessors, copied to host numpy."""
+    lib = load_library()
+    flags = (LV_TIMING if timing else 0) | (LV_KEEP_GRAPHS if keep_graphs else 0)
+    p, _keep = make_params(max_sweeps, max_levels, 0, flags, tuning)
+    r = _vp()
+    _check(lib.lv_louvain(graph.handle, ctypes.byref(p), ctypes.byref(r)), "lv_louvain")
+    try:
+        acc, att = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib.lv_result_num_levels(r, ctypes.byref(acc), ctypes.byref(att)), "lv_result_num_levels")
+        levels = []
+        for lvl in range(att.value):
+            info = lv_level_info()
+            _check(lib.lv_result_level_info(r, lvl, ctypes.byref(info)), "lv_result_level_info")
+            mv = np.zeros(max(info.sweeps, 1), dtype=np.int64)
+            _check(lib.lv_result_level_moves(r, lvl, mv.ctypes.data_as(_i64p), info.sweeps), "lv_result_level_moves")
+            lr = LevelResult(info.as_dict(), [int(x) for x in mv[:info.sweeps]])
+            if lvl < acc.value:
+                lab = np.empty(info.n, dtype=np.int32)
+                _check(lib.lv_result_level_labels(r, lvl, lab.ctypes.data, LV_MEM_HOST), "lv_result_level_labels")
+                lr.labels = lab
+                if keep_graphs:
+                    nnz = ctypes.c_int64()
+                    _check(lib.lv_result_level_graph(r, lvl, None, None, None, ctypes.byref(nnz), LV_MEM_HOST),
+                           "lv_result_level_graph")
+                    off = np.empty(info.n_next + 1, dtype=np.int32)
+                    idx = np.empty(max(nnz.value, 1), dtype=np.int32)
+                    w = np.empty(max(nnz.value, 1), dtype=np.int32)
+                    _check(lib.lv_result_level_graph(r, lvl, off.ctypes.data, idx.ctypes.data, w.ctypes.data,
+                                                     ctypes.byref(nnz), LV_MEM_HOST), "lv_result_level_graph")
+                    lr.graph = (off, idx[:nnz.value], w[:nnz.value])
+            levels.append(lr)
+        fin = np.empty(graph.n, dtype=np.int32)
+        _check(lib.lv_result_final_labels(r, fin.ctypes.data, LV_MEM_HOST), "lv_result_final_labels")
+        qi, m, q = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_double()
+        _check(lib.lv_result_modularity(r, ctypes.byref(qi), ctypes.byref(m), ctypes.byref(q)),
+               "lv_result_modularity")
+        return LouvainResult(qi.value, m.value, q.value, fin, levels)
+    finally:
+        lib.lv_result_destroy(r)
+
+
+@dataclass
+class LpaResult:
+    labels: np.ndarray
+    moves: List[int]
+    info: dict
+
+
+def lpa(graph: Graph, max_sweeps: int = 20, threshold: int = 0, timing: bool = False, out=None,
+        tuning: Optional[dict] = None) -> LpaResult:
+    """lv_lpa; labels land in `out` (numpy or torch int32) or a new numpy array."""
+    lib = load_library()
+    p, _keep = make_params(max_sweeps, 32, threshold, LV_TIMING if timing else 0, tuning)
+    labels = np.empty(graph.n, dtype=np.int32) if out is None else out
+    pl, kind = _ptr(labels)
+    info = lv_level_info()
+    mv = np.zeros(max_sweeps, dtype=np.int64)
+    _check(lib.lv_lpa(graph.handle, ctypes.byref(p), pl, kind, ctypes.byref(info), mv.ctypes.data_as(_i64p),
+                      max_sweeps), "lv_lpa")
+    return LpaResult(labels, [int(x) for x in mv[:info.sweeps]], info.as_dict())
+
+
+def modularity(graph: Graph, labels):
+    """lv_modularity -> (Q_int, M, Q)."""
+    lib = load_library()
+    pl, kind = _ptr(labels)
+    qi, m, q = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_double()
+    _check(lib.lv_modularity(graph.handle, pl, kind, ctypes.byref(qi), ctypes.byref(m), ctypes.byref(q)),
+           "lv_modularity")
+    return qi.value, m.value, q.value

@@ -1,0 +1,150 @@
+// Internal declarations shared by the kernel and host translation units of
+// the Louvain library.  Everything here is gfx950 / HIP only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lv {
+
+constexpr int32_t EMPTY_KEY = -1;
+constexpr int MODE_LOUVAIN = 0;
+constexpr int MODE_LPA = 1;
+constexpr int DIR_DOWN = 0;
+constexpr int DIR_UP = 1;
+
+// Degree classes of the move step.  A vertex with L CSR entries goes to the
+// first class whose bound is >= L (L = 0 never moves and is skipped).
+enum MoveClass : int {
+    CLS_NONE = 0,  // isolated
+    CLS_G8 = 1,    // 8 lanes per vertex, LDS table of 16 slots
+    CLS_G32 = 2,   // 32 lanes, 64 slots
+    CLS_G64 = 3,   // one wavefront, 256 slots
+    CLS_B256 = 4,  // one 256-thread workgroup, 1024 slots
+    CLS_B512 = 5,  // one 512-thread workgroup, 8192 slots (64 KiB)
+    CLS_HUB = 6,   // several workgroups, table in global memory
+    NUM_CLS = 7
+};
+// Largest L each class can hold (table load factor <= 1/2).
+constexpr int32_t CLS_CAP[NUM_CLS] = {0, 8, 32, 128, 512, 4096, INT32_MAX};
+
+// Arguments shared by every move kernel.
+struct MoveArgs {
+    const int32_t* off;
+    const int32_t* idx;
+    const int32_t* w;       // null = unit weights
+    const int32_t* k;       // weighted degree, < 2^31
+    const int32_t* comm;    // labels of the previous sweep
+    const int32_t* sigma;   // community volumes of the previous sweep, < 2^31
+    int64_t M;              // total volume
+    const int32_t* verts;   // vertices of this class
+    int32_t nverts;
+    int32_t dir;            // DIR_DOWN / DIR_UP
+    int32_t mode;           // MODE_LOUVAIN / MODE_LPA
+    int32_t* mv_vert;       // mover list (vertex, target)
+    int32_t* mv_comm;
+    uint32_t* mv_count;
+};
+
+// Global-table (hub) path: per-hub layout built on the host once per level.
+struct HubArgs {
+    int32_t nhubs;
+    const int32_t* hub_vert;     // [nhubs]
+    const int64_t* tab_off;      // [nhubs] slot offset of the hub's table
+    const int32_t* tab_cap;      // [nhubs] slots (power of two)
+    int32_t* table;              // 2 ints per slot: key, value
+    // insert / singleton blocks: block b covers entries [blk_beg[b], blk_end[b]) of hub blk_hub[b]
+    const int32_t* ins_hub;
+    const int32_t* ins_beg;
+    const int32_t* ins_end;
+    int32_t nins;
+    // scan blocks: block b scans slots [scan_beg[b], scan_end[b]) of hub scan_hub[b]
+    const int32_t* scan_hub;
+    const int32_t* scan_beg;
+    const int32_t* scan_end;
+    int32_t nscan;
+    // partial results: one per insert block (singleton sweep) or scan block
+    int64_t* part_score;
+    int32_t* part_comm;
+    int32_t* part_wown;
+    const int32_t* part_first_ins;   // [nhubs+1] partial ranges for the singleton sweep
+    const int32_t* part_first_scan;  // [nhubs+1] partial ranges for later sweeps
+};
+
+// ---- launchers (lv_kernels.hip) ----
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+hipError_t launch_iota(int32_t* p, int32_t n, hipStream_t s);
+hipError_t launch_copy_i32(int32_t* dst, const int32_t* src, int64_t n, hipStream_t s);
+
+// exclusive scans; `total` (device, may be null) receives the sum
+hipError_t scan_exclusive_i32(const int32_t* in, int32_t* out, int64_t n, int32_t* total, void* tmp,
+                              size_t tmp_bytes, hipStream_t s);
+hipError_t scan_exclusive_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* total, void* tmp,
+                              size_t tmp_bytes, hipStream_t s);
+size_t scan_tmp_bytes(int64_t n, size_t elem);
+
+// stable LSD radix sort of (key, value) pairs on key bits [0, bits)
+size_t radix_tmp_bytes(int64_t n);
+hipError_t radix_sort_u64(uint64_t* keys, int32_t* vals, uint64_t* keys_alt, int32_t* vals_alt, int64_t n,
+                          int bits, void* tmp, size_t tmp_bytes, bool* result_in_alt, hipStream_t s);
+hipError_t radix_sort_u32(uint32_t* keys, int32_t* vals, uint32_t* keys_alt, int32_t* vals_alt, int64_t n,
+                          int bits, void* tmp, size_t tmp_bytes, bool* result_in_alt, hipStream_t s);
+
+// graph preparation / validation; err bits: 1 offsets, 2 indices, 4 weights,
+// 8 asymmetric, 16 overflow
+hipError_t launch_check_offsets(int32_t n, const int32_t* off, int64_t nnz, int32_t* err, hipStream_t s);
+hipError_t launch_check_entries(int32_t n, const int32_t* off, const int32_t* idx, const int32_t* w,
+                                int64_t nnz, int32_t* err, hipStream_t s);
+hipError_t launch_check_symmetric(int32_t n, const int32_t* off, const int32_t* idx, const int32_t* w,
+                                  int64_t nnz, int32_t* err, hipStream_t s);
+hipError_t launch_diag_scan(int32_t n, const int32_t* off, const int32_t* idx, int32_t* diag_pos,
+                            int32_t* any_diag, hipStream_t s);
+hipError_t launch_adjacency_weights(int32_t n, const int32_t* w_in, const int32_t* diag_pos, int64_t nnz,
+                                    int32_t* w_out, int32_t* err, hipStream_t s);
+// k = row sums (int32), k64 scratch [n], *total += sum (caller zeroes total)
+hipError_t launch_row_sums(int32_t n, const int32_t* off, const int32_t* w, int64_t nnz, int32_t* k,
+                           int64_t* k64, int64_t* total, hipStream_t s);
+hipError_t launch_degree_unit(int32_t n, const int32_t* off, int32_t* k, hipStream_t s);
+// out2[0] += sum k^2, out2[1] += trace (caller zeroes out2)
+hipError_t launch_sum_sq_trace(int32_t n, const int32_t* off, const int32_t* idx, const int32_t* w,
+                               int64_t nnz, const int32_t* k, int64_t* out2, hipStream_t s);
+
+// classes
+hipError_t launch_classify(int32_t n, const int32_t* off, const int32_t* bounds, uint32_t* cls,
+                           int32_t* vert, hipStream_t s);
+
+hipError_t launch_class_starts(const uint32_t* cls_sorted, int32_t n, int32_t* start, hipStream_t s);
+hipError_t launch_gather_rows(const int32_t* verts, int32_t m, const int32_t* off, int32_t* beg, int32_t* len,
+                              hipStream_t s);
+
+// out[c] += CSR entries of class c; start = host array [NUM_CLS+1] of class bounds
+hipError_t launch_class_entries(const int32_t* verts_sorted, const int32_t* start, const int32_t* off,
+                                int64_t* out, hipStream_t s);
+
+// sweep
+hipError_t launch_move_class(int cls, bool singleton, const MoveArgs& a, hipStream_t s);
+hipError_t launch_hub_clear(int32_t* table, int64_t slots, hipStream_t s);
+hipError_t launch_hub_sweep(bool singleton, const MoveArgs& a, const HubArgs& h, hipStream_t s);
+hipError_t launch_apply(const int32_t* mv_vert, const int32_t* mv_comm, const uint32_t* mv_count,
+                        int32_t max_movers, const int32_t* k, int32_t* comm, int32_t* sigma,
+                        hipStream_t s);
+
+// renumber + aggregation
+hipError_t launch_renumber(int32_t n, const int32_t* comm, int32_t* minv, int32_t* flag, int32_t* pos,
+                           int32_t* labels, int32_t* n_out, void* tmp, size_t tmp_bytes, hipStream_t s);
+hipError_t launch_coarse_degree(int32_t n, const int32_t* comm, const int32_t* flag, const int32_t* labels,
+                                const int32_t* sigma, int32_t* k2, hipStream_t s);
+hipError_t launch_build_keys(int32_t n, const int32_t* off, const int32_t* idx, const int32_t* w,
+                             int64_t nnz, const int32_t* labels, int colbits, uint64_t* keys, int32_t* vals,
+                             hipStream_t s);
+hipError_t launch_segment_heads(const uint64_t* keys, int64_t n, int32_t* head, hipStream_t s);
+hipError_t launch_segment_reduce(const uint64_t* keys, const int32_t* vals, const int32_t* pos, int64_t n,
+                                 int colbits, int32_t* idx2, int32_t* w2, int32_t* rowcnt, hipStream_t s);
+hipError_t launch_compose(int32_t n0, int32_t* final_labels, const int32_t* labels, hipStream_t s);
+hipError_t launch_modularity_parts(int32_t n, const int32_t* off, const int32_t* idx, const int32_t* w,
+                                   int64_t nnz, const int32_t* k, const int32_t* labels, int64_t* tot,
+                                   int64_t* out2, hipStream_t s);
+hipError_t launch_sum_sq_i64(const int64_t* v, int64_t n, int64_t* out, hipStream_t s);
+hipError_t launch_check_labels(const int32_t* labels, int32_t n, int32_t* err, hipStream_t s);
+
+}  // namespace lv

@@ -1,0 +1,175 @@
+"""GPU path vs the CPU oracle through the C ABI: bit-exact labels at every level,
+identical per-sweep move counts, identical Q_int (so FP64 Q is identical too)."""
+import sys
+
+import numpy as np
+import pytest
+
+import bruteforce as bf
+import graphgen
+import oracle
+import paper_2507_06471_amd as lvp
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def compare_louvain(g, tuning=None, max_sweeps=20, max_levels=32, keep_graphs=False, device=False):
+    say(f"case {g.name or 'graph'} n={g.n} nnz={g.nnz} tuning={tuning}")
+    want = oracle.louvain(g, max_sweeps=max_sweeps, max_levels=max_levels, keep_graphs=keep_graphs)
+    with lvp.Graph.from_csr(g, device=device) as dg:
+        got = lvp.louvain(dg, max_sweeps=max_sweeps, max_levels=max_levels, keep_graphs=keep_graphs,
+                          tuning=tuning)
+    assert got.M == want.M
+    assert len(got.levels) == len(want.levels)
+    for lvl, (a, b) in enumerate(zip(got.levels, want.levels)):
+        assert a.moves == [int(x) for x in b.moves], f"level {lvl} moves"
+        assert (a.info["n"], a.info["n_next"], a.info["q_start"], a.info["q_end"]) == (
+            b.n, b.n_next, b.q_start, b.q_end), f"level {lvl} stats"
+        assert bool(a.info["accepted"]) == b.accepted
+        if b.accepted:
+            assert np.array_equal(a.labels, b.labels), f"level {lvl} labels"
+    assert np.array_equal(got.final_labels, want.final_labels)
+    assert got.q_int == want.q_int
+    assert got.q == want.q  # both divide the same integers the same way
+    if keep_graphs:
+        for lvl, a in enumerate(got.accepted):
+            co = want.graphs[lvl + 1]
+            off, idx, w = a.graph
+            assert np.array_equal(off, co.off) and np.array_equal(idx, co.idx) and np.array_equal(w, co.a)
+    return got, want
+
+
+def compare_lpa(g, max_sweeps=20, threshold=0, tuning=None):
+    say(f"lpa case {g.name or 'graph'} n={g.n} nnz={g.nnz}")
+    want = oracle.lpa(g, max_sweeps=max_sweeps, theta=threshold)
+    with lvp.Graph.from_csr(g) as dg:
+        got = lvp.lpa(dg, max_sweeps=max_sweeps, threshold=threshold, tuning=tuning)
+    assert got.moves == [int(x) for x in want.moves]
+    assert np.array_equal(got.labels, want.labels)
+    assert got.info["q_end"] == want.q_int
+
+
+def test_worked_trace():
+    edges = [(0, 1, 1), (0, 2, 1), (1, 2, 1), (3, 4, 1), (3, 5, 1), (4, 5, 1), (2, 3, 1)]
+    got, _ = compare_louvain(bf.to_csr(6, edges), keep_graphs=True)
+    assert got.levels[0].moves == [3, 1, 0, 0]
+    assert list(got.final_labels) == [0, 0, 0, 1, 1, 1]
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_tiny_random_graphs_with_loops_and_weights(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(1, 60))
+    edges = bf.random_graph(rng, n, float(rng.uniform(0.02, 0.4)), 9, True)
+    g = bf.to_csr(n, edges)
+    g.name = f"tiny{seed}"
+    compare_louvain(g, keep_graphs=True)
+    compare_lpa(g)
+
+
+def test_sbm_4096_planted_partition():
+    g = graphgen.sbm(4096, 128, 0.05, 0.0005, seed=1)
+    got, _ = compare_louvain(g, keep_graphs=True)
+    assert got.q > 0.65
+
+
+@pytest.mark.parametrize("scale", [12, 16, 18])
+def test_rmat(scale):
+    g = graphgen.rmat(scale, seed=2)
+    compare_louvain(g)
+
+
+def test_rmat_lpa():
+    compare_lpa(graphgen.rmat(16, seed=2))
+
+
+def test_lfr_weighted():
+    g, _ = graphgen.lfr(30000, kmax=1500, smin=30, smax=3000, seed=3)
+    compare_louvain(g, keep_graphs=True)
+    compare_lpa(g)
+
+
+@pytest.mark.parametrize("tuning", [
+    {"sub_max": 1, "wave_max": 2, "block_max": 3, "hub_chunk": 256},   # nearly all on the hub path
+    {"sub_max": 8, "wave_max": 8, "block_max": 8, "hub_chunk": 300},
+    {"sub_max": 32, "wave_max": 128, "block_max": 512, "hub_chunk": 1000},
+    {"sub_max": 4, "wave_max": 64, "block_max": 4096, "hub_chunk": 4096},
+])
+def test_tuning_never_changes_results(tuning):
+    g = graphgen.rmat(14, seed=5)
+    compare_louvain(g, tuning=tuning)
+    compare_lpa(g, tuning=tuning)
+
+
+def test_device_resident_input():
+    pytest.importorskip("torch")
+    compare_louvain(graphgen.rmat(12, seed=8), device=True)
+
+
+def test_modularity_of_arbitrary_labels():
+    g = graphgen.rmat(12, seed=4)
+    g.weights = graphgen.pair_weights(g, 1, 5, seed=4)
+    rng = np.random.default_rng(1)
+    with lvp.Graph.from_csr(g) as dg:
+        for t in range(5):
+            lab = rng.integers(0, max(1, g.n // (t + 1)), size=g.n).astype(np.int32)
+            qi, m, q = lvp.modularity(dg, lab)
+            wq, wm, wqf = oracle.modularity(g, lab)
+            assert (qi, m, q) == (wq, wm, wqf)
+
+
+@pytest.mark.parametrize("case", ["empty", "single", "no_edges", "loops_only", "star", "clique", "path"])
+def test_edge_cases(case):
+    if case == "empty":
+        g = graphgen.CSR(0, np.zeros(1, np.int32), np.zeros(0, np.int32), None)
+    elif case == "single":
+        g = graphgen.CSR(1, np.zeros(2, np.int32), np.zeros(0, np.int32), None)
+    elif case == "no_edges":
+        g = graphgen.CSR(50, np.zeros(51, np.int32), np.zeros(0, np.int32), None)
+    elif case == "loops_only":
+        g = bf.to_csr(5, [(v, v, v + 1) for v in range(5)])
+    elif case == "star":
+        g = bf.to_csr(200, [(0, v, 1) for v in range(1, 200)])
+    elif case == "clique":
+        g = bf.to_csr(40, [(u, v, 1) for u in range(40) for v in range(u + 1, 40)])
+    else:
+        g = bf.to_csr(100, [(v, v + 1, 1) for v in range(99)])
+    g.name = case
+    compare_louvain(g)
+    if g.n > 0:
+        compare_lpa(g)
+
+
+def test_bad_inputs_rejected():
+    off = np.array([0, 1, 2], np.int32)
+    # asymmetric: 0->1 without 1->0
+    with pytest.raises(lvp.LvError) as ei:
+        lvp.Graph(2, off, np.array([1, 1], np.int32))
+    assert ei.value.status == 3
+    # unsorted row
+    with pytest.raises(lvp.LvError) as ei:
+        lvp.Graph(3, np.array([0, 2, 3, 4], np.int32), np.array([2, 1, 0, 0], np.int32), validate=False)
+    assert ei.value.status == 2
+    # index out of range
+    with pytest.raises(lvp.LvError) as ei:
+        lvp.Graph(2, off, np.array([1, 5], np.int32))
+    assert ei.value.status == 2
+    # zero weight
+    with pytest.raises(lvp.LvError) as ei:
+        lvp.Graph(2, off, np.array([1, 0], np.int32), np.array([0, 0], np.int32))
+    assert ei.value.status == 4
+    # volume overflow
+    with pytest.raises(lvp.LvError) as ei:
+        lvp.Graph(2, off, np.array([1, 0], np.int32), np.array([2**30, 2**30], np.int32))
+    assert ei.value.status == 5
+    # offsets not ending at nnz / decreasing
+    with pytest.raises(lvp.LvError) as ei:
+        lvp.Graph(2, np.array([0, 2, 1], np.int32), np.array([1, 0], np.int32))
+    assert ei.value.status == 2
+    with pytest.raises(lvp.LvError):
+        lvp.Graph(2, np.array([1, 1, 2], np.int32), np.array([1, 0], np.int32))
