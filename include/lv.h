@@ -83,8 +83,13 @@ typedef struct lv_tuning {
     int32_t sub_max;   /* L <= sub_max: a sub-wave group per vertex (power of 2, 2..64)  */
     int32_t wave_max;  /* L <= wave_max: one wavefront per vertex                          */
     int32_t block_max; /* L <= block_max: one workgroup per vertex, LDS table              */
-                       /* L >  block_max: several workgroups per vertex, global table      */
-    int32_t hub_chunk; /* CSR entries per workgroup on the global-table path               */
+                       /* L >  block_max: ceil(L / part_keys) workgroups per vertex, each  */
+                       /* aggregating one hash partition of the communities in LDS         */
+    int32_t part_keys;  /* expected communities per partition workgroup (clamped to       */
+                        /* [32, 3/4 of part_slots])                                       */
+    int32_t part_slots; /* LDS table slots of a partition workgroup, power of two,       */
+                        /* 64..16384 (default 16384); a partition whose communities do   */
+                        /* not fit is redone with a global-memory table                  */
 } lv_tuning;
 
 typedef struct lv_params {

@@ -83,11 +83,11 @@ struct DevBuf {
 };
 
 struct Workspace {
-    DevBuf comm, sigma, mv_vert, mv_comm, cls, vert, cls_alt, vert_alt, minv, flag, pos, labels, tmp, small;
+    DevBuf comm, sigma, dec, cls, vert, cls_alt, vert_alt, minv, flag, pos, labels, tmp, small;
     DevBuf keys, keys_alt, vals, vals_alt, head;
     DevBuf g_off[2], g_idx[2], g_w[2], g_k[2];
     DevBuf hub_table, hub_meta, hub_part, hub_rows;
-    DevBuf k64;
+    DevBuf k64, cs;
 };
 
 struct Timer {
@@ -178,16 +178,18 @@ namespace {
 
 struct Tune {
     int32_t bounds[NUM_CLS];
-    int32_t hub_chunk;
-    int32_t scan_chunk;
+    int32_t part_keys;  // expected distinct communities per partition workgroup
+    int32_t part_slots; // LDS slots of a partition workgroup (power of two, <= 16384)
+    int32_t fb_chunk;   // entries / slots per workgroup on the global-table fallback
 };
 
 Tune make_tune(const lv_tuning* t)
 {
     Tune u;
     for (int c = 0; c < NUM_CLS; ++c) u.bounds[c] = CLS_CAP[c];
-    u.hub_chunk = 4096;
-    u.scan_chunk = 4096;
+    u.part_keys = 12288;
+    u.part_slots = 16384;
+    u.fb_chunk = 4096;
     if (t) {
         // sub_max bounds the 8- and 32-lane classes, wave_max the wavefront
         // class, block_max the workgroup classes; each is clamped to what the
@@ -201,8 +203,11 @@ Tune make_tune(const lv_tuning* t)
             u.bounds[CLS_B256] = std::min(CLS_CAP[CLS_B256], std::max(u.bounds[CLS_G64], t->block_max));
             u.bounds[CLS_B512] = std::min(CLS_CAP[CLS_B512], std::max(u.bounds[CLS_B256], t->block_max));
         }
-        if (t->hub_chunk > 0) u.hub_chunk = std::max(256, t->hub_chunk);
+        if (t->part_slots > 0) u.part_slots = (int32_t)std::min<uint64_t>(16384, std::max<uint64_t>(64, next_pow2((uint64_t)t->part_slots)));
+        if (t->part_keys > 0) u.part_keys = std::max(32, t->part_keys);
     }
+    // a single partition must always fit: part_keys <= 3/4 of the slots
+    u.part_keys = std::min(u.part_keys, u.part_slots / 4 * 3);
     // keep bounds non-decreasing
     for (int c = CLS_G32; c < CLS_HUB; ++c) u.bounds[c] = std::max(u.bounds[c], u.bounds[c - 1]);
     return u;
@@ -266,72 +271,89 @@ lv_status plan_hubs(lv_graph* g, const LevelGraph& G, const int32_t* hub_verts, 
     hipStream_t s = g->stream;
     plan.nhubs = nhubs;
     if (nhubs == 0) return LV_OK;
-    // row starts and lengths of the hubs, read back to size the table layout
+    // row starts and lengths of the hubs, read back to size the layout
     HIP_TRY(ws.hub_rows.ensure(sizeof(int32_t) * 2 * (size_t)nhubs));
     int32_t* d_beg = ws.hub_rows.as<int32_t>();
     int32_t* d_len = d_beg + nhubs;
     HIP_TRY(launch_gather_rows(hub_verts, nhubs, G.off, d_beg, d_len, s));
-    std::vector<int32_t> beg(nhubs), len(nhubs);
+    std::vector<int32_t> beg(nhubs), len(nhubs), hv(nhubs);
     HIP_TRY(hipMemcpyAsync(beg.data(), d_beg, sizeof(int32_t) * nhubs, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(len.data(), d_len, sizeof(int32_t) * nhubs, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(hv.data(), hub_verts, sizeof(int32_t) * nhubs, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    std::vector<int32_t> parts(nhubs), first_blk(nhubs + 1), blk_hub, blk_part;
     std::vector<int64_t> tab_off(nhubs);
-    std::vector<int32_t> tab_cap(nhubs), ins_hub, ins_beg, ins_end, scan_hub, scan_beg, scan_end;
-    std::vector<int32_t> first_ins(nhubs + 1), first_scan(nhubs + 1);
+    std::vector<int32_t> tab_cap(nhubs), ins_hub, ins_beg, ins_end, scan_hub, scan_beg, scan_end, fpart_first(nhubs + 1);
     int64_t slots = 0;
     for (int32_t h = 0; h < nhubs; ++h) {
+        const int32_t P = (int32_t)std::max<int64_t>(1, ((int64_t)len[h] + tu.part_keys - 1) / tu.part_keys);
+        parts[h] = P;
+        first_blk[h] = (int32_t)blk_hub.size();
+        for (int32_t q = 0; q < P; ++q) { blk_hub.push_back(h); blk_part.push_back(q); }
+        fpart_first[h] = (int32_t)scan_hub.size();
+        tab_off[h] = slots;
+        tab_cap[h] = 0;
+        if (P == 1) continue;  // one partition of <= part_keys keys always fits its LDS table
         const uint64_t cap = std::max<uint64_t>(64, next_pow2(2ull * (uint64_t)len[h]));
         if (cap > (uint64_t)INT32_MAX) { set_error_msg("hub table too large"); return LV_E_OVERFLOW; }
-        tab_off[h] = slots;
         tab_cap[h] = (int32_t)cap;
         slots += (int64_t)cap;
-        first_ins[h] = (int32_t)ins_hub.size();
-        for (int64_t e = beg[h]; e < (int64_t)beg[h] + len[h]; e += tu.hub_chunk) {
+        for (int64_t e = beg[h]; e < (int64_t)beg[h] + len[h]; e += tu.fb_chunk) {
             ins_hub.push_back(h);
             ins_beg.push_back((int32_t)e);
-            ins_end.push_back((int32_t)std::min<int64_t>(e + tu.hub_chunk, (int64_t)beg[h] + len[h]));
+            ins_end.push_back((int32_t)std::min<int64_t>(e + tu.fb_chunk, (int64_t)beg[h] + len[h]));
         }
-        first_scan[h] = (int32_t)scan_hub.size();
-        for (int64_t t = 0; t < (int64_t)cap; t += tu.scan_chunk) {
+        for (int64_t t = 0; t < (int64_t)cap; t += tu.fb_chunk) {
             scan_hub.push_back(h);
             scan_beg.push_back((int32_t)t);
-            scan_end.push_back((int32_t)std::min<int64_t>(t + tu.scan_chunk, (int64_t)cap));
+            scan_end.push_back((int32_t)std::min<int64_t>(t + tu.fb_chunk, (int64_t)cap));
         }
     }
-    first_ins[nhubs] = (int32_t)ins_hub.size();
-    first_scan[nhubs] = (int32_t)scan_hub.size();
-    const int32_t nins = (int32_t)ins_hub.size(), nscan = (int32_t)scan_hub.size();
-    const int32_t nparts = std::max(nins, nscan);
-    // one metadata buffer: int64 tab_off, then int32 arrays
-    const size_t b64 = sizeof(int64_t) * (size_t)nhubs;
-    const size_t n32 = (size_t)nhubs * 2 + (size_t)nins * 3 + (size_t)nscan * 3 + (size_t)(nhubs + 1) * 2;
-    HIP_TRY(ws.hub_meta.ensure(b64 + sizeof(int32_t) * n32 + 64));
-    char* base = ws.hub_meta.as<char>();
+    first_blk[nhubs] = (int32_t)blk_hub.size();
+    fpart_first[nhubs] = (int32_t)scan_hub.size();
+    const int32_t nblk = (int32_t)blk_hub.size(), nins = (int32_t)ins_hub.size(), nscan = (int32_t)scan_hub.size();
+    // metadata: int64 tab_off first, then the int32 arrays
     std::vector<int32_t> pack;
-    pack.reserve(n32);
     auto put = [&](const std::vector<int32_t>& v) {
-        size_t at = pack.size();
+        const size_t at = pack.size();
         pack.insert(pack.end(), v.begin(), v.end());
         return at;
     };
-    std::vector<int32_t> hv(nhubs);
-    HIP_TRY(hipMemcpyAsync(hv.data(), hub_verts, sizeof(int32_t) * nhubs, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    const size_t o_hv = put(hv), o_cap = put(tab_cap), o_ih = put(ins_hub), o_ib = put(ins_beg), o_ie = put(ins_end);
-    const size_t o_sh = put(scan_hub), o_sb = put(scan_beg), o_se = put(scan_end), o_fi = put(first_ins),
-                 o_fs = put(first_scan);
-    HIP_TRY(hipMemcpyAsync(base, tab_off.data(), b64, hipMemcpyHostToDevice, s));
+    const size_t o_hv = put(hv), o_parts = put(parts), o_fb = put(first_blk), o_bh = put(blk_hub), o_bp = put(blk_part);
+    const size_t o_cap = put(tab_cap), o_ih = put(ins_hub), o_ib = put(ins_beg), o_ie = put(ins_end);
+    const size_t o_sh = put(scan_hub), o_sb = put(scan_beg), o_se = put(scan_end), o_ff = put(fpart_first);
+    const size_t b64 = sizeof(int64_t) * (size_t)nhubs;
+    HIP_TRY(ws.hub_meta.ensure(b64 + sizeof(int32_t) * pack.size() + 64));
+    char* base = ws.hub_meta.as<char>();
     int32_t* p32 = (int32_t*)(base + b64);
+    HIP_TRY(hipMemcpyAsync(base, tab_off.data(), b64, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(p32, pack.data(), sizeof(int32_t) * pack.size(), hipMemcpyHostToDevice, s));
-    HIP_TRY(ws.hub_part.ensure((sizeof(int64_t) + 2 * sizeof(int32_t)) * (size_t)nparts));
-    HIP_TRY(ws.hub_table.ensure(sizeof(int32_t) * 2 * (size_t)slots));
-    HIP_TRY(launch_hub_clear(ws.hub_table.as<int32_t>(), slots, s));
+    // partial results + flags: [nblk] x (int64 score, int32 comm, wown, flag), [nhubs] fb_flag, [nscan] fallback partials
+    const size_t part_bytes = (size_t)nblk * (8 + 4 * 3) + (size_t)nhubs * 4 + (size_t)std::max(nscan, 1) * (8 + 4 * 2);
+    HIP_TRY(ws.hub_part.ensure(part_bytes + 64));
+    char* pb = ws.hub_part.as<char>();
     HubArgs& a = plan.args;
+    a = HubArgs{};
     a.nhubs = nhubs;
+    a.part_mask = (uint32_t)tu.part_slots - 1u;
     a.hub_vert = p32 + o_hv;
+    a.hub_parts = p32 + o_parts;
+    a.hub_first_blk = p32 + o_fb;
+    a.blk_hub = p32 + o_bh;
+    a.blk_part = p32 + o_bp;
+    a.nblk = nblk;
+    a.part_score = (int64_t*)pb;
+    a.part_comm = (int32_t*)(a.part_score + nblk);
+    a.part_wown = a.part_comm + nblk;
+    a.part_flag = a.part_wown + nblk;
+    a.fb_flag = a.part_flag + nblk;
+    int64_t* fps = (int64_t*)(((uintptr_t)(a.fb_flag + nhubs) + 7) & ~(uintptr_t)7);
+    a.fpart_score = fps;
+    a.fpart_comm = (int32_t*)(fps + std::max(nscan, 1));
+    a.fpart_wown = a.fpart_comm + std::max(nscan, 1);
+    a.fpart_first = p32 + o_ff;
     a.tab_off = (const int64_t*)base;
     a.tab_cap = p32 + o_cap;
-    a.table = ws.hub_table.as<int32_t>();
     a.ins_hub = p32 + o_ih;
     a.ins_beg = p32 + o_ib;
     a.ins_end = p32 + o_ie;
@@ -340,12 +362,11 @@ lv_status plan_hubs(lv_graph* g, const LevelGraph& G, const int32_t* hub_verts, 
     a.scan_beg = p32 + o_sb;
     a.scan_end = p32 + o_se;
     a.nscan = nscan;
-    a.part_score = ws.hub_part.as<int64_t>();
-    a.part_comm = (int32_t*)(a.part_score + nparts);
-    a.part_wown = a.part_comm + nparts;
-    a.part_first_ins = p32 + o_fi;
-    a.part_first_scan = p32 + o_fs;
-    // keep the host vectors alive until the copies finish
+    HIP_TRY(hipMemsetAsync(a.fb_flag, 0, sizeof(int32_t) * (size_t)nhubs, s));
+    HIP_TRY(ws.hub_table.ensure(sizeof(int32_t) * 2 * (size_t)std::max<int64_t>(slots, 1)));
+    a.table = ws.hub_table.as<int32_t>();
+    HIP_TRY(launch_hub_clear(a.table, slots, s));
+    // the host vectors must outlive the asynchronous copies
     HIP_TRY(hipStreamSynchronize(s));
     return LV_OK;
 }
@@ -361,8 +382,8 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
     const size_t nb = sizeof(int32_t) * (size_t)std::max(n, 1);
     HIP_TRY(ws.comm.ensure(nb));
     HIP_TRY(ws.sigma.ensure(nb));
-    HIP_TRY(ws.mv_vert.ensure(nb));
-    HIP_TRY(ws.mv_comm.ensure(nb));
+    HIP_TRY(ws.cs.ensure(2 * nb));
+    HIP_TRY(ws.dec.ensure(nb));
     HIP_TRY(ws.cls.ensure(nb));
     HIP_TRY(ws.vert.ensure(nb));
     HIP_TRY(ws.cls_alt.ensure(nb));
@@ -403,6 +424,7 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
 
     HIP_TRY(launch_iota(ws.comm.as<int32_t>(), n, s));
     HIP_TRY(launch_copy_i32(ws.sigma.as<int32_t>(), G.k, n, s));
+    HIP_TRY(launch_pairs(n, ws.comm.as<int32_t>(), ws.sigma.as<int32_t>(), ws.cs.as<int2>(), s));
     uint32_t* d_count = (uint32_t*)(ws.small.as<char>() + 1024);
 
     MoveArgs a{};
@@ -412,11 +434,10 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
     a.k = G.k;
     a.comm = ws.comm.as<int32_t>();
     a.sigma = ws.sigma.as<int32_t>();
+    a.cs = ws.cs.as<int2>();
     a.M = g->M;
     a.mode = mode;
-    a.mv_vert = ws.mv_vert.as<int32_t>();
-    a.mv_comm = ws.mv_comm.as<int32_t>();
-    a.mv_count = d_count;
+    int32_t* dec_all = ws.dec.as<int32_t>();
 
     Timer tm;
     tm.on = (p.flags & LV_TIMING) != 0;
@@ -433,6 +454,7 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
         if (tm.on) HIP_TRY(tm.mark(&e0));
         for (int c = CLS_G8; c < CLS_HUB; ++c) {
             a.verts = vert_sorted + start[c];
+            a.dec = dec_all + start[c];
             a.nverts = start[c + 1] - start[c];
             if (a.nverts == 0) continue;
             if (tm.on) HIP_TRY(tm.mark(&kb[c]));
@@ -441,14 +463,16 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
             ++out.launches;
         }
         if (hubs.nhubs > 0) {
+            a.dec = dec_all + start[CLS_HUB];
             if (tm.on) HIP_TRY(tm.mark(&kb[CLS_HUB]));
             HIP_TRY(launch_hub_sweep(singleton, a, hubs.args, s));
             if (tm.on) HIP_TRY(tm.mark(&kend[CLS_HUB]));
             out.launches += singleton ? 2 : 3;
         }
         if (tm.on) HIP_TRY(tm.mark(&e1));
-        HIP_TRY(launch_apply(a.mv_vert, a.mv_comm, d_count, active, G.k, ws.comm.as<int32_t>(),
-                             ws.sigma.as<int32_t>(), s));
+        HIP_TRY(launch_apply(vert_sorted + start[CLS_G8], dec_all + start[CLS_G8], active, G.k,
+                             ws.comm.as<int32_t>(), ws.sigma.as<int32_t>(), d_count, s));
+        HIP_TRY(launch_pairs(n, ws.comm.as<int32_t>(), ws.sigma.as<int32_t>(), ws.cs.as<int2>(), s));
         if (tm.on) HIP_TRY(tm.mark(&e2));
         uint32_t cnt = 0;
         HIP_TRY(hipMemcpyAsync(g->pinned, d_count, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
@@ -501,63 +525,62 @@ lv_status renumber(lv_graph* g, int32_t n, int32_t* n2)
     return LV_OK;
 }
 
-// Aggregation (Algorithm 3): coarse CSR A' = S^T A S into ping-pong slot `slot`.
+// Aggregation (Algorithm 3): coarse CSR A' = S^T A S into ping-pong slot `slot`;
+// also Q_end = M * Sigma_in - sum_P k'_P^2, the modularity of the level's partition.
 lv_status aggregate(lv_graph* g, const LevelGraph& G, int32_t n2, int slot, Coarse& out)
 {
     Workspace& ws = g->ws;
     hipStream_t s = g->stream;
     const int64_t E = G.nnz;
+    const size_t E1 = (size_t)std::max<int64_t>(E, 1);
     const int colbits = bits_for(std::max<int64_t>(n2, 2));
     const int bits = 2 * colbits;
-    HIP_TRY(ws.keys.ensure(sizeof(uint64_t) * (size_t)std::max<int64_t>(E, 1)));
-    HIP_TRY(ws.keys_alt.ensure(sizeof(uint64_t) * (size_t)std::max<int64_t>(E, 1)));
-    HIP_TRY(ws.vals.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(E, 1)));
-    HIP_TRY(ws.vals_alt.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(E, 1)));
-    HIP_TRY(ws.head.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(E, 1)));
+    HIP_TRY(ws.keys.ensure(sizeof(uint64_t) * E1));
+    HIP_TRY(ws.keys_alt.ensure(sizeof(uint64_t) * E1));
+    HIP_TRY(ws.vals.ensure(sizeof(int32_t) * E1));
+    HIP_TRY(ws.vals_alt.ensure(sizeof(int32_t) * E1));
+    HIP_TRY(ws.head.ensure(sizeof(int32_t) * E1));
     HIP_TRY(ws.tmp.ensure(std::max(radix_tmp_bytes(E), scan_tmp_bytes(std::max<int64_t>(E, n2 + 1), 8))));
     HIP_TRY(ws.g_off[slot].ensure(sizeof(int32_t) * ((size_t)n2 + 1)));
     HIP_TRY(ws.g_k[slot].ensure(sizeof(int32_t) * (size_t)std::max(n2, 1)));
+    int64_t* d_q = (int64_t*)(ws.small.as<char>() + 2560);  // [0] Sigma_in, [1] sum k'^2
+    HIP_TRY(hipMemsetAsync(d_q, 0, 2 * sizeof(int64_t), s));
     HIP_TRY(launch_coarse_degree(G.n, ws.comm.as<int32_t>(), ws.flag.as<int32_t>(), ws.labels.as<int32_t>(),
                                  ws.sigma.as<int32_t>(), ws.g_k[slot].as<int32_t>(), s));
+    HIP_TRY(launch_sum_sq(ws.g_k[slot].as<int32_t>(), n2, d_q + 1, s));
     HIP_TRY(launch_build_keys(G.n, G.off, G.idx, G.w, E, ws.labels.as<int32_t>(), colbits, ws.keys.as<uint64_t>(),
-                              ws.vals.as<int32_t>(), s));
+                              ws.vals.as<int32_t>(), d_q, s));
     bool in_alt = false;
     HIP_TRY(radix_sort_u64(ws.keys.as<uint64_t>(), ws.vals.as<int32_t>(), ws.keys_alt.as<uint64_t>(),
                            ws.vals_alt.as<int32_t>(), E, bits, ws.tmp.p, ws.tmp.cap, &in_alt, s));
     const uint64_t* keys = in_alt ? ws.keys_alt.as<uint64_t>() : ws.keys.as<uint64_t>();
     const int32_t* vals = in_alt ? ws.vals_alt.as<int32_t>() : ws.vals.as<int32_t>();
+    uint64_t* keys2 = in_alt ? ws.keys.as<uint64_t>() : ws.keys_alt.as<uint64_t>();  // the free sort buffer
     int32_t* d_e2 = (int32_t*)(ws.small.as<char>() + 2304);
     HIP_TRY(launch_segment_heads(keys, E, ws.head.as<int32_t>(), s));
-    // pos reuses the head buffer (exclusive scan in place)
     HIP_TRY(scan_exclusive_i32(ws.head.as<int32_t>(), ws.head.as<int32_t>(), E, d_e2, ws.tmp.p, ws.tmp.cap, s));
+    int64_t q2[2];
     HIP_TRY(hipMemcpyAsync(g->pinned, d_e2, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(g->pinned + 2, d_q, sizeof q2, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     int32_t e2 = 0;
     std::memcpy(&e2, g->pinned, sizeof e2);
+    std::memcpy(q2, g->pinned + 2, sizeof q2);
     if (E == 0) e2 = 0;
     HIP_TRY(ws.g_idx[slot].ensure(sizeof(int32_t) * (size_t)std::max(e2, 1)));
     HIP_TRY(ws.g_w[slot].ensure(sizeof(int32_t) * (size_t)std::max(e2, 1)));
     int32_t* off2 = ws.g_off[slot].as<int32_t>();
     HIP_TRY(hipMemsetAsync(ws.g_w[slot].p, 0, sizeof(int32_t) * (size_t)std::max(e2, 1), s));
-    HIP_TRY(hipMemsetAsync(off2, 0, sizeof(int32_t) * ((size_t)n2 + 1), s));
     HIP_TRY(launch_segment_reduce(keys, vals, ws.head.as<int32_t>(), E, colbits, ws.g_idx[slot].as<int32_t>(),
-                                  ws.g_w[slot].as<int32_t>(), off2, s));
-    HIP_TRY(scan_exclusive_i32(off2, off2, (int64_t)n2 + 1, nullptr, ws.tmp.p, ws.tmp.cap, s));
+                                  ws.g_w[slot].as<int32_t>(), keys2, s));
+    HIP_TRY(launch_row_offsets(keys2, e2, n2, colbits, off2, s));
     out.n2 = n2;
     out.nnz2 = e2;
     out.off = off2;
     out.idx = ws.g_idx[slot].as<int32_t>();
     out.w = ws.g_w[slot].as<int32_t>();
     out.k = ws.g_k[slot].as<int32_t>();
-    // Q_end = M * trace(A') - sum k'^2 (modularity of the level's partition)
-    int64_t* d_q = (int64_t*)(ws.small.as<char>() + 2560);
-    HIP_TRY(hipMemsetAsync(d_q, 0, 2 * sizeof(int64_t), s));
-    HIP_TRY(launch_sum_sq_trace(n2, off2, out.idx, out.w, e2, out.k, d_q, s));
-    int64_t q2[2];
-    HIP_TRY(hipMemcpyAsync(g->pinned, d_q, sizeof q2, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    std::memcpy(q2, g->pinned, sizeof q2);
-    out.q_end = g->M * q2[1] - q2[0];
+    out.q_end = g->M * q2[0] - q2[1];
     return LV_OK;
 }
 
@@ -982,8 +1005,16 @@ lv_status lv_lpa(lv_graph* g, const lv_params* params, int32_t* labels, lv_memki
     if (tm.on) HIP_TRY(tm.mark(&t0));
     LV_TRY(renumber(g, g->n, &n2));
     if (tm.on) HIP_TRY(tm.mark(&t1));
-    int64_t qi = 0;
-    LV_TRY(modularity_impl(g, g->ws.labels.as<int32_t>(), &qi));
+    // Q_int of the final partition: M * Sigma_in - sum of the community volumes squared
+    int64_t* d_q = (int64_t*)(g->ws.small.as<char>() + 2816);
+    HIP_TRY(hipMemsetAsync(d_q, 0, 2 * sizeof(int64_t), g->stream));
+    HIP_TRY(launch_sigma_in(G.n, G.off, G.idx, G.w, G.nnz, g->ws.comm.as<int32_t>(), d_q, g->stream));
+    HIP_TRY(launch_sum_sq(g->ws.sigma.as<int32_t>(), G.n, d_q + 1, g->stream));
+    int64_t q2[2];
+    HIP_TRY(hipMemcpyAsync(g->pinned, d_q, sizeof q2, hipMemcpyDeviceToHost, g->stream));
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    std::memcpy(q2, g->pinned, sizeof q2);
+    const int64_t qi = g->M * q2[0] - q2[1];
     LV_TRY(copy_out(labels, g->ws.labels.as<int32_t>(), g->n, kind, g->stream));
     for (int32_t t = 0; t < moves_cap && t < (int32_t)so.moves.size(); ++t) moves_out[t] = so.moves[t];
     if (info) {

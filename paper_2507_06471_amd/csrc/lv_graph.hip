@@ -1,0 +1,275 @@
+// Graph preparation, validation and modularity kernels (gfx950).
+//
+// Graph model of the paper's Section II-A: undirected, integer weights, a loop
+// counts twice in the weighted degree (stored as A_vv = 2w).  Modularity of
+// Section II-C in integer form: Q_int = M * Sigma_in - sum_C Sigma_tot(C)^2.
+#include "lv_device.h"
+
+namespace lv {
+
+using namespace dev;
+
+namespace {
+
+// err bits: 1 offsets, 2 indices, 4 weights, 8 asymmetric, 16 overflow
+__global__ void k_check_offsets(int32_t n, const int32_t* off, int64_t nnz, int32_t* err)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += (int64_t)gridDim.x * blockDim.x) {
+        bool bad = false;
+        if (i == 0) bad = off[0] != 0;
+        if (i == n) bad = bad || (int64_t)off[n] != nnz;
+        if (i < n) bad = bad || off[i] > off[i + 1];
+        if (bad) atomicOr(err, 1);
+    }
+}
+
+__global__ __launch_bounds__(TILE_BS) void k_check_entries(int32_t n, const int32_t* off, const int32_t* idx,
+                                                            const int32_t* w, int64_t nnz, int32_t* err)
+{
+    for_tile_entries<TILE_BS, TILE_IT>(off, n, nnz, [&](int32_t r, int64_t e) {
+        const int32_t j = idx[e];
+        if (j < 0 || j >= n) atomicOr(err, 2);
+        else if (e > off[r] && idx[e - 1] >= j) atomicOr(err, 2);
+        if (w && w[e] < 1) atomicOr(err, 4);
+    });
+}
+
+__global__ __launch_bounds__(TILE_BS) void k_check_symmetric(int32_t n, const int32_t* off, const int32_t* idx,
+                                                              const int32_t* w, int64_t nnz, int32_t* err)
+{
+    for_tile_entries<TILE_BS, TILE_IT>(off, n, nnz, [&](int32_t r, int64_t e) {
+        const int32_t j = idx[e];
+        if (j == r) return;
+        int64_t lo = off[j], hi = off[j + 1];
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) / 2;
+            if (idx[mid] < r) lo = mid + 1; else hi = mid;
+        }
+        if (lo >= off[j + 1] || idx[lo] != r || (w && w[lo] != w[e])) atomicOr(err, 8);
+    });
+}
+
+// diag_pos[i] = entry of the loop (i, i), or -1
+__global__ void k_diag_scan(int32_t n, const int32_t* off, const int32_t* idx, int32_t* diag_pos, int32_t* any)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        int64_t lo = off[i], hi = off[i + 1];
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) / 2;
+            if (idx[mid] < i) lo = mid + 1; else hi = mid;
+        }
+        const bool has = lo < off[i + 1] && idx[lo] == i;
+        diag_pos[i] = has ? (int32_t)lo : -1;
+        if (has) atomicOr(any, 1);
+    }
+}
+
+// A = caller weights (or 1); each loop entry doubled
+__global__ void k_adjacency_copy(const int32_t* w_in, int64_t nnz, int32_t* w_out)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x)
+        w_out[e] = w_in ? w_in[e] : 1;
+}
+__global__ void k_adjacency_double(int32_t n, const int32_t* diag_pos, int32_t* w_out, int32_t* err)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t p = diag_pos[i];
+        if (p < 0) continue;
+        const int64_t v = 2 * (int64_t)w_out[p];
+        if (v > INT32_MAX) atomicOr(err, 16);
+        else w_out[p] = (int32_t)v;
+    }
+}
+
+// k64[r] += row sums: per-thread runs of one row, one atomic per run
+__global__ __launch_bounds__(TILE_BS) void k_row_sums(int32_t n, const int32_t* off, const int32_t* w, int64_t nnz,
+                                                       unsigned long long* k64)
+{
+    int32_t cur = -1;
+    int64_t acc = 0;
+    for_tile_entries<TILE_BS, TILE_IT>(off, n, nnz, [&](int32_t r, int64_t e) {
+        if (r != cur) {
+            if (cur >= 0) atomicAdd(&k64[cur], (unsigned long long)acc);
+            cur = r;
+            acc = 0;
+        }
+        acc += w[e];
+    });
+    if (cur >= 0) atomicAdd(&k64[cur], (unsigned long long)acc);
+}
+
+__global__ __launch_bounds__(256) void k_narrow_sum(int32_t n, const unsigned long long* k64, int32_t* k,
+                                                     unsigned long long* total)
+{
+    __shared__ unsigned long long red[4];
+    unsigned long long s = 0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const unsigned long long v = k64[i];
+        k[i] = v > (unsigned long long)INT32_MAX ? INT32_MAX : (int32_t)v;
+        s += v;
+    }
+    s = block_sum<256>(s, red);
+    if (threadIdx.x == 0) atomicAdd(total, s);
+}
+
+__global__ void k_degree_unit(int32_t n, const int32_t* off, int32_t* k)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        k[i] = off[i + 1] - off[i];
+}
+
+// out[0] += sum v^2 over an int32 array
+__global__ __launch_bounds__(256) void k_sum_sq(int64_t n, const int32_t* v, unsigned long long* out)
+{
+    __shared__ unsigned long long red[4];
+    unsigned long long s = 0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        s += (unsigned long long)((int64_t)v[i] * (int64_t)v[i]);
+    s = block_sum<256>(s, red);
+    if (threadIdx.x == 0 && s) atomicAdd(out, s);
+}
+
+// out[1] += trace (sum of diagonal entries)
+__global__ __launch_bounds__(TILE_BS) void k_trace(int32_t n, const int32_t* off, const int32_t* idx, const int32_t* w,
+                                                    int64_t nnz, unsigned long long* out)
+{
+    __shared__ unsigned long long red[4];
+    unsigned long long s = 0;
+    for_tile_entries<TILE_BS, TILE_IT>(off, n, nnz, [&](int32_t r, int64_t e) {
+        if (idx[e] == r) s += (unsigned long long)(w ? w[e] : 1);
+    });
+    s = block_sum<TILE_BS>(s, red);
+    if (threadIdx.x == 0 && s) atomicAdd(&out[1], s);
+}
+
+// out[0] += Sigma_in = sum of entries whose endpoints share a label
+__global__ __launch_bounds__(TILE_BS) void k_sigma_in(int32_t n, const int32_t* off, const int32_t* idx, const int32_t* w,
+                                                       int64_t nnz, const int32_t* labels, unsigned long long* out)
+{
+    __shared__ unsigned long long red[4];
+    unsigned long long s = 0;
+    for_tile_entries<TILE_BS, TILE_IT>(off, n, nnz, [&](int32_t r, int64_t e) {
+        if (labels[idx[e]] == labels[r]) s += (unsigned long long)(w ? w[e] : 1);
+    });
+    s = block_sum<TILE_BS>(s, red);
+    if (threadIdx.x == 0 && s) atomicAdd(&out[0], s);
+}
+
+// tot[label] += k_i, one atomic per distinct label of a wavefront
+__global__ __launch_bounds__(256) void k_label_volumes(int32_t n, const int32_t* k, const int32_t* labels,
+                                                       unsigned long long* tot)
+{
+    for (int64_t base = (int64_t)blockIdx.x * 256; base < n; base += (int64_t)gridDim.x * 256) {
+        const int64_t i = base + threadIdx.x;
+        const bool valid = i < n;
+        const int32_t lab = valid ? labels[i] : 0;
+        const unsigned long long kv = valid ? (unsigned long long)k[i] : 0ull;
+        wave_grouped_add<unsigned long long, unsigned long long>(tot, lab, kv, valid);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_sum_sq_u64(const unsigned long long* v, int64_t n, unsigned long long* out)
+{
+    __shared__ unsigned long long red[4];
+    unsigned long long s = 0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) s += v[i] * v[i];
+    s = block_sum<256>(s, red);
+    if (threadIdx.x == 0 && s) atomicAdd(out, s);
+}
+
+__global__ void k_check_labels(const int32_t* labels, int32_t n, int32_t* err)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        if (labels[i] < 0 || labels[i] >= n) atomicOr(err, 1);
+}
+
+}  // namespace
+
+hipError_t launch_check_offsets(int32_t n, const int32_t* off, int64_t nnz, int32_t* err, hipStream_t s)
+{
+    k_check_offsets<<<LV_GRID((int64_t)n + 1)>>>(n, off, nnz, err);
+    return hipGetLastError();
+}
+hipError_t launch_check_entries(int32_t n, const int32_t* off, const int32_t* idx, const int32_t* w, int64_t nnz,
+                                int32_t* err, hipStream_t s)
+{
+    if (nnz <= 0) return hipSuccess;
+    k_check_entries<<<tiles_for(n, nnz), TILE_BS, 0, s>>>(n, off, idx, w, nnz, err);
+    return hipGetLastError();
+}
+hipError_t launch_check_symmetric(int32_t n, const int32_t* off, const int32_t* idx, const int32_t* w, int64_t nnz,
+                                  int32_t* err, hipStream_t s)
+{
+    if (nnz <= 0) return hipSuccess;
+    k_check_symmetric<<<tiles_for(n, nnz), TILE_BS, 0, s>>>(n, off, idx, w, nnz, err);
+    return hipGetLastError();
+}
+hipError_t launch_diag_scan(int32_t n, const int32_t* off, const int32_t* idx, int32_t* diag_pos, int32_t* any,
+                            hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    k_diag_scan<<<LV_GRID(n)>>>(n, off, idx, diag_pos, any);
+    return hipGetLastError();
+}
+hipError_t launch_adjacency_weights(int32_t n, const int32_t* w_in, const int32_t* diag_pos, int64_t nnz,
+                                    int32_t* w_out, int32_t* err, hipStream_t s)
+{
+    if (nnz > 0) k_adjacency_copy<<<LV_GRID(nnz)>>>(w_in, nnz, w_out);
+    if (n > 0) k_adjacency_double<<<LV_GRID(n)>>>(n, diag_pos, w_out, err);
+    return hipGetLastError();
+}
+hipError_t launch_row_sums(int32_t n, const int32_t* off, const int32_t* w, int64_t nnz, int32_t* k, int64_t* k64,
+                           int64_t* total, hipStream_t s)
+{
+    hipError_t e = hipMemsetAsync(k64, 0, sizeof(int64_t) * (size_t)(n > 0 ? n : 1), s);
+    if (e != hipSuccess) return e;
+    if (nnz > 0) k_row_sums<<<tiles_for(n, nnz), TILE_BS, 0, s>>>(n, off, w, nnz, (unsigned long long*)k64);
+    if (n > 0)
+        k_narrow_sum<<<grid_for(n, 256, 4096), 256, 0, s>>>(n, (const unsigned long long*)k64, k,
+                                                            (unsigned long long*)total);
+    return hipGetLastError();
+}
+hipError_t launch_degree_unit(int32_t n, const int32_t* off, int32_t* k, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    k_degree_unit<<<LV_GRID(n)>>>(n, off, k);
+    return hipGetLastError();
+}
+hipError_t launch_sum_sq_trace(int32_t n, const int32_t* off, const int32_t* idx, const int32_t* w, int64_t nnz,
+                               const int32_t* k, int64_t* out2, hipStream_t s)
+{
+    if (n > 0) k_sum_sq<<<grid_for(n, 256, 4096), 256, 0, s>>>(n, k, (unsigned long long*)out2);
+    if (nnz > 0) k_trace<<<tiles_for(n, nnz), TILE_BS, 0, s>>>(n, off, idx, w, nnz, (unsigned long long*)out2);
+    return hipGetLastError();
+}
+hipError_t launch_sum_sq(const int32_t* v, int64_t n, int64_t* out, hipStream_t s)
+{
+    if (n > 0) k_sum_sq<<<grid_for(n, 256, 4096), 256, 0, s>>>(n, v, (unsigned long long*)out);
+    return hipGetLastError();
+}
+hipError_t launch_sigma_in(int32_t n, const int32_t* off, const int32_t* idx, const int32_t* w, int64_t nnz,
+                           const int32_t* labels, int64_t* out, hipStream_t s)
+{
+    if (nnz > 0)
+        k_sigma_in<<<tiles_for(n, nnz), TILE_BS, 0, s>>>(n, off, idx, w, nnz, labels, (unsigned long long*)out);
+    return hipGetLastError();
+}
+hipError_t launch_modularity_parts(int32_t n, const int32_t* off, const int32_t* idx, const int32_t* w, int64_t nnz,
+                                   const int32_t* k, const int32_t* labels, int64_t* tot, int64_t* out2, hipStream_t s)
+{
+    if (n > 0) k_label_volumes<<<grid_for(n, 256, 65536), 256, 0, s>>>(n, k, labels, (unsigned long long*)tot);
+    if (nnz > 0)
+        k_sigma_in<<<tiles_for(n, nnz), TILE_BS, 0, s>>>(n, off, idx, w, nnz, labels, (unsigned long long*)out2);
+    if (n > 0)
+        k_sum_sq_u64<<<grid_for(n, 256, 4096), 256, 0, s>>>((const unsigned long long*)tot, n,
+                                                            (unsigned long long*)(out2 + 1));
+    return hipGetLastError();
+}
+hipError_t launch_check_labels(const int32_t* labels, int32_t n, int32_t* err, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    k_check_labels<<<LV_GRID(n)>>>(labels, n, err);
+    return hipGetLastError();
+}
+
+}  // namespace lv

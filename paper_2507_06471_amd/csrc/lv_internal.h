@@ -36,39 +36,48 @@ struct MoveArgs {
     const int32_t* k;       // weighted degree, < 2^31
     const int32_t* comm;    // labels of the previous sweep
     const int32_t* sigma;   // community volumes of the previous sweep, < 2^31
+    const int2* cs;         // per vertex (comm[v], sigma[comm[v]]) of the previous sweep
     int64_t M;              // total volume
     const int32_t* verts;   // vertices of this class
     int32_t nverts;
     int32_t dir;            // DIR_DOWN / DIR_UP
     int32_t mode;           // MODE_LOUVAIN / MODE_LPA
-    int32_t* mv_vert;       // mover list (vertex, target)
-    int32_t* mv_comm;
-    uint32_t* mv_count;
+    int32_t* dec;           // decision per listed vertex: target community or -1
 };
 
-// Global-table (hub) path: per-hub layout built on the host once per level.
+// Vertices above the workgroup classes: P partitions per vertex, each a
+// 1024-thread workgroup with an LDS table; a global-table fallback per vertex
+// for partitions that overflow.  Layout built on the host once per level.
 struct HubArgs {
     int32_t nhubs;
-    const int32_t* hub_vert;     // [nhubs]
-    const int64_t* tab_off;      // [nhubs] slot offset of the hub's table
-    const int32_t* tab_cap;      // [nhubs] slots (power of two)
-    int32_t* table;              // 2 ints per slot: key, value
-    // insert / singleton blocks: block b covers entries [blk_beg[b], blk_end[b]) of hub blk_hub[b]
-    const int32_t* ins_hub;
+    uint32_t part_mask;            // LDS slots of a partition workgroup - 1
+    const int32_t* hub_vert;       // [nhubs]
+    const int32_t* hub_parts;      // [nhubs] P
+    const int32_t* hub_first_blk;  // [nhubs+1] first partition workgroup of each hub
+    const int32_t* blk_hub;        // [nblk]
+    const int32_t* blk_part;       // [nblk]
+    int32_t nblk;
+    int64_t* part_score;           // [nblk] partial results
+    int32_t* part_comm;
+    int32_t* part_wown;
+    int32_t* part_flag;            // 1 = the partition's table overflowed
+    int32_t* fb_flag;              // [nhubs] hub needs the global-table fallback
+    // fallback: global open-addressing tables (2 ints per slot: key, value)
+    const int64_t* tab_off;        // [nhubs] slot offset of the hub's table
+    const int32_t* tab_cap;        // [nhubs] slots (power of two, 0 if P == 1)
+    int32_t* table;
+    const int32_t* ins_hub;        // insert workgroup b: entries [ins_beg, ins_end) of hub ins_hub
     const int32_t* ins_beg;
     const int32_t* ins_end;
     int32_t nins;
-    // scan blocks: block b scans slots [scan_beg[b], scan_end[b]) of hub scan_hub[b]
-    const int32_t* scan_hub;
+    const int32_t* scan_hub;       // scan workgroup b: slots [scan_beg, scan_end) of hub scan_hub
     const int32_t* scan_beg;
     const int32_t* scan_end;
     int32_t nscan;
-    // partial results: one per insert block (singleton sweep) or scan block
-    int64_t* part_score;
-    int32_t* part_comm;
-    int32_t* part_wown;
-    const int32_t* part_first_ins;   // [nhubs+1] partial ranges for the singleton sweep
-    const int32_t* part_first_scan;  // [nhubs+1] partial ranges for later sweeps
+    int64_t* fpart_score;          // [nscan]
+    int32_t* fpart_comm;
+    int32_t* fpart_wown;
+    const int32_t* fpart_first;    // [nhubs+1] scan-workgroup range of each hub
 };
 
 // ---- launchers (lv_kernels.hip) ----
@@ -125,26 +134,34 @@ hipError_t launch_class_entries(const int32_t* verts_sorted, const int32_t* star
 hipError_t launch_move_class(int cls, bool singleton, const MoveArgs& a, hipStream_t s);
 hipError_t launch_hub_clear(int32_t* table, int64_t slots, hipStream_t s);
 hipError_t launch_hub_sweep(bool singleton, const MoveArgs& a, const HubArgs& h, hipStream_t s);
-hipError_t launch_apply(const int32_t* mv_vert, const int32_t* mv_comm, const uint32_t* mv_count,
-                        int32_t max_movers, const int32_t* k, int32_t* comm, int32_t* sigma,
-                        hipStream_t s);
+hipError_t launch_pairs(int32_t n, const int32_t* comm, const int32_t* sigma, int2* cs, hipStream_t s);
+// commit the decisions dec[0..m) of vertices verts[0..m); *moves += movers
+hipError_t launch_apply(const int32_t* verts, const int32_t* dec, int32_t m, const int32_t* k, int32_t* comm,
+                        int32_t* sigma, uint32_t* moves, hipStream_t s);
 
 // renumber + aggregation
 hipError_t launch_renumber(int32_t n, const int32_t* comm, int32_t* minv, int32_t* flag, int32_t* pos,
                            int32_t* labels, int32_t* n_out, void* tmp, size_t tmp_bytes, hipStream_t s);
 hipError_t launch_coarse_degree(int32_t n, const int32_t* comm, const int32_t* flag, const int32_t* labels,
                                 const int32_t* sigma, int32_t* k2, hipStream_t s);
+// keys = (label(i) << colbits) | label(j); *sigma_in += weight inside communities (caller zeroes it)
 hipError_t launch_build_keys(int32_t n, const int32_t* off, const int32_t* idx, const int32_t* w,
                              int64_t nnz, const int32_t* labels, int colbits, uint64_t* keys, int32_t* vals,
-                             hipStream_t s);
+                             int64_t* sigma_in, hipStream_t s);
 hipError_t launch_segment_heads(const uint64_t* keys, int64_t n, int32_t* head, hipStream_t s);
+// w2 must be zeroed; writes idx2/w2/keys2 of each run of equal keys
 hipError_t launch_segment_reduce(const uint64_t* keys, const int32_t* vals, const int32_t* pos, int64_t n,
-                                 int colbits, int32_t* idx2, int32_t* w2, int32_t* rowcnt, hipStream_t s);
+                                 int colbits, int32_t* idx2, int32_t* w2, uint64_t* keys2, hipStream_t s);
+hipError_t launch_row_offsets(const uint64_t* keys2, int64_t e2, int32_t n2, int colbits, int32_t* off2,
+                              hipStream_t s);
 hipError_t launch_compose(int32_t n0, int32_t* final_labels, const int32_t* labels, hipStream_t s);
 hipError_t launch_modularity_parts(int32_t n, const int32_t* off, const int32_t* idx, const int32_t* w,
                                    int64_t nnz, const int32_t* k, const int32_t* labels, int64_t* tot,
                                    int64_t* out2, hipStream_t s);
-hipError_t launch_sum_sq_i64(const int64_t* v, int64_t n, int64_t* out, hipStream_t s);
+// *out += sum v^2; *out += Sigma_in of labels (caller zeroes)
+hipError_t launch_sum_sq(const int32_t* v, int64_t n, int64_t* out, hipStream_t s);
+hipError_t launch_sigma_in(int32_t n, const int32_t* off, const int32_t* idx, const int32_t* w, int64_t nnz,
+                           const int32_t* labels, int64_t* out, hipStream_t s);
 hipError_t launch_check_labels(const int32_t* labels, int32_t n, int32_t* err, hipStream_t s);
 
 }  // namespace lv

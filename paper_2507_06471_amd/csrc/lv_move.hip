@@ -1,0 +1,565 @@
+// Move step of local moving (Algorithm 2 of arXiv 2507.06471; Algorithm 1's
+// PLPMove in LPA mode) on gfx950.
+//
+// Every vertex i sums its edge weights per neighbouring community,
+// W_i(C) = cut_w(i, C \ {i}), then takes the best community by the exact
+// integer score M*W_i(C) - k_i*Sigma_tot(C) (Louvain; Equation 1's gain is
+// 2*(score - stay)/M^2) or W_i(C) (LPA), ties to the smallest id, and records
+// a move if it beats staying and lies in the sweep's direction.  All reads are
+// of the previous sweep's state.  Each vertex's decision (target community or
+// -1) is written to its slot of the class-sorted vertex list; k_apply then
+// commits the moves.
+//
+// Scheduling by the vertex's number of CSR entries L (degree classes):
+//   L <= 8      8 lanes per vertex, LDS table of <= 16 slots
+//   L <= 32     32 lanes, <= 64 slots
+//   L <= 128    a wavefront, <= 256 slots
+//   L <= 512    a 256-thread workgroup, <= 1024 slots
+//   L <= 4096   a 512-thread workgroup, <= 8192 slots
+//   L >  4096   P = ceil(L / part_keys) 1024-thread workgroups per vertex;
+//               workgroup p aggregates the communities of hash partition p in
+//               an LDS table of part_slots (default 16384) slots; partial
+//               results are merged per vertex.  If a partition's table ever fills up, that vertex
+//               is redone with a global-memory table (never expected with
+//               hashed partitions; it keeps every input exact and finite).
+// In the first sweep of a level every community is a single vertex and CSR
+// columns are unique, so W_i(j) = A_ij and entries are scored directly.
+//
+// Memory traffic: in the classes up to 512 entries a neighbour's community
+// and that community's volume are read together as one 8-byte pair
+// cs[j] = (comm[j], Sigma_tot(comm[j])) (refreshed after every commit), so an
+// entry costs one random gather and the volume is kept in the LDS slot beside
+// the summed weight.  The two largest classes keep 8-byte slots (larger
+// tables per workgroup) and gather Sigma_tot once per distinct community.
+// CSR indices and weights are streamed with non-temporal loads so they do not
+// evict the frequently gathered values from L2.
+#include "lv_device.h"
+
+namespace lv {
+
+using namespace dev;
+
+namespace {
+
+struct Bounds { int32_t b[NUM_CLS]; };
+
+__global__ void k_classify(int32_t n, const int32_t* off, Bounds bd, uint32_t* cls, int32_t* vert)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t L = off[i + 1] - off[i];
+        uint32_t c = CLS_NONE;
+        if (L > 0) {
+            c = CLS_HUB;
+            for (int q = CLS_G8; q < CLS_HUB; ++q)
+                if (L <= bd.b[q]) { c = (uint32_t)q; break; }
+        }
+        cls[i] = c;
+        vert[i] = (int32_t)i;
+    }
+}
+
+__global__ void k_class_starts(const uint32_t* cls, int32_t n, int32_t* start)
+{
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+        if (t == 0 || cls[t] != cls[t - 1]) start[cls[t]] = (int32_t)t;
+}
+
+__global__ __launch_bounds__(256) void k_class_entries(const int32_t* verts, int32_t lo, int32_t hi, const int32_t* off,
+                                                       unsigned long long* out)
+{
+    __shared__ unsigned long long red[4];
+    unsigned long long s = 0;
+    for (int64_t t = lo + (int64_t)blockIdx.x * 256 + threadIdx.x; t < hi; t += (int64_t)gridDim.x * 256) {
+        const int32_t v = verts[t];
+        s += (unsigned long long)(off[v + 1] - off[v]);
+    }
+    s = block_sum<256>(s, red);
+    if (threadIdx.x == 0 && s) atomicAdd(out, s);
+}
+
+__global__ void k_gather_rows(const int32_t* verts, int32_t m, const int32_t* off, int32_t* beg, int32_t* len)
+{
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < m; t += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t v = verts[t];
+        beg[t] = off[v];
+        len[t] = off[v + 1] - off[v];
+    }
+}
+
+constexpr int UNROLL = 4;
+
+// Decision of vertex-list slot `pos`: the best community if it beats staying
+// and lies in the sweep's direction, else -1.
+__device__ __forceinline__ void decide_store(const MoveArgs& a, int64_t pos, int32_t A, int32_t sA, int64_t ki,
+                                             int64_t best_s, int32_t best_c, int32_t w_own)
+{
+    bool mover = false;
+    if (best_c != INT32_MAX) {
+        const bool louvain = a.mode == MODE_LOUVAIN;
+        const int64_t stay = louvain ? a.M * w_own - ki * ((int64_t)sA - ki) : (int64_t)w_own;
+        const bool dir_ok = a.dir == DIR_DOWN ? best_c < A : best_c > A;
+        mover = best_s > stay && dir_ok;
+    }
+    a.dec[pos] = mover ? best_c : -1;
+}
+
+// Score every entry of [e_beg, e_end) as its own community (first sweep of a level).
+template <int STRIDE>
+__device__ __forceinline__ void score_entries_singleton(const MoveArgs& a, int32_t i, int64_t ki, int32_t e_beg,
+                                                        int32_t e_end, int64_t& best_s, int32_t& best_c)
+{
+    const bool louvain = a.mode == MODE_LOUVAIN;
+    for (int32_t e0 = e_beg; e0 < e_end; e0 += STRIDE * UNROLL) {
+        int32_t jj[UNROLL], ww[UNROLL], sg[UNROLL];
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+            const int32_t e = e0 + u * STRIDE;
+            const bool ok = e < e_end;
+            jj[u] = ok ? __builtin_nontemporal_load(&a.idx[e]) : i;
+            ww[u] = (ok && a.w) ? __builtin_nontemporal_load(&a.w[e]) : 1;
+        }
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) sg[u] = (louvain && jj[u] != i) ? a.cs[jj[u]].y : 0;
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+            if (jj[u] == i) continue;
+            const int64_t s = louvain ? a.M * ww[u] - ki * (int64_t)sg[u] : (int64_t)ww[u];
+            if (better(s, jj[u], best_s, best_c)) { best_s = s; best_c = jj[u]; }
+        }
+    }
+}
+
+// Insert (C, W) into an LDS open-addressing table of `mask`+1 slots that is
+// guaranteed to have room (distinct keys < slots); the thread that claims a
+// slot stores the community's volume S beside it.
+template <bool SIG>
+__device__ __forceinline__ void lds_insert(int32_t* key, int32_t* val, int32_t* sig, uint32_t mask, int32_t C,
+                                           int32_t W, int32_t S)
+{
+    uint32_t h = mix32(C) & mask;
+    for (;;) {
+        const int32_t prev = atomicCAS(&key[h], EMPTY_KEY, C);
+        if constexpr (SIG) if (prev == EMPTY_KEY) sig[h] = S;
+        if (prev == EMPTY_KEY || prev == C) { atomicAdd(&val[h], W); return; }
+        h = (h + 1) & mask;
+    }
+}
+
+// Aggregate the entries [e_beg, e_end) (stride STRIDE from the caller's lane)
+// of vertex i into an LDS table, optionally only communities of partition
+// `part` of P.  Returns false if the bounded table had no room (only
+// possible with P > 1).
+template <int STRIDE, bool BOUNDED, bool SIG>
+__device__ __forceinline__ bool aggregate_entries(const MoveArgs& a, int32_t i, int32_t e_beg, int32_t e_end,
+                                                  int32_t* key, int32_t* val, int32_t* sig, uint32_t mask, uint32_t P,
+                                                  uint32_t part)
+{
+    bool ok_all = true;
+    for (int32_t e0 = e_beg; e0 < e_end; e0 += STRIDE * UNROLL) {
+        int32_t jj[UNROLL], ww[UNROLL];
+        int2 cc[UNROLL];
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+            const int32_t e = e0 + u * STRIDE;
+            const bool ok = e < e_end;
+            jj[u] = ok ? __builtin_nontemporal_load(&a.idx[e]) : i;
+            ww[u] = (ok && a.w) ? __builtin_nontemporal_load(&a.w[e]) : 1;
+        }
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+            if constexpr (SIG) cc[u] = jj[u] != i ? a.cs[jj[u]] : make_int2(EMPTY_KEY, 0);
+            else cc[u] = make_int2(jj[u] != i ? a.comm[jj[u]] : EMPTY_KEY, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+            const int32_t C = cc[u].x;
+            if (C == EMPTY_KEY) continue;
+            if constexpr (BOUNDED) {
+                if (P > 1 && part_of(C, P) != part) continue;
+                uint32_t h = mix32(C) & mask;
+                uint32_t probes = 0;
+                for (;;) {
+                    const int32_t prev = atomicCAS(&key[h], EMPTY_KEY, C);
+                    if constexpr (SIG) if (prev == EMPTY_KEY) sig[h] = cc[u].y;
+                    if (prev == EMPTY_KEY || prev == C) { atomicAdd(&val[h], ww[u]); break; }
+                    if (++probes > mask) { ok_all = false; break; }
+                    h = (h + 1) & mask;
+                }
+            } else {
+                lds_insert<SIG>(key, val, sig, mask, C, ww[u], cc[u].y);
+            }
+        }
+    }
+    return ok_all;
+}
+
+// Scan a table's slots [t0, T) step STRIDE: own-community weight and best candidate.
+template <int STRIDE, bool SIG>
+__device__ __forceinline__ void scan_table(const MoveArgs& a, const int32_t* key, const int32_t* val,
+                                           const int32_t* sig, uint32_t t0, uint32_t T, int32_t A, int64_t ki,
+                                           int64_t& best_s, int32_t& best_c, int32_t& w_own)
+{
+    const bool louvain = a.mode == MODE_LOUVAIN;
+    for (uint32_t t = t0; t < T; t += STRIDE) {
+        const int32_t C = key[t];
+        if (C == EMPTY_KEY) continue;
+        const int32_t W = val[t];
+        if (C == A) { w_own = W; continue; }
+        const int64_t s = louvain ? a.M * W - ki * (int64_t)(SIG ? sig[t] : a.sigma[C]) : (int64_t)W;
+        if (better(s, C, best_s, best_c)) { best_s = s; best_c = C; }
+    }
+}
+
+// One group of G lanes per vertex (G <= BS); LDS table of up to SLOTS slots.
+template <int BS, int G, int SLOTS, bool SINGLETON, bool SIG>
+__global__ __launch_bounds__(BS) void k_move(MoveArgs a)
+{
+    constexpr int NG = BS / G;
+    constexpr int TBL = SINGLETON ? 1 : NG * SLOTS;
+    __shared__ int32_t s_key[TBL];
+    __shared__ int32_t s_val[TBL];
+    __shared__ int32_t s_sig[SIG ? TBL : 1];
+    __shared__ int64_t rs[BS / WAVE];
+    __shared__ int32_t rc[BS / WAVE], rw[BS / WAVE];
+
+    const int g = threadIdx.x / G, lane = threadIdx.x % G;
+    const int64_t vi = (int64_t)blockIdx.x * NG + g;
+    const bool has = vi < a.nverts;
+    const int32_t i = has ? a.verts[vi] : 0;
+    const int32_t beg = has ? a.off[i] : 0, end = has ? a.off[i + 1] : 0;
+    const int2 self = has ? a.cs[i] : make_int2(0, 0);
+    const int32_t A = self.x;
+    const int64_t ki = has ? a.k[i] : 0;
+    int64_t best_s = INT64_MIN;
+    int32_t best_c = INT32_MAX, w_own = 0;
+
+    if constexpr (SINGLETON) {
+        score_entries_singleton<G>(a, i, ki, beg + lane, end, best_s, best_c);
+    } else {
+        int32_t* key = s_key + g * SLOTS;
+        int32_t* val = s_val + g * SLOTS;
+        int32_t* sig = SIG ? s_sig + g * SLOTS : s_sig;
+        const uint32_t T = min((uint32_t)SLOTS, pow2_at_least(2u * (uint32_t)(end - beg)));
+        for (uint32_t t = lane; t < T; t += G) { key[t] = EMPTY_KEY; val[t] = 0; }
+        __syncthreads();
+        aggregate_entries<G, false, SIG>(a, i, beg + lane, end, key, val, sig, T - 1u, 1u, 0u);
+        __syncthreads();
+        scan_table<G, SIG>(a, key, val, sig, lane, T, A, ki, best_s, best_c, w_own);
+    }
+
+    if constexpr (G <= WAVE) {
+        group_reduce<G>(best_s, best_c, w_own);
+    } else {
+        group_reduce<WAVE>(best_s, best_c, w_own);
+        const int wid = threadIdx.x / WAVE;
+        if (lane_id() == 0) { rs[wid] = best_s; rc[wid] = best_c; rw[wid] = w_own; }
+        __syncthreads();
+        if (lane == 0) {
+            constexpr int WPG = G / WAVE;
+            for (int w = 1; w < WPG; ++w) {
+                const int src = g * WPG + w;
+                if (better(rs[src], rc[src], best_s, best_c)) { best_s = rs[src]; best_c = rc[src]; }
+                w_own = max(w_own, rw[src]);
+            }
+        }
+    }
+    if (has && lane == 0) decide_store(a, vi, A, self.y, ki, best_s, best_c, w_own);
+}
+
+template <int BS, int G, int SLOTS, bool SIG>
+hipError_t launch_move_t(bool singleton, const MoveArgs& a, hipStream_t s)
+{
+    if (a.nverts <= 0) return hipSuccess;
+    constexpr int NG = BS / G;
+    const unsigned grid = (unsigned)((a.nverts + NG - 1) / NG);
+    if (singleton) k_move<BS, G, SLOTS, true, false><<<grid, BS, 0, s>>>(a);
+    else k_move<BS, G, SLOTS, false, SIG><<<grid, BS, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ partitioned path (L > 4096)
+constexpr int PBS = 1024;
+constexpr int PSLOTS = 16384;
+
+template <bool SINGLETON>
+__global__ __launch_bounds__(PBS) void k_hub_part(MoveArgs a, HubArgs h)
+{
+    __shared__ int32_t s_key[SINGLETON ? 1 : PSLOTS];
+    __shared__ int32_t s_val[SINGLETON ? 1 : PSLOTS];
+    __shared__ int32_t s_sig[1];
+    __shared__ int64_t rs[PBS / WAVE];
+    __shared__ int32_t rc[PBS / WAVE], rw[PBS / WAVE];
+    __shared__ int32_t s_over;
+    const int32_t b = blockIdx.x;
+    const int32_t hh = h.blk_hub[b];
+    const uint32_t part = (uint32_t)h.blk_part[b], P = (uint32_t)h.hub_parts[hh];
+    const int32_t i = h.hub_vert[hh];
+    const int32_t beg = a.off[i], end = a.off[i + 1];
+    const int32_t A = a.cs[i].x;
+    const int64_t ki = a.k[i];
+    int64_t best_s = INT64_MIN;
+    int32_t best_c = INT32_MAX, w_own = 0;
+    int32_t over = 0;
+    if constexpr (SINGLETON) {
+        const int64_t L = end - beg;
+        const int32_t cb = beg + (int32_t)(L * part / P), ce = beg + (int32_t)(L * (part + 1) / P);
+        score_entries_singleton<PBS>(a, i, ki, cb + (int32_t)threadIdx.x, ce, best_s, best_c);
+    } else {
+        const uint32_t T = h.part_mask + 1u;
+        for (uint32_t t = threadIdx.x; t < T; t += PBS) { s_key[t] = EMPTY_KEY; s_val[t] = 0; }
+        if (threadIdx.x == 0) s_over = 0;
+        __syncthreads();
+        if (!aggregate_entries<PBS, true, false>(a, i, beg + (int32_t)threadIdx.x, end, s_key, s_val, s_sig,
+                                                 h.part_mask, P, part))
+            s_over = 1;
+        __syncthreads();
+        over = s_over;
+        if (!over) scan_table<PBS, false>(a, s_key, s_val, s_sig, threadIdx.x, T, A, ki, best_s, best_c, w_own);
+    }
+    block_reduce_best<PBS>(best_s, best_c, w_own, rs, rc, rw);
+    if (threadIdx.x == 0) {
+        h.part_score[b] = best_s;
+        h.part_comm[b] = best_c;
+        h.part_wown[b] = w_own;
+        h.part_flag[b] = over;
+    }
+}
+
+// One wavefront per hub: merge the partitions' partial results, decide.
+__global__ __launch_bounds__(256) void k_hub_finalize(MoveArgs a, HubArgs h)
+{
+    const int64_t hh64 = (int64_t)blockIdx.x * (256 / WAVE) + threadIdx.x / WAVE;
+    const bool has = hh64 < h.nhubs;
+    const int32_t hh = has ? (int32_t)hh64 : 0;
+    int64_t best_s = INT64_MIN;
+    int32_t best_c = INT32_MAX, w_own = 0, i = 0, A = 0, sA = 0, flag = 0;
+    int64_t ki = 0;
+    if (has) {
+        i = h.hub_vert[hh];
+        const int2 self = a.cs[i];
+        A = self.x;
+        sA = self.y;
+        ki = a.k[i];
+        for (int32_t p = h.hub_first_blk[hh] + (int32_t)lane_id(); p < h.hub_first_blk[hh + 1]; p += WAVE) {
+            if (better(h.part_score[p], h.part_comm[p], best_s, best_c)) { best_s = h.part_score[p]; best_c = h.part_comm[p]; }
+            w_own = max(w_own, h.part_wown[p]);
+            flag |= h.part_flag[p];
+        }
+    }
+    group_reduce<WAVE>(best_s, best_c, w_own);
+    const bool overflowed = __ballot(flag != 0) != 0;
+    if (has && overflowed && lane_id() == 0) h.fb_flag[hh] = 1;
+    if (has && !overflowed && lane_id() == 0) decide_store(a, hh, A, sA, ki, best_s, best_c, w_own);
+}
+
+// ---- global-table fallback for hubs whose partition tables overflowed
+constexpr int FBS = 256;
+
+__global__ __launch_bounds__(FBS) void k_fb_insert(MoveArgs a, HubArgs h)
+{
+    const int b = blockIdx.x;
+    const int32_t hh = h.ins_hub[b];
+    if (!h.fb_flag[hh]) return;
+    const int32_t i = h.hub_vert[hh];
+    const uint32_t mask = (uint32_t)h.tab_cap[hh] - 1u;
+    int32_t* tab = h.table + 2 * h.tab_off[hh];
+    for (int32_t e = h.ins_beg[b] + threadIdx.x; e < h.ins_end[b]; e += FBS) {
+        const int32_t j = a.idx[e];
+        if (j == i) continue;
+        const int32_t C = a.cs[j].x;
+        const int32_t W = a.w ? a.w[e] : 1;
+        uint32_t slot = mix32(C) & mask;
+        for (;;) {
+            const int32_t prev = atomicCAS(&tab[2 * slot], EMPTY_KEY, C);
+            if (prev == EMPTY_KEY || prev == C) { atomicAdd(&tab[2 * slot + 1], W); break; }
+            slot = (slot + 1) & mask;
+        }
+    }
+}
+
+__global__ __launch_bounds__(FBS) void k_fb_scan(MoveArgs a, HubArgs h)
+{
+    __shared__ int64_t rs[FBS / WAVE];
+    __shared__ int32_t rc[FBS / WAVE], rw[FBS / WAVE];
+    const int b = blockIdx.x;
+    const int32_t hh = h.scan_hub[b];
+    if (!h.fb_flag[hh]) return;
+    const int32_t i = h.hub_vert[hh];
+    const int32_t A = a.cs[i].x;
+    const int64_t ki = a.k[i];
+    const bool louvain = a.mode == MODE_LOUVAIN;
+    int32_t* tab = h.table + 2 * h.tab_off[hh];
+    int64_t best_s = INT64_MIN;
+    int32_t best_c = INT32_MAX, w_own = 0;
+    for (int32_t t = h.scan_beg[b] + threadIdx.x; t < h.scan_end[b]; t += FBS) {
+        const int32_t C = tab[2 * t];
+        if (C == EMPTY_KEY) continue;
+        const int32_t W = tab[2 * t + 1];
+        tab[2 * t] = EMPTY_KEY;
+        tab[2 * t + 1] = 0;
+        if (C == A) { w_own = W; continue; }
+        const int64_t s = louvain ? a.M * W - ki * (int64_t)a.sigma[C] : (int64_t)W;
+        if (better(s, C, best_s, best_c)) { best_s = s; best_c = C; }
+    }
+    block_reduce_best<FBS>(best_s, best_c, w_own, rs, rc, rw);
+    if (threadIdx.x == 0) { h.fpart_score[b] = best_s; h.fpart_comm[b] = best_c; h.fpart_wown[b] = w_own; }
+}
+
+__global__ __launch_bounds__(256) void k_fb_finalize(MoveArgs a, HubArgs h)
+{
+    const int64_t hh64 = (int64_t)blockIdx.x * (256 / WAVE) + threadIdx.x / WAVE;
+    const bool has = hh64 < h.nhubs && h.fb_flag[hh64];
+    const int32_t hh = has ? (int32_t)hh64 : 0;
+    int64_t best_s = INT64_MIN;
+    int32_t best_c = INT32_MAX, w_own = 0, i = 0, A = 0, sA = 0;
+    int64_t ki = 0;
+    if (has) {
+        i = h.hub_vert[hh];
+        const int2 self = a.cs[i];
+        A = self.x;
+        sA = self.y;
+        ki = a.k[i];
+        for (int32_t p = h.fpart_first[hh] + (int32_t)lane_id(); p < h.fpart_first[hh + 1]; p += WAVE) {
+            if (better(h.fpart_score[p], h.fpart_comm[p], best_s, best_c)) { best_s = h.fpart_score[p]; best_c = h.fpart_comm[p]; }
+            w_own = max(w_own, h.fpart_wown[p]);
+        }
+    }
+    group_reduce<WAVE>(best_s, best_c, w_own);
+    if (has && lane_id() == 0) {
+        decide_store(a, hh, A, sA, ki, best_s, best_c, w_own);
+        h.fb_flag[hh] = 0;
+    }
+}
+
+// ------------------------------------------------------------------ commit (K7)
+// Apply the decisions of the m listed vertices: labels, and community volumes
+// with one atomic per distinct community per wavefront (integer sums, so the
+// order is irrelevant); *moves += number of movers.
+__global__ __launch_bounds__(256) void k_apply(const int32_t* verts, const int32_t* dec, int32_t m, const int32_t* k,
+                                               int32_t* comm, int32_t* sigma, uint32_t* moves)
+{
+    __shared__ uint32_t red[4];
+    uint32_t cnt = 0;
+    for (int64_t base = (int64_t)blockIdx.x * 256; base < m; base += (int64_t)gridDim.x * 256) {
+        const int64_t t = base + threadIdx.x;
+        const int32_t C = t < m ? dec[t] : -1;
+        const bool valid = C >= 0;
+        int32_t A = 0, kv = 0;
+        if (valid) {
+            const int32_t v = verts[t];
+            A = comm[v];
+            kv = k[v];
+            comm[v] = C;
+            ++cnt;
+        }
+        if (__ballot(valid)) {
+            wave_grouped_add<int32_t, int32_t>(sigma, C, kv, valid);
+            wave_grouped_add<int32_t, int32_t>(sigma, A, -kv, valid);
+        }
+    }
+    cnt = block_sum<256>(cnt, red);
+    if (threadIdx.x == 0 && cnt) atomicAdd(moves, cnt);
+}
+
+// cs[v] = (comm[v], Sigma_tot(comm[v])): the pair a move kernel gathers per CSR entry
+__global__ void k_pairs(int32_t n, const int32_t* comm, const int32_t* sigma, int2* cs)
+{
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t c = comm[v];
+        cs[v] = make_int2(c, sigma[c]);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_pairs(int32_t n, const int32_t* comm, const int32_t* sigma, int2* cs, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    k_pairs<<<LV_GRID(n)>>>(n, comm, sigma, cs);
+    return hipGetLastError();
+}
+
+hipError_t launch_classify(int32_t n, const int32_t* off, const int32_t* bounds, uint32_t* cls, int32_t* vert,
+                           hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    Bounds bd;
+    for (int q = 0; q < NUM_CLS; ++q) bd.b[q] = bounds[q];
+    k_classify<<<LV_GRID(n)>>>(n, off, bd, cls, vert);
+    return hipGetLastError();
+}
+hipError_t launch_class_starts(const uint32_t* cls_sorted, int32_t n, int32_t* start, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    k_class_starts<<<LV_GRID(n)>>>(cls_sorted, n, start);
+    return hipGetLastError();
+}
+hipError_t launch_class_entries(const int32_t* verts_sorted, const int32_t* start, const int32_t* off, int64_t* out,
+                                hipStream_t s)
+{
+    for (int c = CLS_G8; c < NUM_CLS; ++c) {
+        const int32_t lo = start[c], hi = start[c + 1];
+        if (hi <= lo) continue;
+        k_class_entries<<<grid_for(hi - lo, 256, 4096), 256, 0, s>>>(verts_sorted, lo, hi, off,
+                                                                     (unsigned long long*)(out + c));
+    }
+    return hipGetLastError();
+}
+hipError_t launch_gather_rows(const int32_t* verts, int32_t m, const int32_t* off, int32_t* beg, int32_t* len,
+                              hipStream_t s)
+{
+    if (m <= 0) return hipSuccess;
+    k_gather_rows<<<LV_GRID(m)>>>(verts, m, off, beg, len);
+    return hipGetLastError();
+}
+
+hipError_t launch_move_class(int cls, bool singleton, const MoveArgs& a, hipStream_t s)
+{
+    switch (cls) {
+    case CLS_G8: return launch_move_t<256, 8, 16, true>(singleton, a, s);
+    case CLS_G32: return launch_move_t<256, 32, 64, true>(singleton, a, s);
+    case CLS_G64: return launch_move_t<256, 64, 256, true>(singleton, a, s);
+    case CLS_B256: return launch_move_t<256, 256, 1024, true>(singleton, a, s);
+    case CLS_B512: return launch_move_t<512, 512, 8192, false>(singleton, a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+__global__ void k_hub_clear(int32_t* table, int64_t slots)
+{
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < slots; t += (int64_t)gridDim.x * blockDim.x) {
+        table[2 * t] = EMPTY_KEY;
+        table[2 * t + 1] = 0;
+    }
+}
+hipError_t launch_hub_clear(int32_t* table, int64_t slots, hipStream_t s)
+{
+    if (slots <= 0) return hipSuccess;
+    k_hub_clear<<<LV_GRID(slots)>>>(table, slots);
+    return hipGetLastError();
+}
+
+hipError_t launch_hub_sweep(bool singleton, const MoveArgs& a, const HubArgs& h, hipStream_t s)
+{
+    if (h.nhubs <= 0) return hipSuccess;
+    if (singleton) k_hub_part<true><<<(unsigned)h.nblk, PBS, 0, s>>>(a, h);
+    else k_hub_part<false><<<(unsigned)h.nblk, PBS, 0, s>>>(a, h);
+    const unsigned fin = (unsigned)((h.nhubs + 3) / 4);
+    k_hub_finalize<<<fin, 256, 0, s>>>(a, h);
+    if (!singleton && h.nins > 0) {
+        k_fb_insert<<<(unsigned)h.nins, FBS, 0, s>>>(a, h);
+        k_fb_scan<<<(unsigned)h.nscan, FBS, 0, s>>>(a, h);
+        k_fb_finalize<<<fin, 256, 0, s>>>(a, h);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_apply(const int32_t* verts, const int32_t* dec, int32_t m, const int32_t* k, int32_t* comm,
+                        int32_t* sigma, uint32_t* moves, hipStream_t s)
+{
+    if (m <= 0) return hipSuccess;
+    k_apply<<<grid_for(m, 256, 2048), 256, 0, s>>>(verts, dec, m, k, comm, sigma, moves);
+    return hipGetLastError();
+}
+
+}  // namespace lv

@@ -95,10 +95,10 @@ def test_lfr_weighted():
 
 
 @pytest.mark.parametrize("tuning", [
-    {"sub_max": 1, "wave_max": 2, "block_max": 3, "hub_chunk": 256},   # nearly all on the hub path
-    {"sub_max": 8, "wave_max": 8, "block_max": 8, "hub_chunk": 300},
-    {"sub_max": 32, "wave_max": 128, "block_max": 512, "hub_chunk": 1000},
-    {"sub_max": 4, "wave_max": 64, "block_max": 4096, "hub_chunk": 4096},
+    {"sub_max": 1, "wave_max": 2, "block_max": 3, "part_keys": 256},    # nearly all partitioned
+    {"sub_max": 8, "wave_max": 8, "block_max": 8, "part_keys": 40, "part_slots": 64},  # forces overflows
+    {"sub_max": 32, "wave_max": 128, "block_max": 512, "part_keys": 1000},
+    {"sub_max": 4, "wave_max": 64, "block_max": 4096, "part_keys": 6144},
 ])
 def test_tuning_never_changes_results(tuning):
     g = graphgen.rmat(14, seed=5)
