@@ -82,14 +82,17 @@ typedef struct lv_result lv_result; /* per-level labels and statistics, library-
 typedef struct lv_tuning {
     int32_t sub_max;   /* L <= sub_max: a sub-wave group per vertex (power of 2, 2..64)  */
     int32_t wave_max;  /* L <= wave_max: one wavefront per vertex                          */
-    int32_t block_max; /* L <= block_max: one workgroup per vertex, LDS table              */
+    int32_t block_max; /* L <= block_max: one workgroup per vertex, LDS table (<= 4096)    */
                        /* L >  block_max: ceil(L / part_keys) workgroups per vertex, each  */
                        /* aggregating one hash partition of the communities in LDS         */
     int32_t part_keys;  /* expected communities per partition workgroup (clamped to       */
                         /* [32, 3/4 of part_slots])                                       */
     int32_t part_slots; /* LDS table slots of a partition workgroup, power of two,       */
-                        /* 64..16384 (default 16384); a partition whose communities do   */
-                        /* not fit is redone with a global-memory table                  */
+                        /* 64..16384 (mode 1) or 64..8192 (mode 2); a partition whose     */
+                        /* communities do not fit is redone with a global-memory table    */
+    int32_t hub_mode;   /* partition workgroups: 0/1 = compact tables re-reading the     */
+                        /* vertex's entries; 2 = tables with community volumes fed from  */
+                        /* the vertex's pairs gathered once into a buffer                 */
 } lv_tuning;
 
 typedef struct lv_params {
@@ -100,7 +103,7 @@ typedef struct lv_params {
     const lv_tuning* tuning; /* NULL = built-in defaults                                   */
 } lv_params;
 
-#define LV_KERNEL_SLOTS 12
+#define LV_KERNEL_SLOTS 14
 
 /* Per-level statistics; times are milliseconds from HIP events (LV_TIMING). */
 typedef struct lv_level_info {
@@ -118,9 +121,10 @@ typedef struct lv_level_info {
     int64_t move_launches; /* number of move-kernel launches                       */
     int64_t move_bytes;    /* algorithmic bytes of the move kernels, all sweeps    */
     /* Per move kernel (LV_TIMING): slot 2*(class-1) + (1 for the first sweep
-       of a level, where every community is a single vertex); classes 1..5 =
-       8-lane, 32-lane, wavefront, 256- and 512-thread workgroup tables, 6 =
-       global table (hubs, its two or three kernels together).  Bytes count each array element a kernel needs once:
+       of a level, where every community is a single vertex); classes 1..6 =
+       8-lane, 32-lane, wavefront, 256-thread, 512-thread (<= 2048 entries)
+       and 512-thread compact (<= 4096) workgroup tables, 7 = partition
+       workgroups (all of that path's kernels together).  Bytes count each array element a kernel needs once:
        indices (and weights) of its rows, and 20 bytes per vertex (vertex list,
        row offset, label, degree, own community volume). */
     double kern_ms[LV_KERNEL_SLOTS];

@@ -31,9 +31,9 @@ LV_MEM_HOST, LV_MEM_DEVICE = 0, 1
 LV_VALIDATE = 1
 LV_TIMING = 1
 LV_KEEP_GRAPHS = 2
-KERNEL_SLOTS = 12
+KERNEL_SLOTS = 14
 # kernel slot -> name (slot = 2*(class-1) + first-sweep flag)
-KERNEL_NAMES = [f"{c}{'/first' if f else ''}" for c in ("g8", "g32", "wave", "block256", "block512", "hub")
+KERNEL_NAMES = [f"{c}{'/first' if f else ''}" for c in ("g8", "g32", "wave", "block256", "block2k", "block4k", "hub")
                 for f in (0, 1)]
 
 _i32p = ctypes.POINTER(ctypes.c_int32)
@@ -44,7 +44,7 @@ _vp = ctypes.c_void_p
 class lv_tuning(ctypes.Structure):
     _fields_ = [("sub_max", ctypes.c_int32), ("wave_max", ctypes.c_int32),
                 ("block_max", ctypes.c_int32), ("part_keys", ctypes.c_int32),
-                ("part_slots", ctypes.c_int32)]
+                ("part_slots", ctypes.c_int32), ("hub_mode", ctypes.c_int32)]
 
 
 class lv_params(ctypes.Structure):

@@ -86,7 +86,7 @@ struct Workspace {
     DevBuf comm, sigma, dec, cls, vert, cls_alt, vert_alt, minv, flag, pos, labels, tmp, small;
     DevBuf keys, keys_alt, vals, vals_alt, head;
     DevBuf g_off[2], g_idx[2], g_w[2], g_k[2];
-    DevBuf hub_table, hub_meta, hub_part, hub_rows;
+    DevBuf hub_table, hub_meta, hub_part, hub_rows, hub_pairs;
     DevBuf k64, cs;
 };
 
@@ -179,7 +179,8 @@ namespace {
 struct Tune {
     int32_t bounds[NUM_CLS];
     int32_t part_keys;  // expected distinct communities per partition workgroup
-    int32_t part_slots; // LDS slots of a partition workgroup (power of two, <= 16384)
+    int32_t part_slots; // LDS slots of a partition workgroup (power of two)
+    int32_t pregather;  // partition mode (see lv_tuning.hub_mode)
     int32_t fb_chunk;   // entries / slots per workgroup on the global-table fallback
 };
 
@@ -187,8 +188,9 @@ Tune make_tune(const lv_tuning* t)
 {
     Tune u;
     for (int c = 0; c < NUM_CLS; ++c) u.bounds[c] = CLS_CAP[c];
-    u.part_keys = 12288;
+    u.part_keys = 8192;
     u.part_slots = 16384;
+    u.pregather = 0;
     u.fb_chunk = 4096;
     if (t) {
         // sub_max bounds the 8- and 32-lane classes, wave_max the wavefront
@@ -202,8 +204,16 @@ Tune make_tune(const lv_tuning* t)
         if (t->block_max > 0) {
             u.bounds[CLS_B256] = std::min(CLS_CAP[CLS_B256], std::max(u.bounds[CLS_G64], t->block_max));
             u.bounds[CLS_B512] = std::min(CLS_CAP[CLS_B512], std::max(u.bounds[CLS_B256], t->block_max));
+            u.bounds[CLS_B4K] = std::min(CLS_CAP[CLS_B4K], std::max(u.bounds[CLS_B512], t->block_max));
         }
-        if (t->part_slots > 0) u.part_slots = (int32_t)std::min<uint64_t>(16384, std::max<uint64_t>(64, next_pow2((uint64_t)t->part_slots)));
+        if (t->hub_mode == 2) {
+            u.pregather = 1;
+            u.part_slots = 8192;
+            u.part_keys = 6144;
+        }
+        const uint64_t max_slots = u.pregather ? 8192 : 16384;
+        if (t->part_slots > 0)
+            u.part_slots = (int32_t)std::min<uint64_t>(max_slots, std::max<uint64_t>(64, next_pow2((uint64_t)t->part_slots)));
         if (t->part_keys > 0) u.part_keys = std::max(32, t->part_keys);
     }
     // a single partition must always fit: part_keys <= 3/4 of the slots
@@ -282,7 +292,8 @@ lv_status plan_hubs(lv_graph* g, const LevelGraph& G, const int32_t* hub_verts, 
     HIP_TRY(hipMemcpyAsync(hv.data(), hub_verts, sizeof(int32_t) * nhubs, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     std::vector<int32_t> parts(nhubs), first_blk(nhubs + 1), blk_hub, blk_part;
-    std::vector<int64_t> tab_off(nhubs);
+    std::vector<int64_t> tab_off(nhubs), pair_off(nhubs);
+    int64_t npairs = 0;
     std::vector<int32_t> tab_cap(nhubs), ins_hub, ins_beg, ins_end, scan_hub, scan_beg, scan_end, fpart_first(nhubs + 1);
     int64_t slots = 0;
     for (int32_t h = 0; h < nhubs; ++h) {
@@ -293,7 +304,9 @@ lv_status plan_hubs(lv_graph* g, const LevelGraph& G, const int32_t* hub_verts, 
         fpart_first[h] = (int32_t)scan_hub.size();
         tab_off[h] = slots;
         tab_cap[h] = 0;
+        pair_off[h] = npairs;
         if (P == 1) continue;  // one partition of <= part_keys keys always fits its LDS table
+        if (tu.pregather) npairs += len[h];
         const uint64_t cap = std::max<uint64_t>(64, next_pow2(2ull * (uint64_t)len[h]));
         if (cap > (uint64_t)INT32_MAX) { set_error_msg("hub table too large"); return LV_E_OVERFLOW; }
         tab_cap[h] = (int32_t)cap;
@@ -323,10 +336,12 @@ lv_status plan_hubs(lv_graph* g, const LevelGraph& G, const int32_t* hub_verts, 
     const size_t o_cap = put(tab_cap), o_ih = put(ins_hub), o_ib = put(ins_beg), o_ie = put(ins_end);
     const size_t o_sh = put(scan_hub), o_sb = put(scan_beg), o_se = put(scan_end), o_ff = put(fpart_first);
     const size_t b64 = sizeof(int64_t) * (size_t)nhubs;
-    HIP_TRY(ws.hub_meta.ensure(b64 + sizeof(int32_t) * pack.size() + 64));
+    HIP_TRY(ws.hub_meta.ensure(2 * b64 + sizeof(int32_t) * pack.size() + 64));
     char* base = ws.hub_meta.as<char>();
-    int32_t* p32 = (int32_t*)(base + b64);
+    int32_t* p32 = (int32_t*)(base + 2 * b64);
     HIP_TRY(hipMemcpyAsync(base, tab_off.data(), b64, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(base + b64, pair_off.data(), b64, hipMemcpyHostToDevice, s));
+    HIP_TRY(ws.hub_pairs.ensure(sizeof(int2) * (size_t)std::max<int64_t>(npairs, 1)));
     HIP_TRY(hipMemcpyAsync(p32, pack.data(), sizeof(int32_t) * pack.size(), hipMemcpyHostToDevice, s));
     // partial results + flags: [nblk] x (int64 score, int32 comm, wown, flag), [nhubs] fb_flag, [nscan] fallback partials
     const size_t part_bytes = (size_t)nblk * (8 + 4 * 3) + (size_t)nhubs * 4 + (size_t)std::max(nscan, 1) * (8 + 4 * 2);
@@ -336,6 +351,7 @@ lv_status plan_hubs(lv_graph* g, const LevelGraph& G, const int32_t* hub_verts, 
     a = HubArgs{};
     a.nhubs = nhubs;
     a.part_mask = (uint32_t)tu.part_slots - 1u;
+    a.pregather = tu.pregather;
     a.hub_vert = p32 + o_hv;
     a.hub_parts = p32 + o_parts;
     a.hub_first_blk = p32 + o_fb;
@@ -353,6 +369,8 @@ lv_status plan_hubs(lv_graph* g, const LevelGraph& G, const int32_t* hub_verts, 
     a.fpart_wown = a.fpart_comm + std::max(nscan, 1);
     a.fpart_first = p32 + o_ff;
     a.tab_off = (const int64_t*)base;
+    a.pair_off = (const int64_t*)(base + b64);
+    a.pairs = ws.hub_pairs.as<int2>();
     a.tab_cap = p32 + o_cap;
     a.ins_hub = p32 + o_ih;
     a.ins_beg = p32 + o_ib;

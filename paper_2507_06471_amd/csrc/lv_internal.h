@@ -21,12 +21,13 @@ enum MoveClass : int {
     CLS_G32 = 2,   // 32 lanes, 64 slots
     CLS_G64 = 3,   // one wavefront, 256 slots
     CLS_B256 = 4,  // one 256-thread workgroup, 1024 slots
-    CLS_B512 = 5,  // one 512-thread workgroup, 8192 slots (64 KiB)
-    CLS_HUB = 6,   // several workgroups, table in global memory
-    NUM_CLS = 7
+    CLS_B512 = 5,  // one 512-thread workgroup, 4096 slots
+    CLS_B4K = 6,   // one 512-thread workgroup, 8192 compact slots
+    CLS_HUB = 7,   // several partition workgroups per vertex
+    NUM_CLS = 8
 };
 // Largest L each class can hold (table load factor <= 1/2).
-constexpr int32_t CLS_CAP[NUM_CLS] = {0, 8, 32, 128, 512, 4096, INT32_MAX};
+constexpr int32_t CLS_CAP[NUM_CLS] = {0, 8, 32, 128, 512, 2048, 4096, INT32_MAX};
 
 // Arguments shared by every move kernel.
 struct MoveArgs {
@@ -51,6 +52,7 @@ struct MoveArgs {
 struct HubArgs {
     int32_t nhubs;
     uint32_t part_mask;            // LDS slots of a partition workgroup - 1
+    int32_t pregather;             // 1: partition tables with volumes, fed from `pairs`
     const int32_t* hub_vert;       // [nhubs]
     const int32_t* hub_parts;      // [nhubs] P
     const int32_t* hub_first_blk;  // [nhubs+1] first partition workgroup of each hub
@@ -62,6 +64,8 @@ struct HubArgs {
     int32_t* part_wown;
     int32_t* part_flag;            // 1 = the partition's table overflowed
     int32_t* fb_flag;              // [nhubs] hub needs the global-table fallback
+    int2* pairs;                   // pre-gathered (community, volume) per entry of hubs with P > 1
+    const int64_t* pair_off;       // [nhubs] offset of a hub's entries in `pairs`
     // fallback: global open-addressing tables (2 ints per slot: key, value)
     const int64_t* tab_off;        // [nhubs] slot offset of the hub's table
     const int32_t* tab_cap;        // [nhubs] slots (power of two, 0 if P == 1)

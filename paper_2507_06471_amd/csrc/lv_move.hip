@@ -15,24 +15,29 @@
 //   L <= 32     32 lanes, <= 64 slots
 //   L <= 128    a wavefront, <= 256 slots
 //   L <= 512    a 256-thread workgroup, <= 1024 slots
-//   L <= 4096   a 512-thread workgroup, <= 8192 slots
+//   L <= 2048   a 512-thread workgroup, <= 4096 slots
+//   L <= 4096   a 512-thread workgroup, <= 8192 compact slots (64 KiB)
 //   L >  4096   P = ceil(L / part_keys) 1024-thread workgroups per vertex;
 //               workgroup p aggregates the communities of hash partition p in
-//               an LDS table of part_slots (default 16384) slots; partial
-//               results are merged per vertex.  If a partition's table ever fills up, that vertex
+//               an LDS table; partial results are merged per vertex, and all P
+//               workgroups of a vertex run on one XCD (shared L2).  Two modes:
+//               compact tables of up to 16384 slots that re-read the vertex's
+//               entries, or (with P > 1) tables of up to 8192 slots fed from
+//               the vertex's (community, volume) pairs gathered once into a
+//               contiguous buffer.  If a partition's table ever fills up, that vertex
 //               is redone with a global-memory table (never expected with
 //               hashed partitions; it keeps every input exact and finite).
 // In the first sweep of a level every community is a single vertex and CSR
 // columns are unique, so W_i(j) = A_ij and entries are scored directly.
 //
-// Memory traffic: in the classes up to 512 entries a neighbour's community
-// and that community's volume are read together as one 8-byte pair
-// cs[j] = (comm[j], Sigma_tot(comm[j])) (refreshed after every commit), so an
-// entry costs one random gather and the volume is kept in the LDS slot beside
-// the summed weight.  The two largest classes keep 8-byte slots (larger
-// tables per workgroup) and gather Sigma_tot once per distinct community.
-// CSR indices and weights are streamed with non-temporal loads so they do not
-// evict the frequently gathered values from L2.
+// Memory traffic: a neighbour's community and that community's volume are
+// read together as one 8-byte pair cs[j] = (comm[j], Sigma_tot(comm[j]))
+// (refreshed after every commit), so an entry costs one random gather and the
+// volume is kept in the LDS slot beside the summed weight.  Compact tables (8
+// bytes a slot, twice the slots per workgroup) instead gather the volume once
+// per distinct community.  CSR indices and weights are streamed with
+// non-temporal loads so they do not evict the frequently gathered pairs from
+// L2.
 #include "lv_device.h"
 
 namespace lv {
@@ -149,26 +154,38 @@ __device__ __forceinline__ void lds_insert(int32_t* key, int32_t* val, int32_t* 
 // of vertex i into an LDS table, optionally only communities of partition
 // `part` of P.  Returns false if the bounded table had no room (only
 // possible with P > 1).
+// `pairs` (optional): the entries' (community, volume) pairs gathered in
+// advance, pairs[e - row_beg], EMPTY_KEY for the vertex's own loop.
 template <int STRIDE, bool BOUNDED, bool SIG>
 __device__ __forceinline__ bool aggregate_entries(const MoveArgs& a, int32_t i, int32_t e_beg, int32_t e_end,
                                                   int32_t* key, int32_t* val, int32_t* sig, uint32_t mask, uint32_t P,
-                                                  uint32_t part)
+                                                  uint32_t part, const int2* pairs = nullptr, int32_t row_beg = 0)
 {
     bool ok_all = true;
     for (int32_t e0 = e_beg; e0 < e_end; e0 += STRIDE * UNROLL) {
         int32_t jj[UNROLL], ww[UNROLL];
         int2 cc[UNROLL];
+        if (pairs) {
 #pragma unroll
-        for (int u = 0; u < UNROLL; ++u) {
-            const int32_t e = e0 + u * STRIDE;
-            const bool ok = e < e_end;
-            jj[u] = ok ? __builtin_nontemporal_load(&a.idx[e]) : i;
-            ww[u] = (ok && a.w) ? __builtin_nontemporal_load(&a.w[e]) : 1;
-        }
+            for (int u = 0; u < UNROLL; ++u) {
+                const int32_t e = e0 + u * STRIDE;
+                const bool ok = e < e_end;
+                cc[u] = ok ? pairs[e - row_beg] : make_int2(EMPTY_KEY, 0);
+                ww[u] = (ok && a.w) ? __builtin_nontemporal_load(&a.w[e]) : 1;
+            }
+        } else {
 #pragma unroll
-        for (int u = 0; u < UNROLL; ++u) {
-            if constexpr (SIG) cc[u] = jj[u] != i ? a.cs[jj[u]] : make_int2(EMPTY_KEY, 0);
-            else cc[u] = make_int2(jj[u] != i ? a.comm[jj[u]] : EMPTY_KEY, 0);
+            for (int u = 0; u < UNROLL; ++u) {
+                const int32_t e = e0 + u * STRIDE;
+                const bool ok = e < e_end;
+                jj[u] = ok ? __builtin_nontemporal_load(&a.idx[e]) : i;
+                ww[u] = (ok && a.w) ? __builtin_nontemporal_load(&a.w[e]) : 1;
+            }
+#pragma unroll
+            for (int u = 0; u < UNROLL; ++u) {
+                if constexpr (SIG) cc[u] = jj[u] != i ? a.cs[jj[u]] : make_int2(EMPTY_KEY, 0);
+                else cc[u] = make_int2(jj[u] != i ? a.comm[jj[u]] : EMPTY_KEY, 0);
+            }
         }
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
@@ -279,18 +296,28 @@ hipError_t launch_move_t(bool singleton, const MoveArgs& a, hipStream_t s)
 
 // ------------------------------------------------------------------ partitioned path (L > 4096)
 constexpr int PBS = 1024;
-constexpr int PSLOTS = 16384;
+constexpr int PSLOTS_SIG = 8192;       // 12-byte slots (key, weight, volume): 96 KiB
+constexpr int PSLOTS_COMPACT = 16384;  // 8-byte slots (key, weight): 128 KiB
 
-template <bool SINGLETON>
+// Workgroups are dispatched to the 8 XCDs round-robin; renumber them so that
+// consecutive logical ids run on one XCD (and share its L2).
+__device__ __forceinline__ int32_t xcd_logical(int32_t b, int32_t nblk)
+{
+    const int32_t x = b & 7, k = b >> 3, q = nblk >> 3, r = nblk & 7;
+    return x * q + min(x, r) + k;
+}
+
+template <bool SINGLETON, bool SIG>
 __global__ __launch_bounds__(PBS) void k_hub_part(MoveArgs a, HubArgs h)
 {
+    constexpr int PSLOTS = SIG ? PSLOTS_SIG : PSLOTS_COMPACT;
     __shared__ int32_t s_key[SINGLETON ? 1 : PSLOTS];
     __shared__ int32_t s_val[SINGLETON ? 1 : PSLOTS];
-    __shared__ int32_t s_sig[1];
+    __shared__ int32_t s_sig[(SINGLETON || !SIG) ? 1 : PSLOTS];
     __shared__ int64_t rs[PBS / WAVE];
     __shared__ int32_t rc[PBS / WAVE], rw[PBS / WAVE];
     __shared__ int32_t s_over;
-    const int32_t b = blockIdx.x;
+    const int32_t b = xcd_logical((int32_t)blockIdx.x, h.nblk);
     const int32_t hh = h.blk_hub[b];
     const uint32_t part = (uint32_t)h.blk_part[b], P = (uint32_t)h.hub_parts[hh];
     const int32_t i = h.hub_vert[hh];
@@ -309,12 +336,13 @@ __global__ __launch_bounds__(PBS) void k_hub_part(MoveArgs a, HubArgs h)
         for (uint32_t t = threadIdx.x; t < T; t += PBS) { s_key[t] = EMPTY_KEY; s_val[t] = 0; }
         if (threadIdx.x == 0) s_over = 0;
         __syncthreads();
-        if (!aggregate_entries<PBS, true, false>(a, i, beg + (int32_t)threadIdx.x, end, s_key, s_val, s_sig,
-                                                 h.part_mask, P, part))
+        const int2* pairs = (SIG && P > 1) ? h.pairs + h.pair_off[hh] : nullptr;
+        if (!aggregate_entries<PBS, true, SIG>(a, i, beg + (int32_t)threadIdx.x, end, s_key, s_val, s_sig,
+                                               h.part_mask, P, part, pairs, beg))
             s_over = 1;
         __syncthreads();
         over = s_over;
-        if (!over) scan_table<PBS, false>(a, s_key, s_val, s_sig, threadIdx.x, T, A, ki, best_s, best_c, w_own);
+        if (!over) scan_table<PBS, SIG>(a, s_key, s_val, s_sig, threadIdx.x, T, A, ki, best_s, best_c, w_own);
     }
     block_reduce_best<PBS>(best_s, best_c, w_own, rs, rc, rw);
     if (threadIdx.x == 0) {
@@ -350,6 +378,21 @@ __global__ __launch_bounds__(256) void k_hub_finalize(MoveArgs a, HubArgs h)
     const bool overflowed = __ballot(flag != 0) != 0;
     if (has && overflowed && lane_id() == 0) h.fb_flag[hh] = 1;
     if (has && !overflowed && lane_id() == 0) decide_store(a, hh, A, sA, ki, best_s, best_c, w_own);
+}
+
+// Pre-gather the (community, volume) pairs of the entries of vertices with
+// P > 1 partitions (one workgroup per chunk of a vertex's entries).
+__global__ __launch_bounds__(256) void k_hub_pairs(MoveArgs a, HubArgs h)
+{
+    const int b = blockIdx.x;
+    const int32_t hh = h.ins_hub[b];
+    const int32_t i = h.hub_vert[hh];
+    const int32_t beg = a.off[i];
+    int2* out = h.pairs + h.pair_off[hh];
+    for (int32_t e = h.ins_beg[b] + threadIdx.x; e < h.ins_end[b]; e += 256) {
+        const int32_t j = __builtin_nontemporal_load(&a.idx[e]);
+        out[e - beg] = j != i ? a.cs[j] : make_int2(EMPTY_KEY, 0);
+    }
 }
 
 // ---- global-table fallback for hubs whose partition tables overflowed
@@ -520,7 +563,8 @@ hipError_t launch_move_class(int cls, bool singleton, const MoveArgs& a, hipStre
     case CLS_G32: return launch_move_t<256, 32, 64, true>(singleton, a, s);
     case CLS_G64: return launch_move_t<256, 64, 256, true>(singleton, a, s);
     case CLS_B256: return launch_move_t<256, 256, 1024, true>(singleton, a, s);
-    case CLS_B512: return launch_move_t<512, 512, 8192, false>(singleton, a, s);
+    case CLS_B512: return launch_move_t<512, 512, 4096, true>(singleton, a, s);
+    case CLS_B4K: return launch_move_t<512, 512, 8192, false>(singleton, a, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -542,8 +586,14 @@ hipError_t launch_hub_clear(int32_t* table, int64_t slots, hipStream_t s)
 hipError_t launch_hub_sweep(bool singleton, const MoveArgs& a, const HubArgs& h, hipStream_t s)
 {
     if (h.nhubs <= 0) return hipSuccess;
-    if (singleton) k_hub_part<true><<<(unsigned)h.nblk, PBS, 0, s>>>(a, h);
-    else k_hub_part<false><<<(unsigned)h.nblk, PBS, 0, s>>>(a, h);
+    if (singleton) {
+        k_hub_part<true, false><<<(unsigned)h.nblk, PBS, 0, s>>>(a, h);
+    } else if (h.pregather) {
+        if (h.nins > 0) k_hub_pairs<<<(unsigned)h.nins, 256, 0, s>>>(a, h);
+        k_hub_part<false, true><<<(unsigned)h.nblk, PBS, 0, s>>>(a, h);
+    } else {
+        k_hub_part<false, false><<<(unsigned)h.nblk, PBS, 0, s>>>(a, h);
+    }
     const unsigned fin = (unsigned)((h.nhubs + 3) / 4);
     k_hub_finalize<<<fin, 256, 0, s>>>(a, h);
     if (!singleton && h.nins > 0) {

@@ -98,7 +98,9 @@ def test_lfr_weighted():
     {"sub_max": 1, "wave_max": 2, "block_max": 3, "part_keys": 256},    # nearly all partitioned
     {"sub_max": 8, "wave_max": 8, "block_max": 8, "part_keys": 40, "part_slots": 64},  # forces overflows
     {"sub_max": 32, "wave_max": 128, "block_max": 512, "part_keys": 1000},
-    {"sub_max": 4, "wave_max": 64, "block_max": 4096, "part_keys": 6144},
+    {"sub_max": 4, "wave_max": 64, "block_max": 4096, "part_keys": 4096},
+    {"block_max": 600, "hub_mode": 2, "part_keys": 500},                   # pre-gathered pairs
+    {"block_max": 300, "hub_mode": 2, "part_keys": 100, "part_slots": 128},  # pairs + overflows
 ])
 def test_tuning_never_changes_results(tuning):
     g = graphgen.rmat(14, seed=5)
