@@ -68,8 +68,10 @@ typedef enum lv_memkind { LV_MEM_HOST = 0, LV_MEM_DEVICE = 1 } lv_memkind;
 #define LV_VALIDATE 1u /* check CSR shape, sortedness, symmetry and weights on the device */
 
 /* lv_params.flags */
-#define LV_TIMING 1u      /* record per-kernel HIP event times (see lv_level_info)          */
+#define LV_TIMING 1u      /* record per-kernel HIP event times (see lv_level_info); sweeps */
+                          /* are then launched one by one instead of from a HIP graph     */
 #define LV_KEEP_GRAPHS 2u /* lv_louvain keeps every coarse graph for lv_result_level_graph */
+#define LV_NO_HIPGRAPH 4u /* launch sweeps one by one even without LV_TIMING              */
 
 typedef struct lv_graph lv_graph;   /* device-resident CSR + workspace, library-owned */
 typedef struct lv_result lv_result; /* per-level labels and statistics, library-owned */
@@ -150,7 +152,23 @@ const char* lv_last_error(void);
 lv_status lv_graph_create_csr(int32_t n, const int32_t* offsets, const int32_t* indices,
                               const int32_t* weights, lv_memkind kind, uint32_t flags, void* stream,
                               lv_graph** out);
+/*
+ * Create one device-resident handle holding `count` independent graphs,
+ * packed one after another into a single CSR (vertex segment offsets), so
+ * that every sweep of every graph runs in the same kernel launches.  Graph g
+ * is given like lv_graph_create_csr's arguments: n[g], offsets[g],
+ * indices[g], weights[g] (weights may be NULL, or weights[g] NULL for unit
+ * weights), all in `kind` memory.  Each graph keeps its own total volume,
+ * sweep counts, stopping rule and levels: lv_louvain / lv_lpa on the handle
+ * give every graph exactly the result it gets alone.  Total vertices and
+ * entries must each stay below 2^31.
+ */
+lv_status lv_graph_create_batch(int32_t count, const int32_t* n, const int32_t* const* offsets,
+                                const int32_t* const* indices, const int32_t* const* weights,
+                                lv_memkind kind, uint32_t flags, void* stream, lv_graph** out);
 lv_status lv_graph_destroy(lv_graph* g);
+/* number of graphs packed in the handle (1 for lv_graph_create_csr) */
+lv_status lv_graph_count(const lv_graph* g, int32_t* count);
 /* n, nnz and total volume M = sum of weighted degrees (loops counted twice). */
 lv_status lv_graph_info(const lv_graph* g, int32_t* n, int64_t* nnz, int64_t* volume);
 
@@ -184,6 +202,19 @@ lv_status lv_result_modularity(const lv_result* r, int64_t* q_int, int64_t* m, d
 lv_status lv_result_destroy(lv_result* r);
 
 /*
+ * Per-graph accessors for handles holding several graphs (graph index g in
+ * [0, count)); the accessors above address graph 0.  Level statistics hold
+ * the timings of the shared launches of that level.
+ */
+lv_status lv_result_graph_num_levels(const lv_result* r, int32_t g, int32_t* accepted, int32_t* attempted);
+lv_status lv_result_graph_level_info(const lv_result* r, int32_t g, int32_t level, lv_level_info* out);
+lv_status lv_result_graph_level_moves(const lv_result* r, int32_t g, int32_t level, int64_t* moves, int32_t cap);
+lv_status lv_result_graph_level_labels(const lv_result* r, int32_t g, int32_t level, int32_t* labels,
+                                       lv_memkind kind);
+lv_status lv_result_graph_final_labels(const lv_result* r, int32_t g, int32_t* labels, lv_memkind kind);
+lv_status lv_result_graph_modularity(const lv_result* r, int32_t g, int64_t* q_int, int64_t* m, double* q);
+
+/*
  * Label propagation (Algorithm 1) as one level of synchronous sweeps with the
  * LPA score, then renumbering.  labels int32[n] in `kind` memory; info may be
  * NULL (then only labels are written); moves_out (may be NULL) receives up to
@@ -191,6 +222,14 @@ lv_status lv_result_destroy(lv_result* r);
  */
 lv_status lv_lpa(lv_graph* g, const lv_params* params, int32_t* labels, lv_memkind kind,
                  lv_level_info* info, int64_t* moves_out, int32_t moves_cap);
+/*
+ * LPA on every graph of a handle: labels int32[sum of n] (graph g's labels at
+ * its packed vertex offset, numbered from 0 within the graph); per graph
+ * (arrays of `count`, each may be NULL): sweeps, Q_int, M; moves int64
+ * [count * moves_stride] (per-sweep mover counts, may be NULL).
+ */
+lv_status lv_lpa_batch(lv_graph* g, const lv_params* params, int32_t* labels, lv_memkind kind,
+                       int32_t* sweeps, int64_t* q_int, int64_t* m, int64_t* moves, int32_t moves_stride);
 
 /* Modularity (Section II-C) of any labels int32[n] with values in [0, n). */
 lv_status lv_modularity(lv_graph* g, const int32_t* labels, lv_memkind kind, int64_t* q_int,

@@ -31,6 +31,7 @@ LV_MEM_HOST, LV_MEM_DEVICE = 0, 1
 LV_VALIDATE = 1
 LV_TIMING = 1
 LV_KEEP_GRAPHS = 2
+LV_NO_HIPGRAPH = 4
 KERNEL_SLOTS = 14
 # kernel slot -> name (slot = 2*(class-1) + first-sweep flag)
 KERNEL_NAMES = [f"{c}{'/first' if f else ''}" for c in ("g8", "g32", "wave", "block256", "block2k", "block4k", "hub")
@@ -78,7 +79,10 @@ SIGNATURES = {
     "lv_last_error": (ctypes.c_char_p, []),
     "lv_graph_create_csr": (ctypes.c_int, [ctypes.c_int32, _vp, _vp, _vp, ctypes.c_int, ctypes.c_uint32, _vp,
                                            ctypes.POINTER(_vp)]),
+    "lv_graph_create_batch": (ctypes.c_int, [ctypes.c_int32, _vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_uint32,
+                                             _vp, ctypes.POINTER(_vp)]),
     "lv_graph_destroy": (ctypes.c_int, [_vp]),
+    "lv_graph_count": (ctypes.c_int, [_vp, _i32p]),
     "lv_graph_info": (ctypes.c_int, [_vp, _i32p, _i64p, _i64p]),
     "lv_louvain": (ctypes.c_int, [_vp, ctypes.POINTER(lv_params), ctypes.POINTER(_vp)]),
     "lv_result_num_levels": (ctypes.c_int, [_vp, _i32p, _i32p]),
@@ -89,8 +93,18 @@ SIGNATURES = {
     "lv_result_final_labels": (ctypes.c_int, [_vp, _vp, ctypes.c_int]),
     "lv_result_modularity": (ctypes.c_int, [_vp, _i64p, _i64p, ctypes.POINTER(ctypes.c_double)]),
     "lv_result_destroy": (ctypes.c_int, [_vp]),
+    "lv_result_graph_num_levels": (ctypes.c_int, [_vp, ctypes.c_int32, _i32p, _i32p]),
+    "lv_result_graph_level_info": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32,
+                                                  ctypes.POINTER(lv_level_info)]),
+    "lv_result_graph_level_moves": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, _i64p, ctypes.c_int32]),
+    "lv_result_graph_level_labels": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, _vp, ctypes.c_int]),
+    "lv_result_graph_final_labels": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, ctypes.c_int]),
+    "lv_result_graph_modularity": (ctypes.c_int, [_vp, ctypes.c_int32, _i64p, _i64p,
+                                                  ctypes.POINTER(ctypes.c_double)]),
     "lv_lpa": (ctypes.c_int, [_vp, ctypes.POINTER(lv_params), _vp, ctypes.c_int,
                               ctypes.POINTER(lv_level_info), _i64p, ctypes.c_int32]),
+    "lv_lpa_batch": (ctypes.c_int, [_vp, ctypes.POINTER(lv_params), _vp, ctypes.c_int, _i32p, _i64p, _i64p,
+                                    _i64p, ctypes.c_int32]),
     "lv_modularity": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _i64p, _i64p, ctypes.POINTER(ctypes.c_double)]),
 }
 
@@ -184,6 +198,40 @@ class Graph:
         _check(lib.lv_graph_info(h, ctypes.byref(nn), ctypes.byref(nnz), ctypes.byref(vol)), "lv_graph_info")
         self.nnz = nnz.value
         self.volume = vol.value
+        self.count = 1
+        self.sizes = [self.n]
+
+    @classmethod
+    def batch(cls, graphs, validate: bool = True):
+        """Pack several ``graphgen.CSR``-like graphs into one handle
+        (lv_graph_create_batch); graph g keeps its own vertex numbering."""
+        lib = load_library()
+        arrs = []
+        for g in graphs:
+            off = np.ascontiguousarray(g.offsets, dtype=np.int32)
+            idx = np.ascontiguousarray(g.indices, dtype=np.int32)
+            w = None if g.weights is None else np.ascontiguousarray(g.weights, dtype=np.int32)
+            arrs.append((int(g.n), off, idx, w))
+        cnt = len(arrs)
+        ns = np.array([a[0] for a in arrs], dtype=np.int32)
+        P = ctypes.c_void_p * cnt
+        po = P(*[a[1].ctypes.data for a in arrs])
+        pi = P(*[a[2].ctypes.data for a in arrs])
+        pw = P(*[(a[3].ctypes.data if a[3] is not None else None) for a in arrs])
+        h = _vp()
+        st = lib.lv_graph_create_batch(cnt, ns.ctypes.data, ctypes.cast(po, _vp), ctypes.cast(pi, _vp),
+                                       ctypes.cast(pw, _vp), LV_MEM_HOST, LV_VALIDATE if validate else 0, None,
+                                       ctypes.byref(h))
+        _check(st, "lv_graph_create_batch")
+        self = cls.__new__(cls)
+        self._h = h
+        nn, nnz, vol = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib.lv_graph_info(h, ctypes.byref(nn), ctypes.byref(nnz), ctypes.byref(vol)), "lv_graph_info")
+        c = ctypes.c_int32()
+        _check(lib.lv_graph_count(h, ctypes.byref(c)), "lv_graph_count")
+        self.n, self.nnz, self.volume, self.count = nn.value, nnz.value, None, c.value
+        self.sizes = [int(x) for x in ns]
+        return self
 
     @classmethod
     def from_csr(cls, g, validate: bool = True, device: bool = False):
@@ -242,45 +290,57 @@ class LouvainResult:
         return [lv for lv in self.levels if lv.info["accepted"]]
 
 
+def _read_graph_result(lib, r, gi: int, n0: int, keep_graphs: bool) -> LouvainResult:
+    acc, att = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib.lv_result_graph_num_levels(r, gi, ctypes.byref(acc), ctypes.byref(att)), "lv_result_graph_num_levels")
+    levels = []
+    for lvl in range(att.value):
+        info = lv_level_info()
+        _check(lib.lv_result_graph_level_info(r, gi, lvl, ctypes.byref(info)), "lv_result_graph_level_info")
+        mv = np.zeros(max(info.sweeps, 1), dtype=np.int64)
+        _check(lib.lv_result_graph_level_moves(r, gi, lvl, mv.ctypes.data_as(_i64p), info.sweeps),
+               "lv_result_graph_level_moves")
+        lr = LevelResult(info.as_dict(), [int(x) for x in mv[:info.sweeps]])
+        if lvl < acc.value:
+            lab = np.empty(info.n, dtype=np.int32)
+            _check(lib.lv_result_graph_level_labels(r, gi, lvl, lab.ctypes.data, LV_MEM_HOST),
+                   "lv_result_graph_level_labels")
+            lr.labels = lab
+            if keep_graphs:
+                nnz = ctypes.c_int64()
+                _check(lib.lv_result_level_graph(r, lvl, None, None, None, ctypes.byref(nnz), LV_MEM_HOST),
+                       "lv_result_level_graph")
+                off = np.empty(info.n_next + 1, dtype=np.int32)
+                idx = np.empty(max(nnz.value, 1), dtype=np.int32)
+                w = np.empty(max(nnz.value, 1), dtype=np.int32)
+                _check(lib.lv_result_level_graph(r, lvl, off.ctypes.data, idx.ctypes.data, w.ctypes.data,
+                                                 ctypes.byref(nnz), LV_MEM_HOST), "lv_result_level_graph")
+                lr.graph = (off, idx[:nnz.value], w[:nnz.value])
+        levels.append(lr)
+    fin = np.empty(n0, dtype=np.int32)
+    _check(lib.lv_result_graph_final_labels(r, gi, fin.ctypes.data, LV_MEM_HOST), "lv_result_graph_final_labels")
+    qi, m, q = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_double()
+    _check(lib.lv_result_graph_modularity(r, gi, ctypes.byref(qi), ctypes.byref(m), ctypes.byref(q)),
+           "lv_result_graph_modularity")
+    return LouvainResult(qi.value, m.value, q.value, fin, levels)
+
+
+def _flags(timing: bool, keep_graphs: bool = False, hipgraph: bool = True) -> int:
+    return (LV_TIMING if timing else 0) | (LV_KEEP_GRAPHS if keep_graphs else 0) | (0 if hipgraph else LV_NO_HIPGRAPH)
+
+
 def louvain(graph: Graph, max_sweeps: int = 20, max_levels: int = 32, timing: bool = False,
-            keep_graphs: bool = False, tuning: Optional[dict] = None) -> LouvainResult:
-    """lv_louvain + result accessors, copied to host numpy."""
+            keep_graphs: bool = False, tuning: Optional[dict] = None, hipgraph: bool = True):
+    """lv_louvain + result accessors, copied to host numpy.  A packed handle
+    (``Graph.batch``) gives one LouvainResult per graph, in order."""
     lib = load_library()
-    flags = (LV_TIMING if timing else 0) | (LV_KEEP_GRAPHS if keep_graphs else 0)
-    p, _keep = make_params(max_sweeps, max_levels, 0, flags, tuning)
+    p, _keep = make_params(max_sweeps, max_levels, 0, _flags(timing, keep_graphs, hipgraph), tuning)
     r = _vp()
     _check(lib.lv_louvain(graph.handle, ctypes.byref(p), ctypes.byref(r)), "lv_louvain")
     try:
-        acc, att = ctypes.c_int32(), ctypes.c_int32()
-        _check(lib.lv_result_num_levels(r, ctypes.byref(acc), ctypes.byref(att)), "lv_result_num_levels")
-        levels = []
-        for lvl in range(att.value):
-            info = lv_level_info()
-            _check(lib.lv_result_level_info(r, lvl, ctypes.byref(info)), "lv_result_level_info")
-            mv = np.zeros(max(info.sweeps, 1), dtype=np.int64)
-            _check(lib.lv_result_level_moves(r, lvl, mv.ctypes.data_as(_i64p), info.sweeps), "lv_result_level_moves")
-            lr = LevelResult(info.as_dict(), [int(x) for x in mv[:info.sweeps]])
-            if lvl < acc.value:
-                lab = np.empty(info.n, dtype=np.int32)
-                _check(lib.lv_result_level_labels(r, lvl, lab.ctypes.data, LV_MEM_HOST), "lv_result_level_labels")
-                lr.labels = lab
-                if keep_graphs:
-                    nnz = ctypes.c_int64()
-                    _check(lib.lv_result_level_graph(r, lvl, None, None, None, ctypes.byref(nnz), LV_MEM_HOST),
-                           "lv_result_level_graph")
-                    off = np.empty(info.n_next + 1, dtype=np.int32)
-                    idx = np.empty(max(nnz.value, 1), dtype=np.int32)
-                    w = np.empty(max(nnz.value, 1), dtype=np.int32)
-                    _check(lib.lv_result_level_graph(r, lvl, off.ctypes.data, idx.ctypes.data, w.ctypes.data,
-                                                     ctypes.byref(nnz), LV_MEM_HOST), "lv_result_level_graph")
-                    lr.graph = (off, idx[:nnz.value], w[:nnz.value])
-            levels.append(lr)
-        fin = np.empty(graph.n, dtype=np.int32)
-        _check(lib.lv_result_final_labels(r, fin.ctypes.data, LV_MEM_HOST), "lv_result_final_labels")
-        qi, m, q = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_double()
-        _check(lib.lv_result_modularity(r, ctypes.byref(qi), ctypes.byref(m), ctypes.byref(q)),
-               "lv_result_modularity")
-        return LouvainResult(qi.value, m.value, q.value, fin, levels)
+        if graph.count == 1:
+            return _read_graph_result(lib, r, 0, graph.n, keep_graphs)
+        return [_read_graph_result(lib, r, gi, graph.sizes[gi], False) for gi in range(graph.count)]
     finally:
         lib.lv_result_destroy(r)
 
@@ -293,10 +353,12 @@ class LpaResult:
 
 
 def lpa(graph: Graph, max_sweeps: int = 20, threshold: int = 0, timing: bool = False, out=None,
-        tuning: Optional[dict] = None) -> LpaResult:
+        tuning: Optional[dict] = None, hipgraph: bool = True) -> LpaResult:
     """lv_lpa; labels land in `out` (numpy or torch int32) or a new numpy array."""
     lib = load_library()
-    p, _keep = make_params(max_sweeps, 32, threshold, LV_TIMING if timing else 0, tuning)
+    if graph.count != 1:
+        return lpa_batch(graph, max_sweeps, threshold, tuning=tuning, hipgraph=hipgraph)
+    p, _keep = make_params(max_sweeps, 32, threshold, _flags(timing, False, hipgraph), tuning)
     labels = np.empty(graph.n, dtype=np.int32) if out is None else out
     pl, kind = _ptr(labels)
     info = lv_level_info()
@@ -304,6 +366,29 @@ def lpa(graph: Graph, max_sweeps: int = 20, threshold: int = 0, timing: bool = F
     _check(lib.lv_lpa(graph.handle, ctypes.byref(p), pl, kind, ctypes.byref(info), mv.ctypes.data_as(_i64p),
                       max_sweeps), "lv_lpa")
     return LpaResult(labels, [int(x) for x in mv[:info.sweeps]], info.as_dict())
+
+
+def lpa_batch(graph: Graph, max_sweeps: int = 20, threshold: int = 0, tuning: Optional[dict] = None,
+              hipgraph: bool = True) -> List[LpaResult]:
+    """lv_lpa_batch over a packed handle: one LpaResult per graph (local labels)."""
+    lib = load_library()
+    p, _keep = make_params(max_sweeps, 32, threshold, _flags(False, False, hipgraph), tuning)
+    G = graph.count
+    labels = np.empty(max(graph.n, 1), dtype=np.int32)
+    sw = np.zeros(G, dtype=np.int32)
+    qi = np.zeros(G, dtype=np.int64)
+    m = np.zeros(G, dtype=np.int64)
+    mv = np.zeros((G, max_sweeps), dtype=np.int64)
+    _check(lib.lv_lpa_batch(graph.handle, ctypes.byref(p), labels.ctypes.data, LV_MEM_HOST, sw.ctypes.data_as(_i32p),
+                            qi.ctypes.data_as(_i64p), m.ctypes.data_as(_i64p), mv.ctypes.data_as(_i64p), max_sweeps),
+           "lv_lpa_batch")
+    out, base = [], 0
+    for gi in range(G):
+        n = graph.sizes[gi]
+        info = {"n": n, "sweeps": int(sw[gi]), "q_end": int(qi[gi]), "M": int(m[gi])}
+        out.append(LpaResult(labels[base:base + n].copy(), [int(x) for x in mv[gi, :sw[gi]]], info))
+        base += n
+    return out
 
 
 def modularity(graph: Graph, labels):

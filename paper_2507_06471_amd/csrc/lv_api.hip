@@ -1,6 +1,14 @@
 // C ABI of the Louvain library (declared in include/lv.h): argument checks,
 // device workspace, and the host-side level driver of Algorithm 3 around the
-// HIP kernels of lv_kernels.hip.
+// HIP kernels.
+//
+// One engine serves every entry point: a handle packs G >= 1 independent
+// graphs into one CSR (vertex segments), and every level runs all of them in
+// the same launches.  Each graph keeps its own total volume M, its own sweep
+// count and stopping rule (kept on the device: no host round trip per sweep,
+// so a level's sweep loop is replayed from a captured HIP graph), its own
+// level acceptance, and leaves the packed graph once its run ends.  A single
+// graph is the case G = 1.
 #include "lv.h"
 #include "lv_internal.h"
 
@@ -62,6 +70,9 @@ hipError_t dev_alloc(void** p, size_t bytes)
 struct DevBuf {
     void* p = nullptr;
     size_t cap = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
     ~DevBuf() { release(); }
     void release()
     {
@@ -83,11 +94,13 @@ struct DevBuf {
 };
 
 struct Workspace {
-    DevBuf comm, sigma, dec, cls, vert, cls_alt, vert_alt, minv, flag, pos, labels, tmp, small;
+    DevBuf comm, sigma, dec, cls, vert, cls_alt, vert_alt, minv, flag, pos, labels, tmp, small, cs;
     DevBuf keys, keys_alt, vals, vals_alt, head;
-    DevBuf g_off[2], g_idx[2], g_w[2], g_k[2];
+    DevBuf g_off[2], g_idx[2], g_w[2], g_k[2], g_gid[2];
     DevBuf hub_table, hub_meta, hub_part, hub_rows, hub_pairs;
-    DevBuf k64, cs;
+    DevBuf k64;
+    // per-graph state of a level (G entries) and sweep control
+    DevBuf ctl, gdone, gsweeps, gmoves, gactive, gsum, gsq, gmeta, segs;
 };
 
 struct Timer {
@@ -115,7 +128,7 @@ struct Timer {
 float elapsed(hipEvent_t a, hipEvent_t b)
 {
     float ms = 0.f;
-    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.f;
+    if (!a || !b || hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.f;
     return ms;
 }
 
@@ -139,13 +152,19 @@ struct lv_graph {
     int device = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
-    int32_t n = 0;
-    int64_t nnz = 0;
+    int32_t n = 0;          // packed vertices
+    int64_t nnz = 0;        // packed entries
+    int32_t G = 1;          // graphs
     DevBuf off, idx, w, k;
     bool weighted = false;  // false: every A entry is 1 (no weights, no loops)
-    int64_t M = 0, trace = 0, sumk2 = 0;
+    std::vector<int32_t> voff;   // [G+1] vertex offset of each graph
+    std::vector<int64_t> eoff;   // [G+1] entry offset of each graph
+    std::vector<int64_t> M;      // [G] total volume
+    std::vector<int64_t> q0;     // [G] Q_int of singletons
+    DevBuf d_gid, d_M;           // per vertex graph id, per graph M (G > 1)
     Workspace ws;
-    int32_t* pinned = nullptr;  // small host staging area
+    int32_t* pinned = nullptr;   // host staging area
+    size_t pinned_bytes = 0;
     ~lv_graph()
     {
         if (pinned) (void)hipHostFree(pinned);
@@ -155,23 +174,35 @@ struct lv_graph {
 
 namespace {
 
+// Labels of one packed level, shared by the graphs that took part in it.
+struct LabelStore {
+    DevBuf labels;
+    int32_t n = 0;
+};
+
 struct LevelRecord {
     lv_level_info info{};
     std::vector<int64_t> moves;
-    DevBuf labels;                  // accepted levels only
-    DevBuf g_off, g_idx, g_w;       // coarse graph (LV_KEEP_GRAPHS)
+    std::shared_ptr<LabelStore> store;  // accepted levels: packed labels of the level
+    int32_t vbase = 0, nbase = 0;       // this graph's slice: labels[vbase + x] - nbase
+    std::shared_ptr<DevBuf> g_off, g_idx, g_w;  // coarse graph (one graph, LV_KEEP_GRAPHS)
     int64_t g_nnz = 0;
+};
+
+struct GraphResult {
+    int32_t n0 = 0, fin_base = 0;
+    int64_t M = 0, q_int = 0;
+    int32_t accepted = 0;
+    std::vector<LevelRecord> levels;
 };
 
 }  // namespace
 
 struct lv_result {
+    int32_t G = 1;
     int32_t n0 = 0;
-    int64_t M = 0;
-    int64_t q_int = 0;
-    int32_t accepted = 0;
-    std::vector<std::unique_ptr<LevelRecord>> levels;
-    DevBuf final_labels;
+    std::vector<GraphResult> graphs;
+    DevBuf final_labels;  // packed like the handle's vertices
 };
 
 namespace {
@@ -248,18 +279,26 @@ lv_status read_params(const lv_params* p, Params& out)
     return LV_OK;
 }
 
-// One level's graph (device pointers).
+// One level's packed graph (device pointers) and its graphs.
 struct LevelGraph {
     int32_t n;
     int64_t nnz;
     const int32_t* off;
     const int32_t* idx;
-    const int32_t* w;  // null = unit
+    const int32_t* w;    // null = unit
     const int32_t* k;
+    int32_t G;           // graphs packed in this level
+    const int32_t* gid;  // per vertex graph (null when G == 1)
+    const int64_t* Mg;   // per graph M, device (null when G == 1)
+    int64_t M;           // M when G == 1
+    std::vector<int32_t> voff;  // [G+1] vertex offsets (host)
+    std::vector<int64_t> Mh;    // [G] total volume of each graph (host)
 };
 
 struct SweepOut {
-    std::vector<int64_t> moves;
+    std::vector<int32_t> sweeps;   // [G]
+    std::vector<uint32_t> moves;   // [G * max_sweeps]
+    int32_t executed = 0;          // sweeps with at least one running graph
     double move_ms = 0, sweep_ms = 0;
     int64_t launches = 0;
     int64_t bytes = 0;
@@ -268,7 +307,7 @@ struct SweepOut {
     int64_t kern_bytes[LV_KERNEL_SLOTS] = {};
 };
 
-// Hub (global table) layout for one level.
+// Hub (partition) layout for one level.
 struct HubPlan {
     int32_t nhubs = 0;
     HubArgs args{};
@@ -389,14 +428,28 @@ lv_status plan_hubs(lv_graph* g, const LevelGraph& G, const int32_t* hub_verts, 
     return LV_OK;
 }
 
+lv_status ensure_pinned(lv_graph* g, size_t bytes)
+{
+    if (g->pinned_bytes >= bytes) return LV_OK;
+    if (g->pinned) (void)hipHostFree(g->pinned);
+    g->pinned = nullptr;
+    g->pinned_bytes = 0;
+    HIP_TRY(hipHostMalloc((void**)&g->pinned, bytes, hipHostMallocDefault));
+    g->pinned_bytes = bytes;
+    return LV_OK;
+}
+
 // Synchronous local-moving sweeps of one level (Algorithm 2; Algorithm 1 in
-// LPA mode).  On return ws.comm holds the level's labels and ws.sigma the
-// community volumes.
-lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p, SweepOut& out)
+// LPA mode) for every graph of G.  gactive (device, may be null) marks the
+// graphs that take part.  On return ws.comm holds the labels and ws.sigma the
+// community volumes; out holds per-graph sweep and move counts.
+lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p, const int32_t* gactive,
+                     SweepOut& out)
 {
     Workspace& ws = g->ws;
     hipStream_t s = g->stream;
     const int32_t n = G.n;
+    const int32_t S = p.max_sweeps;
     const size_t nb = sizeof(int32_t) * (size_t)std::max(n, 1);
     HIP_TRY(ws.comm.ensure(nb));
     HIP_TRY(ws.sigma.ensure(nb));
@@ -408,6 +461,11 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
     HIP_TRY(ws.vert_alt.ensure(nb));
     HIP_TRY(ws.tmp.ensure(std::max(radix_tmp_bytes(n), scan_tmp_bytes(n, 8))));
     HIP_TRY(ws.small.ensure(4096));
+    HIP_TRY(ws.ctl.ensure(sizeof(SweepCtl)));
+    HIP_TRY(ws.gdone.ensure(sizeof(int32_t) * (size_t)G.G));
+    HIP_TRY(ws.gsweeps.ensure(sizeof(int32_t) * (size_t)G.G));
+    HIP_TRY(ws.gmoves.ensure(sizeof(uint32_t) * (size_t)G.G * (size_t)S));
+    LV_TRY(ensure_pinned(g, std::max<size_t>(4096, (sizeof(int32_t) + sizeof(uint32_t) * S) * (size_t)G.G)));
 
     // degree classes: classify, then one stable radix pass groups vertices by class
     HIP_TRY(launch_classify(n, G.off, p.tune.bounds, ws.cls.as<uint32_t>(), ws.vert.as<int32_t>(), s));
@@ -429,21 +487,22 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
 
     HubPlan hubs;
     LV_TRY(plan_hubs(g, G, vert_sorted + start[CLS_HUB], n - start[CLS_HUB], p.tune, hubs));
-    // CSR entries per class, for the per-kernel algorithmic byte counts
+    const bool timing = (p.flags & LV_TIMING) != 0;
     int64_t cls_entries[NUM_CLS] = {};
-    if (p.flags & LV_TIMING) {
+    if (timing) {
         int64_t* d_ce = (int64_t*)(ws.small.as<char>() + 3328);
         HIP_TRY(hipMemsetAsync(d_ce, 0, sizeof cls_entries, s));
         HIP_TRY(launch_class_entries(vert_sorted, start, G.off, d_ce, s));
         HIP_TRY(hipMemcpyAsync(cls_entries, d_ce, sizeof cls_entries, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
     }
-    const int64_t wbytes = G.w ? 8 : 4;
 
+    SweepCtl* ctl = ws.ctl.as<SweepCtl>();
     HIP_TRY(launch_iota(ws.comm.as<int32_t>(), n, s));
     HIP_TRY(launch_copy_i32(ws.sigma.as<int32_t>(), G.k, n, s));
-    HIP_TRY(launch_pairs(n, ws.comm.as<int32_t>(), ws.sigma.as<int32_t>(), ws.cs.as<int2>(), s));
-    uint32_t* d_count = (uint32_t*)(ws.small.as<char>() + 1024);
+    HIP_TRY(launch_pairs(n, ws.comm.as<int32_t>(), ws.sigma.as<int32_t>(), ws.cs.as<int2>(), nullptr, s));
+    HIP_TRY(launch_ctl_init(ctl, G.G, gactive, ws.gdone.as<int32_t>(), ws.gsweeps.as<int32_t>(),
+                            ws.gmoves.as<uint32_t>(), S, s));
 
     MoveArgs a{};
     a.off = G.off;
@@ -453,98 +512,154 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
     a.comm = ws.comm.as<int32_t>();
     a.sigma = ws.sigma.as<int32_t>();
     a.cs = ws.cs.as<int2>();
-    a.M = g->M;
+    a.M = G.M;
+    a.Mg = G.G > 1 ? G.Mg : nullptr;
+    a.gid = G.G > 1 ? G.gid : nullptr;
+    a.gdone = G.G > 1 ? ws.gdone.as<int32_t>() : nullptr;
+    a.ctl = ctl;
     a.mode = mode;
     int32_t* dec_all = ws.dec.as<int32_t>();
+    const int64_t theta = mode == MODE_LPA ? p.lpa_threshold : 0;
 
     Timer tm;
-    tm.on = (p.flags & LV_TIMING) != 0;
+    tm.on = timing;
     tm.s = s;
-    const int64_t sweep_bytes = 4 * ((int64_t)n + 1) + (G.w ? 8 : 4) * G.nnz + 12 * (int64_t)n;
-    const int64_t theta = mode == MODE_LPA ? p.lpa_threshold : 0;
-    out.moves.clear();
-    for (int32_t sw = 1; sw <= p.max_sweeps; ++sw) {
-        a.dir = (sw % 2 == 1) ? DIR_DOWN : DIR_UP;
-        const bool singleton = sw == 1;
-        HIP_TRY(hipMemsetAsync(d_count, 0, sizeof(uint32_t), s));
-        hipEvent_t e0{}, e1{}, e2{};
-        hipEvent_t kb[NUM_CLS] = {}, kend[NUM_CLS] = {};
-        if (tm.on) HIP_TRY(tm.mark(&e0));
+    std::vector<std::vector<hipEvent_t>> ev;  // per sweep: [class begin/end..., sweep begin, moves end, sweep end]
+    // One sweep: move kernels of every class, the partition path, commit,
+    // pair refresh, per-graph stopping rule.
+    auto launch_sweep = [&](bool singleton, std::vector<hipEvent_t>* e) -> lv_status {
+        if (e) { e->assign(2 * NUM_CLS + 3, nullptr); HIP_TRY(tm.mark(&(*e)[2 * NUM_CLS])); }
         for (int c = CLS_G8; c < CLS_HUB; ++c) {
             a.verts = vert_sorted + start[c];
             a.dec = dec_all + start[c];
             a.nverts = start[c + 1] - start[c];
             if (a.nverts == 0) continue;
-            if (tm.on) HIP_TRY(tm.mark(&kb[c]));
+            if (e) HIP_TRY(tm.mark(&(*e)[2 * c]));
             HIP_TRY(launch_move_class(c, singleton, a, s));
-            if (tm.on) HIP_TRY(tm.mark(&kend[c]));
-            ++out.launches;
+            if (e) HIP_TRY(tm.mark(&(*e)[2 * c + 1]));
         }
         if (hubs.nhubs > 0) {
+            a.verts = vert_sorted + start[CLS_HUB];
             a.dec = dec_all + start[CLS_HUB];
-            if (tm.on) HIP_TRY(tm.mark(&kb[CLS_HUB]));
+            a.nverts = hubs.nhubs;
+            if (e) HIP_TRY(tm.mark(&(*e)[2 * CLS_HUB]));
             HIP_TRY(launch_hub_sweep(singleton, a, hubs.args, s));
-            if (tm.on) HIP_TRY(tm.mark(&kend[CLS_HUB]));
-            out.launches += singleton ? 2 : 3;
+            if (e) HIP_TRY(tm.mark(&(*e)[2 * CLS_HUB + 1]));
         }
-        if (tm.on) HIP_TRY(tm.mark(&e1));
-        HIP_TRY(launch_apply(vert_sorted + start[CLS_G8], dec_all + start[CLS_G8], active, G.k,
-                             ws.comm.as<int32_t>(), ws.sigma.as<int32_t>(), d_count, s));
-        HIP_TRY(launch_pairs(n, ws.comm.as<int32_t>(), ws.sigma.as<int32_t>(), ws.cs.as<int2>(), s));
-        if (tm.on) HIP_TRY(tm.mark(&e2));
-        uint32_t cnt = 0;
-        HIP_TRY(hipMemcpyAsync(g->pinned, d_count, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        std::memcpy(&cnt, g->pinned, sizeof cnt);
-        out.moves.push_back((int64_t)cnt);
-        out.bytes += sweep_bytes;
-        if (tm.on) {
-            out.move_ms += elapsed(e0, e1);
-            out.sweep_ms += elapsed(e0, e2);
-            for (int c = CLS_G8; c <= CLS_HUB; ++c) {
-                const int32_t nv = start[c + 1] - start[c];
-                if (nv == 0) continue;
-                const int slot = 2 * c + (singleton ? 1 : 0) - 2;
-                out.kern_ms[slot] += elapsed(kb[c], kend[c]);
-                out.kern_launches[slot] += 1;
-                out.kern_bytes[slot] += wbytes * cls_entries[c] + 20 * (int64_t)nv;
+        if (e) HIP_TRY(tm.mark(&(*e)[2 * NUM_CLS + 1]));
+        HIP_TRY(launch_apply(vert_sorted + start[CLS_G8], dec_all + start[CLS_G8], active, G.k, a.gid,
+                             ws.comm.as<int32_t>(), ws.sigma.as<int32_t>(), ctl, ws.gmoves.as<uint32_t>(), S, s));
+        HIP_TRY(launch_pairs(n, ws.comm.as<int32_t>(), ws.sigma.as<int32_t>(), ws.cs.as<int2>(), ctl, s));
+        HIP_TRY(launch_sweep_end(ctl, G.G, ws.gdone.as<int32_t>(), ws.gsweeps.as<int32_t>(),
+                                 ws.gmoves.as<uint32_t>(), S, theta, s));
+        if (e) HIP_TRY(tm.mark(&(*e)[2 * NUM_CLS + 2]));
+        return LV_OK;
+    };
+    const bool use_graph = !timing && !(p.flags & LV_NO_HIPGRAPH);
+    if (use_graph) {
+        // capture the first sweep and a later sweep once, then replay: the
+        // kernels read the sweep counter and early-exit flag from the device
+        hipGraph_t gr[2] = {nullptr, nullptr};
+        hipGraphExec_t ex[2] = {nullptr, nullptr};
+        lv_status st = LV_OK;
+        for (int q = 0; q < 2 && st == LV_OK; ++q) {
+            hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) { set_error("hipStreamBeginCapture", e); st = from_hip(e); break; }
+            st = launch_sweep(q == 0, nullptr);
+            hipGraph_t gq = nullptr;
+            e = hipStreamEndCapture(s, &gq);
+            if (st == LV_OK && e != hipSuccess) { set_error("hipStreamEndCapture", e); st = from_hip(e); }
+            gr[q] = gq;
+            if (st == LV_OK) {
+                e = hipGraphInstantiate(&ex[q], gr[q], nullptr, nullptr, 0);
+                if (e != hipSuccess) { set_error("hipGraphInstantiate", e); st = from_hip(e); }
             }
-            tm.used = 0;
         }
-        const size_t m = out.moves.size();
-        if (m >= 2 && out.moves[m - 1] <= theta && out.moves[m - 2] <= theta) break;
+        if (st == LV_OK) {
+            for (int32_t sw = 1; sw <= S && st == LV_OK; ++sw) {
+                hipError_t e = hipGraphLaunch(ex[sw == 1 ? 0 : 1], s);
+                if (e != hipSuccess) { set_error("hipGraphLaunch", e); st = from_hip(e); }
+            }
+        }
+        hipError_t es = hipStreamSynchronize(s);
+        for (int q = 0; q < 2; ++q) {
+            if (ex[q]) (void)hipGraphExecDestroy(ex[q]);
+            if (gr[q]) (void)hipGraphDestroy(gr[q]);
+        }
+        LV_TRY(st);
+        HIP_TRY(es);
+    } else {
+        ev.resize(S);
+        for (int32_t sw = 1; sw <= S; ++sw) LV_TRY(launch_sweep(sw == 1, timing ? &ev[sw - 1] : nullptr));
     }
+    // per-graph sweep and move counts (one host round trip per level)
+    uint32_t* h_moves = (uint32_t*)g->pinned;
+    int32_t* h_sweeps = (int32_t*)(h_moves + (size_t)G.G * S);
+    HIP_TRY(hipMemcpyAsync(h_moves, ws.gmoves.p, sizeof(uint32_t) * (size_t)G.G * S, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(h_sweeps, ws.gsweeps.p, sizeof(int32_t) * (size_t)G.G, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    out.moves.assign(h_moves, h_moves + (size_t)G.G * S);
+    out.sweeps.assign(h_sweeps, h_sweeps + G.G);
+    out.executed = 0;
+    for (int32_t q = 0; q < G.G; ++q) out.executed = std::max(out.executed, out.sweeps[q]);
+    const int64_t wbytes = G.w ? 8 : 4;
+    out.bytes = (4 * ((int64_t)n + 1) + wbytes * G.nnz + 12 * (int64_t)n) * out.executed;
+    for (int32_t sw = 1; sw <= out.executed; ++sw) {
+        for (int c = CLS_G8; c <= CLS_HUB; ++c) {
+            const int32_t nv = start[c + 1] - start[c];
+            if (nv == 0) continue;
+            out.launches += c == CLS_HUB ? (sw == 1 ? 2 : 2 + (hubs.args.pregather ? 1 : 0)) : 1;
+            if (!timing) continue;
+            const int slot = 2 * c + (sw == 1 ? 1 : 0) - 2;
+            out.kern_ms[slot] += elapsed(ev[sw - 1][2 * c], ev[sw - 1][2 * c + 1]);
+            out.kern_launches[slot] += 1;
+            out.kern_bytes[slot] += wbytes * cls_entries[c] + 20 * (int64_t)nv;
+        }
+        if (timing) {
+            out.move_ms += elapsed(ev[sw - 1][2 * NUM_CLS], ev[sw - 1][2 * NUM_CLS + 1]);
+            out.sweep_ms += elapsed(ev[sw - 1][2 * NUM_CLS], ev[sw - 1][2 * NUM_CLS + 2]);
+        }
+    }
+    return LV_OK;
+}
+
+// Renumber communities by smallest member (first occurrence) into ws.labels;
+// n2 = communities; voff2[c] = first new label of graph c.
+lv_status renumber(lv_graph* g, const LevelGraph& G, int32_t* n2, std::vector<int32_t>& voff2)
+{
+    Workspace& ws = g->ws;
+    hipStream_t s = g->stream;
+    const int32_t n = G.n;
+    const size_t nb = sizeof(int32_t) * (size_t)(n + 1);
+    HIP_TRY(ws.minv.ensure(nb));
+    HIP_TRY(ws.flag.ensure(nb));
+    HIP_TRY(ws.pos.ensure(nb));
+    HIP_TRY(ws.labels.ensure(nb));
+    HIP_TRY(ws.gmeta.ensure(sizeof(int32_t) * ((size_t)G.G + 1)));
+    int32_t* pos = ws.pos.as<int32_t>();
+    // pos[n] receives the total
+    HIP_TRY(launch_renumber(n, ws.comm.as<int32_t>(), ws.minv.as<int32_t>(), ws.flag.as<int32_t>(), pos,
+                            ws.labels.as<int32_t>(), pos + n, ws.tmp.p, ws.tmp.cap, g->stream));
+    // the new base of graph c is the number of communities before its first vertex
+    std::vector<int32_t> at(G.voff.begin(), G.voff.end());
+    HIP_TRY(hipMemcpyAsync(ws.gmeta.p, at.data(), sizeof(int32_t) * at.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_gather_i32(pos, ws.gmeta.as<int32_t>(), G.G + 1, ws.gmeta.as<int32_t>(), s));
+    voff2.resize(G.G + 1);
+    HIP_TRY(hipMemcpyAsync(voff2.data(), ws.gmeta.p, sizeof(int32_t) * ((size_t)G.G + 1), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *n2 = voff2[G.G];
     return LV_OK;
 }
 
 struct Coarse {
     int32_t n2 = 0;
     int64_t nnz2 = 0;
-    int32_t *off = nullptr, *idx = nullptr, *w = nullptr, *k = nullptr;
-    int64_t q_end = 0;
+    int32_t *off = nullptr, *idx = nullptr, *w = nullptr, *k = nullptr, *gid = nullptr;
+    std::vector<int64_t> q_end;  // [G] Q_int of each graph's partition = M * Sigma_in - sum k'^2
 };
 
-// Renumber communities by smallest member (first occurrence); labels -> ws.labels.
-lv_status renumber(lv_graph* g, int32_t n, int32_t* n2)
-{
-    Workspace& ws = g->ws;
-    hipStream_t s = g->stream;
-    const size_t nb = sizeof(int32_t) * (size_t)std::max(n, 1);
-    HIP_TRY(ws.minv.ensure(nb));
-    HIP_TRY(ws.flag.ensure(nb));
-    HIP_TRY(ws.pos.ensure(nb));
-    HIP_TRY(ws.labels.ensure(nb));
-    int32_t* d_n2 = (int32_t*)(ws.small.as<char>() + 2048);
-    HIP_TRY(launch_renumber(n, ws.comm.as<int32_t>(), ws.minv.as<int32_t>(), ws.flag.as<int32_t>(),
-                            ws.pos.as<int32_t>(), ws.labels.as<int32_t>(), d_n2, ws.tmp.p, ws.tmp.cap, g->stream));
-    HIP_TRY(hipMemcpyAsync(g->pinned, d_n2, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    std::memcpy(n2, g->pinned, sizeof(int32_t));
-    return LV_OK;
-}
-
-// Aggregation (Algorithm 3): coarse CSR A' = S^T A S into ping-pong slot `slot`;
-// also Q_end = M * Sigma_in - sum_P k'_P^2, the modularity of the level's partition.
+// Aggregation (Algorithm 3): coarse CSR A' = S^T A S of the packed level into
+// ping-pong slot `slot`, with each coarse vertex's graph and degree.
 lv_status aggregate(lv_graph* g, const LevelGraph& G, int32_t n2, int slot, Coarse& out)
 {
     Workspace& ws = g->ws;
@@ -561,13 +676,19 @@ lv_status aggregate(lv_graph* g, const LevelGraph& G, int32_t n2, int slot, Coar
     HIP_TRY(ws.tmp.ensure(std::max(radix_tmp_bytes(E), scan_tmp_bytes(std::max<int64_t>(E, n2 + 1), 8))));
     HIP_TRY(ws.g_off[slot].ensure(sizeof(int32_t) * ((size_t)n2 + 1)));
     HIP_TRY(ws.g_k[slot].ensure(sizeof(int32_t) * (size_t)std::max(n2, 1)));
-    int64_t* d_q = (int64_t*)(ws.small.as<char>() + 2560);  // [0] Sigma_in, [1] sum k'^2
-    HIP_TRY(hipMemsetAsync(d_q, 0, 2 * sizeof(int64_t), s));
+    HIP_TRY(ws.g_gid[slot].ensure(sizeof(int32_t) * (size_t)std::max(n2, 1)));
+    HIP_TRY(ws.gsum.ensure(sizeof(int64_t) * (size_t)G.G));
+    HIP_TRY(ws.gsq.ensure(sizeof(int64_t) * (size_t)G.G));
+    int64_t* d_sin = ws.gsum.as<int64_t>();
+    int64_t* d_sq = ws.gsq.as<int64_t>();
+    HIP_TRY(hipMemsetAsync(d_sin, 0, sizeof(int64_t) * (size_t)G.G, s));
+    HIP_TRY(hipMemsetAsync(d_sq, 0, sizeof(int64_t) * (size_t)G.G, s));
+    int32_t* gid2 = G.gid ? ws.g_gid[slot].as<int32_t>() : nullptr;
     HIP_TRY(launch_coarse_degree(G.n, ws.comm.as<int32_t>(), ws.flag.as<int32_t>(), ws.labels.as<int32_t>(),
-                                 ws.sigma.as<int32_t>(), ws.g_k[slot].as<int32_t>(), s));
-    HIP_TRY(launch_sum_sq(ws.g_k[slot].as<int32_t>(), n2, d_q + 1, s));
+                                 ws.sigma.as<int32_t>(), G.gid, ws.g_k[slot].as<int32_t>(), gid2, s));
+    HIP_TRY(launch_sum_sq(ws.g_k[slot].as<int32_t>(), n2, gid2, d_sq, s));
     HIP_TRY(launch_build_keys(G.n, G.off, G.idx, G.w, E, ws.labels.as<int32_t>(), colbits, ws.keys.as<uint64_t>(),
-                              ws.vals.as<int32_t>(), d_q, s));
+                              ws.vals.as<int32_t>(), G.gid, d_sin, s));
     bool in_alt = false;
     HIP_TRY(radix_sort_u64(ws.keys.as<uint64_t>(), ws.vals.as<int32_t>(), ws.keys_alt.as<uint64_t>(),
                            ws.vals_alt.as<int32_t>(), E, bits, ws.tmp.p, ws.tmp.cap, &in_alt, s));
@@ -577,14 +698,17 @@ lv_status aggregate(lv_graph* g, const LevelGraph& G, int32_t n2, int slot, Coar
     int32_t* d_e2 = (int32_t*)(ws.small.as<char>() + 2304);
     HIP_TRY(launch_segment_heads(keys, E, ws.head.as<int32_t>(), s));
     HIP_TRY(scan_exclusive_i32(ws.head.as<int32_t>(), ws.head.as<int32_t>(), E, d_e2, ws.tmp.p, ws.tmp.cap, s));
-    int64_t q2[2];
-    HIP_TRY(hipMemcpyAsync(g->pinned, d_e2, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(g->pinned + 2, d_q, sizeof q2, hipMemcpyDeviceToHost, s));
+    LV_TRY(ensure_pinned(g, std::max<size_t>(4096, 2 * sizeof(int64_t) * (size_t)G.G + 64)));
+    int64_t* h_q = (int64_t*)g->pinned;
+    HIP_TRY(hipMemcpyAsync(h_q, d_sin, sizeof(int64_t) * (size_t)G.G, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(h_q + G.G, d_sq, sizeof(int64_t) * (size_t)G.G, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(h_q + 2 * G.G, d_e2, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     int32_t e2 = 0;
-    std::memcpy(&e2, g->pinned, sizeof e2);
-    std::memcpy(q2, g->pinned + 2, sizeof q2);
+    std::memcpy(&e2, h_q + 2 * G.G, sizeof e2);
     if (E == 0) e2 = 0;
+    out.q_end.resize(G.G);
+    for (int32_t c = 0; c < G.G; ++c) out.q_end[c] = G.Mh[c] * h_q[c] - h_q[G.G + c];
     HIP_TRY(ws.g_idx[slot].ensure(sizeof(int32_t) * (size_t)std::max(e2, 1)));
     HIP_TRY(ws.g_w[slot].ensure(sizeof(int32_t) * (size_t)std::max(e2, 1)));
     int32_t* off2 = ws.g_off[slot].as<int32_t>();
@@ -598,7 +722,280 @@ lv_status aggregate(lv_graph* g, const LevelGraph& G, int32_t n2, int slot, Coar
     out.idx = ws.g_idx[slot].as<int32_t>();
     out.w = ws.g_w[slot].as<int32_t>();
     out.k = ws.g_k[slot].as<int32_t>();
-    out.q_end = g->M * q2[0] - q2[1];
+    out.gid = gid2;
+    return LV_OK;
+}
+
+// Entry offsets of the graphs of a packed CSR: eoff[c] = off[voff[c]].
+lv_status graph_entry_offsets(lv_graph* g, const int32_t* off, const std::vector<int32_t>& voff,
+                              std::vector<int64_t>& eoff)
+{
+    Workspace& ws = g->ws;
+    hipStream_t s = g->stream;
+    const int32_t m = (int32_t)voff.size();
+    HIP_TRY(ws.gmeta.ensure(sizeof(int32_t) * (size_t)m));
+    HIP_TRY(hipMemcpyAsync(ws.gmeta.p, voff.data(), sizeof(int32_t) * (size_t)m, hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_gather_i32(off, ws.gmeta.as<int32_t>(), m, ws.gmeta.as<int32_t>(), s));
+    std::vector<int32_t> e(m);
+    HIP_TRY(hipMemcpyAsync(e.data(), ws.gmeta.p, sizeof(int32_t) * (size_t)m, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    eoff.assign(e.begin(), e.end());
+    return LV_OK;
+}
+
+// Next level's packed graph from the coarse one, keeping only the graphs in
+// `keep` (coarse slots, increasing): their segments are copied, in order,
+// into ping-pong slot `dst`.
+lv_status repack(lv_graph* g, const Coarse& co, const std::vector<int32_t>& voff2, const std::vector<int64_t>& eoff2,
+                 const std::vector<int32_t>& keep, int dst, LevelGraph& next)
+{
+    Workspace& ws = g->ws;
+    hipStream_t s = g->stream;
+    std::vector<RepackSeg> segs;
+    int32_t nv = 0;
+    int64_t ne = 0;
+    next.voff.assign(1, 0);
+    for (int32_t c : keep) {
+        RepackSeg q{};
+        q.src_off = co.off;
+        q.src_idx = co.idx;
+        q.src_w = co.w;
+        q.src_k = co.k;
+        q.src_vb = voff2[c];
+        q.n = voff2[c + 1] - voff2[c];
+        q.dst_vb = nv;
+        q.dst_eb = ne;
+        segs.push_back(q);
+        nv += q.n;
+        ne += eoff2[c + 1] - eoff2[c];
+        next.voff.push_back(nv);
+    }
+    HIP_TRY(ws.segs.ensure(sizeof(RepackSeg) * segs.size()));
+    HIP_TRY(hipMemcpyAsync(ws.segs.p, segs.data(), sizeof(RepackSeg) * segs.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(ws.g_off[dst].ensure(sizeof(int32_t) * ((size_t)nv + 1)));
+    HIP_TRY(ws.g_idx[dst].ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(ne, 1)));
+    HIP_TRY(ws.g_w[dst].ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(ne, 1)));
+    HIP_TRY(ws.g_k[dst].ensure(sizeof(int32_t) * (size_t)std::max(nv, 1)));
+    HIP_TRY(ws.g_gid[dst].ensure(sizeof(int32_t) * (size_t)std::max(nv, 1)));
+    HIP_TRY(launch_repack(ws.segs.as<RepackSeg>(), (int32_t)segs.size(), nv, ne, ws.g_off[dst].as<int32_t>(),
+                          ws.g_idx[dst].as<int32_t>(), ws.g_w[dst].as<int32_t>(), ws.g_k[dst].as<int32_t>(),
+                          ws.g_gid[dst].as<int32_t>(), s));
+    HIP_TRY(hipStreamSynchronize(s));  // the host segment list must outlive the copy
+    next.n = nv;
+    next.nnz = ne;
+    next.off = ws.g_off[dst].as<int32_t>();
+    next.idx = ws.g_idx[dst].as<int32_t>();
+    next.w = ws.g_w[dst].as<int32_t>();
+    next.k = ws.g_k[dst].as<int32_t>();
+    next.G = (int32_t)keep.size();
+    next.gid = next.G > 1 ? ws.g_gid[dst].as<int32_t>() : nullptr;
+    return LV_OK;
+}
+
+// Upload per-graph M of a level (several graphs) to the device.
+lv_status upload_M(lv_graph* g, DevBuf& buf, LevelGraph& G)
+{
+    G.M = G.Mh.empty() ? 0 : G.Mh[0];
+    if (G.G <= 1) { G.Mg = nullptr; return LV_OK; }
+    HIP_TRY(buf.ensure(sizeof(int64_t) * (size_t)G.G));
+    HIP_TRY(hipMemcpyAsync(buf.p, G.Mh.data(), sizeof(int64_t) * (size_t)G.G, hipMemcpyHostToDevice, g->stream));
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    G.Mg = buf.as<int64_t>();
+    return LV_OK;
+}
+
+LevelGraph level0(lv_graph* g)
+{
+    LevelGraph G;
+    G.n = g->n;
+    G.nnz = g->nnz;
+    G.off = g->off.as<int32_t>();
+    G.idx = g->idx.as<int32_t>();
+    G.w = g->weighted ? g->w.as<int32_t>() : nullptr;
+    G.k = g->k.as<int32_t>();
+    G.G = g->G;
+    G.gid = g->G > 1 ? g->d_gid.as<int32_t>() : nullptr;
+    G.Mg = g->G > 1 ? g->d_M.as<int64_t>() : nullptr;
+    G.M = g->M[0];
+    G.voff = g->voff;
+    G.Mh = g->M;
+    return G;
+}
+
+void fill_info(lv_level_info& li, const SweepOut& so, int32_t c, int32_t S)
+{
+    li.sweeps = so.sweeps[c];
+    li.move_ms = so.move_ms;
+    li.sweep_ms = so.sweep_ms;
+    li.move_launches = so.launches;
+    li.move_bytes = so.bytes;
+    for (int t = 0; t < LV_KERNEL_SLOTS; ++t) {
+        li.kern_ms[t] = so.kern_ms[t];
+        li.kern_launches[t] = so.kern_launches[t];
+        li.kern_bytes[t] = so.kern_bytes[t];
+    }
+    (void)S;
+}
+
+// Multi-level Louvain (Algorithm 3) for every graph of the handle.
+lv_status louvain_impl(lv_graph* g, const Params& p, bool keep_graphs, lv_result* r)
+{
+    hipStream_t s = g->stream;
+    Workspace& ws = g->ws;
+    const int32_t G0 = g->G, S = p.max_sweeps;
+    r->G = G0;
+    r->n0 = g->n;
+    r->graphs.resize(G0);
+    for (int32_t q = 0; q < G0; ++q) {
+        GraphResult& gr = r->graphs[q];
+        gr.n0 = g->voff[q + 1] - g->voff[q];
+        gr.fin_base = g->voff[q];
+        gr.M = g->M[q];
+        gr.q_int = g->q0[q];
+    }
+    HIP_TRY(r->final_labels.ensure(sizeof(int32_t) * (size_t)std::max(g->n, 1)));
+    // final labels start as each vertex's index within its graph
+    {
+        HIP_TRY(ws.gmeta.ensure(sizeof(int32_t) * ((size_t)G0 + 1)));
+        HIP_TRY(hipMemcpyAsync(ws.gmeta.p, g->voff.data(), sizeof(int32_t) * ((size_t)G0 + 1), hipMemcpyHostToDevice, s));
+        HIP_TRY(launch_iota(r->final_labels.as<int32_t>(), g->n, s));
+        HIP_TRY(launch_local_labels(g->n, r->final_labels.as<int32_t>(), G0 > 1 ? g->d_gid.as<int32_t>() : nullptr,
+                                    ws.gmeta.as<int32_t>(), r->final_labels.as<int32_t>(), s));
+    }
+    LevelGraph G = level0(g);
+    std::vector<int64_t> eoff = g->eoff;
+    std::vector<int32_t> orig(G0);
+    for (int32_t q = 0; q < G0; ++q) orig[q] = q;
+    std::vector<int64_t> qstart = g->q0;
+    DevBuf Mbuf;
+    int slot = 0;
+    Timer tm;
+    tm.on = (p.flags & LV_TIMING) != 0;
+    tm.s = s;
+    for (;;) {
+        SweepOut so;
+        LV_TRY(run_sweeps(g, G, MODE_LOUVAIN, p, nullptr, so));
+        hipEvent_t t0{}, t1{}, t2{};
+        if (tm.on) HIP_TRY(tm.mark(&t0));
+        int32_t n2 = 0;
+        std::vector<int32_t> voff2;
+        LV_TRY(renumber(g, G, &n2, voff2));
+        if (tm.on) HIP_TRY(tm.mark(&t1));
+        Coarse co;
+        LV_TRY(aggregate(g, G, n2, slot, co));
+        std::vector<int64_t> eoff2;
+        LV_TRY(graph_entry_offsets(g, co.off, voff2, eoff2));
+        double ren_ms = 0, agg_ms = 0;
+        if (tm.on) {
+            HIP_TRY(tm.mark(&t2));
+            HIP_TRY(hipStreamSynchronize(s));
+            ren_ms = elapsed(t0, t1);
+            agg_ms = elapsed(t1, t2);
+            tm.used = 0;
+        }
+        // per-graph acceptance
+        std::vector<int32_t> acc(G.G, 0), keep;
+        bool any = false;
+        for (int32_t c = 0; c < G.G; ++c) {
+            acc[c] = co.q_end[c] > qstart[c] ? 1 : 0;
+            any = any || acc[c];
+        }
+        std::shared_ptr<LabelStore> store;
+        if (any) {
+            store = std::make_shared<LabelStore>();
+            store->n = G.n;
+            HIP_TRY(store->labels.ensure(sizeof(int32_t) * (size_t)std::max(G.n, 1)));
+            HIP_TRY(launch_copy_i32(store->labels.as<int32_t>(), ws.labels.as<int32_t>(), G.n, s));
+        }
+        for (int32_t c = 0; c < G.G; ++c) {
+            GraphResult& gr = r->graphs[orig[c]];
+            LevelRecord rec;
+            lv_level_info& li = rec.info;
+            li.n = G.voff[c + 1] - G.voff[c];
+            li.n_next = voff2[c + 1] - voff2[c];
+            li.nnz = eoff[c + 1] - eoff[c];
+            li.q_start = qstart[c];
+            li.q_end = co.q_end[c];
+            li.accepted = acc[c];
+            li.renumber_ms = ren_ms;
+            li.aggregate_ms = agg_ms;
+            fill_info(li, so, c, S);
+            rec.moves.assign(so.moves.begin() + (size_t)c * S, so.moves.begin() + (size_t)c * S + so.sweeps[c]);
+            if (acc[c]) {
+                rec.store = store;
+                rec.vbase = G.voff[c];
+                rec.nbase = voff2[c];
+                gr.q_int = co.q_end[c];
+                ++gr.accepted;
+                if (keep_graphs && G0 == 1) {
+                    rec.g_off = std::make_shared<DevBuf>();
+                    rec.g_idx = std::make_shared<DevBuf>();
+                    rec.g_w = std::make_shared<DevBuf>();
+                    HIP_TRY(rec.g_off->ensure(sizeof(int32_t) * ((size_t)co.n2 + 1)));
+                    HIP_TRY(rec.g_idx->ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(co.nnz2, 1)));
+                    HIP_TRY(rec.g_w->ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(co.nnz2, 1)));
+                    HIP_TRY(launch_copy_i32(rec.g_off->as<int32_t>(), co.off, (int64_t)co.n2 + 1, s));
+                    HIP_TRY(launch_copy_i32(rec.g_idx->as<int32_t>(), co.idx, co.nnz2, s));
+                    HIP_TRY(launch_copy_i32(rec.g_w->as<int32_t>(), co.w, co.nnz2, s));
+                    rec.g_nnz = co.nnz2;
+                }
+                if (gr.accepted < p.max_levels) keep.push_back(c);
+            }
+            gr.levels.push_back(std::move(rec));
+        }
+        // compose the final labels of the graphs that accepted this level
+        if (any) {
+            if (G0 == 1) {
+                HIP_TRY(launch_compose(g->n, r->final_labels.as<int32_t>(), ws.labels.as<int32_t>(), nullptr, nullptr,
+                                       nullptr, nullptr, s));
+            } else {
+                std::vector<int32_t> meta((size_t)G0 + 2 * (size_t)G.G, -1);
+                for (int32_t c = 0; c < G.G; ++c) {
+                    if (acc[c]) meta[orig[c]] = c;
+                    meta[G0 + c] = G.voff[c];
+                    meta[G0 + G.G + c] = voff2[c];
+                }
+                HIP_TRY(ws.gmeta.ensure(sizeof(int32_t) * meta.size()));
+                HIP_TRY(hipMemcpyAsync(ws.gmeta.p, meta.data(), sizeof(int32_t) * meta.size(), hipMemcpyHostToDevice, s));
+                HIP_TRY(launch_compose(g->n, r->final_labels.as<int32_t>(), ws.labels.as<int32_t>(),
+                                       g->d_gid.as<int32_t>(), ws.gmeta.as<int32_t>(), ws.gmeta.as<int32_t>() + G0,
+                                       ws.gmeta.as<int32_t>() + G0 + G.G, s));
+                HIP_TRY(hipStreamSynchronize(s));
+            }
+        }
+        if (keep.empty()) break;
+        LevelGraph next;
+        std::vector<int32_t> orig2;
+        std::vector<int64_t> q2, eoff_next;
+        for (int32_t c : keep) {
+            orig2.push_back(orig[c]);
+            q2.push_back(co.q_end[c]);
+            next.Mh.push_back(G.Mh[c]);
+        }
+        if ((int32_t)keep.size() == G.G) {
+            next.n = co.n2;
+            next.nnz = co.nnz2;
+            next.off = co.off;
+            next.idx = co.idx;
+            next.w = co.w;
+            next.k = co.k;
+            next.G = G.G;
+            next.gid = G.G > 1 ? co.gid : nullptr;
+            next.voff = voff2;
+            eoff_next = eoff2;
+            slot ^= 1;
+        } else {
+            LV_TRY(repack(g, co, voff2, eoff2, keep, slot ^ 1, next));
+            eoff_next.assign(1, 0);
+            for (int32_t c : keep) eoff_next.push_back(eoff_next.back() + (eoff2[c + 1] - eoff2[c]));
+        }
+        LV_TRY(upload_M(g, Mbuf, next));
+        G = std::move(next);
+        eoff = std::move(eoff_next);
+        orig = std::move(orig2);
+        qstart = std::move(q2);
+    }
+    HIP_TRY(hipStreamSynchronize(s));
     return LV_OK;
 }
 
@@ -608,6 +1005,44 @@ lv_status copy_out(int32_t* dst, const int32_t* src_dev, int64_t count, lv_memki
     HIP_TRY(hipMemcpyAsync(dst, src_dev, sizeof(int32_t) * (size_t)count,
                            kind == LV_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, s));
     HIP_TRY(hipStreamSynchronize(s));
+    return LV_OK;
+}
+
+// LPA (Algorithm 1) as one level of synchronous sweeps for every graph of the
+// handle; labels (numbered within each graph) into ws.labels' slot `out`.
+lv_status lpa_impl(lv_graph* g, const Params& p, int32_t* out_dev, SweepOut& so, std::vector<int32_t>& voff2,
+                   std::vector<int64_t>& q_int, double* ren_ms)
+{
+    Workspace& ws = g->ws;
+    hipStream_t s = g->stream;
+    LevelGraph G = level0(g);
+    LV_TRY(run_sweeps(g, G, MODE_LPA, p, nullptr, so));
+    Timer tm;
+    tm.on = (p.flags & LV_TIMING) != 0;
+    tm.s = s;
+    hipEvent_t t0{}, t1{};
+    if (tm.on) HIP_TRY(tm.mark(&t0));
+    int32_t n2 = 0;
+    LV_TRY(renumber(g, G, &n2, voff2));
+    if (tm.on) HIP_TRY(tm.mark(&t1));
+    // Q_int of each graph's partition: M * Sigma_in - sum of its community volumes squared
+    HIP_TRY(ws.gsum.ensure(sizeof(int64_t) * (size_t)G.G));
+    HIP_TRY(ws.gsq.ensure(sizeof(int64_t) * (size_t)G.G));
+    HIP_TRY(hipMemsetAsync(ws.gsum.p, 0, sizeof(int64_t) * (size_t)G.G, s));
+    HIP_TRY(hipMemsetAsync(ws.gsq.p, 0, sizeof(int64_t) * (size_t)G.G, s));
+    HIP_TRY(launch_sigma_in(G.n, G.off, G.idx, G.w, G.nnz, ws.comm.as<int32_t>(), G.gid, ws.gsum.as<int64_t>(), s));
+    HIP_TRY(launch_sum_sq(ws.sigma.as<int32_t>(), G.n, G.gid, ws.gsq.as<int64_t>(), s));
+    std::vector<int64_t> sin(G.G), sq(G.G);
+    HIP_TRY(hipMemcpyAsync(sin.data(), ws.gsum.p, sizeof(int64_t) * (size_t)G.G, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(sq.data(), ws.gsq.p, sizeof(int64_t) * (size_t)G.G, hipMemcpyDeviceToHost, s));
+    // labels numbered within each graph
+    HIP_TRY(ws.gmeta.ensure(sizeof(int32_t) * ((size_t)G.G + 1)));
+    HIP_TRY(hipMemcpyAsync(ws.gmeta.p, voff2.data(), sizeof(int32_t) * ((size_t)G.G + 1), hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_local_labels(G.n, ws.labels.as<int32_t>(), G.gid, ws.gmeta.as<int32_t>(), out_dev, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    q_int.resize(G.G);
+    for (int32_t c = 0; c < G.G; ++c) q_int[c] = G.Mh[c] * sin[c] - sq[c];
+    *ren_ms = tm.on ? elapsed(t0, t1) : 0.0;
     return LV_OK;
 }
 
@@ -648,36 +1083,36 @@ const char* lv_status_str(lv_status s)
 
 const char* lv_last_error(void) { return g_last_error.c_str(); }
 
+// Device setup of a packed CSR (offsets/indices/weights in `kind` memory,
+// graph g at vertices [voff[g], voff[g+1])): validation, loop doubling,
+// degrees, per-graph M and singleton Q_int.
 static lv_status graph_setup(lv_graph* g, int32_t n, const int32_t* offsets, const int32_t* indices,
-                             const int32_t* weights, lv_memkind kind, uint32_t flags)
+                             const int32_t* weights, lv_memkind kind, uint32_t flags, const std::vector<int32_t>& voff)
 {
     hipStream_t s = g->stream;
-    HIP_TRY(hipHostMalloc((void**)&g->pinned, 4096, hipHostMallocDefault));
-    // offsets first: nnz is needed to size the rest
+    LV_TRY(ensure_pinned(g, 4096));
+    const hipMemcpyKind hk = kind == LV_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
     HIP_TRY(g->off.ensure(sizeof(int32_t) * ((size_t)n + 1)));
-    HIP_TRY(hipMemcpyAsync(g->off.p, offsets, sizeof(int32_t) * ((size_t)n + 1),
-                           kind == LV_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(g->off.p, offsets, sizeof(int32_t) * ((size_t)n + 1), hk, s));
     int32_t first_last[2];
     HIP_TRY(hipMemcpyAsync(&first_last[0], g->off.as<int32_t>(), sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(&first_last[1], g->off.as<int32_t>() + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (first_last[0] != 0 || first_last[1] < 0) { set_error_msg("offsets[0] must be 0 and offsets[n] >= 0"); return LV_E_CSR; }
     const int64_t nnz = first_last[1];
+    const int32_t G = (int32_t)voff.size() - 1;
     g->n = n;
     g->nnz = nnz;
+    g->G = G;
+    g->voff = voff;
     HIP_TRY(g->idx.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(nnz, 1)));
-    if (nnz > 0)
-        HIP_TRY(hipMemcpyAsync(g->idx.p, indices, sizeof(int32_t) * (size_t)nnz,
-                               kind == LV_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, s));
+    if (nnz > 0) HIP_TRY(hipMemcpyAsync(g->idx.p, indices, sizeof(int32_t) * (size_t)nnz, hk, s));
     Workspace& ws = g->ws;
     HIP_TRY(ws.small.ensure(4096));
     int32_t* d_err = ws.small.as<int32_t>();
     HIP_TRY(hipMemsetAsync(d_err, 0, 16, s));
-    // caller weights staged in the w buffer (converted in place below)
     HIP_TRY(g->w.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(nnz, 1)));
-    if (weights && nnz > 0)
-        HIP_TRY(hipMemcpyAsync(g->w.p, weights, sizeof(int32_t) * (size_t)nnz,
-                               kind == LV_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, s));
+    if (weights && nnz > 0) HIP_TRY(hipMemcpyAsync(g->w.p, weights, sizeof(int32_t) * (size_t)nnz, hk, s));
     HIP_TRY(launch_check_offsets(n, g->off.as<int32_t>(), nnz, d_err, s));
     int32_t err = 0;
     HIP_TRY(hipMemcpyAsync(&err, d_err, sizeof err, hipMemcpyDeviceToHost, s));
@@ -692,6 +1127,15 @@ static lv_status graph_setup(lv_graph* g, int32_t n, const int32_t* offsets, con
     if (err & 2) { set_error_msg("column index out of range or row not strictly increasing"); return LV_E_CSR; }
     if (err & 4) { set_error_msg("weight < 1"); return LV_E_WEIGHT; }
     if (err & 8) { set_error_msg("entry without a symmetric partner of equal weight"); return LV_E_ASYMMETRIC; }
+    // graph ids and entry offsets of the packed graphs
+    HIP_TRY(ws.gmeta.ensure(sizeof(int32_t) * ((size_t)G + 1)));
+    if (G > 1) {
+        HIP_TRY(g->d_gid.ensure(sizeof(int32_t) * (size_t)std::max(n, 1)));
+        HIP_TRY(hipMemcpyAsync(ws.gmeta.p, voff.data(), sizeof(int32_t) * ((size_t)G + 1), hipMemcpyHostToDevice, s));
+        HIP_TRY(launch_fill_gid(ws.gmeta.as<int32_t>(), G, n, g->d_gid.as<int32_t>(), s));
+    }
+    const int32_t* gid = G > 1 ? g->d_gid.as<int32_t>() : nullptr;
+    LV_TRY(graph_entry_offsets(g, g->off.as<int32_t>(), voff, g->eoff));
     // loops: A_vv = 2 w (weighted degree counts a loop twice)
     HIP_TRY(ws.minv.ensure(sizeof(int32_t) * (size_t)std::max(n, 1)));
     int32_t* diag = ws.minv.as<int32_t>();
@@ -702,36 +1146,70 @@ static lv_status graph_setup(lv_graph* g, int32_t n, const int32_t* offsets, con
     HIP_TRY(hipStreamSynchronize(s));
     g->weighted = weights != nullptr || any != 0;
     HIP_TRY(g->k.ensure(sizeof(int32_t) * (size_t)std::max(n, 1)));
-    int64_t* d_tot = (int64_t*)(ws.small.as<char>() + 64);
-    HIP_TRY(hipMemsetAsync(d_tot, 0, 3 * sizeof(int64_t), s));
     if (g->weighted) {
+        int64_t* d_tot = (int64_t*)(ws.small.as<char>() + 64);
+        HIP_TRY(hipMemsetAsync(d_tot, 0, sizeof(int64_t), s));
         HIP_TRY(launch_adjacency_weights(n, w_in, diag, nnz, g->w.as<int32_t>(), d_err, s));
         HIP_TRY(ws.k64.ensure(sizeof(int64_t) * (size_t)std::max(n, 1)));
         HIP_TRY(launch_row_sums(n, g->off.as<int32_t>(), g->w.as<int32_t>(), nnz, g->k.as<int32_t>(),
                                 ws.k64.as<int64_t>(), d_tot, s));
+        HIP_TRY(hipStreamSynchronize(s));
         ws.k64.release();
     } else {
         g->w.release();
         HIP_TRY(launch_degree_unit(n, g->off.as<int32_t>(), g->k.as<int32_t>(), s));
-        if (nnz > 0) {
-            int64_t t = nnz;
-            HIP_TRY(hipMemcpyAsync(d_tot, &t, sizeof t, hipMemcpyHostToDevice, s));
+    }
+    // per-graph M, trace and sum of squared degrees
+    HIP_TRY(ws.gsum.ensure(sizeof(int64_t) * (size_t)G));
+    HIP_TRY(ws.gsq.ensure(sizeof(int64_t) * (size_t)G));
+    HIP_TRY(ws.gdone.ensure(sizeof(int64_t) * (size_t)G));
+    HIP_TRY(hipMemsetAsync(ws.gsum.p, 0, sizeof(int64_t) * (size_t)G, s));
+    HIP_TRY(hipMemsetAsync(ws.gsq.p, 0, sizeof(int64_t) * (size_t)G, s));
+    HIP_TRY(hipMemsetAsync(ws.gdone.p, 0, sizeof(int64_t) * (size_t)G, s));
+    HIP_TRY(launch_seg_sum(g->k.as<int32_t>(), n, gid, ws.gsum.as<int64_t>(), s));
+    HIP_TRY(launch_sum_sq(g->k.as<int32_t>(), n, gid, ws.gsq.as<int64_t>(), s));
+    HIP_TRY(launch_trace(n, g->off.as<int32_t>(), g->idx.as<int32_t>(), g->weighted ? g->w.as<int32_t>() : nullptr, nnz,
+                         gid, ws.gdone.as<int64_t>(), s));
+    std::vector<int64_t> Ms(G), sq(G), tr(G);
+    HIP_TRY(hipMemcpyAsync(&err, d_err, sizeof err, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(Ms.data(), ws.gsum.p, sizeof(int64_t) * (size_t)G, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(sq.data(), ws.gsq.p, sizeof(int64_t) * (size_t)G, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(tr.data(), ws.gdone.p, sizeof(int64_t) * (size_t)G, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (err & 16) { set_error_msg("a loop's doubled weight exceeds 2^31 - 1"); return LV_E_OVERFLOW; }
+    g->M = Ms;
+    g->q0.resize(G);
+    for (int32_t q = 0; q < G; ++q) {
+        if (Ms[q] > (int64_t)INT32_MAX) { set_error_msg("total volume M >= 2^31 (graph " + std::to_string(q) + ")"); return LV_E_OVERFLOW; }
+        g->q0[q] = Ms[q] * tr[q] - sq[q];
+    }
+    if (G > 1) {
+        HIP_TRY(g->d_M.ensure(sizeof(int64_t) * (size_t)G));
+        HIP_TRY(hipMemcpyAsync(g->d_M.p, g->M.data(), sizeof(int64_t) * (size_t)G, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    return LV_OK;
+}
+
+static lv_status new_graph(void* stream, lv_graph** out)
+{
+    lv_graph* g = new (std::nothrow) lv_graph();
+    if (!g) return LV_E_NOMEM;
+    hipError_t e = hipGetDevice(&g->device);
+    if (e == hipSuccess) {
+        if (stream) {
+            g->stream = (hipStream_t)stream;
+        } else {
+            e = hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking);
+            g->own_stream = e == hipSuccess;
         }
     }
-    int64_t tot = 0;
-    HIP_TRY(hipMemcpyAsync(&err, d_err, sizeof err, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(&tot, d_tot, sizeof tot, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    if ((err & 16) || tot > (int64_t)INT32_MAX) { set_error_msg("total volume M >= 2^31"); return LV_E_OVERFLOW; }
-    g->M = tot;
-    int64_t* d_q = d_tot + 1;
-    HIP_TRY(launch_sum_sq_trace(n, g->off.as<int32_t>(), g->idx.as<int32_t>(), g->weighted ? g->w.as<int32_t>() : nullptr,
-                                nnz, g->k.as<int32_t>(), d_q, s));
-    int64_t q2[2];
-    HIP_TRY(hipMemcpyAsync(q2, d_q, sizeof q2, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    g->sumk2 = q2[0];
-    g->trace = q2[1];
+    if (e != hipSuccess) {
+        set_error("lv_graph_create", e);
+        delete g;
+        return from_hip(e);
+    }
+    *out = g;
     return LV_OK;
 }
 
@@ -749,23 +1227,69 @@ lv_status lv_graph_create_csr(int32_t n, const int32_t* offsets, const int32_t* 
         set_error_msg("indices is null");
         return LV_E_ARG;
     }
-    lv_graph* g = new (std::nothrow) lv_graph();
-    if (!g) return LV_E_NOMEM;
-    hipError_t e = hipGetDevice(&g->device);
-    if (e == hipSuccess) {
-        if (stream) {
-            g->stream = (hipStream_t)stream;
-        } else {
-            e = hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking);
-            g->own_stream = e == hipSuccess;
-        }
-    }
-    if (e != hipSuccess) {
-        set_error("lv_graph_create_csr", e);
+    lv_graph* g = nullptr;
+    LV_TRY(new_graph(stream, &g));
+    lv_status st = graph_setup(g, n, offsets, indices, weights, kind, flags, std::vector<int32_t>{0, n});
+    if (st != LV_OK) {
+        (void)hipStreamSynchronize(g->stream);
         delete g;
-        return from_hip(e);
+        return st;
     }
-    lv_status st = graph_setup(g, n, offsets, indices, weights, kind, flags);
+    *out = g;
+    return LV_OK;
+}
+
+lv_status lv_graph_create_batch(int32_t count, const int32_t* n, const int32_t* const* offsets,
+                                const int32_t* const* indices, const int32_t* const* weights, lv_memkind kind,
+                                uint32_t flags, void* stream, lv_graph** out)
+{
+    if (!out || count < 1 || !n || !offsets || !indices || (kind != LV_MEM_HOST && kind != LV_MEM_DEVICE)) {
+        set_error_msg("lv_graph_create_batch: count >= 1 and non-null n/offsets/indices/out required");
+        return LV_E_ARG;
+    }
+    // pack on the host: graph g's vertices and entries follow graph g-1's
+    std::vector<int32_t> voff(1, 0);
+    std::vector<std::vector<int32_t>> ho(count);
+    int64_t nv = 0, ne = 0;
+    bool any_w = false;
+    for (int32_t q = 0; q < count; ++q) {
+        if (n[q] < 0 || !offsets[q]) { set_error_msg("graph " + std::to_string(q) + ": n < 0 or null offsets"); return LV_E_ARG; }
+        ho[q].resize((size_t)n[q] + 1);
+        if (kind == LV_MEM_HOST) std::memcpy(ho[q].data(), offsets[q], sizeof(int32_t) * ho[q].size());
+        else HIP_TRY(hipMemcpy(ho[q].data(), offsets[q], sizeof(int32_t) * ho[q].size(), hipMemcpyDeviceToHost));
+        if (ho[q][0] != 0 || ho[q][n[q]] < 0) { set_error_msg("graph " + std::to_string(q) + ": bad offsets"); return LV_E_CSR; }
+        if (ho[q][n[q]] > 0 && !indices[q]) { set_error_msg("graph " + std::to_string(q) + ": null indices"); return LV_E_ARG; }
+        nv += n[q];
+        ne += ho[q][n[q]];
+        if (nv >= INT32_MAX || ne >= INT32_MAX) { set_error_msg("packed graphs exceed 2^31 vertices or entries"); return LV_E_OVERFLOW; }
+        voff.push_back((int32_t)nv);
+        any_w = any_w || (weights && weights[q]);
+    }
+    std::vector<int32_t> off((size_t)nv + 1), idx((size_t)std::max<int64_t>(ne, 1)), w;
+    if (any_w) w.assign((size_t)std::max<int64_t>(ne, 1), 1);
+    int64_t eb = 0;
+    for (int32_t q = 0; q < count; ++q) {
+        const int32_t vb = voff[q];
+        const int64_t m = ho[q][n[q]];
+        for (int32_t x = 0; x <= n[q]; ++x) off[(size_t)vb + x] = (int32_t)(ho[q][x] + eb);
+        if (m > 0) {
+            int32_t* dst = idx.data() + eb;
+            if (kind == LV_MEM_HOST) std::memcpy(dst, indices[q], sizeof(int32_t) * (size_t)m);
+            else HIP_TRY(hipMemcpy(dst, indices[q], sizeof(int32_t) * (size_t)m, hipMemcpyDeviceToHost));
+            for (int64_t t = 0; t < m; ++t) {
+                if (dst[t] < 0 || dst[t] >= n[q]) { set_error_msg("graph " + std::to_string(q) + ": index out of range"); return LV_E_CSR; }
+                dst[t] += vb;
+            }
+            if (weights && weights[q]) {
+                if (kind == LV_MEM_HOST) std::memcpy(w.data() + eb, weights[q], sizeof(int32_t) * (size_t)m);
+                else HIP_TRY(hipMemcpy(w.data() + eb, weights[q], sizeof(int32_t) * (size_t)m, hipMemcpyDeviceToHost));
+            }
+        }
+        eb += m;
+    }
+    lv_graph* g = nullptr;
+    LV_TRY(new_graph(stream, &g));
+    lv_status st = graph_setup(g, (int32_t)nv, off.data(), idx.data(), any_w ? w.data() : nullptr, LV_MEM_HOST, flags, voff);
     if (st != LV_OK) {
         (void)hipStreamSynchronize(g->stream);
         delete g;
@@ -788,86 +1312,14 @@ lv_status lv_graph_info(const lv_graph* g, int32_t* n, int64_t* nnz, int64_t* vo
     if (!g) return LV_E_ARG;
     if (n) *n = g->n;
     if (nnz) *nnz = g->nnz;
-    if (volume) *volume = g->M;
+    if (volume) *volume = g->M.empty() ? 0 : g->M[0];
     return LV_OK;
 }
 
-static lv_status louvain_impl(lv_graph* g, const Params& p, bool keep_graphs, lv_result* r)
+lv_status lv_graph_count(const lv_graph* g, int32_t* count)
 {
-    hipStream_t s = g->stream;
-    Workspace& ws = g->ws;
-    r->n0 = g->n;
-    r->M = g->M;
-    HIP_TRY(r->final_labels.ensure(sizeof(int32_t) * (size_t)std::max(g->n, 1)));
-    HIP_TRY(launch_iota(r->final_labels.as<int32_t>(), g->n, s));
-    LevelGraph G{g->n, g->nnz, g->off.as<int32_t>(), g->idx.as<int32_t>(), g->weighted ? g->w.as<int32_t>() : nullptr,
-                 g->k.as<int32_t>()};
-    int64_t q_start = g->M * g->trace - g->sumk2;
-    r->q_int = q_start;
-    int slot = 0;
-    Timer tm;
-    tm.on = (p.flags & LV_TIMING) != 0;
-    tm.s = s;
-    for (;;) {
-        auto rec = std::make_unique<LevelRecord>();
-        SweepOut so;
-        LV_TRY(run_sweeps(g, G, MODE_LOUVAIN, p, so));
-        hipEvent_t t0{}, t1{}, t2{};
-        if (tm.on) HIP_TRY(tm.mark(&t0));
-        int32_t n2 = 0;
-        LV_TRY(renumber(g, G.n, &n2));
-        if (tm.on) HIP_TRY(tm.mark(&t1));
-        Coarse co;
-        LV_TRY(aggregate(g, G, n2, slot, co));
-        if (tm.on) {
-            HIP_TRY(tm.mark(&t2));
-            HIP_TRY(hipStreamSynchronize(s));
-            rec->info.renumber_ms = elapsed(t0, t1);
-            rec->info.aggregate_ms = elapsed(t1, t2);
-            tm.used = 0;
-        }
-        lv_level_info& li = rec->info;
-        li.n = G.n;
-        li.n_next = n2;
-        li.nnz = G.nnz;
-        li.sweeps = (int32_t)so.moves.size();
-        li.q_start = q_start;
-        li.q_end = co.q_end;
-        li.accepted = co.q_end > q_start ? 1 : 0;
-        li.move_ms = so.move_ms;
-        li.sweep_ms = so.sweep_ms;
-        li.move_launches = so.launches;
-        li.move_bytes = so.bytes;
-        for (int t = 0; t < LV_KERNEL_SLOTS; ++t) {
-            li.kern_ms[t] = so.kern_ms[t];
-            li.kern_launches[t] = so.kern_launches[t];
-            li.kern_bytes[t] = so.kern_bytes[t];
-        }
-        rec->moves = so.moves;
-        const bool accepted = li.accepted != 0;
-        if (accepted) {
-            HIP_TRY(rec->labels.ensure(sizeof(int32_t) * (size_t)std::max(G.n, 1)));
-            HIP_TRY(launch_copy_i32(rec->labels.as<int32_t>(), ws.labels.as<int32_t>(), G.n, s));
-            HIP_TRY(launch_compose(g->n, r->final_labels.as<int32_t>(), ws.labels.as<int32_t>(), s));
-            if (keep_graphs) {
-                HIP_TRY(rec->g_off.ensure(sizeof(int32_t) * ((size_t)co.n2 + 1)));
-                HIP_TRY(rec->g_idx.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(co.nnz2, 1)));
-                HIP_TRY(rec->g_w.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(co.nnz2, 1)));
-                HIP_TRY(launch_copy_i32(rec->g_off.as<int32_t>(), co.off, (int64_t)co.n2 + 1, s));
-                HIP_TRY(launch_copy_i32(rec->g_idx.as<int32_t>(), co.idx, co.nnz2, s));
-                HIP_TRY(launch_copy_i32(rec->g_w.as<int32_t>(), co.w, co.nnz2, s));
-                rec->g_nnz = co.nnz2;
-            }
-            r->q_int = co.q_end;
-            ++r->accepted;
-        }
-        r->levels.push_back(std::move(rec));
-        if (!accepted || r->accepted >= p.max_levels) break;
-        G = LevelGraph{co.n2, co.nnz2, co.off, co.idx, co.w, co.k};
-        q_start = co.q_end;
-        slot ^= 1;
-    }
-    HIP_TRY(hipStreamSynchronize(s));
+    if (!g || !count) return LV_E_ARG;
+    *count = g->G;
     return LV_OK;
 }
 
@@ -889,65 +1341,113 @@ lv_status lv_louvain(lv_graph* g, const lv_params* params, lv_result** out)
     return LV_OK;
 }
 
-lv_status lv_result_num_levels(const lv_result* r, int32_t* accepted, int32_t* attempted)
+static const GraphResult* graph_of(const lv_result* r, int32_t g)
 {
-    if (!r) return LV_E_ARG;
-    if (accepted) *accepted = r->accepted;
-    if (attempted) *attempted = (int32_t)r->levels.size();
+    if (!r || g < 0 || g >= r->G) return nullptr;
+    return &r->graphs[g];
+}
+
+lv_status lv_result_graph_num_levels(const lv_result* r, int32_t g, int32_t* accepted, int32_t* attempted)
+{
+    const GraphResult* gr = graph_of(r, g);
+    if (!gr) return r ? LV_E_NOT_FOUND : LV_E_ARG;
+    if (accepted) *accepted = gr->accepted;
+    if (attempted) *attempted = (int32_t)gr->levels.size();
     return LV_OK;
 }
 
-lv_status lv_result_level_info(const lv_result* r, int32_t level, lv_level_info* out)
+lv_status lv_result_graph_level_info(const lv_result* r, int32_t g, int32_t level, lv_level_info* out)
 {
-    if (!r || !out) return LV_E_ARG;
-    if (level < 0 || level >= (int32_t)r->levels.size()) return LV_E_NOT_FOUND;
-    *out = r->levels[level]->info;
+    const GraphResult* gr = graph_of(r, g);
+    if (!gr || !out) return (!r || !out) ? LV_E_ARG : LV_E_NOT_FOUND;
+    if (level < 0 || level >= (int32_t)gr->levels.size()) return LV_E_NOT_FOUND;
+    *out = gr->levels[level].info;
     return LV_OK;
 }
 
-lv_status lv_result_level_moves(const lv_result* r, int32_t level, int64_t* moves, int32_t cap)
+lv_status lv_result_graph_level_moves(const lv_result* r, int32_t g, int32_t level, int64_t* moves, int32_t cap)
 {
+    const GraphResult* gr = graph_of(r, g);
     if (!r || (!moves && cap > 0) || cap < 0) return LV_E_ARG;
-    if (level < 0 || level >= (int32_t)r->levels.size()) return LV_E_NOT_FOUND;
-    const auto& mv = r->levels[level]->moves;
+    if (!gr || level < 0 || level >= (int32_t)gr->levels.size()) return LV_E_NOT_FOUND;
+    const auto& mv = gr->levels[level].moves;
     for (int32_t t = 0; t < cap && t < (int32_t)mv.size(); ++t) moves[t] = mv[t];
     return LV_OK;
 }
 
+lv_status lv_result_graph_level_labels(const lv_result* r, int32_t g, int32_t level, int32_t* labels, lv_memkind kind)
+{
+    const GraphResult* gr = graph_of(r, g);
+    if (!r || !labels || (kind != LV_MEM_HOST && kind != LV_MEM_DEVICE)) return LV_E_ARG;
+    if (!gr || level < 0 || level >= gr->accepted) return LV_E_NOT_FOUND;
+    const LevelRecord& rec = gr->levels[level];
+    const int32_t cnt = rec.info.n;
+    if (cnt <= 0) return LV_OK;
+    std::vector<int32_t> h((size_t)cnt);
+    HIP_TRY(hipMemcpy(h.data(), rec.store->labels.as<int32_t>() + rec.vbase, sizeof(int32_t) * (size_t)cnt,
+                      hipMemcpyDeviceToHost));
+    for (auto& x : h) x -= rec.nbase;
+    HIP_TRY(hipMemcpy(labels, h.data(), sizeof(int32_t) * (size_t)cnt,
+                      kind == LV_MEM_HOST ? hipMemcpyHostToHost : hipMemcpyHostToDevice));
+    return LV_OK;
+}
+
+lv_status lv_result_graph_final_labels(const lv_result* r, int32_t g, int32_t* labels, lv_memkind kind)
+{
+    const GraphResult* gr = graph_of(r, g);
+    if (!r || !labels || (kind != LV_MEM_HOST && kind != LV_MEM_DEVICE)) return LV_E_ARG;
+    if (!gr) return LV_E_NOT_FOUND;
+    return copy_out(labels, r->final_labels.as<int32_t>() + gr->fin_base, gr->n0, kind, nullptr);
+}
+
+lv_status lv_result_graph_modularity(const lv_result* r, int32_t g, int64_t* q_int, int64_t* m, double* q)
+{
+    const GraphResult* gr = graph_of(r, g);
+    if (!r) return LV_E_ARG;
+    if (!gr) return LV_E_NOT_FOUND;
+    if (q_int) *q_int = gr->q_int;
+    if (m) *m = gr->M;
+    if (q) *q = gr->M > 0 ? (double)gr->q_int / ((double)gr->M * (double)gr->M) : 0.0;
+    return LV_OK;
+}
+
+lv_status lv_result_num_levels(const lv_result* r, int32_t* accepted, int32_t* attempted)
+{
+    return lv_result_graph_num_levels(r, 0, accepted, attempted);
+}
+lv_status lv_result_level_info(const lv_result* r, int32_t level, lv_level_info* out)
+{
+    return lv_result_graph_level_info(r, 0, level, out);
+}
+lv_status lv_result_level_moves(const lv_result* r, int32_t level, int64_t* moves, int32_t cap)
+{
+    return lv_result_graph_level_moves(r, 0, level, moves, cap);
+}
 lv_status lv_result_level_labels(const lv_result* r, int32_t level, int32_t* labels, lv_memkind kind)
 {
-    if (!r || !labels) return LV_E_ARG;
-    if (level < 0 || level >= r->accepted) return LV_E_NOT_FOUND;
-    const LevelRecord& rec = *r->levels[level];
-    return copy_out(labels, rec.labels.as<int32_t>(), rec.info.n, kind, nullptr);
+    return lv_result_graph_level_labels(r, 0, level, labels, kind);
+}
+lv_status lv_result_final_labels(const lv_result* r, int32_t* labels, lv_memkind kind)
+{
+    return lv_result_graph_final_labels(r, 0, labels, kind);
+}
+lv_status lv_result_modularity(const lv_result* r, int64_t* q_int, int64_t* m, double* q)
+{
+    return lv_result_graph_modularity(r, 0, q_int, m, q);
 }
 
 lv_status lv_result_level_graph(const lv_result* r, int32_t level, int32_t* offsets, int32_t* indices,
                                 int32_t* weights, int64_t* nnz, lv_memkind kind)
 {
+    const GraphResult* gr = graph_of(r, 0);
     if (!r || !nnz) return LV_E_ARG;
-    if (level < 0 || level >= r->accepted) return LV_E_NOT_FOUND;
-    const LevelRecord& rec = *r->levels[level];
-    if (!rec.g_off.p) return LV_E_STATE;
+    if (!gr || level < 0 || level >= gr->accepted) return LV_E_NOT_FOUND;
+    const LevelRecord& rec = gr->levels[level];
+    if (!rec.g_off) return LV_E_STATE;
     *nnz = rec.g_nnz;
-    if (offsets) LV_TRY(copy_out(offsets, rec.g_off.as<int32_t>(), (int64_t)rec.info.n_next + 1, kind, nullptr));
-    if (indices) LV_TRY(copy_out(indices, rec.g_idx.as<int32_t>(), rec.g_nnz, kind, nullptr));
-    if (weights) LV_TRY(copy_out(weights, rec.g_w.as<int32_t>(), rec.g_nnz, kind, nullptr));
-    return LV_OK;
-}
-
-lv_status lv_result_final_labels(const lv_result* r, int32_t* labels, lv_memkind kind)
-{
-    if (!r || !labels) return LV_E_ARG;
-    return copy_out(labels, r->final_labels.as<int32_t>(), r->n0, kind, nullptr);
-}
-
-lv_status lv_result_modularity(const lv_result* r, int64_t* q_int, int64_t* m, double* q)
-{
-    if (!r) return LV_E_ARG;
-    if (q_int) *q_int = r->q_int;
-    if (m) *m = r->M;
-    if (q) *q = r->M > 0 ? (double)r->q_int / ((double)r->M * (double)r->M) : 0.0;
+    if (offsets) LV_TRY(copy_out(offsets, rec.g_off->as<int32_t>(), (int64_t)rec.info.n_next + 1, kind, nullptr));
+    if (indices) LV_TRY(copy_out(indices, rec.g_idx->as<int32_t>(), rec.g_nnz, kind, nullptr));
+    if (weights) LV_TRY(copy_out(weights, rec.g_w->as<int32_t>(), rec.g_nnz, kind, nullptr));
     return LV_OK;
 }
 
@@ -981,14 +1481,16 @@ static lv_status modularity_impl(lv_graph* g, const int32_t* labels_dev, int64_t
     HIP_TRY(hipMemcpyAsync(q2, d_q, sizeof q2, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     ws.k64.release();
-    *q_int = g->M * q2[0] - q2[1];
+    *q_int = g->M[0] * q2[0] - q2[1];
     return LV_OK;
 }
 
 lv_status lv_modularity(lv_graph* g, const int32_t* labels, lv_memkind kind, int64_t* q_int, int64_t* m, double* q)
 {
     if (!g || !labels || (kind != LV_MEM_HOST && kind != LV_MEM_DEVICE)) return LV_E_ARG;
+    if (g->G != 1) { set_error_msg("lv_modularity takes a single-graph handle"); return LV_E_STATE; }
     Workspace& ws = g->ws;
+    HIP_TRY(ws.small.ensure(4096));
     const int32_t* dl = labels;
     if (kind == LV_MEM_HOST) {
         HIP_TRY(ws.labels.ensure(sizeof(int32_t) * (size_t)std::max(g->n, 1)));
@@ -998,9 +1500,39 @@ lv_status lv_modularity(lv_graph* g, const int32_t* labels, lv_memkind kind, int
     }
     int64_t qi = 0;
     LV_TRY(modularity_impl(g, dl, &qi));
+    const int64_t M = g->M[0];
     if (q_int) *q_int = qi;
-    if (m) *m = g->M;
-    if (q) *q = g->M > 0 ? (double)qi / ((double)g->M * (double)g->M) : 0.0;
+    if (m) *m = M;
+    if (q) *q = M > 0 ? (double)qi / ((double)M * (double)M) : 0.0;
+    return LV_OK;
+}
+
+lv_status lv_lpa_batch(lv_graph* g, const lv_params* params, int32_t* labels, lv_memkind kind, int32_t* sweeps,
+                       int64_t* q_int, int64_t* m, int64_t* moves, int32_t moves_stride)
+{
+    if (!g || !labels || (kind != LV_MEM_HOST && kind != LV_MEM_DEVICE) || moves_stride < 0 ||
+        (moves && moves_stride == 0))
+        return LV_E_ARG;
+    Params p;
+    LV_TRY(read_params(params, p));
+    Workspace& ws = g->ws;
+    HIP_TRY(ws.pos.ensure(sizeof(int32_t) * ((size_t)g->n + 1)));
+    DevBuf out;
+    HIP_TRY(out.ensure(sizeof(int32_t) * (size_t)std::max(g->n, 1)));
+    SweepOut so;
+    std::vector<int32_t> voff2;
+    std::vector<int64_t> qi;
+    double ren = 0;
+    LV_TRY(lpa_impl(g, p, out.as<int32_t>(), so, voff2, qi, &ren));
+    LV_TRY(copy_out(labels, out.as<int32_t>(), g->n, kind, g->stream));
+    for (int32_t c = 0; c < g->G; ++c) {
+        if (sweeps) sweeps[c] = so.sweeps[c];
+        if (q_int) q_int[c] = qi[c];
+        if (m) m[c] = g->M[c];
+        if (moves)
+            for (int32_t t = 0; t < moves_stride; ++t)
+                moves[(size_t)c * moves_stride + t] = t < so.sweeps[c] ? (int64_t)so.moves[(size_t)c * p.max_sweeps + t] : 0;
+    }
     return LV_OK;
 }
 
@@ -1009,51 +1541,28 @@ lv_status lv_lpa(lv_graph* g, const lv_params* params, int32_t* labels, lv_memki
 {
     if (!g || !labels || (kind != LV_MEM_HOST && kind != LV_MEM_DEVICE) || moves_cap < 0 || (moves_cap > 0 && !moves_out))
         return LV_E_ARG;
+    if (g->G != 1) { set_error_msg("lv_lpa takes a single-graph handle (see lv_lpa_batch)"); return LV_E_STATE; }
     Params p;
     LV_TRY(read_params(params, p));
-    LevelGraph G{g->n, g->nnz, g->off.as<int32_t>(), g->idx.as<int32_t>(), g->weighted ? g->w.as<int32_t>() : nullptr,
-                 g->k.as<int32_t>()};
+    DevBuf out;
+    HIP_TRY(out.ensure(sizeof(int32_t) * (size_t)std::max(g->n, 1)));
     SweepOut so;
-    LV_TRY(run_sweeps(g, G, MODE_LPA, p, so));
-    int32_t n2 = 0;
-    hipEvent_t t0{}, t1{};
-    Timer tm;
-    tm.on = (p.flags & LV_TIMING) != 0;
-    tm.s = g->stream;
-    if (tm.on) HIP_TRY(tm.mark(&t0));
-    LV_TRY(renumber(g, g->n, &n2));
-    if (tm.on) HIP_TRY(tm.mark(&t1));
-    // Q_int of the final partition: M * Sigma_in - sum of the community volumes squared
-    int64_t* d_q = (int64_t*)(g->ws.small.as<char>() + 2816);
-    HIP_TRY(hipMemsetAsync(d_q, 0, 2 * sizeof(int64_t), g->stream));
-    HIP_TRY(launch_sigma_in(G.n, G.off, G.idx, G.w, G.nnz, g->ws.comm.as<int32_t>(), d_q, g->stream));
-    HIP_TRY(launch_sum_sq(g->ws.sigma.as<int32_t>(), G.n, d_q + 1, g->stream));
-    int64_t q2[2];
-    HIP_TRY(hipMemcpyAsync(g->pinned, d_q, sizeof q2, hipMemcpyDeviceToHost, g->stream));
-    HIP_TRY(hipStreamSynchronize(g->stream));
-    std::memcpy(q2, g->pinned, sizeof q2);
-    const int64_t qi = g->M * q2[0] - q2[1];
-    LV_TRY(copy_out(labels, g->ws.labels.as<int32_t>(), g->n, kind, g->stream));
-    for (int32_t t = 0; t < moves_cap && t < (int32_t)so.moves.size(); ++t) moves_out[t] = so.moves[t];
+    std::vector<int32_t> voff2;
+    std::vector<int64_t> qi;
+    double ren = 0;
+    LV_TRY(lpa_impl(g, p, out.as<int32_t>(), so, voff2, qi, &ren));
+    LV_TRY(copy_out(labels, out.as<int32_t>(), g->n, kind, g->stream));
+    for (int32_t t = 0; t < moves_cap && t < so.sweeps[0]; ++t) moves_out[t] = so.moves[t];
     if (info) {
         lv_level_info li{};
         li.n = g->n;
-        li.n_next = n2;
+        li.n_next = voff2[1];
         li.nnz = g->nnz;
-        li.sweeps = (int32_t)so.moves.size();
-        li.q_start = g->M * g->trace - g->sumk2;
-        li.q_end = qi;
+        li.q_start = g->q0[0];
+        li.q_end = qi[0];
         li.accepted = 1;
-        li.move_ms = so.move_ms;
-        li.sweep_ms = so.sweep_ms;
-        li.renumber_ms = tm.on ? elapsed(t0, t1) : 0.0;
-        li.move_launches = so.launches;
-        li.move_bytes = so.bytes;
-        for (int t = 0; t < LV_KERNEL_SLOTS; ++t) {
-            li.kern_ms[t] = so.kern_ms[t];
-            li.kern_launches[t] = so.kern_launches[t];
-            li.kern_bytes[t] = so.kern_bytes[t];
-        }
+        li.renumber_ms = ren;
+        fill_info(li, so, 0, p.max_sweeps);
         *info = li;
     }
     return LV_OK;

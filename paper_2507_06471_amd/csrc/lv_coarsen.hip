@@ -31,31 +31,43 @@ __global__ void k_label(int32_t n, const int32_t* comm, const int32_t* minv, con
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         labels[i] = pos[minv[comm[i]]];
 }
-// coarse degree of community P = its volume Sigma_tot (written by its smallest member)
+// coarse degree of community P = its volume Sigma_tot, and its graph id
+// (written by its smallest member)
 __global__ void k_coarse_degree(int32_t n, const int32_t* comm, const int32_t* flag, const int32_t* labels,
-                                const int32_t* sigma, int32_t* k2)
+                                const int32_t* sigma, const int32_t* gid, int32_t* k2, int32_t* gid2)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        if (flag[i]) k2[labels[i]] = sigma[comm[i]];
+        if (flag[i]) {
+            k2[labels[i]] = sigma[comm[i]];
+            if (gid) gid2[labels[i]] = gid[i];
+        }
 }
 
-// keys/vals per entry; sigma_in += weight of entries inside one community
+// keys/vals per entry; sigma_in[g] += weight of graph g's entries inside one community
 __global__ __launch_bounds__(TILE_BS) void k_build_keys(int32_t n, const int32_t* off, const int32_t* idx,
                                                          const int32_t* w, int64_t nnz, const int32_t* labels,
                                                          int colbits, uint64_t* keys, int32_t* vals,
-                                                         unsigned long long* sigma_in)
+                                                         const int32_t* gid, unsigned long long* sigma_in)
 {
-    __shared__ unsigned long long red[TILE_BS / WAVE];
+    int32_t g_cur = -1;
     unsigned long long s = 0;
     for_tile_entries<TILE_BS, TILE_IT>(off, n, nnz, [&](int32_t r, int64_t e) {
         const uint32_t a = (uint32_t)labels[r], b = (uint32_t)labels[idx[e]];
         const int32_t wv = w ? w[e] : 1;
         keys[e] = ((uint64_t)a << colbits) | (uint64_t)b;
         vals[e] = wv;
-        if (a == b) s += (unsigned long long)wv;
+        if (a == b) {
+            const int32_t gg = gid ? gid[r] : 0;
+            if (gg != g_cur) {
+                if (g_cur >= 0 && s) atomicAdd(&sigma_in[g_cur], s);
+                g_cur = gg;
+                s = 0;
+            }
+            s += (unsigned long long)wv;
+        }
     });
-    s = block_sum<TILE_BS>(s, red);
-    if (threadIdx.x == 0 && s) atomicAdd(sigma_in, s);
+    const bool valid = g_cur >= 0 && s != 0;
+    wave_grouped_add<unsigned long long, unsigned long long>(sigma_in, valid ? g_cur : 0, s, valid);
 }
 
 __global__ void k_segment_heads(const uint64_t* keys, int64_t n, int32_t* head)
@@ -115,13 +127,75 @@ __global__ void k_row_offsets(const uint64_t* keys2, int64_t e2, int32_t n2, int
     }
 }
 
-__global__ void k_compose(int32_t n0, int32_t* fin, const int32_t* labels)
+// Compose final labels of packed original vertices with one level's labels:
+// for a vertex of original graph g that takes part at slot c = slot[g] >= 0
+// (vertex base vbase[c], label base nbase[c] in the level's packed graph):
+// fin = labels[vbase + fin] - nbase.  gid0 null: one graph at slot 0, bases 0.
+__global__ void k_compose(int32_t n0, int32_t* fin, const int32_t* labels, const int32_t* gid0, const int32_t* slot,
+                          const int32_t* vbase, const int32_t* nbase)
 {
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n0; v += (int64_t)gridDim.x * blockDim.x)
-        fin[v] = labels[fin[v]];
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n0; v += (int64_t)gridDim.x * blockDim.x) {
+        if (!gid0) { fin[v] = labels[fin[v]]; continue; }
+        const int32_t c = slot[gid0[v]];
+        if (c < 0) continue;
+        fin[v] = labels[vbase[c] + fin[v]] - nbase[c];
+    }
+}
+
+// Copy CSR segments into one packed CSR.  Segment q takes vertices
+// [src_vb, src_vb + n) of its source CSR (their entries are contiguous and
+// only point inside the segment) to vertices [dst_vb, dst_vb + n) and
+// entries from dst_eb; indices are shifted accordingly; weights default to 1
+// and degrees are copied; gid of the new vertices = q.
+__global__ void k_repack_vertices(const RepackSeg* seg, int32_t nseg, int32_t n_out, int32_t* off, int32_t* k,
+                                  int32_t* gid, int64_t nnz_out)
+{
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n_out; u += (int64_t)gridDim.x * blockDim.x) {
+        int32_t lo = 0, hi = nseg;  // last segment with dst_vb <= u
+        while (hi - lo > 1) {
+            const int32_t mid = (lo + hi) / 2;
+            if (seg[mid].dst_vb <= u) lo = mid; else hi = mid;
+        }
+        const RepackSeg& q = seg[lo];
+        const int64_t x = u - q.dst_vb;
+        const int64_t src_e0 = q.src_off[q.src_vb];
+        off[u] = (int32_t)(q.src_off[q.src_vb + x] - src_e0 + q.dst_eb);
+        k[u] = q.src_k[q.src_vb + x];
+        if (gid) gid[u] = lo;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) off[n_out] = (int32_t)nnz_out;
+}
+__global__ void k_repack_entries(const RepackSeg* seg, int32_t nseg, int64_t nnz_out, int32_t* idx, int32_t* w)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz_out; e += (int64_t)gridDim.x * blockDim.x) {
+        int32_t lo = 0, hi = nseg;  // last segment with dst_eb <= e
+        while (hi - lo > 1) {
+            const int32_t mid = (lo + hi) / 2;
+            if (seg[mid].dst_eb <= e) lo = mid; else hi = mid;
+        }
+        const RepackSeg& q = seg[lo];
+        const int64_t se = q.src_off[q.src_vb] + (e - q.dst_eb);
+        idx[e] = q.src_idx[se] - q.src_vb + q.dst_vb;
+        w[e] = q.src_w ? q.src_w[se] : 1;
+    }
+}
+
+// out[v] = labels[v] - base[gid[v]] (labels numbered from 0 within each graph)
+__global__ void k_local_labels(int32_t n, const int32_t* labels, const int32_t* gid, const int32_t* base, int32_t* out)
+{
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        out[v] = labels[v] - (gid ? base[gid[v]] : 0);
 }
 
 }  // namespace
+
+hipError_t launch_local_labels(int32_t n, const int32_t* labels, const int32_t* gid, const int32_t* base, int32_t* out,
+                               hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    k_local_labels<<<LV_GRID(n)>>>(n, labels, gid, base, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_renumber(int32_t n, const int32_t* comm, int32_t* minv, int32_t* flag, int32_t* pos, int32_t* labels,
                            int32_t* n_out, void* tmp, size_t tb, hipStream_t s)
@@ -137,19 +211,27 @@ hipError_t launch_renumber(int32_t n, const int32_t* comm, int32_t* minv, int32_
     return hipGetLastError();
 }
 hipError_t launch_coarse_degree(int32_t n, const int32_t* comm, const int32_t* flag, const int32_t* labels,
-                                const int32_t* sigma, int32_t* k2, hipStream_t s)
+                                const int32_t* sigma, const int32_t* gid, int32_t* k2, int32_t* gid2, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    k_coarse_degree<<<LV_GRID(n)>>>(n, comm, flag, labels, sigma, k2);
+    k_coarse_degree<<<LV_GRID(n)>>>(n, comm, flag, labels, sigma, gid, k2, gid2);
     return hipGetLastError();
 }
 hipError_t launch_build_keys(int32_t n, const int32_t* off, const int32_t* idx, const int32_t* w, int64_t nnz,
-                             const int32_t* labels, int colbits, uint64_t* keys, int32_t* vals, int64_t* sigma_in,
-                             hipStream_t s)
+                             const int32_t* labels, int colbits, uint64_t* keys, int32_t* vals, const int32_t* gid,
+                             int64_t* sigma_in, hipStream_t s)
 {
     if (nnz <= 0) return hipSuccess;
-    k_build_keys<<<tiles_for(n, nnz), TILE_BS, 0, s>>>(n, off, idx, w, nnz, labels, colbits, keys, vals,
+    k_build_keys<<<tiles_for(n, nnz), TILE_BS, 0, s>>>(n, off, idx, w, nnz, labels, colbits, keys, vals, gid,
                                                         (unsigned long long*)sigma_in);
+    return hipGetLastError();
+}
+hipError_t launch_repack(const RepackSeg* seg, int32_t nseg, int32_t n_out, int64_t nnz_out, int32_t* off, int32_t* idx,
+                         int32_t* w, int32_t* k, int32_t* gid, hipStream_t s)
+{
+    if (nseg <= 0) return hipSuccess;
+    k_repack_vertices<<<LV_GRID((int64_t)n_out + 1)>>>(seg, nseg, n_out, off, k, gid, nnz_out);
+    if (nnz_out > 0) k_repack_entries<<<LV_GRID(nnz_out)>>>(seg, nseg, nnz_out, idx, w);
     return hipGetLastError();
 }
 hipError_t launch_segment_heads(const uint64_t* keys, int64_t n, int32_t* head, hipStream_t s)
@@ -171,10 +253,11 @@ hipError_t launch_row_offsets(const uint64_t* keys2, int64_t e2, int32_t n2, int
     k_row_offsets<<<LV_GRID((int64_t)n2 + 1)>>>(keys2, e2, n2, colbits, off2);
     return hipGetLastError();
 }
-hipError_t launch_compose(int32_t n0, int32_t* fin, const int32_t* labels, hipStream_t s)
+hipError_t launch_compose(int32_t n0, int32_t* fin, const int32_t* labels, const int32_t* gid0, const int32_t* slot,
+                          const int32_t* vbase, const int32_t* nbase, hipStream_t s)
 {
     if (n0 <= 0) return hipSuccess;
-    k_compose<<<LV_GRID(n0)>>>(n0, fin, labels);
+    k_compose<<<LV_GRID(n0)>>>(n0, fin, labels, gid0, slot, vbase, nbase);
     return hipGetLastError();
 }
 

@@ -118,41 +118,75 @@ __global__ void k_degree_unit(int32_t n, const int32_t* off, int32_t* k)
         k[i] = off[i + 1] - off[i];
 }
 
-// out[0] += sum v^2 over an int32 array
-__global__ __launch_bounds__(256) void k_sum_sq(int64_t n, const int32_t* v, unsigned long long* out)
+// out[g] += sum of v_i^2 (or v_i) over the vertices of graph g (gid null: one graph)
+template <bool SQUARE>
+__global__ __launch_bounds__(256) void k_sum_sq(int64_t n, const int32_t* v, const int32_t* gid,
+                                                unsigned long long* out)
 {
-    __shared__ unsigned long long red[4];
-    unsigned long long s = 0;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
-        s += (unsigned long long)((int64_t)v[i] * (int64_t)v[i]);
-    s = block_sum<256>(s, red);
-    if (threadIdx.x == 0 && s) atomicAdd(out, s);
+    for (int64_t base = (int64_t)blockIdx.x * 256; base < n; base += (int64_t)gridDim.x * 256) {
+        const int64_t i = base + threadIdx.x;
+        const bool valid = i < n;
+        const int64_t x = valid ? (int64_t)v[i] : 0;
+        const unsigned long long y = (unsigned long long)(SQUARE ? x * x : x);
+        wave_grouped_add<unsigned long long, unsigned long long>(out, valid && gid ? gid[i] : 0, y, valid);
+    }
 }
 
-// out[1] += trace (sum of diagonal entries)
+// gid[v] = graph of vertex v: the last g with voff[g] <= v
+__global__ void k_fill_gid(const int32_t* voff, int32_t G, int32_t n, int32_t* gid)
+{
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        int32_t lo = 0, hi = G;
+        while (hi - lo > 1) {
+            const int32_t mid = (lo + hi) / 2;
+            if (voff[mid] <= v) lo = mid; else hi = mid;
+        }
+        gid[v] = lo;
+    }
+}
+
+// Per-thread running sum for one graph, flushed when the graph changes and at
+// the end (one atomic per graph per wavefront in the common case).
+struct GraphAcc {
+    int32_t g = -1;
+    unsigned long long s = 0;
+    __device__ void add(unsigned long long* out, int32_t gg, unsigned long long x)
+    {
+        if (gg != g) {
+            if (g >= 0 && s) atomicAdd(&out[g], s);
+            g = gg;
+            s = 0;
+        }
+        s += x;
+    }
+    __device__ void flush(unsigned long long* out)
+    {
+        const bool valid = g >= 0 && s != 0;
+        wave_grouped_add<unsigned long long, unsigned long long>(out, valid ? g : 0, s, valid);
+    }
+};
+
+// out[g] += trace (sum of diagonal entries) of graph g
 __global__ __launch_bounds__(TILE_BS) void k_trace(int32_t n, const int32_t* off, const int32_t* idx, const int32_t* w,
-                                                    int64_t nnz, unsigned long long* out)
+                                                    int64_t nnz, const int32_t* gid, unsigned long long* out)
 {
-    __shared__ unsigned long long red[4];
-    unsigned long long s = 0;
+    GraphAcc acc;
     for_tile_entries<TILE_BS, TILE_IT>(off, n, nnz, [&](int32_t r, int64_t e) {
-        if (idx[e] == r) s += (unsigned long long)(w ? w[e] : 1);
+        if (idx[e] == r) acc.add(out, gid ? gid[r] : 0, (unsigned long long)(w ? w[e] : 1));
     });
-    s = block_sum<TILE_BS>(s, red);
-    if (threadIdx.x == 0 && s) atomicAdd(&out[1], s);
+    acc.flush(out);
 }
 
-// out[0] += Sigma_in = sum of entries whose endpoints share a label
+// out[g] += Sigma_in of graph g: entries whose endpoints share a label
 __global__ __launch_bounds__(TILE_BS) void k_sigma_in(int32_t n, const int32_t* off, const int32_t* idx, const int32_t* w,
-                                                       int64_t nnz, const int32_t* labels, unsigned long long* out)
+                                                       int64_t nnz, const int32_t* labels, const int32_t* gid,
+                                                       unsigned long long* out)
 {
-    __shared__ unsigned long long red[4];
-    unsigned long long s = 0;
+    GraphAcc acc;
     for_tile_entries<TILE_BS, TILE_IT>(off, n, nnz, [&](int32_t r, int64_t e) {
-        if (labels[idx[e]] == labels[r]) s += (unsigned long long)(w ? w[e] : 1);
+        if (labels[idx[e]] == labels[r]) acc.add(out, gid ? gid[r] : 0, (unsigned long long)(w ? w[e] : 1));
     });
-    s = block_sum<TILE_BS>(s, red);
-    if (threadIdx.x == 0 && s) atomicAdd(&out[0], s);
+    acc.flush(out);
 }
 
 // tot[label] += k_i, one atomic per distinct label of a wavefront
@@ -235,23 +269,33 @@ hipError_t launch_degree_unit(int32_t n, const int32_t* off, int32_t* k, hipStre
     k_degree_unit<<<LV_GRID(n)>>>(n, off, k);
     return hipGetLastError();
 }
-hipError_t launch_sum_sq_trace(int32_t n, const int32_t* off, const int32_t* idx, const int32_t* w, int64_t nnz,
-                               const int32_t* k, int64_t* out2, hipStream_t s)
+hipError_t launch_sum_sq(const int32_t* v, int64_t n, const int32_t* gid, int64_t* out, hipStream_t s)
 {
-    if (n > 0) k_sum_sq<<<grid_for(n, 256, 4096), 256, 0, s>>>(n, k, (unsigned long long*)out2);
-    if (nnz > 0) k_trace<<<tiles_for(n, nnz), TILE_BS, 0, s>>>(n, off, idx, w, nnz, (unsigned long long*)out2);
+    if (n > 0) k_sum_sq<true><<<grid_for(n, 256, 4096), 256, 0, s>>>(n, v, gid, (unsigned long long*)out);
     return hipGetLastError();
 }
-hipError_t launch_sum_sq(const int32_t* v, int64_t n, int64_t* out, hipStream_t s)
+hipError_t launch_seg_sum(const int32_t* v, int64_t n, const int32_t* gid, int64_t* out, hipStream_t s)
 {
-    if (n > 0) k_sum_sq<<<grid_for(n, 256, 4096), 256, 0, s>>>(n, v, (unsigned long long*)out);
+    if (n > 0) k_sum_sq<false><<<grid_for(n, 256, 4096), 256, 0, s>>>(n, v, gid, (unsigned long long*)out);
+    return hipGetLastError();
+}
+hipError_t launch_fill_gid(const int32_t* voff, int32_t G, int32_t n, int32_t* gid, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    k_fill_gid<<<LV_GRID(n)>>>(voff, G, n, gid);
+    return hipGetLastError();
+}
+hipError_t launch_trace(int32_t n, const int32_t* off, const int32_t* idx, const int32_t* w, int64_t nnz,
+                        const int32_t* gid, int64_t* out, hipStream_t s)
+{
+    if (nnz > 0) k_trace<<<tiles_for(n, nnz), TILE_BS, 0, s>>>(n, off, idx, w, nnz, gid, (unsigned long long*)out);
     return hipGetLastError();
 }
 hipError_t launch_sigma_in(int32_t n, const int32_t* off, const int32_t* idx, const int32_t* w, int64_t nnz,
-                           const int32_t* labels, int64_t* out, hipStream_t s)
+                           const int32_t* labels, const int32_t* gid, int64_t* out, hipStream_t s)
 {
     if (nnz > 0)
-        k_sigma_in<<<tiles_for(n, nnz), TILE_BS, 0, s>>>(n, off, idx, w, nnz, labels, (unsigned long long*)out);
+        k_sigma_in<<<tiles_for(n, nnz), TILE_BS, 0, s>>>(n, off, idx, w, nnz, labels, gid, (unsigned long long*)out);
     return hipGetLastError();
 }
 hipError_t launch_modularity_parts(int32_t n, const int32_t* off, const int32_t* idx, const int32_t* w, int64_t nnz,
@@ -259,7 +303,8 @@ hipError_t launch_modularity_parts(int32_t n, const int32_t* off, const int32_t*
 {
     if (n > 0) k_label_volumes<<<grid_for(n, 256, 65536), 256, 0, s>>>(n, k, labels, (unsigned long long*)tot);
     if (nnz > 0)
-        k_sigma_in<<<tiles_for(n, nnz), TILE_BS, 0, s>>>(n, off, idx, w, nnz, labels, (unsigned long long*)out2);
+        k_sigma_in<<<tiles_for(n, nnz), TILE_BS, 0, s>>>(n, off, idx, w, nnz, labels, nullptr,
+                                                         (unsigned long long*)out2);
     if (n > 0)
         k_sum_sq_u64<<<grid_for(n, 256, 4096), 256, 0, s>>>((const unsigned long long*)tot, n,
                                                             (unsigned long long*)(out2 + 1));

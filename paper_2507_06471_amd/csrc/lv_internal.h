@@ -29,6 +29,13 @@ enum MoveClass : int {
 // Largest L each class can hold (table load factor <= 1/2).
 constexpr int32_t CLS_CAP[NUM_CLS] = {0, 8, 32, 128, 512, 2048, 4096, INT32_MAX};
 
+// Device-side sweep control of one level: completed sweeps and whether every
+// graph of the level has stopped (kernels of later sweeps then exit early).
+struct SweepCtl {
+    int32_t sweep;
+    int32_t all_done;
+};
+
 // Arguments shared by every move kernel.
 struct MoveArgs {
     const int32_t* off;
@@ -38,12 +45,28 @@ struct MoveArgs {
     const int32_t* comm;    // labels of the previous sweep
     const int32_t* sigma;   // community volumes of the previous sweep, < 2^31
     const int2* cs;         // per vertex (comm[v], sigma[comm[v]]) of the previous sweep
-    int64_t M;              // total volume
+    int64_t M;              // total volume (one graph)
+    const int64_t* Mg;      // per-graph total volume when several graphs are packed (else null)
+    const int32_t* gid;     // graph of each vertex (null for one graph)
+    const int32_t* gdone;   // per graph: 1 = stopped for the rest of this level
+    const SweepCtl* ctl;    // sweep counter / early exit
     const int32_t* verts;   // vertices of this class
     int32_t nverts;
-    int32_t dir;            // DIR_DOWN / DIR_UP
     int32_t mode;           // MODE_LOUVAIN / MODE_LPA
     int32_t* dec;           // decision per listed vertex: target community or -1
+};
+
+// One segment of a packed CSR rebuild (see launch_repack).
+struct RepackSeg {
+    const int32_t* src_off;
+    const int32_t* src_idx;
+    const int32_t* src_w;   // null = unit weights
+    const int32_t* src_k;
+    int32_t src_vb;         // first source vertex
+    int32_t n;              // vertices
+    int32_t dst_vb;         // first destination vertex
+    int32_t pad;
+    int64_t dst_eb;         // first destination entry
 };
 
 // Vertices above the workgroup classes: P partitions per vertex, each a
@@ -88,6 +111,11 @@ struct HubArgs {
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 hipError_t launch_iota(int32_t* p, int32_t n, hipStream_t s);
 hipError_t launch_copy_i32(int32_t* dst, const int32_t* src, int64_t n, hipStream_t s);
+// dst[t] = src[idx[t]] (dst may alias idx)
+hipError_t launch_gather_i32(const int32_t* src, const int32_t* idx, int32_t m, int32_t* dst, hipStream_t s);
+// out[v] = labels[v] - base[gid[v]] (gid null: copy)
+hipError_t launch_local_labels(int32_t n, const int32_t* labels, const int32_t* gid, const int32_t* base, int32_t* out,
+                               hipStream_t s);
 
 // exclusive scans; `total` (device, may be null) receives the sum
 hipError_t scan_exclusive_i32(const int32_t* in, int32_t* out, int64_t n, int32_t* total, void* tmp,
@@ -118,9 +146,15 @@ hipError_t launch_adjacency_weights(int32_t n, const int32_t* w_in, const int32_
 hipError_t launch_row_sums(int32_t n, const int32_t* off, const int32_t* w, int64_t nnz, int32_t* k,
                            int64_t* k64, int64_t* total, hipStream_t s);
 hipError_t launch_degree_unit(int32_t n, const int32_t* off, int32_t* k, hipStream_t s);
-// out2[0] += sum k^2, out2[1] += trace (caller zeroes out2)
-hipError_t launch_sum_sq_trace(int32_t n, const int32_t* off, const int32_t* idx, const int32_t* w,
-                               int64_t nnz, const int32_t* k, int64_t* out2, hipStream_t s);
+// per graph g (gid null: one graph): out[g] += sum of v^2 / trace (caller zeroes out)
+hipError_t launch_sum_sq(const int32_t* v, int64_t n, const int32_t* gid, int64_t* out, hipStream_t s);
+hipError_t launch_trace(int32_t n, const int32_t* off, const int32_t* idx, const int32_t* w, int64_t nnz,
+                        const int32_t* gid, int64_t* out, hipStream_t s);
+hipError_t launch_seg_sum(const int32_t* v, int64_t n, const int32_t* gid, int64_t* out, hipStream_t s);
+hipError_t launch_fill_gid(const int32_t* voff, int32_t G, int32_t n, int32_t* gid, hipStream_t s);
+// out[g] += Sigma_in of labels within graph g
+hipError_t launch_sigma_in(int32_t n, const int32_t* off, const int32_t* idx, const int32_t* w, int64_t nnz,
+                           const int32_t* labels, const int32_t* gid, int64_t* out, hipStream_t s);
 
 // classes
 hipError_t launch_classify(int32_t n, const int32_t* off, const int32_t* bounds, uint32_t* cls,
@@ -138,34 +172,42 @@ hipError_t launch_class_entries(const int32_t* verts_sorted, const int32_t* star
 hipError_t launch_move_class(int cls, bool singleton, const MoveArgs& a, hipStream_t s);
 hipError_t launch_hub_clear(int32_t* table, int64_t slots, hipStream_t s);
 hipError_t launch_hub_sweep(bool singleton, const MoveArgs& a, const HubArgs& h, hipStream_t s);
-hipError_t launch_pairs(int32_t n, const int32_t* comm, const int32_t* sigma, int2* cs, hipStream_t s);
-// commit the decisions dec[0..m) of vertices verts[0..m); *moves += movers
-hipError_t launch_apply(const int32_t* verts, const int32_t* dec, int32_t m, const int32_t* k, int32_t* comm,
-                        int32_t* sigma, uint32_t* moves, hipStream_t s);
+hipError_t launch_pairs(int32_t n, const int32_t* comm, const int32_t* sigma, int2* cs, const SweepCtl* ctl,
+                        hipStream_t s);
+// commit the decisions dec[0..m) of vertices verts[0..m); per-graph movers into gmoves
+hipError_t launch_apply(const int32_t* verts, const int32_t* dec, int32_t m, const int32_t* k, const int32_t* gid,
+                        int32_t* comm, int32_t* sigma, const SweepCtl* ctl, uint32_t* gmoves, int32_t max_sweeps,
+                        hipStream_t s);
+// level start: sweep counter 0; gdone[g] = !gactive[g] (gactive null = all run); moves zeroed
+hipError_t launch_ctl_init(SweepCtl* ctl, int32_t G, const int32_t* gactive, int32_t* gdone, int32_t* gsweeps,
+                           uint32_t* gmoves, int32_t max_sweeps, hipStream_t s);
+hipError_t launch_sweep_end(SweepCtl* ctl, int32_t G, int32_t* gdone, int32_t* gsweeps, const uint32_t* gmoves,
+                            int32_t max_sweeps, int64_t theta, hipStream_t s);
 
 // renumber + aggregation
 hipError_t launch_renumber(int32_t n, const int32_t* comm, int32_t* minv, int32_t* flag, int32_t* pos,
                            int32_t* labels, int32_t* n_out, void* tmp, size_t tmp_bytes, hipStream_t s);
 hipError_t launch_coarse_degree(int32_t n, const int32_t* comm, const int32_t* flag, const int32_t* labels,
-                                const int32_t* sigma, int32_t* k2, hipStream_t s);
-// keys = (label(i) << colbits) | label(j); *sigma_in += weight inside communities (caller zeroes it)
+                                const int32_t* sigma, const int32_t* gid, int32_t* k2, int32_t* gid2, hipStream_t s);
+// keys = (label(i) << colbits) | label(j); sigma_in[g] += weight inside communities (caller zeroes it)
 hipError_t launch_build_keys(int32_t n, const int32_t* off, const int32_t* idx, const int32_t* w,
                              int64_t nnz, const int32_t* labels, int colbits, uint64_t* keys, int32_t* vals,
-                             int64_t* sigma_in, hipStream_t s);
+                             const int32_t* gid, int64_t* sigma_in, hipStream_t s);
+// rebuild a packed CSR (off[n_out+1], idx/w[nnz_out], k, gid) from device segment descriptors
+hipError_t launch_repack(const RepackSeg* seg, int32_t nseg, int32_t n_out, int64_t nnz_out, int32_t* off,
+                         int32_t* idx, int32_t* w, int32_t* k, int32_t* gid, hipStream_t s);
 hipError_t launch_segment_heads(const uint64_t* keys, int64_t n, int32_t* head, hipStream_t s);
 // w2 must be zeroed; writes idx2/w2/keys2 of each run of equal keys
 hipError_t launch_segment_reduce(const uint64_t* keys, const int32_t* vals, const int32_t* pos, int64_t n,
                                  int colbits, int32_t* idx2, int32_t* w2, uint64_t* keys2, hipStream_t s);
 hipError_t launch_row_offsets(const uint64_t* keys2, int64_t e2, int32_t n2, int colbits, int32_t* off2,
                               hipStream_t s);
-hipError_t launch_compose(int32_t n0, int32_t* final_labels, const int32_t* labels, hipStream_t s);
+hipError_t launch_compose(int32_t n0, int32_t* final_labels, const int32_t* labels, const int32_t* gid0,
+                          const int32_t* slot, const int32_t* vbase, const int32_t* nbase, hipStream_t s);
 hipError_t launch_modularity_parts(int32_t n, const int32_t* off, const int32_t* idx, const int32_t* w,
                                    int64_t nnz, const int32_t* k, const int32_t* labels, int64_t* tot,
                                    int64_t* out2, hipStream_t s);
-// *out += sum v^2; *out += Sigma_in of labels (caller zeroes)
-hipError_t launch_sum_sq(const int32_t* v, int64_t n, int64_t* out, hipStream_t s);
-hipError_t launch_sigma_in(int32_t n, const int32_t* off, const int32_t* idx, const int32_t* w, int64_t nnz,
-                           const int32_t* labels, int64_t* out, hipStream_t s);
+
 hipError_t launch_check_labels(const int32_t* labels, int32_t n, int32_t* err, hipStream_t s);
 
 }  // namespace lv

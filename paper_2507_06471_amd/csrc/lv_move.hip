@@ -93,16 +93,28 @@ __global__ void k_gather_rows(const int32_t* verts, int32_t m, const int32_t* of
 
 constexpr int UNROLL = 4;
 
+// Sweep direction from the device-side sweep counter: sweeps 1, 3, ... move
+// down, sweeps 2, 4, ... up.
+__device__ __forceinline__ int sweep_dir(const SweepCtl* c) { return (c->sweep % 2 == 0) ? DIR_DOWN : DIR_UP; }
+
+// Total volume of the graph vertex i belongs to (graphs packed in one CSR
+// each keep their own M), and whether that graph has stopped this level.
+__device__ __forceinline__ int64_t vertex_M(const MoveArgs& a, int32_t i) { return a.Mg ? a.Mg[a.gid[i]] : a.M; }
+__device__ __forceinline__ bool vertex_frozen(const MoveArgs& a, int32_t i)
+{
+    return a.gdone && a.gdone[a.gid ? a.gid[i] : 0];
+}
+
 // Decision of vertex-list slot `pos`: the best community if it beats staying
 // and lies in the sweep's direction, else -1.
 __device__ __forceinline__ void decide_store(const MoveArgs& a, int64_t pos, int32_t A, int32_t sA, int64_t ki,
-                                             int64_t best_s, int32_t best_c, int32_t w_own)
+                                             int64_t M, int64_t best_s, int32_t best_c, int32_t w_own)
 {
     bool mover = false;
     if (best_c != INT32_MAX) {
         const bool louvain = a.mode == MODE_LOUVAIN;
-        const int64_t stay = louvain ? a.M * w_own - ki * ((int64_t)sA - ki) : (int64_t)w_own;
-        const bool dir_ok = a.dir == DIR_DOWN ? best_c < A : best_c > A;
+        const int64_t stay = louvain ? M * w_own - ki * ((int64_t)sA - ki) : (int64_t)w_own;
+        const bool dir_ok = sweep_dir(a.ctl) == DIR_DOWN ? best_c < A : best_c > A;
         mover = best_s > stay && dir_ok;
     }
     a.dec[pos] = mover ? best_c : -1;
@@ -110,8 +122,8 @@ __device__ __forceinline__ void decide_store(const MoveArgs& a, int64_t pos, int
 
 // Score every entry of [e_beg, e_end) as its own community (first sweep of a level).
 template <int STRIDE>
-__device__ __forceinline__ void score_entries_singleton(const MoveArgs& a, int32_t i, int64_t ki, int32_t e_beg,
-                                                        int32_t e_end, int64_t& best_s, int32_t& best_c)
+__device__ __forceinline__ void score_entries_singleton(const MoveArgs& a, int32_t i, int64_t ki, int64_t M,
+                                                        int32_t e_beg, int32_t e_end, int64_t& best_s, int32_t& best_c)
 {
     const bool louvain = a.mode == MODE_LOUVAIN;
     for (int32_t e0 = e_beg; e0 < e_end; e0 += STRIDE * UNROLL) {
@@ -128,7 +140,7 @@ __device__ __forceinline__ void score_entries_singleton(const MoveArgs& a, int32
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
             if (jj[u] == i) continue;
-            const int64_t s = louvain ? a.M * ww[u] - ki * (int64_t)sg[u] : (int64_t)ww[u];
+            const int64_t s = louvain ? M * ww[u] - ki * (int64_t)sg[u] : (int64_t)ww[u];
             if (better(s, jj[u], best_s, best_c)) { best_s = s; best_c = jj[u]; }
         }
     }
@@ -214,7 +226,7 @@ __device__ __forceinline__ bool aggregate_entries(const MoveArgs& a, int32_t i, 
 template <int STRIDE, bool SIG>
 __device__ __forceinline__ void scan_table(const MoveArgs& a, const int32_t* key, const int32_t* val,
                                            const int32_t* sig, uint32_t t0, uint32_t T, int32_t A, int64_t ki,
-                                           int64_t& best_s, int32_t& best_c, int32_t& w_own)
+                                           int64_t M, int64_t& best_s, int32_t& best_c, int32_t& w_own)
 {
     const bool louvain = a.mode == MODE_LOUVAIN;
     for (uint32_t t = t0; t < T; t += STRIDE) {
@@ -222,7 +234,7 @@ __device__ __forceinline__ void scan_table(const MoveArgs& a, const int32_t* key
         if (C == EMPTY_KEY) continue;
         const int32_t W = val[t];
         if (C == A) { w_own = W; continue; }
-        const int64_t s = louvain ? a.M * W - ki * (int64_t)(SIG ? sig[t] : a.sigma[C]) : (int64_t)W;
+        const int64_t s = louvain ? M * W - ki * (int64_t)(SIG ? sig[t] : a.sigma[C]) : (int64_t)W;
         if (better(s, C, best_s, best_c)) { best_s = s; best_c = C; }
     }
 }
@@ -239,19 +251,23 @@ __global__ __launch_bounds__(BS) void k_move(MoveArgs a)
     __shared__ int64_t rs[BS / WAVE];
     __shared__ int32_t rc[BS / WAVE], rw[BS / WAVE];
 
+    if (a.ctl->all_done) return;
     const int g = threadIdx.x / G, lane = threadIdx.x % G;
     const int64_t vi = (int64_t)blockIdx.x * NG + g;
     const bool has = vi < a.nverts;
-    const int32_t i = has ? a.verts[vi] : 0;
-    const int32_t beg = has ? a.off[i] : 0, end = has ? a.off[i + 1] : 0;
-    const int2 self = has ? a.cs[i] : make_int2(0, 0);
+    const int32_t i0 = has ? a.verts[vi] : 0;
+    const bool live = has && !vertex_frozen(a, i0);
+    const int32_t i = i0;
+    const int32_t beg = live ? a.off[i] : 0, end = live ? a.off[i + 1] : 0;
+    const int2 self = live ? a.cs[i] : make_int2(0, 0);
     const int32_t A = self.x;
-    const int64_t ki = has ? a.k[i] : 0;
+    const int64_t ki = live ? a.k[i] : 0;
+    const int64_t M = live ? vertex_M(a, i) : 0;
     int64_t best_s = INT64_MIN;
     int32_t best_c = INT32_MAX, w_own = 0;
 
     if constexpr (SINGLETON) {
-        score_entries_singleton<G>(a, i, ki, beg + lane, end, best_s, best_c);
+        score_entries_singleton<G>(a, i, ki, M, beg + lane, end, best_s, best_c);
     } else {
         int32_t* key = s_key + g * SLOTS;
         int32_t* val = s_val + g * SLOTS;
@@ -261,7 +277,7 @@ __global__ __launch_bounds__(BS) void k_move(MoveArgs a)
         __syncthreads();
         aggregate_entries<G, false, SIG>(a, i, beg + lane, end, key, val, sig, T - 1u, 1u, 0u);
         __syncthreads();
-        scan_table<G, SIG>(a, key, val, sig, lane, T, A, ki, best_s, best_c, w_own);
+        scan_table<G, SIG>(a, key, val, sig, lane, T, A, ki, M, best_s, best_c, w_own);
     }
 
     if constexpr (G <= WAVE) {
@@ -280,7 +296,10 @@ __global__ __launch_bounds__(BS) void k_move(MoveArgs a)
             }
         }
     }
-    if (has && lane == 0) decide_store(a, vi, A, self.y, ki, best_s, best_c, w_own);
+    if (has && lane == 0) {
+        if (live) decide_store(a, vi, A, self.y, ki, M, best_s, best_c, w_own);
+        else a.dec[vi] = -1;
+    }
 }
 
 template <int BS, int G, int SLOTS, bool SIG>
@@ -317,20 +336,26 @@ __global__ __launch_bounds__(PBS) void k_hub_part(MoveArgs a, HubArgs h)
     __shared__ int64_t rs[PBS / WAVE];
     __shared__ int32_t rc[PBS / WAVE], rw[PBS / WAVE];
     __shared__ int32_t s_over;
+    if (a.ctl->all_done) return;
     const int32_t b = xcd_logical((int32_t)blockIdx.x, h.nblk);
     const int32_t hh = h.blk_hub[b];
     const uint32_t part = (uint32_t)h.blk_part[b], P = (uint32_t)h.hub_parts[hh];
     const int32_t i = h.hub_vert[hh];
+    if (vertex_frozen(a, i)) {
+        if (threadIdx.x == 0) { h.part_score[b] = INT64_MIN; h.part_comm[b] = INT32_MAX; h.part_wown[b] = 0; h.part_flag[b] = 0; }
+        return;
+    }
     const int32_t beg = a.off[i], end = a.off[i + 1];
     const int32_t A = a.cs[i].x;
     const int64_t ki = a.k[i];
+    const int64_t M = vertex_M(a, i);
     int64_t best_s = INT64_MIN;
     int32_t best_c = INT32_MAX, w_own = 0;
     int32_t over = 0;
     if constexpr (SINGLETON) {
         const int64_t L = end - beg;
         const int32_t cb = beg + (int32_t)(L * part / P), ce = beg + (int32_t)(L * (part + 1) / P);
-        score_entries_singleton<PBS>(a, i, ki, cb + (int32_t)threadIdx.x, ce, best_s, best_c);
+        score_entries_singleton<PBS>(a, i, ki, M, cb + (int32_t)threadIdx.x, ce, best_s, best_c);
     } else {
         const uint32_t T = h.part_mask + 1u;
         for (uint32_t t = threadIdx.x; t < T; t += PBS) { s_key[t] = EMPTY_KEY; s_val[t] = 0; }
@@ -342,7 +367,7 @@ __global__ __launch_bounds__(PBS) void k_hub_part(MoveArgs a, HubArgs h)
             s_over = 1;
         __syncthreads();
         over = s_over;
-        if (!over) scan_table<PBS, SIG>(a, s_key, s_val, s_sig, threadIdx.x, T, A, ki, best_s, best_c, w_own);
+        if (!over) scan_table<PBS, SIG>(a, s_key, s_val, s_sig, threadIdx.x, T, A, ki, M, best_s, best_c, w_own);
     }
     block_reduce_best<PBS>(best_s, best_c, w_own, rs, rc, rw);
     if (threadIdx.x == 0) {
@@ -356,6 +381,7 @@ __global__ __launch_bounds__(PBS) void k_hub_part(MoveArgs a, HubArgs h)
 // One wavefront per hub: merge the partitions' partial results, decide.
 __global__ __launch_bounds__(256) void k_hub_finalize(MoveArgs a, HubArgs h)
 {
+    if (a.ctl->all_done) return;
     const int64_t hh64 = (int64_t)blockIdx.x * (256 / WAVE) + threadIdx.x / WAVE;
     const bool has = hh64 < h.nhubs;
     const int32_t hh = has ? (int32_t)hh64 : 0;
@@ -377,13 +403,14 @@ __global__ __launch_bounds__(256) void k_hub_finalize(MoveArgs a, HubArgs h)
     group_reduce<WAVE>(best_s, best_c, w_own);
     const bool overflowed = __ballot(flag != 0) != 0;
     if (has && overflowed && lane_id() == 0) h.fb_flag[hh] = 1;
-    if (has && !overflowed && lane_id() == 0) decide_store(a, hh, A, sA, ki, best_s, best_c, w_own);
+    if (has && !overflowed && lane_id() == 0) decide_store(a, hh, A, sA, ki, vertex_M(a, i), best_s, best_c, w_own);
 }
 
 // Pre-gather the (community, volume) pairs of the entries of vertices with
 // P > 1 partitions (one workgroup per chunk of a vertex's entries).
 __global__ __launch_bounds__(256) void k_hub_pairs(MoveArgs a, HubArgs h)
 {
+    if (a.ctl->all_done) return;
     const int b = blockIdx.x;
     const int32_t hh = h.ins_hub[b];
     const int32_t i = h.hub_vert[hh];
@@ -400,6 +427,7 @@ constexpr int FBS = 256;
 
 __global__ __launch_bounds__(FBS) void k_fb_insert(MoveArgs a, HubArgs h)
 {
+    if (a.ctl->all_done) return;
     const int b = blockIdx.x;
     const int32_t hh = h.ins_hub[b];
     if (!h.fb_flag[hh]) return;
@@ -424,6 +452,7 @@ __global__ __launch_bounds__(FBS) void k_fb_scan(MoveArgs a, HubArgs h)
 {
     __shared__ int64_t rs[FBS / WAVE];
     __shared__ int32_t rc[FBS / WAVE], rw[FBS / WAVE];
+    if (a.ctl->all_done) return;
     const int b = blockIdx.x;
     const int32_t hh = h.scan_hub[b];
     if (!h.fb_flag[hh]) return;
@@ -441,7 +470,7 @@ __global__ __launch_bounds__(FBS) void k_fb_scan(MoveArgs a, HubArgs h)
         tab[2 * t] = EMPTY_KEY;
         tab[2 * t + 1] = 0;
         if (C == A) { w_own = W; continue; }
-        const int64_t s = louvain ? a.M * W - ki * (int64_t)a.sigma[C] : (int64_t)W;
+        const int64_t s = louvain ? vertex_M(a, i) * W - ki * (int64_t)a.sigma[C] : (int64_t)W;
         if (better(s, C, best_s, best_c)) { best_s = s; best_c = C; }
     }
     block_reduce_best<FBS>(best_s, best_c, w_own, rs, rc, rw);
@@ -450,6 +479,7 @@ __global__ __launch_bounds__(FBS) void k_fb_scan(MoveArgs a, HubArgs h)
 
 __global__ __launch_bounds__(256) void k_fb_finalize(MoveArgs a, HubArgs h)
 {
+    if (a.ctl->all_done) return;
     const int64_t hh64 = (int64_t)blockIdx.x * (256 / WAVE) + threadIdx.x / WAVE;
     const bool has = hh64 < h.nhubs && h.fb_flag[hh64];
     const int32_t hh = has ? (int32_t)hh64 : 0;
@@ -469,7 +499,7 @@ __global__ __launch_bounds__(256) void k_fb_finalize(MoveArgs a, HubArgs h)
     }
     group_reduce<WAVE>(best_s, best_c, w_own);
     if (has && lane_id() == 0) {
-        decide_store(a, hh, A, sA, ki, best_s, best_c, w_own);
+        decide_store(a, hh, A, sA, ki, vertex_M(a, i), best_s, best_c, w_own);
         h.fb_flag[hh] = 0;
     }
 }
@@ -477,36 +507,73 @@ __global__ __launch_bounds__(256) void k_fb_finalize(MoveArgs a, HubArgs h)
 // ------------------------------------------------------------------ commit (K7)
 // Apply the decisions of the m listed vertices: labels, and community volumes
 // with one atomic per distinct community per wavefront (integer sums, so the
-// order is irrelevant); *moves += number of movers.
+// order is irrelevant).  The movers of graph g in this sweep are counted in
+// gmoves[g * max_sweeps + sweep].
 __global__ __launch_bounds__(256) void k_apply(const int32_t* verts, const int32_t* dec, int32_t m, const int32_t* k,
-                                               int32_t* comm, int32_t* sigma, uint32_t* moves)
+                                               const int32_t* gid, int32_t* comm, int32_t* sigma, const SweepCtl* ctl,
+                                               uint32_t* gmoves, int32_t max_sweeps)
 {
-    __shared__ uint32_t red[4];
-    uint32_t cnt = 0;
+    if (ctl->all_done) return;
+    uint32_t* moves = gmoves + ctl->sweep;
     for (int64_t base = (int64_t)blockIdx.x * 256; base < m; base += (int64_t)gridDim.x * 256) {
         const int64_t t = base + threadIdx.x;
         const int32_t C = t < m ? dec[t] : -1;
         const bool valid = C >= 0;
-        int32_t A = 0, kv = 0;
+        int32_t A = 0, kv = 0, gv = 0;
         if (valid) {
             const int32_t v = verts[t];
             A = comm[v];
             kv = k[v];
+            gv = gid ? gid[v] : 0;
             comm[v] = C;
-            ++cnt;
         }
         if (__ballot(valid)) {
             wave_grouped_add<int32_t, int32_t>(sigma, C, kv, valid);
             wave_grouped_add<int32_t, int32_t>(sigma, A, -kv, valid);
+            wave_grouped_add<uint32_t, uint32_t>(moves, (int64_t)gv * max_sweeps, 1u, valid);
         }
     }
-    cnt = block_sum<256>(cnt, red);
-    if (threadIdx.x == 0 && cnt) atomicAdd(moves, cnt);
+}
+
+// After sweep s (1-based): a running graph stops when s >= 2 and its last two
+// sweeps moved at most theta vertices each, or when s == max_sweeps.  Sets
+// all_done when no graph runs any more, so later sweeps' kernels exit early.
+__global__ __launch_bounds__(256) void k_sweep_end(SweepCtl* ctl, int32_t G, int32_t* gdone, int32_t* gsweeps,
+                                                   const uint32_t* gmoves, int32_t max_sweeps, int64_t theta)
+{
+    __shared__ int32_t red[4];
+    if (ctl->all_done) return;
+    const int32_t s = ctl->sweep + 1;
+    int32_t running = 0;
+    for (int32_t g = threadIdx.x; g < G; g += 256) {
+        if (gdone[g]) continue;
+        const uint32_t* mv = gmoves + (int64_t)g * max_sweeps;
+        const bool stop = (s >= 2 && (int64_t)mv[s - 1] <= theta && (int64_t)mv[s - 2] <= theta) || s >= max_sweeps;
+        if (stop) { gdone[g] = 1; gsweeps[g] = s; } else ++running;
+    }
+    running = block_sum<256>(running, red);
+    if (threadIdx.x == 0) {
+        ctl->sweep = s;
+        ctl->all_done = running == 0 ? 1 : 0;
+    }
+}
+
+__global__ void k_ctl_init(SweepCtl* ctl, int32_t G, const int32_t* gactive, int32_t* gdone, int32_t* gsweeps,
+                           uint32_t* gmoves, int32_t max_sweeps)
+{
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = t0; t < (int64_t)G * max_sweeps; t += stride) gmoves[t] = 0;
+    for (int64_t g = t0; g < G; g += stride) {
+        gdone[g] = gactive && !gactive[g] ? 1 : 0;
+        gsweeps[g] = 0;
+    }
+    if (t0 == 0) { ctl->sweep = 0; ctl->all_done = 0; }
 }
 
 // cs[v] = (comm[v], Sigma_tot(comm[v])): the pair a move kernel gathers per CSR entry
-__global__ void k_pairs(int32_t n, const int32_t* comm, const int32_t* sigma, int2* cs)
+__global__ void k_pairs(int32_t n, const int32_t* comm, const int32_t* sigma, int2* cs, const SweepCtl* ctl)
 {
+    if (ctl && ctl->all_done) return;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
         const int32_t c = comm[v];
         cs[v] = make_int2(c, sigma[c]);
@@ -515,10 +582,24 @@ __global__ void k_pairs(int32_t n, const int32_t* comm, const int32_t* sigma, in
 
 }  // namespace
 
-hipError_t launch_pairs(int32_t n, const int32_t* comm, const int32_t* sigma, int2* cs, hipStream_t s)
+hipError_t launch_pairs(int32_t n, const int32_t* comm, const int32_t* sigma, int2* cs, const SweepCtl* ctl,
+                        hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    k_pairs<<<LV_GRID(n)>>>(n, comm, sigma, cs);
+    k_pairs<<<LV_GRID(n)>>>(n, comm, sigma, cs, ctl);
+    return hipGetLastError();
+}
+hipError_t launch_ctl_init(SweepCtl* ctl, int32_t G, const int32_t* gactive, int32_t* gdone, int32_t* gsweeps,
+                           uint32_t* gmoves, int32_t max_sweeps, hipStream_t s)
+{
+    k_ctl_init<<<grid_for((int64_t)G * max_sweeps + 1, 256, 4096), 256, 0, s>>>(ctl, G, gactive, gdone, gsweeps,
+                                                                             gmoves, max_sweeps);
+    return hipGetLastError();
+}
+hipError_t launch_sweep_end(SweepCtl* ctl, int32_t G, int32_t* gdone, int32_t* gsweeps, const uint32_t* gmoves,
+                            int32_t max_sweeps, int64_t theta, hipStream_t s)
+{
+    k_sweep_end<<<1, 256, 0, s>>>(ctl, G, gdone, gsweeps, gmoves, max_sweeps, theta);
     return hipGetLastError();
 }
 
@@ -604,11 +685,12 @@ hipError_t launch_hub_sweep(bool singleton, const MoveArgs& a, const HubArgs& h,
     return hipGetLastError();
 }
 
-hipError_t launch_apply(const int32_t* verts, const int32_t* dec, int32_t m, const int32_t* k, int32_t* comm,
-                        int32_t* sigma, uint32_t* moves, hipStream_t s)
+hipError_t launch_apply(const int32_t* verts, const int32_t* dec, int32_t m, const int32_t* k, const int32_t* gid,
+                        int32_t* comm, int32_t* sigma, const SweepCtl* ctl, uint32_t* gmoves, int32_t max_sweeps,
+                        hipStream_t s)
 {
     if (m <= 0) return hipSuccess;
-    k_apply<<<grid_for(m, 256, 2048), 256, 0, s>>>(verts, dec, m, k, comm, sigma, moves);
+    k_apply<<<grid_for(m, 256, 2048), 256, 0, s>>>(verts, dec, m, k, gid, comm, sigma, ctl, gmoves, max_sweeps);
     return hipGetLastError();
 }
 

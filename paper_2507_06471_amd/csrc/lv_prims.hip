@@ -208,7 +208,22 @@ hipError_t radix_sort_t(K* keys, int32_t* vals, K* keys_alt, int32_t* vals_alt, 
     return hipGetLastError();
 }
 
+__global__ void k_gather_i32(const int32_t* src, const int32_t* idx, int32_t m, int32_t* dst)
+{
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < m; t += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t v = src[idx[t]];
+        dst[t] = v;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_gather_i32(const int32_t* src, const int32_t* idx, int32_t m, int32_t* dst, hipStream_t s)
+{
+    if (m <= 0) return hipSuccess;
+    k_gather_i32<<<LV_GRID(m)>>>(src, idx, m, dst);
+    return hipGetLastError();
+}
 
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s)
 {
