@@ -46,6 +46,8 @@ def main():
     ap.add_argument("--cpu-sweeps", type=int, default=2, help="oracle sweeps timed for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="run one plain device copy of this many MiB before the steps (PMC calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported by this build",
@@ -66,6 +68,16 @@ def main():
     t = time.time()
     dg = lvp.Graph.from_csr(g, validate=True)
     log(f"graph resident on the device in {time.time() - t:.1f}s (volume M={dg.volume})")
+
+    if args.copy_probe_mib > 0:
+        # a plain copy kernel of known size: reads and writes copy_probe_mib MiB
+        src = torch.ones(args.copy_probe_mib << 18, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: {args.copy_probe_mib} MiB read + {args.copy_probe_mib} MiB written")
+        del src, dst
 
     def step(timing=True):
         r = lvp.louvain(dg, timing=timing)

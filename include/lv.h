@@ -90,11 +90,13 @@ typedef struct lv_tuning {
     int32_t part_keys;  /* expected communities per partition workgroup (clamped to       */
                         /* [32, 3/4 of part_slots])                                       */
     int32_t part_slots; /* LDS table slots of a partition workgroup, power of two,       */
-                        /* 64..16384 (mode 1) or 64..8192 (mode 2); a partition whose     */
+                        /* 64..16384 (mode 1) or 64..2048 (mode 2); a partition whose     */
                         /* communities do not fit is redone with a global-memory table    */
-    int32_t hub_mode;   /* partition workgroups: 0/1 = compact tables re-reading the     */
-                        /* vertex's entries; 2 = tables with community volumes fed from  */
-                        /* the vertex's pairs gathered once into a buffer                 */
+    int32_t hub_mode;   /* partition workgroups: 1 = compact tables, each workgroup       */
+                        /* re-reading the vertex's entries; 0/2 = one scatter pass sums   */
+                        /* the entries per community within chunks and appends them to    */
+                        /* per-partition buckets that the partition workgroups read       */
+    int32_t hub_chunk;  /* mode 2: entries per scatter workgroup, 1024, 2048 or 4096      */
 } lv_tuning;
 
 typedef struct lv_params {

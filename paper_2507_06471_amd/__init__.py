@@ -45,7 +45,8 @@ _vp = ctypes.c_void_p
 class lv_tuning(ctypes.Structure):
     _fields_ = [("sub_max", ctypes.c_int32), ("wave_max", ctypes.c_int32),
                 ("block_max", ctypes.c_int32), ("part_keys", ctypes.c_int32),
-                ("part_slots", ctypes.c_int32), ("hub_mode", ctypes.c_int32)]
+                ("part_slots", ctypes.c_int32), ("hub_mode", ctypes.c_int32),
+                ("hub_chunk", ctypes.c_int32)]
 
 
 class lv_params(ctypes.Structure):

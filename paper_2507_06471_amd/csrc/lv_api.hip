@@ -97,7 +97,7 @@ struct Workspace {
     DevBuf comm, sigma, dec, cls, vert, cls_alt, vert_alt, minv, flag, pos, labels, tmp, small, cs;
     DevBuf keys, keys_alt, vals, vals_alt, head;
     DevBuf g_off[2], g_idx[2], g_w[2], g_k[2], g_gid[2];
-    DevBuf hub_table, hub_meta, hub_part, hub_rows, hub_pairs;
+    DevBuf hub_table, hub_meta, hub_part, hub_rows, hub_cnt, hub_bucket, hub_bucket_w;
     DevBuf k64;
     // per-graph state of a level (G entries) and sweep control
     DevBuf ctl, gdone, gsweeps, gmoves, gactive, gsum, gsq, gmeta, segs;
@@ -211,18 +211,21 @@ struct Tune {
     int32_t bounds[NUM_CLS];
     int32_t part_keys;  // expected distinct communities per partition workgroup
     int32_t part_slots; // LDS slots of a partition workgroup (power of two)
-    int32_t pregather;  // partition mode (see lv_tuning.hub_mode)
+    int32_t bucketed;   // partition mode (see lv_tuning.hub_mode)
     int32_t fb_chunk;   // entries / slots per workgroup on the global-table fallback
+    int32_t sc_chunk;   // entries per scatter workgroup (bucketed mode)
 };
 
 Tune make_tune(const lv_tuning* t)
 {
     Tune u;
     for (int c = 0; c < NUM_CLS; ++c) u.bounds[c] = CLS_CAP[c];
-    u.part_keys = 8192;
-    u.part_slots = 16384;
-    u.pregather = 0;
+    // default partition mode: bucketed, 768 expected communities per 2048-slot table
+    u.part_keys = 768;
+    u.part_slots = 2048;
+    u.bucketed = 1;
     u.fb_chunk = 4096;
+    u.sc_chunk = 1024;
     if (t) {
         // sub_max bounds the 8- and 32-lane classes, wave_max the wavefront
         // class, block_max the workgroup classes; each is clamped to what the
@@ -237,15 +240,16 @@ Tune make_tune(const lv_tuning* t)
             u.bounds[CLS_B512] = std::min(CLS_CAP[CLS_B512], std::max(u.bounds[CLS_B256], t->block_max));
             u.bounds[CLS_B4K] = std::min(CLS_CAP[CLS_B4K], std::max(u.bounds[CLS_B512], t->block_max));
         }
-        if (t->hub_mode == 2) {
-            u.pregather = 1;
-            u.part_slots = 8192;
-            u.part_keys = 6144;
+        if (t->hub_mode == 1) {
+            u.bucketed = 0;
+            u.part_slots = 16384;
+            u.part_keys = 8192;
         }
-        const uint64_t max_slots = u.pregather ? 8192 : 16384;
+        const uint64_t max_slots = u.bucketed ? 2048 : 16384;
         if (t->part_slots > 0)
             u.part_slots = (int32_t)std::min<uint64_t>(max_slots, std::max<uint64_t>(64, next_pow2((uint64_t)t->part_slots)));
         if (t->part_keys > 0) u.part_keys = std::max(32, t->part_keys);
+        if (t->hub_chunk > 0) u.sc_chunk = t->hub_chunk <= 1024 ? 1024 : t->hub_chunk <= 2048 ? 2048 : 4096;
     }
     // a single partition must always fit: part_keys <= 3/4 of the slots
     u.part_keys = std::min(u.part_keys, u.part_slots / 4 * 3);
@@ -313,9 +317,10 @@ struct HubPlan {
     HubArgs args{};
 };
 
-lv_status plan_hubs(lv_graph* g, const LevelGraph& G, const int32_t* hub_verts, int32_t nhubs, const Tune& tu,
+lv_status plan_hubs(lv_graph* g, const LevelGraph& G, const int32_t* hub_verts, int32_t nhubs, const Tune& tu_in,
                     HubPlan& plan)
 {
+    Tune tu = tu_in;
     Workspace& ws = g->ws;
     hipStream_t s = g->stream;
     plan.nhubs = nhubs;
@@ -330,22 +335,36 @@ lv_status plan_hubs(lv_graph* g, const LevelGraph& G, const int32_t* hub_verts, 
     HIP_TRY(hipMemcpyAsync(len.data(), d_len, sizeof(int32_t) * nhubs, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(hv.data(), hub_verts, sizeof(int32_t) * nhubs, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    if (tu.bucketed) {
+        // the scatter pass histograms at most HUB_PMAX partitions of a vertex:
+        // a level with a longer row uses the compact mode instead
+        const int32_t maxL = *std::max_element(len.begin(), len.end());
+        if (((int64_t)maxL + tu.part_keys - 1) / tu.part_keys > HUB_PMAX) {
+            tu.bucketed = 0;
+            tu.part_slots = 16384;
+            tu.part_keys = 8192;
+        }
+    }
     std::vector<int32_t> parts(nhubs), first_blk(nhubs + 1), blk_hub, blk_part;
-    std::vector<int64_t> tab_off(nhubs), pair_off(nhubs);
-    int64_t npairs = 0;
+    std::vector<int64_t> tab_off(nhubs);
     std::vector<int32_t> tab_cap(nhubs), ins_hub, ins_beg, ins_end, scan_hub, scan_beg, scan_end, fpart_first(nhubs + 1);
+    std::vector<int32_t> sc_hub, sc_beg, sc_end;
     int64_t slots = 0;
     for (int32_t h = 0; h < nhubs; ++h) {
-        const int32_t P = (int32_t)std::max<int64_t>(1, ((int64_t)len[h] + tu.part_keys - 1) / tu.part_keys);
-        parts[h] = P;
+        const int64_t P = std::max<int64_t>(1, ((int64_t)len[h] + tu.part_keys - 1) / tu.part_keys);
+        parts[h] = (int32_t)P;
         first_blk[h] = (int32_t)blk_hub.size();
         for (int32_t q = 0; q < P; ++q) { blk_hub.push_back(h); blk_part.push_back(q); }
         fpart_first[h] = (int32_t)scan_hub.size();
         tab_off[h] = slots;
         tab_cap[h] = 0;
-        pair_off[h] = npairs;
         if (P == 1) continue;  // one partition of <= part_keys keys always fits its LDS table
-        if (tu.pregather) npairs += len[h];
+        if (tu.bucketed)
+            for (int64_t e = beg[h]; e < (int64_t)beg[h] + len[h]; e += tu.sc_chunk) {
+                sc_hub.push_back(h);
+                sc_beg.push_back((int32_t)e);
+                sc_end.push_back((int32_t)std::min<int64_t>(e + tu.sc_chunk, (int64_t)beg[h] + len[h]));
+            }
         const uint64_t cap = std::max<uint64_t>(64, next_pow2(2ull * (uint64_t)len[h]));
         if (cap > (uint64_t)INT32_MAX) { set_error_msg("hub table too large"); return LV_E_OVERFLOW; }
         tab_cap[h] = (int32_t)cap;
@@ -364,6 +383,7 @@ lv_status plan_hubs(lv_graph* g, const LevelGraph& G, const int32_t* hub_verts, 
     first_blk[nhubs] = (int32_t)blk_hub.size();
     fpart_first[nhubs] = (int32_t)scan_hub.size();
     const int32_t nblk = (int32_t)blk_hub.size(), nins = (int32_t)ins_hub.size(), nscan = (int32_t)scan_hub.size();
+    const int32_t nsc = (int32_t)sc_hub.size();
     // metadata: int64 tab_off first, then the int32 arrays
     std::vector<int32_t> pack;
     auto put = [&](const std::vector<int32_t>& v) {
@@ -374,13 +394,12 @@ lv_status plan_hubs(lv_graph* g, const LevelGraph& G, const int32_t* hub_verts, 
     const size_t o_hv = put(hv), o_parts = put(parts), o_fb = put(first_blk), o_bh = put(blk_hub), o_bp = put(blk_part);
     const size_t o_cap = put(tab_cap), o_ih = put(ins_hub), o_ib = put(ins_beg), o_ie = put(ins_end);
     const size_t o_sh = put(scan_hub), o_sb = put(scan_beg), o_se = put(scan_end), o_ff = put(fpart_first);
+    const size_t o_ch = put(sc_hub), o_cb = put(sc_beg), o_ce = put(sc_end);
     const size_t b64 = sizeof(int64_t) * (size_t)nhubs;
-    HIP_TRY(ws.hub_meta.ensure(2 * b64 + sizeof(int32_t) * pack.size() + 64));
+    HIP_TRY(ws.hub_meta.ensure(b64 + sizeof(int32_t) * pack.size() + 64));
     char* base = ws.hub_meta.as<char>();
-    int32_t* p32 = (int32_t*)(base + 2 * b64);
+    int32_t* p32 = (int32_t*)(base + b64);
     HIP_TRY(hipMemcpyAsync(base, tab_off.data(), b64, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(base + b64, pair_off.data(), b64, hipMemcpyHostToDevice, s));
-    HIP_TRY(ws.hub_pairs.ensure(sizeof(int2) * (size_t)std::max<int64_t>(npairs, 1)));
     HIP_TRY(hipMemcpyAsync(p32, pack.data(), sizeof(int32_t) * pack.size(), hipMemcpyHostToDevice, s));
     // partial results + flags: [nblk] x (int64 score, int32 comm, wown, flag), [nhubs] fb_flag, [nscan] fallback partials
     const size_t part_bytes = (size_t)nblk * (8 + 4 * 3) + (size_t)nhubs * 4 + (size_t)std::max(nscan, 1) * (8 + 4 * 2);
@@ -390,7 +409,7 @@ lv_status plan_hubs(lv_graph* g, const LevelGraph& G, const int32_t* hub_verts, 
     a = HubArgs{};
     a.nhubs = nhubs;
     a.part_mask = (uint32_t)tu.part_slots - 1u;
-    a.pregather = tu.pregather;
+    a.bucketed = tu.bucketed;
     a.hub_vert = p32 + o_hv;
     a.hub_parts = p32 + o_parts;
     a.hub_first_blk = p32 + o_fb;
@@ -408,8 +427,22 @@ lv_status plan_hubs(lv_graph* g, const LevelGraph& G, const int32_t* hub_verts, 
     a.fpart_wown = a.fpart_comm + std::max(nscan, 1);
     a.fpart_first = p32 + o_ff;
     a.tab_off = (const int64_t*)base;
-    a.pair_off = (const int64_t*)(base + b64);
-    a.pairs = ws.hub_pairs.as<int2>();
+    a.sc_hub = p32 + o_ch;
+    a.sc_beg = p32 + o_cb;
+    a.sc_end = p32 + o_ce;
+    a.nsc = nsc;
+    a.sc_chunk = tu.sc_chunk;
+    a.bucket_cap = tu.part_slots;
+    if (tu.bucketed && nsc > 0) {
+        const size_t nb = (size_t)nblk * (size_t)tu.part_slots;
+        HIP_TRY(ws.hub_cnt.ensure(sizeof(int32_t) * (size_t)nblk));
+        HIP_TRY(ws.hub_bucket.ensure(sizeof(int2) * nb));
+        a.bucket_cnt = ws.hub_cnt.as<int32_t>();
+        a.bucket = ws.hub_bucket.as<int2>();
+        HIP_TRY(ws.hub_bucket_w.ensure(sizeof(int32_t) * nb));
+        a.bucket_w = ws.hub_bucket_w.as<int32_t>();
+        HIP_TRY(launch_fill_i32(a.bucket_cnt, 0, nblk, s));
+    }
     a.tab_cap = p32 + o_cap;
     a.ins_hub = p32 + o_ih;
     a.ins_beg = p32 + o_ib;
@@ -608,7 +641,7 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
         for (int c = CLS_G8; c <= CLS_HUB; ++c) {
             const int32_t nv = start[c + 1] - start[c];
             if (nv == 0) continue;
-            out.launches += c == CLS_HUB ? (sw == 1 ? 2 : 2 + (hubs.args.pregather ? 1 : 0)) : 1;
+            out.launches += c == CLS_HUB ? (sw == 1 ? 2 : 2 + (hubs.args.bucketed && hubs.args.nsc > 0 ? 1 : 0) + (hubs.args.nins > 0 ? 3 : 0)) : 1;
             if (!timing) continue;
             const int slot = 2 * c + (sw == 1 ? 1 : 0) - 2;
             out.kern_ms[slot] += elapsed(ev[sw - 1][2 * c], ev[sw - 1][2 * c + 1]);

@@ -140,19 +140,19 @@ __device__ __forceinline__ int64_t mp_rows(const int32_t* off, int32_t n, int64_
     return lo;
 }
 
-// Visit the CSR entries of this workgroup's merge-path tile with their row.
+// Visit the CSR entries of merge-path tile `tile` with their row.
 // Tile b covers merged items [b*T, (b+1)*T), T = BS*IT, so it spans at most T
 // rows (empty rows included) and its row offsets always fit in LDS.  Thread t
 // visits the tile's entries y0 + t*IT + j, j < IT, in order.  Every thread of
 // the workgroup must call it (it synchronises).
 template <int BS, int IT, typename F>
-__device__ __forceinline__ void for_tile_entries(const int32_t* off, int32_t n, int64_t nnz, F&& f)
+__device__ __forceinline__ void for_tile_entries_at(int64_t tile, const int32_t* off, int32_t n, int64_t nnz, F&& f)
 {
     constexpr int T = BS * IT;
     __shared__ int32_t s_off[T + 2];
     __shared__ int64_t s_x[2];
     const int64_t total = (int64_t)n + nnz;
-    const int64_t d0 = (int64_t)blockIdx.x * T;
+    const int64_t d0 = tile * T;
     const int64_t d1 = d0 + T < total ? d0 + T : total;
     if (threadIdx.x < 2) s_x[threadIdx.x] = mp_rows(off, n, threadIdx.x ? d1 : d0);
     __syncthreads();
@@ -178,6 +178,12 @@ __device__ __forceinline__ void for_tile_entries(const int32_t* off, int32_t n, 
     }
 }
 
+template <int BS, int IT, typename F>
+__device__ __forceinline__ void for_tile_entries(const int32_t* off, int32_t n, int64_t nnz, F&& f)
+{
+    for_tile_entries_at<BS, IT>((int64_t)blockIdx.x, off, n, nnz, f);
+}
+
 constexpr int TILE_BS = 256;
 constexpr int TILE_IT = 8;
 constexpr int64_t TILE = TILE_BS * TILE_IT;
@@ -186,6 +192,50 @@ inline unsigned tiles_for(int32_t n, int64_t nnz)
 {
     const int64_t t = ((int64_t)n + nnz + TILE - 1) / TILE;
     return (unsigned)(t > 0 ? t : 1);
+}
+
+// Block-wide flush of per-thread (graph, sum) accumulators: when every
+// pending sum of the workgroup belongs to one graph, a single atomic;
+// otherwise one atomic per distinct graph per wavefront.  All threads of the
+// workgroup must call it.
+template <int BS, typename T>
+__device__ __forceinline__ void block_flush_sums(T* out, int64_t g, T s)
+{
+    __shared__ int64_t s_key[BS / WAVE];
+    __shared__ T s_val[BS / WAVE];
+    __shared__ int32_t s_mixed;
+    const bool valid = g >= 0 && s != 0;
+    const uint64_t vm = __ballot(valid);
+    const int leader = vm ? __ffsll((unsigned long long)vm) - 1 : 0;
+    const int64_t lk = __shfl((long long)g, leader);
+    const bool uniform = __ballot(valid && g != lk) == 0;
+    T c = valid ? s : (T)0;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) c += __shfl_xor(c, d);
+    if (threadIdx.x == 0) s_mixed = 0;
+    __syncthreads();
+    if (lane_id() == 0) {
+        s_key[threadIdx.x / WAVE] = vm ? lk : -1;
+        s_val[threadIdx.x / WAVE] = c;
+        if (!uniform) s_mixed = 1;
+    }
+    __syncthreads();
+    if (s_mixed) {
+        wave_grouped_add<T, T>(out, valid ? g : 0, s, valid);
+    } else if (threadIdx.x == 0) {
+        int64_t cur = -1;
+        T acc = 0;
+        for (int w = 0; w < BS / WAVE; ++w) {
+            if (s_key[w] < 0) continue;
+            if (s_key[w] != cur) {
+                if (cur >= 0 && acc) atomicAdd(&out[cur], acc);
+                cur = s_key[w];
+                acc = 0;
+            }
+            acc += s_val[w];
+        }
+        if (cur >= 0 && acc) atomicAdd(&out[cur], acc);
+    }
 }
 
 inline int grid_for(int64_t n, int64_t per_block, int64_t cap = 1 << 20)

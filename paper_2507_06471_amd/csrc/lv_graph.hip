@@ -118,18 +118,39 @@ __global__ void k_degree_unit(int32_t n, const int32_t* off, int32_t* k)
         k[i] = off[i + 1] - off[i];
 }
 
+// Per-thread running sum for one graph, flushed when the graph changes and at
+// the end (one atomic per graph per wavefront in the common case).
+struct GraphAcc {
+    int32_t g = -1;
+    unsigned long long s = 0;
+    __device__ void add(unsigned long long* out, int32_t gg, unsigned long long x)
+    {
+        if (gg != g) {
+            if (g >= 0 && s) atomicAdd(&out[g], s);
+            g = gg;
+            s = 0;
+        }
+        s += x;
+    }
+    // all threads of a 256-thread workgroup must call it
+    __device__ void flush_block(unsigned long long* out) { block_flush_sums<256, unsigned long long>(out, g, s); }
+};
+
+// Merge-path tiles visited by each workgroup of a grid of at most this many
+// (fewer workgroups, fewer atomics on the per-graph sums)
+constexpr unsigned SUM_GRID = 2048;
+
 // out[g] += sum of v_i^2 (or v_i) over the vertices of graph g (gid null: one graph)
 template <bool SQUARE>
 __global__ __launch_bounds__(256) void k_sum_sq(int64_t n, const int32_t* v, const int32_t* gid,
                                                 unsigned long long* out)
 {
-    for (int64_t base = (int64_t)blockIdx.x * 256; base < n; base += (int64_t)gridDim.x * 256) {
-        const int64_t i = base + threadIdx.x;
-        const bool valid = i < n;
-        const int64_t x = valid ? (int64_t)v[i] : 0;
-        const unsigned long long y = (unsigned long long)(SQUARE ? x * x : x);
-        wave_grouped_add<unsigned long long, unsigned long long>(out, valid && gid ? gid[i] : 0, y, valid);
+    GraphAcc acc;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const int64_t x = (int64_t)v[i];
+        acc.add(out, gid ? gid[i] : 0, (unsigned long long)(SQUARE ? x * x : x));
     }
+    acc.flush_block(out);
 }
 
 // gid[v] = graph of vertex v: the last g with voff[g] <= v
@@ -145,36 +166,17 @@ __global__ void k_fill_gid(const int32_t* voff, int32_t G, int32_t n, int32_t* g
     }
 }
 
-// Per-thread running sum for one graph, flushed when the graph changes and at
-// the end (one atomic per graph per wavefront in the common case).
-struct GraphAcc {
-    int32_t g = -1;
-    unsigned long long s = 0;
-    __device__ void add(unsigned long long* out, int32_t gg, unsigned long long x)
-    {
-        if (gg != g) {
-            if (g >= 0 && s) atomicAdd(&out[g], s);
-            g = gg;
-            s = 0;
-        }
-        s += x;
-    }
-    __device__ void flush(unsigned long long* out)
-    {
-        const bool valid = g >= 0 && s != 0;
-        wave_grouped_add<unsigned long long, unsigned long long>(out, valid ? g : 0, s, valid);
-    }
-};
-
 // out[g] += trace (sum of diagonal entries) of graph g
 __global__ __launch_bounds__(TILE_BS) void k_trace(int32_t n, const int32_t* off, const int32_t* idx, const int32_t* w,
                                                     int64_t nnz, const int32_t* gid, unsigned long long* out)
 {
     GraphAcc acc;
-    for_tile_entries<TILE_BS, TILE_IT>(off, n, nnz, [&](int32_t r, int64_t e) {
-        if (idx[e] == r) acc.add(out, gid ? gid[r] : 0, (unsigned long long)(w ? w[e] : 1));
-    });
-    acc.flush(out);
+    const int64_t tiles = ((int64_t)n + nnz + TILE - 1) / TILE;
+    for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x)
+        for_tile_entries_at<TILE_BS, TILE_IT>(t, off, n, nnz, [&](int32_t r, int64_t e) {
+            if (idx[e] == r) acc.add(out, gid ? gid[r] : 0, (unsigned long long)(w ? w[e] : 1));
+        });
+    acc.flush_block(out);
 }
 
 // out[g] += Sigma_in of graph g: entries whose endpoints share a label
@@ -183,10 +185,12 @@ __global__ __launch_bounds__(TILE_BS) void k_sigma_in(int32_t n, const int32_t* 
                                                        unsigned long long* out)
 {
     GraphAcc acc;
-    for_tile_entries<TILE_BS, TILE_IT>(off, n, nnz, [&](int32_t r, int64_t e) {
-        if (labels[idx[e]] == labels[r]) acc.add(out, gid ? gid[r] : 0, (unsigned long long)(w ? w[e] : 1));
-    });
-    acc.flush(out);
+    const int64_t tiles = ((int64_t)n + nnz + TILE - 1) / TILE;
+    for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x)
+        for_tile_entries_at<TILE_BS, TILE_IT>(t, off, n, nnz, [&](int32_t r, int64_t e) {
+            if (labels[idx[e]] == labels[r]) acc.add(out, gid ? gid[r] : 0, (unsigned long long)(w ? w[e] : 1));
+        });
+    acc.flush_block(out);
 }
 
 // tot[label] += k_i, one atomic per distinct label of a wavefront
@@ -288,14 +292,14 @@ hipError_t launch_fill_gid(const int32_t* voff, int32_t G, int32_t n, int32_t* g
 hipError_t launch_trace(int32_t n, const int32_t* off, const int32_t* idx, const int32_t* w, int64_t nnz,
                         const int32_t* gid, int64_t* out, hipStream_t s)
 {
-    if (nnz > 0) k_trace<<<tiles_for(n, nnz), TILE_BS, 0, s>>>(n, off, idx, w, nnz, gid, (unsigned long long*)out);
+    if (nnz > 0) k_trace<<<std::min(tiles_for(n, nnz), SUM_GRID), TILE_BS, 0, s>>>(n, off, idx, w, nnz, gid, (unsigned long long*)out);
     return hipGetLastError();
 }
 hipError_t launch_sigma_in(int32_t n, const int32_t* off, const int32_t* idx, const int32_t* w, int64_t nnz,
                            const int32_t* labels, const int32_t* gid, int64_t* out, hipStream_t s)
 {
     if (nnz > 0)
-        k_sigma_in<<<tiles_for(n, nnz), TILE_BS, 0, s>>>(n, off, idx, w, nnz, labels, gid, (unsigned long long*)out);
+        k_sigma_in<<<std::min(tiles_for(n, nnz), SUM_GRID), TILE_BS, 0, s>>>(n, off, idx, w, nnz, labels, gid, (unsigned long long*)out);
     return hipGetLastError();
 }
 hipError_t launch_modularity_parts(int32_t n, const int32_t* off, const int32_t* idx, const int32_t* w, int64_t nnz,
@@ -303,7 +307,7 @@ hipError_t launch_modularity_parts(int32_t n, const int32_t* off, const int32_t*
 {
     if (n > 0) k_label_volumes<<<grid_for(n, 256, 65536), 256, 0, s>>>(n, k, labels, (unsigned long long*)tot);
     if (nnz > 0)
-        k_sigma_in<<<tiles_for(n, nnz), TILE_BS, 0, s>>>(n, off, idx, w, nnz, labels, nullptr,
+        k_sigma_in<<<std::min(tiles_for(n, nnz), SUM_GRID), TILE_BS, 0, s>>>(n, off, idx, w, nnz, labels, nullptr,
                                                          (unsigned long long*)out2);
     if (n > 0)
         k_sum_sq_u64<<<grid_for(n, 256, 4096), 256, 0, s>>>((const unsigned long long*)tot, n,

@@ -75,7 +75,7 @@ struct RepackSeg {
 struct HubArgs {
     int32_t nhubs;
     uint32_t part_mask;            // LDS slots of a partition workgroup - 1
-    int32_t pregather;             // 1: partition tables with volumes, fed from `pairs`
+    int32_t bucketed;              // 1: partition tables with volumes, fed from per-partition buckets
     const int32_t* hub_vert;       // [nhubs]
     const int32_t* hub_parts;      // [nhubs] P
     const int32_t* hub_first_blk;  // [nhubs+1] first partition workgroup of each hub
@@ -87,8 +87,20 @@ struct HubArgs {
     int32_t* part_wown;
     int32_t* part_flag;            // 1 = the partition's table overflowed
     int32_t* fb_flag;              // [nhubs] hub needs the global-table fallback
-    int2* pairs;                   // pre-gathered (community, volume) per entry of hubs with P > 1
-    const int64_t* pair_off;       // [nhubs] offset of a hub's entries in `pairs`
+    // buckets (bucketed mode, hubs with P > 1): bucket b belongs to partition
+    // workgroup b and holds up to bucket_cap (community, volume) pairs with
+    // their weight sums, per chunk of the hub's row, of the communities in
+    // that partition; bucket_cnt[b] counts the pairs offered (more than
+    // bucket_cap: the hub takes the global-table fallback)
+    int32_t bucket_cap;
+    int32_t* bucket_cnt;           // [nblk], zero between sweeps
+    int2* bucket;                  // [nblk * bucket_cap]
+    int32_t* bucket_w;             // [nblk * bucket_cap] weight sums
+    int32_t sc_chunk;              // entries per scatter workgroup: 1024, 2048 or 4096
+    const int32_t* sc_hub;         // scatter workgroup b: entries [sc_beg, sc_end) of hub sc_hub
+    const int32_t* sc_beg;
+    const int32_t* sc_end;
+    int32_t nsc;
     // fallback: global open-addressing tables (2 ints per slot: key, value)
     const int64_t* tab_off;        // [nhubs] slot offset of the hub's table
     const int32_t* tab_cap;        // [nhubs] slots (power of two, 0 if P == 1)
@@ -106,6 +118,10 @@ struct HubArgs {
     int32_t* fpart_wown;
     const int32_t* fpart_first;    // [nhubs+1] scan-workgroup range of each hub
 };
+
+// partitions per hub in bucketed mode are limited by the scatter kernel's LDS histogram
+constexpr int32_t HUB_PMAX = 4096;
+
 
 // ---- launchers (lv_kernels.hip) ----
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);

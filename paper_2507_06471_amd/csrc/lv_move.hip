@@ -21,12 +21,15 @@
 //               workgroup p aggregates the communities of hash partition p in
 //               an LDS table; partial results are merged per vertex, and all P
 //               workgroups of a vertex run on one XCD (shared L2).  Two modes:
-//               compact tables of up to 16384 slots that re-read the vertex's
-//               entries, or (with P > 1) tables of up to 8192 slots fed from
-//               the vertex's (community, volume) pairs gathered once into a
-//               contiguous buffer.  If a partition's table ever fills up, that vertex
-//               is redone with a global-memory table (never expected with
-//               hashed partitions; it keeps every input exact and finite).
+//               compact tables of up to 16384 slots, each workgroup re-reading
+//               the vertex's entries and keeping its partition's; or (with
+//               P > 1) a scatter pass that reads the entries once, sums them
+//               per community within chunks of 1024-4096 entries, and appends each
+//               (community, volume, weight) to its partition's bucket, and
+//               256-thread workgroups with 2048-slot tables fed from the
+//               buckets.  If a partition's bucket or table ever fills up,
+//               that vertex is redone with a global-memory table (it keeps
+//               every input exact and finite).
 // In the first sweep of a level every community is a single vertex and CSR
 // columns are unique, so W_i(j) = A_ij and entries are scored directly.
 //
@@ -162,42 +165,45 @@ __device__ __forceinline__ void lds_insert(int32_t* key, int32_t* val, int32_t* 
     }
 }
 
+// As lds_insert, but gives up (returns false) after probing every slot.
+template <bool SIG>
+__device__ __forceinline__ bool lds_insert_bounded(int32_t* key, int32_t* val, int32_t* sig, uint32_t mask, int32_t C,
+                                                   int32_t W, int32_t S)
+{
+    uint32_t h = mix32(C) & mask;
+    for (uint32_t probes = 0; probes <= mask; ++probes) {
+        const int32_t prev = atomicCAS(&key[h], EMPTY_KEY, C);
+        if constexpr (SIG) if (prev == EMPTY_KEY) sig[h] = S;
+        if (prev == EMPTY_KEY || prev == C) { atomicAdd(&val[h], W); return true; }
+        h = (h + 1) & mask;
+    }
+    return false;
+}
+
 // Aggregate the entries [e_beg, e_end) (stride STRIDE from the caller's lane)
 // of vertex i into an LDS table, optionally only communities of partition
 // `part` of P.  Returns false if the bounded table had no room (only
 // possible with P > 1).
-// `pairs` (optional): the entries' (community, volume) pairs gathered in
-// advance, pairs[e - row_beg], EMPTY_KEY for the vertex's own loop.
 template <int STRIDE, bool BOUNDED, bool SIG>
 __device__ __forceinline__ bool aggregate_entries(const MoveArgs& a, int32_t i, int32_t e_beg, int32_t e_end,
                                                   int32_t* key, int32_t* val, int32_t* sig, uint32_t mask, uint32_t P,
-                                                  uint32_t part, const int2* pairs = nullptr, int32_t row_beg = 0)
+                                                  uint32_t part)
 {
     bool ok_all = true;
     for (int32_t e0 = e_beg; e0 < e_end; e0 += STRIDE * UNROLL) {
         int32_t jj[UNROLL], ww[UNROLL];
         int2 cc[UNROLL];
-        if (pairs) {
 #pragma unroll
-            for (int u = 0; u < UNROLL; ++u) {
-                const int32_t e = e0 + u * STRIDE;
-                const bool ok = e < e_end;
-                cc[u] = ok ? pairs[e - row_beg] : make_int2(EMPTY_KEY, 0);
-                ww[u] = (ok && a.w) ? __builtin_nontemporal_load(&a.w[e]) : 1;
-            }
-        } else {
+        for (int u = 0; u < UNROLL; ++u) {
+            const int32_t e = e0 + u * STRIDE;
+            const bool ok = e < e_end;
+            jj[u] = ok ? __builtin_nontemporal_load(&a.idx[e]) : i;
+            ww[u] = (ok && a.w) ? __builtin_nontemporal_load(&a.w[e]) : 1;
+        }
 #pragma unroll
-            for (int u = 0; u < UNROLL; ++u) {
-                const int32_t e = e0 + u * STRIDE;
-                const bool ok = e < e_end;
-                jj[u] = ok ? __builtin_nontemporal_load(&a.idx[e]) : i;
-                ww[u] = (ok && a.w) ? __builtin_nontemporal_load(&a.w[e]) : 1;
-            }
-#pragma unroll
-            for (int u = 0; u < UNROLL; ++u) {
-                if constexpr (SIG) cc[u] = jj[u] != i ? a.cs[jj[u]] : make_int2(EMPTY_KEY, 0);
-                else cc[u] = make_int2(jj[u] != i ? a.comm[jj[u]] : EMPTY_KEY, 0);
-            }
+        for (int u = 0; u < UNROLL; ++u) {
+            if constexpr (SIG) cc[u] = jj[u] != i ? a.cs[jj[u]] : make_int2(EMPTY_KEY, 0);
+            else cc[u] = make_int2(jj[u] != i ? a.comm[jj[u]] : EMPTY_KEY, 0);
         }
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
@@ -205,19 +211,35 @@ __device__ __forceinline__ bool aggregate_entries(const MoveArgs& a, int32_t i, 
             if (C == EMPTY_KEY) continue;
             if constexpr (BOUNDED) {
                 if (P > 1 && part_of(C, P) != part) continue;
-                uint32_t h = mix32(C) & mask;
-                uint32_t probes = 0;
-                for (;;) {
-                    const int32_t prev = atomicCAS(&key[h], EMPTY_KEY, C);
-                    if constexpr (SIG) if (prev == EMPTY_KEY) sig[h] = cc[u].y;
-                    if (prev == EMPTY_KEY || prev == C) { atomicAdd(&val[h], ww[u]); break; }
-                    if (++probes > mask) { ok_all = false; break; }
-                    h = (h + 1) & mask;
-                }
+                if (!lds_insert_bounded<SIG>(key, val, sig, mask, C, ww[u], cc[u].y)) ok_all = false;
             } else {
                 lds_insert<SIG>(key, val, sig, mask, C, ww[u], cc[u].y);
             }
         }
+    }
+    return ok_all;
+}
+
+// Aggregate bucket entries [t0, cnt) (stride STRIDE) into a bounded LDS table.
+template <int STRIDE>
+__device__ __forceinline__ bool aggregate_bucket(const int2* src, const int32_t* src_w, int32_t t0, int32_t cnt,
+                                                 int32_t* key, int32_t* val, int32_t* sig, uint32_t mask)
+{
+    bool ok_all = true;
+    for (int32_t b0 = t0; b0 < cnt; b0 += STRIDE * UNROLL) {
+        int2 cc[UNROLL];
+        int32_t ww[UNROLL];
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+            const int32_t t = b0 + u * STRIDE;
+            const bool ok = t < cnt;
+            cc[u] = ok ? src[t] : make_int2(EMPTY_KEY, 0);
+            ww[u] = (ok && src_w) ? src_w[t] : 1;
+        }
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u)
+            if (cc[u].x != EMPTY_KEY && !lds_insert_bounded<true>(key, val, sig, mask, cc[u].x, ww[u], cc[u].y))
+                ok_all = false;
     }
     return ok_all;
 }
@@ -314,9 +336,10 @@ hipError_t launch_move_t(bool singleton, const MoveArgs& a, hipStream_t s)
 }
 
 // ------------------------------------------------------------------ partitioned path (L > 4096)
-constexpr int PBS = 1024;
-constexpr int PSLOTS_SIG = 8192;       // 12-byte slots (key, weight, volume): 96 KiB
+constexpr int PBS = 1024;               // compact partition workgroups and the scatter pass
 constexpr int PSLOTS_COMPACT = 16384;  // 8-byte slots (key, weight): 128 KiB
+constexpr int BBS = 256;               // bucketed partition workgroups
+constexpr int BSLOTS = 2048;           // 12-byte slots (key, weight, volume): 24 KiB, six workgroups a CU
 
 // Workgroups are dispatched to the 8 XCDs round-robin; renumber them so that
 // consecutive logical ids run on one XCD (and share its L2).
@@ -326,15 +349,17 @@ __device__ __forceinline__ int32_t xcd_logical(int32_t b, int32_t nblk)
     return x * q + min(x, r) + k;
 }
 
-template <bool SINGLETON, bool SIG>
-__global__ __launch_bounds__(PBS) void k_hub_part(MoveArgs a, HubArgs h)
+// One workgroup per (vertex, partition): aggregate the partition's
+// communities in LDS (or, in the first sweep, score a contiguous 1/P of the
+// entries directly) and write the partial best.
+template <bool SINGLETON, bool SIG, int BS, int SLOTS>
+__global__ __launch_bounds__(BS) void k_hub_part(MoveArgs a, HubArgs h)
 {
-    constexpr int PSLOTS = SIG ? PSLOTS_SIG : PSLOTS_COMPACT;
-    __shared__ int32_t s_key[SINGLETON ? 1 : PSLOTS];
-    __shared__ int32_t s_val[SINGLETON ? 1 : PSLOTS];
-    __shared__ int32_t s_sig[(SINGLETON || !SIG) ? 1 : PSLOTS];
-    __shared__ int64_t rs[PBS / WAVE];
-    __shared__ int32_t rc[PBS / WAVE], rw[PBS / WAVE];
+    __shared__ int32_t s_key[SINGLETON ? 1 : SLOTS];
+    __shared__ int32_t s_val[SINGLETON ? 1 : SLOTS];
+    __shared__ int32_t s_sig[(SINGLETON || !SIG) ? 1 : SLOTS];
+    __shared__ int64_t rs[BS / WAVE];
+    __shared__ int32_t rc[BS / WAVE], rw[BS / WAVE];
     __shared__ int32_t s_over;
     if (a.ctl->all_done) return;
     const int32_t b = xcd_logical((int32_t)blockIdx.x, h.nblk);
@@ -355,21 +380,34 @@ __global__ __launch_bounds__(PBS) void k_hub_part(MoveArgs a, HubArgs h)
     if constexpr (SINGLETON) {
         const int64_t L = end - beg;
         const int32_t cb = beg + (int32_t)(L * part / P), ce = beg + (int32_t)(L * (part + 1) / P);
-        score_entries_singleton<PBS>(a, i, ki, M, cb + (int32_t)threadIdx.x, ce, best_s, best_c);
+        score_entries_singleton<BS>(a, i, ki, M, cb + (int32_t)threadIdx.x, ce, best_s, best_c);
     } else {
         const uint32_t T = h.part_mask + 1u;
-        for (uint32_t t = threadIdx.x; t < T; t += PBS) { s_key[t] = EMPTY_KEY; s_val[t] = 0; }
+        // bucketed: this partition's communities were scattered to its bucket;
+        // a bucket offered more than it holds sends the vertex to the
+        // global-table fallback
+        const int32_t cnt = (SIG && h.bucketed && P > 1) ? h.bucket_cnt[b] : -1;
+        for (uint32_t t = threadIdx.x; t < T; t += BS) { s_key[t] = EMPTY_KEY; s_val[t] = 0; }
         if (threadIdx.x == 0) s_over = 0;
         __syncthreads();
-        const int2* pairs = (SIG && P > 1) ? h.pairs + h.pair_off[hh] : nullptr;
-        if (!aggregate_entries<PBS, true, SIG>(a, i, beg + (int32_t)threadIdx.x, end, s_key, s_val, s_sig,
-                                               h.part_mask, P, part, pairs, beg))
-            s_over = 1;
+        if (cnt >= 0 && threadIdx.x == 0) h.bucket_cnt[b] = 0;  // every thread has read it
+        bool ok;
+        if (cnt > h.bucket_cap) {
+            ok = false;
+        } else if (cnt >= 0) {
+            const size_t at = (size_t)b * (size_t)h.bucket_cap;
+            ok = aggregate_bucket<BS>(h.bucket + at, h.bucket_w + at, (int32_t)threadIdx.x, cnt, s_key, s_val, s_sig,
+                                      h.part_mask);
+        } else {
+            ok = aggregate_entries<BS, true, SIG>(a, i, beg + (int32_t)threadIdx.x, end, s_key, s_val, s_sig,
+                                                  h.part_mask, P, part);
+        }
+        if (!ok) s_over = 1;
         __syncthreads();
         over = s_over;
-        if (!over) scan_table<PBS, SIG>(a, s_key, s_val, s_sig, threadIdx.x, T, A, ki, M, best_s, best_c, w_own);
+        if (!over) scan_table<BS, SIG>(a, s_key, s_val, s_sig, threadIdx.x, T, A, ki, M, best_s, best_c, w_own);
     }
-    block_reduce_best<PBS>(best_s, best_c, w_own, rs, rc, rw);
+    block_reduce_best<BS>(best_s, best_c, w_own, rs, rc, rw);
     if (threadIdx.x == 0) {
         h.part_score[b] = best_s;
         h.part_comm[b] = best_c;
@@ -406,19 +444,80 @@ __global__ __launch_bounds__(256) void k_hub_finalize(MoveArgs a, HubArgs h)
     if (has && !overflowed && lane_id() == 0) decide_store(a, hh, A, sA, ki, vertex_M(a, i), best_s, best_c, w_own);
 }
 
-// Pre-gather the (community, volume) pairs of the entries of vertices with
-// P > 1 partitions (one workgroup per chunk of a vertex's entries).
-__global__ __launch_bounds__(256) void k_hub_pairs(MoveArgs a, HubArgs h)
+// Scatter the entries of hubs with P > 1 into their partitions' buckets.  A
+// workgroup takes a chunk of a row, sums its entries per community in LDS
+// (so a community shared by many neighbours costs one bucket entry per
+// chunk), and appends each (community, volume, weight sum) to the bucket of
+// the community's partition.  Positions inside a bucket depend on timing; the
+// sums a partition workgroup forms from them do not.
+template <int SBS, int EPT>
+__global__ __launch_bounds__(SBS) void k_hub_scatter(MoveArgs a, HubArgs h)
 {
+    constexpr int SC_EPT = EPT;
+    constexpr int SC_SLOTS = 2 * SBS * EPT;
+    constexpr int SC_SPT = 2 * EPT;
+    __shared__ int32_t t_key[SC_SLOTS];
+    __shared__ int32_t t_val[SC_SLOTS];
+    __shared__ int32_t t_sig[SC_SLOTS];
+    __shared__ int32_t s_cnt[HUB_PMAX];  // per-partition counts, then bucket bases
     if (a.ctl->all_done) return;
     const int b = blockIdx.x;
-    const int32_t hh = h.ins_hub[b];
+    const int32_t hh = h.sc_hub[b];
     const int32_t i = h.hub_vert[hh];
-    const int32_t beg = a.off[i];
-    int2* out = h.pairs + h.pair_off[hh];
-    for (int32_t e = h.ins_beg[b] + threadIdx.x; e < h.ins_end[b]; e += 256) {
-        const int32_t j = __builtin_nontemporal_load(&a.idx[e]);
-        out[e - beg] = j != i ? a.cs[j] : make_int2(EMPTY_KEY, 0);
+    if (vertex_frozen(a, i)) return;
+    const uint32_t P = (uint32_t)h.hub_parts[hh];
+    const int32_t e0 = h.sc_beg[b], e1 = h.sc_end[b];
+    for (uint32_t t = threadIdx.x; t < (uint32_t)SC_SLOTS; t += SBS) { t_key[t] = EMPTY_KEY; t_val[t] = 0; }
+    for (uint32_t t = threadIdx.x; t < P; t += SBS) s_cnt[t] = 0;
+    __syncthreads();
+    {
+        int32_t jj[SC_EPT], ww[SC_EPT];
+        int2 cc[SC_EPT];
+#pragma unroll
+        for (int u = 0; u < SC_EPT; ++u) {
+            const int32_t e = e0 + u * SBS + (int32_t)threadIdx.x;
+            const bool ok = e < e1;
+            jj[u] = ok ? __builtin_nontemporal_load(&a.idx[e]) : i;
+            ww[u] = (ok && a.w) ? __builtin_nontemporal_load(&a.w[e]) : 1;
+        }
+#pragma unroll
+        for (int u = 0; u < SC_EPT; ++u) cc[u] = jj[u] != i ? a.cs[jj[u]] : make_int2(EMPTY_KEY, 0);
+        // at most SBS * EPT distinct keys in twice as many slots: always room
+#pragma unroll
+        for (int u = 0; u < SC_EPT; ++u)
+            if (cc[u].x != EMPTY_KEY) lds_insert<true>(t_key, t_val, t_sig, SC_SLOTS - 1, cc[u].x, ww[u], cc[u].y);
+    }
+    __syncthreads();
+    uint32_t pp[SC_SPT];
+    int32_t rk[SC_SPT];
+#pragma unroll
+    for (int u = 0; u < SC_SPT; ++u) {
+        const int32_t C = t_key[u * SBS + threadIdx.x];
+        pp[u] = 0;
+        rk[u] = -1;
+        if (C != EMPTY_KEY) {
+            pp[u] = part_of(C, P);
+            rk[u] = atomicAdd(&s_cnt[pp[u]], 1);
+        }
+    }
+    __syncthreads();
+    int32_t* cnt = h.bucket_cnt + h.hub_first_blk[hh];
+    for (uint32_t t = threadIdx.x; t < P; t += SBS) {
+        const int32_t c = s_cnt[t];
+        s_cnt[t] = c ? atomicAdd(&cnt[t], c) : 0;
+    }
+    __syncthreads();
+    const size_t cap = (size_t)h.bucket_cap;
+    const size_t first = (size_t)h.hub_first_blk[hh];
+#pragma unroll
+    for (int u = 0; u < SC_SPT; ++u) {
+        if (rk[u] < 0) continue;
+        const int32_t pos = s_cnt[pp[u]] + rk[u];
+        if (pos >= h.bucket_cap) continue;  // the partition's workgroup flags the overflow
+        const int32_t t = u * SBS + threadIdx.x;
+        const size_t at = (first + pp[u]) * cap + (size_t)pos;
+        h.bucket[at] = make_int2(t_key[t], t_sig[t]);
+        h.bucket_w[at] = t_val[t];
     }
 }
 
@@ -515,24 +614,32 @@ __global__ __launch_bounds__(256) void k_apply(const int32_t* verts, const int32
 {
     if (ctl->all_done) return;
     uint32_t* moves = gmoves + ctl->sweep;
+    int64_t my_g = -1;  // this thread's running mover count, for graph my_g
+    uint32_t my_n = 0;
     for (int64_t base = (int64_t)blockIdx.x * 256; base < m; base += (int64_t)gridDim.x * 256) {
         const int64_t t = base + threadIdx.x;
         const int32_t C = t < m ? dec[t] : -1;
         const bool valid = C >= 0;
-        int32_t A = 0, kv = 0, gv = 0;
+        int32_t A = 0, kv = 0;
         if (valid) {
             const int32_t v = verts[t];
             A = comm[v];
             kv = k[v];
-            gv = gid ? gid[v] : 0;
+            const int64_t gv = gid ? (int64_t)gid[v] * max_sweeps : 0;
+            if (gv != my_g) {
+                if (my_n) atomicAdd(&moves[my_g], my_n);
+                my_g = gv;
+                my_n = 0;
+            }
+            ++my_n;
             comm[v] = C;
         }
         if (__ballot(valid)) {
             wave_grouped_add<int32_t, int32_t>(sigma, C, kv, valid);
             wave_grouped_add<int32_t, int32_t>(sigma, A, -kv, valid);
-            wave_grouped_add<uint32_t, uint32_t>(moves, (int64_t)gv * max_sweeps, 1u, valid);
         }
     }
+    block_flush_sums<256, uint32_t>(moves, my_n ? my_g : -1, my_n);
 }
 
 // After sweep s (1-based): a running graph stops when s >= 2 and its last two
@@ -667,13 +774,21 @@ hipError_t launch_hub_clear(int32_t* table, int64_t slots, hipStream_t s)
 hipError_t launch_hub_sweep(bool singleton, const MoveArgs& a, const HubArgs& h, hipStream_t s)
 {
     if (h.nhubs <= 0) return hipSuccess;
-    if (singleton) {
-        k_hub_part<true, false><<<(unsigned)h.nblk, PBS, 0, s>>>(a, h);
-    } else if (h.pregather) {
-        if (h.nins > 0) k_hub_pairs<<<(unsigned)h.nins, 256, 0, s>>>(a, h);
-        k_hub_part<false, true><<<(unsigned)h.nblk, PBS, 0, s>>>(a, h);
+    if (h.bucketed) {
+        if (singleton) {
+            k_hub_part<true, false, BBS, 1><<<(unsigned)h.nblk, BBS, 0, s>>>(a, h);
+        } else {
+            if (h.nsc > 0) {
+                if (h.sc_chunk == 1024) k_hub_scatter<256, 4><<<(unsigned)h.nsc, 256, 0, s>>>(a, h);
+                else if (h.sc_chunk == 2048) k_hub_scatter<256, 8><<<(unsigned)h.nsc, 256, 0, s>>>(a, h);
+                else k_hub_scatter<512, 8><<<(unsigned)h.nsc, 512, 0, s>>>(a, h);
+            }
+            k_hub_part<false, true, BBS, BSLOTS><<<(unsigned)h.nblk, BBS, 0, s>>>(a, h);
+        }
+    } else if (singleton) {
+        k_hub_part<true, false, PBS, 1><<<(unsigned)h.nblk, PBS, 0, s>>>(a, h);
     } else {
-        k_hub_part<false, false><<<(unsigned)h.nblk, PBS, 0, s>>>(a, h);
+        k_hub_part<false, false, PBS, PSLOTS_COMPACT><<<(unsigned)h.nblk, PBS, 0, s>>>(a, h);
     }
     const unsigned fin = (unsigned)((h.nhubs + 3) / 4);
     k_hub_finalize<<<fin, 256, 0, s>>>(a, h);

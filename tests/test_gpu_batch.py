@@ -85,7 +85,7 @@ def test_batch_with_hubs_and_tuning():
               graphgen.sbm(2048, 64, 0.08, 0.001, seed=9), graphgen.rmat(12, seed=6)]
     for t, g in enumerate(graphs):
         g.name = f"h{t}"
-    tuning = {"sub_max": 8, "wave_max": 8, "block_max": 8, "part_keys": 40, "part_slots": 64}
+    tuning = {"sub_max": 8, "wave_max": 8, "block_max": 8, "part_keys": 40, "part_slots": 64, "hub_chunk": 1024}
     say("batch with forced partitions/overflows")
     with lvp.Graph.batch(graphs) as bg:
         got = lvp.louvain(bg, tuning=tuning)

@@ -97,13 +97,28 @@ def test_lfr_weighted():
 @pytest.mark.parametrize("tuning", [
     {"sub_max": 1, "wave_max": 2, "block_max": 3, "part_keys": 256},    # nearly all partitioned
     {"sub_max": 8, "wave_max": 8, "block_max": 8, "part_keys": 40, "part_slots": 64},  # forces overflows
+    {"sub_max": 8, "wave_max": 8, "block_max": 8, "part_keys": 40, "part_slots": 64, "hub_mode": 1},
+    {"block_max": 600, "hub_mode": 1, "part_keys": 500},                   # compact re-reading partitions
     {"sub_max": 32, "wave_max": 128, "block_max": 512, "part_keys": 1000},
     {"sub_max": 4, "wave_max": 64, "block_max": 4096, "part_keys": 4096},
-    {"block_max": 600, "hub_mode": 2, "part_keys": 500},                   # pre-gathered pairs
-    {"block_max": 300, "hub_mode": 2, "part_keys": 100, "part_slots": 128},  # pairs + overflows
+    {"block_max": 600, "hub_mode": 2, "part_keys": 500},                   # bucketed partitions
+    {"block_max": 300, "hub_mode": 2, "part_keys": 100, "part_slots": 128},  # buckets + overflows
+    {"block_max": 64, "hub_mode": 2, "part_keys": 32, "part_slots": 64},     # many small buckets
+    {"block_max": 64, "hub_mode": 2, "part_keys": 48, "hub_chunk": 1024},
+    {"block_max": 300, "hub_mode": 2, "part_keys": 200, "hub_chunk": 4096},
 ])
 def test_tuning_never_changes_results(tuning):
     g = graphgen.rmat(14, seed=5)
+    compare_louvain(g, tuning=tuning)
+    compare_lpa(g, tuning=tuning)
+
+
+@pytest.mark.parametrize("tuning", [
+    {"block_max": 200, "hub_mode": 2, "part_keys": 64},
+    {"block_max": 100, "hub_mode": 2, "part_keys": 40, "part_slots": 64},
+])
+def test_weighted_bucketed_partitions(tuning):
+    g, _ = graphgen.lfr(20000, kmax=1500, smin=30, smax=3000, seed=7)
     compare_louvain(g, tuning=tuning)
     compare_lpa(g, tuning=tuning)
 
