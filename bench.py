@@ -35,6 +35,110 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+PMC_FILE = os.path.join(ROOT, "profiles", "pmc_rmat24.txt")
+
+
+KERNEL_SOURCES = ("lv_device.h", "lv_internal.h", "lv_move.hip")  # where the move kernels are defined
+
+
+def kernel_source_digest() -> str:
+    """Digest of the move kernels' sources, to tell whether stored counters still describe them."""
+    import hashlib
+
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2507_06471_amd", "csrc")
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(slot: str):
+    """HBM bytes per launch of the kernel in `slot` from the stored rocprofv3
+    FETCH_SIZE / WRITE_SIZE passes over this workload, each scaled by the
+    counter's reading for a plain copy of known size; None if there is no
+    record or the kernel sources changed since it was taken."""
+    if not os.path.exists(PMC_FILE):
+        return None
+    with open(PMC_FILE) as fh:
+        recs = [dict(kv.split("=", 1) for kv in line.split()) for line in fh if line.strip() and not line.startswith("#")]
+    for r in recs:
+        if r.get("slot") == slot:
+            if r.get("src") != kernel_source_digest():
+                return None
+            fetch = float(r["fetch_kib"]) / float(r["copy_fetch_factor"])
+            write = float(r["write_kib"]) / float(r["copy_write_factor"])
+            return round((fetch + write) * 1024.0)
+    return None
+
+
+def batch_leg(args, lvp, graphgen, np, torch):
+    """Mixed batch of independent graphs: one packed handle (every graph in the
+    same launches, sweeps captured as hipGraphs, autotuned classes) against
+    one graph per call on the same GPU, over a sample of the same graphs.
+    Both sides start from device-resident graphs and end with every graph's
+    final labels and modularity on the host; partitions must be identical."""
+    t = time.time()
+    gs = graphgen.batch_mix(args.batch_graphs, seed=4)
+    V = sum(g.n for g in gs)
+    E = sum(g.nnz for g in gs)
+    log(f"batch: {len(gs)} graphs, {V} vertices, {E} entries, generated in {time.time() - t:.1f}s")
+    t = time.time()
+    bg = lvp.Graph.batch(gs, validate=True)
+    log(f"batch: packed handle resident in {time.time() - t:.1f}s")
+    cfg, est = lvp.autotune(bg)
+    log(f"batch: autotuned {cfg} (estimated level-0 {est:.1f} ms)")
+    fp = lvp.louvain_final(bg, autotuned=True)  # warm-up
+    reps = []
+    for _ in range(args.batch_reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fp = lvp.louvain_final(bg, autotuned=True)
+        reps.append(time.perf_counter() - t0)
+    batch_s = float(np.median(reps))
+    # entries processed by local moving, from a timed run's per-level counts
+    # (per graph: sum over levels of entries x sweeps)
+    detail = lvp.louvain(bg, autotuned=True)
+    lm_entries = sum(lv.info["nnz"] * lv.info["sweeps"] for r in detail for lv in r.levels)
+    bases = np.concatenate([[0], np.cumsum([g.n for g in gs])])
+    # one graph per call over an evenly spaced sample
+    step_ = max(1, len(gs) // args.batch_sample)
+    sample = list(range(0, len(gs), step_))[:args.batch_sample]
+    handles = [lvp.Graph.from_csr(gs[i], validate=True) for i in sample]
+    for h in handles[:4]:
+        lvp.louvain_final(h)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    singles = [lvp.louvain_final(h) for h in handles]
+    single_s = time.perf_counter() - t0
+    same = True
+    for i, h, fs in zip(sample, handles, singles):
+        lo, hi = bases[i], bases[i + 1]
+        same &= bool(np.array_equal(fs.labels, fp.labels[lo:hi])) and int(fs.q_int[0]) == int(fp.q_int[i])
+        h.close()
+    sample_entries = sum(lv.info["nnz"] * lv.info["sweeps"] for i in sample for lv in detail[i].levels)
+    bg.close()
+    out = {
+        "workload": f"{len(gs)} graphs alternating SBM (blocks of 128, 75% of the degree inside) and R-MAT "
+                    "(0.57, 0.19, 0.19); n log-uniform in [1024, 65536], mean degree uniform in [8, 32], "
+                    "unit weights, seed 4",
+        "graphs": len(gs), "vertices": V, "entries": E,
+        "batched": {"ms": round(batch_s * 1e3, 2), "graphs_per_s": round(len(gs) / batch_s, 1),
+                    "local_move_gteps": round(lm_entries / batch_s / 1e9, 3), "reps": len(reps),
+                    "tuning": cfg},
+        "one_graph_per_call": {"sample_graphs": len(sample), "ms": round(single_s * 1e3, 2),
+                               "graphs_per_s": round(len(sample) / single_s, 1),
+                               "local_move_gteps": round(sample_entries / single_s / 1e9, 3)},
+        "identical_partitions": same,
+    }
+    out["speedup_graphs_per_s"] = round(out["batched"]["graphs_per_s"] / out["one_graph_per_call"]["graphs_per_s"], 2)
+    log(f"batch: {out}")
+    if not same:
+        print("batched partitions differ from one-graph-per-call partitions", file=sys.stderr, flush=True)
+        sys.exit(1)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -46,6 +150,9 @@ def main():
     ap.add_argument("--cpu-sweeps", type=int, default=2, help="oracle sweeps timed for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--batch-graphs", type=int, default=4096, help="graphs in the batch leg (0: skip it)")
+    ap.add_argument("--batch-sample", type=int, default=256, help="graphs run one per call for the baseline")
+    ap.add_argument("--batch-reps", type=int, default=3)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB before the steps (PMC calibration)")
     args = ap.parse_args()
@@ -122,7 +229,9 @@ def main():
     K = len(runs)
     gteps = lm_edges / (lm_ms * 1e-3) / 1e9 if lm_ms > 0 else 0.0
     lpa_gteps = lpa_edges / (lpa_ms * 1e-3) / 1e9 if lpa_ms > 0 else 0.0
-    dom = int(np.argmax(kern_ms))
+    # dominant kernel: the longest-running single kernel that reads the graph
+    # (the hub partition slot reads only the scatter pass's buckets)
+    dom = int(np.argmax(np.where(kern_bytes > 0, kern_ms, -1.0)))
     avg_launch_ms = kern_ms[dom] / max(1, kern_launches[dom])
     bytes_per_launch = kern_bytes[dom] / max(1, kern_launches[dom])
     achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9 if avg_launch_ms > 0 else 0.0
@@ -175,6 +284,13 @@ def main():
                 print("first-sweep partition differs from the oracle", file=sys.stderr, flush=True)
                 sys.exit(1)
 
+    dg.close()
+    gn, gnnz = g.n, g.nnz
+    del g
+    if not args.no_cpu_baseline or not args.no_parity:
+        del adj, k, c, sigma
+    batch = batch_leg(args, lvp, graphgen, np, torch) if args.batch_graphs > 0 else None
+
     out = {
         "metric": METRIC,
         "value": round(gteps, 4),
@@ -191,9 +307,10 @@ def main():
         "config": {"workload": f"R-MAT scale {args.scale}, edge factor {args.edge_factor:g} (a=0.57, b=0.19, "
                                "c=0.19), symmetrised, loops/duplicates removed, unit weights; Louvain all levels "
                                "+ LPA max 20 sweeps",
-                   "n": g.n, "nnz": g.nnz, "seed": args.seed},
+                   "n": gn, "nnz": gnnz, "seed": args.seed},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(lvp.KERNEL_NAMES[dom]) if args.scale == 24 else None,
                      "kernel": lvp.KERNEL_NAMES[dom], "avg_launch_ms": round(float(avg_launch_ms), 4),
                      "bytes_per_launch": int(bytes_per_launch)},
         "cpu_baseline": cpu,
@@ -205,9 +322,9 @@ def main():
         "lpa": {"gteps": round(lpa_gteps, 4), "sweeps": runs[0][1].info["sweeps"], "q": runs[0][1].info["q_end"] / float(dg.volume) ** 2},
         "phase_ms_per_step": {k_: round(v / K, 3) for k_, v in phases.items()},
         "kernels": kernels,
+        "batch": batch,
     }
     print(json.dumps(out), flush=True)
-    dg.close()
 
 
 if __name__ == "__main__":

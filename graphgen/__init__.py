@@ -44,6 +44,7 @@ def _load():
             build_library()
         lib = ctypes.CDLL(_LIB_PATH)
         lib.gg_free.argtypes = [ctypes.c_void_p]
+        lib.gg_set_threads.argtypes = [ctypes.c_int]
         lib.gg_rand.restype = ctypes.c_uint64
         lib.gg_rand.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
         lib.gg_stream_key.restype = ctypes.c_uint64
@@ -195,3 +196,46 @@ def rand_u64(key: int, counter: int) -> int:
 
 def loguniform_int(lo: int, hi: int, u: float) -> int:
     return int(math.floor(math.exp(math.log(lo) + u * (math.log(hi) - math.log(lo)))))
+
+
+def batch_mix(count: int = 4096, seed: int = 4, n_lo: int = 1024, n_hi: int = 65536, deg_lo: float = 8.0,
+              deg_hi: float = 32.0, block: int = 128, intra: float = 0.75):
+    """The mixed batch workload: `count` independent graphs alternating SBM and
+    R-MAT, vertex counts log-uniform in [n_lo, n_hi], mean degree uniform in
+    [deg_lo, deg_hi], unit weights.  SBM: blocks of `block` vertices with a
+    fraction `intra` of the expected degree inside the block.  R-MAT: scale
+    ceil(log2 n), (0.57, 0.19, 0.19), ids >= n dropped, n * degree / 2 samples.
+    Parameters are drawn from a numpy generator seeded with `seed`; graph t
+    uses generator seed `seed * 1_000_003 + t`."""
+    rng = np.random.default_rng(seed)
+    specs = []
+    for t in range(count):
+        n = int(round(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi)))))
+        d = float(rng.uniform(deg_lo, deg_hi))
+        specs.append((t, n, d, seed * 1_000_003 + t))
+
+    def make(spec):
+        t, n, d, gs = spec
+        if t % 2 == 0:
+            b = min(block, n)
+            p_in = min(1.0, intra * d / max(1, b - 1))
+            p_out = min(1.0, (1.0 - intra) * d / max(1, n - b))
+            g = sbm(n, b, p_in, p_out, seed=gs)
+        else:
+            scale = max(1, int(np.ceil(np.log2(n))))
+            g = rmat(scale, n=n, samples=int(round(n * d / 2)), seed=gs)
+        g.name = f"mix{t}"
+        return g
+
+    # the graphs are independent: generate them on host threads, one OpenMP
+    # thread each (the C generators release the interpreter lock)
+    from concurrent.futures import ThreadPoolExecutor
+
+    workers = max(1, min(16, os.cpu_count() or 1))
+    lib = _load()
+
+    def init():
+        lib.gg_set_threads(1)
+
+    with ThreadPoolExecutor(workers, initializer=init) as ex:
+        return list(ex.map(make, specs))

@@ -51,6 +51,9 @@ static inline double u01(uint64_t h) { return (double)(h >> 11) * (1.0 / 9007199
 
 void gg_free(void* p) { free(p); }
 
+/* OpenMP team size for the calling thread's later generator calls */
+void gg_set_threads(int t) { if (t > 0) omp_set_num_threads(t); }
+
 uint64_t gg_rand(uint64_t key, uint64_t counter) { return rnd(key, counter); }
 uint64_t gg_stream_key(uint64_t seed, uint64_t tag) { return stream_key(seed, tag); }
 

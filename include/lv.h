@@ -72,6 +72,8 @@ typedef enum lv_memkind { LV_MEM_HOST = 0, LV_MEM_DEVICE = 1 } lv_memkind;
                           /* are then launched one by one instead of from a HIP graph     */
 #define LV_KEEP_GRAPHS 2u /* lv_louvain keeps every coarse graph for lv_result_level_graph */
 #define LV_NO_HIPGRAPH 4u /* launch sweeps one by one even without LV_TIMING              */
+#define LV_AUTOTUNE 8u    /* with tuning == NULL: use the handle's autotuned setting (lv_autotune), */
+                           /* chosen on the handle's first such call                               */
 
 typedef struct lv_graph lv_graph;   /* device-resident CSR + workspace, library-owned */
 typedef struct lv_result lv_result; /* per-level labels and statistics, library-owned */
@@ -107,7 +109,7 @@ typedef struct lv_params {
     const lv_tuning* tuning; /* NULL = built-in defaults                                   */
 } lv_params;
 
-#define LV_KERNEL_SLOTS 14
+#define LV_KERNEL_SLOTS 15
 
 /* Per-level statistics; times are milliseconds from HIP events (LV_TIMING). */
 typedef struct lv_level_info {
@@ -128,9 +130,11 @@ typedef struct lv_level_info {
        of a level, where every community is a single vertex); classes 1..6 =
        8-lane, 32-lane, wavefront, 256-thread, 512-thread (<= 2048 entries)
        and 512-thread compact (<= 4096) workgroup tables, 7 = partition
-       workgroups (all of that path's kernels together).  Bytes count each array element a kernel needs once:
-       indices (and weights) of its rows, and 20 bytes per vertex (vertex list,
-       row offset, label, degree, own community volume). */
+       workgroups (with their merge and fallback kernels); slot 14 = the
+       bucketed mode's scatter pass, which then carries class 7's bytes.
+       Bytes count each array element a kernel needs once: indices (and
+       weights) of its rows, and 20 bytes per vertex (vertex list, row offset,
+       label, degree, own community volume). */
     double kern_ms[LV_KERNEL_SLOTS];
     int64_t kern_launches[LV_KERNEL_SLOTS];
     int64_t kern_bytes[LV_KERNEL_SLOTS];
@@ -168,6 +172,19 @@ lv_status lv_graph_create_csr(int32_t n, const int32_t* offsets, const int32_t* 
 lv_status lv_graph_create_batch(int32_t count, const int32_t* n, const int32_t* const* offsets,
                                 const int32_t* const* indices, const int32_t* const* weights,
                                 lv_memkind kind, uint32_t flags, void* stream, lv_graph** out);
+/*
+ * Autotuner: picks the degree-class bounds (sub_max, wave_max, block_max)
+ * and the partition settings (hub_mode, part_keys, hub_chunk) for this
+ * handle by coordinate descent, timing each candidate on the handle's
+ * level-0 graph (one first sweep and two later sweeps, HIP events) and
+ * scoring it as a whole level of params->max_sweeps sweeps.  Writes the
+ * fastest setting to *out (zero fields = defaults) and, if est_ms is not
+ * NULL, its estimated level time in milliseconds; the handle keeps it for
+ * LV_AUTOTUNE calls.  Tuning never changes results.  About 11 timed trials;
+ * the handle's state is otherwise unchanged.
+ */
+lv_status lv_autotune(lv_graph* g, const lv_params* params, lv_tuning* out, double* est_ms);
+
 lv_status lv_graph_destroy(lv_graph* g);
 /* number of graphs packed in the handle (1 for lv_graph_create_csr) */
 lv_status lv_graph_count(const lv_graph* g, int32_t* count);
@@ -215,6 +232,11 @@ lv_status lv_result_graph_level_labels(const lv_result* r, int32_t g, int32_t le
                                        lv_memkind kind);
 lv_status lv_result_graph_final_labels(const lv_result* r, int32_t g, int32_t* labels, lv_memkind kind);
 lv_status lv_result_graph_modularity(const lv_result* r, int32_t g, int64_t* q_int, int64_t* m, double* q);
+/* Every graph at once: final labels int32[total vertices] packed like the
+   handle (graph g at its vertex offset, numbered within graph g), and
+   per-graph q_int, m, q arrays of length count (any may be NULL). */
+lv_status lv_result_final_labels_all(const lv_result* r, int32_t* labels, lv_memkind kind);
+lv_status lv_result_modularity_all(const lv_result* r, int64_t* q_int, int64_t* m, double* q);
 
 /*
  * Label propagation (Algorithm 1) as one level of synchronous sweeps with the

@@ -32,10 +32,12 @@ LV_VALIDATE = 1
 LV_TIMING = 1
 LV_KEEP_GRAPHS = 2
 LV_NO_HIPGRAPH = 4
-KERNEL_SLOTS = 14
-# kernel slot -> name (slot = 2*(class-1) + first-sweep flag)
+LV_AUTOTUNE = 8
+KERNEL_SLOTS = 15
+# kernel slot -> name (slot = 2*(class-1) + first-sweep flag; the last slot is
+# the bucketed hub scatter pass, whose partition workgroups are timed as "hub")
 KERNEL_NAMES = [f"{c}{'/first' if f else ''}" for c in ("g8", "g32", "wave", "block256", "block2k", "block4k", "hub")
-                for f in (0, 1)]
+                for f in (0, 1)] + ["hub/scatter"]
 
 _i32p = ctypes.POINTER(ctypes.c_int32)
 _i64p = ctypes.POINTER(ctypes.c_int64)
@@ -83,6 +85,8 @@ SIGNATURES = {
     "lv_graph_create_batch": (ctypes.c_int, [ctypes.c_int32, _vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_uint32,
                                              _vp, ctypes.POINTER(_vp)]),
     "lv_graph_destroy": (ctypes.c_int, [_vp]),
+    "lv_autotune": (ctypes.c_int, [_vp, ctypes.POINTER(lv_params), ctypes.POINTER(lv_tuning),
+                                   ctypes.POINTER(ctypes.c_double)]),
     "lv_graph_count": (ctypes.c_int, [_vp, _i32p]),
     "lv_graph_info": (ctypes.c_int, [_vp, _i32p, _i64p, _i64p]),
     "lv_louvain": (ctypes.c_int, [_vp, ctypes.POINTER(lv_params), ctypes.POINTER(_vp)]),
@@ -104,6 +108,8 @@ SIGNATURES = {
                                                   ctypes.POINTER(ctypes.c_double)]),
     "lv_lpa": (ctypes.c_int, [_vp, ctypes.POINTER(lv_params), _vp, ctypes.c_int,
                               ctypes.POINTER(lv_level_info), _i64p, ctypes.c_int32]),
+    "lv_result_final_labels_all": (ctypes.c_int, [_vp, _vp, ctypes.c_int]),
+    "lv_result_modularity_all": (ctypes.c_int, [_vp, _i64p, _i64p, ctypes.POINTER(ctypes.c_double)]),
     "lv_lpa_batch": (ctypes.c_int, [_vp, ctypes.POINTER(lv_params), _vp, ctypes.c_int, _i32p, _i64p, _i64p,
                                     _i64p, ctypes.c_int32]),
     "lv_modularity": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _i64p, _i64p, ctypes.POINTER(ctypes.c_double)]),
@@ -291,6 +297,39 @@ class LouvainResult:
         return [lv for lv in self.levels if lv.info["accepted"]]
 
 
+@dataclass
+class FinalPartition:
+    labels: np.ndarray     # packed like the handle: graph g's labels at its vertex offset
+    q_int: np.ndarray      # [count]
+    M: np.ndarray          # [count]
+    q: np.ndarray          # [count]
+
+
+def louvain_final(graph: Graph, max_sweeps: int = 20, max_levels: int = 32, tuning: Optional[dict] = None,
+                  autotuned: bool = False, out=None) -> FinalPartition:
+    """lv_louvain, then only the final labels and modularity of every graph
+    (two calls, whatever the number of graphs); `out` may be a numpy or
+    torch int32 buffer of the handle's total vertex count."""
+    lib = load_library()
+    p, _keep = make_params(max_sweeps, max_levels, 0, _flags(False, False, True, autotuned), tuning)
+    r = _vp()
+    _check(lib.lv_louvain(graph.handle, ctypes.byref(p), ctypes.byref(r)), "lv_louvain")
+    try:
+        labels = np.empty(max(graph.n, 1), dtype=np.int32) if out is None else out
+        pl, kind = _ptr(labels)
+        _check(lib.lv_result_final_labels_all(r, pl, kind), "lv_result_final_labels_all")
+        G = graph.count
+        qi = np.zeros(G, dtype=np.int64)
+        m = np.zeros(G, dtype=np.int64)
+        q = np.zeros(G, dtype=np.float64)
+        _check(lib.lv_result_modularity_all(r, qi.ctypes.data_as(_i64p), m.ctypes.data_as(_i64p),
+                                            q.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+               "lv_result_modularity_all")
+        return FinalPartition(labels[:graph.n] if out is None else labels, qi, m, q)
+    finally:
+        lib.lv_result_destroy(r)
+
+
 def _read_graph_result(lib, r, gi: int, n0: int, keep_graphs: bool) -> LouvainResult:
     acc, att = ctypes.c_int32(), ctypes.c_int32()
     _check(lib.lv_result_graph_num_levels(r, gi, ctypes.byref(acc), ctypes.byref(att)), "lv_result_graph_num_levels")
@@ -326,16 +365,18 @@ def _read_graph_result(lib, r, gi: int, n0: int, keep_graphs: bool) -> LouvainRe
     return LouvainResult(qi.value, m.value, q.value, fin, levels)
 
 
-def _flags(timing: bool, keep_graphs: bool = False, hipgraph: bool = True) -> int:
-    return (LV_TIMING if timing else 0) | (LV_KEEP_GRAPHS if keep_graphs else 0) | (0 if hipgraph else LV_NO_HIPGRAPH)
+def _flags(timing: bool, keep_graphs: bool = False, hipgraph: bool = True, autotuned: bool = False) -> int:
+    return ((LV_TIMING if timing else 0) | (LV_KEEP_GRAPHS if keep_graphs else 0) | (0 if hipgraph else LV_NO_HIPGRAPH)
+            | (LV_AUTOTUNE if autotuned else 0))
 
 
 def louvain(graph: Graph, max_sweeps: int = 20, max_levels: int = 32, timing: bool = False,
-            keep_graphs: bool = False, tuning: Optional[dict] = None, hipgraph: bool = True):
+            keep_graphs: bool = False, tuning: Optional[dict] = None, hipgraph: bool = True,
+            autotuned: bool = False):
     """lv_louvain + result accessors, copied to host numpy.  A packed handle
     (``Graph.batch``) gives one LouvainResult per graph, in order."""
     lib = load_library()
-    p, _keep = make_params(max_sweeps, max_levels, 0, _flags(timing, keep_graphs, hipgraph), tuning)
+    p, _keep = make_params(max_sweeps, max_levels, 0, _flags(timing, keep_graphs, hipgraph, autotuned), tuning)
     r = _vp()
     _check(lib.lv_louvain(graph.handle, ctypes.byref(p), ctypes.byref(r)), "lv_louvain")
     try:
@@ -354,12 +395,12 @@ class LpaResult:
 
 
 def lpa(graph: Graph, max_sweeps: int = 20, threshold: int = 0, timing: bool = False, out=None,
-        tuning: Optional[dict] = None, hipgraph: bool = True) -> LpaResult:
+        tuning: Optional[dict] = None, hipgraph: bool = True, autotuned: bool = False) -> LpaResult:
     """lv_lpa; labels land in `out` (numpy or torch int32) or a new numpy array."""
     lib = load_library()
     if graph.count != 1:
-        return lpa_batch(graph, max_sweeps, threshold, tuning=tuning, hipgraph=hipgraph)
-    p, _keep = make_params(max_sweeps, 32, threshold, _flags(timing, False, hipgraph), tuning)
+        return lpa_batch(graph, max_sweeps, threshold, tuning=tuning, hipgraph=hipgraph, autotuned=autotuned)
+    p, _keep = make_params(max_sweeps, 32, threshold, _flags(timing, False, hipgraph, autotuned), tuning)
     labels = np.empty(graph.n, dtype=np.int32) if out is None else out
     pl, kind = _ptr(labels)
     info = lv_level_info()
@@ -370,10 +411,10 @@ def lpa(graph: Graph, max_sweeps: int = 20, threshold: int = 0, timing: bool = F
 
 
 def lpa_batch(graph: Graph, max_sweeps: int = 20, threshold: int = 0, tuning: Optional[dict] = None,
-              hipgraph: bool = True) -> List[LpaResult]:
+              hipgraph: bool = True, autotuned: bool = False) -> List[LpaResult]:
     """lv_lpa_batch over a packed handle: one LpaResult per graph (local labels)."""
     lib = load_library()
-    p, _keep = make_params(max_sweeps, 32, threshold, _flags(False, False, hipgraph), tuning)
+    p, _keep = make_params(max_sweeps, 32, threshold, _flags(False, False, hipgraph, autotuned), tuning)
     G = graph.count
     labels = np.empty(max(graph.n, 1), dtype=np.int32)
     sw = np.zeros(G, dtype=np.int32)
@@ -390,6 +431,17 @@ def lpa_batch(graph: Graph, max_sweeps: int = 20, threshold: int = 0, tuning: Op
         out.append(LpaResult(labels[base:base + n].copy(), [int(x) for x in mv[gi, :sw[gi]]], info))
         base += n
     return out
+
+
+def autotune(graph: Graph, max_sweeps: int = 20):
+    """lv_autotune -> (tuning dict, estimated level ms); the handle keeps the
+    setting for calls with ``autotuned=True``."""
+    lib = load_library()
+    p, _keep = make_params(max_sweeps, 32, 0, 0, None)
+    t = lv_tuning()
+    ms = ctypes.c_double()
+    _check(lib.lv_autotune(graph.handle, ctypes.byref(p), ctypes.byref(t), ctypes.byref(ms)), "lv_autotune")
+    return {name: getattr(t, name) for name, _ in lv_tuning._fields_}, ms.value
 
 
 def modularity(graph: Graph, labels):

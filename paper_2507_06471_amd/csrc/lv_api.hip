@@ -165,6 +165,8 @@ struct lv_graph {
     Workspace ws;
     int32_t* pinned = nullptr;   // host staging area
     size_t pinned_bytes = 0;
+    bool has_tuned = false;      // LV_AUTOTUNE: the setting chosen on first use
+    lv_tuning tuned{};
     ~lv_graph()
     {
         if (pinned) (void)hipHostFree(pinned);
@@ -298,6 +300,9 @@ struct LevelGraph {
     std::vector<int32_t> voff;  // [G+1] vertex offsets (host)
     std::vector<int64_t> Mh;    // [G] total volume of each graph (host)
 };
+
+// timing slot of the bucketed scatter pass (after the 2 x 7 class slots)
+constexpr int SLOT_HUB_SCATTER = LV_KERNEL_SLOTS - 1;
 
 struct SweepOut {
     std::vector<int32_t> sweeps;   // [G]
@@ -561,7 +566,7 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
     // One sweep: move kernels of every class, the partition path, commit,
     // pair refresh, per-graph stopping rule.
     auto launch_sweep = [&](bool singleton, std::vector<hipEvent_t>* e) -> lv_status {
-        if (e) { e->assign(2 * NUM_CLS + 3, nullptr); HIP_TRY(tm.mark(&(*e)[2 * NUM_CLS])); }
+        if (e) { e->assign(2 * NUM_CLS + 4, nullptr); HIP_TRY(tm.mark(&(*e)[2 * NUM_CLS])); }
         for (int c = CLS_G8; c < CLS_HUB; ++c) {
             a.verts = vert_sorted + start[c];
             a.dec = dec_all + start[c];
@@ -576,6 +581,10 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
             a.dec = dec_all + start[CLS_HUB];
             a.nverts = hubs.nhubs;
             if (e) HIP_TRY(tm.mark(&(*e)[2 * CLS_HUB]));
+            if (!singleton && hubs.args.bucketed && hubs.args.nsc > 0) {
+                HIP_TRY(launch_hub_scatter(a, hubs.args, s));
+                if (e) HIP_TRY(tm.mark(&(*e)[2 * NUM_CLS + 3]));
+            }
             HIP_TRY(launch_hub_sweep(singleton, a, hubs.args, s));
             if (e) HIP_TRY(tm.mark(&(*e)[2 * CLS_HUB + 1]));
         }
@@ -644,7 +653,18 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
             out.launches += c == CLS_HUB ? (sw == 1 ? 2 : 2 + (hubs.args.bucketed && hubs.args.nsc > 0 ? 1 : 0) + (hubs.args.nins > 0 ? 3 : 0)) : 1;
             if (!timing) continue;
             const int slot = 2 * c + (sw == 1 ? 1 : 0) - 2;
-            out.kern_ms[slot] += elapsed(ev[sw - 1][2 * c], ev[sw - 1][2 * c + 1]);
+            const std::vector<hipEvent_t>& E = ev[sw - 1];
+            if (c == CLS_HUB && E[2 * NUM_CLS + 3]) {
+                // the scatter pass reads the rows (the class's algorithmic bytes);
+                // the partition workgroups read the buckets it wrote
+                out.kern_ms[SLOT_HUB_SCATTER] += elapsed(E[2 * c], E[2 * NUM_CLS + 3]);
+                out.kern_launches[SLOT_HUB_SCATTER] += 1;
+                out.kern_bytes[SLOT_HUB_SCATTER] += wbytes * cls_entries[c] + 20 * (int64_t)nv;
+                out.kern_ms[slot] += elapsed(E[2 * NUM_CLS + 3], E[2 * c + 1]);
+                out.kern_launches[slot] += 1;
+                continue;
+            }
+            out.kern_ms[slot] += elapsed(E[2 * c], E[2 * c + 1]);
             out.kern_launches[slot] += 1;
             out.kern_bytes[slot] += wbytes * cls_entries[c] + 20 * (int64_t)nv;
         }
@@ -853,6 +873,73 @@ LevelGraph level0(lv_graph* g)
     G.voff = g->voff;
     G.Mh = g->M;
     return G;
+}
+
+// Autotuner: coordinate descent over the tuning knobs; each candidate is timed
+// on the level-0 graph (a first sweep and two later sweeps, HIP events) and
+// scored as the time of a whole level of max_sweeps sweeps.  Settings only
+// choose which kernel handles which vertex, never the result.
+lv_status autotune(lv_graph* g, const Params& base, lv_tuning* best, double* best_ms)
+{
+    *best = lv_tuning{};
+    *best_ms = 0.0;
+    if (g->n == 0 || g->nnz == 0) return LV_OK;
+    auto cost = [&](const lv_tuning& t, double* ms) -> lv_status {
+        Params p = base;
+        p.max_sweeps = std::min(3, base.max_sweeps);
+        p.flags = LV_TIMING;
+        p.tune = make_tune(&t);
+        SweepOut so;
+        const LevelGraph G = level0(g);
+        LV_TRY(run_sweeps(g, G, MODE_LOUVAIN, p, nullptr, so));
+        double first = 0.0, later = 0.0;
+        for (int q = 0; q < LV_KERNEL_SLOTS; ++q) {
+            if (q < 2 * (NUM_CLS - 1) && (q & 1)) first += so.kern_ms[q];
+            else later += so.kern_ms[q];
+        }
+        const int32_t nl = std::max(1, so.executed - 1);
+        *ms = first + later / nl * std::max(0, base.max_sweeps - 1);
+        return LV_OK;
+    };
+    double cur = 0.0;
+    LV_TRY(cost(*best, &cur));
+    struct Knob { int32_t lv_tuning::*field; std::vector<int32_t> values; };
+    const std::vector<Knob> knobs = {
+        {&lv_tuning::sub_max, {4, 16}},
+        {&lv_tuning::wave_max, {64}},
+        {&lv_tuning::block_max, {2048}},
+        {&lv_tuning::hub_mode, {1}},
+        {&lv_tuning::part_keys, {512, 1024}},
+        {&lv_tuning::hub_chunk, {2048, 4096}},
+    };
+    for (const Knob& kb : knobs) {
+        lv_tuning keep = *best;
+        for (int32_t v : kb.values) {
+            lv_tuning t = *best;
+            t.*(kb.field) = v;
+            if (kb.field == &lv_tuning::part_keys && t.hub_mode == 1) t.part_keys = v * 8;  // compact tables are 8x larger
+            double ms = 0.0;
+            LV_TRY(cost(t, &ms));
+            if (ms < cur * 0.98) { cur = ms; keep = t; }
+        }
+        *best = keep;
+    }
+    *best_ms = cur;
+    return LV_OK;
+}
+
+// The tuning a call runs with: the caller's, else (LV_AUTOTUNE) the handle's
+// autotuned setting, chosen on first use, else the defaults.
+lv_status resolve_tuning(lv_graph* g, const lv_params* params, Params& p)
+{
+    if (!params || params->tuning || !(params->flags & LV_AUTOTUNE)) return LV_OK;
+    if (!g->has_tuned) {
+        double ms = 0.0;
+        LV_TRY(autotune(g, p, &g->tuned, &ms));
+        g->has_tuned = true;
+    }
+    p.tune = make_tune(&g->tuned);
+    return LV_OK;
 }
 
 void fill_info(lv_level_info& li, const SweepOut& so, int32_t c, int32_t S)
@@ -1332,6 +1419,21 @@ lv_status lv_graph_create_batch(int32_t count, const int32_t* n, const int32_t* 
     return LV_OK;
 }
 
+lv_status lv_autotune(lv_graph* g, const lv_params* params, lv_tuning* out, double* est_ms)
+{
+    if (!g || !out) { set_error_msg("lv_autotune: null graph or out"); return LV_E_ARG; }
+    Params p;
+    LV_TRY(read_params(params, p));
+    lv_tuning t{};
+    double ms = 0.0;
+    LV_TRY(autotune(g, p, &t, &ms));
+    g->tuned = t;
+    g->has_tuned = true;
+    *out = t;
+    if (est_ms) *est_ms = ms;
+    return LV_OK;
+}
+
 lv_status lv_graph_destroy(lv_graph* g)
 {
     if (!g) return LV_E_ARG;
@@ -1361,6 +1463,7 @@ lv_status lv_louvain(lv_graph* g, const lv_params* params, lv_result** out)
     if (!g || !out) { set_error_msg("lv_louvain: null graph or out"); return LV_E_ARG; }
     Params p;
     LV_TRY(read_params(params, p));
+    LV_TRY(resolve_tuning(g, params, p));
     lv_result* r = new (std::nothrow) lv_result();
     if (!r) return LV_E_NOMEM;
     const bool keep = params && (params->flags & LV_KEEP_GRAPHS);
@@ -1441,6 +1544,24 @@ lv_status lv_result_graph_modularity(const lv_result* r, int32_t g, int64_t* q_i
     if (q_int) *q_int = gr->q_int;
     if (m) *m = gr->M;
     if (q) *q = gr->M > 0 ? (double)gr->q_int / ((double)gr->M * (double)gr->M) : 0.0;
+    return LV_OK;
+}
+
+lv_status lv_result_final_labels_all(const lv_result* r, int32_t* labels, lv_memkind kind)
+{
+    if (!r || !labels || (kind != LV_MEM_HOST && kind != LV_MEM_DEVICE)) return LV_E_ARG;
+    return copy_out(labels, r->final_labels.as<int32_t>(), r->n0, kind, nullptr);
+}
+
+lv_status lv_result_modularity_all(const lv_result* r, int64_t* q_int, int64_t* m, double* q)
+{
+    if (!r) return LV_E_ARG;
+    for (int32_t c = 0; c < r->G; ++c) {
+        const GraphResult& gr = r->graphs[c];
+        if (q_int) q_int[c] = gr.q_int;
+        if (m) m[c] = gr.M;
+        if (q) q[c] = gr.M > 0 ? (double)gr.q_int / ((double)gr.M * (double)gr.M) : 0.0;
+    }
     return LV_OK;
 }
 
@@ -1548,6 +1669,7 @@ lv_status lv_lpa_batch(lv_graph* g, const lv_params* params, int32_t* labels, lv
         return LV_E_ARG;
     Params p;
     LV_TRY(read_params(params, p));
+    LV_TRY(resolve_tuning(g, params, p));
     Workspace& ws = g->ws;
     HIP_TRY(ws.pos.ensure(sizeof(int32_t) * ((size_t)g->n + 1)));
     DevBuf out;
@@ -1577,6 +1699,7 @@ lv_status lv_lpa(lv_graph* g, const lv_params* params, int32_t* labels, lv_memki
     if (g->G != 1) { set_error_msg("lv_lpa takes a single-graph handle (see lv_lpa_batch)"); return LV_E_STATE; }
     Params p;
     LV_TRY(read_params(params, p));
+    LV_TRY(resolve_tuning(g, params, p));
     DevBuf out;
     HIP_TRY(out.ensure(sizeof(int32_t) * (size_t)std::max(g->n, 1)));
     SweepOut so;

@@ -187,6 +187,9 @@ hipError_t launch_class_entries(const int32_t* verts_sorted, const int32_t* star
 // sweep
 hipError_t launch_move_class(int cls, bool singleton, const MoveArgs& a, hipStream_t s);
 hipError_t launch_hub_clear(int32_t* table, int64_t slots, hipStream_t s);
+// bucketed mode, sweeps after the first: scatter the hubs' entries to the partition buckets
+hipError_t launch_hub_scatter(const MoveArgs& a, const HubArgs& h, hipStream_t s);
+// partition workgroups, merge and decision, global-table fallback
 hipError_t launch_hub_sweep(bool singleton, const MoveArgs& a, const HubArgs& h, hipStream_t s);
 hipError_t launch_pairs(int32_t n, const int32_t* comm, const int32_t* sigma, int2* cs, const SweepCtl* ctl,
                         hipStream_t s);

@@ -771,20 +771,21 @@ hipError_t launch_hub_clear(int32_t* table, int64_t slots, hipStream_t s)
     return hipGetLastError();
 }
 
+hipError_t launch_hub_scatter(const MoveArgs& a, const HubArgs& h, hipStream_t s)
+{
+    if (h.nhubs <= 0 || !h.bucketed || h.nsc <= 0) return hipSuccess;
+    if (h.sc_chunk == 1024) k_hub_scatter<256, 4><<<(unsigned)h.nsc, 256, 0, s>>>(a, h);
+    else if (h.sc_chunk == 2048) k_hub_scatter<256, 8><<<(unsigned)h.nsc, 256, 0, s>>>(a, h);
+    else k_hub_scatter<512, 8><<<(unsigned)h.nsc, 512, 0, s>>>(a, h);
+    return hipGetLastError();
+}
+
 hipError_t launch_hub_sweep(bool singleton, const MoveArgs& a, const HubArgs& h, hipStream_t s)
 {
     if (h.nhubs <= 0) return hipSuccess;
     if (h.bucketed) {
-        if (singleton) {
-            k_hub_part<true, false, BBS, 1><<<(unsigned)h.nblk, BBS, 0, s>>>(a, h);
-        } else {
-            if (h.nsc > 0) {
-                if (h.sc_chunk == 1024) k_hub_scatter<256, 4><<<(unsigned)h.nsc, 256, 0, s>>>(a, h);
-                else if (h.sc_chunk == 2048) k_hub_scatter<256, 8><<<(unsigned)h.nsc, 256, 0, s>>>(a, h);
-                else k_hub_scatter<512, 8><<<(unsigned)h.nsc, 512, 0, s>>>(a, h);
-            }
-            k_hub_part<false, true, BBS, BSLOTS><<<(unsigned)h.nblk, BBS, 0, s>>>(a, h);
-        }
+        if (singleton) k_hub_part<true, false, BBS, 1><<<(unsigned)h.nblk, BBS, 0, s>>>(a, h);
+        else k_hub_part<false, true, BBS, BSLOTS><<<(unsigned)h.nblk, BBS, 0, s>>>(a, h);
     } else if (singleton) {
         k_hub_part<true, false, PBS, 1><<<(unsigned)h.nblk, PBS, 0, s>>>(a, h);
     } else {

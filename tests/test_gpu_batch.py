@@ -126,3 +126,28 @@ def test_batch_rejects_bad_member():
     with pytest.raises(lvp.LvError) as ei:
         lvp.Graph.batch([good, oob])
     assert ei.value.status == 2
+
+
+def test_autotuned_results_equal_oracle():
+    g = graphgen.rmat(14, seed=12)
+    want = oracle.louvain(g)
+    with lvp.Graph.from_csr(g) as dg:
+        cfg, ms = lvp.autotune(dg)
+        say(f"autotuned {cfg} est {ms:.3f} ms")
+        assert ms > 0
+        check_graph(lvp.louvain(dg, autotuned=True), want, "autotuned")
+        l = lvp.lpa(dg, autotuned=True)
+    wl = oracle.lpa(g)
+    assert np.array_equal(l.labels, wl.labels)
+
+
+def test_batch_final_partition_accessors():
+    graphs = mixed_batch(5, 9)
+    with lvp.Graph.batch(graphs) as bg:
+        fp = lvp.louvain_final(bg, autotuned=True)
+    base = 0
+    for t, g in enumerate(graphs):
+        want = oracle.louvain(g)
+        assert np.array_equal(fp.labels[base:base + g.n], want.final_labels), g.name
+        assert (fp.q_int[t], fp.M[t], fp.q[t]) == (want.q_int, want.M, want.q), g.name
+        base += g.n
