@@ -139,6 +139,115 @@ def batch_leg(args, lvp, graphgen, np, torch):
     return out
 
 
+def serving_leg(args, lvp, graphgen, np, torch):
+    """Poisson trace of Louvain jobs replayed twice in real time: through a
+    FIFO loop that runs one graph per call (create from host memory, Louvain,
+    final labels) and through the continuous-batching server.  Latency is
+    arrival -> result; every job's partition must equal its graph's result
+    alone."""
+    import threading
+
+    t = time.time()
+    pool = graphgen.serving_pool(args.serve_pool, seed=5)
+    log(f"serving: pool of {len(pool)} graphs (n {min(g.n for g in pool)}..{max(g.n for g in pool)}, "
+        f"{sum(g.nnz for g in pool)} entries) generated in {time.time() - t:.1f}s")
+    # per-graph service time of one-graph-per-call, and each graph's partition alone
+    alone, svc = [], []
+    for g in pool:
+        with lvp.Graph.from_csr(g) as h:
+            lvp.louvain_final(h)
+    for g in pool:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        with lvp.Graph.from_csr(g) as h:
+            fp = lvp.louvain_final(h)
+        svc.append(time.perf_counter() - t0)
+        alone.append((fp.labels.copy(), int(fp.q_int[0])))
+    rng = np.random.default_rng(5)
+    J = args.serve_jobs
+    which = rng.integers(0, len(pool), size=J)
+    mean_svc = float(np.mean([svc[i] for i in which]))
+    rate = args.serve_load / mean_svc
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=J))
+    entries = [pool[i].nnz for i in which]
+    log(f"serving: {J} jobs, mean one-per-call service {mean_svc * 1e3:.2f} ms, Poisson rate {rate:.1f}/s "
+        f"({args.serve_load:.0%} of one-per-call capacity)")
+
+    def summarize(lat, span, same):
+        lat = np.asarray(lat) * 1e3
+        return {"jobs_per_s": round(J / span, 2), "p50_ms": round(float(np.percentile(lat, 50)), 2),
+                "p99_ms": round(float(np.percentile(lat, 99)), 2), "mean_ms": round(float(lat.mean()), 2),
+                "span_s": round(span, 2), "identical_partitions": same}
+
+    # FIFO, one graph per call
+    same = True
+    lat = np.zeros(J)
+    t0 = time.perf_counter()
+    for i in range(J):
+        now = time.perf_counter()
+        if now < t0 + arrivals[i]:
+            time.sleep(t0 + arrivals[i] - now)
+        with lvp.Graph.from_csr(pool[which[i]]) as h:
+            fp = lvp.louvain_final(h)
+        done = time.perf_counter()
+        lat[i] = done - (t0 + arrivals[i])
+        same &= bool(np.array_equal(fp.labels, alone[which[i]][0])) and int(fp.q_int[0]) == alone[which[i]][1]
+        if i % 200 == 0:
+            log(f"serving: fifo job {i}")
+    fifo = summarize(lat, time.perf_counter() - t0, same)
+    log(f"serving: one graph per call {fifo}")
+
+    # continuous batching server
+    srv = lvp.Server(max_jobs=args.serve_max_jobs)
+    tickets = [0] * J
+    submitted = [0.0] * J
+    ready = [threading.Event() for _ in range(J)]
+    t0 = time.perf_counter()
+
+    def submitter():
+        for i in range(J):
+            now = time.perf_counter()
+            if now < t0 + arrivals[i]:
+                time.sleep(t0 + arrivals[i] - now)
+            submitted[i] = time.perf_counter()
+            tickets[i] = srv.submit(pool[which[i]])
+            ready[i].set()
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    same = True
+    lat = np.zeros(J)
+    end = 0.0
+    for i in range(J):
+        ready[i].wait()
+        srv.wait(tickets[i])
+        labels, info = srv.result(tickets[i], pool[which[i]].n)
+        fin = submitted[i] + info["total_ms"] * 1e-3
+        end = max(end, fin)
+        lat[i] = fin - (t0 + arrivals[i])
+        same &= bool(np.array_equal(labels, alone[which[i]][0])) and int(info["q_int"]) == alone[which[i]][1]
+        if i % 200 == 0:
+            log(f"serving: server job {i}")
+    th.join()
+    stats = srv.stats()
+    srv.close()
+    batched = summarize(lat, end - t0, same)
+    batched["max_batch"] = int(stats["max_batch"])
+    batched["packed_levels"] = int(stats["steps"])
+    log(f"serving: continuous batching {batched}")
+    out = {"workload": f"{J} Louvain jobs, Poisson arrivals at {args.serve_load:.0%} of one-graph-per-call "
+                       f"capacity ({rate:.1f}/s); graphs from a pool of {len(pool)} R-MAT graphs, n log-uniform "
+                       "in [1e4, 4e6], edge factor uniform in {8..16}, unit weights, seed 5",
+           "mean_entries": round(float(np.mean(entries))), "one_graph_per_call": fifo,
+           "continuous_batching": batched,
+           "p99_speedup": round(fifo["p99_ms"] / batched["p99_ms"], 2) if batched["p99_ms"] > 0 else None,
+           "throughput_speedup": round(batched["jobs_per_s"] / fifo["jobs_per_s"], 2)}
+    if not (fifo["identical_partitions"] and batched["identical_partitions"]):
+        print("a served partition differs from the graph's partition alone", file=sys.stderr, flush=True)
+        sys.exit(1)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -153,6 +262,10 @@ def main():
     ap.add_argument("--batch-graphs", type=int, default=4096, help="graphs in the batch leg (0: skip it)")
     ap.add_argument("--batch-sample", type=int, default=256, help="graphs run one per call for the baseline")
     ap.add_argument("--batch-reps", type=int, default=3)
+    ap.add_argument("--serve-jobs", type=int, default=1000, help="jobs in the serving trace (0: skip it)")
+    ap.add_argument("--serve-pool", type=int, default=32, help="distinct graphs the jobs draw from")
+    ap.add_argument("--serve-load", type=float, default=0.8, help="arrival rate / one-per-call capacity")
+    ap.add_argument("--serve-max-jobs", type=int, default=64)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB before the steps (PMC calibration)")
     args = ap.parse_args()
@@ -290,6 +403,7 @@ def main():
     if not args.no_cpu_baseline or not args.no_parity:
         del adj, k, c, sigma
     batch = batch_leg(args, lvp, graphgen, np, torch) if args.batch_graphs > 0 else None
+    serving = serving_leg(args, lvp, graphgen, np, torch) if args.serve_jobs > 0 else None
 
     out = {
         "metric": METRIC,
@@ -323,6 +437,7 @@ def main():
         "phase_ms_per_step": {k_: round(v / K, 3) for k_, v in phases.items()},
         "kernels": kernels,
         "batch": batch,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
 

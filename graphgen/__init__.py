@@ -239,3 +239,30 @@ def batch_mix(count: int = 4096, seed: int = 4, n_lo: int = 1024, n_hi: int = 65
 
     with ThreadPoolExecutor(workers, initializer=init) as ex:
         return list(ex.map(make, specs))
+
+
+def serving_pool(count: int = 32, seed: int = 5, n_lo: int = 10_000, n_hi: int = 4_000_000,
+                 ef_lo: int = 8, ef_hi: int = 16):
+    """Graphs for the serving workload: R-MAT (0.57, 0.19, 0.19), vertex
+    counts log-uniform in [n_lo, n_hi], edge factor uniform in {ef_lo..ef_hi}
+    (n * ef samples), scale ceil(log2 n) with ids >= n dropped, unit weights.
+    Generated on host threads, one OpenMP thread each."""
+    rng = np.random.default_rng(seed)
+    specs = []
+    for t in range(count):
+        n = int(round(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi)))))
+        ef = int(rng.integers(ef_lo, ef_hi + 1))
+        specs.append((t, n, ef, seed * 1_000_003 + t))
+
+    def make(spec):
+        t, n, ef, gs = spec
+        scale = max(1, int(np.ceil(np.log2(n))))
+        g = rmat(scale, n=n, samples=n * ef, seed=gs)
+        g.name = f"serve{t}_n{n}_ef{ef}"
+        return g
+
+    from concurrent.futures import ThreadPoolExecutor
+
+    lib = _load()
+    with ThreadPoolExecutor(max(1, min(16, os.cpu_count() or 1)), initializer=lambda: lib.gg_set_threads(1)) as ex:
+        return list(ex.map(make, specs))

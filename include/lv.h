@@ -259,6 +259,78 @@ lv_status lv_lpa_batch(lv_graph* g, const lv_params* params, int32_t* labels, lv
 lv_status lv_modularity(lv_graph* g, const int32_t* labels, lv_memkind kind, int64_t* q_int,
                         int64_t* m, double* q);
 
+/* ---------------------------------------------------------------------------
+ * Serving loop (continuous batching).  A server owns a worker thread and a
+ * stream on the current device.  Jobs (CSR graphs, same conventions as
+ * lv_graph_create_csr) are submitted at any time and copied to host memory;
+ * at every level boundary the worker admits queued jobs in arrival order
+ * while their working-set estimates (72 B per entry + 96 B per vertex + 1
+ * MiB) fit the memory budget and the in-flight count fits max_jobs, packs
+ * the coarse graphs of the jobs that continue together with the level-0
+ * graphs of the admitted ones, and runs one Louvain level (Algorithm 3) for
+ * all of them in the same launches.  Each job keeps its own M, stopping rule
+ * and acceptance, so its partition equals lv_louvain's on its graph alone.
+ * Every server call is thread-safe; results are kept until lv_server_result.
+ * ------------------------------------------------------------------------- */
+typedef struct lv_server lv_server;
+
+typedef struct lv_server_config {
+    int64_t mem_budget;  /* bytes for the in-flight jobs' estimates; 0 = half the free device memory */
+    int32_t max_jobs;    /* in-flight jobs at most; 0 = 256                                           */
+    int32_t max_sweeps;  /* 0 = 20                                                                    */
+    int32_t max_levels;  /* 0 = 32                                                                    */
+    uint32_t flags;      /* LV_VALIDATE: check each job's CSR (symmetry included) at admission         */
+    const lv_tuning* tuning; /* NULL = defaults                                                      */
+} lv_server_config;
+
+#define LV_JOB_QUEUED 0
+#define LV_JOB_RUNNING 1
+#define LV_JOB_DONE 2
+
+typedef struct lv_job_info {
+    int32_t status;     /* lv_status of the job                                   */
+    int32_t n;          /* vertices                                               */
+    int32_t levels;     /* accepted levels                                        */
+    int32_t steps;      /* levels attempted (batch steps the job took part in)    */
+    int64_t q_int;      /* Q_int of the final partition                           */
+    int64_t m;          /* total volume M                                         */
+    double q;           /* Q_int / M^2                                            */
+    int64_t entries;    /* sum over its levels of CSR entries x sweeps            */
+    double queue_ms;    /* submit -> admission                                    */
+    double total_ms;    /* submit -> result ready                                 */
+} lv_job_info;
+
+typedef struct lv_server_stats {
+    int64_t submitted, completed;
+    int64_t steps;      /* packed levels run                                      */
+    int64_t max_batch;  /* most jobs in one packed level                          */
+    int64_t entries;    /* packed entries x sweeps executed                       */
+    int64_t queued, in_flight;
+    int64_t mem_in_use, mem_budget;
+} lv_server_stats;
+
+/* cfg may be NULL (defaults).  LV_E_STATE if the worker thread cannot start. */
+lv_status lv_server_create(const lv_server_config* cfg, lv_server** out);
+/* Copies the CSR (host or device memory) and queues the job; *ticket names it.
+   LV_E_TOO_LARGE if its estimate alone exceeds the budget.  Malformed input
+   is reported by the job's result (validation happens at admission). */
+lv_status lv_server_submit(lv_server* s, int32_t n, const int32_t* offsets, const int32_t* indices,
+                           const int32_t* weights, lv_memkind kind, uint64_t* ticket);
+/* *state = LV_JOB_QUEUED / RUNNING / DONE; LV_E_NOT_FOUND for an unknown ticket. */
+lv_status lv_server_poll(lv_server* s, uint64_t ticket, int32_t* state);
+/* Blocks until the job is done (timeout_ms < 0: no limit); LV_E_BUSY on timeout. */
+lv_status lv_server_wait(lv_server* s, uint64_t ticket, int64_t timeout_ms);
+/* For a done job: labels int32[n] (final partition, renumbered by smallest
+   member; may be NULL) and *info (may be NULL); then forgets the ticket.
+   Returns the job's status (its error text through lv_last_error). */
+lv_status lv_server_result(lv_server* s, uint64_t ticket, int32_t* labels, lv_memkind kind, lv_job_info* info);
+/* A queued job is dropped; a running one leaves at its next level boundary
+   with LV_E_CANCELLED (unless it finished there). */
+lv_status lv_server_cancel(lv_server* s, uint64_t ticket);
+lv_status lv_server_stats_get(lv_server* s, lv_server_stats* out);
+/* Cancels what is queued or running, joins the worker, frees everything. */
+lv_status lv_server_destroy(lv_server* s);
+
 #ifdef __cplusplus
 }
 #endif

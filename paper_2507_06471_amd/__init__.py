@@ -75,6 +75,24 @@ class lv_level_info(ctypes.Structure):
         return out
 
 
+class lv_server_config(ctypes.Structure):
+    _fields_ = [("mem_budget", ctypes.c_int64), ("max_jobs", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
+                ("max_levels", ctypes.c_int32), ("flags", ctypes.c_uint32), ("tuning", ctypes.POINTER(lv_tuning))]
+
+
+class lv_job_info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("n", ctypes.c_int32), ("levels", ctypes.c_int32),
+                ("steps", ctypes.c_int32), ("q_int", ctypes.c_int64), ("m", ctypes.c_int64), ("q", ctypes.c_double),
+                ("entries", ctypes.c_int64), ("queue_ms", ctypes.c_double), ("total_ms", ctypes.c_double)]
+
+
+class lv_server_stats(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int64) for f in ("submitted", "completed", "steps", "max_batch", "entries", "queued",
+                                              "in_flight", "mem_in_use", "mem_budget")]
+
+
+JOB_QUEUED, JOB_RUNNING, JOB_DONE = 0, 1, 2
+
 # name -> (restype, argtypes); every entry point declared in include/lv.h
 SIGNATURES = {
     "lv_params_default": (None, [ctypes.POINTER(lv_params)]),
@@ -112,6 +130,15 @@ SIGNATURES = {
     "lv_result_modularity_all": (ctypes.c_int, [_vp, _i64p, _i64p, ctypes.POINTER(ctypes.c_double)]),
     "lv_lpa_batch": (ctypes.c_int, [_vp, ctypes.POINTER(lv_params), _vp, ctypes.c_int, _i32p, _i64p, _i64p,
                                     _i64p, ctypes.c_int32]),
+    "lv_server_create": (ctypes.c_int, [ctypes.POINTER(lv_server_config), ctypes.POINTER(_vp)]),
+    "lv_server_submit": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, _vp, _vp, ctypes.c_int,
+                                        ctypes.POINTER(ctypes.c_uint64)]),
+    "lv_server_poll": (ctypes.c_int, [_vp, ctypes.c_uint64, _i32p]),
+    "lv_server_wait": (ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.c_int64]),
+    "lv_server_result": (ctypes.c_int, [_vp, ctypes.c_uint64, _vp, ctypes.c_int, ctypes.POINTER(lv_job_info)]),
+    "lv_server_cancel": (ctypes.c_int, [_vp, ctypes.c_uint64]),
+    "lv_server_stats_get": (ctypes.c_int, [_vp, ctypes.POINTER(lv_server_stats)]),
+    "lv_server_destroy": (ctypes.c_int, [_vp]),
     "lv_modularity": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _i64p, _i64p, ctypes.POINTER(ctypes.c_double)]),
 }
 
@@ -452,3 +479,78 @@ def modularity(graph: Graph, labels):
     _check(lib.lv_modularity(graph.handle, pl, kind, ctypes.byref(qi), ctypes.byref(m), ctypes.byref(q)),
            "lv_modularity")
     return qi.value, m.value, q.value
+
+
+class Server:
+    """Continuous-batching Louvain server (lv_server_*).  Thread-safe: submit
+    from any thread; results are collected per ticket."""
+
+    def __init__(self, mem_budget: int = 0, max_jobs: int = 0, max_sweeps: int = 0, max_levels: int = 0,
+                 validate: bool = True, tuning: Optional[dict] = None):
+        lib = load_library()
+        cfg = lv_server_config(mem_budget, max_jobs, max_sweeps, max_levels, LV_VALIDATE if validate else 0)
+        self._tuning = None
+        if tuning:
+            self._tuning = lv_tuning(**tuning)
+            cfg.tuning = ctypes.pointer(self._tuning)
+        h = _vp()
+        _check(lib.lv_server_create(ctypes.byref(cfg), ctypes.byref(h)), "lv_server_create")
+        self._h = h
+
+    def submit(self, g) -> int:
+        """Queue a ``graphgen.CSR``-like graph (host arrays); returns its ticket."""
+        lib = load_library()
+        off = np.ascontiguousarray(g.offsets, dtype=np.int32)
+        idx = np.ascontiguousarray(g.indices, dtype=np.int32)
+        w = None if g.weights is None else np.ascontiguousarray(g.weights, dtype=np.int32)
+        t = ctypes.c_uint64()
+        _check(lib.lv_server_submit(self._h, int(g.n), off.ctypes.data, idx.ctypes.data,
+                                    None if w is None else w.ctypes.data, LV_MEM_HOST, ctypes.byref(t)),
+               "lv_server_submit")
+        return t.value
+
+    def poll(self, ticket: int) -> int:
+        st = ctypes.c_int32()
+        _check(load_library().lv_server_poll(self._h, ticket, ctypes.byref(st)), "lv_server_poll")
+        return st.value
+
+    def wait(self, ticket: int, timeout_ms: int = -1) -> bool:
+        st = load_library().lv_server_wait(self._h, ticket, timeout_ms)
+        if st == 8:  # LV_E_BUSY: timed out
+            return False
+        _check(st, "lv_server_wait")
+        return True
+
+    def result(self, ticket: int, n: int):
+        """(labels, info dict) of a finished job; raises LvError with the job's status."""
+        lib = load_library()
+        labels = np.empty(max(n, 1), dtype=np.int32)
+        info = lv_job_info()
+        st = lib.lv_server_result(self._h, ticket, labels.ctypes.data, LV_MEM_HOST, ctypes.byref(info))
+        _check(st, "lv_server_result")
+        return labels[:n], {name: getattr(info, name) for name, _ in lv_job_info._fields_}
+
+    def cancel(self, ticket: int):
+        _check(load_library().lv_server_cancel(self._h, ticket), "lv_server_cancel")
+
+    def stats(self) -> dict:
+        st = lv_server_stats()
+        _check(load_library().lv_server_stats_get(self._h, ctypes.byref(st)), "lv_server_stats_get")
+        return {name: getattr(st, name) for name, _ in lv_server_stats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().lv_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

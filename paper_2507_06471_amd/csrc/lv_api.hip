@@ -1725,3 +1725,5 @@ lv_status lv_lpa(lv_graph* g, const lv_params* params, int32_t* labels, lv_memki
 }
 
 }  // extern "C"
+
+#include "lv_server.inc"
