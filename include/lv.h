@@ -111,7 +111,10 @@ typedef struct lv_params {
 
 #define LV_KERNEL_SLOTS 15
 
-/* Per-level statistics; times are milliseconds from HIP events (LV_TIMING). */
+/* Per-level statistics; times are milliseconds from HIP events.  sweep_ms,
+   renumber_ms and aggregate_ms are always measured (events around each
+   phase); move_ms and the per-kernel arrays need LV_TIMING, which also
+   launches the sweeps one kernel at a time. */
 typedef struct lv_level_info {
     int32_t n;          /* vertices of this level's graph                        */
     int32_t n_next;     /* communities after renumbering                          */

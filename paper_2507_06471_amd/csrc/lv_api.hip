@@ -98,6 +98,7 @@ struct Workspace {
     DevBuf keys, keys_alt, vals, vals_alt, head;
     DevBuf g_off[2], g_idx[2], g_w[2], g_k[2], g_gid[2];
     DevBuf hub_table, hub_meta, hub_part, hub_rows, hub_cnt, hub_bucket, hub_bucket_w;
+    DevBuf rows;  // per-level row descriptors of the class-sorted vertices
     DevBuf k64;
     // per-graph state of a level (G entries) and sweep control
     DevBuf ctl, gdone, gsweeps, gmoves, gactive, gsum, gsq, gmeta, segs;
@@ -522,6 +523,8 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
     for (int c = NUM_CLS - 1; c >= 0; --c)
         if (start[c] < 0) start[c] = start[c + 1];
     const int32_t active = n - start[CLS_G8];  // vertices with at least one entry
+    HIP_TRY(ws.rows.ensure(sizeof(int4) * (size_t)std::max(active, 1)));
+    HIP_TRY(launch_row_descriptors(vert_sorted + start[CLS_G8], active, G.off, G.k, ws.rows.as<int4>(), s));
 
     HubPlan hubs;
     LV_TRY(plan_hubs(g, G, vert_sorted + start[CLS_HUB], n - start[CLS_HUB], p.tune, hubs));
@@ -569,6 +572,7 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
         if (e) { e->assign(2 * NUM_CLS + 4, nullptr); HIP_TRY(tm.mark(&(*e)[2 * NUM_CLS])); }
         for (int c = CLS_G8; c < CLS_HUB; ++c) {
             a.verts = vert_sorted + start[c];
+            a.rows = ws.rows.as<int4>() + (start[c] - start[CLS_G8]);
             a.dec = dec_all + start[c];
             a.nverts = start[c + 1] - start[c];
             if (a.nverts == 0) continue;
@@ -577,15 +581,17 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
             if (e) HIP_TRY(tm.mark(&(*e)[2 * c + 1]));
         }
         if (hubs.nhubs > 0) {
+            const hipStream_t hs = s;
             a.verts = vert_sorted + start[CLS_HUB];
+            a.rows = nullptr;
             a.dec = dec_all + start[CLS_HUB];
             a.nverts = hubs.nhubs;
             if (e) HIP_TRY(tm.mark(&(*e)[2 * CLS_HUB]));
             if (!singleton && hubs.args.bucketed && hubs.args.nsc > 0) {
-                HIP_TRY(launch_hub_scatter(a, hubs.args, s));
+                HIP_TRY(launch_hub_scatter(a, hubs.args, hs));
                 if (e) HIP_TRY(tm.mark(&(*e)[2 * NUM_CLS + 3]));
             }
-            HIP_TRY(launch_hub_sweep(singleton, a, hubs.args, s));
+            HIP_TRY(launch_hub_sweep(singleton, a, hubs.args, hs));
             if (e) HIP_TRY(tm.mark(&(*e)[2 * CLS_HUB + 1]));
         }
         if (e) HIP_TRY(tm.mark(&(*e)[2 * NUM_CLS + 1]));
@@ -617,13 +623,19 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
                 if (e != hipSuccess) { set_error("hipGraphInstantiate", e); st = from_hip(e); }
             }
         }
+        Timer ph;
+        ph.s = s;
+        hipEvent_t p0{}, p1{};
         if (st == LV_OK) {
+            HIP_TRY(ph.mark(&p0));
             for (int32_t sw = 1; sw <= S && st == LV_OK; ++sw) {
                 hipError_t e = hipGraphLaunch(ex[sw == 1 ? 0 : 1], s);
                 if (e != hipSuccess) { set_error("hipGraphLaunch", e); st = from_hip(e); }
             }
+            if (st == LV_OK) HIP_TRY(ph.mark(&p1));
         }
         hipError_t es = hipStreamSynchronize(s);
+        if (st == LV_OK && es == hipSuccess) out.sweep_ms = elapsed(p0, p1);
         for (int q = 0; q < 2; ++q) {
             if (ex[q]) (void)hipGraphExecDestroy(ex[q]);
             if (gr[q]) (void)hipGraphDestroy(gr[q]);
@@ -632,7 +644,16 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
         HIP_TRY(es);
     } else {
         ev.resize(S);
+        Timer ph;
+        ph.s = s;
+        hipEvent_t p0{}, p1{};
+        if (!timing) HIP_TRY(ph.mark(&p0));
         for (int32_t sw = 1; sw <= S; ++sw) LV_TRY(launch_sweep(sw == 1, timing ? &ev[sw - 1] : nullptr));
+        if (!timing) {
+            HIP_TRY(ph.mark(&p1));
+            HIP_TRY(hipStreamSynchronize(s));
+            out.sweep_ms = elapsed(p0, p1);
+        }
     }
     // per-graph sweep and move counts (one host round trip per level)
     uint32_t* h_moves = (uint32_t*)g->pinned;
@@ -990,7 +1011,7 @@ lv_status louvain_impl(lv_graph* g, const Params& p, bool keep_graphs, lv_result
     DevBuf Mbuf;
     int slot = 0;
     Timer tm;
-    tm.on = (p.flags & LV_TIMING) != 0;
+    tm.on = true;  // phase times (renumber, aggregate) are always measured
     tm.s = s;
     for (;;) {
         SweepOut so;
@@ -1138,7 +1159,7 @@ lv_status lpa_impl(lv_graph* g, const Params& p, int32_t* out_dev, SweepOut& so,
     LevelGraph G = level0(g);
     LV_TRY(run_sweeps(g, G, MODE_LPA, p, nullptr, so));
     Timer tm;
-    tm.on = (p.flags & LV_TIMING) != 0;
+    tm.on = true;
     tm.s = s;
     hipEvent_t t0{}, t1{};
     if (tm.on) HIP_TRY(tm.mark(&t0));

@@ -51,6 +51,7 @@ struct MoveArgs {
     const int32_t* gdone;   // per graph: 1 = stopped for the rest of this level
     const SweepCtl* ctl;    // sweep counter / early exit
     const int32_t* verts;   // vertices of this class
+    const int4* rows;       // per listed vertex: (vertex, row begin, row end, degree)
     int32_t nverts;
     int32_t mode;           // MODE_LOUVAIN / MODE_LPA
     int32_t* dec;           // decision per listed vertex: target community or -1
@@ -177,6 +178,9 @@ hipError_t launch_classify(int32_t n, const int32_t* off, const int32_t* bounds,
                            int32_t* vert, hipStream_t s);
 
 hipError_t launch_class_starts(const uint32_t* cls_sorted, int32_t n, int32_t* start, hipStream_t s);
+// rows[t] = (v, off[v], off[v+1], k[v]) for v = verts[t], t < m
+hipError_t launch_row_descriptors(const int32_t* verts, int32_t m, const int32_t* off, const int32_t* k, int4* rows,
+                                  hipStream_t s);
 hipError_t launch_gather_rows(const int32_t* verts, int32_t m, const int32_t* off, int32_t* beg, int32_t* len,
                               hipStream_t s);
 

@@ -85,6 +85,14 @@ __global__ __launch_bounds__(256) void k_class_entries(const int32_t* verts, int
     if (threadIdx.x == 0 && s) atomicAdd(out, s);
 }
 
+__global__ void k_row_descriptors(const int32_t* verts, int32_t m, const int32_t* off, const int32_t* k, int4* rows)
+{
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < m; t += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t v = verts[t];
+        rows[t] = make_int4(v, off[v], off[v + 1], k[v]);
+    }
+}
+
 __global__ void k_gather_rows(const int32_t* verts, int32_t m, const int32_t* off, int32_t* beg, int32_t* len)
 {
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < m; t += (int64_t)gridDim.x * blockDim.x) {
@@ -277,13 +285,13 @@ __global__ __launch_bounds__(BS) void k_move(MoveArgs a)
     const int g = threadIdx.x / G, lane = threadIdx.x % G;
     const int64_t vi = (int64_t)blockIdx.x * NG + g;
     const bool has = vi < a.nverts;
-    const int32_t i0 = has ? a.verts[vi] : 0;
-    const bool live = has && !vertex_frozen(a, i0);
-    const int32_t i = i0;
-    const int32_t beg = live ? a.off[i] : 0, end = live ? a.off[i + 1] : 0;
+    const int4 row = has ? a.rows[vi] : make_int4(0, 0, 0, 0);
+    const int32_t i = row.x;
+    const bool live = has && !vertex_frozen(a, i);
+    const int32_t beg = live ? row.y : 0, end = live ? row.z : 0;
     const int2 self = live ? a.cs[i] : make_int2(0, 0);
     const int32_t A = self.x;
-    const int64_t ki = live ? a.k[i] : 0;
+    const int64_t ki = live ? row.w : 0;
     const int64_t M = live ? vertex_M(a, i) : 0;
     int64_t best_s = INT64_MIN;
     int32_t best_c = INT32_MAX, w_own = 0;
@@ -734,6 +742,13 @@ hipError_t launch_class_entries(const int32_t* verts_sorted, const int32_t* star
         k_class_entries<<<grid_for(hi - lo, 256, 4096), 256, 0, s>>>(verts_sorted, lo, hi, off,
                                                                      (unsigned long long*)(out + c));
     }
+    return hipGetLastError();
+}
+hipError_t launch_row_descriptors(const int32_t* verts, int32_t m, const int32_t* off, const int32_t* k, int4* rows,
+                                  hipStream_t s)
+{
+    if (m <= 0) return hipSuccess;
+    k_row_descriptors<<<LV_GRID(m)>>>(verts, m, off, k, rows);
     return hipGetLastError();
 }
 hipError_t launch_gather_rows(const int32_t* verts, int32_t m, const int32_t* off, int32_t* beg, int32_t* len,
