@@ -16,7 +16,8 @@
 //   L <= 128    a wavefront, <= 256 slots
 //   L <= 512    a 256-thread workgroup, <= 1024 slots
 //   L <= 2048   a 512-thread workgroup, <= 4096 slots
-//   L <= 4096   a 512-thread workgroup, <= 8192 compact slots (64 KiB)
+//   L <= 4096   a 512-thread workgroup, <= 4096 slots (load up to 1: at most L
+//               distinct communities, and these rows mostly hold ~2300 entries)
 //   L >  4096   P = ceil(L / part_keys) 1024-thread workgroups per vertex;
 //               workgroup p aggregates the communities of hash partition p in
 //               an LDS table; partial results are merged per vertex, and all P
@@ -270,7 +271,8 @@ __device__ __forceinline__ void scan_table(const MoveArgs& a, const int32_t* key
 }
 
 // One group of G lanes per vertex (G <= BS); LDS table of up to SLOTS slots.
-template <int BS, int G, int SLOTS, bool SINGLETON, bool SIG>
+// (CLS only names the instantiation, so each degree class has its own kernel symbol)
+template <int CLS, int BS, int G, int SLOTS, bool SINGLETON, bool SIG>
 __global__ __launch_bounds__(BS) void k_move(MoveArgs a)
 {
     constexpr int NG = BS / G;
@@ -332,14 +334,14 @@ __global__ __launch_bounds__(BS) void k_move(MoveArgs a)
     }
 }
 
-template <int BS, int G, int SLOTS, bool SIG>
+template <int CLS, int BS, int G, int SLOTS, bool SIG>
 hipError_t launch_move_t(bool singleton, const MoveArgs& a, hipStream_t s)
 {
     if (a.nverts <= 0) return hipSuccess;
     constexpr int NG = BS / G;
     const unsigned grid = (unsigned)((a.nverts + NG - 1) / NG);
-    if (singleton) k_move<BS, G, SLOTS, true, false><<<grid, BS, 0, s>>>(a);
-    else k_move<BS, G, SLOTS, false, SIG><<<grid, BS, 0, s>>>(a);
+    if (singleton) k_move<CLS, BS, G, SLOTS, true, false><<<grid, BS, 0, s>>>(a);
+    else k_move<CLS, BS, G, SLOTS, false, SIG><<<grid, BS, 0, s>>>(a);
     return hipGetLastError();
 }
 
@@ -762,12 +764,12 @@ hipError_t launch_gather_rows(const int32_t* verts, int32_t m, const int32_t* of
 hipError_t launch_move_class(int cls, bool singleton, const MoveArgs& a, hipStream_t s)
 {
     switch (cls) {
-    case CLS_G8: return launch_move_t<256, 8, 16, true>(singleton, a, s);
-    case CLS_G32: return launch_move_t<256, 32, 64, true>(singleton, a, s);
-    case CLS_G64: return launch_move_t<256, 64, 256, true>(singleton, a, s);
-    case CLS_B256: return launch_move_t<256, 256, 1024, true>(singleton, a, s);
-    case CLS_B512: return launch_move_t<512, 512, 4096, true>(singleton, a, s);
-    case CLS_B4K: return launch_move_t<512, 512, 8192, false>(singleton, a, s);
+    case CLS_G8: return launch_move_t<CLS_G8, 256, 8, 16, true>(singleton, a, s);
+    case CLS_G32: return launch_move_t<CLS_G32, 256, 32, 64, true>(singleton, a, s);
+    case CLS_G64: return launch_move_t<CLS_G64, 256, 64, 256, true>(singleton, a, s);
+    case CLS_B256: return launch_move_t<CLS_B256, 256, 256, 1024, true>(singleton, a, s);
+    case CLS_B512: return launch_move_t<CLS_B512, 512, 512, 4096, true>(singleton, a, s);
+    case CLS_B4K: return launch_move_t<CLS_B4K, 512, 512, 4096, true>(singleton, a, s);
     default: return hipErrorInvalidValue;
     }
 }
