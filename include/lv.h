@@ -86,7 +86,7 @@ typedef struct lv_result lv_result; /* per-level labels and statistics, library-
 typedef struct lv_tuning {
     int32_t sub_max;   /* L <= sub_max: a sub-wave group per vertex (power of 2, 2..64)  */
     int32_t wave_max;  /* L <= wave_max: one wavefront per vertex                          */
-    int32_t block_max; /* L <= block_max: one workgroup per vertex, LDS table (<= 4096)    */
+    int32_t block_max; /* L <= block_max: one workgroup per vertex, LDS table (<= 3584)    */
                        /* L >  block_max: ceil(L / part_keys) workgroups per vertex, each  */
                        /* aggregating one hash partition of the communities in LDS         */
     int32_t part_keys;  /* expected communities per partition workgroup (clamped to       */
@@ -132,7 +132,7 @@ typedef struct lv_level_info {
     /* Per move kernel (LV_TIMING): slot 2*(class-1) + (1 for the first sweep
        of a level, where every community is a single vertex); classes 1..6 =
        8-lane, 32-lane, wavefront, 256-thread, 512-thread (<= 2048 entries)
-       and 512-thread compact (<= 4096) workgroup tables, 7 = partition
+       and 512-thread (<= 3584) workgroup tables, 7 = partition
        workgroups (with their merge and fallback kernels); slot 14 = the
        bucketed mode's scatter pass, which then carries class 7's bytes.
        Bytes count each array element a kernel needs once: indices (and

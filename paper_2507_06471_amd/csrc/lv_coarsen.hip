@@ -43,29 +43,68 @@ __global__ void k_coarse_degree(int32_t n, const int32_t* comm, const int32_t* f
         }
 }
 
-// keys/vals per entry; sigma_in[g] += weight of graph g's entries inside one community
+// keys/vals per entry; sigma_in[g] += weight of graph g's entries inside one community.
+// Merge-path tiles as in for_tile_entries, with the tile's indices and weights
+// loaded into LDS and its keys and weights stored from LDS, both coalesced.
 __global__ __launch_bounds__(TILE_BS) void k_build_keys(int32_t n, const int32_t* off, const int32_t* idx,
                                                          const int32_t* w, int64_t nnz, const int32_t* labels,
                                                          int colbits, uint64_t* keys, int32_t* vals,
                                                          const int32_t* gid, unsigned long long* sigma_in)
 {
+    constexpr int T = TILE_BS * TILE_IT;
+    __shared__ int32_t s_off[T + 2];
+    __shared__ int64_t s_x[2];
+    __shared__ int32_t s_j[T];
+    __shared__ int32_t s_w[T];
+    __shared__ uint64_t s_key[T];
+    const int64_t total = (int64_t)n + nnz;
+    const int64_t d0 = (int64_t)blockIdx.x * T;
+    const int64_t d1 = d0 + T < total ? d0 + T : total;
+    if (threadIdx.x < 2) s_x[threadIdx.x] = mp_rows(off, n, threadIdx.x ? d1 : d0);
+    __syncthreads();
+    const int64_t x0 = s_x[0], x1 = s_x[1];
+    const int64_t y0 = d0 - x0, y1 = d1 - x1;
+    const int64_t last = x1 + 1 < n ? x1 + 1 : n;
+    const int64_t rows = last - x0 + 1;
+    const int32_t ne = (int32_t)(y1 - y0);
+    for (int64_t t = threadIdx.x; t < rows; t += TILE_BS) s_off[t] = off[x0 + t];
+    for (int32_t q = threadIdx.x; q < ne; q += TILE_BS) {
+        s_j[q] = idx[y0 + q];
+        s_w[q] = w ? w[y0 + q] : 1;
+    }
+    __syncthreads();
     int32_t g_cur = -1;
     unsigned long long s = 0;
-    for_tile_entries<TILE_BS, TILE_IT>(off, n, nnz, [&](int32_t r, int64_t e) {
-        const uint32_t a = (uint32_t)labels[r], b = (uint32_t)labels[idx[e]];
-        const int32_t wv = w ? w[e] : 1;
-        keys[e] = ((uint64_t)a << colbits) | (uint64_t)b;
-        vals[e] = wv;
-        if (a == b) {
-            const int32_t gg = gid ? gid[r] : 0;
-            if (gg != g_cur) {
-                if (g_cur >= 0 && s) atomicAdd(&sigma_in[g_cur], s);
-                g_cur = gg;
-                s = 0;
-            }
-            s += (unsigned long long)wv;
+    const int32_t q0 = threadIdx.x * TILE_IT;
+    if (q0 < ne) {
+        int64_t lo = 0, hi = rows;  // row of entry y0 + q0: last r with off[r] <= y0 + q0
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) / 2;
+            if ((int64_t)s_off[mid] <= y0 + q0) lo = mid + 1; else hi = mid;
         }
-    });
+        int64_t r = x0 + lo - 1;
+        for (int j = 0; j < TILE_IT && q0 + j < ne; ++j) {
+            const int64_t e = y0 + q0 + j;
+            while ((int64_t)s_off[r + 1 - x0] <= e) ++r;
+            const uint32_t a = (uint32_t)labels[r], b = (uint32_t)labels[s_j[q0 + j]];
+            const int32_t wv = s_w[q0 + j];
+            s_key[q0 + j] = ((uint64_t)a << colbits) | (uint64_t)b;
+            if (a == b) {
+                const int32_t gg = gid ? gid[r] : 0;
+                if (gg != g_cur) {
+                    if (g_cur >= 0 && s) atomicAdd(&sigma_in[g_cur], s);
+                    g_cur = gg;
+                    s = 0;
+                }
+                s += (unsigned long long)wv;
+            }
+        }
+    }
+    __syncthreads();
+    for (int32_t q = threadIdx.x; q < ne; q += TILE_BS) {
+        keys[y0 + q] = s_key[q];
+        vals[y0 + q] = s_w[q];
+    }
     const bool valid = g_cur >= 0 && s != 0;
     wave_grouped_add<unsigned long long, unsigned long long>(sigma_in, valid ? g_cur : 0, s, valid);
 }
@@ -76,30 +115,46 @@ __global__ void k_segment_heads(const uint64_t* keys, int64_t n, int32_t* head)
         head[e] = (e == 0 || keys[e] != keys[e - 1]) ? 1 : 0;
 }
 
-// Sum the weights of each run of equal keys.  Thread t owns SR_IT consecutive
-// entries; a run wholly inside one thread is stored directly, a run crossing
-// a thread boundary is added atomically, one atomic per distinct run per
-// wavefront.  pos = exclusive scan of the head flags (output slot of a run).
+// Sum the weights of each run of equal keys.  A workgroup stages its tile of
+// 256 * SR_IT keys and weights in LDS (coalesced loads, plus the keys just
+// before and after the tile); thread t then owns SR_IT consecutive entries.
+// A run wholly inside one thread is stored directly, a run crossing a thread
+// boundary is added atomically, one atomic per distinct run per wavefront.
+// pos = exclusive scan of the head flags (output slot of a run).  Keys use at
+// most 62 bits, so all-ones marks "no key".
 constexpr int SR_IT = 8;
+constexpr int SR_TILE = 256 * SR_IT;
 __global__ __launch_bounds__(256) void k_segment_reduce(const uint64_t* keys, const int32_t* vals, const int32_t* pos,
                                                         int64_t n, int colbits, int32_t* idx2, int32_t* w2,
                                                         uint64_t* keys2)
 {
+    __shared__ uint64_t s_k[SR_TILE + 2];  // s_k[q + 1] = key of tile entry q
+    __shared__ int32_t s_v[SR_TILE];
     const uint64_t cmask = (1ull << colbits) - 1ull;
-    const int64_t base = ((int64_t)blockIdx.x * 256 + threadIdx.x) * SR_IT;
-    const int64_t end = base + SR_IT < n ? base + SR_IT : n;
+    const uint64_t NONE = ~0ull;
+    const int64_t tile0 = (int64_t)blockIdx.x * SR_TILE;
+    const int32_t cnt = (int32_t)(n - tile0 < SR_TILE ? n - tile0 : SR_TILE);
+    for (int32_t q = threadIdx.x; q < cnt; q += 256) {
+        s_k[q + 1] = keys[tile0 + q];
+        s_v[q] = vals[tile0 + q];
+    }
+    if (threadIdx.x == 0) s_k[0] = tile0 > 0 ? keys[tile0 - 1] : NONE;
+    if (threadIdx.x == 1) s_k[cnt + 1] = tile0 + cnt < n ? keys[tile0 + cnt] : NONE;
+    __syncthreads();
+    const int32_t q0 = threadIdx.x * SR_IT;
+    const int32_t q1 = q0 + SR_IT < cnt ? q0 + SR_IT : cnt;
     int64_t o_first = 0, o_last = 0;
     int32_t s_first = 0, s_last = 0;
     bool a_first = false, a_last = false;
-    for (int64_t e = base; e < end;) {
-        const uint64_t key = keys[e];
-        const bool head = e == 0 || keys[e - 1] != key;
-        const int64_t o = (int64_t)pos[e] + (head ? 1 : 0) - 1;
+    for (int32_t q = q0; q < q1;) {
+        const uint64_t key = s_k[q + 1];
+        const bool head = s_k[q] != key;
         int32_t sum = 0;
-        int64_t e2 = e;
-        while (e2 < end && keys[e2] == key) { sum += vals[e2]; ++e2; }
+        int32_t q2 = q;
+        while (q2 < q1 && s_k[q2 + 1] == key) { sum += s_v[q2]; ++q2; }
+        const int64_t o = (int64_t)pos[tile0 + q] + (head ? 1 : 0) - 1;
         if (head) { idx2[o] = (int32_t)(key & cmask); keys2[o] = key; }
-        const bool cont_next = e2 == end && end < n && keys[end] == key;
+        const bool cont_next = q2 == q1 && s_k[q1 + 1] == key;
         if (head && !cont_next) {
             w2[o] = sum;
         } else if (!head) {  // continues from the previous thread (only the first run can)
@@ -107,7 +162,7 @@ __global__ __launch_bounds__(256) void k_segment_reduce(const uint64_t* keys, co
         } else {             // starts here and continues into the next thread
             a_last = true; o_last = o; s_last = sum;
         }
-        e = e2;
+        q = q2;
     }
     wave_grouped_add<int32_t, int32_t>(w2, o_first, s_first, a_first);
     wave_grouped_add<int32_t, int32_t>(w2, o_last, s_last, a_last);
@@ -244,7 +299,7 @@ hipError_t launch_segment_reduce(const uint64_t* keys, const int32_t* vals, cons
                                  int32_t* idx2, int32_t* w2, uint64_t* keys2, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    k_segment_reduce<<<(unsigned)((n + 256 * SR_IT - 1) / (256 * SR_IT)), 256, 0, s>>>(keys, vals, pos, n, colbits,
+    k_segment_reduce<<<(unsigned)((n + SR_TILE - 1) / SR_TILE), 256, 0, s>>>(keys, vals, pos, n, colbits,
                                                                                        idx2, w2, keys2);
     return hipGetLastError();
 }

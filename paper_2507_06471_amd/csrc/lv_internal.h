@@ -27,7 +27,9 @@ enum MoveClass : int {
     NUM_CLS = 8
 };
 // Largest L each class can hold (table load factor <= 1/2).
-constexpr int32_t CLS_CAP[NUM_CLS] = {0, 8, 32, 128, 512, 2048, 4096, INT32_MAX};
+// row-length caps of the classes; the 4096-slot table of the last workgroup
+// class is kept at load <= 7/8
+constexpr int32_t CLS_CAP[NUM_CLS] = {0, 8, 32, 128, 512, 2048, 3584, INT32_MAX};
 
 // Device-side sweep control of one level: completed sweeps and whether every
 // graph of the level has stopped (kernels of later sweeps then exit early).

@@ -16,9 +16,8 @@
 //   L <= 128    a wavefront, <= 256 slots
 //   L <= 512    a 256-thread workgroup, <= 1024 slots
 //   L <= 2048   a 512-thread workgroup, <= 4096 slots
-//   L <= 4096   a 512-thread workgroup, <= 4096 slots (load up to 1: at most L
-//               distinct communities, and these rows mostly hold ~2300 entries)
-//   L >  4096   P = ceil(L / part_keys) 1024-thread workgroups per vertex;
+//   L <= 3584   a 512-thread workgroup, 4096 slots (load at most 7/8)
+//   L >  3584   P = ceil(L / part_keys) workgroups per vertex;
 //               workgroup p aggregates the communities of hash partition p in
 //               an LDS table; partial results are merged per vertex, and all P
 //               workgroups of a vertex run on one XCD (shared L2).  Two modes:
@@ -345,7 +344,7 @@ hipError_t launch_move_t(bool singleton, const MoveArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
-// ------------------------------------------------------------------ partitioned path (L > 4096)
+// ------------------------------------------------------------------ partitioned path (L > block_max)
 constexpr int PBS = 1024;               // compact partition workgroups and the scatter pass
 constexpr int PSLOTS_COMPACT = 16384;  // 8-byte slots (key, weight): 128 KiB
 constexpr int BBS = 256;               // bucketed partition workgroups

@@ -105,7 +105,7 @@ hipError_t scan_exclusive_t(const T* in, T* out, int64_t n, T* total, char* tmp,
 }
 
 // ------------------------------------------------------------------ radix sort (K10)
-constexpr int RADIX_IT = 16;
+constexpr int RADIX_IT = 8;
 constexpr int64_t RADIX_TILE = 256 * RADIX_IT;
 
 // mask of lanes (among `active`) whose 8-bit digit equals the calling lane's
@@ -140,23 +140,57 @@ __global__ __launch_bounds__(256) void k_radix_hist(const K* keys, int64_t n, in
     counts[(int64_t)threadIdx.x * nblocks + blockIdx.x] = (int32_t)h[threadIdx.x];
 }
 
+// Stable scatter of one tile by the current digit.  The tile is first ranked
+// and reordered by digit in LDS (stable: tile order within a digit), then
+// written out so that each digit's run of the tile lands contiguously at its
+// global offset.  counts/offsets are digit-major: offsets[d * nblocks + b] is
+// where tile b's elements with digit d start.
 template <typename K>
 __global__ __launch_bounds__(256) void k_radix_scatter(const K* keys, const int32_t* vals, K* keys_out, int32_t* vals_out,
                                                        int64_t n, int shift, const int32_t* offsets, int nblocks)
 {
-    __shared__ uint32_t s_base[256];
+    __shared__ K s_key[RADIX_TILE];
+    __shared__ int32_t s_val[RADIX_TILE];
+    __shared__ uint32_t s_gbase[256];  // global start of each digit's run of this tile
+    __shared__ uint32_t s_lbase[256];  // its start inside the tile
+    __shared__ uint32_t s_run[256];    // elements of each digit placed so far
     __shared__ uint32_t s_wcnt[4][256];
     const int t = threadIdx.x, wid = t / WAVE;
-    s_base[t] = (uint32_t)offsets[(int64_t)t * nblocks + blockIdx.x];
+    const int64_t base = (int64_t)blockIdx.x * RADIX_TILE;
+    const int64_t total = (int64_t)256 * nblocks;
+    const int64_t at = (int64_t)t * nblocks + blockIdx.x;
+    const uint32_t g0 = (uint32_t)offsets[at];
+    const uint32_t next = at + 1 < total ? (uint32_t)offsets[at + 1] : (uint32_t)n;
+    s_gbase[t] = g0;
+    s_lbase[t] = next - g0;  // this tile's count of digit t, scanned below
+    s_run[t] = 0;
 #pragma unroll
     for (int w = 0; w < 4; ++w) s_wcnt[w][t] = 0;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * RADIX_TILE;
+    // exclusive scan of the 256 digit counts: inclusive scan within each
+    // wavefront by shuffles, then the four wavefront totals
+    {
+        const uint32_t own = s_lbase[t];
+        uint32_t v = own;
+#pragma unroll
+        for (int d = 1; d < WAVE; d <<= 1) {
+            const uint32_t y = __shfl_up(v, d);
+            if ((int)lane_id() >= d) v += y;
+        }
+        if ((int)lane_id() == WAVE - 1) s_wcnt[0][wid] = v;
+        __syncthreads();
+        uint32_t before = 0;
+        for (int w = 0; w < wid; ++w) before += s_wcnt[0][w];
+        __syncthreads();
+        s_lbase[t] = before + v - own;
+        s_wcnt[0][t] = 0;
+    }
+    __syncthreads();
     for (int it = 0; it < RADIX_IT; ++it) {
         const int64_t p = base + it * 256 + t;
         const bool valid = p < n;
-        K key = valid ? keys[p] : (K)0;
-        int32_t v = valid ? vals[p] : 0;
+        const K key = valid ? keys[p] : (K)0;
+        const int32_t v = valid ? vals[p] : 0;
         const uint32_t d = (uint32_t)(key >> shift) & 255u;
         const uint64_t act = __ballot(valid);
         const uint64_t peers = match_digit(d, act);
@@ -165,13 +199,13 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const K* keys, const int3
         if (valid && rank == 0) s_wcnt[wid][d] = tag | (uint32_t)__popcll(peers);
         __syncthreads();
         if (valid) {
-            uint32_t o = s_base[d] + rank;
+            uint32_t o = s_lbase[d] + s_run[d] + rank;
             for (int w = 0; w < wid; ++w) {
                 const uint32_t x = s_wcnt[w][d];
                 if ((x & 0xFFFF0000u) == tag) o += x & 0xFFFFu;
             }
-            keys_out[o] = key;
-            vals_out[o] = v;
+            s_key[o] = key;
+            s_val[o] = v;
         }
         uint32_t add = 0;
 #pragma unroll
@@ -180,7 +214,16 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const K* keys, const int3
             if ((x & 0xFFFF0000u) == tag) add += x & 0xFFFFu;
         }
         __syncthreads();
-        s_base[t] += add;
+        s_run[t] += add;
+    }
+    __syncthreads();
+    const int64_t cnt = n - base < RADIX_TILE ? n - base : RADIX_TILE;
+    for (int64_t q = t; q < cnt; q += 256) {
+        const K key = s_key[q];
+        const uint32_t d = (uint32_t)(key >> shift) & 255u;
+        const uint32_t g = s_gbase[d] + ((uint32_t)q - s_lbase[d]);
+        keys_out[g] = key;
+        vals_out[g] = s_val[q];
     }
 }
 
