@@ -242,6 +242,7 @@ Tune make_tune(const lv_tuning* t)
             u.bounds[CLS_B256] = std::min(CLS_CAP[CLS_B256], std::max(u.bounds[CLS_G64], t->block_max));
             u.bounds[CLS_B512] = std::min(CLS_CAP[CLS_B512], std::max(u.bounds[CLS_B256], t->block_max));
             u.bounds[CLS_B4K] = std::min(CLS_CAP[CLS_B4K], std::max(u.bounds[CLS_B512], t->block_max));
+            u.bounds[CLS_B8K] = std::min(CLS_CAP[CLS_B8K], std::max(u.bounds[CLS_B4K], t->block_max));
         }
         if (t->hub_mode == 1) {
             u.bucketed = 0;
@@ -928,7 +929,7 @@ lv_status autotune(lv_graph* g, const Params& base, lv_tuning* best, double* bes
     const std::vector<Knob> knobs = {
         {&lv_tuning::sub_max, {4, 16}},
         {&lv_tuning::wave_max, {64}},
-        {&lv_tuning::block_max, {2048}},
+        {&lv_tuning::block_max, {3584, 2048}},
         {&lv_tuning::hub_mode, {1}},
         {&lv_tuning::part_keys, {512, 1024}},
         {&lv_tuning::hub_chunk, {2048, 4096}},

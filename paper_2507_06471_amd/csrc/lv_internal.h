@@ -22,14 +22,15 @@ enum MoveClass : int {
     CLS_G64 = 3,   // one wavefront, 256 slots
     CLS_B256 = 4,  // one 256-thread workgroup, 1024 slots
     CLS_B512 = 5,  // one 512-thread workgroup, 4096 slots
-    CLS_B4K = 6,   // one 512-thread workgroup, 8192 compact slots
-    CLS_HUB = 7,   // several partition workgroups per vertex
-    NUM_CLS = 8
+    CLS_B4K = 6,   // one 512-thread workgroup, 4096 slots
+    CLS_B8K = 7,   // one 1024-thread workgroup, 16384 compact slots
+    CLS_HUB = 8,   // several partition workgroups per vertex
+    NUM_CLS = 9
 };
 // Largest L each class can hold (table load factor <= 1/2).
-// row-length caps of the classes; the 4096-slot table of the last workgroup
-// class is kept at load <= 7/8
-constexpr int32_t CLS_CAP[NUM_CLS] = {0, 8, 32, 128, 512, 2048, 3584, INT32_MAX};
+// row-length caps of the classes; the 4096-slot table of the 512-thread
+// class is kept at load <= 7/8, the 16384-slot one at load <= 1/2
+constexpr int32_t CLS_CAP[NUM_CLS] = {0, 8, 32, 128, 512, 2048, 3584, 8192, INT32_MAX};
 
 // Device-side sweep control of one level: completed sweeps and whether every
 // graph of the level has stopped (kernels of later sweeps then exit early).

@@ -17,7 +17,9 @@
 //   L <= 512    a 256-thread workgroup, <= 1024 slots
 //   L <= 2048   a 512-thread workgroup, <= 4096 slots
 //   L <= 3584   a 512-thread workgroup, 4096 slots (load at most 7/8)
-//   L >  3584   P = ceil(L / part_keys) workgroups per vertex;
+//   L <= 8192   a 1024-thread workgroup, 16384 compact slots (128 KiB; the
+//               volume is gathered per distinct community at scan time)
+//   L >  8192   P = ceil(L / part_keys) workgroups per vertex;
 //               workgroup p aggregates the communities of hash partition p in
 //               an LDS table; partial results are merged per vertex, and all P
 //               workgroups of a vertex run on one XCD (shared L2).  Two modes:
@@ -769,6 +771,7 @@ hipError_t launch_move_class(int cls, bool singleton, const MoveArgs& a, hipStre
     case CLS_B256: return launch_move_t<CLS_B256, 256, 256, 1024, true>(singleton, a, s);
     case CLS_B512: return launch_move_t<CLS_B512, 512, 512, 4096, true>(singleton, a, s);
     case CLS_B4K: return launch_move_t<CLS_B4K, 512, 512, 4096, true>(singleton, a, s);
+    case CLS_B8K: return launch_move_t<CLS_B8K, 1024, 1024, 16384, false>(singleton, a, s);
     default: return hipErrorInvalidValue;
     }
 }
