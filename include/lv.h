@@ -84,9 +84,9 @@ typedef struct lv_result lv_result; /* per-level labels and statistics, library-
  * Zero fields take the built-in defaults.
  */
 typedef struct lv_tuning {
-    int32_t sub_max;   /* L <= sub_max: a sub-wave group per vertex (power of 2, 2..64)  */
-    int32_t wave_max;  /* L <= wave_max: one wavefront per vertex                          */
-    int32_t block_max; /* L <= block_max: one workgroup per vertex, LDS table (<= 8192)    */
+    int32_t sub_max;   /* rows up to sub_max entries: groups of 4..32 lanes (<= 128)      */
+    int32_t wave_max;  /* rows up to wave_max entries: one wavefront (<= 256)              */
+    int32_t block_max; /* rows up to block_max entries: 128..1024-thread groups (<= 8192)  */
                        /* L >  block_max: ceil(L / part_keys) workgroups per vertex, each  */
                        /* aggregating one hash partition of the communities in LDS         */
     int32_t part_keys;  /* expected communities per partition workgroup (clamped to       */
@@ -109,7 +109,7 @@ typedef struct lv_params {
     const lv_tuning* tuning; /* NULL = built-in defaults                                   */
 } lv_params;
 
-#define LV_KERNEL_SLOTS 17
+#define LV_KERNEL_SLOTS 23
 
 /* Per-level statistics; times are milliseconds from HIP events.  sweep_ms,
    renumber_ms and aggregate_ms are always measured (events around each
@@ -130,15 +130,14 @@ typedef struct lv_level_info {
     int64_t move_launches; /* number of move-kernel launches                       */
     int64_t move_bytes;    /* algorithmic bytes of the move kernels, all sweeps    */
     /* Per move kernel (LV_TIMING): slot 2*(class-1) + (1 for the first sweep
-       of a level, where every community is a single vertex); classes 1..6 =
-       8-lane, 32-lane, wavefront, 256-thread, 512-thread (<= 2048 entries),
-       512-thread (<= 3584) and 1024-thread (<= 8192) workgroup tables,
-       8 = partition workgroups (with their merge and fallback kernels);
-       slot 16 = the bucketed mode's scatter pass, which then carries class
-       8's bytes.
-       Bytes count each array element a kernel needs once: indices (and
-       weights) of its rows, and 20 bytes per vertex (vertex list, row offset,
-       label, degree, own community volume). */
+       of a level, where every community is a single vertex); classes 1..10 =
+       rows of at most 4, 8, 32, 128, 256, 512, 1024, 2048, 3584 and 8192
+       entries (groups of 4 lanes up to 1024-thread workgroups), 11 =
+       partition workgroups (with their merge and fallback kernels); slot 22
+       = the bucketed mode's scatter pass, which then carries class 11's
+       bytes.  Bytes count each array element a kernel needs once: indices
+       (and weights) of its rows, and 20 bytes per vertex (vertex list, row
+       offset, label, degree, own community volume). */
     double kern_ms[LV_KERNEL_SLOTS];
     int64_t kern_launches[LV_KERNEL_SLOTS];
     int64_t kern_bytes[LV_KERNEL_SLOTS];

@@ -230,20 +230,16 @@ Tune make_tune(const lv_tuning* t)
     u.fb_chunk = 4096;
     u.sc_chunk = 1024;
     if (t) {
-        // sub_max bounds the 8- and 32-lane classes, wave_max the wavefront
-        // class, block_max the workgroup classes; each is clamped to what the
-        // class's table holds, so no setting can overflow a table.
-        if (t->sub_max > 0) {
-            u.bounds[CLS_G8] = std::min(CLS_CAP[CLS_G8], t->sub_max);
-            u.bounds[CLS_G32] = std::min(CLS_CAP[CLS_G32], std::max(u.bounds[CLS_G8], t->sub_max));
-        }
-        if (t->wave_max > 0) u.bounds[CLS_G64] = std::min(CLS_CAP[CLS_G64], std::max(u.bounds[CLS_G32], t->wave_max));
-        if (t->block_max > 0) {
-            u.bounds[CLS_B256] = std::min(CLS_CAP[CLS_B256], std::max(u.bounds[CLS_G64], t->block_max));
-            u.bounds[CLS_B512] = std::min(CLS_CAP[CLS_B512], std::max(u.bounds[CLS_B256], t->block_max));
-            u.bounds[CLS_B4K] = std::min(CLS_CAP[CLS_B4K], std::max(u.bounds[CLS_B512], t->block_max));
-            u.bounds[CLS_B8K] = std::min(CLS_CAP[CLS_B8K], std::max(u.bounds[CLS_B4K], t->block_max));
-        }
+        // sub_max bounds the sub-wavefront classes, wave_max the wavefront
+        // class, block_max the workgroup classes; each is clamped to the
+        // class's cap, so no setting can overflow a table.
+        auto cap = [&](int c, int32_t knob) { u.bounds[c] = std::min(CLS_CAP[c], knob); };
+        if (t->sub_max > 0)
+            for (int c = CLS_L4; c < CLS_FIRST_WAVE; ++c) cap(c, t->sub_max);
+        if (t->wave_max > 0)
+            for (int c = CLS_FIRST_WAVE; c < CLS_FIRST_BLOCK; ++c) cap(c, t->wave_max);
+        if (t->block_max > 0)
+            for (int c = CLS_FIRST_BLOCK; c < CLS_HUB; ++c) cap(c, t->block_max);
         if (t->hub_mode == 1) {
             u.bucketed = 0;
             u.part_slots = 16384;
@@ -258,7 +254,7 @@ Tune make_tune(const lv_tuning* t)
     // a single partition must always fit: part_keys <= 3/4 of the slots
     u.part_keys = std::min(u.part_keys, u.part_slots / 4 * 3);
     // keep bounds non-decreasing
-    for (int c = CLS_G32; c < CLS_HUB; ++c) u.bounds[c] = std::max(u.bounds[c], u.bounds[c - 1]);
+    for (int c = CLS_L8; c < CLS_HUB; ++c) u.bounds[c] = std::max(u.bounds[c], u.bounds[c - 1]);
     return u;
 }
 
@@ -523,9 +519,9 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
     start[NUM_CLS] = n;
     for (int c = NUM_CLS - 1; c >= 0; --c)
         if (start[c] < 0) start[c] = start[c + 1];
-    const int32_t active = n - start[CLS_G8];  // vertices with at least one entry
+    const int32_t active = n - start[CLS_L4];  // vertices with at least one entry
     HIP_TRY(ws.rows.ensure(sizeof(int4) * (size_t)std::max(active, 1)));
-    HIP_TRY(launch_row_descriptors(vert_sorted + start[CLS_G8], active, G.off, G.k, ws.rows.as<int4>(), s));
+    HIP_TRY(launch_row_descriptors(vert_sorted + start[CLS_L4], active, G.off, G.k, ws.rows.as<int4>(), s));
 
     HubPlan hubs;
     LV_TRY(plan_hubs(g, G, vert_sorted + start[CLS_HUB], n - start[CLS_HUB], p.tune, hubs));
@@ -571,9 +567,9 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
     // pair refresh, per-graph stopping rule.
     auto launch_sweep = [&](bool singleton, std::vector<hipEvent_t>* e) -> lv_status {
         if (e) { e->assign(2 * NUM_CLS + 4, nullptr); HIP_TRY(tm.mark(&(*e)[2 * NUM_CLS])); }
-        for (int c = CLS_G8; c < CLS_HUB; ++c) {
+        for (int c = CLS_L4; c < CLS_HUB; ++c) {
             a.verts = vert_sorted + start[c];
-            a.rows = ws.rows.as<int4>() + (start[c] - start[CLS_G8]);
+            a.rows = ws.rows.as<int4>() + (start[c] - start[CLS_L4]);
             a.dec = dec_all + start[c];
             a.nverts = start[c + 1] - start[c];
             if (a.nverts == 0) continue;
@@ -596,7 +592,7 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
             if (e) HIP_TRY(tm.mark(&(*e)[2 * CLS_HUB + 1]));
         }
         if (e) HIP_TRY(tm.mark(&(*e)[2 * NUM_CLS + 1]));
-        HIP_TRY(launch_apply(vert_sorted + start[CLS_G8], dec_all + start[CLS_G8], active, G.k, a.gid,
+        HIP_TRY(launch_apply(vert_sorted + start[CLS_L4], dec_all + start[CLS_L4], active, G.k, a.gid,
                              ws.comm.as<int32_t>(), ws.sigma.as<int32_t>(), ctl, ws.gmoves.as<uint32_t>(), S, s));
         HIP_TRY(launch_pairs(n, ws.comm.as<int32_t>(), ws.sigma.as<int32_t>(), ws.cs.as<int2>(), ctl, s));
         HIP_TRY(launch_sweep_end(ctl, G.G, ws.gdone.as<int32_t>(), ws.gsweeps.as<int32_t>(),
@@ -669,7 +665,7 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
     const int64_t wbytes = G.w ? 8 : 4;
     out.bytes = (4 * ((int64_t)n + 1) + wbytes * G.nnz + 12 * (int64_t)n) * out.executed;
     for (int32_t sw = 1; sw <= out.executed; ++sw) {
-        for (int c = CLS_G8; c <= CLS_HUB; ++c) {
+        for (int c = CLS_L4; c <= CLS_HUB; ++c) {
             const int32_t nv = start[c + 1] - start[c];
             if (nv == 0) continue;
             out.launches += c == CLS_HUB ? (sw == 1 ? 2 : 2 + (hubs.args.bucketed && hubs.args.nsc > 0 ? 1 : 0) + (hubs.args.nins > 0 ? 3 : 0)) : 1;
@@ -927,8 +923,8 @@ lv_status autotune(lv_graph* g, const Params& base, lv_tuning* best, double* bes
     LV_TRY(cost(*best, &cur));
     struct Knob { int32_t lv_tuning::*field; std::vector<int32_t> values; };
     const std::vector<Knob> knobs = {
-        {&lv_tuning::sub_max, {4, 16}},
-        {&lv_tuning::wave_max, {64}},
+        {&lv_tuning::sub_max, {32, 8}},
+        {&lv_tuning::wave_max, {128}},
         {&lv_tuning::block_max, {3584, 2048}},
         {&lv_tuning::hub_mode, {1}},
         {&lv_tuning::part_keys, {512, 1024}},

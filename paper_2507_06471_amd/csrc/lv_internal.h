@@ -17,20 +17,25 @@ constexpr int DIR_UP = 1;
 // first class whose bound is >= L (L = 0 never moves and is skipped).
 enum MoveClass : int {
     CLS_NONE = 0,  // isolated
-    CLS_G8 = 1,    // 8 lanes per vertex, LDS table of 16 slots
-    CLS_G32 = 2,   // 32 lanes, 64 slots
-    CLS_G64 = 3,   // one wavefront, 256 slots
-    CLS_B256 = 4,  // one 256-thread workgroup, 1024 slots
-    CLS_B512 = 5,  // one 512-thread workgroup, 4096 slots
-    CLS_B4K = 6,   // one 512-thread workgroup, 4096 slots
-    CLS_B8K = 7,   // one 1024-thread workgroup, 16384 compact slots
-    CLS_HUB = 8,   // several partition workgroups per vertex
-    NUM_CLS = 9
+    CLS_L4,        // L <= 4:     4 lanes per vertex, LDS table of 8 slots
+    CLS_L8,        // L <= 8:     8 lanes, 16 slots
+    CLS_L32,       // L <= 32:    16 lanes, 64 slots
+    CLS_L128,      // L <= 128:   32 lanes, 256 slots
+    CLS_L256,      // L <= 256:   one wavefront, 512 slots
+    CLS_L512,      // L <= 512:   128 lanes, 1024 slots
+    CLS_L1K,       // L <= 1024:  one 256-thread workgroup, 2048 slots
+    CLS_L2K,       // L <= 2048:  one 512-thread workgroup, 4096 slots
+    CLS_L3K5,      // L <= 3584:  one 512-thread workgroup, 4096 slots (load <= 7/8)
+    CLS_L8K,       // L <= 8192:  one 1024-thread workgroup, 16384 compact slots
+    CLS_HUB,       // several partition workgroups per vertex
+    NUM_CLS
 };
-// Largest L each class can hold (table load factor <= 1/2).
-// row-length caps of the classes; the 4096-slot table of the 512-thread
-// class is kept at load <= 7/8, the 16384-slot one at load <= 1/2
-constexpr int32_t CLS_CAP[NUM_CLS] = {0, 8, 32, 128, 512, 2048, 3584, 8192, INT32_MAX};
+
+// row-length caps of the classes (a vertex takes the first class whose cap is
+// at least its number of entries L)
+constexpr int32_t CLS_CAP[NUM_CLS] = {0, 4, 8, 32, 128, 256, 512, 1024, 2048, 3584, 8192, INT32_MAX};
+// classes of groups narrower than a wavefront, of one wavefront, of workgroups
+constexpr int CLS_FIRST_WAVE = CLS_L256, CLS_FIRST_BLOCK = CLS_L512;
 
 // Device-side sweep control of one level: completed sweeps and whether every
 // graph of the level has stopped (kernels of later sweeps then exit early).

@@ -10,12 +10,17 @@
 // -1) is written to its slot of the class-sorted vertex list; k_apply then
 // commits the moves.
 //
-// Scheduling by the vertex's number of CSR entries L (degree classes):
-//   L <= 8      8 lanes per vertex, LDS table of <= 16 slots
-//   L <= 32     32 lanes, <= 64 slots
-//   L <= 128    a wavefront, <= 256 slots
-//   L <= 512    a 256-thread workgroup, <= 1024 slots
-//   L <= 2048   a 512-thread workgroup, <= 4096 slots
+// Scheduling by the vertex's number of CSR entries L (degree classes): about
+// one lane per four entries, so that a lane keeps four loads in flight and a
+// compute unit holds many vertices; tables of at most 24 KiB up to L = 1024.
+//   L <= 4      4 lanes per vertex, LDS table of 8 slots
+//   L <= 8      8 lanes, 16 slots
+//   L <= 32     16 lanes, 64 slots
+//   L <= 128    32 lanes, 256 slots
+//   L <= 256    a wavefront, 512 slots
+//   L <= 512    128 lanes, 1024 slots
+//   L <= 1024   a 256-thread workgroup, 2048 slots
+//   L <= 2048   a 512-thread workgroup, 4096 slots
 //   L <= 3584   a 512-thread workgroup, 4096 slots (load at most 7/8)
 //   L <= 8192   a 1024-thread workgroup, 16384 compact slots (128 KiB; the
 //               volume is gathered per distinct community at scan time)
@@ -60,7 +65,7 @@ __global__ void k_classify(int32_t n, const int32_t* off, Bounds bd, uint32_t* c
         uint32_t c = CLS_NONE;
         if (L > 0) {
             c = CLS_HUB;
-            for (int q = CLS_G8; q < CLS_HUB; ++q)
+            for (int q = CLS_L4; q < CLS_HUB; ++q)
                 if (L <= bd.b[q]) { c = (uint32_t)q; break; }
         }
         cls[i] = c;
@@ -739,7 +744,7 @@ hipError_t launch_class_starts(const uint32_t* cls_sorted, int32_t n, int32_t* s
 hipError_t launch_class_entries(const int32_t* verts_sorted, const int32_t* start, const int32_t* off, int64_t* out,
                                 hipStream_t s)
 {
-    for (int c = CLS_G8; c < NUM_CLS; ++c) {
+    for (int c = CLS_L4; c < NUM_CLS; ++c) {
         const int32_t lo = start[c], hi = start[c + 1];
         if (hi <= lo) continue;
         k_class_entries<<<grid_for(hi - lo, 256, 4096), 256, 0, s>>>(verts_sorted, lo, hi, off,
@@ -765,13 +770,16 @@ hipError_t launch_gather_rows(const int32_t* verts, int32_t m, const int32_t* of
 hipError_t launch_move_class(int cls, bool singleton, const MoveArgs& a, hipStream_t s)
 {
     switch (cls) {
-    case CLS_G8: return launch_move_t<CLS_G8, 256, 8, 16, true>(singleton, a, s);
-    case CLS_G32: return launch_move_t<CLS_G32, 256, 32, 64, true>(singleton, a, s);
-    case CLS_G64: return launch_move_t<CLS_G64, 256, 64, 256, true>(singleton, a, s);
-    case CLS_B256: return launch_move_t<CLS_B256, 256, 256, 1024, true>(singleton, a, s);
-    case CLS_B512: return launch_move_t<CLS_B512, 512, 512, 4096, true>(singleton, a, s);
-    case CLS_B4K: return launch_move_t<CLS_B4K, 512, 512, 4096, true>(singleton, a, s);
-    case CLS_B8K: return launch_move_t<CLS_B8K, 1024, 1024, 16384, false>(singleton, a, s);
+    case CLS_L4: return launch_move_t<CLS_L4, 256, 4, 8, true>(singleton, a, s);
+    case CLS_L8: return launch_move_t<CLS_L8, 256, 8, 16, true>(singleton, a, s);
+    case CLS_L32: return launch_move_t<CLS_L32, 256, 16, 64, true>(singleton, a, s);
+    case CLS_L128: return launch_move_t<CLS_L128, 256, 32, 256, true>(singleton, a, s);
+    case CLS_L256: return launch_move_t<CLS_L256, 256, 64, 512, true>(singleton, a, s);
+    case CLS_L512: return launch_move_t<CLS_L512, 256, 128, 1024, true>(singleton, a, s);
+    case CLS_L1K: return launch_move_t<CLS_L1K, 256, 256, 2048, true>(singleton, a, s);
+    case CLS_L2K: return launch_move_t<CLS_L2K, 512, 512, 4096, true>(singleton, a, s);
+    case CLS_L3K5: return launch_move_t<CLS_L3K5, 512, 512, 4096, true>(singleton, a, s);
+    case CLS_L8K: return launch_move_t<CLS_L8K, 1024, 1024, 16384, false>(singleton, a, s);
     default: return hipErrorInvalidValue;
     }
 }
