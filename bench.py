@@ -4,8 +4,10 @@
 Workload: R-MAT scale 24, edge factor 16 (a=0.57, b=0.19, c=0.19), symmetrised,
 self-loops and duplicates removed, unit weights (16.8M vertices, ~521M CSR
 entries).  One step = multi-level Louvain (local moving, renumbering and
-aggregation at every level) followed by LPA (max 20 sweeps) on the same
-device-resident graph.  The graph is created (copied to HBM) before timing.
+aggregation at every level; final labels and per-level statistics copied to
+the host) followed by LPA (max 20 sweeps; labels copied to the host) on the
+same device-resident graph.  The graph is created (copied to HBM) before
+timing.
 
 The timed steps run the production path (each level's sweeps captured as
 hipGraphs, degree classes on concurrent streams).
@@ -332,7 +334,9 @@ def main():
         del src, dst
 
     def step(timing):
-        r = lvp.louvain(dg, timing=timing)
+        # the job's results: final labels and per-level statistics of Louvain,
+        # labels of LPA (the per-level labels stay on the device)
+        r = lvp.louvain(dg, timing=timing, level_labels=False)
         lp = lvp.lpa(dg, timing=timing)
         return r, lp
 

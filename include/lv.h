@@ -66,6 +66,8 @@ typedef enum lv_memkind { LV_MEM_HOST = 0, LV_MEM_DEVICE = 1 } lv_memkind;
 
 /* lv_graph_create_csr flags */
 #define LV_VALIDATE 1u /* check CSR shape, sortedness, symmetry and weights on the device */
+#define LV_KEEP_ORDER 2u  /* create: store the vertices in input order (default: by descending    */
+                          /* degree within each graph, for cache locality; results are the same)  */
 
 /* lv_params.flags */
 #define LV_TIMING 1u      /* record per-kernel HIP event times (see lv_level_info); sweeps */

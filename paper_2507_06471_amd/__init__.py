@@ -29,6 +29,7 @@ STATUS_NAMES = {
 }
 LV_MEM_HOST, LV_MEM_DEVICE = 0, 1
 LV_VALIDATE = 1
+LV_KEEP_ORDER = 2
 LV_TIMING = 1
 LV_KEEP_GRAPHS = 2
 LV_NO_HIPGRAPH = 4
@@ -215,7 +216,8 @@ def make_params(max_sweeps: int = 20, max_levels: int = 32, lpa_threshold: int =
 class Graph:
     """Device-resident graph handle (lv_graph_create_csr / lv_graph_destroy)."""
 
-    def __init__(self, n: int, offsets, indices, weights=None, validate: bool = True, stream: int = 0):
+    def __init__(self, n: int, offsets, indices, weights=None, validate: bool = True, stream: int = 0,
+                 keep_order: bool = False):
         lib = load_library()
         po, ko = _ptr(offsets)
         pi, ki = _ptr(indices)
@@ -224,8 +226,8 @@ class Graph:
         if len(kinds) != 1:
             raise ValueError("offsets, indices and weights must live in the same memory")
         h = _vp()
-        st = lib.lv_graph_create_csr(int(n), po, pi, pw, ko, LV_VALIDATE if validate else 0,
-                                     stream or None, ctypes.byref(h))
+        flags = (LV_VALIDATE if validate else 0) | (LV_KEEP_ORDER if keep_order else 0)
+        st = lib.lv_graph_create_csr(int(n), po, pi, pw, ko, flags, stream or None, ctypes.byref(h))
         _check(st, "lv_graph_create_csr")
         self._h = h
         self.n = int(n)
@@ -237,7 +239,7 @@ class Graph:
         self.sizes = [self.n]
 
     @classmethod
-    def batch(cls, graphs, validate: bool = True):
+    def batch(cls, graphs, validate: bool = True, keep_order: bool = False):
         """Pack several ``graphgen.CSR``-like graphs into one handle
         (lv_graph_create_batch); graph g keeps its own vertex numbering."""
         lib = load_library()
@@ -255,7 +257,8 @@ class Graph:
         pw = P(*[(a[3].ctypes.data if a[3] is not None else None) for a in arrs])
         h = _vp()
         st = lib.lv_graph_create_batch(cnt, ns.ctypes.data, ctypes.cast(po, _vp), ctypes.cast(pi, _vp),
-                                       ctypes.cast(pw, _vp), LV_MEM_HOST, LV_VALIDATE if validate else 0, None,
+                                       ctypes.cast(pw, _vp), LV_MEM_HOST,
+                                       (LV_VALIDATE if validate else 0) | (LV_KEEP_ORDER if keep_order else 0), None,
                                        ctypes.byref(h))
         _check(st, "lv_graph_create_batch")
         self = cls.__new__(cls)
@@ -269,7 +272,7 @@ class Graph:
         return self
 
     @classmethod
-    def from_csr(cls, g, validate: bool = True, device: bool = False):
+    def from_csr(cls, g, validate: bool = True, device: bool = False, keep_order: bool = False):
         """From a ``graphgen.CSR``-like object (n, offsets, indices, weights)."""
         off = np.ascontiguousarray(g.offsets, dtype=np.int32)
         idx = np.ascontiguousarray(g.indices, dtype=np.int32)
@@ -280,7 +283,7 @@ class Graph:
             off, idx = torch.from_numpy(off).cuda(), torch.from_numpy(idx).cuda()
             w = None if w is None else torch.from_numpy(w).cuda()
             torch.cuda.synchronize()
-        return cls(g.n, off, idx, w, validate=validate)
+        return cls(g.n, off, idx, w, validate=validate, keep_order=keep_order)
 
     @property
     def handle(self):
@@ -358,7 +361,7 @@ def louvain_final(graph: Graph, max_sweeps: int = 20, max_levels: int = 32, tuni
         lib.lv_result_destroy(r)
 
 
-def _read_graph_result(lib, r, gi: int, n0: int, keep_graphs: bool) -> LouvainResult:
+def _read_graph_result(lib, r, gi: int, n0: int, keep_graphs: bool, level_labels: bool = True) -> LouvainResult:
     acc, att = ctypes.c_int32(), ctypes.c_int32()
     _check(lib.lv_result_graph_num_levels(r, gi, ctypes.byref(acc), ctypes.byref(att)), "lv_result_graph_num_levels")
     levels = []
@@ -369,7 +372,7 @@ def _read_graph_result(lib, r, gi: int, n0: int, keep_graphs: bool) -> LouvainRe
         _check(lib.lv_result_graph_level_moves(r, gi, lvl, mv.ctypes.data_as(_i64p), info.sweeps),
                "lv_result_graph_level_moves")
         lr = LevelResult(info.as_dict(), [int(x) for x in mv[:info.sweeps]])
-        if lvl < acc.value:
+        if lvl < acc.value and level_labels:
             lab = np.empty(info.n, dtype=np.int32)
             _check(lib.lv_result_graph_level_labels(r, gi, lvl, lab.ctypes.data, LV_MEM_HOST),
                    "lv_result_graph_level_labels")
@@ -400,17 +403,19 @@ def _flags(timing: bool, keep_graphs: bool = False, hipgraph: bool = True, autot
 
 def louvain(graph: Graph, max_sweeps: int = 20, max_levels: int = 32, timing: bool = False,
             keep_graphs: bool = False, tuning: Optional[dict] = None, hipgraph: bool = True,
-            autotuned: bool = False):
+            autotuned: bool = False, level_labels: bool = True):
     """lv_louvain + result accessors, copied to host numpy.  A packed handle
-    (``Graph.batch``) gives one LouvainResult per graph, in order."""
+    (``Graph.batch``) gives one LouvainResult per graph, in order.  With
+    level_labels=False only the final labels are copied (levels keep their
+    statistics and move counts)."""
     lib = load_library()
     p, _keep = make_params(max_sweeps, max_levels, 0, _flags(timing, keep_graphs, hipgraph, autotuned), tuning)
     r = _vp()
     _check(lib.lv_louvain(graph.handle, ctypes.byref(p), ctypes.byref(r)), "lv_louvain")
     try:
         if graph.count == 1:
-            return _read_graph_result(lib, r, 0, graph.n, keep_graphs)
-        return [_read_graph_result(lib, r, gi, graph.sizes[gi], False) for gi in range(graph.count)]
+            return _read_graph_result(lib, r, 0, graph.n, keep_graphs, level_labels)
+        return [_read_graph_result(lib, r, gi, graph.sizes[gi], False, level_labels) for gi in range(graph.count)]
     finally:
         lib.lv_result_destroy(r)
 

@@ -91,6 +91,11 @@ struct DevBuf {
         return e;
     }
     template <typename T> T* as() const { return (T*)p; }
+    void swap(DevBuf& o)
+    {
+        std::swap(p, o.p);
+        std::swap(cap, o.cap);
+    }
 };
 
 struct Workspace {
@@ -163,6 +168,12 @@ struct lv_graph {
     std::vector<int64_t> M;      // [G] total volume
     std::vector<int64_t> q0;     // [G] Q_int of singletons
     DevBuf d_gid, d_M;           // per vertex graph id, per graph M (G > 1)
+    // Storage order: vertices are kept by descending degree within each
+    // graph (unless LV_KEEP_ORDER); orig[p] = vertex id at position p,
+    // inv[id] = its position.  Every segment of a packed handle keeps its
+    // range, so graph ids by position and by id coincide.
+    bool reordered = false;
+    DevBuf orig, inv;
     Workspace ws;
     int32_t* pinned = nullptr;   // host staging area
     size_t pinned_bytes = 0;
@@ -297,6 +308,7 @@ struct LevelGraph {
     int64_t M;           // M when G == 1
     std::vector<int32_t> voff;  // [G+1] vertex offsets (host)
     std::vector<int64_t> Mh;    // [G] total volume of each graph (host)
+    const int32_t* orig = nullptr;  // vertex id at each position (null: the position)
 };
 
 // timing slot of the bucketed scatter pass (after the 2 x 7 class slots)
@@ -536,8 +548,15 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
     }
 
     SweepCtl* ctl = ws.ctl.as<SweepCtl>();
-    HIP_TRY(launch_iota(ws.comm.as<int32_t>(), n, s));
-    HIP_TRY(launch_copy_i32(ws.sigma.as<int32_t>(), G.k, n, s));
+    // Singleton communities are named by vertex id; with degree-ordered
+    // storage the id of position p is orig[p] and its volume sits at sigma[id].
+    if (G.orig) {
+        HIP_TRY(launch_copy_i32(ws.comm.as<int32_t>(), G.orig, n, s));
+        HIP_TRY(launch_scatter_i32(G.k, G.orig, n, ws.sigma.as<int32_t>(), s));
+    } else {
+        HIP_TRY(launch_iota(ws.comm.as<int32_t>(), n, s));
+        HIP_TRY(launch_copy_i32(ws.sigma.as<int32_t>(), G.k, n, s));
+    }
     HIP_TRY(launch_pairs(n, ws.comm.as<int32_t>(), ws.sigma.as<int32_t>(), ws.cs.as<int2>(), nullptr, s));
     HIP_TRY(launch_ctl_init(ctl, G.G, gactive, ws.gdone.as<int32_t>(), ws.gsweeps.as<int32_t>(),
                             ws.gmoves.as<uint32_t>(), S, s));
@@ -709,7 +728,7 @@ lv_status renumber(lv_graph* g, const LevelGraph& G, int32_t* n2, std::vector<in
     HIP_TRY(ws.gmeta.ensure(sizeof(int32_t) * ((size_t)G.G + 1)));
     int32_t* pos = ws.pos.as<int32_t>();
     // pos[n] receives the total
-    HIP_TRY(launch_renumber(n, ws.comm.as<int32_t>(), ws.minv.as<int32_t>(), ws.flag.as<int32_t>(), pos,
+    HIP_TRY(launch_renumber(n, ws.comm.as<int32_t>(), G.orig, ws.minv.as<int32_t>(), ws.flag.as<int32_t>(), pos,
                             ws.labels.as<int32_t>(), pos + n, ws.tmp.p, ws.tmp.cap, g->stream));
     // the new base of graph c is the number of communities before its first vertex
     std::vector<int32_t> at(G.voff.begin(), G.voff.end());
@@ -755,8 +774,8 @@ lv_status aggregate(lv_graph* g, const LevelGraph& G, int32_t n2, int slot, Coar
     HIP_TRY(hipMemsetAsync(d_sin, 0, sizeof(int64_t) * (size_t)G.G, s));
     HIP_TRY(hipMemsetAsync(d_sq, 0, sizeof(int64_t) * (size_t)G.G, s));
     int32_t* gid2 = G.gid ? ws.g_gid[slot].as<int32_t>() : nullptr;
-    HIP_TRY(launch_coarse_degree(G.n, ws.comm.as<int32_t>(), ws.flag.as<int32_t>(), ws.labels.as<int32_t>(),
-                                 ws.sigma.as<int32_t>(), G.gid, ws.g_k[slot].as<int32_t>(), gid2, s));
+    HIP_TRY(launch_coarse_degree(G.n, ws.comm.as<int32_t>(), ws.labels.as<int32_t>(), ws.sigma.as<int32_t>(), G.gid,
+                                 ws.g_k[slot].as<int32_t>(), gid2, s));
     HIP_TRY(launch_sum_sq(ws.g_k[slot].as<int32_t>(), n2, gid2, d_sq, s));
     HIP_TRY(launch_build_keys(G.n, G.off, G.idx, G.w, E, ws.labels.as<int32_t>(), colbits, ws.keys.as<uint64_t>(),
                               ws.vals.as<int32_t>(), G.gid, d_sin, s));
@@ -850,7 +869,7 @@ lv_status repack(lv_graph* g, const Coarse& co, const std::vector<int32_t>& voff
     HIP_TRY(ws.g_gid[dst].ensure(sizeof(int32_t) * (size_t)std::max(nv, 1)));
     HIP_TRY(launch_repack(ws.segs.as<RepackSeg>(), (int32_t)segs.size(), nv, ne, ws.g_off[dst].as<int32_t>(),
                           ws.g_idx[dst].as<int32_t>(), ws.g_w[dst].as<int32_t>(), ws.g_k[dst].as<int32_t>(),
-                          ws.g_gid[dst].as<int32_t>(), s));
+                          ws.g_gid[dst].as<int32_t>(), nullptr, s));
     HIP_TRY(hipStreamSynchronize(s));  // the host segment list must outlive the copy
     next.n = nv;
     next.nnz = ne;
@@ -890,6 +909,7 @@ LevelGraph level0(lv_graph* g)
     G.M = g->M[0];
     G.voff = g->voff;
     G.Mh = g->M;
+    G.orig = g->reordered ? g->orig.as<int32_t>() : nullptr;
     return G;
 }
 
@@ -996,7 +1016,9 @@ lv_status louvain_impl(lv_graph* g, const Params& p, bool keep_graphs, lv_result
     {
         HIP_TRY(ws.gmeta.ensure(sizeof(int32_t) * ((size_t)G0 + 1)));
         HIP_TRY(hipMemcpyAsync(ws.gmeta.p, g->voff.data(), sizeof(int32_t) * ((size_t)G0 + 1), hipMemcpyHostToDevice, s));
-        HIP_TRY(launch_iota(r->final_labels.as<int32_t>(), g->n, s));
+        // each vertex's position within its graph in level 0's storage order
+        if (g->reordered) HIP_TRY(launch_copy_i32(r->final_labels.as<int32_t>(), g->inv.as<int32_t>(), g->n, s));
+        else HIP_TRY(launch_iota(r->final_labels.as<int32_t>(), g->n, s));
         HIP_TRY(launch_local_labels(g->n, r->final_labels.as<int32_t>(), G0 > 1 ? g->d_gid.as<int32_t>() : nullptr,
                                     ws.gmeta.as<int32_t>(), r->final_labels.as<int32_t>(), s));
     }
@@ -1043,7 +1065,10 @@ lv_status louvain_impl(lv_graph* g, const Params& p, bool keep_graphs, lv_result
             store = std::make_shared<LabelStore>();
             store->n = G.n;
             HIP_TRY(store->labels.ensure(sizeof(int32_t) * (size_t)std::max(G.n, 1)));
-            HIP_TRY(launch_copy_i32(store->labels.as<int32_t>(), ws.labels.as<int32_t>(), G.n, s));
+            if (G.orig)  // kept in vertex-id order
+                HIP_TRY(launch_scatter_i32(ws.labels.as<int32_t>(), G.orig, G.n, store->labels.as<int32_t>(), s));
+            else
+                HIP_TRY(launch_copy_i32(store->labels.as<int32_t>(), ws.labels.as<int32_t>(), G.n, s));
         }
         for (int32_t c = 0; c < G.G; ++c) {
             GraphResult& gr = r->graphs[orig[c]];
@@ -1176,7 +1201,12 @@ lv_status lpa_impl(lv_graph* g, const Params& p, int32_t* out_dev, SweepOut& so,
     // labels numbered within each graph
     HIP_TRY(ws.gmeta.ensure(sizeof(int32_t) * ((size_t)G.G + 1)));
     HIP_TRY(hipMemcpyAsync(ws.gmeta.p, voff2.data(), sizeof(int32_t) * ((size_t)G.G + 1), hipMemcpyHostToDevice, s));
-    HIP_TRY(launch_local_labels(G.n, ws.labels.as<int32_t>(), G.gid, ws.gmeta.as<int32_t>(), out_dev, s));
+    if (G.orig) {  // vertex-id order
+        HIP_TRY(launch_local_labels(G.n, ws.labels.as<int32_t>(), G.gid, ws.gmeta.as<int32_t>(), ws.pos.as<int32_t>(), s));
+        HIP_TRY(launch_scatter_i32(ws.pos.as<int32_t>(), G.orig, G.n, out_dev, s));
+    } else {
+        HIP_TRY(launch_local_labels(G.n, ws.labels.as<int32_t>(), G.gid, ws.gmeta.as<int32_t>(), out_dev, s));
+    }
     HIP_TRY(hipStreamSynchronize(s));
     q_int.resize(G.G);
     for (int32_t c = 0; c < G.G; ++c) q_int[c] = G.Mh[c] * sin[c] - sq[c];
@@ -1220,6 +1250,63 @@ const char* lv_status_str(lv_status s)
 }
 
 const char* lv_last_error(void) { return g_last_error.c_str(); }
+
+// Store the graph by descending degree within each packed graph: the
+// gathered (community, volume) pairs of frequent neighbours then share cache
+// lines.  Ids, and so every decision and label, stay those of the input.
+static lv_status reorder_by_degree(lv_graph* g)
+{
+    const int32_t n = g->n;
+    const int64_t nnz = g->nnz;
+    if (n < 2 || nnz == 0) return LV_OK;
+    Workspace& ws = g->ws;
+    hipStream_t s = g->stream;
+    const int32_t* gid = g->G > 1 ? g->d_gid.as<int32_t>() : nullptr;
+    int32_t* d_max = (int32_t*)(ws.small.as<char>() + 3584);
+    HIP_TRY(hipMemsetAsync(d_max, 0, sizeof(int32_t), s));
+    HIP_TRY(launch_max_degree(n, g->off.as<int32_t>(), d_max, s));
+    int32_t maxdeg = 0;
+    HIP_TRY(hipMemcpyAsync(&maxdeg, d_max, sizeof maxdeg, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const int db = bits_for((int64_t)maxdeg + 1);
+    const int bits = db + (g->G > 1 ? bits_for(g->G) : 0);
+    const size_t nb = sizeof(int32_t) * (size_t)n;
+    HIP_TRY(ws.keys.ensure(2 * nb));
+    HIP_TRY(ws.keys_alt.ensure(2 * nb));
+    HIP_TRY(ws.vals.ensure(nb));
+    HIP_TRY(ws.vals_alt.ensure(nb));
+    HIP_TRY(ws.tmp.ensure(std::max(radix_tmp_bytes(n), scan_tmp_bytes((int64_t)n + 1, 8))));
+    HIP_TRY(launch_degree_keys(n, g->off.as<int32_t>(), gid, maxdeg, db, ws.keys.as<uint64_t>(), ws.vals.as<int32_t>(), s));
+    bool in_alt = false;
+    HIP_TRY(radix_sort_u64(ws.keys.as<uint64_t>(), ws.vals.as<int32_t>(), ws.keys_alt.as<uint64_t>(),
+                           ws.vals_alt.as<int32_t>(), n, bits, ws.tmp.p, ws.tmp.cap, &in_alt, s));
+    HIP_TRY(g->orig.ensure(nb));
+    HIP_TRY(g->inv.ensure(nb));
+    HIP_TRY(launch_copy_i32(g->orig.as<int32_t>(), in_alt ? ws.vals_alt.as<int32_t>() : ws.vals.as<int32_t>(), n, s));
+    HIP_TRY(launch_inverse(g->orig.as<int32_t>(), n, g->inv.as<int32_t>(), s));
+    DevBuf off2, idx2, w2, k2;
+    HIP_TRY(off2.ensure(sizeof(int32_t) * ((size_t)n + 1)));
+    HIP_TRY(idx2.ensure(sizeof(int32_t) * (size_t)nnz));
+    if (g->weighted) HIP_TRY(w2.ensure(sizeof(int32_t) * (size_t)nnz));
+    HIP_TRY(k2.ensure(nb));
+    HIP_TRY(launch_perm_lengths(g->orig.as<int32_t>(), n, g->off.as<int32_t>(), off2.as<int32_t>(), s));
+    HIP_TRY(scan_exclusive_i32(off2.as<int32_t>(), off2.as<int32_t>(), n, off2.as<int32_t>() + n, ws.tmp.p, ws.tmp.cap, s));
+    HIP_TRY(launch_perm_rows(n, off2.as<int32_t>(), nnz, g->orig.as<int32_t>(), g->off.as<int32_t>(),
+                             g->idx.as<int32_t>(), g->weighted ? g->w.as<int32_t>() : nullptr, g->inv.as<int32_t>(),
+                             idx2.as<int32_t>(), g->weighted ? w2.as<int32_t>() : nullptr, s));
+    HIP_TRY(launch_gather_i32(g->k.as<int32_t>(), g->orig.as<int32_t>(), n, k2.as<int32_t>(), s));
+    HIP_TRY(hipStreamSynchronize(s));
+    g->off.swap(off2);
+    g->idx.swap(idx2);
+    if (g->weighted) g->w.swap(w2);
+    g->k.swap(k2);
+    g->reordered = true;
+    ws.keys.release();
+    ws.keys_alt.release();
+    ws.vals.release();
+    ws.vals_alt.release();
+    return LV_OK;
+}
 
 // Device setup of a packed CSR (offsets/indices/weights in `kind` memory,
 // graph g at vertices [voff[g], voff[g+1])): validation, loop doubling,
@@ -1326,6 +1413,7 @@ static lv_status graph_setup(lv_graph* g, int32_t n, const int32_t* offsets, con
         HIP_TRY(hipMemcpyAsync(g->d_M.p, g->M.data(), sizeof(int64_t) * (size_t)G, hipMemcpyHostToDevice, s));
         HIP_TRY(hipStreamSynchronize(s));
     }
+    if (!(flags & LV_KEEP_ORDER)) LV_TRY(reorder_by_degree(g));
     return LV_OK;
 }
 
@@ -1669,6 +1757,11 @@ lv_status lv_modularity(lv_graph* g, const int32_t* labels, lv_memkind kind, int
         if (g->n > 0)
             HIP_TRY(hipMemcpyAsync(ws.labels.p, labels, sizeof(int32_t) * (size_t)g->n, hipMemcpyHostToDevice, g->stream));
         dl = ws.labels.as<int32_t>();
+    }
+    if (g->reordered && g->n > 0) {  // to storage positions
+        HIP_TRY(ws.pos.ensure(sizeof(int32_t) * ((size_t)g->n + 1)));
+        HIP_TRY(launch_gather_i32(dl, g->orig.as<int32_t>(), g->n, ws.pos.as<int32_t>(), g->stream));
+        dl = ws.pos.as<int32_t>();
     }
     int64_t qi = 0;
     LV_TRY(modularity_impl(g, dl, &qi));

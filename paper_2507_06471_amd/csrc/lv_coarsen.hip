@@ -14,17 +14,23 @@ using namespace dev;
 
 namespace {
 
-__global__ void k_minv(int32_t n, const int32_t* comm, int32_t* minv)
+// Vertices are stored at positions i; orig[i] is the vertex id (null: i).
+// Community ids are vertex ids, and renumbering goes by the smallest member
+// id, so minv and the first-member flags are indexed by id.
+__global__ void k_minv(int32_t n, const int32_t* comm, const int32_t* orig, int32_t* minv)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const int32_t c = comm[i];
-        if (minv[c] > (int32_t)i) atomicMin(&minv[c], (int32_t)i);  // read first: skips most contended atomics
+        const int32_t id = orig ? orig[i] : (int32_t)i;
+        if (minv[c] > id) atomicMin(&minv[c], id);  // read first: skips most contended atomics
     }
 }
-__global__ void k_first_flag(int32_t n, const int32_t* comm, const int32_t* minv, int32_t* flag)
+__global__ void k_first_flag(int32_t n, const int32_t* comm, const int32_t* orig, const int32_t* minv, int32_t* flag)
 {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        flag[i] = minv[comm[i]] == (int32_t)i ? 1 : 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t id = orig ? orig[i] : (int32_t)i;
+        flag[id] = minv[comm[i]] == id ? 1 : 0;
+    }
 }
 __global__ void k_label(int32_t n, const int32_t* comm, const int32_t* minv, const int32_t* pos, int32_t* labels)
 {
@@ -32,15 +38,14 @@ __global__ void k_label(int32_t n, const int32_t* comm, const int32_t* minv, con
         labels[i] = pos[minv[comm[i]]];
 }
 // coarse degree of community P = its volume Sigma_tot, and its graph id
-// (written by its smallest member)
-__global__ void k_coarse_degree(int32_t n, const int32_t* comm, const int32_t* flag, const int32_t* labels,
-                                const int32_t* sigma, const int32_t* gid, int32_t* k2, int32_t* gid2)
+// (every member writes the same values)
+__global__ void k_coarse_degree(int32_t n, const int32_t* comm, const int32_t* labels, const int32_t* sigma,
+                                const int32_t* gid, int32_t* k2, int32_t* gid2)
 {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        if (flag[i]) {
-            k2[labels[i]] = sigma[comm[i]];
-            if (gid) gid2[labels[i]] = gid[i];
-        }
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        k2[labels[i]] = sigma[comm[i]];
+        if (gid) gid2[labels[i]] = gid[i];
+    }
 }
 
 // keys/vals per entry; sigma_in[g] += weight of graph g's entries inside one community.
@@ -201,9 +206,11 @@ __global__ void k_compose(int32_t n0, int32_t* fin, const int32_t* labels, const
 // [src_vb, src_vb + n) of its source CSR (their entries are contiguous and
 // only point inside the segment) to vertices [dst_vb, dst_vb + n) and
 // entries from dst_eb; indices are shifted accordingly; weights default to 1
-// and degrees are copied; gid of the new vertices = q.
+// and degrees are copied; gid of the new vertices = q; orig (if not null)
+// gets each new vertex's id: its segment's first id plus its id within the
+// segment (src_orig, else its position).
 __global__ void k_repack_vertices(const RepackSeg* seg, int32_t nseg, int32_t n_out, int32_t* off, int32_t* k,
-                                  int32_t* gid, int64_t nnz_out)
+                                  int32_t* gid, int32_t* orig, int64_t nnz_out)
 {
     for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n_out; u += (int64_t)gridDim.x * blockDim.x) {
         int32_t lo = 0, hi = nseg;  // last segment with dst_vb <= u
@@ -217,6 +224,7 @@ __global__ void k_repack_vertices(const RepackSeg* seg, int32_t nseg, int32_t n_
         off[u] = (int32_t)(q.src_off[q.src_vb + x] - src_e0 + q.dst_eb);
         k[u] = q.src_k[q.src_vb + x];
         if (gid) gid[u] = lo;
+        if (orig) orig[u] = q.dst_vb + (q.src_orig ? q.src_orig[q.src_vb + x] - q.src_vb : (int32_t)x);
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) off[n_out] = (int32_t)nnz_out;
 }
@@ -252,24 +260,24 @@ hipError_t launch_local_labels(int32_t n, const int32_t* labels, const int32_t* 
     return hipGetLastError();
 }
 
-hipError_t launch_renumber(int32_t n, const int32_t* comm, int32_t* minv, int32_t* flag, int32_t* pos, int32_t* labels,
-                           int32_t* n_out, void* tmp, size_t tb, hipStream_t s)
+hipError_t launch_renumber(int32_t n, const int32_t* comm, const int32_t* orig, int32_t* minv, int32_t* flag,
+                           int32_t* pos, int32_t* labels, int32_t* n_out, void* tmp, size_t tb, hipStream_t s)
 {
     if (n <= 0) return hipMemsetAsync(n_out, 0, sizeof(int32_t), s);
     hipError_t e = launch_fill_i32(minv, INT32_MAX, n, s);
     if (e != hipSuccess) return e;
-    k_minv<<<LV_GRID(n)>>>(n, comm, minv);
-    k_first_flag<<<LV_GRID(n)>>>(n, comm, minv, flag);
+    k_minv<<<LV_GRID(n)>>>(n, comm, orig, minv);
+    k_first_flag<<<LV_GRID(n)>>>(n, comm, orig, minv, flag);
     e = scan_exclusive_i32(flag, pos, n, n_out, tmp, tb, s);
     if (e != hipSuccess) return e;
     k_label<<<LV_GRID(n)>>>(n, comm, minv, pos, labels);
     return hipGetLastError();
 }
-hipError_t launch_coarse_degree(int32_t n, const int32_t* comm, const int32_t* flag, const int32_t* labels,
-                                const int32_t* sigma, const int32_t* gid, int32_t* k2, int32_t* gid2, hipStream_t s)
+hipError_t launch_coarse_degree(int32_t n, const int32_t* comm, const int32_t* labels, const int32_t* sigma,
+                                const int32_t* gid, int32_t* k2, int32_t* gid2, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    k_coarse_degree<<<LV_GRID(n)>>>(n, comm, flag, labels, sigma, gid, k2, gid2);
+    k_coarse_degree<<<LV_GRID(n)>>>(n, comm, labels, sigma, gid, k2, gid2);
     return hipGetLastError();
 }
 hipError_t launch_build_keys(int32_t n, const int32_t* off, const int32_t* idx, const int32_t* w, int64_t nnz,
@@ -282,10 +290,10 @@ hipError_t launch_build_keys(int32_t n, const int32_t* off, const int32_t* idx, 
     return hipGetLastError();
 }
 hipError_t launch_repack(const RepackSeg* seg, int32_t nseg, int32_t n_out, int64_t nnz_out, int32_t* off, int32_t* idx,
-                         int32_t* w, int32_t* k, int32_t* gid, hipStream_t s)
+                         int32_t* w, int32_t* k, int32_t* gid, int32_t* orig, hipStream_t s)
 {
     if (nseg <= 0) return hipSuccess;
-    k_repack_vertices<<<LV_GRID((int64_t)n_out + 1)>>>(seg, nseg, n_out, off, k, gid, nnz_out);
+    k_repack_vertices<<<LV_GRID((int64_t)n_out + 1)>>>(seg, nseg, n_out, off, k, gid, orig, nnz_out);
     if (nnz_out > 0) k_repack_entries<<<LV_GRID(nnz_out)>>>(seg, nseg, nnz_out, idx, w);
     return hipGetLastError();
 }

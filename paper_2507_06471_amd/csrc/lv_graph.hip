@@ -221,7 +221,99 @@ __global__ void k_check_labels(const int32_t* labels, int32_t n, int32_t* err)
         if (labels[i] < 0 || labels[i] >= n) atomicOr(err, 1);
 }
 
+// ---- storage order by descending degree
+// key of position v: graph id above (maxdeg - degree), so that a stable sort
+// keeps each packed graph's segment in place and puts its high-degree
+// vertices first (ties keep their order)
+__global__ void k_degree_keys(int32_t n, const int32_t* off, const int32_t* gid, int32_t maxdeg, int db, uint64_t* keys,
+                              int32_t* vals)
+{
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t g = gid ? (uint64_t)gid[v] : 0ull;
+        keys[v] = (g << db) | (uint64_t)(maxdeg - (off[v + 1] - off[v]));
+        vals[v] = (int32_t)v;
+    }
+}
+__global__ __launch_bounds__(256) void k_max_degree(int32_t n, const int32_t* off, int32_t* out)
+{
+    int32_t m = 0;
+    for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < n; v += (int64_t)gridDim.x * 256)
+        m = max(m, off[v + 1] - off[v]);
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) m = max(m, __shfl_xor(m, d));
+    if (lane_id() == 0) atomicMax(out, m);
+}
+__global__ void k_inverse(const int32_t* perm, int32_t n, int32_t* inv)
+{
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
+        inv[perm[q]] = (int32_t)q;
+}
+__global__ void k_perm_lengths(const int32_t* perm, int32_t n, const int32_t* off, int32_t* len)
+{
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t v = perm[q];
+        len[q] = off[v + 1] - off[v];
+    }
+}
+// new row q = old row perm[q], its column positions mapped through inv
+__global__ __launch_bounds__(TILE_BS) void k_perm_rows(int32_t n, const int32_t* off_new, int64_t nnz,
+                                                        const int32_t* perm, const int32_t* off, const int32_t* idx,
+                                                        const int32_t* w, const int32_t* inv, int32_t* idx_new,
+                                                        int32_t* w_new)
+{
+    for_tile_entries<TILE_BS, TILE_IT>(off_new, n, nnz, [&](int32_t q, int64_t e) {
+        const int64_t src = (int64_t)off[perm[q]] + (e - off_new[q]);
+        idx_new[e] = inv[idx[src]];
+        if (w) w_new[e] = w[src];
+    });
+}
+__global__ void k_scatter_i32(const int32_t* src, const int32_t* idx, int32_t m, int32_t* dst)
+{
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < m; t += (int64_t)gridDim.x * blockDim.x)
+        dst[idx[t]] = src[t];
+}
+
 }  // namespace
+
+hipError_t launch_degree_keys(int32_t n, const int32_t* off, const int32_t* gid, int32_t maxdeg, int db, uint64_t* keys,
+                              int32_t* vals, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    k_degree_keys<<<LV_GRID(n)>>>(n, off, gid, maxdeg, db, keys, vals);
+    return hipGetLastError();
+}
+hipError_t launch_max_degree(int32_t n, const int32_t* off, int32_t* out, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    k_max_degree<<<grid_for(n, 256, 4096), 256, 0, s>>>(n, off, out);
+    return hipGetLastError();
+}
+hipError_t launch_inverse(const int32_t* perm, int32_t n, int32_t* inv, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    k_inverse<<<LV_GRID(n)>>>(perm, n, inv);
+    return hipGetLastError();
+}
+hipError_t launch_perm_lengths(const int32_t* perm, int32_t n, const int32_t* off, int32_t* len, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    k_perm_lengths<<<LV_GRID(n)>>>(perm, n, off, len);
+    return hipGetLastError();
+}
+hipError_t launch_perm_rows(int32_t n, const int32_t* off_new, int64_t nnz, const int32_t* perm, const int32_t* off,
+                            const int32_t* idx, const int32_t* w, const int32_t* inv, int32_t* idx_new, int32_t* w_new,
+                            hipStream_t s)
+{
+    if (nnz <= 0) return hipSuccess;
+    k_perm_rows<<<tiles_for(n, nnz), TILE_BS, 0, s>>>(n, off_new, nnz, perm, off, idx, w, inv, idx_new, w_new);
+    return hipGetLastError();
+}
+hipError_t launch_scatter_i32(const int32_t* src, const int32_t* idx, int32_t m, int32_t* dst, hipStream_t s)
+{
+    if (m <= 0) return hipSuccess;
+    k_scatter_i32<<<LV_GRID(m)>>>(src, idx, m, dst);
+    return hipGetLastError();
+}
 
 hipError_t launch_check_offsets(int32_t n, const int32_t* off, int64_t nnz, int32_t* err, hipStream_t s)
 {

@@ -71,6 +71,7 @@ struct RepackSeg {
     const int32_t* src_idx;
     const int32_t* src_w;   // null = unit weights
     const int32_t* src_k;
+    const int32_t* src_orig; // vertex id of each source position (null: the position)
     int32_t src_vb;         // first source vertex
     int32_t n;              // vertices
     int32_t dst_vb;         // first destination vertex
@@ -216,17 +217,29 @@ hipError_t launch_sweep_end(SweepCtl* ctl, int32_t G, int32_t* gdone, int32_t* g
                             int32_t max_sweeps, int64_t theta, hipStream_t s);
 
 // renumber + aggregation
-hipError_t launch_renumber(int32_t n, const int32_t* comm, int32_t* minv, int32_t* flag, int32_t* pos,
-                           int32_t* labels, int32_t* n_out, void* tmp, size_t tmp_bytes, hipStream_t s);
-hipError_t launch_coarse_degree(int32_t n, const int32_t* comm, const int32_t* flag, const int32_t* labels,
-                                const int32_t* sigma, const int32_t* gid, int32_t* k2, int32_t* gid2, hipStream_t s);
+hipError_t launch_renumber(int32_t n, const int32_t* comm, const int32_t* orig, int32_t* minv, int32_t* flag,
+                           int32_t* pos, int32_t* labels, int32_t* n_out, void* tmp, size_t tb, hipStream_t s);
+hipError_t launch_coarse_degree(int32_t n, const int32_t* comm, const int32_t* labels, const int32_t* sigma,
+                                const int32_t* gid, int32_t* k2, int32_t* gid2, hipStream_t s);
+// Storage order by descending degree (within each packed graph): keys for
+// the sort, the inverse map, the permuted row lengths and rows.
+hipError_t launch_degree_keys(int32_t n, const int32_t* off, const int32_t* gid, int32_t maxdeg, int db, uint64_t* keys,
+                              int32_t* vals, hipStream_t s);
+hipError_t launch_max_degree(int32_t n, const int32_t* off, int32_t* out, hipStream_t s);
+hipError_t launch_inverse(const int32_t* perm, int32_t n, int32_t* inv, hipStream_t s);
+hipError_t launch_perm_lengths(const int32_t* perm, int32_t n, const int32_t* off, int32_t* len, hipStream_t s);
+hipError_t launch_perm_rows(int32_t n, const int32_t* off_new, int64_t nnz, const int32_t* perm, const int32_t* off,
+                            const int32_t* idx, const int32_t* w, const int32_t* inv, int32_t* idx_new, int32_t* w_new,
+                            hipStream_t s);
+// dst[idx[t]] = src[t]
+hipError_t launch_scatter_i32(const int32_t* src, const int32_t* idx, int32_t m, int32_t* dst, hipStream_t s);
 // keys = (label(i) << colbits) | label(j); sigma_in[g] += weight inside communities (caller zeroes it)
 hipError_t launch_build_keys(int32_t n, const int32_t* off, const int32_t* idx, const int32_t* w,
                              int64_t nnz, const int32_t* labels, int colbits, uint64_t* keys, int32_t* vals,
                              const int32_t* gid, int64_t* sigma_in, hipStream_t s);
 // rebuild a packed CSR (off[n_out+1], idx/w[nnz_out], k, gid) from device segment descriptors
-hipError_t launch_repack(const RepackSeg* seg, int32_t nseg, int32_t n_out, int64_t nnz_out, int32_t* off,
-                         int32_t* idx, int32_t* w, int32_t* k, int32_t* gid, hipStream_t s);
+hipError_t launch_repack(const RepackSeg* seg, int32_t nseg, int32_t n_out, int64_t nnz_out, int32_t* off, int32_t* idx,
+                         int32_t* w, int32_t* k, int32_t* gid, int32_t* orig, hipStream_t s);
 hipError_t launch_segment_heads(const uint64_t* keys, int64_t n, int32_t* head, hipStream_t s);
 // w2 must be zeroed; writes idx2/w2/keys2 of each run of equal keys
 hipError_t launch_segment_reduce(const uint64_t* keys, const int32_t* vals, const int32_t* pos, int64_t n,

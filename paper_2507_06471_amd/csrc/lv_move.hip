@@ -145,7 +145,8 @@ __device__ __forceinline__ void score_entries_singleton(const MoveArgs& a, int32
 {
     const bool louvain = a.mode == MODE_LOUVAIN;
     for (int32_t e0 = e_beg; e0 < e_end; e0 += STRIDE * UNROLL) {
-        int32_t jj[UNROLL], ww[UNROLL], sg[UNROLL];
+        int32_t jj[UNROLL], ww[UNROLL];
+        int2 cc[UNROLL];
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
             const int32_t e = e0 + u * STRIDE;
@@ -153,13 +154,15 @@ __device__ __forceinline__ void score_entries_singleton(const MoveArgs& a, int32
             jj[u] = ok ? __builtin_nontemporal_load(&a.idx[e]) : i;
             ww[u] = (ok && a.w) ? __builtin_nontemporal_load(&a.w[e]) : 1;
         }
+        // A singleton neighbour's community is its vertex id, which differs
+        // from its storage position when rows are kept in degree order.
 #pragma unroll
-        for (int u = 0; u < UNROLL; ++u) sg[u] = (louvain && jj[u] != i) ? a.cs[jj[u]].y : 0;
+        for (int u = 0; u < UNROLL; ++u) cc[u] = jj[u] != i ? a.cs[jj[u]] : make_int2(0, 0);
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
             if (jj[u] == i) continue;
-            const int64_t s = louvain ? M * ww[u] - ki * (int64_t)sg[u] : (int64_t)ww[u];
-            if (better(s, jj[u], best_s, best_c)) { best_s = s; best_c = jj[u]; }
+            const int64_t s = louvain ? M * ww[u] - ki * (int64_t)cc[u].y : (int64_t)ww[u];
+            if (better(s, cc[u].x, best_s, best_c)) { best_s = s; best_c = cc[u].x; }
         }
     }
 }
@@ -276,6 +279,23 @@ __device__ __forceinline__ void scan_table(const MoveArgs& a, const int32_t* key
     }
 }
 
+// Make a group's LDS writes visible to the whole group.  A group within one
+// wavefront needs no workgroup barrier: a wavefront's LDS operations are
+// performed in order, so a wavefront-scope fence (which keeps the compiler
+// from moving LDS accesses across it) suffices, and the wavefronts of a
+// workgroup do not wait for each other.
+template <int G>
+__device__ __forceinline__ void group_sync()
+{
+    if constexpr (G <= WAVE) {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
 // One group of G lanes per vertex (G <= BS); LDS table of up to SLOTS slots.
 // (CLS only names the instantiation, so each degree class has its own kernel symbol)
 template <int CLS, int BS, int G, int SLOTS, bool SINGLETON, bool SIG>
@@ -312,9 +332,9 @@ __global__ __launch_bounds__(BS) void k_move(MoveArgs a)
         int32_t* sig = SIG ? s_sig + g * SLOTS : s_sig;
         const uint32_t T = min((uint32_t)SLOTS, pow2_at_least(2u * (uint32_t)(end - beg)));
         for (uint32_t t = lane; t < T; t += G) { key[t] = EMPTY_KEY; val[t] = 0; }
-        __syncthreads();
+        group_sync<G>();
         aggregate_entries<G, false, SIG>(a, i, beg + lane, end, key, val, sig, T - 1u, 1u, 0u);
-        __syncthreads();
+        group_sync<G>();
         scan_table<G, SIG>(a, key, val, sig, lane, T, A, ki, M, best_s, best_c, w_own);
     }
 

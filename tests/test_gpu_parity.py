@@ -18,10 +18,10 @@ def say(*a):
     sys.stdout.flush()
 
 
-def compare_louvain(g, tuning=None, max_sweeps=20, max_levels=32, keep_graphs=False, device=False):
-    say(f"case {g.name or 'graph'} n={g.n} nnz={g.nnz} tuning={tuning}")
+def compare_louvain(g, tuning=None, max_sweeps=20, max_levels=32, keep_graphs=False, device=False, keep_order=False):
+    say(f"case {g.name or 'graph'} n={g.n} nnz={g.nnz} tuning={tuning} keep_order={keep_order}")
     want = oracle.louvain(g, max_sweeps=max_sweeps, max_levels=max_levels, keep_graphs=keep_graphs)
-    with lvp.Graph.from_csr(g, device=device) as dg:
+    with lvp.Graph.from_csr(g, device=device, keep_order=keep_order) as dg:
         got = lvp.louvain(dg, max_sweeps=max_sweeps, max_levels=max_levels, keep_graphs=keep_graphs,
                           tuning=tuning)
     assert got.M == want.M
@@ -44,10 +44,10 @@ def compare_louvain(g, tuning=None, max_sweeps=20, max_levels=32, keep_graphs=Fa
     return got, want
 
 
-def compare_lpa(g, max_sweeps=20, threshold=0, tuning=None):
+def compare_lpa(g, max_sweeps=20, threshold=0, tuning=None, keep_order=False):
     say(f"lpa case {g.name or 'graph'} n={g.n} nnz={g.nnz}")
     want = oracle.lpa(g, max_sweeps=max_sweeps, theta=threshold)
-    with lvp.Graph.from_csr(g) as dg:
+    with lvp.Graph.from_csr(g, keep_order=keep_order) as dg:
         got = lvp.lpa(dg, max_sweeps=max_sweeps, threshold=threshold, tuning=tuning)
     assert got.moves == [int(x) for x in want.moves]
     assert np.array_equal(got.labels, want.labels)
@@ -126,6 +126,25 @@ def test_weighted_bucketed_partitions(tuning):
 def test_device_resident_input():
     pytest.importorskip("torch")
     compare_louvain(graphgen.rmat(12, seed=8), device=True)
+
+
+@pytest.mark.parametrize("maker", ["rmat", "lfr", "tiny"])
+def test_input_order_storage_gives_same_results(maker):
+    # LV_KEEP_ORDER stores the input order; the default stores by degree
+    if maker == "rmat":
+        g = graphgen.rmat(13, seed=21)
+    elif maker == "lfr":
+        g, _ = graphgen.lfr(8000, kmax=400, smin=20, smax=800, seed=22)
+    else:
+        rng = np.random.default_rng(23)
+        g = bf.to_csr(40, bf.random_graph(rng, 40, 0.2, 9, True))
+        g.name = "tiny23"
+    compare_louvain(g, keep_graphs=True, keep_order=True)
+    compare_lpa(g, keep_order=True)
+    rng = np.random.default_rng(24)
+    lab = rng.integers(0, max(1, g.n // 3), size=g.n).astype(np.int32)
+    with lvp.Graph.from_csr(g) as a, lvp.Graph.from_csr(g, keep_order=True) as b:
+        assert lvp.modularity(a, lab) == lvp.modularity(b, lab) == oracle.modularity(g, lab)
 
 
 def test_modularity_of_arbitrary_labels():
