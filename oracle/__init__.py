@@ -70,9 +70,10 @@ def _configure(lib):
                                         ctypes.c_int, ctypes.c_int, _i32p, i32, _i32p]
     lib.orc_decide_vertices.restype = ctypes.c_int
     lib.orc_sweep.argtypes = [i32, _i32p, _i32p, _i32p, _i64p, i64, _i32p, _i64p, ctypes.c_int,
-                              ctypes.c_int, _i32p]
+                              ctypes.c_int, ctypes.c_void_p, _i32p]
     lib.orc_sweep.restype = i64
-    lib.orc_local_move.argtypes = [i32, _i32p, _i32p, _i32p, ctypes.c_int, i32, i64, _i32p, _i64p]
+    lib.orc_local_move.argtypes = [i32, _i32p, _i32p, _i32p, ctypes.c_int, i32, i64, ctypes.c_int, _i32p,
+                                   _i64p]
     lib.orc_local_move.restype = i32
     lib.orc_renumber.argtypes = [i32, _i32p, _i32p]
     lib.orc_renumber.restype = i32
@@ -156,14 +157,16 @@ def modularity(g, labels) -> tuple:
     return q, m, q_float(q, m)
 
 
-def sweep(adj: Adj, c, sigma, direction: int, mode: int = LOUVAIN):
-    """One synchronous sweep against state (c, sigma); returns (c_next, moves)."""
+def sweep(adj: Adj, c, sigma, direction: int, mode: int = LOUVAIN, active=None):
+    """One synchronous sweep against state (c, sigma); returns (c_next, moves).
+    `active` (bool per vertex, None = all) limits which vertices are evaluated."""
     k, M = degrees(adj)
     c = np.ascontiguousarray(c, dtype=np.int32)
     sigma = np.ascontiguousarray(sigma, dtype=np.int64)
     nxt = np.empty(adj.n, dtype=np.int32)
+    act = None if active is None else np.ascontiguousarray(active, dtype=np.uint8)
     mv = _load().orc_sweep(adj.n, _p32(adj.off), _p32(adj.idx), _p32(adj.a), _p64(k), M, _p32(c),
-                           _p64(sigma), direction, mode, _p32(nxt))
+                           _p64(sigma), direction, mode, None if act is None else act.ctypes.data, _p32(nxt))
     if mv < 0:
         raise MemoryError("oracle sweep")
     return nxt, int(mv)
@@ -185,12 +188,13 @@ def decide_vertices(adj: Adj, verts, c, sigma, direction: int, mode: int = LOUVA
     return out
 
 
-def local_move(adj: Adj, mode: int = LOUVAIN, max_sweeps: int = 20, theta: int = 0):
-    """One level from singletons; returns (labels c, per-sweep moves)."""
+def local_move(adj: Adj, mode: int = LOUVAIN, max_sweeps: int = 20, theta: int = 0, prune: bool = False):
+    """One level from singletons; returns (labels c, per-sweep moves).  With
+    `prune`, only active vertices are evaluated (rule in lv_oracle.c)."""
     c = np.empty(adj.n, dtype=np.int32)
     moves = np.zeros(max_sweeps, dtype=np.int64)
     s = _load().orc_local_move(adj.n, _p32(adj.off), _p32(adj.idx), _p32(adj.a), mode, max_sweeps,
-                               theta, _p32(c), _p64(moves))
+                               theta, int(bool(prune)), _p32(c), _p64(moves))
     if s < 0:
         raise RuntimeError(f"oracle local_move failed ({-s})")
     return c, moves[:s].copy()
@@ -247,7 +251,7 @@ class LouvainResult:
         return [lv for lv in self.levels if lv.accepted]
 
 
-def louvain(g, max_sweeps: int = 20, max_levels: int = 32, keep_graphs: bool = False):
+def louvain(g, max_sweeps: int = 20, max_levels: int = 32, keep_graphs: bool = False, prune: bool = False):
     """Multi-level Louvain (Alg. 3) under the oracle's deterministic semantics.
 
     Level l: Q_start = Q_int of singletons on G_l; local moving; renumber;
@@ -263,7 +267,7 @@ def louvain(g, max_sweeps: int = 20, max_levels: int = 32, keep_graphs: bool = F
     graphs = [adj]
     while True:
         q_start = singleton_qint(adj)
-        c, moves = local_move(adj, LOUVAIN, max_sweeps, 0)
+        c, moves = local_move(adj, LOUVAIN, max_sweeps, 0, prune)
         labels, n2 = renumber(c)
         adj2 = aggregate(adj, labels, n2)
         q_end = singleton_qint(adj2)
@@ -295,10 +299,10 @@ class LpaResult:
     q: float
 
 
-def lpa(g, max_sweeps: int = 20, theta: int = 0) -> LpaResult:
+def lpa(g, max_sweeps: int = 20, theta: int = 0, prune: bool = False) -> LpaResult:
     """Label propagation (Alg. 1) as one level of synchronous sweeps, then renumber."""
     adj = adjacency(g)
-    c, moves = local_move(adj, LPA, max_sweeps, theta)
+    c, moves = local_move(adj, LPA, max_sweeps, theta, prune)
     labels, _ = renumber(c)
     q, M = modularity_int(adj, labels)
     return LpaResult(labels, moves, q, M, q_float(q, M))

@@ -177,10 +177,14 @@ int orc_decide_vertices(int32_t n, const int32_t* off, const int32_t* idx, const
     return rc;
 }
 
-/* One synchronous sweep over all vertices; returns the number of movers (or -1). */
+/*
+ * One synchronous sweep; returns the number of movers (or -1).  With an
+ * `active` mask (NULL = every vertex) a vertex whose mask byte is 0 is not
+ * evaluated and keeps its community.
+ */
 int64_t orc_sweep(int32_t n, const int32_t* off, const int32_t* idx, const int32_t* a,
                   const int64_t* k, int64_t M, const int32_t* c, const int64_t* sigma, int dir, int mode,
-                  int32_t* c_next)
+                  const uint8_t* active, int32_t* c_next)
 {
     int64_t moves = 0;
     int failed = 0;
@@ -196,7 +200,8 @@ int64_t orc_sweep(int32_t n, const int32_t* off, const int32_t* idx, const int32
             for (int32_t t = 0; t < n; ++t) mark[t] = -1;
 #pragma omp for schedule(dynamic, 1024)
             for (int32_t i = 0; i < n; ++i) {
-                c_next[i] = decide(i, off, idx, a, k, M, c, sigma, dir, mode, acc, mark, list, i);
+                c_next[i] = (active && !active[i]) ? c[i]
+                                                   : decide(i, off, idx, a, k, M, c, sigma, dir, mode, acc, mark, list, i);
                 if (c_next[i] != c[i]) ++moves;
             }
         }
@@ -213,29 +218,61 @@ int64_t orc_sweep(int32_t n, const int32_t* off, const int32_t* idx, const int32
  * moved at most `theta` vertices (theta = 0 for Louvain), or when s reaches
  * max_sweeps.  Writes the final labels to c and the per-sweep mover counts
  * to moves[0..sweeps-1]; returns the sweep count (or a negative error).
+ *
+ * prune != 0 restricts evaluation to active vertices (Alg. 1's V_active and
+ * Alg. 2's needCheck: a vertex is reconsidered only after its own community
+ * or a neighbour's changed).  Under synchronous sweeps whose direction
+ * alternates, a vertex is evaluated in sweep s when s <= 2, or when it or one
+ * of its neighbours changed community in sweep s-1 or in sweep s-2; the second
+ * sweep back covers a move the previous sweep's direction did not allow.
+ * Vertices that are not evaluated keep their community.
  */
 int32_t orc_local_move(int32_t n, const int32_t* off, const int32_t* idx, const int32_t* a, int mode,
-                       int32_t max_sweeps, int64_t theta, int32_t* c, int64_t* moves)
+                       int32_t max_sweeps, int64_t theta, int prune, int32_t* c, int64_t* moves)
 {
     if (max_sweeps < 1) return -ORC_E_ARG;
-    int64_t* k = (int64_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
-    int64_t* sigma = (int64_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
-    int32_t* nxt = (int32_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
-    if (!k || !sigma || !nxt) { free(k); free(sigma); free(nxt); return -ORC_E_NOMEM; }
+    const size_t nn = (size_t)(n > 0 ? n : 1);
+    int64_t* k = (int64_t*)malloc(nn * sizeof(int64_t));
+    int64_t* sigma = (int64_t*)malloc(nn * sizeof(int64_t));
+    int32_t* nxt = (int32_t*)malloc(nn * sizeof(int32_t));
+    uint8_t* chg1 = (uint8_t*)calloc(nn, 1);  /* changed in the previous sweep */
+    uint8_t* chg2 = (uint8_t*)calloc(nn, 1);  /* changed in the sweep before it */
+    uint8_t* act = (uint8_t*)malloc(nn);
+    if (!k || !sigma || !nxt || !chg1 || !chg2 || !act) {
+        free(k); free(sigma); free(nxt); free(chg1); free(chg2); free(act);
+        return -ORC_E_NOMEM;
+    }
     int64_t M = orc_degrees(n, off, a, k);
     for (int32_t i = 0; i < n; ++i) { c[i] = i; sigma[i] = k[i]; }
     int32_t s;
+    int rc = 0;
     for (s = 1; s <= max_sweeps; ++s) {
         int dir = (s % 2 == 1) ? ORC_DOWN : ORC_UP;
-        int64_t mv = orc_sweep(n, off, idx, a, k, M, c, sigma, dir, mode, nxt);
-        if (mv < 0) { free(k); free(sigma); free(nxt); return -ORC_E_NOMEM; }
+        const uint8_t* mask = NULL;
+        if (prune && s > 2) {
+            for (int32_t i = 0; i < n; ++i) act[i] = chg1[i] | chg2[i];
+            mask = act;
+        }
+        int64_t mv = orc_sweep(n, off, idx, a, k, M, c, sigma, dir, mode, mask, nxt);
+        if (mv < 0) { rc = -ORC_E_NOMEM; break; }
         moves[s - 1] = mv;
+        if (prune) {
+            /* chg2 <- chg1, then chg1 <- {movers and every neighbour of a mover} */
+            uint8_t* t = chg2; chg2 = chg1; chg1 = t;
+            memset(chg1, 0, nn);
+            for (int32_t i = 0; i < n; ++i)
+                if (nxt[i] != c[i]) {
+                    chg1[i] = 1;
+                    for (int32_t e = off[i]; e < off[i + 1]; ++e) chg1[idx[e]] = 1;
+                }
+        }
         memcpy(c, nxt, (size_t)n * sizeof(int32_t));
         for (int32_t i = 0; i < n; ++i) sigma[i] = 0;
         for (int32_t i = 0; i < n; ++i) sigma[c[i]] += k[i];
         if (s >= 2 && moves[s - 1] <= theta && moves[s - 2] <= theta) break;
     }
-    free(k); free(sigma); free(nxt);
+    free(k); free(sigma); free(nxt); free(chg1); free(chg2); free(act);
+    if (rc) return rc;
     return s > max_sweeps ? max_sweeps : s;
 }
 

@@ -92,6 +92,42 @@ def sweep(A, labels, down: bool, lpa: bool = False) -> List[int]:
     return [decide(A, labels, i, down, lpa) for i in range(len(A))]
 
 
+def local_move(A, lpa: bool = False, prune: bool = False, max_sweeps: int = 20, theta: int = 0):
+    """One level of synchronous sweeps from singletons, every decision by
+    `decide`; returns (labels, per-sweep mover counts).
+
+    With `prune`, the set of vertices evaluated in sweep s is read off the
+    label history: every vertex while s <= 2, afterwards vertex i only if some
+    vertex of {i} and its neighbours carries a different label after sweep
+    s-1 than after s-2, or after s-2 than after s-3.  Other vertices keep
+    their label.  The level ends after two consecutive sweeps with at most
+    `theta` movers, or after `max_sweeps`.
+    """
+    n = len(A)
+    hist = [list(range(n))]  # hist[t] = labels after sweep t
+
+    def changed_in(t: int, j: int) -> bool:
+        return t >= 1 and hist[t][j] != hist[t - 1][j]
+
+    moves: List[int] = []
+    for s in range(1, max_sweeps + 1):
+        cur = hist[-1]
+        down = s % 2 == 1
+        nxt = []
+        for i in range(n):
+            if prune and s > 2:
+                closed = [i] + [j for j in range(n) if j != i and A[i][j] > 0]
+                if not any(changed_in(s - 1, j) or changed_in(s - 2, j) for j in closed):
+                    nxt.append(cur[i])
+                    continue
+            nxt.append(decide(A, cur, i, down, lpa))
+        moves.append(sum(a != b for a, b in zip(cur, nxt)))
+        hist.append(nxt)
+        if s >= 2 and moves[-1] <= theta and moves[-2] <= theta:
+            break
+    return hist[-1], moves
+
+
 def random_graph(rng: np.random.Generator, n: int, p: float, wmax: int, loops: bool):
     edges = []
     for u in range(n):

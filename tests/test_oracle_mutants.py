@@ -32,6 +32,9 @@ MUTANTS = {
     "stop_after_one_zero_sweep": ("if (s >= 2 && moves[s - 1] <= theta && moves[s - 2] <= theta) break;",
                                   "if (moves[s - 1] <= theta) break;"),
     "lpa_stay_ignores_own_label": (": wA;", ": 0;"),
+    "prune_one_sweep_back": ("act[i] = chg1[i] | chg2[i];", "act[i] = chg1[i];"),
+    "prune_ignores_neighbours": ("for (int32_t e = off[i]; e < off[i + 1]; ++e) chg1[idx[e]] = 1;", ""),
+    "prune_from_second_sweep": ("if (prune && s > 2) {", "if (prune && s > 1) {"),
 }
 
 
@@ -93,6 +96,27 @@ def detect() -> list:
     r = oracle.louvain(bf.to_csr(6, edges))
     if Fraction(r.q_int, r.M * r.M) != Fraction(5, 14) or list(r.levels[0].moves) != [3, 1, 0, 0]:
         failed.append("trace")
+    # pruned levels vs the brute-force replay (LPA on small graphs, Louvain on tiny ones)
+    prune_bad = False
+    for t in range(60):
+        lpa = t % 2 == 0
+        rng = np.random.default_rng(9500 + t)
+        n = int(rng.integers(2, 25 if lpa else 10))
+        edges = bf.random_graph(rng, n, float(rng.uniform(0.1, 0.6)), 5, bool(t % 3 == 0))
+        if not edges:
+            continue
+        A = bf.dense_adjacency(n, edges)
+        try:
+            adj = oracle.adjacency(bf.to_csr(n, edges))
+            c, mv = oracle.local_move(adj, oracle.LPA if lpa else oracle.LOUVAIN, 20, 0, True)
+        except (ValueError, RuntimeError):
+            prune_bad = True
+            break
+        if (list(c), list(mv)) != bf.local_move(A, lpa, True):
+            prune_bad = True
+            break
+    if prune_bad:
+        failed.append("prune")
     return failed
 
 
