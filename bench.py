@@ -83,6 +83,42 @@ def measured_traffic(slot: str):
     return None
 
 
+def prune_leg(args, lvp, dg, runs, phases, K, torch):
+    """The same job with active-vertex pruning (LV_PRUNE): only vertices whose
+    neighbourhood changed in the last two sweeps are evaluated.  Louvain's
+    partition differs from the full sweeps' (its Q is reported beside the
+    full one); LPA's must be identical.  Entries per second count every entry
+    of every executed sweep, as for the full sweeps, so they are an
+    equivalent rate, not bytes read."""
+    reps = []
+    for _ in range(args.prune_reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = lvp.louvain(dg, level_labels=False, prune=True)
+        lp = lvp.lpa(dg, prune=True)
+        torch.cuda.synchronize()
+        reps.append((time.perf_counter() - t0, r, lp))
+    lm = sum(lv.info["sweep_ms"] for _, r, _ in reps for lv in r.levels) / len(reps)
+    edges = sum(lv.info["nnz"] * lv.info["sweeps"] for lv in reps[0][1].levels)
+    lpa_ms = sum(lp.info["sweep_ms"] for _, _, lp in reps) / len(reps)
+    r, lp = reps[0][1], reps[0][2]
+    full_r, full_lp = runs[0]
+    lpa_same = full_lp.moves == lp.moves and bool((full_lp.labels == lp.labels).all())
+    if not lpa_same:
+        print("pruned LPA differs from full LPA", file=sys.stderr, flush=True)
+        sys.exit(1)
+    out = {"local_move_ms": round(lm, 3),
+           "local_move_speedup": round(phases["local_move_ms"] / K / lm, 3) if lm > 0 else None,
+           "equiv_gteps": round(edges / (lm * 1e-3) / 1e9, 3) if lm > 0 else None,
+           "ms_per_step": round(sum(t for t, _, _ in reps) / len(reps) * 1e3, 3),
+           "levels": len(r.accepted), "sweeps_per_level": [lv.info["sweeps"] for lv in r.levels],
+           "q": r.q, "q_full_sweeps": full_r.q,
+           "lpa_ms": round(lpa_ms, 3), "lpa_speedup": round(phases["lpa_ms"] / K / lpa_ms, 3) if lpa_ms > 0 else None,
+           "lpa_equal_to_full": lpa_same}
+    log(f"pruned: {out}")
+    return out
+
+
 def batch_leg(args, lvp, graphgen, np, torch):
     """Mixed batch of independent graphs: one packed handle (every graph in the
     same launches, sweeps captured as hipGraphs, autotuned classes) against
@@ -300,6 +336,8 @@ def main():
     ap.add_argument("--serve-load", type=float, default=0.8, help="arrival rate / one-per-call capacity")
     ap.add_argument("--serve-max-jobs", type=int, default=64)
     ap.add_argument("--serve-capacity-jobs", type=int, default=200, help="jobs of the saturated capacity runs")
+    ap.add_argument("--prune-reps", type=int, default=2,
+                    help="timed steps with active-vertex pruning (LV_PRUNE) after the main steps (0: skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB before the steps (PMC calibration)")
     args = ap.parse_args()
@@ -403,6 +441,8 @@ def main():
     qi, m, q = lvp.modularity(dg, r0.final_labels)
     assert (qi, m) == (r0.q_int, r0.M), "reported modularity differs from the labels' modularity"
 
+    pruned = prune_leg(args, lvp, dg, runs, phases, K, torch) if args.prune_reps > 0 else None
+
     parity = None
     cpu = None
     if not args.no_cpu_baseline or not args.no_parity:
@@ -479,6 +519,7 @@ def main():
         "lpa": {"gteps": round(lpa_gteps, 4), "sweeps": runs[0][1].info["sweeps"], "q": runs[0][1].info["q_end"] / float(dg.volume) ** 2},
         "phase_ms_per_step": {k_: round(v / K, 3) for k_, v in phases.items()},
         "kernels": kernels,
+        "pruned": pruned,
         "batch": batch,
         "serving": serving,
     }

@@ -76,6 +76,11 @@ typedef enum lv_memkind { LV_MEM_HOST = 0, LV_MEM_DEVICE = 1 } lv_memkind;
 #define LV_NO_HIPGRAPH 4u /* launch sweeps one by one even without LV_TIMING              */
 #define LV_AUTOTUNE 8u    /* with tuning == NULL: use the handle's autotuned setting (lv_autotune), */
                            /* chosen on the handle's first such call                               */
+#define LV_PRUNE 16u      /* active-vertex pruning (Alg. 1's V_active, Alg. 2's needCheck), read   */
+                          /* for synchronous sweeps: sweep s evaluates every vertex while s <= 2,   */
+                          /* afterwards only a vertex that, or one of whose neighbours, changed     */
+                          /* community in sweep s-1 or s-2; the others keep their community.        */
+                          /* Changes results (for Louvain; LPA's are provably the same).           */
 
 typedef struct lv_graph lv_graph;   /* device-resident CSR + workspace, library-owned */
 typedef struct lv_result lv_result; /* per-level labels and statistics, library-owned */

@@ -104,6 +104,7 @@ struct Workspace {
     DevBuf g_off[2], g_idx[2], g_w[2], g_k[2], g_gid[2];
     DevBuf hub_table, hub_meta, hub_part, hub_rows, hub_cnt, hub_bucket, hub_bucket_w;
     DevBuf rows;  // per-level row descriptors of the class-sorted vertices
+    DevBuf mark;  // active-vertex pruning: last sweep that changed the vertex's neighbourhood
     DevBuf k64;
     // per-graph state of a level (G entries) and sweep control
     DevBuf ctl, gdone, gsweeps, gmoves, gactive, gsum, gsq, gmeta, segs;
@@ -363,9 +364,15 @@ lv_status plan_hubs(lv_graph* g, const LevelGraph& G, const int32_t* hub_verts, 
     std::vector<int32_t> parts(nhubs), first_blk(nhubs + 1), blk_hub, blk_part;
     std::vector<int64_t> tab_off(nhubs);
     std::vector<int32_t> tab_cap(nhubs), ins_hub, ins_beg, ins_end, scan_hub, scan_beg, scan_end, fpart_first(nhubs + 1);
-    std::vector<int32_t> sc_hub, sc_beg, sc_end;
+    std::vector<int32_t> sc_hub, sc_beg, sc_end, mk_hub, mk_beg, mk_end;
     int64_t slots = 0;
+    constexpr int64_t MARK_CHUNK = 4096;  // entries per pruning-mark workgroup
     for (int32_t h = 0; h < nhubs; ++h) {
+        for (int64_t e = beg[h]; e < (int64_t)beg[h] + len[h]; e += MARK_CHUNK) {
+            mk_hub.push_back(h);
+            mk_beg.push_back((int32_t)e);
+            mk_end.push_back((int32_t)std::min<int64_t>(e + MARK_CHUNK, (int64_t)beg[h] + len[h]));
+        }
         const int64_t P = std::max<int64_t>(1, ((int64_t)len[h] + tu.part_keys - 1) / tu.part_keys);
         parts[h] = (int32_t)P;
         first_blk[h] = (int32_t)blk_hub.size();
@@ -410,6 +417,7 @@ lv_status plan_hubs(lv_graph* g, const LevelGraph& G, const int32_t* hub_verts, 
     const size_t o_cap = put(tab_cap), o_ih = put(ins_hub), o_ib = put(ins_beg), o_ie = put(ins_end);
     const size_t o_sh = put(scan_hub), o_sb = put(scan_beg), o_se = put(scan_end), o_ff = put(fpart_first);
     const size_t o_ch = put(sc_hub), o_cb = put(sc_beg), o_ce = put(sc_end);
+    const size_t o_mh = put(mk_hub), o_mb = put(mk_beg), o_me = put(mk_end);
     const size_t b64 = sizeof(int64_t) * (size_t)nhubs;
     HIP_TRY(ws.hub_meta.ensure(b64 + sizeof(int32_t) * pack.size() + 64));
     char* base = ws.hub_meta.as<char>();
@@ -446,6 +454,10 @@ lv_status plan_hubs(lv_graph* g, const LevelGraph& G, const int32_t* hub_verts, 
     a.sc_beg = p32 + o_cb;
     a.sc_end = p32 + o_ce;
     a.nsc = nsc;
+    a.mk_hub = p32 + o_mh;
+    a.mk_beg = p32 + o_mb;
+    a.mk_end = p32 + o_me;
+    a.nmk = (int32_t)mk_hub.size();
     a.sc_chunk = tu.sc_chunk;
     a.bucket_cap = tu.part_slots;
     if (tu.bucketed && nsc > 0) {
@@ -575,6 +587,13 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
     a.gdone = G.G > 1 ? ws.gdone.as<int32_t>() : nullptr;
     a.ctl = ctl;
     a.mode = mode;
+    int32_t* mark = nullptr;
+    if (p.flags & LV_PRUNE) {
+        HIP_TRY(ws.mark.ensure(nb));
+        mark = ws.mark.as<int32_t>();
+        HIP_TRY(launch_fill_i32(mark, 0, n, s));
+    }
+    a.mark = mark;
     int32_t* dec_all = ws.dec.as<int32_t>();
     const int64_t theta = mode == MODE_LPA ? p.lpa_threshold : 0;
 
@@ -611,6 +630,14 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
             if (e) HIP_TRY(tm.mark(&(*e)[2 * CLS_HUB + 1]));
         }
         if (e) HIP_TRY(tm.mark(&(*e)[2 * NUM_CLS + 1]));
+        if (mark) {
+            HIP_TRY(launch_mark_movers(ws.rows.as<int4>(), dec_all + start[CLS_L4], start[CLS_HUB] - start[CLS_L4], G.idx,
+                                       mark, ctl, s));
+            if (hubs.nhubs > 0) {
+                a.dec = dec_all + start[CLS_HUB];
+                HIP_TRY(launch_hub_mark(a, hubs.args, mark, s));
+            }
+        }
         HIP_TRY(launch_apply(vert_sorted + start[CLS_L4], dec_all + start[CLS_L4], active, G.k, a.gid,
                              ws.comm.as<int32_t>(), ws.sigma.as<int32_t>(), ctl, ws.gmoves.as<uint32_t>(), S, s));
         HIP_TRY(launch_pairs(n, ws.comm.as<int32_t>(), ws.sigma.as<int32_t>(), ws.cs.as<int2>(), ctl, s));

@@ -63,6 +63,8 @@ struct MoveArgs {
     int32_t nverts;
     int32_t mode;           // MODE_LOUVAIN / MODE_LPA
     int32_t* dec;           // decision per listed vertex: target community or -1
+    const int32_t* mark;    // active-vertex pruning: per vertex, the last sweep in which it or a
+                            // neighbour changed community (null: every vertex is evaluated)
 };
 
 // One segment of a packed CSR rebuild (see launch_repack).
@@ -111,6 +113,10 @@ struct HubArgs {
     const int32_t* sc_beg;
     const int32_t* sc_end;
     int32_t nsc;
+    const int32_t* mk_hub;         // pruning marks, workgroup b: entries [mk_beg, mk_end) of hub mk_hub
+    const int32_t* mk_beg;
+    const int32_t* mk_end;
+    int32_t nmk;
     // fallback: global open-addressing tables (2 ints per slot: key, value)
     const int64_t* tab_off;        // [nhubs] slot offset of the hub's table
     const int32_t* tab_cap;        // [nhubs] slots (power of two, 0 if P == 1)
@@ -204,6 +210,12 @@ hipError_t launch_hub_clear(int32_t* table, int64_t slots, hipStream_t s);
 hipError_t launch_hub_scatter(const MoveArgs& a, const HubArgs& h, hipStream_t s);
 // partition workgroups, merge and decision, global-table fallback
 hipError_t launch_hub_sweep(bool singleton, const MoveArgs& a, const HubArgs& h, hipStream_t s);
+// Active-vertex pruning: after the decisions of a sweep, record the sweep
+// number for every mover and every neighbour of a mover (rows: the m listed
+// vertices below the hub class; the hubs through their mark chunks).
+hipError_t launch_mark_movers(const int4* rows, const int32_t* dec, int32_t m, const int32_t* idx, int32_t* mark,
+                              const SweepCtl* ctl, hipStream_t s);
+hipError_t launch_hub_mark(const MoveArgs& a, const HubArgs& h, int32_t* mark, hipStream_t s);
 hipError_t launch_pairs(int32_t n, const int32_t* comm, const int32_t* sigma, int2* cs, const SweepCtl* ctl,
                         hipStream_t s);
 // commit the decisions dec[0..m) of vertices verts[0..m); per-graph movers into gmoves

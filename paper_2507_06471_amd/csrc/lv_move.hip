@@ -123,6 +123,17 @@ __device__ __forceinline__ bool vertex_frozen(const MoveArgs& a, int32_t i)
     return a.gdone && a.gdone[a.gid ? a.gid[i] : 0];
 }
 
+// Active-vertex pruning (Alg. 1's V_active, Alg. 2's needCheck) for
+// synchronous sweeps: sweep s evaluates every vertex while s <= 2, afterwards
+// only a vertex that, or one of whose neighbours, changed community in sweep
+// s-1 or s-2.  mark[i] holds the last such sweep (0 at the level's start).
+__device__ __forceinline__ bool vertex_skipped(const MoveArgs& a, int32_t i)
+{
+    if (!a.mark) return false;
+    const int32_t s = a.ctl->sweep + 1;
+    return s > 2 && a.mark[i] < s - 2;
+}
+
 // Decision of vertex-list slot `pos`: the best community if it beats staying
 // and lies in the sweep's direction, else -1.
 __device__ __forceinline__ void decide_store(const MoveArgs& a, int64_t pos, int32_t A, int32_t sA, int64_t ki,
@@ -315,7 +326,7 @@ __global__ __launch_bounds__(BS) void k_move(MoveArgs a)
     const bool has = vi < a.nverts;
     const int4 row = has ? a.rows[vi] : make_int4(0, 0, 0, 0);
     const int32_t i = row.x;
-    const bool live = has && !vertex_frozen(a, i);
+    const bool live = has && !vertex_frozen(a, i) && !vertex_skipped(a, i);
     const int32_t beg = live ? row.y : 0, end = live ? row.z : 0;
     const int2 self = live ? a.cs[i] : make_int2(0, 0);
     const int32_t A = self.x;
@@ -402,7 +413,7 @@ __global__ __launch_bounds__(BS) void k_hub_part(MoveArgs a, HubArgs h)
     const int32_t hh = h.blk_hub[b];
     const uint32_t part = (uint32_t)h.blk_part[b], P = (uint32_t)h.hub_parts[hh];
     const int32_t i = h.hub_vert[hh];
-    if (vertex_frozen(a, i)) {
+    if (vertex_frozen(a, i) || vertex_skipped(a, i)) {
         if (threadIdx.x == 0) { h.part_score[b] = INT64_MIN; h.part_comm[b] = INT32_MAX; h.part_wown[b] = 0; h.part_flag[b] = 0; }
         return;
     }
@@ -500,7 +511,7 @@ __global__ __launch_bounds__(SBS) void k_hub_scatter(MoveArgs a, HubArgs h)
     const int b = blockIdx.x;
     const int32_t hh = h.sc_hub[b];
     const int32_t i = h.hub_vert[hh];
-    if (vertex_frozen(a, i)) return;
+    if (vertex_frozen(a, i) || vertex_skipped(a, i)) return;
     const uint32_t P = (uint32_t)h.hub_parts[hh];
     const int32_t e0 = h.sc_beg[b], e1 = h.sc_end[b];
     for (uint32_t t = threadIdx.x; t < (uint32_t)SC_SLOTS; t += SBS) { t_key[t] = EMPTY_KEY; t_val[t] = 0; }
@@ -639,6 +650,59 @@ __global__ __launch_bounds__(256) void k_fb_finalize(MoveArgs a, HubArgs h)
     }
 }
 
+// ------------------------------------------------------------------ pruning marks
+// After the decisions of sweep s: mark[v] = s for every mover v and every
+// neighbour of one.  One wavefront per 64 listed vertices walks its movers'
+// rows one after another (rows below the hub class hold at most 8192 entries).
+// mark[idx[e]] = s for e in [e0, e1), `step` lanes apart from this lane's
+// first entry; four index loads are in flight before their stores.
+__device__ __forceinline__ void mark_entries(const int32_t* __restrict__ idx, int32_t* __restrict__ mark, int32_t e0,
+                                             int32_t e1, int32_t step, int32_t s)
+{
+    constexpr int U = 4;
+    for (int32_t e = e0; e < e1; e += U * step) {
+        int32_t j[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) j[u] = e + u * step < e1 ? __builtin_nontemporal_load(&idx[e + u * step]) : -1;
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (j[u] >= 0) mark[j[u]] = s;
+    }
+}
+
+// After the decisions of sweep s: mark[v] = s for every mover v and every
+// neighbour of one.  One wavefront per 64 listed vertices walks its movers'
+// rows one after another (rows below the hub class hold at most 8192 entries).
+__global__ __launch_bounds__(256) void k_mark_movers(const int4* __restrict__ rows, const int32_t* __restrict__ dec,
+                                                     int32_t m, const int32_t* __restrict__ idx,
+                                                     int32_t* __restrict__ mark, const SweepCtl* ctl)
+{
+    if (ctl->all_done) return;
+    const int32_t s = ctl->sweep + 1;
+    const int64_t w0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) / WAVE * WAVE;
+    const int lane = (int)lane_id();
+    const bool mover = w0 + lane < m && dec[w0 + lane] >= 0;
+    uint64_t todo = __ballot(mover);
+    while (todo) {
+        const int b = __builtin_ctzll(todo);
+        todo &= todo - 1;
+        const int4 r = rows[w0 + b];
+        if (lane == 0) mark[r.x] = s;
+        mark_entries(idx, mark, r.y + lane, r.z, WAVE, s);
+    }
+}
+
+// The same for the hubs: workgroup b marks one chunk of a moving hub's row.
+__global__ __launch_bounds__(256) void k_hub_mark(MoveArgs a, HubArgs h, int32_t* __restrict__ mark)
+{
+    if (a.ctl->all_done) return;
+    const int32_t hh = h.mk_hub[blockIdx.x];
+    if (a.dec[hh] < 0) return;
+    const int32_t s = a.ctl->sweep + 1;
+    if (threadIdx.x == 0) mark[h.hub_vert[hh]] = s;
+    mark_entries(a.idx, mark, h.mk_beg[blockIdx.x] + (int32_t)threadIdx.x, h.mk_end[blockIdx.x], 256, s);
+}
+
 // ------------------------------------------------------------------ commit (K7)
 // Apply the decisions of the m listed vertices: labels, and community volumes
 // with one atomic per distinct community per wavefront (integer sums, so the
@@ -724,6 +788,21 @@ __global__ void k_pairs(int32_t n, const int32_t* comm, const int32_t* sigma, in
 }
 
 }  // namespace
+
+hipError_t launch_mark_movers(const int4* rows, const int32_t* dec, int32_t m, const int32_t* idx, int32_t* mark,
+                              const SweepCtl* ctl, hipStream_t s)
+{
+    if (m <= 0) return hipSuccess;
+    k_mark_movers<<<(unsigned)(((int64_t)m + 255) / 256), 256, 0, s>>>(rows, dec, m, idx, mark, ctl);
+    return hipGetLastError();
+}
+
+hipError_t launch_hub_mark(const MoveArgs& a, const HubArgs& h, int32_t* mark, hipStream_t s)
+{
+    if (h.nmk <= 0) return hipSuccess;
+    k_hub_mark<<<(unsigned)h.nmk, 256, 0, s>>>(a, h, mark);
+    return hipGetLastError();
+}
 
 hipError_t launch_pairs(int32_t n, const int32_t* comm, const int32_t* sigma, int2* cs, const SweepCtl* ctl,
                         hipStream_t s)

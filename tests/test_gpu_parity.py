@@ -18,12 +18,13 @@ def say(*a):
     sys.stdout.flush()
 
 
-def compare_louvain(g, tuning=None, max_sweeps=20, max_levels=32, keep_graphs=False, device=False, keep_order=False):
-    say(f"case {g.name or 'graph'} n={g.n} nnz={g.nnz} tuning={tuning} keep_order={keep_order}")
-    want = oracle.louvain(g, max_sweeps=max_sweeps, max_levels=max_levels, keep_graphs=keep_graphs)
+def compare_louvain(g, tuning=None, max_sweeps=20, max_levels=32, keep_graphs=False, device=False, keep_order=False,
+                    prune=False, hipgraph=True, timing=False):
+    say(f"case {g.name or 'graph'} n={g.n} nnz={g.nnz} tuning={tuning} keep_order={keep_order} prune={prune}")
+    want = oracle.louvain(g, max_sweeps=max_sweeps, max_levels=max_levels, keep_graphs=keep_graphs, prune=prune)
     with lvp.Graph.from_csr(g, device=device, keep_order=keep_order) as dg:
         got = lvp.louvain(dg, max_sweeps=max_sweeps, max_levels=max_levels, keep_graphs=keep_graphs,
-                          tuning=tuning)
+                          tuning=tuning, prune=prune, hipgraph=hipgraph, timing=timing)
     assert got.M == want.M
     assert len(got.levels) == len(want.levels)
     for lvl, (a, b) in enumerate(zip(got.levels, want.levels)):
@@ -44,11 +45,11 @@ def compare_louvain(g, tuning=None, max_sweeps=20, max_levels=32, keep_graphs=Fa
     return got, want
 
 
-def compare_lpa(g, max_sweeps=20, threshold=0, tuning=None, keep_order=False):
-    say(f"lpa case {g.name or 'graph'} n={g.n} nnz={g.nnz}")
-    want = oracle.lpa(g, max_sweeps=max_sweeps, theta=threshold)
+def compare_lpa(g, max_sweeps=20, threshold=0, tuning=None, keep_order=False, prune=False):
+    say(f"lpa case {g.name or 'graph'} n={g.n} nnz={g.nnz} prune={prune}")
+    want = oracle.lpa(g, max_sweeps=max_sweeps, theta=threshold, prune=prune)
     with lvp.Graph.from_csr(g, keep_order=keep_order) as dg:
-        got = lvp.lpa(dg, max_sweeps=max_sweeps, threshold=threshold, tuning=tuning)
+        got = lvp.lpa(dg, max_sweeps=max_sweeps, threshold=threshold, tuning=tuning, prune=prune)
     assert got.moves == [int(x) for x in want.moves]
     assert np.array_equal(got.labels, want.labels)
     assert got.info["q_end"] == want.q_int
