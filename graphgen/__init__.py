@@ -53,6 +53,8 @@ def _load():
         lib.gg_csr_from_edges.argtypes = [ctypes.c_int32, ctypes.c_int64, _i32p, _i32p] + out3
         lib.gg_rmat.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, ctypes.c_double,
                                 ctypes.c_double, ctypes.c_double, ctypes.c_uint64] + out3
+        lib.gg_rmat_edges.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, ctypes.c_double,
+                                      ctypes.c_double, ctypes.c_double, ctypes.c_uint64, _i32p, _i32p]
         lib.gg_sbm.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                                ctypes.c_uint64] + out3
         lib.gg_pair_weights.argtypes = [ctypes.c_int32, _i32p, _i32p, ctypes.c_int32, ctypes.c_int32,
@@ -117,6 +119,21 @@ def rmat(scale: int, edge_factor: float = 16.0, a: float = 0.57, b: float = 0.19
                        ctypes.byref(nnz)), "rmat")
     off, idx = _take(off_p, idx_p, nv, nnz.value)
     return CSR(nv, off, idx, None, f"rmat{scale}_ef{edge_factor:g}_s{seed}")
+
+
+def rmat_edges(scale: int, edge_factor: float = 16.0, a: float = 0.57, b: float = 0.19, c: float = 0.19,
+               seed: int = 2, n: Optional[int] = None, samples: Optional[int] = None):
+    """The raw samples behind ``rmat`` with the same arguments: (u, v) int32
+    arrays, one per quadrant descent, loops and repeated pairs included (a
+    sample outside [0, n) is recorded as the loop (0, 0))."""
+    lib = _load()
+    nv = (1 << scale) if n is None else int(n)
+    ns = int(round(edge_factor * (1 << scale))) if samples is None else int(samples)
+    u = np.empty(max(ns, 1), dtype=np.int32)
+    v = np.empty(max(ns, 1), dtype=np.int32)
+    _check(lib.gg_rmat_edges(scale, nv, ns, a, b, c, seed, u.ctypes.data_as(_i32p), v.ctypes.data_as(_i32p)),
+           "rmat_edges")
+    return u[:ns], v[:ns]
 
 
 def sbm(n: int, block_size: int, p_in: float, p_out: float, seed: int = 1) -> CSR:

@@ -147,8 +147,8 @@ int gg_csr_from_edges(int32_t n, int64_t m, const int32_t* eu, const int32_t* ev
  * permutation.  Endpoints >= n are dropped (n <= 2^scale).  Each level draws a
  * 32-bit uniform; two levels share one 64-bit counter output.
  */
-int gg_rmat(int32_t scale, int32_t n, int64_t samples, double a, double b, double c,
-            uint64_t seed, int32_t** off, int32_t** idx, int64_t* nnz)
+int gg_rmat_edges(int32_t scale, int32_t n, int64_t samples, double a, double b, double c, uint64_t seed,
+                  int32_t* eu, int32_t* ev)
 {
     if (scale < 1 || scale > 30 || n < 1 || n > (1LL << scale) || samples < 0) return GG_E_ARG;
     if (a < 0 || b < 0 || c < 0 || a + b + c > 1.0) return GG_E_ARG;
@@ -157,9 +157,6 @@ int gg_rmat(int32_t scale, int32_t n, int64_t samples, double a, double b, doubl
     const uint64_t tc = (uint64_t)((a + b + c) * 4294967296.0);
     const uint64_t key = stream_key(seed, 0x524D4154ULL);
     const int draws = (scale + 1) / 2;
-    int32_t* eu = (int32_t*)malloc((size_t)(samples > 0 ? samples : 1) * sizeof(int32_t));
-    int32_t* ev = (int32_t*)malloc((size_t)(samples > 0 ? samples : 1) * sizeof(int32_t));
-    if (!eu || !ev) { free(eu); free(ev); return GG_E_NOMEM; }
 #pragma omp parallel for schedule(static)
     for (int64_t e = 0; e < samples; ++e) {
         uint32_t r = 0, col = 0;
@@ -178,7 +175,18 @@ int gg_rmat(int32_t scale, int32_t n, int64_t samples, double a, double b, doubl
         if ((int64_t)r >= n || (int64_t)col >= n) { eu[e] = 0; ev[e] = 0; }  /* dropped as a loop */
         else { eu[e] = (int32_t)r; ev[e] = (int32_t)col; }
     }
-    int rc = build_csr(n, samples, eu, ev, off, idx, nnz);
+    return GG_OK;
+}
+
+int gg_rmat(int32_t scale, int32_t n, int64_t samples, double a, double b, double c,
+            uint64_t seed, int32_t** off, int32_t** idx, int64_t* nnz)
+{
+    if (samples < 0) return GG_E_ARG;
+    int32_t* eu = (int32_t*)malloc((size_t)(samples > 0 ? samples : 1) * sizeof(int32_t));
+    int32_t* ev = (int32_t*)malloc((size_t)(samples > 0 ? samples : 1) * sizeof(int32_t));
+    if (!eu || !ev) { free(eu); free(ev); return GG_E_NOMEM; }
+    int rc = gg_rmat_edges(scale, n, samples, a, b, c, seed, eu, ev);
+    if (rc == GG_OK) rc = build_csr(n, samples, eu, ev, off, idx, nnz);
     free(eu); free(ev);
     return rc;
 }

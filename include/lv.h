@@ -68,6 +68,9 @@ typedef enum lv_memkind { LV_MEM_HOST = 0, LV_MEM_DEVICE = 1 } lv_memkind;
 #define LV_VALIDATE 1u /* check CSR shape, sortedness, symmetry and weights on the device */
 #define LV_KEEP_ORDER 2u  /* create: store the vertices in input order (default: by descending    */
                           /* degree within each graph, for cache locality; results are the same)  */
+#define LV_EDGES_NO_LOOPS 4u /* lv_graph_create_edges: drop loops (u, u)                          */
+#define LV_EDGES_SIMPLE 8u   /* lv_graph_create_edges: a pair listed several times keeps weight 1 */
+                             /* (no weights may be given)                                        */
 
 /* lv_params.flags */
 #define LV_TIMING 1u      /* record per-kernel HIP event times (see lv_level_info); sweeps */
@@ -168,6 +171,36 @@ const char* lv_last_error(void);
 lv_status lv_graph_create_csr(int32_t n, const int32_t* offsets, const int32_t* indices,
                               const int32_t* weights, lv_memkind kind, uint32_t flags, void* stream,
                               lv_graph** out);
+/*
+ * Create a device-resident graph from an undirected edge list (Section II-A:
+ * G(V, E, w) with E a set of unordered pairs, loops allowed).  Edge t joins
+ * src[t] and dst[t] (both in [0, n)) with weight weights[t] >= 1 (NULL =
+ * unit); m edges, each array int32[m] in `kind` memory.  A pair listed
+ * several times, in either orientation, becomes one edge whose weight is the
+ * sum of its listings (as the aggregation phase of Section III-B sums the
+ * weights of edges whose endpoints coincide); with LV_EDGES_SIMPLE its weight
+ * is 1 instead.  A loop (v, v, w) is one edge of weight w at v (its weighted
+ * degree counts 2w), unless LV_EDGES_NO_LOOPS drops it.  The graph is built
+ * on the device (keys sorted, equal pairs merged) and stored exactly as
+ * lv_graph_create_csr would store its symmetric CSR with sorted rows;
+ * LV_KEEP_ORDER applies as there.  Errors: LV_E_CSR (endpoint out of
+ * range), LV_E_WEIGHT (weight < 1), LV_E_OVERFLOW (2m >= 2^31 or total
+ * volume >= 2^31), LV_E_ARG (bad arguments, or weights with
+ * LV_EDGES_SIMPLE).
+ */
+lv_status lv_graph_create_edges(int32_t n, int64_t m, const int32_t* src, const int32_t* dst,
+                                const int32_t* weights, lv_memkind kind, uint32_t flags, void* stream,
+                                lv_graph** out);
+/*
+ * The graph held by a handle as a symmetric CSR in vertex-id order with
+ * sorted rows, in the caller's convention (a loop's diagonal entry carries
+ * its weight w, not 2w): offsets int32[n+1], indices and weights int32[nnz]
+ * in `kind` memory (weights may be NULL).  *nnz_out (if not NULL) receives
+ * nnz; with all three buffers NULL only nnz is returned.  For a packed handle
+ * the packed CSR is returned (graph g's vertices after graph g-1's).
+ */
+lv_status lv_graph_csr(lv_graph* g, int32_t* offsets, int32_t* indices, int32_t* weights, int64_t* nnz_out,
+                       lv_memkind kind);
 /*
  * Create one device-resident handle holding `count` independent graphs,
  * packed one after another into a single CSR (vertex segment offsets), so

@@ -221,6 +221,54 @@ def aggregate(adj: Adj, labels, n2: int) -> Adj:
     return Adj(n2, off2, idx2[:e2].copy(), a2[:e2].copy())
 
 
+def graph_from_edges(n: int, src, dst, w=None, drop_loops: bool = False, simple: bool = False):
+    """Undirected edge list -> symmetric CSR in the caller's convention.
+
+    Section II-A: G(V, E, w) with E a set of unordered pairs {u, v}, loops
+    allowed.  Every listing of a pair, in either orientation, is merged into
+    one edge whose weight is the sum of the listings' weights (Section III-B
+    sums the weights of edges whose endpoints coincide); with `simple` the
+    merged edge has weight 1.  A loop (v, v) is one diagonal entry carrying
+    its weight (the weighted degree counts it twice later); `drop_loops`
+    removes loops.  Rows come out sorted.  Returns (offsets, indices,
+    weights), int32.  Raises ValueError for an endpoint outside [0, n) or a
+    weight below 1, OverflowError for a merged weight above 2^31 - 1.
+    """
+    src = np.asarray(src, dtype=np.int64)
+    dst = np.asarray(dst, dtype=np.int64)
+    w = np.ones(len(src), dtype=np.int64) if w is None else np.asarray(w, dtype=np.int64)
+    if len(src) != len(dst) or len(w) != len(src):
+        raise ValueError("src, dst and w differ in length")
+    if len(src) and (min(src.min(), dst.min()) < 0 or max(src.max(), dst.max()) >= n):
+        raise ValueError("edge endpoint outside [0, n)")
+    if len(w) and w.min() < 1:
+        raise ValueError("edge weight < 1")
+    lo, hi = np.minimum(src, dst), np.maximum(src, dst)
+    if drop_loops:
+        keep = lo != hi
+        lo, hi, w = lo[keep], hi[keep], w[keep]
+    # one record per unordered pair, its listings' weights summed
+    pair = lo * max(n, 1) + hi
+    pairs, which = np.unique(pair, return_inverse=True)
+    weight = np.zeros(len(pairs), dtype=np.int64)
+    np.add.at(weight, which, w)
+    if simple:
+        weight[:] = 1
+    if len(weight) and weight.max() > np.iinfo(np.int32).max:
+        raise OverflowError("merged edge weight above 2^31 - 1")
+    a, b = pairs // max(n, 1), pairs % max(n, 1)
+    # both directions of a non-loop pair, one entry for a loop
+    off_diag = a != b
+    rows = np.concatenate([a, b[off_diag]])
+    cols = np.concatenate([b, a[off_diag]])
+    vals = np.concatenate([weight, weight[off_diag]])
+    order = np.lexsort((cols, rows))
+    rows, cols, vals = rows[order], cols[order], vals[order]
+    offsets = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(offsets, rows + 1, 1)
+    return np.cumsum(offsets).astype(np.int32), cols.astype(np.int32), vals.astype(np.int32)
+
+
 def singleton_qint(adj: Adj) -> int:
     return int(_load().orc_singleton_qint(adj.n, _p32(adj.off), _p32(adj.idx), _p32(adj.a)))
 

@@ -30,6 +30,8 @@ STATUS_NAMES = {
 LV_MEM_HOST, LV_MEM_DEVICE = 0, 1
 LV_VALIDATE = 1
 LV_KEEP_ORDER = 2
+LV_EDGES_NO_LOOPS = 4
+LV_EDGES_SIMPLE = 8
 LV_TIMING = 1
 LV_KEEP_GRAPHS = 2
 LV_NO_HIPGRAPH = 4
@@ -143,6 +145,9 @@ SIGNATURES = {
     "lv_server_stats_get": (ctypes.c_int, [_vp, ctypes.POINTER(lv_server_stats)]),
     "lv_server_destroy": (ctypes.c_int, [_vp]),
     "lv_modularity": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _i64p, _i64p, ctypes.POINTER(ctypes.c_double)]),
+    "lv_graph_create_edges": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, _vp, _vp, _vp, ctypes.c_int,
+                                             ctypes.c_uint32, _vp, ctypes.POINTER(_vp)]),
+    "lv_graph_csr": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i64p, ctypes.c_int]),
 }
 
 _lib = None
@@ -285,6 +290,48 @@ class Graph:
             w = None if w is None else torch.from_numpy(w).cuda()
             torch.cuda.synchronize()
         return cls(g.n, off, idx, w, validate=validate, keep_order=keep_order)
+
+    @classmethod
+    def from_edges(cls, n: int, src, dst, weights=None, drop_loops: bool = False, simple: bool = False,
+                   keep_order: bool = False):
+        """lv_graph_create_edges: an undirected edge list (numpy or torch
+        int32, all in the same memory), built into a CSR on the device."""
+        lib = load_library()
+        if isinstance(src, np.ndarray):
+            src = np.ascontiguousarray(src, dtype=np.int32)
+            dst = np.ascontiguousarray(dst, dtype=np.int32)
+            weights = None if weights is None else np.ascontiguousarray(weights, dtype=np.int32)
+        ps, ks = _ptr(src)
+        pd, kd = _ptr(dst)
+        pw, kw = _ptr(weights)
+        kinds = {ks, kd} | ({kw} if weights is not None else set())
+        if len(kinds) != 1:
+            raise ValueError("src, dst and weights must live in the same memory")
+        m = int(src.shape[0])
+        flags = ((LV_EDGES_NO_LOOPS if drop_loops else 0) | (LV_EDGES_SIMPLE if simple else 0)
+                 | (LV_KEEP_ORDER if keep_order else 0))
+        h = _vp()
+        _check(lib.lv_graph_create_edges(int(n), m, ps, pd, pw, ks, flags, None, ctypes.byref(h)),
+               "lv_graph_create_edges")
+        self = cls.__new__(cls)
+        self._h = h
+        nn, nnz, vol = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib.lv_graph_info(h, ctypes.byref(nn), ctypes.byref(nnz), ctypes.byref(vol)), "lv_graph_info")
+        self.n, self.nnz, self.volume, self.count = nn.value, nnz.value, vol.value, 1
+        self.sizes = [self.n]
+        return self
+
+    def csr(self):
+        """lv_graph_csr: (offsets, indices, weights) in vertex-id order, host numpy."""
+        lib = load_library()
+        nnz = ctypes.c_int64()
+        _check(lib.lv_graph_csr(self._h, None, None, None, ctypes.byref(nnz), LV_MEM_HOST), "lv_graph_csr")
+        off = np.empty(self.n + 1, dtype=np.int32)
+        idx = np.empty(max(nnz.value, 1), dtype=np.int32)
+        w = np.empty(max(nnz.value, 1), dtype=np.int32)
+        _check(lib.lv_graph_csr(self._h, off.ctypes.data, idx.ctypes.data, w.ctypes.data, ctypes.byref(nnz),
+                                LV_MEM_HOST), "lv_graph_csr")
+        return off, idx[:nnz.value], w[:nnz.value]
 
     @property
     def handle(self):

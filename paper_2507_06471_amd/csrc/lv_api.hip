@@ -1466,6 +1466,185 @@ static lv_status new_graph(void* stream, lv_graph** out)
     return LV_OK;
 }
 
+// Canonical CSR (n rows, sorted columns, equal keys merged with their values
+// summed) from E (row << cb | col) keys in ws.keys / ws.vals, of which the
+// `valid` smallest are entries (the rest carry the all-ones key).
+static lv_status csr_from_keys(lv_graph* g, int64_t E, int64_t valid, int cb, int32_t n, DevBuf& off, DevBuf& idx,
+                               DevBuf& w, int64_t& nnz, uint64_t** keys_out)
+{
+    Workspace& ws = g->ws;
+    hipStream_t s = g->stream;
+    bool in_alt = false;
+    HIP_TRY(radix_sort_u64(ws.keys.as<uint64_t>(), ws.vals.as<int32_t>(), ws.keys_alt.as<uint64_t>(),
+                           ws.vals_alt.as<int32_t>(), E, 2 * cb, ws.tmp.p, ws.tmp.cap, &in_alt, s));
+    const uint64_t* keys = in_alt ? ws.keys_alt.as<uint64_t>() : ws.keys.as<uint64_t>();
+    const int32_t* vals = in_alt ? ws.vals_alt.as<int32_t>() : ws.vals.as<int32_t>();
+    uint64_t* keys2 = in_alt ? ws.keys.as<uint64_t>() : ws.keys_alt.as<uint64_t>();
+    HIP_TRY(ws.head.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(valid, 1)));
+    int32_t* d_e2 = (int32_t*)(ws.small.as<char>() + 2304);
+    HIP_TRY(hipMemsetAsync(d_e2, 0, sizeof(int32_t), s));
+    HIP_TRY(launch_segment_heads(keys, valid, ws.head.as<int32_t>(), s));
+    if (valid > 0)
+        HIP_TRY(scan_exclusive_i32(ws.head.as<int32_t>(), ws.head.as<int32_t>(), valid, d_e2, ws.tmp.p, ws.tmp.cap, s));
+    int32_t e2 = 0;
+    HIP_TRY(hipMemcpyAsync(&e2, d_e2, sizeof e2, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(off.ensure(sizeof(int32_t) * ((size_t)n + 1)));
+    HIP_TRY(idx.ensure(sizeof(int32_t) * (size_t)std::max(e2, 1)));
+    HIP_TRY(w.ensure(sizeof(int32_t) * (size_t)std::max(e2, 1)));
+    HIP_TRY(hipMemsetAsync(w.p, 0, sizeof(int32_t) * (size_t)std::max(e2, 1), s));
+    HIP_TRY(launch_segment_reduce(keys, vals, ws.head.as<int32_t>(), valid, cb, idx.as<int32_t>(), w.as<int32_t>(), keys2, s));
+    HIP_TRY(launch_row_offsets(keys2, e2, n, cb, off.as<int32_t>(), s));
+    nnz = e2;
+    if (keys_out) *keys_out = keys2;
+    return LV_OK;
+}
+
+static lv_status sort_workspace(lv_graph* g, int64_t E)
+{
+    Workspace& ws = g->ws;
+    const size_t E1 = (size_t)std::max<int64_t>(E, 1);
+    HIP_TRY(ws.small.ensure(4096));
+    HIP_TRY(ws.keys.ensure(sizeof(uint64_t) * E1));
+    HIP_TRY(ws.keys_alt.ensure(sizeof(uint64_t) * E1));
+    HIP_TRY(ws.vals.ensure(sizeof(int32_t) * E1));
+    HIP_TRY(ws.vals_alt.ensure(sizeof(int32_t) * E1));
+    HIP_TRY(ws.tmp.ensure(std::max(radix_tmp_bytes(E), scan_tmp_bytes(E, 8))));
+    return LV_OK;
+}
+
+static void release_sort_workspace(lv_graph* g)
+{
+    Workspace& ws = g->ws;
+    ws.keys.release();
+    ws.keys_alt.release();
+    ws.vals.release();
+    ws.vals_alt.release();
+    ws.head.release();
+}
+
+static lv_status create_from_edges(lv_graph* g, int32_t n, int64_t m, const int32_t* src, const int32_t* dst,
+                                   const int32_t* weights, lv_memkind kind, uint32_t flags)
+{
+    hipStream_t s = g->stream;
+    Workspace& ws = g->ws;
+    LV_TRY(ensure_pinned(g, 4096));
+    // the edge list in device memory
+    DevBuf d_src, d_dst, d_w;
+    const int32_t* us = src;
+    const int32_t* vs = dst;
+    const int32_t* ws_in = weights;
+    if (kind == LV_MEM_HOST && m > 0) {
+        HIP_TRY(d_src.ensure(sizeof(int32_t) * (size_t)m));
+        HIP_TRY(d_dst.ensure(sizeof(int32_t) * (size_t)m));
+        HIP_TRY(hipMemcpyAsync(d_src.p, src, sizeof(int32_t) * (size_t)m, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(d_dst.p, dst, sizeof(int32_t) * (size_t)m, hipMemcpyHostToDevice, s));
+        us = d_src.as<int32_t>();
+        vs = d_dst.as<int32_t>();
+        if (weights) {
+            HIP_TRY(d_w.ensure(sizeof(int32_t) * (size_t)m));
+            HIP_TRY(hipMemcpyAsync(d_w.p, weights, sizeof(int32_t) * (size_t)m, hipMemcpyHostToDevice, s));
+            ws_in = d_w.as<int32_t>();
+        }
+    }
+    const int cb = bits_for((int64_t)n + 1);
+    const int64_t E = 2 * m;
+    LV_TRY(sort_workspace(g, E));
+    int64_t* d_stats = (int64_t*)(ws.small.as<char>() + 3840);
+    int32_t* d_err = ws.small.as<int32_t>();
+    HIP_TRY(hipMemsetAsync(d_stats, 0, 2 * sizeof(int64_t), s));
+    HIP_TRY(hipMemsetAsync(d_err, 0, sizeof(int32_t), s));
+    HIP_TRY(launch_edge_keys(m, us, vs, ws_in, n, cb, (flags & LV_EDGES_NO_LOOPS) != 0, ws.keys.as<uint64_t>(),
+                             ws.vals.as<int32_t>(), d_stats, d_err, s));
+    int64_t stats[2] = {0, 0};
+    int32_t err = 0;
+    HIP_TRY(hipMemcpyAsync(stats, d_stats, sizeof stats, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&err, d_err, sizeof err, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    d_src.release();
+    d_dst.release();
+    if (err & 2) { set_error_msg("edge endpoint outside [0, n)"); return LV_E_CSR; }
+    if (err & 4) { set_error_msg("edge weight < 1"); return LV_E_WEIGHT; }
+    // merged weights are sums of int32 weights: bounded by the volume, checked first
+    if (!(flags & LV_EDGES_SIMPLE) && stats[1] > (int64_t)INT32_MAX) {
+        set_error_msg("total volume M >= 2^31");
+        return LV_E_OVERFLOW;
+    }
+    DevBuf off, idx, w;
+    int64_t nnz = 0;
+    LV_TRY(csr_from_keys(g, E, stats[0], cb, n, off, idx, w, nnz, nullptr));
+    d_w.release();
+    release_sort_workspace(g);
+    const bool unit = (flags & LV_EDGES_SIMPLE) != 0;
+    return graph_setup(g, n, off.as<int32_t>(), idx.as<int32_t>(), unit ? nullptr : w.as<int32_t>(), LV_MEM_DEVICE,
+                       flags & LV_KEEP_ORDER, std::vector<int32_t>{0, n});
+}
+
+lv_status lv_graph_create_edges(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, const int32_t* weights,
+                                lv_memkind kind, uint32_t flags, void* stream, lv_graph** out)
+{
+    if (!out || n < 0 || m < 0 || (m > 0 && (!src || !dst)) || (kind != LV_MEM_HOST && kind != LV_MEM_DEVICE)) {
+        set_error_msg("lv_graph_create_edges: null out, n < 0, m < 0, null endpoints or bad memkind");
+        return LV_E_ARG;
+    }
+    if ((flags & LV_EDGES_SIMPLE) && weights) {
+        set_error_msg("lv_graph_create_edges: LV_EDGES_SIMPLE takes no weights");
+        return LV_E_ARG;
+    }
+    if (n == INT32_MAX || m >= ((int64_t)1 << 30)) {
+        set_error_msg("lv_graph_create_edges: n must be < 2^31 - 1 and 2m < 2^31");
+        return LV_E_OVERFLOW;
+    }
+    lv_graph* g = nullptr;
+    LV_TRY(new_graph(stream, &g));
+    lv_status st = create_from_edges(g, n, m, src, dst, weights, kind, flags);
+    if (st != LV_OK) {
+        (void)hipStreamSynchronize(g->stream);
+        delete g;
+        return st;
+    }
+    *out = g;
+    return LV_OK;
+}
+
+lv_status lv_graph_csr(lv_graph* g, int32_t* offsets, int32_t* indices, int32_t* weights, int64_t* nnz_out,
+                       lv_memkind kind)
+{
+    if (!g || (kind != LV_MEM_HOST && kind != LV_MEM_DEVICE)) { set_error_msg("lv_graph_csr: null graph or bad memkind"); return LV_E_ARG; }
+    if (nnz_out) *nnz_out = g->nnz;
+    if (!offsets && !indices && !weights) return LV_OK;
+    if (!offsets || (g->nnz > 0 && !indices)) { set_error_msg("lv_graph_csr: null offsets or indices"); return LV_E_ARG; }
+    hipStream_t s = g->stream;
+    Workspace& ws = g->ws;
+    const int32_t n = g->n;
+    const int cb = bits_for((int64_t)n + 1);
+    LV_TRY(sort_workspace(g, g->nnz));
+    // keys (id of the row, id of the column): the stored positions mapped back to ids
+    DevBuf ids;
+    const int32_t* labels = g->reordered ? g->orig.as<int32_t>() : nullptr;
+    if (!labels) {
+        HIP_TRY(ids.ensure(sizeof(int32_t) * (size_t)std::max(n, 1)));
+        HIP_TRY(launch_iota(ids.as<int32_t>(), n, s));
+        labels = ids.as<int32_t>();
+    }
+    int64_t* d_scratch = (int64_t*)(ws.small.as<char>() + 3840);
+    HIP_TRY(hipMemsetAsync(d_scratch, 0, sizeof(int64_t), s));
+    HIP_TRY(launch_build_keys(n, g->off.as<int32_t>(), g->idx.as<int32_t>(), g->weighted ? g->w.as<int32_t>() : nullptr,
+                              g->nnz, labels, cb, ws.keys.as<uint64_t>(), ws.vals.as<int32_t>(), nullptr, d_scratch, s));
+    DevBuf off, idx, w;
+    int64_t nnz = 0;
+    uint64_t* keys2 = nullptr;
+    LV_TRY(csr_from_keys(g, g->nnz, g->nnz, cb, n, off, idx, w, nnz, &keys2));
+    HIP_TRY(launch_halve_diagonal(keys2, nnz, cb, w.as<int32_t>(), s));
+    const hipMemcpyKind hk = kind == LV_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+    HIP_TRY(hipMemcpyAsync(offsets, off.p, sizeof(int32_t) * ((size_t)n + 1), hk, s));
+    if (nnz > 0) HIP_TRY(hipMemcpyAsync(indices, idx.p, sizeof(int32_t) * (size_t)nnz, hk, s));
+    if (weights && nnz > 0) HIP_TRY(hipMemcpyAsync(weights, w.p, sizeof(int32_t) * (size_t)nnz, hk, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    release_sort_workspace(g);
+    return LV_OK;
+}
+
 lv_status lv_graph_create_csr(int32_t n, const int32_t* offsets, const int32_t* indices, const int32_t* weights,
                               lv_memkind kind, uint32_t flags, void* stream, lv_graph** out)
 {

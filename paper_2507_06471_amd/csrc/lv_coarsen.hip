@@ -174,6 +174,62 @@ __global__ __launch_bounds__(256) void k_segment_reduce(const uint64_t* keys, co
 }
 
 // off2[r] = first coarse entry of row r (keys2 sorted, row in the high bits)
+// Graph construction from an undirected edge list (Section II-A: an edge set
+// of unordered pairs, loops allowed).  Edge t = (u, v, w) becomes the keys
+// u:v and v:u with weight w (one key u:u for a loop, none for a dropped loop);
+// unused slots get the all-ones key of 2*cb bits, which sorts last.  Per
+// workgroup: stats[0] += kept entries, stats[1] += their volume (a loop's
+// weight counted twice, as the weighted degree does); err |= 2 for an
+// endpoint outside [0, n), 4 for a weight < 1.
+__global__ __launch_bounds__(256) void k_edge_keys(int64_t m, const int32_t* src, const int32_t* dst, const int32_t* w,
+                                                   int32_t n, int cb, int drop_loops, uint64_t* keys, int32_t* vals,
+                                                   unsigned long long* stats, int32_t* err)
+{
+    __shared__ unsigned long long red[256 / WAVE];
+    const uint64_t none = (1ull << (2 * cb)) - 1ull;
+    unsigned long long ne = 0, vol = 0;
+    int32_t bad = 0;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < m; t += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t u = src[t], v = dst[t], x = w ? w[t] : 1;
+        uint64_t k0 = none, k1 = none;
+        if (u < 0 || u >= n || v < 0 || v >= n) {
+            bad |= 2;
+        } else if (x < 1) {
+            bad |= 4;
+        } else if (u != v) {
+            k0 = ((uint64_t)u << cb) | (uint64_t)v;
+            k1 = ((uint64_t)v << cb) | (uint64_t)u;
+            ne += 2;
+            vol += 2ull * (unsigned long long)x;
+        } else if (!drop_loops) {
+            k0 = ((uint64_t)u << cb) | (uint64_t)u;
+            ne += 1;
+            vol += 2ull * (unsigned long long)x;
+        }
+        keys[2 * t] = k0;
+        keys[2 * t + 1] = k1;
+        vals[2 * t] = x;
+        vals[2 * t + 1] = x;
+    }
+    if (bad) atomicOr(err, bad);
+    ne = block_sum<256>(ne, red);
+    vol = block_sum<256>(vol, red);
+    if (threadIdx.x == 0 && ne) {
+        atomicAdd(&stats[0], ne);
+        atomicAdd(&stats[1], vol);
+    }
+}
+
+// Stored loops are doubled (A_vv = 2w); the caller's convention carries w.
+__global__ void k_halve_diagonal(const uint64_t* keys2, int64_t e2, int cb, int32_t* w2)
+{
+    const uint64_t lo = (1ull << cb) - 1ull;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < e2; e += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t k = keys2[e];
+        if ((k >> cb) == (k & lo)) w2[e] /= 2;
+    }
+}
+
 __global__ void k_row_offsets(const uint64_t* keys2, int64_t e2, int32_t n2, int colbits, int32_t* off2)
 {
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r <= n2; r += (int64_t)gridDim.x * blockDim.x) {
@@ -309,6 +365,19 @@ hipError_t launch_segment_reduce(const uint64_t* keys, const int32_t* vals, cons
     if (n <= 0) return hipSuccess;
     k_segment_reduce<<<(unsigned)((n + SR_TILE - 1) / SR_TILE), 256, 0, s>>>(keys, vals, pos, n, colbits,
                                                                                        idx2, w2, keys2);
+    return hipGetLastError();
+}
+hipError_t launch_edge_keys(int64_t m, const int32_t* src, const int32_t* dst, const int32_t* w, int32_t n, int cb,
+                            bool drop_loops, uint64_t* keys, int32_t* vals, int64_t* stats, int32_t* err, hipStream_t s)
+{
+    if (m <= 0) return hipSuccess;
+    k_edge_keys<<<LV_GRID(m)>>>(m, src, dst, w, n, cb, drop_loops ? 1 : 0, keys, vals, (unsigned long long*)stats, err);
+    return hipGetLastError();
+}
+hipError_t launch_halve_diagonal(const uint64_t* keys2, int64_t e2, int cb, int32_t* w2, hipStream_t s)
+{
+    if (e2 <= 0) return hipSuccess;
+    k_halve_diagonal<<<LV_GRID(e2)>>>(keys2, e2, cb, w2);
     return hipGetLastError();
 }
 hipError_t launch_row_offsets(const uint64_t* keys2, int64_t e2, int32_t n2, int colbits, int32_t* off2, hipStream_t s)

@@ -256,6 +256,10 @@ hipError_t launch_segment_heads(const uint64_t* keys, int64_t n, int32_t* head, 
 // w2 must be zeroed; writes idx2/w2/keys2 of each run of equal keys
 hipError_t launch_segment_reduce(const uint64_t* keys, const int32_t* vals, const int32_t* pos, int64_t n,
                                  int colbits, int32_t* idx2, int32_t* w2, uint64_t* keys2, hipStream_t s);
+// Edge list -> 2m keys/values (see lv_graph_create_edges); stats = {entries, volume}.
+hipError_t launch_edge_keys(int64_t m, const int32_t* src, const int32_t* dst, const int32_t* w, int32_t n, int cb,
+                            bool drop_loops, uint64_t* keys, int32_t* vals, int64_t* stats, int32_t* err, hipStream_t s);
+hipError_t launch_halve_diagonal(const uint64_t* keys2, int64_t e2, int cb, int32_t* w2, hipStream_t s);
 hipError_t launch_row_offsets(const uint64_t* keys2, int64_t e2, int32_t n2, int colbits, int32_t* off2,
                               hipStream_t s);
 hipError_t launch_compose(int32_t n0, int32_t* final_labels, const int32_t* labels, const int32_t* gid0,
