@@ -119,6 +119,42 @@ def prune_leg(args, lvp, dg, runs, phases, K, torch):
     return out
 
 
+def edges_leg(args, lvp, graphgen, g, np, torch):
+    """The step before the path: the benchmark graph built on the device from
+    its raw R-MAT samples (loops dropped, repeated pairs merged to weight 1),
+    timed from device-resident edge arrays to a ready handle (sort, merge,
+    CSR, degrees, degree-ordered storage).  The built CSR must equal the
+    generator's."""
+    t = time.time()
+    u, v = graphgen.rmat_edges(args.scale, args.edge_factor, seed=args.seed)
+    du, dv = torch.from_numpy(u).cuda(), torch.from_numpy(v).cuda()
+    del u, v
+    torch.cuda.synchronize()
+    log(f"edges: {du.numel()} raw samples resident in {time.time() - t:.1f}s")
+    times = []
+    for rep in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        eg = lvp.Graph.from_edges(g.n, du, dv, drop_loops=True, simple=True)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        if rep == 0:
+            off, idx, _ = eg.csr()
+            equal = bool(np.array_equal(off, g.offsets) and np.array_equal(idx, g.indices))
+            del off, idx
+        eg.close()
+    m = int(du.numel())
+    del du, dv
+    best = min(times)
+    out = {"edges": m, "ms": round(best * 1e3, 2), "medges_per_s": round(m / best / 1e6, 1),
+           "csr_equal_to_generator": equal, "timed": "device edge arrays -> ready handle, best of 2"}
+    log(f"edges: {out}")
+    if not equal:
+        print("edge-list construction differs from the generator's CSR", file=sys.stderr, flush=True)
+        sys.exit(1)
+    return out
+
+
 def batch_leg(args, lvp, graphgen, np, torch):
     """Mixed batch of independent graphs: one packed handle (every graph in the
     same launches, sweeps captured as hipGraphs, autotuned classes) against
@@ -338,6 +374,8 @@ def main():
     ap.add_argument("--serve-capacity-jobs", type=int, default=200, help="jobs of the saturated capacity runs")
     ap.add_argument("--prune-reps", type=int, default=2,
                     help="timed steps with active-vertex pruning (LV_PRUNE) after the main steps (0: skip)")
+    ap.add_argument("--no-edges-leg", action="store_true",
+                    help="skip building the graph from its raw R-MAT samples on the device")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB before the steps (PMC calibration)")
     args = ap.parse_args()
@@ -442,6 +480,7 @@ def main():
     assert (qi, m) == (r0.q_int, r0.M), "reported modularity differs from the labels' modularity"
 
     pruned = prune_leg(args, lvp, dg, runs, phases, K, torch) if args.prune_reps > 0 else None
+    edges = None if args.no_edges_leg else edges_leg(args, lvp, graphgen, g, np, torch)
 
     parity = None
     cpu = None
@@ -520,6 +559,7 @@ def main():
         "phase_ms_per_step": {k_: round(v / K, 3) for k_, v in phases.items()},
         "kernels": kernels,
         "pruned": pruned,
+        "edges_to_csr": edges,
         "batch": batch,
         "serving": serving,
     }
