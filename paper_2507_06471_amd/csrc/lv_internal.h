@@ -26,7 +26,7 @@ enum MoveClass : int {
     CLS_L1K,       // L <= 1024:  one 256-thread workgroup, 2048 slots
     CLS_L2K,       // L <= 2048:  one 512-thread workgroup, 4096 slots
     CLS_L3K5,      // L <= 3584:  one 512-thread workgroup, 4096 slots (load <= 7/8)
-    CLS_L8K,       // L <= 8192:  one 1024-thread workgroup, 16384 compact slots
+    CLS_L8K,       // L <= 8192:  one 1024-thread workgroup, 10112 compact slots (two workgroups a CU)
     CLS_HUB,       // several partition workgroups per vertex
     NUM_CLS
 };

@@ -178,19 +178,21 @@ __device__ __forceinline__ void score_entries_singleton(const MoveArgs& a, int32
     }
 }
 
-// Insert (C, W) into an LDS open-addressing table of `mask`+1 slots that is
-// guaranteed to have room (distinct keys < slots); the thread that claims a
-// slot stores the community's volume S beside it.
-template <bool SIG>
+// Insert (C, W) into an LDS open-addressing table that is guaranteed to have
+// room (distinct keys < slots); the thread that claims a slot stores the
+// community's volume S beside it.  The table has mask+1 slots (a power of
+// two), or with MOD exactly `mask` slots of any count, hashed by a
+// multiply-high reduction.
+template <bool SIG, bool MOD = false>
 __device__ __forceinline__ void lds_insert(int32_t* key, int32_t* val, int32_t* sig, uint32_t mask, int32_t C,
                                            int32_t W, int32_t S)
 {
-    uint32_t h = mix32(C) & mask;
+    uint32_t h = MOD ? (uint32_t)(((uint64_t)mix32(C) * mask) >> 32) : (mix32(C) & mask);
     for (;;) {
         const int32_t prev = atomicCAS(&key[h], EMPTY_KEY, C);
         if constexpr (SIG) if (prev == EMPTY_KEY) sig[h] = S;
         if (prev == EMPTY_KEY || prev == C) { atomicAdd(&val[h], W); return; }
-        h = (h + 1) & mask;
+        if constexpr (MOD) h = h + 1 == mask ? 0u : h + 1; else h = (h + 1) & mask;
     }
 }
 
@@ -213,36 +215,36 @@ __device__ __forceinline__ bool lds_insert_bounded(int32_t* key, int32_t* val, i
 // of vertex i into an LDS table, optionally only communities of partition
 // `part` of P.  Returns false if the bounded table had no room (only
 // possible with P > 1).
-template <int STRIDE, bool BOUNDED, bool SIG>
+template <int STRIDE, bool BOUNDED, bool SIG, int U = UNROLL, bool MOD = false>
 __device__ __forceinline__ bool aggregate_entries(const MoveArgs& a, int32_t i, int32_t e_beg, int32_t e_end,
                                                   int32_t* key, int32_t* val, int32_t* sig, uint32_t mask, uint32_t P,
                                                   uint32_t part)
 {
     bool ok_all = true;
-    for (int32_t e0 = e_beg; e0 < e_end; e0 += STRIDE * UNROLL) {
-        int32_t jj[UNROLL], ww[UNROLL];
-        int2 cc[UNROLL];
+    for (int32_t e0 = e_beg; e0 < e_end; e0 += STRIDE * U) {
+        int32_t jj[U], ww[U];
+        int2 cc[U];
 #pragma unroll
-        for (int u = 0; u < UNROLL; ++u) {
+        for (int u = 0; u < U; ++u) {
             const int32_t e = e0 + u * STRIDE;
             const bool ok = e < e_end;
             jj[u] = ok ? __builtin_nontemporal_load(&a.idx[e]) : i;
             ww[u] = (ok && a.w) ? __builtin_nontemporal_load(&a.w[e]) : 1;
         }
 #pragma unroll
-        for (int u = 0; u < UNROLL; ++u) {
+        for (int u = 0; u < U; ++u) {
             if constexpr (SIG) cc[u] = jj[u] != i ? a.cs[jj[u]] : make_int2(EMPTY_KEY, 0);
             else cc[u] = make_int2(jj[u] != i ? a.comm[jj[u]] : EMPTY_KEY, 0);
         }
 #pragma unroll
-        for (int u = 0; u < UNROLL; ++u) {
+        for (int u = 0; u < U; ++u) {
             const int32_t C = cc[u].x;
             if (C == EMPTY_KEY) continue;
             if constexpr (BOUNDED) {
                 if (P > 1 && part_of(C, P) != part) continue;
                 if (!lds_insert_bounded<SIG>(key, val, sig, mask, C, ww[u], cc[u].y)) ok_all = false;
             } else {
-                lds_insert<SIG>(key, val, sig, mask, C, ww[u], cc[u].y);
+                lds_insert<SIG, MOD>(key, val, sig, mask, C, ww[u], cc[u].y);
             }
         }
     }
@@ -280,13 +282,36 @@ __device__ __forceinline__ void scan_table(const MoveArgs& a, const int32_t* key
                                            int64_t M, int64_t& best_s, int32_t& best_c, int32_t& w_own)
 {
     const bool louvain = a.mode == MODE_LOUVAIN;
-    for (uint32_t t = t0; t < T; t += STRIDE) {
-        const int32_t C = key[t];
-        if (C == EMPTY_KEY) continue;
-        const int32_t W = val[t];
-        if (C == A) { w_own = W; continue; }
-        const int64_t s = louvain ? M * W - ki * (int64_t)(SIG ? sig[t] : a.sigma[C]) : (int64_t)W;
-        if (better(s, C, best_s, best_c)) { best_s = s; best_c = C; }
+    if constexpr (SIG) {
+        for (uint32_t t = t0; t < T; t += STRIDE) {
+            const int32_t C = key[t];
+            if (C == EMPTY_KEY) continue;
+            const int32_t W = val[t];
+            if (C == A) { w_own = W; continue; }
+            const int64_t s = louvain ? M * W - ki * (int64_t)sig[t] : (int64_t)W;
+            if (better(s, C, best_s, best_c)) { best_s = s; best_c = C; }
+        }
+    } else {
+        // volumes gathered from global memory: issue SU gathers before using any
+        constexpr int SU = 8;
+        for (uint32_t tb = t0; tb < T; tb += STRIDE * SU) {
+            int32_t Cs[SU], Ws[SU], Ss[SU];
+#pragma unroll
+            for (int u = 0; u < SU; ++u) {
+                const uint32_t t = tb + u * STRIDE;
+                Cs[u] = t < T ? key[t] : EMPTY_KEY;
+                Ws[u] = t < T ? val[t] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < SU; ++u) Ss[u] = (louvain && Cs[u] != EMPTY_KEY && Cs[u] != A) ? a.sigma[Cs[u]] : 0;
+#pragma unroll
+            for (int u = 0; u < SU; ++u) {
+                if (Cs[u] == EMPTY_KEY) continue;
+                if (Cs[u] == A) { w_own = Ws[u]; continue; }
+                const int64_t s = louvain ? M * Ws[u] - ki * (int64_t)Ss[u] : (int64_t)Ws[u];
+                if (better(s, Cs[u], best_s, best_c)) { best_s = s; best_c = Cs[u]; }
+            }
+        }
     }
 }
 
@@ -341,10 +366,14 @@ __global__ __launch_bounds__(BS) void k_move(MoveArgs a)
         int32_t* key = s_key + g * SLOTS;
         int32_t* val = s_val + g * SLOTS;
         int32_t* sig = SIG ? s_sig + g * SLOTS : s_sig;
-        const uint32_t T = min((uint32_t)SLOTS, pow2_at_least(2u * (uint32_t)(end - beg)));
+        // a power-of-two SLOTS sizes the table to the row; any other SLOTS is
+        // one fixed table, larger than every row of the class
+        constexpr bool POW2 = (SLOTS & (SLOTS - 1)) == 0;
+        const uint32_t T = POW2 ? min((uint32_t)SLOTS, pow2_at_least(2u * (uint32_t)(end - beg))) : (uint32_t)SLOTS;
         for (uint32_t t = lane; t < T; t += G) { key[t] = EMPTY_KEY; val[t] = 0; }
         group_sync<G>();
-        aggregate_entries<G, false, SIG>(a, i, beg + lane, end, key, val, sig, T - 1u, 1u, 0u);
+        aggregate_entries<G, false, SIG, (G >= 1024 ? 8 : UNROLL), !POW2>(a, i, beg + lane, end, key, val, sig,
+                                                                          POW2 ? T - 1u : T, 1u, 0u);
         group_sync<G>();
         scan_table<G, SIG>(a, key, val, sig, lane, T, A, ki, M, best_s, best_c, w_own);
     }
@@ -374,6 +403,7 @@ __global__ __launch_bounds__(BS) void k_move(MoveArgs a)
 template <int CLS, int BS, int G, int SLOTS, bool SIG>
 hipError_t launch_move_t(bool singleton, const MoveArgs& a, hipStream_t s)
 {
+    static_assert(SLOTS > CLS_CAP[CLS], "a class's table must hold every distinct community of its longest row");
     if (a.nverts <= 0) return hipSuccess;
     constexpr int NG = BS / G;
     const unsigned grid = (unsigned)((a.nverts + NG - 1) / NG);
@@ -878,7 +908,9 @@ hipError_t launch_move_class(int cls, bool singleton, const MoveArgs& a, hipStre
     case CLS_L1K: return launch_move_t<CLS_L1K, 256, 256, 2048, true>(singleton, a, s);
     case CLS_L2K: return launch_move_t<CLS_L2K, 512, 512, 4096, true>(singleton, a, s);
     case CLS_L3K5: return launch_move_t<CLS_L3K5, 512, 512, 4096, true>(singleton, a, s);
-    case CLS_L8K: return launch_move_t<CLS_L8K, 1024, 1024, 16384, false>(singleton, a, s);
+    // 10112 8-byte slots (79 KiB): two workgroups fit a CU's 160 KiB, and every row of the class
+    // (at most 8192 entries) leaves free slots
+    case CLS_L8K: return launch_move_t<CLS_L8K, 1024, 1024, 10112, false>(singleton, a, s);
     default: return hipErrorInvalidValue;
     }
 }
