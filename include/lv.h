@@ -141,7 +141,7 @@ typedef struct lv_level_info {
     int64_t move_bytes;    /* algorithmic bytes of the move kernels, all sweeps    */
     /* Per move kernel (LV_TIMING): slot 2*(class-1) + (1 for the first sweep
        of a level, where every community is a single vertex); classes 1..10 =
-       rows of at most 4, 8, 32, 128, 256, 512, 1024, 2048, 3584 and 8192
+       rows of at most 4, 8, 32, 128, 256, 512, 1024, 2048, 3072 and 8192
        entries (groups of 4 lanes up to 1024-thread workgroups), 11 =
        partition workgroups (with their merge and fallback kernels); slot 22
        = the bucketed mode's scatter pass, which then carries class 11's

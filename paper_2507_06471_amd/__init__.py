@@ -41,7 +41,7 @@ KERNEL_SLOTS = 23
 # kernel slot -> name (slot = 2*(class-1) + first-sweep flag; the last slot is
 # the bucketed hub scatter pass, whose partition workgroups are timed as "hub")
 KERNEL_NAMES = [f"{c}{'/first' if f else ''}"
-                for c in ("l4", "l8", "l32", "l128", "l256", "l512", "l1k", "l2k", "l3k5", "l8k", "hub")
+                for c in ("l4", "l8", "l32", "l128", "l256", "l512", "l1k", "l2k", "l3k", "l8k", "hub")
                 for f in (0, 1)] + ["hub/scatter"]
 
 _i32p = ctypes.POINTER(ctypes.c_int32)

@@ -105,6 +105,7 @@ struct Workspace {
     DevBuf hub_table, hub_meta, hub_part, hub_rows, hub_cnt, hub_bucket, hub_bucket_w;
     DevBuf rows;  // per-level row descriptors of the class-sorted vertices
     DevBuf mark;  // active-vertex pruning: last sweep that changed the vertex's neighbourhood
+    DevBuf tiles; // aggregation: per key tile its count, first entry and output position
     DevBuf k64;
     // per-graph state of a level (G entries) and sweep control
     DevBuf ctl, gdone, gsweeps, gmoves, gactive, gsum, gsq, gmeta, segs;
@@ -777,6 +778,33 @@ struct Coarse {
 
 // Aggregation (Algorithm 3): coarse CSR A' = S^T A S of the packed level into
 // ping-pong slot `slot`, with each coarse vertex's graph and degree.
+// Keys label(i) << colbits | label(j) of every CSR entry, summed per tile and
+// packed densely into ws.keys / ws.vals (ws.keys_alt / ws.vals_alt hold the
+// tiles' output first); *e1 = their number.  ws.keys* must hold nnz items.
+lv_status tile_keys(lv_graph* g, int32_t n, const int32_t* off, const int32_t* idx, const int32_t* w, int64_t nnz,
+                    const int32_t* labels, int colbits, const int32_t* gid, int64_t* sigma_in, int64_t* e1)
+{
+    Workspace& ws = g->ws;
+    hipStream_t s = g->stream;
+    const unsigned tiles = build_keys_tiles(n, nnz);
+    HIP_TRY(ws.tiles.ensure(sizeof(int32_t) * 3 * (size_t)tiles));
+    HIP_TRY(ws.tmp.ensure(std::max(radix_tmp_bytes(nnz), scan_tmp_bytes(std::max<int64_t>(nnz, tiles), 8))));
+    int32_t* cnt = ws.tiles.as<int32_t>();
+    int32_t* base = cnt + tiles;
+    int32_t* pos = base + tiles;
+    int32_t* d_tot = (int32_t*)(ws.small.as<char>() + 2560);
+    HIP_TRY(launch_build_keys(n, off, idx, w, nnz, labels, colbits, ws.keys_alt.as<uint64_t>(), ws.vals_alt.as<int32_t>(),
+                              cnt, base, gid, sigma_in, s));
+    HIP_TRY(scan_exclusive_i32(cnt, pos, tiles, d_tot, ws.tmp.p, ws.tmp.cap, s));
+    int32_t tot = 0;
+    HIP_TRY(hipMemcpyAsync(&tot, d_tot, sizeof tot, hipMemcpyDeviceToHost, s));
+    HIP_TRY(launch_compact_tiles(ws.keys_alt.as<uint64_t>(), ws.vals_alt.as<int32_t>(), cnt, base, pos, tiles,
+                                 ws.keys.as<uint64_t>(), ws.vals.as<int32_t>(), s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *e1 = tot;
+    return LV_OK;
+}
+
 lv_status aggregate(lv_graph* g, const LevelGraph& G, int32_t n2, int slot, Coarse& out)
 {
     Workspace& ws = g->ws;
@@ -804,17 +832,20 @@ lv_status aggregate(lv_graph* g, const LevelGraph& G, int32_t n2, int slot, Coar
     HIP_TRY(launch_coarse_degree(G.n, ws.comm.as<int32_t>(), ws.labels.as<int32_t>(), ws.sigma.as<int32_t>(), G.gid,
                                  ws.g_k[slot].as<int32_t>(), gid2, s));
     HIP_TRY(launch_sum_sq(ws.g_k[slot].as<int32_t>(), n2, gid2, d_sq, s));
-    HIP_TRY(launch_build_keys(G.n, G.off, G.idx, G.w, E, ws.labels.as<int32_t>(), colbits, ws.keys.as<uint64_t>(),
-                              ws.vals.as<int32_t>(), G.gid, d_sin, s));
+    // keys summed within tiles first: only the tiles' distinct keys are sorted
+    int64_t Ek = 0;
+    LV_TRY(tile_keys(g, G.n, G.off, G.idx, G.w, E, ws.labels.as<int32_t>(), colbits, G.gid, d_sin, &Ek));
     bool in_alt = false;
     HIP_TRY(radix_sort_u64(ws.keys.as<uint64_t>(), ws.vals.as<int32_t>(), ws.keys_alt.as<uint64_t>(),
-                           ws.vals_alt.as<int32_t>(), E, bits, ws.tmp.p, ws.tmp.cap, &in_alt, s));
+                           ws.vals_alt.as<int32_t>(), Ek, bits, ws.tmp.p, ws.tmp.cap, &in_alt, s));
     const uint64_t* keys = in_alt ? ws.keys_alt.as<uint64_t>() : ws.keys.as<uint64_t>();
     const int32_t* vals = in_alt ? ws.vals_alt.as<int32_t>() : ws.vals.as<int32_t>();
     uint64_t* keys2 = in_alt ? ws.keys.as<uint64_t>() : ws.keys_alt.as<uint64_t>();  // the free sort buffer
     int32_t* d_e2 = (int32_t*)(ws.small.as<char>() + 2304);
-    HIP_TRY(launch_segment_heads(keys, E, ws.head.as<int32_t>(), s));
-    HIP_TRY(scan_exclusive_i32(ws.head.as<int32_t>(), ws.head.as<int32_t>(), E, d_e2, ws.tmp.p, ws.tmp.cap, s));
+    HIP_TRY(hipMemsetAsync(d_e2, 0, sizeof(int32_t), s));
+    HIP_TRY(launch_segment_heads(keys, Ek, ws.head.as<int32_t>(), s));
+    if (Ek > 0)
+        HIP_TRY(scan_exclusive_i32(ws.head.as<int32_t>(), ws.head.as<int32_t>(), Ek, d_e2, ws.tmp.p, ws.tmp.cap, s));
     LV_TRY(ensure_pinned(g, std::max<size_t>(4096, 2 * sizeof(int64_t) * (size_t)G.G + 64)));
     int64_t* h_q = (int64_t*)g->pinned;
     HIP_TRY(hipMemcpyAsync(h_q, d_sin, sizeof(int64_t) * (size_t)G.G, hipMemcpyDeviceToHost, s));
@@ -830,7 +861,7 @@ lv_status aggregate(lv_graph* g, const LevelGraph& G, int32_t n2, int slot, Coar
     HIP_TRY(ws.g_w[slot].ensure(sizeof(int32_t) * (size_t)std::max(e2, 1)));
     int32_t* off2 = ws.g_off[slot].as<int32_t>();
     HIP_TRY(hipMemsetAsync(ws.g_w[slot].p, 0, sizeof(int32_t) * (size_t)std::max(e2, 1), s));
-    HIP_TRY(launch_segment_reduce(keys, vals, ws.head.as<int32_t>(), E, colbits, ws.g_idx[slot].as<int32_t>(),
+    HIP_TRY(launch_segment_reduce(keys, vals, ws.head.as<int32_t>(), Ek, colbits, ws.g_idx[slot].as<int32_t>(),
                                   ws.g_w[slot].as<int32_t>(), keys2, s));
     HIP_TRY(launch_row_offsets(keys2, e2, n2, colbits, off2, s));
     out.n2 = n2;
@@ -972,7 +1003,7 @@ lv_status autotune(lv_graph* g, const Params& base, lv_tuning* best, double* bes
     const std::vector<Knob> knobs = {
         {&lv_tuning::sub_max, {32, 8}},
         {&lv_tuning::wave_max, {128}},
-        {&lv_tuning::block_max, {3584, 2048}},
+        {&lv_tuning::block_max, {3072, 2048}},
         {&lv_tuning::hub_mode, {1}},
         {&lv_tuning::part_keys, {512, 1024}},
         {&lv_tuning::hub_chunk, {2048, 4096}},
@@ -1629,12 +1660,13 @@ lv_status lv_graph_csr(lv_graph* g, int32_t* offsets, int32_t* indices, int32_t*
     }
     int64_t* d_scratch = (int64_t*)(ws.small.as<char>() + 3840);
     HIP_TRY(hipMemsetAsync(d_scratch, 0, sizeof(int64_t), s));
-    HIP_TRY(launch_build_keys(n, g->off.as<int32_t>(), g->idx.as<int32_t>(), g->weighted ? g->w.as<int32_t>() : nullptr,
-                              g->nnz, labels, cb, ws.keys.as<uint64_t>(), ws.vals.as<int32_t>(), nullptr, d_scratch, s));
+    int64_t Ek = 0;
+    LV_TRY(tile_keys(g, n, g->off.as<int32_t>(), g->idx.as<int32_t>(), g->weighted ? g->w.as<int32_t>() : nullptr,
+                     g->nnz, labels, cb, nullptr, d_scratch, &Ek));
     DevBuf off, idx, w;
     int64_t nnz = 0;
     uint64_t* keys2 = nullptr;
-    LV_TRY(csr_from_keys(g, g->nnz, g->nnz, cb, n, off, idx, w, nnz, &keys2));
+    LV_TRY(csr_from_keys(g, Ek, Ek, cb, n, off, idx, w, nnz, &keys2));
     HIP_TRY(launch_halve_diagonal(keys2, nnz, cb, w.as<int32_t>(), s));
     const hipMemcpyKind hk = kind == LV_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
     HIP_TRY(hipMemcpyAsync(offsets, off.p, sizeof(int32_t) * ((size_t)n + 1), hk, s));

@@ -20,12 +20,12 @@ enum MoveClass : int {
     CLS_L4,        // L <= 4:     4 lanes per vertex, LDS table of 8 slots
     CLS_L8,        // L <= 8:     8 lanes, 16 slots
     CLS_L32,       // L <= 32:    16 lanes, 64 slots
-    CLS_L128,      // L <= 128:   32 lanes, 256 slots
-    CLS_L256,      // L <= 256:   one wavefront, 512 slots
-    CLS_L512,      // L <= 512:   128 lanes, 1024 slots
-    CLS_L1K,       // L <= 1024:  one 256-thread workgroup, 2048 slots
-    CLS_L2K,       // L <= 2048:  one 512-thread workgroup, 4096 slots
-    CLS_L3K5,      // L <= 3584:  one 512-thread workgroup, 4096 slots (load <= 7/8)
+    CLS_L128,      // L <= 128:   32 lanes, 208 slots
+    CLS_L256,      // L <= 256:   one wavefront, 424 slots
+    CLS_L512,      // L <= 512:   128 lanes, 848 slots
+    CLS_L1K,       // L <= 1024:  one 256-thread workgroup, 1696 slots
+    CLS_L2K,       // L <= 2048:  one 512-thread workgroup, 3392 slots
+    CLS_L3K,       // L <= 3072:  one 512-thread workgroup, 4096 slots
     CLS_L8K,       // L <= 8192:  one 1024-thread workgroup, 10112 compact slots (two workgroups a CU)
     CLS_HUB,       // several partition workgroups per vertex
     NUM_CLS
@@ -33,7 +33,7 @@ enum MoveClass : int {
 
 // row-length caps of the classes (a vertex takes the first class whose cap is
 // at least its number of entries L)
-constexpr int32_t CLS_CAP[NUM_CLS] = {0, 4, 8, 32, 128, 256, 512, 1024, 2048, 3584, 8192, INT32_MAX};
+constexpr int32_t CLS_CAP[NUM_CLS] = {0, 4, 8, 32, 128, 256, 512, 1024, 2048, 3072, 8192, INT32_MAX};
 // classes of groups narrower than a wavefront, of one wavefront, of workgroups
 constexpr int CLS_FIRST_WAVE = CLS_L256, CLS_FIRST_BLOCK = CLS_L512;
 
@@ -246,9 +246,15 @@ hipError_t launch_perm_rows(int32_t n, const int32_t* off_new, int64_t nnz, cons
 // dst[idx[t]] = src[t]
 hipError_t launch_scatter_i32(const int32_t* src, const int32_t* idx, int32_t m, int32_t* dst, hipStream_t s);
 // keys = (label(i) << colbits) | label(j); sigma_in[g] += weight inside communities (caller zeroes it)
-hipError_t launch_build_keys(int32_t n, const int32_t* off, const int32_t* idx, const int32_t* w,
-                             int64_t nnz, const int32_t* labels, int colbits, uint64_t* keys, int32_t* vals,
-                             const int32_t* gid, int64_t* sigma_in, hipStream_t s);
+// Aggregation keys summed per merge-path tile (build_keys_tiles(n, nnz)
+// tiles): tile b leaves cnt[b] distinct keys/values at base[b]; pack them with
+// launch_compact_tiles (pos = exclusive scan of cnt).
+unsigned build_keys_tiles(int32_t n, int64_t nnz);
+hipError_t launch_build_keys(int32_t n, const int32_t* off, const int32_t* idx, const int32_t* w, int64_t nnz,
+                             const int32_t* labels, int colbits, uint64_t* keys, int32_t* vals, int32_t* cnt,
+                             int32_t* base, const int32_t* gid, int64_t* sigma_in, hipStream_t s);
+hipError_t launch_compact_tiles(const uint64_t* keys, const int32_t* vals, const int32_t* cnt, const int32_t* base,
+                                const int32_t* pos, unsigned tiles, uint64_t* keys2, int32_t* vals2, hipStream_t s);
 // rebuild a packed CSR (off[n_out+1], idx/w[nnz_out], k, gid) from device segment descriptors
 hipError_t launch_repack(const RepackSeg* seg, int32_t nseg, int32_t n_out, int64_t nnz_out, int32_t* off, int32_t* idx,
                          int32_t* w, int32_t* k, int32_t* gid, int32_t* orig, hipStream_t s);

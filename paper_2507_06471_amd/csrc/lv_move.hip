@@ -12,18 +12,23 @@
 //
 // Scheduling by the vertex's number of CSR entries L (degree classes): about
 // one lane per four entries, so that a lane keeps four loads in flight and a
-// compute unit holds many vertices; tables of at most 24 KiB up to L = 1024.
+// compute unit holds many vertices.  Table sizes (12-byte slots: community,
+// weight, volume) let every class run 8 wavefronts a SIMD: at most 20 KiB
+// per 256-thread and 40 KiB per 512-thread workgroup.  Sizes that are not a
+// power of two hash by a multiply-high reduction; a row of L entries uses
+// min(slots, 2L + 1) of them, so a table never fills.
 //   L <= 4      4 lanes per vertex, LDS table of 8 slots
 //   L <= 8      8 lanes, 16 slots
 //   L <= 32     16 lanes, 64 slots
-//   L <= 128    32 lanes, 256 slots
-//   L <= 256    a wavefront, 512 slots
-//   L <= 512    128 lanes, 1024 slots
-//   L <= 1024   a 256-thread workgroup, 2048 slots
-//   L <= 2048   a 512-thread workgroup, 4096 slots
-//   L <= 3584   a 512-thread workgroup, 4096 slots (load at most 7/8)
-//   L <= 8192   a 1024-thread workgroup, 16384 compact slots (128 KiB; the
-//               volume is gathered per distinct community at scan time)
+//   L <= 128    32 lanes, 208 slots
+//   L <= 256    a wavefront, 424 slots
+//   L <= 512    128 lanes, 848 slots
+//   L <= 1024   a 256-thread workgroup, 1696 slots
+//   L <= 2048   a 512-thread workgroup, 3392 slots
+//   L <= 3072   a 512-thread workgroup, 4096 slots
+//   L <= 8192   a 1024-thread workgroup, 10112 compact 8-byte slots (79 KiB,
+//               two workgroups a CU; the volume is gathered per distinct
+//               community at scan time)
 //   L >  8192   P = ceil(L / part_keys) workgroups per vertex;
 //               workgroup p aggregates the communities of hash partition p in
 //               an LDS table; partial results are merged per vertex, and all P
@@ -366,10 +371,12 @@ __global__ __launch_bounds__(BS) void k_move(MoveArgs a)
         int32_t* key = s_key + g * SLOTS;
         int32_t* val = s_val + g * SLOTS;
         int32_t* sig = SIG ? s_sig + g * SLOTS : s_sig;
-        // a power-of-two SLOTS sizes the table to the row; any other SLOTS is
-        // one fixed table, larger than every row of the class
+        // a table of up to SLOTS slots sized to the row (a power of two when
+        // SLOTS is one, else 2L + 1 with multiply-high hashing); SLOTS exceeds
+        // every row of the class, so the table never fills
         constexpr bool POW2 = (SLOTS & (SLOTS - 1)) == 0;
-        const uint32_t T = POW2 ? min((uint32_t)SLOTS, pow2_at_least(2u * (uint32_t)(end - beg))) : (uint32_t)SLOTS;
+        const uint32_t T = POW2 ? min((uint32_t)SLOTS, pow2_at_least(2u * (uint32_t)(end - beg)))
+                                : min((uint32_t)SLOTS, 2u * (uint32_t)(end - beg) + 1u);
         for (uint32_t t = lane; t < T; t += G) { key[t] = EMPTY_KEY; val[t] = 0; }
         group_sync<G>();
         aggregate_entries<G, false, SIG, (G >= 1024 ? 8 : UNROLL), !POW2>(a, i, beg + lane, end, key, val, sig,
@@ -902,12 +909,16 @@ hipError_t launch_move_class(int cls, bool singleton, const MoveArgs& a, hipStre
     case CLS_L4: return launch_move_t<CLS_L4, 256, 4, 8, true>(singleton, a, s);
     case CLS_L8: return launch_move_t<CLS_L8, 256, 8, 16, true>(singleton, a, s);
     case CLS_L32: return launch_move_t<CLS_L32, 256, 16, 64, true>(singleton, a, s);
-    case CLS_L128: return launch_move_t<CLS_L128, 256, 32, 256, true>(singleton, a, s);
-    case CLS_L256: return launch_move_t<CLS_L256, 256, 64, 512, true>(singleton, a, s);
-    case CLS_L512: return launch_move_t<CLS_L512, 256, 128, 1024, true>(singleton, a, s);
-    case CLS_L1K: return launch_move_t<CLS_L1K, 256, 256, 2048, true>(singleton, a, s);
-    case CLS_L2K: return launch_move_t<CLS_L2K, 512, 512, 4096, true>(singleton, a, s);
-    case CLS_L3K5: return launch_move_t<CLS_L3K5, 512, 512, 4096, true>(singleton, a, s);
+    // 1664-1696 slots of 12 bytes per 256-thread workgroup (<= 20 KiB), 3392 per
+    // 512-thread workgroup (<= 40 KiB): eight wavefronts a SIMD.  Rows of
+    // 2049-3072 entries keep 4096 slots (six wavefronts a SIMD): at their load
+    // a 3392-slot table probes longer than the extra workgroup gains.
+    case CLS_L128: return launch_move_t<CLS_L128, 256, 32, 208, true>(singleton, a, s);
+    case CLS_L256: return launch_move_t<CLS_L256, 256, 64, 424, true>(singleton, a, s);
+    case CLS_L512: return launch_move_t<CLS_L512, 256, 128, 848, true>(singleton, a, s);
+    case CLS_L1K: return launch_move_t<CLS_L1K, 256, 256, 1696, true>(singleton, a, s);
+    case CLS_L2K: return launch_move_t<CLS_L2K, 512, 512, 3392, true>(singleton, a, s);
+    case CLS_L3K: return launch_move_t<CLS_L3K, 512, 512, 4096, true>(singleton, a, s);
     // 10112 8-byte slots (79 KiB): two workgroups fit a CU's 160 KiB, and every row of the class
     // (at most 8192 entries) leaves free slots
     case CLS_L8K: return launch_move_t<CLS_L8K, 1024, 1024, 10112, false>(singleton, a, s);
