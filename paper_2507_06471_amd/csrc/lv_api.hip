@@ -326,6 +326,7 @@ struct SweepOut {
     double kern_ms[LV_KERNEL_SLOTS] = {};
     int64_t kern_launches[LV_KERNEL_SLOTS] = {};
     int64_t kern_bytes[LV_KERNEL_SLOTS] = {};
+    int32_t isolated = 0;          // vertices without entries
 };
 
 // Hub (partition) layout for one level.
@@ -545,6 +546,7 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
     for (int c = NUM_CLS - 1; c >= 0; --c)
         if (start[c] < 0) start[c] = start[c + 1];
     const int32_t active = n - start[CLS_L4];  // vertices with at least one entry
+    out.isolated = start[CLS_L4];
     HIP_TRY(ws.rows.ensure(sizeof(int4) * (size_t)std::max(active, 1)));
     HIP_TRY(launch_row_descriptors(vert_sorted + start[CLS_L4], active, G.off, G.k, ws.rows.as<int4>(), s));
 
@@ -778,23 +780,31 @@ struct Coarse {
 
 // Aggregation (Algorithm 3): coarse CSR A' = S^T A S of the packed level into
 // ping-pong slot `slot`, with each coarse vertex's graph and degree.
-// Keys label(i) << colbits | label(j) of every CSR entry, summed per tile and
-// packed densely into ws.keys / ws.vals (ws.keys_alt / ws.vals_alt hold the
-// tiles' output first); *e1 = their number.  ws.keys* must hold nnz items.
-lv_status tile_keys(lv_graph* g, int32_t n, const int32_t* off, const int32_t* idx, const int32_t* w, int64_t nnz,
-                    const int32_t* labels, int colbits, const int32_t* gid, int64_t* sigma_in, int64_t* e1)
+// Keys label(i) << colbits | label(j) of every CSR entry in ws.keys /
+// ws.vals, *e1 = their number.  With `agg` equal keys are summed within tiles
+// first and the tiles' distinct keys packed densely (the tiles' output goes
+// to ws.keys_alt / ws.vals_alt first); else one key per entry.  ws.keys* must
+// hold nnz items.
+lv_status tile_keys(lv_graph* g, bool agg, int32_t n, const int32_t* off, const int32_t* idx, const int32_t* w,
+                    int64_t nnz, const int32_t* labels, int colbits, const int32_t* gid, int64_t* sigma_in, int64_t* e1)
 {
     Workspace& ws = g->ws;
     hipStream_t s = g->stream;
     const unsigned tiles = build_keys_tiles(n, nnz);
+    if (!agg) {
+        HIP_TRY(launch_build_keys(false, n, off, idx, w, nnz, labels, colbits, ws.keys.as<uint64_t>(),
+                                  ws.vals.as<int32_t>(), nullptr, nullptr, gid, sigma_in, s));
+        *e1 = nnz;
+        return LV_OK;
+    }
     HIP_TRY(ws.tiles.ensure(sizeof(int32_t) * 3 * (size_t)tiles));
     HIP_TRY(ws.tmp.ensure(std::max(radix_tmp_bytes(nnz), scan_tmp_bytes(std::max<int64_t>(nnz, tiles), 8))));
     int32_t* cnt = ws.tiles.as<int32_t>();
     int32_t* base = cnt + tiles;
     int32_t* pos = base + tiles;
     int32_t* d_tot = (int32_t*)(ws.small.as<char>() + 2560);
-    HIP_TRY(launch_build_keys(n, off, idx, w, nnz, labels, colbits, ws.keys_alt.as<uint64_t>(), ws.vals_alt.as<int32_t>(),
-                              cnt, base, gid, sigma_in, s));
+    HIP_TRY(launch_build_keys(true, n, off, idx, w, nnz, labels, colbits, ws.keys_alt.as<uint64_t>(),
+                              ws.vals_alt.as<int32_t>(), cnt, base, gid, sigma_in, s));
     HIP_TRY(scan_exclusive_i32(cnt, pos, tiles, d_tot, ws.tmp.p, ws.tmp.cap, s));
     int32_t tot = 0;
     HIP_TRY(hipMemcpyAsync(&tot, d_tot, sizeof tot, hipMemcpyDeviceToHost, s));
@@ -805,7 +815,9 @@ lv_status tile_keys(lv_graph* g, int32_t n, const int32_t* off, const int32_t* i
     return LV_OK;
 }
 
-lv_status aggregate(lv_graph* g, const LevelGraph& G, int32_t n2, int slot, Coarse& out)
+// isolated: vertices without entries (each stays its own community), to
+// judge how strongly the level merged.
+lv_status aggregate(lv_graph* g, const LevelGraph& G, int32_t n2, int32_t isolated, int slot, Coarse& out)
 {
     Workspace& ws = g->ws;
     hipStream_t s = g->stream;
@@ -832,9 +844,12 @@ lv_status aggregate(lv_graph* g, const LevelGraph& G, int32_t n2, int slot, Coar
     HIP_TRY(launch_coarse_degree(G.n, ws.comm.as<int32_t>(), ws.labels.as<int32_t>(), ws.sigma.as<int32_t>(), G.gid,
                                  ws.g_k[slot].as<int32_t>(), gid2, s));
     HIP_TRY(launch_sum_sq(ws.g_k[slot].as<int32_t>(), n2, gid2, d_sq, s));
-    // keys summed within tiles first: only the tiles' distinct keys are sorted
+    // After a level that merged strongly (more than 20 vertices per community
+    // with entries) most of a row's entries share a few keys: sum them within
+    // tiles first, so that only the tiles' distinct keys are sorted.
+    const bool agg = (int64_t)(n2 - isolated) * 20 < (int64_t)(G.n - isolated);
     int64_t Ek = 0;
-    LV_TRY(tile_keys(g, G.n, G.off, G.idx, G.w, E, ws.labels.as<int32_t>(), colbits, G.gid, d_sin, &Ek));
+    LV_TRY(tile_keys(g, agg, G.n, G.off, G.idx, G.w, E, ws.labels.as<int32_t>(), colbits, G.gid, d_sin, &Ek));
     bool in_alt = false;
     HIP_TRY(radix_sort_u64(ws.keys.as<uint64_t>(), ws.vals.as<int32_t>(), ws.keys_alt.as<uint64_t>(),
                            ws.vals_alt.as<int32_t>(), Ek, bits, ws.tmp.p, ws.tmp.cap, &in_alt, s));
@@ -1100,7 +1115,7 @@ lv_status louvain_impl(lv_graph* g, const Params& p, bool keep_graphs, lv_result
         LV_TRY(renumber(g, G, &n2, voff2));
         if (tm.on) HIP_TRY(tm.mark(&t1));
         Coarse co;
-        LV_TRY(aggregate(g, G, n2, slot, co));
+        LV_TRY(aggregate(g, G, n2, so.isolated, slot, co));
         std::vector<int64_t> eoff2;
         LV_TRY(graph_entry_offsets(g, co.off, voff2, eoff2));
         double ren_ms = 0, agg_ms = 0;
@@ -1661,7 +1676,7 @@ lv_status lv_graph_csr(lv_graph* g, int32_t* offsets, int32_t* indices, int32_t*
     int64_t* d_scratch = (int64_t*)(ws.small.as<char>() + 3840);
     HIP_TRY(hipMemsetAsync(d_scratch, 0, sizeof(int64_t), s));
     int64_t Ek = 0;
-    LV_TRY(tile_keys(g, n, g->off.as<int32_t>(), g->idx.as<int32_t>(), g->weighted ? g->w.as<int32_t>() : nullptr,
+    LV_TRY(tile_keys(g, false, n, g->off.as<int32_t>(), g->idx.as<int32_t>(), g->weighted ? g->w.as<int32_t>() : nullptr,
                      g->nnz, labels, cb, nullptr, d_scratch, &Ek));
     DevBuf off, idx, w;
     int64_t nnz = 0;

@@ -48,15 +48,80 @@ __global__ void k_coarse_degree(int32_t n, const int32_t* comm, const int32_t* l
     }
 }
 
-// Aggregation keys, summed per tile.  Tile b covers merge-path items
-// [b*AG_T, (b+1)*AG_T) of the n row ends and nnz entries; each of its entries
-// (i, j, w) becomes the key label(i) << colbits | label(j) with weight w.
-// Row labels are staged in LDS, column labels gathered in one batched pass,
-// and equal keys of the tile summed in an LDS hash table (a tile holds at
-// most AG_T distinct keys in twice as many slots).  The tile's distinct keys
-// are written from entry y0 of the tile on: keys[y0 + r], vals[y0 + r],
-// r < cnt[b], and base[b] = y0.  sigma_in[g] += weight of graph g's entries
-// inside one community.
+// Plain keys: keys/vals per entry; sigma_in[g] += weight of graph g's entries inside one community.
+// Merge-path tiles as in for_tile_entries, with the tile's indices and weights
+// loaded into LDS and its keys and weights stored from LDS, both coalesced.
+__global__ __launch_bounds__(TILE_BS) void k_entry_keys(int32_t n, const int32_t* off, const int32_t* idx,
+                                                         const int32_t* w, int64_t nnz, const int32_t* labels,
+                                                         int colbits, uint64_t* keys, int32_t* vals,
+                                                         const int32_t* gid, unsigned long long* sigma_in)
+{
+    constexpr int T = TILE_BS * TILE_IT;
+    __shared__ int32_t s_off[T + 2];
+    __shared__ int64_t s_x[2];
+    __shared__ int32_t s_j[T];
+    __shared__ int32_t s_w[T];
+    __shared__ uint64_t s_key[T];
+    const int64_t total = (int64_t)n + nnz;
+    const int64_t d0 = (int64_t)blockIdx.x * T;
+    const int64_t d1 = d0 + T < total ? d0 + T : total;
+    if (threadIdx.x < 2) s_x[threadIdx.x] = mp_rows(off, n, threadIdx.x ? d1 : d0);
+    __syncthreads();
+    const int64_t x0 = s_x[0], x1 = s_x[1];
+    const int64_t y0 = d0 - x0, y1 = d1 - x1;
+    const int64_t last = x1 + 1 < n ? x1 + 1 : n;
+    const int64_t rows = last - x0 + 1;
+    const int32_t ne = (int32_t)(y1 - y0);
+    for (int64_t t = threadIdx.x; t < rows; t += TILE_BS) s_off[t] = off[x0 + t];
+    for (int32_t q = threadIdx.x; q < ne; q += TILE_BS) {
+        s_j[q] = idx[y0 + q];
+        s_w[q] = w ? w[y0 + q] : 1;
+    }
+    __syncthreads();
+    int32_t g_cur = -1;
+    unsigned long long s = 0;
+    const int32_t q0 = threadIdx.x * TILE_IT;
+    if (q0 < ne) {
+        int64_t lo = 0, hi = rows;  // row of entry y0 + q0: last r with off[r] <= y0 + q0
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) / 2;
+            if ((int64_t)s_off[mid] <= y0 + q0) lo = mid + 1; else hi = mid;
+        }
+        int64_t r = x0 + lo - 1;
+        for (int j = 0; j < TILE_IT && q0 + j < ne; ++j) {
+            const int64_t e = y0 + q0 + j;
+            while ((int64_t)s_off[r + 1 - x0] <= e) ++r;
+            const uint32_t a = (uint32_t)labels[r], b = (uint32_t)labels[s_j[q0 + j]];
+            const int32_t wv = s_w[q0 + j];
+            s_key[q0 + j] = ((uint64_t)a << colbits) | (uint64_t)b;
+            if (a == b) {
+                const int32_t gg = gid ? gid[r] : 0;
+                if (gg != g_cur) {
+                    if (g_cur >= 0 && s) atomicAdd(&sigma_in[g_cur], s);
+                    g_cur = gg;
+                    s = 0;
+                }
+                s += (unsigned long long)wv;
+            }
+        }
+    }
+    __syncthreads();
+    for (int32_t q = threadIdx.x; q < ne; q += TILE_BS) {
+        keys[y0 + q] = s_key[q];
+        vals[y0 + q] = s_w[q];
+    }
+    const bool valid = g_cur >= 0 && s != 0;
+    wave_grouped_add<unsigned long long, unsigned long long>(sigma_in, valid ? g_cur : 0, s, valid);
+}
+
+// Aggregation keys.  Tile b covers merge-path items [b*AG_T, (b+1)*AG_T) of
+// the n row ends and nnz entries; each of its entries (i, j, w) becomes the
+// key label(i) << colbits | label(j) with weight w.  Row labels are staged in
+// LDS and column labels gathered in one batched pass.
+// Equal keys of the tile are summed in an LDS hash table (at most AG_T
+// distinct keys in twice as many slots); the tile's distinct keys go to
+// keys[y0 + r], vals[y0 + r], r < cnt[b], base[b] = y0.
+// sigma_in[g] += weight of graph g's entries inside one community.
 constexpr int AG_IT = 4;
 constexpr int AG_T = TILE_BS * AG_IT;  // items per tile
 constexpr int AG_HS = 2 * AG_T;        // hash slots
@@ -67,7 +132,18 @@ __device__ __forceinline__ uint32_t key_slot(uint64_t k)
     return (uint32_t)((k * 0x9E3779B97F4A7C15ull) >> 40) & (uint32_t)(AG_HS - 1);
 }
 
-__global__ __launch_bounds__(TILE_BS) void k_build_keys(int32_t n, const int32_t* off, const int32_t* idx,
+__device__ __forceinline__ void hash_add(uint64_t* h_key, int32_t* h_val, uint64_t key, int32_t wv)
+{
+    uint32_t h = key_slot(key);
+    for (;;) {
+        const uint64_t prev =
+            atomicCAS((unsigned long long*)&h_key[h], (unsigned long long)AG_EMPTY, (unsigned long long)key);
+        if (prev == AG_EMPTY || prev == key) { atomicAdd(&h_val[h], wv); return; }
+        h = (h + 1) & (uint32_t)(AG_HS - 1);
+    }
+}
+
+__global__ __launch_bounds__(TILE_BS) void k_tile_keys(int32_t n, const int32_t* off, const int32_t* idx,
                                                          const int32_t* w, int64_t nnz, const int32_t* labels,
                                                          int colbits, uint64_t* keys, int32_t* vals, int32_t* cnt,
                                                          int32_t* base, const int32_t* gid,
@@ -131,14 +207,7 @@ __global__ __launch_bounds__(TILE_BS) void k_build_keys(int32_t n, const int32_t
             while ((int64_t)s_off[r + 1 - x0] <= e) ++r;
             const uint32_t a = (uint32_t)s_rl[r - x0], b = (uint32_t)s_j[q0 + j];
             const int32_t wv = s_w[q0 + j];
-            const uint64_t key = ((uint64_t)a << colbits) | (uint64_t)b;
-            uint32_t h = key_slot(key);
-            for (;;) {
-                const uint64_t prev = atomicCAS((unsigned long long*)&h_key[h], (unsigned long long)AG_EMPTY,
-                                                (unsigned long long)key);
-                if (prev == AG_EMPTY || prev == key) { atomicAdd(&h_val[h], wv); break; }
-                h = (h + 1) & (uint32_t)(AG_HS - 1);
-            }
+            hash_add(h_key, h_val, ((uint64_t)a << colbits) | (uint64_t)b, wv);
             if (a == b) {
                 const int32_t gg = gid ? gid[r] : 0;
                 if (gg != g_cur) {
@@ -416,12 +485,16 @@ unsigned build_keys_tiles(int32_t n, int64_t nnz)
     const int64_t t = ((int64_t)n + nnz + AG_T - 1) / AG_T;
     return (unsigned)(t > 0 ? t : 1);
 }
-hipError_t launch_build_keys(int32_t n, const int32_t* off, const int32_t* idx, const int32_t* w, int64_t nnz,
+hipError_t launch_build_keys(bool agg, int32_t n, const int32_t* off, const int32_t* idx, const int32_t* w, int64_t nnz,
                              const int32_t* labels, int colbits, uint64_t* keys, int32_t* vals, int32_t* cnt,
                              int32_t* base, const int32_t* gid, int64_t* sigma_in, hipStream_t s)
 {
-    k_build_keys<<<build_keys_tiles(n, nnz), TILE_BS, 0, s>>>(n, off, idx, w, nnz, labels, colbits, keys, vals, cnt,
-                                                               base, gid, (unsigned long long*)sigma_in);
+    if (agg)
+        k_tile_keys<<<build_keys_tiles(n, nnz), TILE_BS, 0, s>>>(n, off, idx, w, nnz, labels, colbits, keys, vals, cnt,
+                                                                  base, gid, (unsigned long long*)sigma_in);
+    else if (nnz > 0)
+        k_entry_keys<<<tiles_for(n, nnz), TILE_BS, 0, s>>>(n, off, idx, w, nnz, labels, colbits, keys, vals, gid,
+                                                            (unsigned long long*)sigma_in);
     return hipGetLastError();
 }
 hipError_t launch_compact_tiles(const uint64_t* keys, const int32_t* vals, const int32_t* cnt, const int32_t* base,

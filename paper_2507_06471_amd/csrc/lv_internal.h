@@ -246,11 +246,12 @@ hipError_t launch_perm_rows(int32_t n, const int32_t* off_new, int64_t nnz, cons
 // dst[idx[t]] = src[t]
 hipError_t launch_scatter_i32(const int32_t* src, const int32_t* idx, int32_t m, int32_t* dst, hipStream_t s);
 // keys = (label(i) << colbits) | label(j); sigma_in[g] += weight inside communities (caller zeroes it)
-// Aggregation keys summed per merge-path tile (build_keys_tiles(n, nnz)
-// tiles): tile b leaves cnt[b] distinct keys/values at base[b]; pack them with
-// launch_compact_tiles (pos = exclusive scan of cnt).
+// Aggregation keys per merge-path tile (build_keys_tiles(n, nnz) tiles).  agg:
+// summed per tile, tile b leaving cnt[b] distinct keys/values at base[b] (pack
+// them with launch_compact_tiles, pos = exclusive scan of cnt); else one key
+// per entry at the entry's index.
 unsigned build_keys_tiles(int32_t n, int64_t nnz);
-hipError_t launch_build_keys(int32_t n, const int32_t* off, const int32_t* idx, const int32_t* w, int64_t nnz,
+hipError_t launch_build_keys(bool agg, int32_t n, const int32_t* off, const int32_t* idx, const int32_t* w, int64_t nnz,
                              const int32_t* labels, int colbits, uint64_t* keys, int32_t* vals, int32_t* cnt,
                              int32_t* base, const int32_t* gid, int64_t* sigma_in, hipStream_t s);
 hipError_t launch_compact_tiles(const uint64_t* keys, const int32_t* vals, const int32_t* cnt, const int32_t* base,
