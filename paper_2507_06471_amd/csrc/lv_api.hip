@@ -793,22 +793,21 @@ lv_status tile_keys(lv_graph* g, bool agg, int32_t n, const int32_t* off, const 
     const unsigned tiles = build_keys_tiles(n, nnz);
     if (!agg) {
         HIP_TRY(launch_build_keys(false, n, off, idx, w, nnz, labels, colbits, ws.keys.as<uint64_t>(),
-                                  ws.vals.as<int32_t>(), nullptr, nullptr, gid, sigma_in, s));
+                                  ws.vals.as<int32_t>(), nullptr, gid, sigma_in, s));
         *e1 = nnz;
         return LV_OK;
     }
-    HIP_TRY(ws.tiles.ensure(sizeof(int32_t) * 3 * (size_t)tiles));
+    HIP_TRY(ws.tiles.ensure(sizeof(int32_t) * 5 * (size_t)tiles));
     HIP_TRY(ws.tmp.ensure(std::max(radix_tmp_bytes(nnz), scan_tmp_bytes(std::max<int64_t>(nnz, tiles), 8))));
-    int32_t* cnt = ws.tiles.as<int32_t>();
-    int32_t* base = cnt + tiles;
-    int32_t* pos = base + tiles;
+    int32_t* meta = ws.tiles.as<int32_t>();
+    int32_t* pos = meta + 4 * (size_t)tiles;
     int32_t* d_tot = (int32_t*)(ws.small.as<char>() + 2560);
     HIP_TRY(launch_build_keys(true, n, off, idx, w, nnz, labels, colbits, ws.keys_alt.as<uint64_t>(),
-                              ws.vals_alt.as<int32_t>(), cnt, base, gid, sigma_in, s));
-    HIP_TRY(scan_exclusive_i32(cnt, pos, tiles, d_tot, ws.tmp.p, ws.tmp.cap, s));
+                              ws.vals_alt.as<int32_t>(), meta, gid, sigma_in, s));
+    HIP_TRY(scan_exclusive_i32(meta, pos, tiles, d_tot, ws.tmp.p, ws.tmp.cap, s));
     int32_t tot = 0;
     HIP_TRY(hipMemcpyAsync(&tot, d_tot, sizeof tot, hipMemcpyDeviceToHost, s));
-    HIP_TRY(launch_compact_tiles(ws.keys_alt.as<uint64_t>(), ws.vals_alt.as<int32_t>(), cnt, base, pos, tiles,
+    HIP_TRY(launch_compact_tiles(ws.keys_alt.as<uint64_t>(), ws.vals_alt.as<int32_t>(), meta, pos, tiles,
                                  ws.keys.as<uint64_t>(), ws.vals.as<int32_t>(), s));
     HIP_TRY(hipStreamSynchronize(s));
     *e1 = tot;

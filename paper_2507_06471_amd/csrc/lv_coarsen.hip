@@ -114,17 +114,22 @@ __global__ __launch_bounds__(TILE_BS) void k_entry_keys(int32_t n, const int32_t
     wave_grouped_add<unsigned long long, unsigned long long>(sigma_in, valid ? g_cur : 0, s, valid);
 }
 
-// Aggregation keys.  Tile b covers merge-path items [b*AG_T, (b+1)*AG_T) of
-// the n row ends and nnz entries; each of its entries (i, j, w) becomes the
-// key label(i) << colbits | label(j) with weight w.  Row labels are staged in
-// LDS and column labels gathered in one batched pass.
-// Equal keys of the tile are summed in an LDS hash table (at most AG_T
-// distinct keys in twice as many slots); the tile's distinct keys go to
-// keys[y0 + r], vals[y0 + r], r < cnt[b], base[b] = y0.
+// Aggregation keys summed per tile, for levels that merged strongly.  Tile b
+// covers merge-path items [b*AG_T, (b+1)*AG_T) of the n row ends and nnz
+// entries; thread t takes AG_IT consecutive entries of it, loads their
+// indices and weights and gathers their column labels before using any.
+// Each entry (i, j, w) becomes the key label(i) << colbits | label(j) and is
+// added into the tile's LDS hash table.  An entry that finds no slot within
+// AG_PROBE probes is written out as it is (the global sort merges equal keys
+// anyway), from the end of the tile's range.  Out: the table's distinct keys
+// at keys[y0 + r], r < cnt[b], and the unplaced entries at
+// keys[y0 + ne - ovf[b] + r], r < ovf[b].  meta holds four arrays of one
+// int per tile: keys contributed (cnt + ovf), y0, cnt, ne.
 // sigma_in[g] += weight of graph g's entries inside one community.
-constexpr int AG_IT = 4;
-constexpr int AG_T = TILE_BS * AG_IT;  // items per tile
-constexpr int AG_HS = 2 * AG_T;        // hash slots
+constexpr int AG_IT = 16;
+constexpr int AG_T = TILE_BS * AG_IT;  // merge-path items per tile
+constexpr int AG_HS = 2048;            // hash slots (24 KiB)
+constexpr int AG_PROBE = 64;
 constexpr uint64_t AG_EMPTY = ~0ull;   // keys use at most 62 bits
 
 __device__ __forceinline__ uint32_t key_slot(uint64_t k)
@@ -132,82 +137,74 @@ __device__ __forceinline__ uint32_t key_slot(uint64_t k)
     return (uint32_t)((k * 0x9E3779B97F4A7C15ull) >> 40) & (uint32_t)(AG_HS - 1);
 }
 
-__device__ __forceinline__ void hash_add(uint64_t* h_key, int32_t* h_val, uint64_t key, int32_t wv)
+__device__ __forceinline__ bool hash_add(uint64_t* h_key, int32_t* h_val, uint64_t key, int32_t wv)
 {
     uint32_t h = key_slot(key);
-    for (;;) {
+    for (int p = 0; p < AG_PROBE; ++p) {
         const uint64_t prev =
             atomicCAS((unsigned long long*)&h_key[h], (unsigned long long)AG_EMPTY, (unsigned long long)key);
-        if (prev == AG_EMPTY || prev == key) { atomicAdd(&h_val[h], wv); return; }
+        if (prev == AG_EMPTY || prev == key) { atomicAdd(&h_val[h], wv); return true; }
         h = (h + 1) & (uint32_t)(AG_HS - 1);
     }
+    return false;
 }
 
 __global__ __launch_bounds__(TILE_BS) void k_tile_keys(int32_t n, const int32_t* off, const int32_t* idx,
-                                                         const int32_t* w, int64_t nnz, const int32_t* labels,
-                                                         int colbits, uint64_t* keys, int32_t* vals, int32_t* cnt,
-                                                         int32_t* base, const int32_t* gid,
-                                                         unsigned long long* sigma_in)
+                                                        const int32_t* w, int64_t nnz, const int32_t* labels,
+                                                        int colbits, uint64_t* keys, int32_t* vals, int32_t* meta,
+                                                        const int32_t* gid, unsigned long long* sigma_in)
 {
     __shared__ uint64_t h_key[AG_HS];
     __shared__ int32_t h_val[AG_HS];
-    __shared__ int32_t s_off[AG_T + 2];
-    __shared__ int32_t s_rl[AG_T + 2];
-    __shared__ int32_t s_j[AG_T];
-    __shared__ int32_t s_w[AG_T];
     __shared__ int64_t s_x[2];
-    __shared__ int32_t s_cnt;
+    __shared__ int32_t s_cnt, s_ovf;
     const int64_t total = (int64_t)n + nnz;
     const int64_t d0 = (int64_t)blockIdx.x * AG_T;
     const int64_t d1 = d0 + AG_T < total ? d0 + AG_T : total;
     if (threadIdx.x < 2) s_x[threadIdx.x] = mp_rows(off, n, threadIdx.x ? d1 : d0);
-    if (threadIdx.x == 0) s_cnt = 0;
+    if (threadIdx.x == 0) { s_cnt = 0; s_ovf = 0; }
     for (int t = threadIdx.x; t < AG_HS; t += TILE_BS) { h_key[t] = AG_EMPTY; h_val[t] = 0; }
     __syncthreads();
     const int64_t x0 = s_x[0], x1 = s_x[1];
     const int64_t y0 = d0 - x0, y1 = d1 - x1;
-    const int64_t last = x1 + 1 < n ? x1 + 1 : n;
-    const int64_t rows = last - x0 + 1;
     const int32_t ne = (int32_t)(y1 - y0);
-    for (int64_t t = threadIdx.x; t < rows; t += TILE_BS) {
-        s_off[t] = off[x0 + t];
-        s_rl[t] = x0 + t < n ? labels[x0 + t] : 0;
-    }
-    for (int32_t q = threadIdx.x; q < ne; q += TILE_BS) {
-        s_j[q] = idx[y0 + q];
-        s_w[q] = w ? w[y0 + q] : 1;
-    }
-    __syncthreads();
-    {
-        int32_t lj[AG_IT];
-#pragma unroll
-        for (int u = 0; u < AG_IT; ++u) {
-            const int32_t q = threadIdx.x + u * TILE_BS;
-            lj[u] = q < ne ? labels[s_j[q]] : 0;
-        }
-#pragma unroll
-        for (int u = 0; u < AG_IT; ++u) {
-            const int32_t q = threadIdx.x + u * TILE_BS;
-            if (q < ne) s_j[q] = lj[u];
-        }
-    }
-    __syncthreads();
+    const int64_t last = x1 + 1 < n ? x1 + 1 : n;
     int32_t g_cur = -1;
     unsigned long long s = 0;
     const int32_t q0 = threadIdx.x * AG_IT;
     if (q0 < ne) {
-        int64_t lo = 0, hi = rows;  // row of entry y0 + q0: last r with off[r] <= y0 + q0
-        while (lo < hi) {
-            const int64_t mid = (lo + hi) / 2;
-            if ((int64_t)s_off[mid] <= y0 + q0) lo = mid + 1; else hi = mid;
+        const int32_t m = ne - q0 < AG_IT ? ne - q0 : AG_IT;
+        int32_t jj[AG_IT], ww[AG_IT];
+#pragma unroll
+        for (int u = 0; u < AG_IT; ++u) {
+            jj[u] = u < m ? idx[y0 + q0 + u] : 0;
+            ww[u] = (u < m && w) ? w[y0 + q0 + u] : 1;
         }
-        int64_t r = x0 + lo - 1;
-        for (int j = 0; j < AG_IT && q0 + j < ne; ++j) {
-            const int64_t e = y0 + q0 + j;
-            while ((int64_t)s_off[r + 1 - x0] <= e) ++r;
-            const uint32_t a = (uint32_t)s_rl[r - x0], b = (uint32_t)s_j[q0 + j];
-            const int32_t wv = s_w[q0 + j];
-            hash_add(h_key, h_val, ((uint64_t)a << colbits) | (uint64_t)b, wv);
+#pragma unroll
+        for (int u = 0; u < AG_IT; ++u) jj[u] = u < m ? labels[jj[u]] : 0;
+        int64_t lo = x0, hi = last;  // row of entry y0 + q0: last r with off[r] <= y0 + q0
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) / 2;
+            if ((int64_t)off[mid] <= y0 + q0) lo = mid; else hi = mid - 1;
+        }
+        int64_t r = lo;
+        int64_t rend = off[r + 1];
+        uint32_t a = (uint32_t)labels[r];
+#pragma unroll
+        for (int u = 0; u < AG_IT; ++u) {
+            if (u >= m) break;
+            const int64_t e = y0 + q0 + u;
+            if (e >= rend) {
+                do { ++r; rend = off[r + 1]; } while (e >= rend);
+                a = (uint32_t)labels[r];
+            }
+            const uint32_t b = (uint32_t)jj[u];
+            const uint64_t key = ((uint64_t)a << colbits) | (uint64_t)b;
+            if (!hash_add(h_key, h_val, key, ww[u])) {
+                const int32_t p = ne - 1 - atomicAdd(&s_ovf, 1);
+                keys[y0 + p] = key;
+                vals[y0 + p] = ww[u];
+            }
             if (a == b) {
                 const int32_t gg = gid ? gid[r] : 0;
                 if (gg != g_cur) {
@@ -215,7 +212,7 @@ __global__ __launch_bounds__(TILE_BS) void k_tile_keys(int32_t n, const int32_t*
                     g_cur = gg;
                     s = 0;
                 }
-                s += (unsigned long long)wv;
+                s += (unsigned long long)ww[u];
             }
         }
     }
@@ -225,36 +222,40 @@ __global__ __launch_bounds__(TILE_BS) void k_tile_keys(int32_t n, const int32_t*
         const int t = t0 + threadIdx.x;
         const uint64_t k = h_key[t];
         const bool has = k != AG_EMPTY;
-        const uint64_t m = __ballot(has);
+        const uint64_t mk = __ballot(has);
         int32_t wbase = 0;
-        if (lane_id() == 0 && m) wbase = atomicAdd(&s_cnt, __popcll(m));
+        if (lane_id() == 0 && mk) wbase = atomicAdd(&s_cnt, __popcll(mk));
         wbase = __shfl(wbase, 0);
         if (has) {
-            const int32_t pos = wbase + __popcll(m & ((1ull << lane_id()) - 1ull));
+            const int32_t pos = wbase + __popcll(mk & ((1ull << lane_id()) - 1ull));
             keys[y0 + pos] = k;
             vals[y0 + pos] = h_val[t];
         }
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        cnt[blockIdx.x] = s_cnt;
-        base[blockIdx.x] = (int32_t)y0;
+        const int64_t T = gridDim.x, b = blockIdx.x;
+        meta[b] = s_cnt + s_ovf;  // keys the tile contributes
+        meta[T + b] = (int32_t)y0;
+        meta[2 * T + b] = s_cnt;
+        meta[3 * T + b] = ne;
     }
     const bool valid = g_cur >= 0 && s != 0;
     wave_grouped_add<unsigned long long, unsigned long long>(sigma_in, valid ? g_cur : 0, s, valid);
 }
 
-// Pack the tiles' distinct keys densely: tile b's cnt[b] keys from base[b]
-// go to pos[b] (the exclusive scan of cnt).
-__global__ __launch_bounds__(256) void k_compact_tiles(const uint64_t* keys, const int32_t* vals, const int32_t* cnt,
-                                                       const int32_t* base, const int32_t* pos, uint64_t* keys2,
-                                                       int32_t* vals2)
+// Pack the tiles' keys densely: tile b's distinct keys [y0, y0 + c) and
+// unplaced entries [y0 + ne - o, y0 + ne), o = total - c, go to pos[b] on.
+__global__ __launch_bounds__(256) void k_compact_tiles(const uint64_t* keys, const int32_t* vals, const int32_t* meta,
+                                                       const int32_t* pos, uint64_t* keys2, int32_t* vals2)
 {
-    const int b = blockIdx.x;
-    const int32_t c = cnt[b], from = base[b], to = pos[b];
-    for (int32_t q = threadIdx.x; q < c; q += 256) {
-        keys2[to + q] = keys[from + q];
-        vals2[to + q] = vals[from + q];
+    const int64_t T = gridDim.x, b = blockIdx.x;
+    const int32_t tot = meta[b], from = meta[T + b], c = meta[2 * T + b], ne = meta[3 * T + b];
+    const int32_t to = pos[blockIdx.x];
+    for (int32_t q = threadIdx.x; q < tot; q += 256) {
+        const int32_t src = q < c ? from + q : from + ne - (tot - q);
+        keys2[to + q] = keys[src];
+        vals2[to + q] = vals[src];
     }
 }
 
@@ -486,21 +487,21 @@ unsigned build_keys_tiles(int32_t n, int64_t nnz)
     return (unsigned)(t > 0 ? t : 1);
 }
 hipError_t launch_build_keys(bool agg, int32_t n, const int32_t* off, const int32_t* idx, const int32_t* w, int64_t nnz,
-                             const int32_t* labels, int colbits, uint64_t* keys, int32_t* vals, int32_t* cnt,
-                             int32_t* base, const int32_t* gid, int64_t* sigma_in, hipStream_t s)
+                             const int32_t* labels, int colbits, uint64_t* keys, int32_t* vals, int32_t* meta,
+                             const int32_t* gid, int64_t* sigma_in, hipStream_t s)
 {
     if (agg)
-        k_tile_keys<<<build_keys_tiles(n, nnz), TILE_BS, 0, s>>>(n, off, idx, w, nnz, labels, colbits, keys, vals, cnt,
-                                                                  base, gid, (unsigned long long*)sigma_in);
+        k_tile_keys<<<build_keys_tiles(n, nnz), TILE_BS, 0, s>>>(n, off, idx, w, nnz, labels, colbits, keys, vals, meta,
+                                                                  gid, (unsigned long long*)sigma_in);
     else if (nnz > 0)
         k_entry_keys<<<tiles_for(n, nnz), TILE_BS, 0, s>>>(n, off, idx, w, nnz, labels, colbits, keys, vals, gid,
                                                             (unsigned long long*)sigma_in);
     return hipGetLastError();
 }
-hipError_t launch_compact_tiles(const uint64_t* keys, const int32_t* vals, const int32_t* cnt, const int32_t* base,
-                                const int32_t* pos, unsigned tiles, uint64_t* keys2, int32_t* vals2, hipStream_t s)
+hipError_t launch_compact_tiles(const uint64_t* keys, const int32_t* vals, const int32_t* meta, const int32_t* pos,
+                                unsigned tiles, uint64_t* keys2, int32_t* vals2, hipStream_t s)
 {
-    k_compact_tiles<<<tiles, 256, 0, s>>>(keys, vals, cnt, base, pos, keys2, vals2);
+    k_compact_tiles<<<tiles, 256, 0, s>>>(keys, vals, meta, pos, keys2, vals2);
     return hipGetLastError();
 }
 hipError_t launch_repack(const RepackSeg* seg, int32_t nseg, int32_t n_out, int64_t nnz_out, int32_t* off, int32_t* idx,

@@ -246,16 +246,17 @@ hipError_t launch_perm_rows(int32_t n, const int32_t* off_new, int64_t nnz, cons
 // dst[idx[t]] = src[t]
 hipError_t launch_scatter_i32(const int32_t* src, const int32_t* idx, int32_t m, int32_t* dst, hipStream_t s);
 // keys = (label(i) << colbits) | label(j); sigma_in[g] += weight inside communities (caller zeroes it)
-// Aggregation keys per merge-path tile (build_keys_tiles(n, nnz) tiles).  agg:
-// summed per tile, tile b leaving cnt[b] distinct keys/values at base[b] (pack
-// them with launch_compact_tiles, pos = exclusive scan of cnt); else one key
-// per entry at the entry's index.
+// Aggregation keys.  agg = false: one key per entry at the entry's index.
+// agg = true: summed per tile (build_keys_tiles(n, nnz) = T tiles), tile b
+// leaving meta[b + k T], k = 0..3 = {keys, first entry, distinct keys,
+// entries}; pack them with launch_compact_tiles (pos = exclusive scan of
+// meta[0..T)).
 unsigned build_keys_tiles(int32_t n, int64_t nnz);
 hipError_t launch_build_keys(bool agg, int32_t n, const int32_t* off, const int32_t* idx, const int32_t* w, int64_t nnz,
-                             const int32_t* labels, int colbits, uint64_t* keys, int32_t* vals, int32_t* cnt,
-                             int32_t* base, const int32_t* gid, int64_t* sigma_in, hipStream_t s);
-hipError_t launch_compact_tiles(const uint64_t* keys, const int32_t* vals, const int32_t* cnt, const int32_t* base,
-                                const int32_t* pos, unsigned tiles, uint64_t* keys2, int32_t* vals2, hipStream_t s);
+                             const int32_t* labels, int colbits, uint64_t* keys, int32_t* vals, int32_t* meta,
+                             const int32_t* gid, int64_t* sigma_in, hipStream_t s);
+hipError_t launch_compact_tiles(const uint64_t* keys, const int32_t* vals, const int32_t* meta, const int32_t* pos,
+                                unsigned tiles, uint64_t* keys2, int32_t* vals2, hipStream_t s);
 // rebuild a packed CSR (off[n_out+1], idx/w[nnz_out], k, gid) from device segment descriptors
 hipError_t launch_repack(const RepackSeg* seg, int32_t nseg, int32_t n_out, int64_t nnz_out, int32_t* off, int32_t* idx,
                          int32_t* w, int32_t* k, int32_t* gid, int32_t* orig, hipStream_t s);
