@@ -48,78 +48,14 @@ __global__ void k_coarse_degree(int32_t n, const int32_t* comm, const int32_t* l
     }
 }
 
-// Plain keys: keys/vals per entry; sigma_in[g] += weight of graph g's entries inside one community.
-// Merge-path tiles as in for_tile_entries, with the tile's indices and weights
-// loaded into LDS and its keys and weights stored from LDS, both coalesced.
-__global__ __launch_bounds__(TILE_BS) void k_entry_keys(int32_t n, const int32_t* off, const int32_t* idx,
-                                                         const int32_t* w, int64_t nnz, const int32_t* labels,
-                                                         int colbits, uint64_t* keys, int32_t* vals,
-                                                         const int32_t* gid, unsigned long long* sigma_in)
-{
-    constexpr int T = TILE_BS * TILE_IT;
-    __shared__ int32_t s_off[T + 2];
-    __shared__ int64_t s_x[2];
-    __shared__ int32_t s_j[T];
-    __shared__ int32_t s_w[T];
-    __shared__ uint64_t s_key[T];
-    const int64_t total = (int64_t)n + nnz;
-    const int64_t d0 = (int64_t)blockIdx.x * T;
-    const int64_t d1 = d0 + T < total ? d0 + T : total;
-    if (threadIdx.x < 2) s_x[threadIdx.x] = mp_rows(off, n, threadIdx.x ? d1 : d0);
-    __syncthreads();
-    const int64_t x0 = s_x[0], x1 = s_x[1];
-    const int64_t y0 = d0 - x0, y1 = d1 - x1;
-    const int64_t last = x1 + 1 < n ? x1 + 1 : n;
-    const int64_t rows = last - x0 + 1;
-    const int32_t ne = (int32_t)(y1 - y0);
-    for (int64_t t = threadIdx.x; t < rows; t += TILE_BS) s_off[t] = off[x0 + t];
-    for (int32_t q = threadIdx.x; q < ne; q += TILE_BS) {
-        s_j[q] = idx[y0 + q];
-        s_w[q] = w ? w[y0 + q] : 1;
-    }
-    __syncthreads();
-    int32_t g_cur = -1;
-    unsigned long long s = 0;
-    const int32_t q0 = threadIdx.x * TILE_IT;
-    if (q0 < ne) {
-        int64_t lo = 0, hi = rows;  // row of entry y0 + q0: last r with off[r] <= y0 + q0
-        while (lo < hi) {
-            const int64_t mid = (lo + hi) / 2;
-            if ((int64_t)s_off[mid] <= y0 + q0) lo = mid + 1; else hi = mid;
-        }
-        int64_t r = x0 + lo - 1;
-        for (int j = 0; j < TILE_IT && q0 + j < ne; ++j) {
-            const int64_t e = y0 + q0 + j;
-            while ((int64_t)s_off[r + 1 - x0] <= e) ++r;
-            const uint32_t a = (uint32_t)labels[r], b = (uint32_t)labels[s_j[q0 + j]];
-            const int32_t wv = s_w[q0 + j];
-            s_key[q0 + j] = ((uint64_t)a << colbits) | (uint64_t)b;
-            if (a == b) {
-                const int32_t gg = gid ? gid[r] : 0;
-                if (gg != g_cur) {
-                    if (g_cur >= 0 && s) atomicAdd(&sigma_in[g_cur], s);
-                    g_cur = gg;
-                    s = 0;
-                }
-                s += (unsigned long long)wv;
-            }
-        }
-    }
-    __syncthreads();
-    for (int32_t q = threadIdx.x; q < ne; q += TILE_BS) {
-        keys[y0 + q] = s_key[q];
-        vals[y0 + q] = s_w[q];
-    }
-    const bool valid = g_cur >= 0 && s != 0;
-    wave_grouped_add<unsigned long long, unsigned long long>(sigma_in, valid ? g_cur : 0, s, valid);
-}
-
-// Aggregation keys summed per tile, for levels that merged strongly.  Tile b
-// covers merge-path items [b*AG_T, (b+1)*AG_T) of the n row ends and nnz
-// entries; thread t takes AG_IT consecutive entries of it, loads their
-// indices and weights and gathers their column labels before using any.
-// Each entry (i, j, w) becomes the key label(i) << colbits | label(j) and is
-// added into the tile's LDS hash table.  An entry that finds no slot within
+// Aggregation keys.  Tile b covers merge-path items [b*AG_T, (b+1)*AG_T) of
+// the n row ends and nnz entries; thread t takes AG_IT consecutive entries of
+// it, loads their indices and weights and gathers their column labels before
+// using any.  Each entry (i, j, w) becomes the key label(i) << colbits |
+// label(j) with weight w.
+//   SUM = false: every entry's key and weight go to keys[e], vals[e].
+//   SUM = true (levels that merged strongly): the keys are added into the
+// tile's LDS hash table.  An entry that finds no slot within
 // AG_PROBE probes is written out as it is (the global sort merges equal keys
 // anyway), from the end of the tile's range.  Out: the table's distinct keys
 // at keys[y0 + r], r < cnt[b], and the unplaced entries at
@@ -149,13 +85,14 @@ __device__ __forceinline__ bool hash_add(uint64_t* h_key, int32_t* h_val, uint64
     return false;
 }
 
+template <bool SUM>
 __global__ __launch_bounds__(TILE_BS) void k_tile_keys(int32_t n, const int32_t* off, const int32_t* idx,
                                                         const int32_t* w, int64_t nnz, const int32_t* labels,
                                                         int colbits, uint64_t* keys, int32_t* vals, int32_t* meta,
                                                         const int32_t* gid, unsigned long long* sigma_in)
 {
-    __shared__ uint64_t h_key[AG_HS];
-    __shared__ int32_t h_val[AG_HS];
+    __shared__ uint64_t h_key[SUM ? AG_HS : 1];
+    __shared__ int32_t h_val[SUM ? AG_HS : 1];
     __shared__ int64_t s_x[2];
     __shared__ int32_t s_cnt, s_ovf;
     const int64_t total = (int64_t)n + nnz;
@@ -163,7 +100,8 @@ __global__ __launch_bounds__(TILE_BS) void k_tile_keys(int32_t n, const int32_t*
     const int64_t d1 = d0 + AG_T < total ? d0 + AG_T : total;
     if (threadIdx.x < 2) s_x[threadIdx.x] = mp_rows(off, n, threadIdx.x ? d1 : d0);
     if (threadIdx.x == 0) { s_cnt = 0; s_ovf = 0; }
-    for (int t = threadIdx.x; t < AG_HS; t += TILE_BS) { h_key[t] = AG_EMPTY; h_val[t] = 0; }
+    if constexpr (SUM)
+        for (int t = threadIdx.x; t < AG_HS; t += TILE_BS) { h_key[t] = AG_EMPTY; h_val[t] = 0; }
     __syncthreads();
     const int64_t x0 = s_x[0], x1 = s_x[1];
     const int64_t y0 = d0 - x0, y1 = d1 - x1;
@@ -200,10 +138,15 @@ __global__ __launch_bounds__(TILE_BS) void k_tile_keys(int32_t n, const int32_t*
             }
             const uint32_t b = (uint32_t)jj[u];
             const uint64_t key = ((uint64_t)a << colbits) | (uint64_t)b;
-            if (!hash_add(h_key, h_val, key, ww[u])) {
-                const int32_t p = ne - 1 - atomicAdd(&s_ovf, 1);
-                keys[y0 + p] = key;
-                vals[y0 + p] = ww[u];
+            if constexpr (SUM) {
+                if (!hash_add(h_key, h_val, key, ww[u])) {
+                    const int32_t p = ne - 1 - atomicAdd(&s_ovf, 1);
+                    keys[y0 + p] = key;
+                    vals[y0 + p] = ww[u];
+                }
+            } else {
+                keys[e] = key;
+                vals[e] = ww[u];
             }
             if (a == b) {
                 const int32_t gg = gid ? gid[r] : 0;
@@ -216,6 +159,7 @@ __global__ __launch_bounds__(TILE_BS) void k_tile_keys(int32_t n, const int32_t*
             }
         }
     }
+    if constexpr (SUM) {
     __syncthreads();
     // distinct keys out: one LDS atomic per wavefront reserves its positions
     for (int t0 = 0; t0 < AG_HS; t0 += TILE_BS) {
@@ -239,6 +183,7 @@ __global__ __launch_bounds__(TILE_BS) void k_tile_keys(int32_t n, const int32_t*
         meta[T + b] = (int32_t)y0;
         meta[2 * T + b] = s_cnt;
         meta[3 * T + b] = ne;
+    }
     }
     const bool valid = g_cur >= 0 && s != 0;
     wave_grouped_add<unsigned long long, unsigned long long>(sigma_in, valid ? g_cur : 0, s, valid);
@@ -491,11 +436,11 @@ hipError_t launch_build_keys(bool agg, int32_t n, const int32_t* off, const int3
                              const int32_t* gid, int64_t* sigma_in, hipStream_t s)
 {
     if (agg)
-        k_tile_keys<<<build_keys_tiles(n, nnz), TILE_BS, 0, s>>>(n, off, idx, w, nnz, labels, colbits, keys, vals, meta,
-                                                                  gid, (unsigned long long*)sigma_in);
+        k_tile_keys<true><<<build_keys_tiles(n, nnz), TILE_BS, 0, s>>>(n, off, idx, w, nnz, labels, colbits, keys, vals,
+                                                                        meta, gid, (unsigned long long*)sigma_in);
     else if (nnz > 0)
-        k_entry_keys<<<tiles_for(n, nnz), TILE_BS, 0, s>>>(n, off, idx, w, nnz, labels, colbits, keys, vals, gid,
-                                                            (unsigned long long*)sigma_in);
+        k_tile_keys<false><<<build_keys_tiles(n, nnz), TILE_BS, 0, s>>>(n, off, idx, w, nnz, labels, colbits, keys,
+                                                                         vals, meta, gid, (unsigned long long*)sigma_in);
     return hipGetLastError();
 }
 hipError_t launch_compact_tiles(const uint64_t* keys, const int32_t* vals, const int32_t* meta, const int32_t* pos,
