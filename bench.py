@@ -400,11 +400,12 @@ def main():
     log(f"graph resident on the device in {time.time() - t:.1f}s (volume M={dg.volume})")
 
     if args.copy_probe_mib > 0:
-        # a plain copy kernel of known size: reads and writes copy_probe_mib MiB
+        # a plain streaming kernel of known size under a name no other kernel
+        # here has: reads and writes copy_probe_mib MiB
         src = torch.ones(args.copy_probe_mib << 18, dtype=torch.int32, device="cuda")
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
-        dst.copy_(src)
+        torch.bitwise_not(src, out=dst)
         torch.cuda.synchronize()
         log(f"copy probe: {args.copy_probe_mib} MiB read + {args.copy_probe_mib} MiB written")
         del src, dst
