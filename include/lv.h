@@ -84,6 +84,13 @@ typedef enum lv_memkind { LV_MEM_HOST = 0, LV_MEM_DEVICE = 1 } lv_memkind;
                           /* afterwards only a vertex that, or one of whose neighbours, changed     */
                           /* community in sweep s-1 or s-2; the others keep their community.        */
                           /* Changes results (for Louvain; LPA's are provably the same).           */
+#define LV_ASYNC 32u      /* asynchronous sweeps, as Alg. 1 and 2 are written: every vertex reads */
+                          /* the labels and community volumes as they stand, and a mover updates  */
+                          /* both in place at once (atomics); no direction gate; a level ends     */
+                          /* after one sweep with at most threshold moves.  Results depend on     */
+                          /* scheduling and are not reproducible; every invariant (Sigma_tot sums */
+                          /* to M, exact Q_int of the returned labels, level acceptance) holds.  */
+                          /* With LV_PRUNE the active set looks one sweep back (Alg. 2).          */
 
 typedef struct lv_graph lv_graph;   /* device-resident CSR + workspace, library-owned */
 typedef struct lv_result lv_result; /* per-level labels and statistics, library-owned */

@@ -37,6 +37,7 @@ LV_KEEP_GRAPHS = 2
 LV_NO_HIPGRAPH = 4
 LV_AUTOTUNE = 8
 LV_PRUNE = 16
+LV_ASYNC = 32
 KERNEL_SLOTS = 23
 # kernel slot -> name (slot = 2*(class-1) + first-sweep flag; the last slot is
 # the bucketed hub scatter pass, whose partition workgroups are timed as "hub")
@@ -385,12 +386,12 @@ class FinalPartition:
 
 
 def louvain_final(graph: Graph, max_sweeps: int = 20, max_levels: int = 32, tuning: Optional[dict] = None,
-                  autotuned: bool = False, out=None, prune: bool = False) -> FinalPartition:
+                  autotuned: bool = False, out=None, prune: bool = False, asynchronous: bool = False) -> FinalPartition:
     """lv_louvain, then only the final labels and modularity of every graph
     (two calls, whatever the number of graphs); `out` may be a numpy or
     torch int32 buffer of the handle's total vertex count."""
     lib = load_library()
-    p, _keep = make_params(max_sweeps, max_levels, 0, _flags(False, False, True, autotuned, prune), tuning)
+    p, _keep = make_params(max_sweeps, max_levels, 0, _flags(False, False, True, autotuned, prune, asynchronous), tuning)
     r = _vp()
     _check(lib.lv_louvain(graph.handle, ctypes.byref(p), ctypes.byref(r)), "lv_louvain")
     try:
@@ -445,20 +446,22 @@ def _read_graph_result(lib, r, gi: int, n0: int, keep_graphs: bool, level_labels
 
 
 def _flags(timing: bool, keep_graphs: bool = False, hipgraph: bool = True, autotuned: bool = False,
-           prune: bool = False) -> int:
+           prune: bool = False, asynchronous: bool = False) -> int:
     return ((LV_TIMING if timing else 0) | (LV_KEEP_GRAPHS if keep_graphs else 0) | (0 if hipgraph else LV_NO_HIPGRAPH)
-            | (LV_AUTOTUNE if autotuned else 0) | (LV_PRUNE if prune else 0))
+            | (LV_AUTOTUNE if autotuned else 0) | (LV_PRUNE if prune else 0) | (LV_ASYNC if asynchronous else 0))
 
 
 def louvain(graph: Graph, max_sweeps: int = 20, max_levels: int = 32, timing: bool = False,
             keep_graphs: bool = False, tuning: Optional[dict] = None, hipgraph: bool = True,
-            autotuned: bool = False, level_labels: bool = True, prune: bool = False):
+            autotuned: bool = False, level_labels: bool = True, prune: bool = False, asynchronous: bool = False):
     """lv_louvain + result accessors, copied to host numpy.  A packed handle
     (``Graph.batch``) gives one LouvainResult per graph, in order.  With
     level_labels=False only the final labels are copied (levels keep their
-    statistics and move counts).  prune=True sets LV_PRUNE."""
+    statistics and move counts).  prune=True sets LV_PRUNE, asynchronous=True
+    LV_ASYNC."""
     lib = load_library()
-    p, _keep = make_params(max_sweeps, max_levels, 0, _flags(timing, keep_graphs, hipgraph, autotuned, prune), tuning)
+    p, _keep = make_params(max_sweeps, max_levels, 0, _flags(timing, keep_graphs, hipgraph, autotuned, prune,
+                                                            asynchronous), tuning)
     r = _vp()
     _check(lib.lv_louvain(graph.handle, ctypes.byref(p), ctypes.byref(r)), "lv_louvain")
     try:
@@ -477,13 +480,15 @@ class LpaResult:
 
 
 def lpa(graph: Graph, max_sweeps: int = 20, threshold: int = 0, timing: bool = False, out=None,
-        tuning: Optional[dict] = None, hipgraph: bool = True, autotuned: bool = False, prune: bool = False) -> LpaResult:
+        tuning: Optional[dict] = None, hipgraph: bool = True, autotuned: bool = False, prune: bool = False,
+        asynchronous: bool = False) -> LpaResult:
     """lv_lpa; labels land in `out` (numpy or torch int32) or a new numpy array."""
     lib = load_library()
     if graph.count != 1:
         return lpa_batch(graph, max_sweeps, threshold, tuning=tuning, hipgraph=hipgraph, autotuned=autotuned,
-                         prune=prune)
-    p, _keep = make_params(max_sweeps, 32, threshold, _flags(timing, False, hipgraph, autotuned, prune), tuning)
+                         prune=prune, asynchronous=asynchronous)
+    p, _keep = make_params(max_sweeps, 32, threshold, _flags(timing, False, hipgraph, autotuned, prune, asynchronous),
+                           tuning)
     labels = np.empty(graph.n, dtype=np.int32) if out is None else out
     pl, kind = _ptr(labels)
     info = lv_level_info()
@@ -494,10 +499,12 @@ def lpa(graph: Graph, max_sweeps: int = 20, threshold: int = 0, timing: bool = F
 
 
 def lpa_batch(graph: Graph, max_sweeps: int = 20, threshold: int = 0, tuning: Optional[dict] = None,
-              hipgraph: bool = True, autotuned: bool = False, prune: bool = False) -> List[LpaResult]:
+              hipgraph: bool = True, autotuned: bool = False, prune: bool = False,
+              asynchronous: bool = False) -> List[LpaResult]:
     """lv_lpa_batch over a packed handle: one LpaResult per graph (local labels)."""
     lib = load_library()
-    p, _keep = make_params(max_sweeps, 32, threshold, _flags(False, False, hipgraph, autotuned, prune), tuning)
+    p, _keep = make_params(max_sweeps, 32, threshold, _flags(False, False, hipgraph, autotuned, prune, asynchronous),
+                           tuning)
     G = graph.count
     labels = np.empty(max(graph.n, 1), dtype=np.int32)
     sw = np.zeros(G, dtype=np.int32)

@@ -590,6 +590,12 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
     a.gdone = G.G > 1 ? ws.gdone.as<int32_t>() : nullptr;
     a.ctl = ctl;
     a.mode = mode;
+    const bool async = (p.flags & LV_ASYNC) != 0;
+    a.live_comm = async ? ws.comm.as<int32_t>() : nullptr;
+    a.live_sigma = async ? ws.sigma.as<int32_t>() : nullptr;
+    a.gmoves = ws.gmoves.as<uint32_t>();
+    a.max_sweeps = S;
+    a.prune_back = async ? 1 : 2;
     int32_t* mark = nullptr;
     if (p.flags & LV_PRUNE) {
         HIP_TRY(ws.mark.ensure(nb));
@@ -607,6 +613,7 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
     // One sweep: move kernels of every class, the partition path, commit,
     // pair refresh, per-graph stopping rule.
     auto launch_sweep = [&](bool singleton, std::vector<hipEvent_t>* e) -> lv_status {
+        singleton = singleton && !async;  // an asynchronous sweep changes communities as it runs
         if (e) { e->assign(2 * NUM_CLS + 4, nullptr); HIP_TRY(tm.mark(&(*e)[2 * NUM_CLS])); }
         for (int c = CLS_L4; c < CLS_HUB; ++c) {
             a.verts = vert_sorted + start[c];
@@ -615,7 +622,7 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
             a.nverts = start[c + 1] - start[c];
             if (a.nverts == 0) continue;
             if (e) HIP_TRY(tm.mark(&(*e)[2 * c]));
-            HIP_TRY(launch_move_class(c, singleton, a, s));
+            HIP_TRY(launch_move_class(c, singleton, async, a, s));
             if (e) HIP_TRY(tm.mark(&(*e)[2 * c + 1]));
         }
         if (hubs.nhubs > 0) {
@@ -641,11 +648,15 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
                 HIP_TRY(launch_hub_mark(a, hubs.args, mark, s));
             }
         }
-        HIP_TRY(launch_apply(vert_sorted + start[CLS_L4], dec_all + start[CLS_L4], active, G.k, a.gid,
-                             ws.comm.as<int32_t>(), ws.sigma.as<int32_t>(), ctl, ws.gmoves.as<uint32_t>(), S, s));
-        HIP_TRY(launch_pairs(n, ws.comm.as<int32_t>(), ws.sigma.as<int32_t>(), ws.cs.as<int2>(), ctl, s));
+        if (!async) {  // asynchronous sweeps have moved already
+            HIP_TRY(launch_apply(vert_sorted + start[CLS_L4], dec_all + start[CLS_L4], active, G.k, a.gid,
+                                 ws.comm.as<int32_t>(), ws.sigma.as<int32_t>(), ctl, ws.gmoves.as<uint32_t>(), S, s));
+            HIP_TRY(launch_pairs(n, ws.comm.as<int32_t>(), ws.sigma.as<int32_t>(), ws.cs.as<int2>(), ctl, s));
+        }
+        // synchronous sweeps alternate direction, so a level ends after two
+        // quiet sweeps; an asynchronous level ends after one (Alg. 2's test)
         HIP_TRY(launch_sweep_end(ctl, G.G, ws.gdone.as<int32_t>(), ws.gsweeps.as<int32_t>(),
-                                 ws.gmoves.as<uint32_t>(), S, theta, s));
+                                 ws.gmoves.as<uint32_t>(), S, theta, async ? 1 : 2, s));
         if (e) HIP_TRY(tm.mark(&(*e)[2 * NUM_CLS + 2]));
         return LV_OK;
     };
@@ -1088,9 +1099,8 @@ lv_status louvain_impl(lv_graph* g, const Params& p, bool keep_graphs, lv_result
     {
         HIP_TRY(ws.gmeta.ensure(sizeof(int32_t) * ((size_t)G0 + 1)));
         HIP_TRY(hipMemcpyAsync(ws.gmeta.p, g->voff.data(), sizeof(int32_t) * ((size_t)G0 + 1), hipMemcpyHostToDevice, s));
-        // each vertex's position within its graph in level 0's storage order
-        if (g->reordered) HIP_TRY(launch_copy_i32(r->final_labels.as<int32_t>(), g->inv.as<int32_t>(), g->n, s));
-        else HIP_TRY(launch_iota(r->final_labels.as<int32_t>(), g->n, s));
+        // (a graph that accepts no level keeps the singleton partition in id order)
+        HIP_TRY(launch_iota(r->final_labels.as<int32_t>(), g->n, s));
         HIP_TRY(launch_local_labels(g->n, r->final_labels.as<int32_t>(), G0 > 1 ? g->d_gid.as<int32_t>() : nullptr,
                                     ws.gmeta.as<int32_t>(), r->final_labels.as<int32_t>(), s));
     }
@@ -1178,11 +1188,13 @@ lv_status louvain_impl(lv_graph* g, const Params& p, bool keep_graphs, lv_result
             }
             gr.levels.push_back(std::move(rec));
         }
-        // compose the final labels of the graphs that accepted this level
+        // compose the final labels of the graphs that accepted this level, with
+        // the level's labels in vertex-id order (the store's copy when the
+        // level is stored by degree)
         if (any) {
+            const int32_t* lab_id = G.orig ? store->labels.as<int32_t>() : ws.labels.as<int32_t>();
             if (G0 == 1) {
-                HIP_TRY(launch_compose(g->n, r->final_labels.as<int32_t>(), ws.labels.as<int32_t>(), nullptr, nullptr,
-                                       nullptr, nullptr, s));
+                HIP_TRY(launch_compose(g->n, r->final_labels.as<int32_t>(), lab_id, nullptr, nullptr, nullptr, nullptr, s));
             } else {
                 std::vector<int32_t> meta((size_t)G0 + 2 * (size_t)G.G, -1);
                 for (int32_t c = 0; c < G.G; ++c) {
@@ -1192,7 +1204,7 @@ lv_status louvain_impl(lv_graph* g, const Params& p, bool keep_graphs, lv_result
                 }
                 HIP_TRY(ws.gmeta.ensure(sizeof(int32_t) * meta.size()));
                 HIP_TRY(hipMemcpyAsync(ws.gmeta.p, meta.data(), sizeof(int32_t) * meta.size(), hipMemcpyHostToDevice, s));
-                HIP_TRY(launch_compose(g->n, r->final_labels.as<int32_t>(), ws.labels.as<int32_t>(),
+                HIP_TRY(launch_compose(g->n, r->final_labels.as<int32_t>(), lab_id,
                                        g->d_gid.as<int32_t>(), ws.gmeta.as<int32_t>(), ws.gmeta.as<int32_t>() + G0,
                                        ws.gmeta.as<int32_t>() + G0 + G.G, s));
                 HIP_TRY(hipStreamSynchronize(s));

@@ -65,6 +65,14 @@ struct MoveArgs {
     int32_t* dec;           // decision per listed vertex: target community or -1
     const int32_t* mark;    // active-vertex pruning: per vertex, the last sweep in which it or a
                             // neighbour changed community (null: every vertex is evaluated)
+    int32_t prune_back;     // pruning looks this many sweeps back (2 synchronous, 1 asynchronous)
+    // asynchronous mode (null: synchronous): labels and community volumes read
+    // and updated in place during the sweep; moves counted into
+    // gmoves[graph * max_sweeps + sweep]
+    int32_t* live_comm;
+    int32_t* live_sigma;
+    uint32_t* gmoves;
+    int32_t max_sweeps;
 };
 
 // One segment of a packed CSR rebuild (see launch_repack).
@@ -204,7 +212,7 @@ hipError_t launch_class_entries(const int32_t* verts_sorted, const int32_t* star
                                 int64_t* out, hipStream_t s);
 
 // sweep
-hipError_t launch_move_class(int cls, bool singleton, const MoveArgs& a, hipStream_t s);
+hipError_t launch_move_class(int cls, bool singleton, bool async, const MoveArgs& a, hipStream_t s);
 hipError_t launch_hub_clear(int32_t* table, int64_t slots, hipStream_t s);
 // bucketed mode, sweeps after the first: scatter the hubs' entries to the partition buckets
 hipError_t launch_hub_scatter(const MoveArgs& a, const HubArgs& h, hipStream_t s);
@@ -226,7 +234,7 @@ hipError_t launch_apply(const int32_t* verts, const int32_t* dec, int32_t m, con
 hipError_t launch_ctl_init(SweepCtl* ctl, int32_t G, const int32_t* gactive, int32_t* gdone, int32_t* gsweeps,
                            uint32_t* gmoves, int32_t max_sweeps, hipStream_t s);
 hipError_t launch_sweep_end(SweepCtl* ctl, int32_t G, int32_t* gdone, int32_t* gsweeps, const uint32_t* gmoves,
-                            int32_t max_sweeps, int64_t theta, hipStream_t s);
+                            int32_t max_sweeps, int64_t theta, int32_t consecutive, hipStream_t s);
 
 // renumber + aggregation
 hipError_t launch_renumber(int32_t n, const int32_t* comm, const int32_t* orig, int32_t* minv, int32_t* flag,

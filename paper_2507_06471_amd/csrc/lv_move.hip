@@ -136,7 +136,49 @@ __device__ __forceinline__ bool vertex_skipped(const MoveArgs& a, int32_t i)
 {
     if (!a.mark) return false;
     const int32_t s = a.ctl->sweep + 1;
-    return s > 2 && a.mark[i] < s - 2;
+    return s > a.prune_back && a.mark[i] < s - a.prune_back;
+}
+
+// Asynchronous mode (Alg. 2 as written: labels and community volumes change
+// in place while the sweep runs).  Label and (label, volume) of vertex j as
+// they stand now, or from the sweep's snapshot in synchronous mode.
+__device__ __forceinline__ int32_t comm_now(const MoveArgs& a, int32_t j)
+{
+    return a.live_comm ? a.live_comm[j] : a.cs[j].x;
+}
+__device__ __forceinline__ int2 pair_now(const MoveArgs& a, int32_t j)
+{
+    if (!a.live_comm) return a.cs[j];
+    const int32_t c = a.live_comm[j];
+    return make_int2(c, a.live_sigma[c]);
+}
+// Graph-major index into gmoves of vertex i's graph for the current sweep.
+__device__ __forceinline__ int64_t move_slot(const MoveArgs& a, int32_t i)
+{
+    return (a.gid ? (int64_t)a.gid[i] * a.max_sweeps : 0) + a.ctl->sweep;
+}
+
+// Asynchronous decision of vertex i (own community A read when its table was
+// built; only i changes its own label): against the live volume of A, move
+// at once if the best community beats staying (no direction gate), updating
+// both volumes atomically and the label in place.  Returns whether i moved.
+__device__ __forceinline__ bool decide_apply(const MoveArgs& a, int64_t pos, int32_t i, int32_t A, int64_t ki,
+                                             int64_t M, int64_t best_s, int32_t best_c, int32_t w_own)
+{
+    bool mover = false;
+    if (best_c != INT32_MAX) {
+        const bool louvain = a.mode == MODE_LOUVAIN;
+        const int64_t sA = louvain ? (int64_t)a.live_sigma[A] : 0;
+        const int64_t stay = louvain ? M * w_own - ki * (sA - ki) : (int64_t)w_own;
+        mover = best_s > stay;
+    }
+    if (mover) {
+        atomicAdd(&a.live_sigma[A], -(int32_t)ki);
+        atomicAdd(&a.live_sigma[best_c], (int32_t)ki);
+        a.live_comm[i] = best_c;
+    }
+    a.dec[pos] = mover ? best_c : -1;
+    return mover;
 }
 
 // Decision of vertex-list slot `pos`: the best community if it beats staying
@@ -339,7 +381,7 @@ __device__ __forceinline__ void group_sync()
 
 // One group of G lanes per vertex (G <= BS); LDS table of up to SLOTS slots.
 // (CLS only names the instantiation, so each degree class has its own kernel symbol)
-template <int CLS, int BS, int G, int SLOTS, bool SINGLETON, bool SIG>
+template <int CLS, int BS, int G, int SLOTS, bool SINGLETON, bool SIG, bool ASYNC = false>
 __global__ __launch_bounds__(BS) void k_move(MoveArgs a)
 {
     constexpr int NG = BS / G;
@@ -358,7 +400,7 @@ __global__ __launch_bounds__(BS) void k_move(MoveArgs a)
     const int32_t i = row.x;
     const bool live = has && !vertex_frozen(a, i) && !vertex_skipped(a, i);
     const int32_t beg = live ? row.y : 0, end = live ? row.z : 0;
-    const int2 self = live ? a.cs[i] : make_int2(0, 0);
+    const int2 self = live ? (ASYNC ? make_int2(a.live_comm[i], 0) : a.cs[i]) : make_int2(0, 0);
     const int32_t A = self.x;
     const int64_t ki = live ? row.w : 0;
     const int64_t M = live ? vertex_M(a, i) : 0;
@@ -401,20 +443,25 @@ __global__ __launch_bounds__(BS) void k_move(MoveArgs a)
             }
         }
     }
+    bool moved = false;
     if (has && lane == 0) {
-        if (live) decide_store(a, vi, A, self.y, ki, M, best_s, best_c, w_own);
-        else a.dec[vi] = -1;
+        if (!live) a.dec[vi] = -1;
+        else if constexpr (ASYNC) moved = decide_apply(a, vi, i, A, ki, M, best_s, best_c, w_own);
+        else decide_store(a, vi, A, self.y, ki, M, best_s, best_c, w_own);
     }
+    if constexpr (ASYNC) block_flush_sums<BS, uint32_t>(a.gmoves, moved ? move_slot(a, i) : -1, moved ? 1u : 0u);
 }
 
 template <int CLS, int BS, int G, int SLOTS, bool SIG>
-hipError_t launch_move_t(bool singleton, const MoveArgs& a, hipStream_t s)
+hipError_t launch_move_t(bool singleton, bool async, const MoveArgs& a, hipStream_t s)
 {
     static_assert(SLOTS > CLS_CAP[CLS], "a class's table must hold every distinct community of its longest row");
     if (a.nverts <= 0) return hipSuccess;
     constexpr int NG = BS / G;
     const unsigned grid = (unsigned)((a.nverts + NG - 1) / NG);
-    if (singleton) k_move<CLS, BS, G, SLOTS, true, false><<<grid, BS, 0, s>>>(a);
+    // asynchronous sweeps read volumes live at scan time (compact tables)
+    if (async) k_move<CLS, BS, G, SLOTS, false, false, true><<<grid, BS, 0, s>>>(a);
+    else if (singleton) k_move<CLS, BS, G, SLOTS, true, false><<<grid, BS, 0, s>>>(a);
     else k_move<CLS, BS, G, SLOTS, false, SIG><<<grid, BS, 0, s>>>(a);
     return hipGetLastError();
 }
@@ -455,7 +502,7 @@ __global__ __launch_bounds__(BS) void k_hub_part(MoveArgs a, HubArgs h)
         return;
     }
     const int32_t beg = a.off[i], end = a.off[i + 1];
-    const int32_t A = a.cs[i].x;
+    const int32_t A = comm_now(a, i);
     const int64_t ki = a.k[i];
     const int64_t M = vertex_M(a, i);
     int64_t best_s = INT64_MIN;
@@ -512,7 +559,7 @@ __global__ __launch_bounds__(256) void k_hub_finalize(MoveArgs a, HubArgs h)
     int64_t ki = 0;
     if (has) {
         i = h.hub_vert[hh];
-        const int2 self = a.cs[i];
+        const int2 self = pair_now(a, i);
         A = self.x;
         sA = self.y;
         ki = a.k[i];
@@ -525,7 +572,13 @@ __global__ __launch_bounds__(256) void k_hub_finalize(MoveArgs a, HubArgs h)
     group_reduce<WAVE>(best_s, best_c, w_own);
     const bool overflowed = __ballot(flag != 0) != 0;
     if (has && overflowed && lane_id() == 0) h.fb_flag[hh] = 1;
-    if (has && !overflowed && lane_id() == 0) decide_store(a, hh, A, sA, ki, vertex_M(a, i), best_s, best_c, w_own);
+    if (has && !overflowed && lane_id() == 0) {
+        if (a.live_comm) {
+            if (decide_apply(a, hh, i, A, ki, vertex_M(a, i), best_s, best_c, w_own)) atomicAdd(&a.gmoves[move_slot(a, i)], 1u);
+        } else {
+            decide_store(a, hh, A, sA, ki, vertex_M(a, i), best_s, best_c, w_own);
+        }
+    }
 }
 
 // Scatter the entries of hubs with P > 1 into their partitions' buckets.  A
@@ -565,7 +618,7 @@ __global__ __launch_bounds__(SBS) void k_hub_scatter(MoveArgs a, HubArgs h)
             ww[u] = (ok && a.w) ? __builtin_nontemporal_load(&a.w[e]) : 1;
         }
 #pragma unroll
-        for (int u = 0; u < SC_EPT; ++u) cc[u] = jj[u] != i ? a.cs[jj[u]] : make_int2(EMPTY_KEY, 0);
+        for (int u = 0; u < SC_EPT; ++u) cc[u] = jj[u] != i ? pair_now(a, jj[u]) : make_int2(EMPTY_KEY, 0);
         // at most SBS * EPT distinct keys in twice as many slots: always room
 #pragma unroll
         for (int u = 0; u < SC_EPT; ++u)
@@ -620,7 +673,7 @@ __global__ __launch_bounds__(FBS) void k_fb_insert(MoveArgs a, HubArgs h)
     for (int32_t e = h.ins_beg[b] + threadIdx.x; e < h.ins_end[b]; e += FBS) {
         const int32_t j = a.idx[e];
         if (j == i) continue;
-        const int32_t C = a.cs[j].x;
+        const int32_t C = comm_now(a, j);
         const int32_t W = a.w ? a.w[e] : 1;
         uint32_t slot = mix32(C) & mask;
         for (;;) {
@@ -640,7 +693,7 @@ __global__ __launch_bounds__(FBS) void k_fb_scan(MoveArgs a, HubArgs h)
     const int32_t hh = h.scan_hub[b];
     if (!h.fb_flag[hh]) return;
     const int32_t i = h.hub_vert[hh];
-    const int32_t A = a.cs[i].x;
+    const int32_t A = comm_now(a, i);
     const int64_t ki = a.k[i];
     const bool louvain = a.mode == MODE_LOUVAIN;
     int32_t* tab = h.table + 2 * h.tab_off[hh];
@@ -671,7 +724,7 @@ __global__ __launch_bounds__(256) void k_fb_finalize(MoveArgs a, HubArgs h)
     int64_t ki = 0;
     if (has) {
         i = h.hub_vert[hh];
-        const int2 self = a.cs[i];
+        const int2 self = pair_now(a, i);
         A = self.x;
         sA = self.y;
         ki = a.k[i];
@@ -682,7 +735,11 @@ __global__ __launch_bounds__(256) void k_fb_finalize(MoveArgs a, HubArgs h)
     }
     group_reduce<WAVE>(best_s, best_c, w_own);
     if (has && lane_id() == 0) {
-        decide_store(a, hh, A, sA, ki, vertex_M(a, i), best_s, best_c, w_own);
+        if (a.live_comm) {
+            if (decide_apply(a, hh, i, A, ki, vertex_M(a, i), best_s, best_c, w_own)) atomicAdd(&a.gmoves[move_slot(a, i)], 1u);
+        } else {
+            decide_store(a, hh, A, sA, ki, vertex_M(a, i), best_s, best_c, w_own);
+        }
         h.fb_flag[hh] = 0;
     }
 }
@@ -783,7 +840,8 @@ __global__ __launch_bounds__(256) void k_apply(const int32_t* verts, const int32
 // sweeps moved at most theta vertices each, or when s == max_sweeps.  Sets
 // all_done when no graph runs any more, so later sweeps' kernels exit early.
 __global__ __launch_bounds__(256) void k_sweep_end(SweepCtl* ctl, int32_t G, int32_t* gdone, int32_t* gsweeps,
-                                                   const uint32_t* gmoves, int32_t max_sweeps, int64_t theta)
+                                                   const uint32_t* gmoves, int32_t max_sweeps, int64_t theta,
+                                                   int32_t consecutive)
 {
     __shared__ int32_t red[4];
     if (ctl->all_done) return;
@@ -792,7 +850,9 @@ __global__ __launch_bounds__(256) void k_sweep_end(SweepCtl* ctl, int32_t G, int
     for (int32_t g = threadIdx.x; g < G; g += 256) {
         if (gdone[g]) continue;
         const uint32_t* mv = gmoves + (int64_t)g * max_sweeps;
-        const bool stop = (s >= 2 && (int64_t)mv[s - 1] <= theta && (int64_t)mv[s - 2] <= theta) || s >= max_sweeps;
+        bool quiet = s >= consecutive;
+        for (int32_t q = 1; q <= consecutive && quiet; ++q) quiet = (int64_t)mv[s - q] <= theta;
+        const bool stop = quiet || s >= max_sweeps;
         if (stop) { gdone[g] = 1; gsweeps[g] = s; } else ++running;
     }
     running = block_sum<256>(running, red);
@@ -856,9 +916,9 @@ hipError_t launch_ctl_init(SweepCtl* ctl, int32_t G, const int32_t* gactive, int
     return hipGetLastError();
 }
 hipError_t launch_sweep_end(SweepCtl* ctl, int32_t G, int32_t* gdone, int32_t* gsweeps, const uint32_t* gmoves,
-                            int32_t max_sweeps, int64_t theta, hipStream_t s)
+                            int32_t max_sweeps, int64_t theta, int32_t consecutive, hipStream_t s)
 {
-    k_sweep_end<<<1, 256, 0, s>>>(ctl, G, gdone, gsweeps, gmoves, max_sweeps, theta);
+    k_sweep_end<<<1, 256, 0, s>>>(ctl, G, gdone, gsweeps, gmoves, max_sweeps, theta, consecutive);
     return hipGetLastError();
 }
 
@@ -903,25 +963,25 @@ hipError_t launch_gather_rows(const int32_t* verts, int32_t m, const int32_t* of
     return hipGetLastError();
 }
 
-hipError_t launch_move_class(int cls, bool singleton, const MoveArgs& a, hipStream_t s)
+hipError_t launch_move_class(int cls, bool singleton, bool async, const MoveArgs& a, hipStream_t s)
 {
     switch (cls) {
-    case CLS_L4: return launch_move_t<CLS_L4, 256, 4, 8, true>(singleton, a, s);
-    case CLS_L8: return launch_move_t<CLS_L8, 256, 8, 16, true>(singleton, a, s);
-    case CLS_L32: return launch_move_t<CLS_L32, 256, 16, 64, true>(singleton, a, s);
+    case CLS_L4: return launch_move_t<CLS_L4, 256, 4, 8, true>(singleton, async, a, s);
+    case CLS_L8: return launch_move_t<CLS_L8, 256, 8, 16, true>(singleton, async, a, s);
+    case CLS_L32: return launch_move_t<CLS_L32, 256, 16, 64, true>(singleton, async, a, s);
     // 1664-1696 slots of 12 bytes per 256-thread workgroup (<= 20 KiB), 3392 per
     // 512-thread workgroup (<= 40 KiB): eight wavefronts a SIMD.  Rows of
     // 2049-3072 entries keep 4096 slots (six wavefronts a SIMD): at their load
     // a 3392-slot table probes longer than the extra workgroup gains.
-    case CLS_L128: return launch_move_t<CLS_L128, 256, 32, 208, true>(singleton, a, s);
-    case CLS_L256: return launch_move_t<CLS_L256, 256, 64, 424, true>(singleton, a, s);
-    case CLS_L512: return launch_move_t<CLS_L512, 256, 128, 848, true>(singleton, a, s);
-    case CLS_L1K: return launch_move_t<CLS_L1K, 256, 256, 1696, true>(singleton, a, s);
-    case CLS_L2K: return launch_move_t<CLS_L2K, 512, 512, 3392, true>(singleton, a, s);
-    case CLS_L3K: return launch_move_t<CLS_L3K, 512, 512, 4096, true>(singleton, a, s);
+    case CLS_L128: return launch_move_t<CLS_L128, 256, 32, 208, true>(singleton, async, a, s);
+    case CLS_L256: return launch_move_t<CLS_L256, 256, 64, 424, true>(singleton, async, a, s);
+    case CLS_L512: return launch_move_t<CLS_L512, 256, 128, 848, true>(singleton, async, a, s);
+    case CLS_L1K: return launch_move_t<CLS_L1K, 256, 256, 1696, true>(singleton, async, a, s);
+    case CLS_L2K: return launch_move_t<CLS_L2K, 512, 512, 3392, true>(singleton, async, a, s);
+    case CLS_L3K: return launch_move_t<CLS_L3K, 512, 512, 4096, true>(singleton, async, a, s);
     // 10112 8-byte slots (79 KiB): two workgroups fit a CU's 160 KiB, and every row of the class
     // (at most 8192 entries) leaves free slots
-    case CLS_L8K: return launch_move_t<CLS_L8K, 1024, 1024, 10112, false>(singleton, a, s);
+    case CLS_L8K: return launch_move_t<CLS_L8K, 1024, 1024, 10112, false>(singleton, async, a, s);
     default: return hipErrorInvalidValue;
     }
 }

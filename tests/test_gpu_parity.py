@@ -210,3 +210,30 @@ def test_bad_inputs_rejected():
     assert ei.value.status == 2
     with pytest.raises(lvp.LvError):
         lvp.Graph(2, np.array([1, 1, 2], np.int32), np.array([1, 0], np.int32))
+
+
+def rejected_first_level_graph():
+    """Heavy loops make every move lose (e.g. 80 * 1 - 11 * 62 < 0), so level 0
+    is rejected and the singletons stay; vertex 1 has the longest row, so the
+    degree-ordered storage puts it first (positions differ from ids)."""
+    g = bf.to_csr(3, [(0, 1, 1), (1, 2, 1), (0, 0, 5), (1, 1, 30), (2, 2, 3)])
+    g.name = "rejected-first-level"
+    return g
+
+
+def test_first_level_rejected_keeps_singletons():
+    g = rejected_first_level_graph()
+    got, want = compare_louvain(g)
+    assert not want.levels[0].accepted and list(want.final_labels) == [0, 1, 2]
+    assert list(got.final_labels) == [0, 1, 2]
+    graphs = [graphgen.rmat(8, seed=1), g, graphgen.sbm(300, 30, 0.2, 0.01, seed=2)]
+    with lvp.Graph.batch(graphs) as bg:
+        rs = lvp.louvain(bg)
+    for gg, r in zip(graphs, rs):
+        assert np.array_equal(r.final_labels, oracle.louvain(gg).final_labels), gg.name
+    with lvp.Server() as srv:
+        tickets = [srv.submit(gg) for gg in graphs]
+        for gg, t in zip(graphs, tickets):
+            assert srv.wait(t, 60000)
+            labels, info = srv.result(t, gg.n)
+            assert np.array_equal(labels, oracle.louvain(gg).final_labels), gg.name
