@@ -119,6 +119,38 @@ def prune_leg(args, lvp, dg, runs, phases, K, torch):
     return out
 
 
+def async_leg(args, lvp, dg, runs, phases, K, torch):
+    """The same job with asynchronous sweeps (LV_ASYNC, Alg. 1 and 2 as
+    written: labels and volumes updated in place during a sweep).  Results
+    depend on scheduling; Q is reported beside the synchronous sweeps' Q and
+    the reported Q_int is checked against the modularity of the labels."""
+    reps = []
+    for _ in range(args.async_reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = lvp.louvain(dg, level_labels=False, asynchronous=True)
+        lp = lvp.lpa(dg, asynchronous=True)
+        torch.cuda.synchronize()
+        reps.append((time.perf_counter() - t0, r, lp))
+    for _, r, _ in reps:
+        qi, m, _ = lvp.modularity(dg, r.final_labels)
+        if (qi, m) != (r.q_int, r.M):
+            print("asynchronous run: reported modularity differs from its labels'", file=sys.stderr, flush=True)
+            sys.exit(1)
+    lm = sum(lv.info["sweep_ms"] for _, r, _ in reps for lv in r.levels) / len(reps)
+    edges = sum(lv.info["nnz"] * lv.info["sweeps"] for lv in reps[0][1].levels)
+    lpa_ms = sum(lp.info["sweep_ms"] for _, _, lp in reps) / len(reps)
+    r0, lp0 = reps[0][1], reps[0][2]
+    out = {"local_move_ms": round(lm, 3), "gteps": round(edges / (lm * 1e-3) / 1e9, 3) if lm > 0 else None,
+           "ms_per_step": round(sum(t for t, _, _ in reps) / len(reps) * 1e3, 3),
+           "levels": len(r0.accepted), "sweeps_per_level": [lv.info["sweeps"] for lv in r0.levels],
+           "q": [r.q for _, r, _ in reps], "q_full_sweeps": runs[0][0].q,
+           "lpa_ms": round(lpa_ms, 3), "lpa_sweeps": lp0.info["sweeps"],
+           "lpa_q": lp0.info["q_end"] / float(dg.volume) ** 2}
+    log(f"asynchronous: {out}")
+    return out
+
+
 def edges_leg(args, lvp, graphgen, g, np, torch):
     """The step before the path: the benchmark graph built on the device from
     its raw R-MAT samples (loops dropped, repeated pairs merged to weight 1),
@@ -374,6 +406,8 @@ def main():
     ap.add_argument("--serve-capacity-jobs", type=int, default=200, help="jobs of the saturated capacity runs")
     ap.add_argument("--prune-reps", type=int, default=2,
                     help="timed steps with active-vertex pruning (LV_PRUNE) after the main steps (0: skip)")
+    ap.add_argument("--async-reps", type=int, default=2,
+                    help="timed steps with asynchronous sweeps (LV_ASYNC) after the main steps (0: skip)")
     ap.add_argument("--no-edges-leg", action="store_true",
                     help="skip building the graph from its raw R-MAT samples on the device")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -481,6 +515,7 @@ def main():
     assert (qi, m) == (r0.q_int, r0.M), "reported modularity differs from the labels' modularity"
 
     pruned = prune_leg(args, lvp, dg, runs, phases, K, torch) if args.prune_reps > 0 else None
+    asynchronous = async_leg(args, lvp, dg, runs, phases, K, torch) if args.async_reps > 0 else None
     edges = None if args.no_edges_leg else edges_leg(args, lvp, graphgen, g, np, torch)
 
     parity = None
@@ -560,6 +595,7 @@ def main():
         "phase_ms_per_step": {k_: round(v / K, 3) for k_, v in phases.items()},
         "kernels": kernels,
         "pruned": pruned,
+        "asynchronous": asynchronous,
         "edges_to_csr": edges,
         "batch": batch,
         "serving": serving,
