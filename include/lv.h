@@ -116,6 +116,8 @@ typedef struct lv_tuning {
                         /* the entries per community within chunks and appends them to    */
                         /* per-partition buckets that the partition workgroups read       */
     int32_t hub_chunk;  /* mode 2: entries per scatter workgroup, 1024, 2048 or 4096      */
+    int32_t order_min;  /* coarse levels with at least this many entries are stored by    */
+                        /* descending degree, like level 0 (0 = 2^22)                      */
 } lv_tuning;
 
 typedef struct lv_params {

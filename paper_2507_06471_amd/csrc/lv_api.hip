@@ -106,6 +106,7 @@ struct Workspace {
     DevBuf rows;  // per-level row descriptors of the class-sorted vertices
     DevBuf mark;  // active-vertex pruning: last sweep that changed the vertex's neighbourhood
     DevBuf tiles; // aggregation: per key tile its count, first entry and output position
+    DevBuf p_off, p_idx, p_w, p_k, p_orig, p_inv;  // a coarse level stored by degree
     DevBuf k64;
     // per-graph state of a level (G entries) and sweep control
     DevBuf ctl, gdone, gsweeps, gmoves, gactive, gsum, gsq, gmeta, segs;
@@ -230,6 +231,7 @@ struct Tune {
     int32_t bucketed;   // partition mode (see lv_tuning.hub_mode)
     int32_t fb_chunk;   // entries / slots per workgroup on the global-table fallback
     int32_t sc_chunk;   // entries per scatter workgroup (bucketed mode)
+    int64_t order_min;  // coarse levels with at least this many entries are stored by degree
 };
 
 Tune make_tune(const lv_tuning* t)
@@ -240,6 +242,7 @@ Tune make_tune(const lv_tuning* t)
     u.part_keys = 768;
     u.part_slots = 2048;
     u.bucketed = 1;
+    u.order_min = (int64_t)1 << 22;
     u.fb_chunk = 4096;
     u.sc_chunk = 1024;
     if (t) {
@@ -263,6 +266,7 @@ Tune make_tune(const lv_tuning* t)
             u.part_slots = (int32_t)std::min<uint64_t>(max_slots, std::max<uint64_t>(64, next_pow2((uint64_t)t->part_slots)));
         if (t->part_keys > 0) u.part_keys = std::max(32, t->part_keys);
         if (t->hub_chunk > 0) u.sc_chunk = t->hub_chunk <= 1024 ? 1024 : t->hub_chunk <= 2048 ? 2048 : 4096;
+        if (t->order_min > 0) u.order_min = t->order_min;
     }
     // a single partition must always fit: part_keys <= 3/4 of the slots
     u.part_keys = std::min(u.part_keys, u.part_slots / 4 * 3);
@@ -1079,6 +1083,53 @@ void fill_info(lv_level_info& li, const SweepOut& so, int32_t c, int32_t S)
 }
 
 // Multi-level Louvain (Algorithm 3) for every graph of the handle.
+// Storage by descending number of entries within each packed graph (the
+// graph id is the major key, so every graph keeps its vertex range): orig[p]
+// = the vertex stored at position p, inv its inverse; the rows, weights (w
+// may be null) and degrees permuted into off2 / idx2 / w2 / k2, column
+// indices mapped to positions.  Sorts in ws.keys* / ws.vals*.
+lv_status degree_order(lv_graph* g, int32_t n, int64_t nnz, const int32_t* off, const int32_t* idx, const int32_t* w,
+                       const int32_t* k, const int32_t* gid, int32_t G, DevBuf& orig, DevBuf& inv, DevBuf& off2,
+                       DevBuf& idx2, DevBuf& w2, DevBuf& k2)
+{
+    Workspace& ws = g->ws;
+    hipStream_t s = g->stream;
+    HIP_TRY(ws.small.ensure(4096));
+    int32_t* d_max = (int32_t*)(ws.small.as<char>() + 3584);
+    HIP_TRY(hipMemsetAsync(d_max, 0, sizeof(int32_t), s));
+    HIP_TRY(launch_max_degree(n, off, d_max, s));
+    int32_t maxdeg = 0;
+    HIP_TRY(hipMemcpyAsync(&maxdeg, d_max, sizeof maxdeg, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const int db = bits_for((int64_t)maxdeg + 1);
+    const int bits = db + (G > 1 ? bits_for(G) : 0);
+    const size_t nb = sizeof(int32_t) * (size_t)n;
+    HIP_TRY(ws.keys.ensure(2 * nb));
+    HIP_TRY(ws.keys_alt.ensure(2 * nb));
+    HIP_TRY(ws.vals.ensure(nb));
+    HIP_TRY(ws.vals_alt.ensure(nb));
+    HIP_TRY(ws.tmp.ensure(std::max(radix_tmp_bytes(n), scan_tmp_bytes((int64_t)n + 1, 8))));
+    HIP_TRY(launch_degree_keys(n, off, gid, maxdeg, db, ws.keys.as<uint64_t>(), ws.vals.as<int32_t>(), s));
+    bool in_alt = false;
+    HIP_TRY(radix_sort_u64(ws.keys.as<uint64_t>(), ws.vals.as<int32_t>(), ws.keys_alt.as<uint64_t>(),
+                           ws.vals_alt.as<int32_t>(), n, bits, ws.tmp.p, ws.tmp.cap, &in_alt, s));
+    HIP_TRY(orig.ensure(nb));
+    HIP_TRY(inv.ensure(nb));
+    HIP_TRY(launch_copy_i32(orig.as<int32_t>(), in_alt ? ws.vals_alt.as<int32_t>() : ws.vals.as<int32_t>(), n, s));
+    HIP_TRY(launch_inverse(orig.as<int32_t>(), n, inv.as<int32_t>(), s));
+    HIP_TRY(off2.ensure(sizeof(int32_t) * ((size_t)n + 1)));
+    HIP_TRY(idx2.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(nnz, 1)));
+    if (w) HIP_TRY(w2.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(nnz, 1)));
+    HIP_TRY(k2.ensure(nb));
+    HIP_TRY(launch_perm_lengths(orig.as<int32_t>(), n, off, off2.as<int32_t>(), s));
+    HIP_TRY(scan_exclusive_i32(off2.as<int32_t>(), off2.as<int32_t>(), n, off2.as<int32_t>() + n, ws.tmp.p, ws.tmp.cap, s));
+    HIP_TRY(launch_perm_rows(n, off2.as<int32_t>(), nnz, orig.as<int32_t>(), off, idx, w, inv.as<int32_t>(),
+                             idx2.as<int32_t>(), w ? w2.as<int32_t>() : nullptr, s));
+    HIP_TRY(launch_gather_i32(k, orig.as<int32_t>(), n, k2.as<int32_t>(), s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return LV_OK;
+}
+
 lv_status louvain_impl(lv_graph* g, const Params& p, bool keep_graphs, lv_result* r)
 {
     hipStream_t s = g->stream;
@@ -1237,6 +1288,16 @@ lv_status louvain_impl(lv_graph* g, const Params& p, bool keep_graphs, lv_result
             for (int32_t c : keep) eoff_next.push_back(eoff_next.back() + (eoff2[c + 1] - eoff2[c]));
         }
         LV_TRY(upload_M(g, Mbuf, next));
+        if (next.nnz >= p.tune.order_min && next.n >= 2) {
+            // store a large coarse level by degree too (ids stay the coarse ids)
+            LV_TRY(degree_order(g, next.n, next.nnz, next.off, next.idx, next.w, next.k, next.gid, next.G, ws.p_orig,
+                                ws.p_inv, ws.p_off, ws.p_idx, ws.p_w, ws.p_k));
+            next.off = ws.p_off.as<int32_t>();
+            next.idx = ws.p_idx.as<int32_t>();
+            next.w = next.w ? ws.p_w.as<int32_t>() : nullptr;
+            next.k = ws.p_k.as<int32_t>();
+            next.orig = ws.p_orig.as<int32_t>();
+        }
         G = std::move(next);
         eoff = std::move(eoff_next);
         orig = std::move(orig2);
@@ -1340,51 +1401,17 @@ const char* lv_last_error(void) { return g_last_error.c_str(); }
 // lines.  Ids, and so every decision and label, stay those of the input.
 static lv_status reorder_by_degree(lv_graph* g)
 {
-    const int32_t n = g->n;
-    const int64_t nnz = g->nnz;
-    if (n < 2 || nnz == 0) return LV_OK;
-    Workspace& ws = g->ws;
-    hipStream_t s = g->stream;
-    const int32_t* gid = g->G > 1 ? g->d_gid.as<int32_t>() : nullptr;
-    int32_t* d_max = (int32_t*)(ws.small.as<char>() + 3584);
-    HIP_TRY(hipMemsetAsync(d_max, 0, sizeof(int32_t), s));
-    HIP_TRY(launch_max_degree(n, g->off.as<int32_t>(), d_max, s));
-    int32_t maxdeg = 0;
-    HIP_TRY(hipMemcpyAsync(&maxdeg, d_max, sizeof maxdeg, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    const int db = bits_for((int64_t)maxdeg + 1);
-    const int bits = db + (g->G > 1 ? bits_for(g->G) : 0);
-    const size_t nb = sizeof(int32_t) * (size_t)n;
-    HIP_TRY(ws.keys.ensure(2 * nb));
-    HIP_TRY(ws.keys_alt.ensure(2 * nb));
-    HIP_TRY(ws.vals.ensure(nb));
-    HIP_TRY(ws.vals_alt.ensure(nb));
-    HIP_TRY(ws.tmp.ensure(std::max(radix_tmp_bytes(n), scan_tmp_bytes((int64_t)n + 1, 8))));
-    HIP_TRY(launch_degree_keys(n, g->off.as<int32_t>(), gid, maxdeg, db, ws.keys.as<uint64_t>(), ws.vals.as<int32_t>(), s));
-    bool in_alt = false;
-    HIP_TRY(radix_sort_u64(ws.keys.as<uint64_t>(), ws.vals.as<int32_t>(), ws.keys_alt.as<uint64_t>(),
-                           ws.vals_alt.as<int32_t>(), n, bits, ws.tmp.p, ws.tmp.cap, &in_alt, s));
-    HIP_TRY(g->orig.ensure(nb));
-    HIP_TRY(g->inv.ensure(nb));
-    HIP_TRY(launch_copy_i32(g->orig.as<int32_t>(), in_alt ? ws.vals_alt.as<int32_t>() : ws.vals.as<int32_t>(), n, s));
-    HIP_TRY(launch_inverse(g->orig.as<int32_t>(), n, g->inv.as<int32_t>(), s));
+    if (g->n < 2 || g->nnz == 0) return LV_OK;
     DevBuf off2, idx2, w2, k2;
-    HIP_TRY(off2.ensure(sizeof(int32_t) * ((size_t)n + 1)));
-    HIP_TRY(idx2.ensure(sizeof(int32_t) * (size_t)nnz));
-    if (g->weighted) HIP_TRY(w2.ensure(sizeof(int32_t) * (size_t)nnz));
-    HIP_TRY(k2.ensure(nb));
-    HIP_TRY(launch_perm_lengths(g->orig.as<int32_t>(), n, g->off.as<int32_t>(), off2.as<int32_t>(), s));
-    HIP_TRY(scan_exclusive_i32(off2.as<int32_t>(), off2.as<int32_t>(), n, off2.as<int32_t>() + n, ws.tmp.p, ws.tmp.cap, s));
-    HIP_TRY(launch_perm_rows(n, off2.as<int32_t>(), nnz, g->orig.as<int32_t>(), g->off.as<int32_t>(),
-                             g->idx.as<int32_t>(), g->weighted ? g->w.as<int32_t>() : nullptr, g->inv.as<int32_t>(),
-                             idx2.as<int32_t>(), g->weighted ? w2.as<int32_t>() : nullptr, s));
-    HIP_TRY(launch_gather_i32(g->k.as<int32_t>(), g->orig.as<int32_t>(), n, k2.as<int32_t>(), s));
-    HIP_TRY(hipStreamSynchronize(s));
+    LV_TRY(degree_order(g, g->n, g->nnz, g->off.as<int32_t>(), g->idx.as<int32_t>(),
+                        g->weighted ? g->w.as<int32_t>() : nullptr, g->k.as<int32_t>(),
+                        g->G > 1 ? g->d_gid.as<int32_t>() : nullptr, g->G, g->orig, g->inv, off2, idx2, w2, k2));
     g->off.swap(off2);
     g->idx.swap(idx2);
     if (g->weighted) g->w.swap(w2);
     g->k.swap(k2);
     g->reordered = true;
+    Workspace& ws = g->ws;
     ws.keys.release();
     ws.keys_alt.release();
     ws.vals.release();

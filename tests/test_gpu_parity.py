@@ -237,3 +237,33 @@ def test_first_level_rejected_keeps_singletons():
             assert srv.wait(t, 60000)
             labels, info = srv.result(t, gg.n)
             assert np.array_equal(labels, oracle.louvain(gg).final_labels), gg.name
+
+
+@pytest.mark.parametrize("maker", ["tiny", "sbm", "rmat14", "rmat16", "lfr", "rejected"])
+def test_coarse_levels_stored_by_degree(maker):
+    # order_min = 1 stores every coarse level by degree (the default does so
+    # from 2^22 entries); results must not change
+    if maker == "tiny":
+        rng = np.random.default_rng(31)
+        g = bf.to_csr(50, bf.random_graph(rng, 50, 0.15, 9, True))
+    elif maker == "sbm":
+        g = graphgen.sbm(4096, 128, 0.05, 0.0005, seed=1)
+    elif maker == "lfr":
+        g, _ = graphgen.lfr(20000, kmax=1500, smin=30, smax=3000, seed=7)
+    elif maker == "rejected":
+        g = rejected_first_level_graph()
+    else:
+        g = graphgen.rmat(int(maker[4:]), seed=2)
+    tuning = {"order_min": 1}
+    compare_louvain(g, tuning=tuning, keep_graphs=True)
+    compare_louvain(g, tuning=dict(tuning, block_max=64, hub_mode=2, part_keys=48), prune=True)
+
+
+def test_coarse_levels_stored_by_degree_in_batches():
+    from test_gpu_batch import check_graph, mixed_batch
+
+    graphs = mixed_batch(2, 33)
+    with lvp.Graph.batch(graphs) as bg:
+        got = lvp.louvain(bg, tuning={"order_min": 1})
+    for g, r in zip(graphs, got):
+        check_graph(r, oracle.louvain(g), g.name)
