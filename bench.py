@@ -514,6 +514,13 @@ def main():
     qi, m, q = lvp.modularity(dg, r0.final_labels)
     assert (qi, m) == (r0.q_int, r0.M), "reported modularity differs from the labels' modularity"
 
+    # the pure-gather ceiling of the move kernels on this graph (stored order):
+    # one random 8-byte pair per entry and nothing else
+    ceiling = lvp.probe_gather(dg, reps=5)
+    gather_ceiling = {"entries_per_s": round(ceiling / 1e9, 3), "unit": "G entries/s",
+                      "local_move": round(gteps, 3), "frac": round(gteps * 1e9 / ceiling, 4) if ceiling > 0 else None,
+                      "probe": "lv_probe_gather: stream the stored column indices, gather one 8-byte pair each"}
+    log(f"gather ceiling: {gather_ceiling}")
     pruned = prune_leg(args, lvp, dg, runs, phases, K, torch) if args.prune_reps > 0 else None
     asynchronous = async_leg(args, lvp, dg, runs, phases, K, torch) if args.async_reps > 0 else None
     edges = None if args.no_edges_leg else edges_leg(args, lvp, graphgen, g, np, torch)
@@ -585,6 +592,7 @@ def main():
                      "traffic": measured_traffic(lvp.KERNEL_NAMES[dom]) if args.scale == 24 else None,
                      "kernel": lvp.KERNEL_NAMES[dom], "avg_launch_ms": round(float(avg_launch_ms), 4),
                      "bytes_per_launch": int(bytes_per_launch)},
+        "gather_ceiling": gather_ceiling,
         "cpu_baseline": cpu,
         "parity": parity,
         "louvain": {"levels": len(r0.accepted), "q": r0.q, "q_int": r0.q_int, "M": r0.M,

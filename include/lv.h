@@ -307,6 +307,18 @@ lv_status lv_lpa(lv_graph* g, const lv_params* params, int32_t* labels, lv_memki
 lv_status lv_lpa_batch(lv_graph* g, const lv_params* params, int32_t* labels, lv_memkind kind,
                        int32_t* sweeps, int64_t* q_int, int64_t* m, int64_t* moves, int32_t moves_stride);
 
+/*
+ * Diagnostic: the gather ceiling of the local-moving kernels on this handle.
+ * Streams the handle's stored column indices (all packed graphs, in storage
+ * order) and gathers one 8-byte (label, volume) pair per entry from a
+ * scratch table of n pairs, with no other work, `reps` times (HIP events on
+ * the handle's stream).  *entries_per_s receives entries per second.  A sweep
+ * of the move kernels does this and more, so its entry rate cannot exceed
+ * it; bandwidth figures, which count each entry's bytes once, miss that the
+ * pairs arrive one cache line at a time.  Allocates and frees the table.
+ */
+lv_status lv_probe_gather(lv_graph* g, int32_t reps, double* entries_per_s);
+
 /* Modularity (Section II-C) of any labels int32[n] with values in [0, n). */
 lv_status lv_modularity(lv_graph* g, const int32_t* labels, lv_memkind kind, int64_t* q_int,
                         int64_t* m, double* q);

@@ -149,6 +149,7 @@ SIGNATURES = {
     "lv_graph_create_edges": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, _vp, _vp, _vp, ctypes.c_int,
                                              ctypes.c_uint32, _vp, ctypes.POINTER(_vp)]),
     "lv_graph_csr": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i64p, ctypes.c_int]),
+    "lv_probe_gather": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
 }
 
 _lib = None
@@ -521,6 +522,13 @@ def lpa_batch(graph: Graph, max_sweeps: int = 20, threshold: int = 0, tuning: Op
         out.append(LpaResult(labels[base:base + n].copy(), [int(x) for x in mv[gi, :sw[gi]]], info))
         base += n
     return out
+
+
+def probe_gather(graph: Graph, reps: int = 5) -> float:
+    """lv_probe_gather: the handle's pure-gather ceiling in entries per second."""
+    out = ctypes.c_double()
+    _check(load_library().lv_probe_gather(graph.handle, int(reps), ctypes.byref(out)), "lv_probe_gather")
+    return out.value
 
 
 def autotune(graph: Graph, max_sweeps: int = 20):

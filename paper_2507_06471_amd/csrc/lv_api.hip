@@ -2036,6 +2036,28 @@ static lv_status modularity_impl(lv_graph* g, const int32_t* labels_dev, int64_t
     return LV_OK;
 }
 
+lv_status lv_probe_gather(lv_graph* g, int32_t reps, double* entries_per_s)
+{
+    if (!g || reps < 1 || !entries_per_s) { set_error_msg("lv_probe_gather: null graph/out or reps < 1"); return LV_E_ARG; }
+    hipStream_t s = g->stream;
+    DevBuf tab, sink;
+    HIP_TRY(tab.ensure(sizeof(int2) * (size_t)std::max(g->n, 1)));
+    HIP_TRY(sink.ensure(sizeof(unsigned long long)));
+    HIP_TRY(hipMemsetAsync(tab.p, 0x5a, sizeof(int2) * (size_t)std::max(g->n, 1), s));
+    const int32_t* idx = g->idx.as<int32_t>();
+    HIP_TRY(launch_probe_gather(idx, tab.as<int2>(), g->nnz, sink.as<unsigned long long>(), s));  // warm-up
+    Timer t;
+    t.s = s;
+    hipEvent_t e0{}, e1{};
+    HIP_TRY(t.mark(&e0));
+    for (int32_t r = 0; r < reps; ++r) HIP_TRY(launch_probe_gather(idx, tab.as<int2>(), g->nnz, sink.as<unsigned long long>(), s));
+    HIP_TRY(t.mark(&e1));
+    HIP_TRY(hipStreamSynchronize(s));
+    const double ms = elapsed(e0, e1) / reps;
+    *entries_per_s = ms > 0 ? (double)g->nnz / (ms * 1e-3) : 0.0;
+    return LV_OK;
+}
+
 lv_status lv_modularity(lv_graph* g, const int32_t* labels, lv_memkind kind, int64_t* q_int, int64_t* m, double* q)
 {
     if (!g || !labels || (kind != LV_MEM_HOST && kind != LV_MEM_DEVICE)) return LV_E_ARG;

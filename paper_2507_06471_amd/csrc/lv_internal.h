@@ -221,6 +221,8 @@ hipError_t launch_hub_sweep(bool singleton, const MoveArgs& a, const HubArgs& h,
 // Active-vertex pruning: after the decisions of a sweep, record the sweep
 // number for every mover and every neighbour of a mover (rows: the m listed
 // vertices below the hub class; the hubs through their mark chunks).
+// Gather probe (see lv_probe_gather): stream idx[0, nnz) and gather tab[idx[e]].
+hipError_t launch_probe_gather(const int32_t* idx, const int2* tab, int64_t nnz, unsigned long long* sink, hipStream_t s);
 hipError_t launch_mark_movers(const int4* rows, const int32_t* dec, int32_t m, const int32_t* idx, int32_t* mark,
                               const SweepCtl* ctl, hipStream_t s);
 hipError_t launch_hub_mark(const MoveArgs& a, const HubArgs& h, int32_t* mark, hipStream_t s);

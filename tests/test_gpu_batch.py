@@ -151,3 +151,14 @@ def test_batch_final_partition_accessors():
         assert np.array_equal(fp.labels[base:base + g.n], want.final_labels), g.name
         assert (fp.q_int[t], fp.M[t], fp.q[t]) == (want.q_int, want.M, want.q), g.name
         base += g.n
+
+
+def test_gather_probe_reports_a_rate():
+    g = graphgen.rmat(14, seed=3)
+    with lvp.Graph.from_csr(g) as dg:
+        rate = lvp.probe_gather(dg, reps=2)
+    say(f"gather ceiling on R-MAT 14: {rate / 1e9:.1f} G entries/s")
+    assert np.isfinite(rate) and rate > 0
+    with pytest.raises(lvp.LvError):
+        with lvp.Graph.from_csr(g) as dg:
+            lvp.probe_gather(dg, reps=0)
