@@ -576,7 +576,8 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
         HIP_TRY(launch_iota(ws.comm.as<int32_t>(), n, s));
         HIP_TRY(launch_copy_i32(ws.sigma.as<int32_t>(), G.k, n, s));
     }
-    HIP_TRY(launch_pairs(n, ws.comm.as<int32_t>(), ws.sigma.as<int32_t>(), ws.cs.as<int2>(), nullptr, s));
+    const int32_t* act_verts = vert_sorted + start[CLS_L4];  // vertices with entries (the only pairs ever gathered)
+    HIP_TRY(launch_pairs(active, act_verts, ws.comm.as<int32_t>(), ws.sigma.as<int32_t>(), ws.cs.as<int2>(), nullptr, s));
     HIP_TRY(launch_ctl_init(ctl, G.G, gactive, ws.gdone.as<int32_t>(), ws.gsweeps.as<int32_t>(),
                             ws.gmoves.as<uint32_t>(), S, s));
 
@@ -653,9 +654,10 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
             }
         }
         if (!async) {  // asynchronous sweeps have moved already
-            HIP_TRY(launch_apply(vert_sorted + start[CLS_L4], dec_all + start[CLS_L4], active, G.k, a.gid,
-                                 ws.comm.as<int32_t>(), ws.sigma.as<int32_t>(), ctl, ws.gmoves.as<uint32_t>(), S, s));
-            HIP_TRY(launch_pairs(n, ws.comm.as<int32_t>(), ws.sigma.as<int32_t>(), ws.cs.as<int2>(), ctl, s));
+            HIP_TRY(launch_apply(act_verts, dec_all + start[CLS_L4], active, G.k, a.gid, ws.comm.as<int32_t>(),
+                                 ws.sigma.as<int32_t>(), ctl, ws.gmoves.as<uint32_t>(), S, s));
+            HIP_TRY(launch_pairs(active, act_verts, ws.comm.as<int32_t>(), ws.sigma.as<int32_t>(), ws.cs.as<int2>(),
+                                 ctl, s));
         }
         // synchronous sweeps alternate direction, so a level ends after two
         // quiet sweeps; an asynchronous level ends after one (Alg. 2's test)

@@ -226,8 +226,8 @@ hipError_t launch_probe_gather(const int32_t* idx, const int2* tab, int64_t nnz,
 hipError_t launch_mark_movers(const int4* rows, const int32_t* dec, int32_t m, const int32_t* idx, int32_t* mark,
                               const SweepCtl* ctl, hipStream_t s);
 hipError_t launch_hub_mark(const MoveArgs& a, const HubArgs& h, int32_t* mark, hipStream_t s);
-hipError_t launch_pairs(int32_t n, const int32_t* comm, const int32_t* sigma, int2* cs, const SweepCtl* ctl,
-                        hipStream_t s);
+hipError_t launch_pairs(int32_t n, const int32_t* verts, const int32_t* comm, const int32_t* sigma, int2* cs,
+                        const SweepCtl* ctl, hipStream_t s);
 // commit the decisions dec[0..m) of vertices verts[0..m); per-graph movers into gmoves
 hipError_t launch_apply(const int32_t* verts, const int32_t* dec, int32_t m, const int32_t* k, const int32_t* gid,
                         int32_t* comm, int32_t* sigma, const SweepCtl* ctl, uint32_t* gmoves, int32_t max_sweeps,

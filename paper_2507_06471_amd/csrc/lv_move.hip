@@ -798,15 +798,54 @@ __global__ __launch_bounds__(256) void k_hub_mark(MoveArgs a, HubArgs h, int32_t
 }
 
 // ------------------------------------------------------------------ commit (K7)
-// Apply the decisions of the m listed vertices: labels, and community volumes
-// with one atomic per distinct community per wavefront (integer sums, so the
-// order is irrelevant).  The movers of graph g in this sweep are counted in
-// gmoves[g * max_sweeps + sweep].
+// Apply the decisions of the m listed vertices: labels and community
+// volumes (LPA's modularity reads the volumes too).  A wavefront sums its
+// volume changes per community (integer sums, so order is irrelevant) and
+// adds them into the workgroup's LDS table; the table is added into the
+// volumes once at the end, so a community that many movers leave or join
+// costs one global atomic per workgroup.  A change that finds no table slot
+// within APPLY_PROBE probes is added globally at once.  The movers of graph g
+// in this sweep are counted in gmoves[g * max_sweeps + sweep].
+constexpr int APPLY_SLOTS = 4096;
+constexpr int APPLY_PROBE = 32;
+
+__device__ __forceinline__ void apply_add(int32_t* key, int32_t* val, int32_t* sigma, int32_t C, int32_t d)
+{
+    uint32_t h = mix32(C) & (uint32_t)(APPLY_SLOTS - 1);
+    for (int p = 0; p < APPLY_PROBE; ++p) {
+        const int32_t prev = atomicCAS(&key[h], EMPTY_KEY, C);
+        if (prev == EMPTY_KEY || prev == C) { atomicAdd(&val[h], d); return; }
+        h = (h + 1) & (uint32_t)(APPLY_SLOTS - 1);
+    }
+    atomicAdd(&sigma[C], d);
+}
+
+// As wave_grouped_add, into the LDS table.
+__device__ __forceinline__ void wave_grouped_apply(int32_t* key, int32_t* val, int32_t* sigma, int32_t C, int32_t d,
+                                                   bool valid)
+{
+    uint64_t pending = __ballot(valid);
+    while (pending) {
+        const int leader = __ffsll((unsigned long long)pending) - 1;
+        const int32_t lc = __shfl(C, leader);
+        const uint64_t grp = __ballot(valid && C == lc) & pending;
+        int32_t c = ((grp >> lane_id()) & 1ull) ? d : 0;
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) c += __shfl_xor(c, m);
+        if ((int)lane_id() == leader && c) apply_add(key, val, sigma, lc, c);
+        pending &= ~grp;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_apply(const int32_t* verts, const int32_t* dec, int32_t m, const int32_t* k,
                                                const int32_t* gid, int32_t* comm, int32_t* sigma, const SweepCtl* ctl,
                                                uint32_t* gmoves, int32_t max_sweeps)
 {
+    __shared__ int32_t t_key[APPLY_SLOTS];
+    __shared__ int32_t t_val[APPLY_SLOTS];
     if (ctl->all_done) return;
+    for (int t = threadIdx.x; t < APPLY_SLOTS; t += 256) { t_key[t] = EMPTY_KEY; t_val[t] = 0; }
+    __syncthreads();
     uint32_t* moves = gmoves + ctl->sweep;
     int64_t my_g = -1;  // this thread's running mover count, for graph my_g
     uint32_t my_n = 0;
@@ -829,10 +868,13 @@ __global__ __launch_bounds__(256) void k_apply(const int32_t* verts, const int32
             comm[v] = C;
         }
         if (__ballot(valid)) {
-            wave_grouped_add<int32_t, int32_t>(sigma, C, kv, valid);
-            wave_grouped_add<int32_t, int32_t>(sigma, A, -kv, valid);
+            wave_grouped_apply(t_key, t_val, sigma, C, kv, valid);
+            wave_grouped_apply(t_key, t_val, sigma, A, -kv, valid);
         }
     }
+    __syncthreads();
+    for (int t = threadIdx.x; t < APPLY_SLOTS; t += 256)
+        if (t_key[t] != EMPTY_KEY && t_val[t] != 0) atomicAdd(&sigma[t_key[t]], t_val[t]);
     block_flush_sums<256, uint32_t>(moves, my_n ? my_g : -1, my_n);
 }
 
@@ -874,11 +916,15 @@ __global__ void k_ctl_init(SweepCtl* ctl, int32_t G, const int32_t* gactive, int
     if (t0 == 0) { ctl->sweep = 0; ctl->all_done = 0; }
 }
 
-// cs[v] = (comm[v], Sigma_tot(comm[v])): the pair a move kernel gathers per CSR entry
-__global__ void k_pairs(int32_t n, const int32_t* comm, const int32_t* sigma, int2* cs, const SweepCtl* ctl)
+// cs[v] = (comm[v], Sigma_tot(comm[v])): the pair a move kernel gathers per
+// CSR entry, for the listed vertices (verts null: v < n).  Only vertices with
+// entries need it: nobody gathers an isolated vertex's pair.
+__global__ void k_pairs(int32_t n, const int32_t* verts, const int32_t* comm, const int32_t* sigma, int2* cs,
+                        const SweepCtl* ctl)
 {
     if (ctl && ctl->all_done) return;
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t v = verts ? verts[t] : (int32_t)t;
         const int32_t c = comm[v];
         cs[v] = make_int2(c, sigma[c]);
     }
@@ -901,11 +947,11 @@ hipError_t launch_hub_mark(const MoveArgs& a, const HubArgs& h, int32_t* mark, h
     return hipGetLastError();
 }
 
-hipError_t launch_pairs(int32_t n, const int32_t* comm, const int32_t* sigma, int2* cs, const SweepCtl* ctl,
-                        hipStream_t s)
+hipError_t launch_pairs(int32_t n, const int32_t* verts, const int32_t* comm, const int32_t* sigma, int2* cs,
+                        const SweepCtl* ctl, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    k_pairs<<<LV_GRID(n)>>>(n, comm, sigma, cs, ctl);
+    k_pairs<<<LV_GRID(n)>>>(n, verts, comm, sigma, cs, ctl);
     return hipGetLastError();
 }
 hipError_t launch_ctl_init(SweepCtl* ctl, int32_t G, const int32_t* gactive, int32_t* gdone, int32_t* gsweeps,
