@@ -55,9 +55,10 @@ __global__ void k_coarse_degree(int32_t n, const int32_t* comm, const int32_t* l
 // label(j) with weight w.
 //   SUM = false: every entry's key and weight go to keys[e], vals[e].
 //   SUM = true (levels that merged strongly): the keys are added into the
-// tile's LDS hash table.  An entry that finds no slot within
-// AG_PROBE probes is written out as it is (the global sort merges equal keys
-// anyway), from the end of the tile's range.  Out: the table's distinct keys
+// tile's LDS hash table.  An entry that finds no slot within AG_PROBE
+// probes, or arrives once the table holds AG_FILL keys (a tile whose keys
+// barely repeat stops summing early), is written out as it is (the global
+// sort merges equal keys anyway), from the end of the tile's range.  Out: the table's distinct keys
 // at keys[y0 + r], r < cnt[b], and the unplaced entries at
 // keys[y0 + ne - ovf[b] + r], r < ovf[b].  meta holds four arrays of one
 // int per tile: keys contributed (cnt + ovf), y0, cnt, ne.
@@ -65,7 +66,8 @@ __global__ void k_coarse_degree(int32_t n, const int32_t* comm, const int32_t* l
 constexpr int AG_IT = 16;
 constexpr int AG_T = TILE_BS * AG_IT;  // merge-path items per tile
 constexpr int AG_HS = 2048;            // hash slots (24 KiB)
-constexpr int AG_PROBE = 64;
+constexpr int AG_PROBE = 16;
+constexpr int AG_FILL = AG_HS * 3 / 4;
 constexpr uint64_t AG_EMPTY = ~0ull;   // keys use at most 62 bits
 
 __device__ __forceinline__ uint32_t key_slot(uint64_t k)
@@ -73,12 +75,14 @@ __device__ __forceinline__ uint32_t key_slot(uint64_t k)
     return (uint32_t)((k * 0x9E3779B97F4A7C15ull) >> 40) & (uint32_t)(AG_HS - 1);
 }
 
-__device__ __forceinline__ bool hash_add(uint64_t* h_key, int32_t* h_val, uint64_t key, int32_t wv)
+// Adds (key, wv) to the table; *fill counts the keys placed so far.
+__device__ __forceinline__ bool hash_add(uint64_t* h_key, int32_t* h_val, int32_t* fill, uint64_t key, int32_t wv)
 {
     uint32_t h = key_slot(key);
     for (int p = 0; p < AG_PROBE; ++p) {
         const uint64_t prev =
             atomicCAS((unsigned long long*)&h_key[h], (unsigned long long)AG_EMPTY, (unsigned long long)key);
+        if (prev == AG_EMPTY) atomicAdd(fill, 1);
         if (prev == AG_EMPTY || prev == key) { atomicAdd(&h_val[h], wv); return true; }
         h = (h + 1) & (uint32_t)(AG_HS - 1);
     }
@@ -94,12 +98,12 @@ __global__ __launch_bounds__(TILE_BS) void k_tile_keys(int32_t n, const int32_t*
     __shared__ uint64_t h_key[SUM ? AG_HS : 1];
     __shared__ int32_t h_val[SUM ? AG_HS : 1];
     __shared__ int64_t s_x[2];
-    __shared__ int32_t s_cnt, s_ovf;
+    __shared__ int32_t s_cnt, s_ovf, s_fill;
     const int64_t total = (int64_t)n + nnz;
     const int64_t d0 = (int64_t)blockIdx.x * AG_T;
     const int64_t d1 = d0 + AG_T < total ? d0 + AG_T : total;
     if (threadIdx.x < 2) s_x[threadIdx.x] = mp_rows(off, n, threadIdx.x ? d1 : d0);
-    if (threadIdx.x == 0) { s_cnt = 0; s_ovf = 0; }
+    if (threadIdx.x == 0) { s_cnt = 0; s_ovf = 0; s_fill = 0; }
     if constexpr (SUM)
         for (int t = threadIdx.x; t < AG_HS; t += TILE_BS) { h_key[t] = AG_EMPTY; h_val[t] = 0; }
     __syncthreads();
@@ -139,7 +143,8 @@ __global__ __launch_bounds__(TILE_BS) void k_tile_keys(int32_t n, const int32_t*
             const uint32_t b = (uint32_t)jj[u];
             const uint64_t key = ((uint64_t)a << colbits) | (uint64_t)b;
             if constexpr (SUM) {
-                if (!hash_add(h_key, h_val, key, ww[u])) {
+                const bool full = *(volatile int32_t*)&s_fill >= AG_FILL;
+                if (full || !hash_add(h_key, h_val, &s_fill, key, ww[u])) {
                     const int32_t p = ne - 1 - atomicAdd(&s_ovf, 1);
                     keys[y0 + p] = key;
                     vals[y0 + p] = ww[u];

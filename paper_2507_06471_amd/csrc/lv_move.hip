@@ -804,25 +804,32 @@ __global__ __launch_bounds__(256) void k_hub_mark(MoveArgs a, HubArgs h, int32_t
 // adds them into the workgroup's LDS table; the table is added into the
 // volumes once at the end, so a community that many movers leave or join
 // costs one global atomic per workgroup.  A change that finds no table slot
-// within APPLY_PROBE probes is added globally at once.  The movers of graph g
-// in this sweep are counted in gmoves[g * max_sweeps + sweep].
+// within APPLY_PROBE probes, or arrives once the table holds APPLY_FILL
+// communities (a workgroup whose movers touch many communities gains
+// nothing from it), is added globally at once.  The movers of graph g in this
+// sweep are counted in gmoves[g * max_sweeps + sweep].
 constexpr int APPLY_SLOTS = 4096;
-constexpr int APPLY_PROBE = 32;
+constexpr int APPLY_PROBE = 16;
+constexpr int APPLY_FILL = APPLY_SLOTS * 3 / 4;
 
-__device__ __forceinline__ void apply_add(int32_t* key, int32_t* val, int32_t* sigma, int32_t C, int32_t d)
+__device__ __forceinline__ void apply_add(int32_t* key, int32_t* val, int32_t* fill, int32_t* sigma, int32_t C,
+                                          int32_t d)
 {
-    uint32_t h = mix32(C) & (uint32_t)(APPLY_SLOTS - 1);
-    for (int p = 0; p < APPLY_PROBE; ++p) {
-        const int32_t prev = atomicCAS(&key[h], EMPTY_KEY, C);
-        if (prev == EMPTY_KEY || prev == C) { atomicAdd(&val[h], d); return; }
-        h = (h + 1) & (uint32_t)(APPLY_SLOTS - 1);
+    if (*(volatile int32_t*)fill < APPLY_FILL) {
+        uint32_t h = mix32(C) & (uint32_t)(APPLY_SLOTS - 1);
+        for (int p = 0; p < APPLY_PROBE; ++p) {
+            const int32_t prev = atomicCAS(&key[h], EMPTY_KEY, C);
+            if (prev == EMPTY_KEY) atomicAdd(fill, 1);
+            if (prev == EMPTY_KEY || prev == C) { atomicAdd(&val[h], d); return; }
+            h = (h + 1) & (uint32_t)(APPLY_SLOTS - 1);
+        }
     }
     atomicAdd(&sigma[C], d);
 }
 
 // As wave_grouped_add, into the LDS table.
-__device__ __forceinline__ void wave_grouped_apply(int32_t* key, int32_t* val, int32_t* sigma, int32_t C, int32_t d,
-                                                   bool valid)
+__device__ __forceinline__ void wave_grouped_apply(int32_t* key, int32_t* val, int32_t* fill, int32_t* sigma,
+                                                   int32_t C, int32_t d, bool valid)
 {
     uint64_t pending = __ballot(valid);
     while (pending) {
@@ -832,7 +839,7 @@ __device__ __forceinline__ void wave_grouped_apply(int32_t* key, int32_t* val, i
         int32_t c = ((grp >> lane_id()) & 1ull) ? d : 0;
 #pragma unroll
         for (int m = 32; m >= 1; m >>= 1) c += __shfl_xor(c, m);
-        if ((int)lane_id() == leader && c) apply_add(key, val, sigma, lc, c);
+        if ((int)lane_id() == leader && c) apply_add(key, val, fill, sigma, lc, c);
         pending &= ~grp;
     }
 }
@@ -843,7 +850,9 @@ __global__ __launch_bounds__(256) void k_apply(const int32_t* verts, const int32
 {
     __shared__ int32_t t_key[APPLY_SLOTS];
     __shared__ int32_t t_val[APPLY_SLOTS];
+    __shared__ int32_t t_fill;
     if (ctl->all_done) return;
+    if (threadIdx.x == 0) t_fill = 0;
     for (int t = threadIdx.x; t < APPLY_SLOTS; t += 256) { t_key[t] = EMPTY_KEY; t_val[t] = 0; }
     __syncthreads();
     uint32_t* moves = gmoves + ctl->sweep;
@@ -868,8 +877,8 @@ __global__ __launch_bounds__(256) void k_apply(const int32_t* verts, const int32
             comm[v] = C;
         }
         if (__ballot(valid)) {
-            wave_grouped_apply(t_key, t_val, sigma, C, kv, valid);
-            wave_grouped_apply(t_key, t_val, sigma, A, -kv, valid);
+            wave_grouped_apply(t_key, t_val, &t_fill, sigma, C, kv, valid);
+            wave_grouped_apply(t_key, t_val, &t_fill, sigma, A, -kv, valid);
         }
     }
     __syncthreads();
