@@ -184,6 +184,52 @@ __device__ __forceinline__ void for_tile_entries(const int32_t* off, int32_t n, 
     for_tile_entries_at<BS, IT>((int64_t)blockIdx.x, off, n, nnz, f);
 }
 
+// As for_tile_entries_at, but consecutive threads take consecutive entries
+// (thread t visits y0 + t + j*BS), so loads and stores indexed by the entry
+// coalesce.  The row of each entry is found first, by each thread walking IT
+// consecutive entries, and kept in LDS.  Every thread of the workgroup must
+// call it (it synchronises).
+template <int BS, int IT, typename F>
+__device__ __forceinline__ void for_tile_entries_co_at(int64_t tile, const int32_t* off, int32_t n, int64_t nnz, F&& f)
+{
+    constexpr int T = BS * IT;
+    __shared__ int32_t s_off[T + 2];
+    __shared__ int32_t s_row[T];
+    __shared__ int64_t s_x[2];
+    const int64_t total = (int64_t)n + nnz;
+    const int64_t d0 = tile * T;
+    const int64_t d1 = d0 + T < total ? d0 + T : total;
+    if (threadIdx.x < 2) s_x[threadIdx.x] = mp_rows(off, n, threadIdx.x ? d1 : d0);
+    __syncthreads();
+    const int64_t x0 = s_x[0], x1 = s_x[1];
+    const int64_t y0 = d0 - x0, y1 = d1 - x1;
+    const int64_t last = x1 + 1 < n ? x1 + 1 : n;
+    const int64_t cnt = last - x0 + 1;
+    for (int64_t t = threadIdx.x; t < cnt; t += BS) s_off[t] = off[x0 + t];
+    __syncthreads();
+    const int64_t my0 = y0 + (int64_t)threadIdx.x * IT;
+    if (my0 < y1) {
+        int64_t lo = 0, hi = cnt;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) / 2;
+            if ((int64_t)s_off[mid] <= my0) lo = mid + 1; else hi = mid;
+        }
+        int64_t r = x0 + lo - 1;
+        for (int j = 0; j < IT; ++j) {
+            const int64_t e = my0 + j;
+            if (e >= y1) break;
+            while ((int64_t)s_off[r + 1 - x0] <= e) ++r;
+            s_row[e - y0] = (int32_t)r;
+        }
+    }
+    __syncthreads();
+    for (int j = 0; j < IT; ++j) {
+        const int64_t e = y0 + threadIdx.x + (int64_t)j * BS;
+        if (e >= y1) break;
+        f(s_row[e - y0], e);
+    }
+}
+
 constexpr int TILE_BS = 256;
 constexpr int TILE_IT = 8;
 constexpr int64_t TILE = TILE_BS * TILE_IT;

@@ -173,7 +173,7 @@ __global__ __launch_bounds__(TILE_BS) void k_trace(int32_t n, const int32_t* off
     GraphAcc acc;
     const int64_t tiles = ((int64_t)n + nnz + TILE - 1) / TILE;
     for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x)
-        for_tile_entries_at<TILE_BS, TILE_IT>(t, off, n, nnz, [&](int32_t r, int64_t e) {
+        for_tile_entries_co_at<TILE_BS, TILE_IT>(t, off, n, nnz, [&](int32_t r, int64_t e) {
             if (idx[e] == r) acc.add(out, gid ? gid[r] : 0, (unsigned long long)(w ? w[e] : 1));
         });
     acc.flush_block(out);
@@ -187,7 +187,7 @@ __global__ __launch_bounds__(TILE_BS) void k_sigma_in(int32_t n, const int32_t* 
     GraphAcc acc;
     const int64_t tiles = ((int64_t)n + nnz + TILE - 1) / TILE;
     for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x)
-        for_tile_entries_at<TILE_BS, TILE_IT>(t, off, n, nnz, [&](int32_t r, int64_t e) {
+        for_tile_entries_co_at<TILE_BS, TILE_IT>(t, off, n, nnz, [&](int32_t r, int64_t e) {
             if (labels[idx[e]] == labels[r]) acc.add(out, gid ? gid[r] : 0, (unsigned long long)(w ? w[e] : 1));
         });
     acc.flush_block(out);
@@ -261,7 +261,7 @@ __global__ __launch_bounds__(TILE_BS) void k_perm_rows(int32_t n, const int32_t*
                                                         const int32_t* w, const int32_t* inv, int32_t* idx_new,
                                                         int32_t* w_new)
 {
-    for_tile_entries<TILE_BS, TILE_IT>(off_new, n, nnz, [&](int32_t q, int64_t e) {
+    for_tile_entries_co_at<TILE_BS, TILE_IT>((int64_t)blockIdx.x, off_new, n, nnz, [&](int32_t q, int64_t e) {
         const int64_t src = (int64_t)off[perm[q]] + (e - off_new[q]);
         idx_new[e] = inv[idx[src]];
         if (w) w_new[e] = w[src];
