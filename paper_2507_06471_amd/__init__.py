@@ -411,7 +411,8 @@ def louvain_final(graph: Graph, max_sweeps: int = 20, max_levels: int = 32, tuni
         lib.lv_result_destroy(r)
 
 
-def _read_graph_result(lib, r, gi: int, n0: int, keep_graphs: bool, level_labels: bool = True) -> LouvainResult:
+def _read_graph_result(lib, r, gi: int, n0: int, keep_graphs: bool, level_labels: bool = True,
+                       fin_out=None) -> LouvainResult:
     acc, att = ctypes.c_int32(), ctypes.c_int32()
     _check(lib.lv_result_graph_num_levels(r, gi, ctypes.byref(acc), ctypes.byref(att)), "lv_result_graph_num_levels")
     levels = []
@@ -438,8 +439,9 @@ def _read_graph_result(lib, r, gi: int, n0: int, keep_graphs: bool, level_labels
                                                  ctypes.byref(nnz), LV_MEM_HOST), "lv_result_level_graph")
                 lr.graph = (off, idx[:nnz.value], w[:nnz.value])
         levels.append(lr)
-    fin = np.empty(n0, dtype=np.int32)
-    _check(lib.lv_result_graph_final_labels(r, gi, fin.ctypes.data, LV_MEM_HOST), "lv_result_graph_final_labels")
+    fin = np.empty(n0, dtype=np.int32) if fin_out is None else fin_out
+    pf, kind = _ptr(fin)
+    _check(lib.lv_result_graph_final_labels(r, gi, pf, kind), "lv_result_graph_final_labels")
     qi, m, q = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_double()
     _check(lib.lv_result_graph_modularity(r, gi, ctypes.byref(qi), ctypes.byref(m), ctypes.byref(q)),
            "lv_result_graph_modularity")
@@ -454,12 +456,16 @@ def _flags(timing: bool, keep_graphs: bool = False, hipgraph: bool = True, autot
 
 def louvain(graph: Graph, max_sweeps: int = 20, max_levels: int = 32, timing: bool = False,
             keep_graphs: bool = False, tuning: Optional[dict] = None, hipgraph: bool = True,
-            autotuned: bool = False, level_labels: bool = True, prune: bool = False, asynchronous: bool = False):
+            autotuned: bool = False, level_labels: bool = True, prune: bool = False, asynchronous: bool = False,
+            out=None):
     """lv_louvain + result accessors, copied to host numpy.  A packed handle
     (``Graph.batch``) gives one LouvainResult per graph, in order.  With
     level_labels=False only the final labels are copied (levels keep their
     statistics and move counts).  prune=True sets LV_PRUNE, asynchronous=True
-    LV_ASYNC."""
+    LV_ASYNC.  `out` (one graph only) takes the final labels instead of a new
+    numpy array: a numpy or torch int32 buffer of n entries, host or device."""
+    if out is not None and graph.count != 1:
+        raise ValueError("out= takes the final labels of a one-graph handle")
     lib = load_library()
     p, _keep = make_params(max_sweeps, max_levels, 0, _flags(timing, keep_graphs, hipgraph, autotuned, prune,
                                                             asynchronous), tuning)
@@ -467,7 +473,7 @@ def louvain(graph: Graph, max_sweeps: int = 20, max_levels: int = 32, timing: bo
     _check(lib.lv_louvain(graph.handle, ctypes.byref(p), ctypes.byref(r)), "lv_louvain")
     try:
         if graph.count == 1:
-            return _read_graph_result(lib, r, 0, graph.n, keep_graphs, level_labels)
+            return _read_graph_result(lib, r, 0, graph.n, keep_graphs, level_labels, out)
         return [_read_graph_result(lib, r, gi, graph.sizes[gi], False, level_labels) for gi in range(graph.count)]
     finally:
         lib.lv_result_destroy(r)

@@ -129,6 +129,26 @@ def test_device_resident_input():
     compare_louvain(graphgen.rmat(12, seed=8), device=True)
 
 
+def test_labels_into_device_buffers():
+    # final Louvain labels and LPA labels written straight into device tensors
+    torch = pytest.importorskip("torch")
+    g = graphgen.rmat(13, seed=9)
+    say(f"case rmat13 out= device buffers n={g.n}")
+    want = oracle.louvain(g)
+    want_lpa = oracle.lpa(g)
+    fin = torch.full((g.n,), -1, dtype=torch.int32, device="cuda")
+    lab = torch.full((g.n,), -1, dtype=torch.int32, device="cuda")
+    with lvp.Graph.from_csr(g) as dg:
+        got = lvp.louvain(dg, level_labels=False, out=fin)
+        got_lpa = lvp.lpa(dg, out=lab)
+    assert got.final_labels is fin
+    assert np.array_equal(fin.cpu().numpy(), want.final_labels) and got.q_int == want.q_int
+    assert np.array_equal(lab.cpu().numpy(), want_lpa.labels)
+    with lvp.Graph.batch([g, g]) as bg:
+        with pytest.raises(ValueError):
+            lvp.louvain(bg, out=fin)
+
+
 @pytest.mark.parametrize("maker", ["rmat", "lfr", "tiny"])
 def test_input_order_storage_gives_same_results(maker):
     # LV_KEEP_ORDER stores the input order; the default stores by degree
