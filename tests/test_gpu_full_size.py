@@ -1,9 +1,14 @@
-"""The benchmark's graph at its full size, in the launch configuration the
+"""The workloads at their full sizes, in the launch configuration the
 benchmark times (captured sweeps, every degree class, the bucketed partition
-path): level 0's local moving (all of its sweeps) and LPA against the oracle,
-every label and every per-sweep move count.  The oracle's sweeps over 520 M
-entries take a second or two each; its aggregation would take minutes, so
-Louvain stops after level 0."""
+path), against the oracle: every label and every per-sweep move count.
+
+- R-MAT 24 (520.8 M entries) and LFR with 10 M vertices: level 0's local
+  moving (all of its sweeps) and LPA.  The oracle's sweeps take a second or
+  two each; its aggregation at these sizes would take minutes, so Louvain
+  stops after level 0.
+- The 4,096-graph batch (about 1.15e9 entries in one handle): complete
+  Louvain on the device, twelve evenly spaced graphs against the oracle run
+  on each graph alone."""
 import sys
 
 import numpy as np
@@ -61,3 +66,46 @@ def test_rmat24_lpa(rmat24):
         got = lvp.lpa(dg, max_sweeps=SWEEPS)
     assert got.moves == [int(x) for x in moves]
     assert np.array_equal(got.labels, want)
+
+
+@pytest.mark.timeout(600)
+def test_lfr_10m_level0_louvain_and_lpa():
+    # the LFR configuration at full size: 10 M vertices, weights 1..8
+    say("generating LFR n=10,000,000 seed 3")
+    g, _ = graphgen.lfr(10_000_000, seed=3)
+    say(f"generated n={g.n} nnz={g.nnz}")
+    adj = oracle.adjacency(g)
+    c, moves = oracle.local_move(adj, oracle.LOUVAIN, max_sweeps=SWEEPS)
+    want, n2 = oracle.renumber(c)
+    q_want, m_want = oracle.modularity_int(adj, want)
+    c, lpa_moves = oracle.local_move(adj, oracle.LPA, max_sweeps=SWEEPS)
+    want_lpa, _ = oracle.renumber(c)
+    say(f"oracle moves {list(moves)}; LPA {list(lpa_moves)}; GPU")
+    with lvp.Graph.from_csr(g, validate=False) as dg:
+        got = lvp.louvain(dg, max_sweeps=SWEEPS, max_levels=1)
+        got_lpa = lvp.lpa(dg, max_sweeps=SWEEPS)
+    lvl = got.levels[0]
+    assert lvl.moves == [int(x) for x in moves]
+    assert lvl.info["n_next"] == n2 and np.array_equal(lvl.labels, want)
+    assert (lvl.info["q_end"], got.M) == (q_want, m_want)
+    assert got_lpa.moves == [int(x) for x in lpa_moves]
+    assert np.array_equal(got_lpa.labels, want_lpa)
+
+
+@pytest.mark.timeout(600)
+def test_batch_4096_graphs_sampled():
+    # the batch configuration at full size (4,096 graphs packed in one
+    # handle, about 1.15e9 entries), complete Louvain; sampled graphs against
+    # the oracle run on each graph alone
+    say("generating the 4,096-graph batch, seed 4")
+    gs = graphgen.batch_mix(4096, seed=4)
+    say(f"generated {sum(x.nnz for x in gs)} entries")
+    with lvp.Graph.batch(gs, validate=False) as bg:
+        got = lvp.louvain(bg, level_labels=False)
+    assert len(got) == len(gs)
+    for i in np.linspace(0, len(gs) - 1, 12).astype(int):
+        say(f"graph {i}: n={gs[i].n} nnz={gs[i].nnz}")
+        want = oracle.louvain(gs[i])
+        assert np.array_equal(got[i].final_labels, want.final_labels), f"graph {i} labels"
+        assert got[i].q_int == want.q_int and got[i].M == want.M
+        assert [lv.moves for lv in got[i].levels] == [[int(x) for x in lv.moves] for lv in want.levels]
