@@ -8,7 +8,10 @@ path), against the oracle: every label and every per-sweep move count.
   stops after level 0.
 - The 4,096-graph batch (about 1.15e9 entries in one handle): complete
   Louvain on the device, twelve evenly spaced graphs against the oracle run
-  on each graph alone."""
+  on each graph alone.
+- The serving pool (32 R-MAT graphs of 10 k to 4 M vertices) through one
+  server at once: every job against a one-graph-per-call run, and every job
+  of up to 12 M entries against the oracle."""
 import sys
 
 import numpy as np
@@ -109,3 +112,32 @@ def test_batch_4096_graphs_sampled():
         assert np.array_equal(got[i].final_labels, want.final_labels), f"graph {i} labels"
         assert got[i].q_int == want.q_int and got[i].M == want.M
         assert [lv.moves for lv in got[i].levels] == [[int(x) for x in lv.moves] for lv in want.levels]
+
+
+@pytest.mark.timeout(600)
+def test_serving_pool_full_size():
+    # the serving configuration's graphs (R-MAT, 10 k to 4 M vertices, edge
+    # factor 8..16), all submitted at once to one server: every job against a
+    # one-graph-per-call run, and those of up to 12 M entries against the oracle
+    say("generating the serving pool, seed 5")
+    pool = graphgen.serving_pool(32, seed=5)
+    say(f"generated {len(pool)} graphs, {sum(g.nnz for g in pool)} entries")
+    with lvp.Server() as srv:
+        tickets = [srv.submit(g) for g in pool]
+        served = []
+        for g, t in zip(pool, tickets):
+            assert srv.wait(t, 120000), g.name
+            served.append(srv.result(t, g.n))
+        st = srv.stats()
+        say(f"stats {st}")
+        assert st["completed"] == len(pool) and st["in_flight"] == 0 and st["mem_in_use"] == 0
+    for g, (labels, info) in zip(pool, served):
+        say(f"{g.name}: nnz={g.nnz}")
+        assert info["status"] == 0, g.name
+        with lvp.Graph.from_csr(g, validate=False) as dg:
+            alone = lvp.louvain(dg, level_labels=False)
+        assert np.array_equal(labels, alone.final_labels) and info["q_int"] == alone.q_int, g.name
+        if g.nnz <= 12_000_000:
+            want = oracle.louvain(g)
+            assert np.array_equal(labels, want.final_labels), g.name
+            assert (info["q_int"], info["m"]) == (want.q_int, want.M), g.name
