@@ -124,7 +124,8 @@ typedef struct lv_params {
     int32_t max_sweeps;    /* sweeps per level, default 20 (Alg. 2 maxIteration)          */
     int32_t max_levels;    /* accepted Louvain levels, default 32                         */
     int64_t lpa_threshold; /* LPA stops after two sweeps with <= this many moves (Alg. 1) */
-    uint32_t flags;        /* LV_TIMING                                                    */
+    uint32_t flags;        /* LV_TIMING | LV_KEEP_GRAPHS | LV_NO_HIPGRAPH | LV_AUTOTUNE |  */
+                           /* LV_PRUNE | LV_ASYNC                                          */
     const lv_tuning* tuning; /* NULL = built-in defaults                                   */
 } lv_params;
 
