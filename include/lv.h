@@ -118,6 +118,11 @@ typedef struct lv_tuning {
     int32_t hub_chunk;  /* mode 2: entries per scatter workgroup, 1024, 2048 or 4096      */
     int32_t order_min;  /* coarse levels with at least this many entries are stored by    */
                         /* descending degree, like level 0 (0 = 2^22)                      */
+    int32_t agg_sort;   /* aggregation: 1 = always sort and reduce the keys               */
+                        /* (label(i), label(j)) of the entries; 0 = by community after a   */
+                        /* level with at most 20 vertices per community (members' rows    */
+                        /* laid out by label, each community's entries summed in LDS, the */
+                        /* longest sorted), sorting otherwise.  Same coarse graphs.       */
 } lv_tuning;
 
 typedef struct lv_params {

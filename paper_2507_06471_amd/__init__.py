@@ -54,7 +54,8 @@ class lv_tuning(ctypes.Structure):
     _fields_ = [("sub_max", ctypes.c_int32), ("wave_max", ctypes.c_int32),
                 ("block_max", ctypes.c_int32), ("part_keys", ctypes.c_int32),
                 ("part_slots", ctypes.c_int32), ("hub_mode", ctypes.c_int32),
-                ("hub_chunk", ctypes.c_int32), ("order_min", ctypes.c_int32)]
+                ("hub_chunk", ctypes.c_int32), ("order_min", ctypes.c_int32),
+                ("agg_sort", ctypes.c_int32)]
 
 
 class lv_params(ctypes.Structure):

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblv.so")
-SOURCES = ["lv_prims.hip", "lv_graph.hip", "lv_move.hip", "lv_coarsen.hip", "lv_probe.hip", "lv_api.hip"]
+SOURCES = ["lv_prims.hip", "lv_graph.hip", "lv_move.hip", "lv_coarsen.hip", "lv_agg.hip", "lv_probe.hip", "lv_api.hip"]
 ARCH = os.environ.get("LV_OFFLOAD_ARCH", "gfx950")
 
 

@@ -108,6 +108,9 @@ struct Workspace {
     DevBuf tiles; // aggregation: per key tile its count, first entry and output position
     DevBuf p_off, p_idx, p_w, p_k, p_orig, p_inv;  // a coarse level stored by degree
     DevBuf k64;
+    // aggregation by community: entry offsets in member order, segment starts,
+    // distinct counts, long segments' offsets, their sort keys and results
+    DevBuf a_voff, a_seg, a_cnt, a_hoff, a_uoff, h_keys, h_keys_alt, h_col, h_wt;
     // per-graph state of a level (G entries) and sweep control
     DevBuf ctl, gdone, gsweeps, gmoves, gactive, gsum, gsq, gmeta, segs;
 };
@@ -232,6 +235,7 @@ struct Tune {
     int32_t fb_chunk;   // entries / slots per workgroup on the global-table fallback
     int32_t sc_chunk;   // entries per scatter workgroup (bucketed mode)
     int64_t order_min;  // coarse levels with at least this many entries are stored by degree
+    int32_t agg_sort;   // 1: aggregation sorts every entry's key (else by community)
 };
 
 Tune make_tune(const lv_tuning* t)
@@ -245,6 +249,7 @@ Tune make_tune(const lv_tuning* t)
     u.order_min = (int64_t)1 << 22;
     u.fb_chunk = 4096;
     u.sc_chunk = 1024;
+    u.agg_sort = 0;
     if (t) {
         // sub_max bounds the sub-wavefront classes, wave_max the wavefront
         // class, block_max the workgroup classes; each is clamped to the
@@ -267,6 +272,7 @@ Tune make_tune(const lv_tuning* t)
         if (t->part_keys > 0) u.part_keys = std::max(32, t->part_keys);
         if (t->hub_chunk > 0) u.sc_chunk = t->hub_chunk <= 1024 ? 1024 : t->hub_chunk <= 2048 ? 2048 : 4096;
         if (t->order_min > 0) u.order_min = t->order_min;
+        u.agg_sort = t->agg_sort == 1 ? 1 : 0;
     }
     // a single partition must always fit: part_keys <= 3/4 of the slots
     u.part_keys = std::min(u.part_keys, u.part_slots / 4 * 3);
@@ -793,6 +799,7 @@ struct Coarse {
     int64_t nnz2 = 0;
     int32_t *off = nullptr, *idx = nullptr, *w = nullptr, *k = nullptr, *gid = nullptr;
     std::vector<int64_t> q_end;  // [G] Q_int of each graph's partition = M * Sigma_in - sum k'^2
+    bool sorted = true;          // columns sorted within each row
 };
 
 // Aggregation (Algorithm 3): coarse CSR A' = S^T A S of the packed level into
@@ -833,7 +840,138 @@ lv_status tile_keys(lv_graph* g, bool agg, int32_t n, const int32_t* off, const 
 
 // isolated: vertices without entries (each stays its own community), to
 // judge how strongly the level merged.
-lv_status aggregate(lv_graph* g, const LevelGraph& G, int32_t n2, int32_t isolated, int slot, Coarse& out)
+// Aggregation by community: members' rows laid out by label, each coarse
+// vertex's segment summed in LDS (segments of up to 8192 entries, by degree
+// class) or sorted and reduced (longer ones), then packed into the coarse CSR
+// of ping-pong slot `slot`.  d_sin[graph] += Sigma_in; *e2_out = coarse
+// entries.  Uses ws.keys / ws.keys_alt (8 bytes per entry each) as staging.
+lv_status aggregate_by_community(lv_graph* g, const LevelGraph& G, int32_t n2, int slot, int colbits, int32_t* gid2,
+                                 int64_t* d_sin, int32_t* e2_out, const int32_t* bounds)
+{
+    Workspace& ws = g->ws;
+    hipStream_t s = g->stream;
+    const int32_t n = G.n;
+    const int64_t E = G.nnz;
+    const int32_t* labels = ws.labels.as<int32_t>();
+    HIP_TRY(ws.tmp.ensure(std::max(radix_tmp_bytes(std::max<int64_t>(n, E)),
+                                   scan_tmp_bytes(std::max<int64_t>(std::max<int64_t>(n, E), n2) + 1, 8))));
+    // 1. positions grouped by label (stable: by position within a label)
+    HIP_TRY(launch_copy_i32(ws.cls.as<int32_t>(), labels, n, s));
+    HIP_TRY(launch_iota(ws.vert.as<int32_t>(), n, s));
+    bool alt = false;
+    HIP_TRY(radix_sort_u32(ws.cls.as<uint32_t>(), ws.vert.as<int32_t>(), ws.cls_alt.as<uint32_t>(),
+                           ws.vert_alt.as<int32_t>(), n, colbits, ws.tmp.p, ws.tmp.cap, &alt, s));
+    const uint32_t* lab_sorted = alt ? ws.cls_alt.as<uint32_t>() : ws.cls.as<uint32_t>();
+    const int32_t* mem = alt ? ws.vert_alt.as<int32_t>() : ws.vert.as<int32_t>();
+    // 2. entry offsets in member order, 3. each coarse vertex's segment
+    HIP_TRY(ws.a_voff.ensure(sizeof(int32_t) * ((size_t)n + 1)));
+    HIP_TRY(ws.a_seg.ensure(sizeof(int32_t) * ((size_t)n2 + 1)));
+    int32_t* voff = ws.a_voff.as<int32_t>();
+    int32_t* seg = ws.a_seg.as<int32_t>();
+    HIP_TRY(launch_member_lengths(n, mem, G.off, voff, s));
+    if (n > 0) HIP_TRY(scan_exclusive_i32(voff, voff, n, voff + n, ws.tmp.p, ws.tmp.cap, s));
+    HIP_TRY(launch_segment_starts(n, lab_sorted, voff, n2, (int32_t)E, seg, s));
+    // 4. staging: the members' rows, columns replaced by their labels
+    int32_t* col = (int32_t*)ws.keys.p;
+    int32_t* wt = G.w ? col + E : nullptr;
+    int32_t* col2 = (int32_t*)ws.keys_alt.p;
+    int32_t* wt2 = col2 + E;
+    HIP_TRY(launch_perm_rows(n, voff, E, mem, G.off, G.idx, G.w, labels, col, wt, s));
+    // 5. coarse vertices by segment length, with the local-moving classes'
+    // bounds (the tuning's, never above a class's table)
+    HIP_TRY(launch_classify(n2, seg, bounds, ws.cls.as<uint32_t>(), ws.vert.as<int32_t>(), s));
+    HIP_TRY(radix_sort_u32(ws.cls.as<uint32_t>(), ws.vert.as<int32_t>(), ws.cls_alt.as<uint32_t>(),
+                           ws.vert_alt.as<int32_t>(), n2, 8, ws.tmp.p, ws.tmp.cap, &alt, s));
+    const uint32_t* cls_sorted = alt ? ws.cls_alt.as<uint32_t>() : ws.cls.as<uint32_t>();
+    const int32_t* vsorted = alt ? ws.vert_alt.as<int32_t>() : ws.vert.as<int32_t>();
+    int32_t* d_start = ws.small.as<int32_t>();
+    HIP_TRY(launch_fill_i32(d_start, -1, NUM_CLS + 1, s));
+    HIP_TRY(launch_class_starts(cls_sorted, n2, d_start, s));
+    int32_t start[NUM_CLS + 1];
+    HIP_TRY(hipMemcpyAsync(start, d_start, sizeof start, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    start[NUM_CLS] = n2;
+    for (int c = NUM_CLS - 1; c >= 0; --c)
+        if (start[c] < 0) start[c] = start[c + 1];
+    // 6. segments of up to 8192 entries: summed in LDS
+    HIP_TRY(ws.a_cnt.ensure(sizeof(int32_t) * ((size_t)n2 + 1)));
+    int32_t* cnt = ws.a_cnt.as<int32_t>();
+    HIP_TRY(launch_fill_i32(cnt, 0, (int64_t)n2 + 1, s));
+    AggArgs aa{};
+    aa.seg = seg;
+    aa.col = col;
+    aa.wt = wt;
+    aa.col2 = col2;
+    aa.wt2 = wt2;
+    aa.cnt = cnt;
+    aa.gid2 = gid2;
+    aa.sigma_in = d_sin;
+    for (int c = CLS_L4; c < CLS_HUB; ++c) {
+        aa.verts = vsorted + start[c];
+        aa.m = start[c + 1] - start[c];
+        HIP_TRY(launch_agg_class(c, aa, s));
+    }
+    // 7. longer segments: keys sorted and reduced, placed at their segments
+    const int32_t nh = n2 - start[CLS_HUB];
+    if (nh > 0) {
+        const int32_t* hv = vsorted + start[CLS_HUB];
+        HIP_TRY(ws.a_hoff.ensure(sizeof(int32_t) * ((size_t)nh + 1)));
+        int32_t* hoff = ws.a_hoff.as<int32_t>();
+        HIP_TRY(launch_long_lengths(nh, hv, seg, hoff, s));
+        HIP_TRY(scan_exclusive_i32(hoff, hoff, nh, hoff + nh, ws.tmp.p, ws.tmp.cap, s));
+        int32_t eh = 0;
+        HIP_TRY(hipMemcpyAsync(&eh, hoff + nh, sizeof eh, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        HIP_TRY(ws.h_keys.ensure(sizeof(uint64_t) * (size_t)std::max(eh, 1)));
+        HIP_TRY(ws.h_keys_alt.ensure(sizeof(uint64_t) * (size_t)std::max(eh, 1)));
+        HIP_TRY(ws.tmp.ensure(std::max(radix_tmp_bytes(eh), scan_tmp_bytes(eh, 8))));
+        HIP_TRY(launch_long_keys(nh, hv, hoff, eh, seg, col, wt, colbits, ws.h_keys.as<uint64_t>(),
+                                 ws.vals.as<int32_t>(), s));
+        bool halt = false;
+        HIP_TRY(radix_sort_u64(ws.h_keys.as<uint64_t>(), ws.vals.as<int32_t>(), ws.h_keys_alt.as<uint64_t>(),
+                               ws.vals_alt.as<int32_t>(), eh, 2 * colbits, ws.tmp.p, ws.tmp.cap, &halt, s));
+        const uint64_t* ks = halt ? ws.h_keys_alt.as<uint64_t>() : ws.h_keys.as<uint64_t>();
+        const int32_t* vs = halt ? ws.vals_alt.as<int32_t>() : ws.vals.as<int32_t>();
+        uint64_t* keys2 = halt ? ws.h_keys.as<uint64_t>() : ws.h_keys_alt.as<uint64_t>();
+        int32_t* d_eu = (int32_t*)(ws.small.as<char>() + 2304);
+        HIP_TRY(launch_segment_heads(ks, eh, ws.head.as<int32_t>(), s));
+        HIP_TRY(scan_exclusive_i32(ws.head.as<int32_t>(), ws.head.as<int32_t>(), eh, d_eu, ws.tmp.p, ws.tmp.cap, s));
+        int32_t eu = 0;
+        HIP_TRY(hipMemcpyAsync(&eu, d_eu, sizeof eu, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        HIP_TRY(ws.h_col.ensure(sizeof(int32_t) * (size_t)std::max(eu, 1)));
+        HIP_TRY(ws.h_wt.ensure(sizeof(int32_t) * (size_t)std::max(eu, 1)));
+        HIP_TRY(ws.a_uoff.ensure(sizeof(int32_t) * ((size_t)n2 + 1)));
+        HIP_TRY(hipMemsetAsync(ws.h_wt.p, 0, sizeof(int32_t) * (size_t)std::max(eu, 1), s));
+        HIP_TRY(launch_segment_reduce(ks, vs, ws.head.as<int32_t>(), eh, colbits, ws.h_col.as<int32_t>(),
+                                      ws.h_wt.as<int32_t>(), keys2, s));
+        HIP_TRY(launch_row_offsets(keys2, eu, n2, colbits, ws.a_uoff.as<int32_t>(), s));
+        HIP_TRY(launch_long_place(eu, keys2, ws.h_col.as<int32_t>(), ws.h_wt.as<int32_t>(), ws.a_uoff.as<int32_t>(),
+                                  seg, colbits, col2, wt2, gid2, d_sin, s));
+        HIP_TRY(launch_long_counts(nh, hv, ws.a_uoff.as<int32_t>(), cnt, s));
+    }
+    // 8. coarse row offsets and the packed rows
+    int32_t* off2 = ws.g_off[slot].as<int32_t>();
+    if (n2 > 0) HIP_TRY(scan_exclusive_i32(cnt, off2, n2, off2 + n2, ws.tmp.p, ws.tmp.cap, s));
+    else HIP_TRY(launch_fill_i32(off2, 0, 1, s));
+    int32_t e2 = 0;
+    HIP_TRY(hipMemcpyAsync(&e2, off2 + n2, sizeof e2, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(ws.g_idx[slot].ensure(sizeof(int32_t) * (size_t)std::max(e2, 1)));
+    HIP_TRY(ws.g_w[slot].ensure(sizeof(int32_t) * (size_t)std::max(e2, 1)));
+    HIP_TRY(launch_pack_rows(n2, off2, e2, seg, col2, wt2, ws.g_idx[slot].as<int32_t>(), ws.g_w[slot].as<int32_t>(),
+                             s));
+    *e2_out = e2;
+    return LV_OK;
+}
+
+// A level that merged weakly (at most 20 vertices with entries per
+// community) is aggregated by community (lv_agg.hip), which leaves a coarse
+// row's columns in table order; after a strong merge, or with by_sort, the
+// entries' keys are sorted and reduced (summed within tiles first after a
+// strong merge), which leaves them sorted.
+lv_status aggregate(lv_graph* g, const LevelGraph& G, int32_t n2, int32_t isolated, int slot, Coarse& out,
+                    bool by_sort = false, const int32_t* bounds = CLS_CAP)
 {
     Workspace& ws = g->ws;
     hipStream_t s = g->stream;
@@ -864,6 +1002,26 @@ lv_status aggregate(lv_graph* g, const LevelGraph& G, int32_t n2, int32_t isolat
     // with entries) most of a row's entries share a few keys: sum them within
     // tiles first, so that only the tiles' distinct keys are sorted.
     const bool agg = (int64_t)(n2 - isolated) * 20 < (int64_t)(G.n - isolated);
+    if (!by_sort && !agg) {
+        int32_t e2 = 0;
+        LV_TRY(aggregate_by_community(g, G, n2, slot, colbits, gid2, d_sin, &e2, bounds));
+        LV_TRY(ensure_pinned(g, std::max<size_t>(4096, 2 * sizeof(int64_t) * (size_t)G.G + 64)));
+        int64_t* h_q = (int64_t*)g->pinned;
+        HIP_TRY(hipMemcpyAsync(h_q, d_sin, sizeof(int64_t) * (size_t)G.G, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(h_q + G.G, d_sq, sizeof(int64_t) * (size_t)G.G, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        out.q_end.resize(G.G);
+        for (int32_t c = 0; c < G.G; ++c) out.q_end[c] = G.Mh[c] * h_q[c] - h_q[G.G + c];
+        out.n2 = n2;
+        out.nnz2 = e2;
+        out.off = ws.g_off[slot].as<int32_t>();
+        out.idx = ws.g_idx[slot].as<int32_t>();
+        out.w = ws.g_w[slot].as<int32_t>();
+        out.k = ws.g_k[slot].as<int32_t>();
+        out.gid = gid2;
+        out.sorted = false;
+        return LV_OK;
+    }
     int64_t Ek = 0;
     LV_TRY(tile_keys(g, agg, G.n, G.off, G.idx, G.w, E, ws.labels.as<int32_t>(), colbits, G.gid, d_sin, &Ek));
     bool in_alt = false;
@@ -902,6 +1060,7 @@ lv_status aggregate(lv_graph* g, const LevelGraph& G, int32_t n2, int32_t isolat
     out.w = ws.g_w[slot].as<int32_t>();
     out.k = ws.g_k[slot].as<int32_t>();
     out.gid = gid2;
+    out.sorted = true;
     return LV_OK;
 }
 
@@ -1132,6 +1291,28 @@ lv_status degree_order(lv_graph* g, int32_t n, int64_t nnz, const int32_t* off, 
     return LV_OK;
 }
 
+// Sort the columns within every row of a device CSR in place (weights
+// follow); uses ws.keys* / ws.vals* (at least nnz items each).
+lv_status sort_rows(lv_graph* g, int32_t n, int64_t nnz, const int32_t* off, int32_t* idx, int32_t* w)
+{
+    if (n <= 0 || nnz <= 1) return LV_OK;
+    Workspace& ws = g->ws;
+    hipStream_t s = g->stream;
+    const int cb = bits_for(std::max<int64_t>(n, 2));
+    HIP_TRY(ws.keys.ensure(sizeof(uint64_t) * (size_t)nnz));
+    HIP_TRY(ws.keys_alt.ensure(sizeof(uint64_t) * (size_t)nnz));
+    HIP_TRY(ws.vals.ensure(sizeof(int32_t) * (size_t)nnz));
+    HIP_TRY(ws.vals_alt.ensure(sizeof(int32_t) * (size_t)nnz));
+    HIP_TRY(ws.tmp.ensure(radix_tmp_bytes(nnz)));
+    HIP_TRY(launch_row_keys(n, off, nnz, idx, w, cb, ws.keys.as<uint64_t>(), ws.vals.as<int32_t>(), s));
+    bool alt = false;
+    HIP_TRY(radix_sort_u64(ws.keys.as<uint64_t>(), ws.vals.as<int32_t>(), ws.keys_alt.as<uint64_t>(),
+                           ws.vals_alt.as<int32_t>(), nnz, 2 * cb, ws.tmp.p, ws.tmp.cap, &alt, s));
+    HIP_TRY(launch_unpack_keys(nnz, alt ? ws.keys_alt.as<uint64_t>() : ws.keys.as<uint64_t>(),
+                               alt ? ws.vals_alt.as<int32_t>() : ws.vals.as<int32_t>(), cb, idx, w, s));
+    return LV_OK;
+}
+
 lv_status louvain_impl(lv_graph* g, const Params& p, bool keep_graphs, lv_result* r)
 {
     hipStream_t s = g->stream;
@@ -1177,7 +1358,7 @@ lv_status louvain_impl(lv_graph* g, const Params& p, bool keep_graphs, lv_result
         LV_TRY(renumber(g, G, &n2, voff2));
         if (tm.on) HIP_TRY(tm.mark(&t1));
         Coarse co;
-        LV_TRY(aggregate(g, G, n2, so.isolated, slot, co));
+        LV_TRY(aggregate(g, G, n2, so.isolated, slot, co, p.tune.agg_sort != 0, p.tune.bounds));
         std::vector<int64_t> eoff2;
         LV_TRY(graph_entry_offsets(g, co.off, voff2, eoff2));
         double ren_ms = 0, agg_ms = 0;
@@ -1226,6 +1407,7 @@ lv_status louvain_impl(lv_graph* g, const Params& p, bool keep_graphs, lv_result
                 gr.q_int = co.q_end[c];
                 ++gr.accepted;
                 if (keep_graphs && G0 == 1) {
+                    if (!co.sorted) LV_TRY(sort_rows(g, co.n2, co.nnz2, co.off, co.idx, co.w));
                     rec.g_off = std::make_shared<DevBuf>();
                     rec.g_idx = std::make_shared<DevBuf>();
                     rec.g_w = std::make_shared<DevBuf>();

@@ -230,6 +230,41 @@ __device__ __forceinline__ void for_tile_entries_co_at(int64_t tile, const int32
     }
 }
 
+// Insert (C, W) into an LDS open-addressing table that is guaranteed to have
+// room (distinct keys < slots); the thread that claims a slot stores the
+// community's volume S beside it.  The table has mask+1 slots (a power of
+// two), or with MOD exactly `mask` slots of any count, hashed by a
+// multiply-high reduction.
+template <bool SIG, bool MOD = false>
+__device__ __forceinline__ void lds_insert(int32_t* key, int32_t* val, int32_t* sig, uint32_t mask, int32_t C,
+                                           int32_t W, int32_t S)
+{
+    uint32_t h = MOD ? (uint32_t)(((uint64_t)mix32(C) * mask) >> 32) : (mix32(C) & mask);
+    for (;;) {
+        const int32_t prev = atomicCAS(&key[h], EMPTY_KEY, C);
+        if constexpr (SIG) if (prev == EMPTY_KEY) sig[h] = S;
+        if (prev == EMPTY_KEY || prev == C) { atomicAdd(&val[h], W); return; }
+        if constexpr (MOD) h = h + 1 == mask ? 0u : h + 1; else h = (h + 1) & mask;
+    }
+}
+
+// Make a group's LDS writes visible to the whole group.  A group within one
+// wavefront needs no workgroup barrier: a wavefront's LDS operations are
+// performed in order, so a wavefront-scope fence (which keeps the compiler
+// from moving LDS accesses across it) suffices, and the wavefronts of a
+// workgroup do not wait for each other.
+template <int G>
+__device__ __forceinline__ void group_sync()
+{
+    if constexpr (G <= WAVE) {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
 constexpr int TILE_BS = 256;
 constexpr int TILE_IT = 8;
 constexpr int64_t TILE = TILE_BS * TILE_IT;

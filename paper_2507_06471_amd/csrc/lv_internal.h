@@ -36,6 +36,8 @@ enum MoveClass : int {
 constexpr int32_t CLS_CAP[NUM_CLS] = {0, 4, 8, 32, 128, 256, 512, 1024, 2048, 3072, 8192, INT32_MAX};
 // classes of groups narrower than a wavefront, of one wavefront, of workgroups
 constexpr int CLS_FIRST_WAVE = CLS_L256, CLS_FIRST_BLOCK = CLS_L512;
+// table slots of the L8K class (8-byte slots: key and weight sum)
+constexpr int32_t L8K_SLOTS = 10112;
 
 // Device-side sweep control of one level: completed sweeps and whether every
 // graph of the level has stopped (kernels of later sweeps then exit early).
@@ -287,5 +289,42 @@ hipError_t launch_modularity_parts(int32_t n, const int32_t* off, const int32_t*
                                    int64_t* out2, hipStream_t s);
 
 hipError_t launch_check_labels(const int32_t* labels, int32_t n, int32_t* err, hipStream_t s);
+
+// ---- aggregation by community (lv_agg.hip)
+// One degree class of coarse vertices: verts[0..m) are coarse vertices whose
+// segments [seg[P], seg[P+1]) of (col, wt) (wt null: unit) are summed; the
+// distinct pairs go to [seg[P], seg[P] + cnt[P]) of (col2, wt2);
+// sigma_in[graph] += the weight of the pair (P, P).
+struct AggArgs {
+    const int32_t* verts;
+    int32_t m;
+    const int32_t* seg;
+    const int32_t* col;
+    const int32_t* wt;
+    int32_t* col2;
+    int32_t* wt2;
+    int32_t* cnt;
+    const int32_t* gid2;    // graph of each coarse vertex (null: one graph)
+    int64_t* sigma_in;
+};
+hipError_t launch_member_lengths(int32_t n, const int32_t* mem, const int32_t* off, int32_t* dm, hipStream_t s);
+hipError_t launch_segment_starts(int32_t n, const uint32_t* lab_sorted, const int32_t* voff, int32_t n2, int32_t nnz,
+                                 int32_t* seg, hipStream_t s);
+hipError_t launch_agg_class(int cls, const AggArgs& a, hipStream_t s);
+hipError_t launch_long_lengths(int32_t nh, const int32_t* hv, const int32_t* seg, int32_t* hd, hipStream_t s);
+hipError_t launch_long_keys(int32_t nh, const int32_t* hv, const int32_t* hoff, int64_t eh, const int32_t* seg,
+                            const int32_t* col, const int32_t* wt, int colbits, uint64_t* keys, int32_t* vals,
+                            hipStream_t s);
+hipError_t launch_long_place(int64_t eu, const uint64_t* keys2, const int32_t* col_u, const int32_t* wt_u,
+                             const int32_t* uoff, const int32_t* seg, int colbits, int32_t* col2, int32_t* wt2,
+                             const int32_t* gid2, int64_t* sigma_in, hipStream_t s);
+hipError_t launch_long_counts(int32_t nh, const int32_t* hv, const int32_t* uoff, int32_t* cnt, hipStream_t s);
+hipError_t launch_pack_rows(int32_t n2, const int32_t* off2, int64_t e2, const int32_t* seg, const int32_t* col2,
+                            const int32_t* wt2, int32_t* idx, int32_t* w, hipStream_t s);
+// sort the columns of every row of a CSR in place (keys / vals: nnz items each, plus alternates)
+hipError_t launch_row_keys(int32_t n, const int32_t* off, int64_t nnz, const int32_t* idx, const int32_t* w,
+                           int colbits, uint64_t* keys, int32_t* vals, hipStream_t s);
+hipError_t launch_unpack_keys(int64_t nnz, const uint64_t* keys, const int32_t* vals, int colbits, int32_t* idx,
+                              int32_t* w, hipStream_t s);
 
 }  // namespace lv

@@ -107,10 +107,14 @@ def test_lfr_weighted():
     {"block_max": 64, "hub_mode": 2, "part_keys": 32, "part_slots": 64},     # many small buckets
     {"block_max": 64, "hub_mode": 2, "part_keys": 48, "hub_chunk": 1024},
     {"block_max": 300, "hub_mode": 2, "part_keys": 200, "hub_chunk": 4096},
+    {"agg_sort": 1},                                                       # aggregation by sorting only
+    {"agg_sort": 1, "block_max": 64, "hub_mode": 2, "part_keys": 48},
 ])
 def test_tuning_never_changes_results(tuning):
+    # the class bounds also route coarse vertices between aggregation in LDS
+    # and the sorted path for long segments; coarse graphs are compared too
     g = graphgen.rmat(14, seed=5)
-    compare_louvain(g, tuning=tuning)
+    compare_louvain(g, tuning=tuning, keep_graphs=True)
     compare_lpa(g, tuning=tuning)
 
 
