@@ -1,7 +1,8 @@
-// Renumbering and aggregation (Algorithm 3 of arXiv 2507.06471) on gfx950.
+// Renumbering and aggregation by sorting (Algorithm 3 of arXiv 2507.06471) on
+// gfx950; aggregation by community is in lv_agg.hip.
 //
-// Renumber (K9): a community's new id is the rank of its smallest member
-// vertex.  Aggregation (K10/K11): every CSR entry (i, j, A_ij) becomes the key
+// Renumber: a community's new id is the rank of its smallest member vertex.
+// Aggregation by sorting: every CSR entry (i, j, A_ij) becomes the key
 // (label(i), label(j)) with weight A_ij; keys are radix-sorted and equal keys
 // merged with their weights summed, giving the coarse CSR A' = S^T A S with
 // sorted columns.  The community's internal weight lands on the diagonal,
