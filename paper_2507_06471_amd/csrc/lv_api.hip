@@ -19,6 +19,7 @@
 #include <memory>
 #include <new>
 #include <string>
+#include <initializer_list>
 #include <vector>
 
 using namespace lv;
@@ -345,6 +346,45 @@ struct HubPlan {
     HubArgs args{};
 };
 
+lv_status ensure_pinned(lv_graph* g, size_t bytes)
+{
+    if (g->pinned_bytes >= bytes) return LV_OK;
+    if (g->pinned) (void)hipHostFree(g->pinned);
+    g->pinned = nullptr;
+    g->pinned_bytes = 0;
+    HIP_TRY(hipHostMalloc((void**)&g->pinned, bytes, hipHostMallocDefault));
+    g->pinned_bytes = bytes;
+    return LV_OK;
+}
+
+// Read small device results back to host memory through the handle's pinned
+// staging area, several in one wait.  Overwrites the staging area.
+struct HostCopy {
+    void* dst;
+    const void* src;
+    size_t bytes;
+};
+lv_status read_back(lv_graph* g, std::initializer_list<HostCopy> parts)
+{
+    auto padded = [](size_t b) { return (b + 15) & ~(size_t)15; };
+    size_t total = 0;
+    for (const HostCopy& p : parts) total += padded(p.bytes);
+    LV_TRY(ensure_pinned(g, std::max<size_t>(total, 4096)));
+    char* base = (char*)g->pinned;
+    size_t at = 0;
+    for (const HostCopy& p : parts) {
+        if (p.bytes) HIP_TRY(hipMemcpyAsync(base + at, p.src, p.bytes, hipMemcpyDeviceToHost, g->stream));
+        at += padded(p.bytes);
+    }
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    at = 0;
+    for (const HostCopy& p : parts) {
+        if (p.bytes) std::memcpy(p.dst, base + at, p.bytes);
+        at += padded(p.bytes);
+    }
+    return LV_OK;
+}
+
 lv_status plan_hubs(lv_graph* g, const LevelGraph& G, const int32_t* hub_verts, int32_t nhubs, const Tune& tu_in,
                     HubPlan& plan)
 {
@@ -359,10 +399,8 @@ lv_status plan_hubs(lv_graph* g, const LevelGraph& G, const int32_t* hub_verts, 
     int32_t* d_len = d_beg + nhubs;
     HIP_TRY(launch_gather_rows(hub_verts, nhubs, G.off, d_beg, d_len, s));
     std::vector<int32_t> beg(nhubs), len(nhubs), hv(nhubs);
-    HIP_TRY(hipMemcpyAsync(beg.data(), d_beg, sizeof(int32_t) * nhubs, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(len.data(), d_len, sizeof(int32_t) * nhubs, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(hv.data(), hub_verts, sizeof(int32_t) * nhubs, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    const size_t hb = sizeof(int32_t) * (size_t)nhubs;
+    LV_TRY(read_back(g, {{beg.data(), d_beg, hb}, {len.data(), d_len, hb}, {hv.data(), hub_verts, hb}}));
     if (tu.bucketed) {
         // the scatter pass histograms at most HUB_PMAX partitions of a vertex:
         // a level with a longer row uses the compact mode instead
@@ -500,16 +538,6 @@ lv_status plan_hubs(lv_graph* g, const LevelGraph& G, const int32_t* hub_verts, 
     return LV_OK;
 }
 
-lv_status ensure_pinned(lv_graph* g, size_t bytes)
-{
-    if (g->pinned_bytes >= bytes) return LV_OK;
-    if (g->pinned) (void)hipHostFree(g->pinned);
-    g->pinned = nullptr;
-    g->pinned_bytes = 0;
-    HIP_TRY(hipHostMalloc((void**)&g->pinned, bytes, hipHostMallocDefault));
-    g->pinned_bytes = bytes;
-    return LV_OK;
-}
 
 // Synchronous local-moving sweeps of one level (Algorithm 2; Algorithm 1 in
 // LPA mode) for every graph of G.  gactive (device, may be null) marks the
@@ -550,8 +578,7 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
     HIP_TRY(launch_fill_i32(d_start, -1, NUM_CLS + 1, s));
     HIP_TRY(launch_class_starts(cls_sorted, n, d_start, s));
     int32_t start[NUM_CLS + 1];
-    HIP_TRY(hipMemcpyAsync(start, d_start, sizeof start, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    LV_TRY(read_back(g, {{start, d_start, sizeof start}}));
     start[NUM_CLS] = n;
     for (int c = NUM_CLS - 1; c >= 0; --c)
         if (start[c] < 0) start[c] = start[c + 1];
@@ -788,8 +815,7 @@ lv_status renumber(lv_graph* g, const LevelGraph& G, int32_t* n2, std::vector<in
     HIP_TRY(hipMemcpyAsync(ws.gmeta.p, at.data(), sizeof(int32_t) * at.size(), hipMemcpyHostToDevice, s));
     HIP_TRY(launch_gather_i32(pos, ws.gmeta.as<int32_t>(), G.G + 1, ws.gmeta.as<int32_t>(), s));
     voff2.resize(G.G + 1);
-    HIP_TRY(hipMemcpyAsync(voff2.data(), ws.gmeta.p, sizeof(int32_t) * ((size_t)G.G + 1), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    LV_TRY(read_back(g, {{voff2.data(), ws.gmeta.p, sizeof(int32_t) * ((size_t)G.G + 1)}}));
     *n2 = voff2[G.G];
     return LV_OK;
 }
@@ -888,8 +914,7 @@ lv_status aggregate_by_community(lv_graph* g, const LevelGraph& G, int32_t n2, i
     HIP_TRY(launch_fill_i32(d_start, -1, NUM_CLS + 1, s));
     HIP_TRY(launch_class_starts(cls_sorted, n2, d_start, s));
     int32_t start[NUM_CLS + 1];
-    HIP_TRY(hipMemcpyAsync(start, d_start, sizeof start, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    LV_TRY(read_back(g, {{start, d_start, sizeof start}}));
     start[NUM_CLS] = n2;
     for (int c = NUM_CLS - 1; c >= 0; --c)
         if (start[c] < 0) start[c] = start[c + 1];
@@ -920,8 +945,7 @@ lv_status aggregate_by_community(lv_graph* g, const LevelGraph& G, int32_t n2, i
         HIP_TRY(launch_long_lengths(nh, hv, seg, hoff, s));
         HIP_TRY(scan_exclusive_i32(hoff, hoff, nh, hoff + nh, ws.tmp.p, ws.tmp.cap, s));
         int32_t eh = 0;
-        HIP_TRY(hipMemcpyAsync(&eh, hoff + nh, sizeof eh, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
+        LV_TRY(read_back(g, {{&eh, hoff + nh, sizeof eh}}));
         HIP_TRY(ws.h_keys.ensure(sizeof(uint64_t) * (size_t)std::max(eh, 1)));
         HIP_TRY(ws.h_keys_alt.ensure(sizeof(uint64_t) * (size_t)std::max(eh, 1)));
         HIP_TRY(ws.tmp.ensure(std::max(radix_tmp_bytes(eh), scan_tmp_bytes(eh, 8))));
@@ -937,8 +961,7 @@ lv_status aggregate_by_community(lv_graph* g, const LevelGraph& G, int32_t n2, i
         HIP_TRY(launch_segment_heads(ks, eh, ws.head.as<int32_t>(), s));
         HIP_TRY(scan_exclusive_i32(ws.head.as<int32_t>(), ws.head.as<int32_t>(), eh, d_eu, ws.tmp.p, ws.tmp.cap, s));
         int32_t eu = 0;
-        HIP_TRY(hipMemcpyAsync(&eu, d_eu, sizeof eu, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
+        LV_TRY(read_back(g, {{&eu, d_eu, sizeof eu}}));
         HIP_TRY(ws.h_col.ensure(sizeof(int32_t) * (size_t)std::max(eu, 1)));
         HIP_TRY(ws.h_wt.ensure(sizeof(int32_t) * (size_t)std::max(eu, 1)));
         HIP_TRY(ws.a_uoff.ensure(sizeof(int32_t) * ((size_t)n2 + 1)));
@@ -955,8 +978,7 @@ lv_status aggregate_by_community(lv_graph* g, const LevelGraph& G, int32_t n2, i
     if (n2 > 0) HIP_TRY(scan_exclusive_i32(cnt, off2, n2, off2 + n2, ws.tmp.p, ws.tmp.cap, s));
     else HIP_TRY(launch_fill_i32(off2, 0, 1, s));
     int32_t e2 = 0;
-    HIP_TRY(hipMemcpyAsync(&e2, off2 + n2, sizeof e2, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    LV_TRY(read_back(g, {{&e2, off2 + n2, sizeof e2}}));
     HIP_TRY(ws.g_idx[slot].ensure(sizeof(int32_t) * (size_t)std::max(e2, 1)));
     HIP_TRY(ws.g_w[slot].ensure(sizeof(int32_t) * (size_t)std::max(e2, 1)));
     HIP_TRY(launch_pack_rows(n2, off2, e2, seg, col2, wt2, ws.g_idx[slot].as<int32_t>(), ws.g_w[slot].as<int32_t>(),
@@ -1075,8 +1097,7 @@ lv_status graph_entry_offsets(lv_graph* g, const int32_t* off, const std::vector
     HIP_TRY(hipMemcpyAsync(ws.gmeta.p, voff.data(), sizeof(int32_t) * (size_t)m, hipMemcpyHostToDevice, s));
     HIP_TRY(launch_gather_i32(off, ws.gmeta.as<int32_t>(), m, ws.gmeta.as<int32_t>(), s));
     std::vector<int32_t> e(m);
-    HIP_TRY(hipMemcpyAsync(e.data(), ws.gmeta.p, sizeof(int32_t) * (size_t)m, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    LV_TRY(read_back(g, {{e.data(), ws.gmeta.p, sizeof(int32_t) * (size_t)m}}));
     eoff.assign(e.begin(), e.end());
     return LV_OK;
 }
@@ -1260,8 +1281,7 @@ lv_status degree_order(lv_graph* g, int32_t n, int64_t nnz, const int32_t* off, 
     HIP_TRY(hipMemsetAsync(d_max, 0, sizeof(int32_t), s));
     HIP_TRY(launch_max_degree(n, off, d_max, s));
     int32_t maxdeg = 0;
-    HIP_TRY(hipMemcpyAsync(&maxdeg, d_max, sizeof maxdeg, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    LV_TRY(read_back(g, {{&maxdeg, d_max, sizeof maxdeg}}));
     const int db = bits_for((int64_t)maxdeg + 1);
     const int bits = db + (G > 1 ? bits_for(G) : 0);
     const size_t nb = sizeof(int32_t) * (size_t)n;
