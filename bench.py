@@ -534,6 +534,13 @@ def main():
                       "local_move": round(gteps, 3), "frac": round(gteps * 1e9 / ceiling, 4) if ceiling > 0 else None,
                       "probe": "lv_probe_gather: stream the stored column indices, gather one 8-byte pair each"}
     log(f"gather ceiling: {gather_ceiling}")
+    # a STREAM-style copy of the index array with the library's probe kernel:
+    # the measured bandwidth beside the 8 TB/s peak
+    copy_bps = lvp.probe_copy(dg, reps=5)
+    stream_copy = {"gbs": round(copy_bps / 1e9, 1), "frac_of_peak": round(copy_bps / 8.0e12, 4),
+                   "dominant_kernel_frac": round(float(achieved) * 1e9 / copy_bps, 4) if copy_bps > 0 else None,
+                   "probe": "lv_probe_copy: 16-byte copy of the stored column indices, bytes read + written"}
+    log(f"stream copy: {stream_copy}")
     pruned = prune_leg(args, lvp, dg, runs, phases, K, torch) if args.prune_reps > 0 else None
     asynchronous = async_leg(args, lvp, dg, runs, phases, K, torch) if args.async_reps > 0 else None
     edges = None if args.no_edges_leg else edges_leg(args, lvp, graphgen, g, np, torch)
@@ -605,7 +612,7 @@ def main():
                      "traffic": measured_traffic(lvp.KERNEL_NAMES[dom]) if args.scale == 24 else None,
                      "kernel": lvp.KERNEL_NAMES[dom], "avg_launch_ms": round(float(avg_launch_ms), 4),
                      "bytes_per_launch": int(bytes_per_launch)},
-        "gather_ceiling": gather_ceiling,
+        "gather_ceiling": gather_ceiling, "stream_copy": stream_copy,
         "cpu_baseline": cpu,
         "parity": parity,
         "louvain": {"levels": len(r0.accepted), "q": r0.q, "q_int": r0.q_int, "M": r0.M,

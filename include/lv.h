@@ -324,6 +324,15 @@ lv_status lv_lpa_batch(lv_graph* g, const lv_params* params, int32_t* labels, lv
  * pairs arrive one cache line at a time.  Allocates and frees the table.
  */
 lv_status lv_probe_gather(lv_graph* g, int32_t reps, double* entries_per_s);
+/*
+ * Diagnostic: a STREAM-style copy on the handle's device, the measured
+ * bandwidth the HBM roofline is set against.  Copies the handle's stored
+ * column indices (nnz int32) into a scratch buffer of the same size with
+ * 16-byte loads and stores, `reps` times (HIP events on the handle's
+ * stream); *bytes_per_s receives bytes read plus written per second (0 for
+ * a handle without entries).  Allocates and frees the scratch buffer.
+ */
+lv_status lv_probe_copy(lv_graph* g, int32_t reps, double* bytes_per_s);
 
 /* Modularity (Section II-C) of any labels int32[n] with values in [0, n). */
 lv_status lv_modularity(lv_graph* g, const int32_t* labels, lv_memkind kind, int64_t* q_int,

@@ -151,6 +151,7 @@ SIGNATURES = {
                                              ctypes.c_uint32, _vp, ctypes.POINTER(_vp)]),
     "lv_graph_csr": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i64p, ctypes.c_int]),
     "lv_probe_gather": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
+    "lv_probe_copy": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
 }
 
 _lib = None
@@ -535,6 +536,13 @@ def probe_gather(graph: Graph, reps: int = 5) -> float:
     """lv_probe_gather: the handle's pure-gather ceiling in entries per second."""
     out = ctypes.c_double()
     _check(load_library().lv_probe_gather(graph.handle, int(reps), ctypes.byref(out)), "lv_probe_gather")
+    return out.value
+
+
+def probe_copy(graph: Graph, reps: int = 5) -> float:
+    """lv_probe_copy: a STREAM-style copy of the handle's index array, bytes read plus written per second."""
+    out = ctypes.c_double()
+    _check(load_library().lv_probe_copy(graph.handle, int(reps), ctypes.byref(out)), "lv_probe_copy")
     return out.value
 
 

@@ -2262,6 +2262,28 @@ lv_status lv_probe_gather(lv_graph* g, int32_t reps, double* entries_per_s)
     return LV_OK;
 }
 
+lv_status lv_probe_copy(lv_graph* g, int32_t reps, double* bytes_per_s)
+{
+    if (!g || reps < 1 || !bytes_per_s) { set_error_msg("lv_probe_copy: null graph/out or reps < 1"); return LV_E_ARG; }
+    hipStream_t s = g->stream;
+    const int64_t n = g->nnz;
+    if (n <= 0) { *bytes_per_s = 0.0; return LV_OK; }
+    DevBuf dst;
+    HIP_TRY(dst.ensure(sizeof(int32_t) * (size_t)n));
+    const int32_t* src = g->idx.as<int32_t>();
+    HIP_TRY(launch_probe_copy(src, dst.as<int32_t>(), n, s));  // warm-up
+    Timer t;
+    t.s = s;
+    hipEvent_t e0{}, e1{};
+    HIP_TRY(t.mark(&e0));
+    for (int32_t r = 0; r < reps; ++r) HIP_TRY(launch_probe_copy(src, dst.as<int32_t>(), n, s));
+    HIP_TRY(t.mark(&e1));
+    HIP_TRY(hipStreamSynchronize(s));
+    const double ms = elapsed(e0, e1) / reps;
+    *bytes_per_s = ms > 0 ? 2.0 * sizeof(int32_t) * (double)n / (ms * 1e-3) : 0.0;
+    return LV_OK;
+}
+
 lv_status lv_modularity(lv_graph* g, const int32_t* labels, lv_memkind kind, int64_t* q_int, int64_t* m, double* q)
 {
     if (!g || !labels || (kind != LV_MEM_HOST && kind != LV_MEM_DEVICE)) return LV_E_ARG;

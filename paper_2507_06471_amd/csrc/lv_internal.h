@@ -224,6 +224,8 @@ hipError_t launch_hub_sweep(bool singleton, const MoveArgs& a, const HubArgs& h,
 // number for every mover and every neighbour of a mover (rows: the m listed
 // vertices below the hub class; the hubs through their mark chunks).
 // Gather probe (see lv_probe_gather): stream idx[0, nnz) and gather tab[idx[e]].
+// dst[0..n) = src[0..n) with 16-byte accesses (src, dst 16-byte aligned)
+hipError_t launch_probe_copy(const int32_t* src, int32_t* dst, int64_t n, hipStream_t s);
 hipError_t launch_probe_gather(const int32_t* idx, const int2* tab, int64_t nnz, unsigned long long* sink, hipStream_t s);
 hipError_t launch_mark_movers(const int4* rows, const int32_t* dec, int32_t m, const int32_t* idx, int32_t* mark,
                               const SweepCtl* ctl, hipStream_t s);

@@ -162,3 +162,20 @@ def test_gather_probe_reports_a_rate():
     with pytest.raises(lvp.LvError):
         with lvp.Graph.from_csr(g) as dg:
             lvp.probe_gather(dg, reps=0)
+
+
+def test_copy_probe_reports_a_bandwidth():
+    g = graphgen.rmat(15, seed=4)
+    with lvp.Graph.from_csr(g) as dg:
+        rate = lvp.probe_copy(dg, reps=2)
+        empty = lvp.Graph.from_csr(graphgen.CSR(3, np.zeros(4, np.int32), np.zeros(0, np.int32), None))
+        try:
+            zero = lvp.probe_copy(empty, reps=1)
+        finally:
+            empty.close()
+    say(f"copy probe on R-MAT 15 ({g.nnz} entries): {rate / 1e9:.1f} GB/s")
+    assert np.isfinite(rate) and 0 < rate < 20e12
+    assert zero == 0.0
+    with pytest.raises(lvp.LvError):
+        with lvp.Graph.from_csr(g) as dg:
+            lvp.probe_copy(dg, reps=0)
