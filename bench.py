@@ -18,11 +18,24 @@ Printed JSON line (one):
               (HIP events around each level's sweep loop)
   roofline    the dominant move kernel, from one instrumented step after the
               timed region (kernels one at a time, HIP events around each on
-              the library's stream): algorithmic bytes per launch / average
-              launch duration; traffic from the stored rocprofv3 counters
-  cpu_baseline  the CPU oracle, unmodified, timed on this host over a bounded
-              sample: level-0 synchronous sweeps over the full graph
-  parity      the GPU's first-sweep partition equals the oracle's, bit for bit
+              the library's stream): compulsory bytes per launch (8 per CSR
+              entry + 36 per vertex of its class) / average launch duration;
+              traffic from the stored rocprofv3 counters.  Beside it the
+              local-moving phase as a whole: level0_frac and all_levels_frac
+              = compulsory bytes of the sweeps (8E + 36n per sweep of a level
+              with n vertices and E entries) / the timed steps' sweep time /
+              8 TB/s, with the per-level figures in `levels`
+  cpu_baseline  the CPU oracle, unmodified, timed on this host: one warm-up
+              and five timed repetitions (median and mean) of level-0 sweeps
+              over the full graph, and per-phase (local moving, renumbering,
+              aggregation) Louvain runs of the small SBM configuration and a
+              sample of the batch graphs on all host threads and on one
+  parity      every level of the timed runs equals the oracle's per-level
+              digests (tests/golden/rmat24_seed2_digests.json): sizes, Q_int,
+              per-sweep move counts, SHA-256 of the final labels; the GPU's
+              first-sweep partition equals the oracle's, bit for bit
+  workloads   the small SBM (4,096 vertices) and the 10 M-vertex LFR graph:
+              time per step and local-move rate
   batch       4,096 mixed graphs in one packed handle vs one graph per call
   serving     a Poisson trace of Louvain jobs: continuous batching vs FIFO one
               graph per call, throughput and p50/p99 latency
@@ -40,6 +53,51 @@ sys.path.insert(0, ROOT)
 
 METRIC = "local-move GTEPS + %HBM roofline at exact partitions; batched p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
+GOLDEN = os.path.join(ROOT, "tests", "golden", "rmat24_seed2_digests.json")
+# the paper's own local-moving times (context, not the target): Section V-B,
+# strong scaling on com-livejournal (3,997,962 vertices, 34,681,189 edges)
+PAPER_CONTEXT = {
+    "local_move_s": {"2_threads": 16.8, "128_threads": 2.4},
+    "louvain_total_s": {"2_threads": 25.6, "128_threads": 5.6},
+    "hardware": "2 x AMD EPYC 7763 (128 cores), 512 GB, Chapel/Arachne",
+    "workload": "com-livejournal, 3,997,962 vertices, 34,681,189 edges, all levels",
+    "source": "Section V-B (strong scaling) and Section IV-B (setup)",
+    "note": "different graph and hardware; quoted as context only",
+}
+
+
+def sha256_i32(*arrays) -> str:
+    import hashlib
+
+    import numpy as np
+
+    h = hashlib.sha256()
+    for a in arrays:
+        h.update(np.ascontiguousarray(a, dtype="<i4").tobytes())
+    return h.hexdigest()
+
+
+def level_roofline(runs, peak_gbs=HBM_PEAK_GBS):
+    """Compulsory-bytes roofline of local moving per level of the timed steps:
+    a sweep over a level with n vertices and E entries touches 8E + 36n bytes
+    (indices and weights; offsets, label, degree and volume read, label and
+    volume written per vertex), sweep time from the HIP events around each
+    level's sweeps, averaged over the steps."""
+    K = len(runs)
+    levels = []
+    for lvl, lv in enumerate(runs[0][0].levels):
+        i = lv.info
+        ms = sum(r.levels[lvl].info["sweep_ms"] for r, _ in runs) / K
+        b = 8 * i["nnz"] + 36 * i["n"]
+        sw = i["sweeps"]
+        levels.append({"level": lvl, "n": i["n"], "nnz": i["nnz"], "sweeps": sw,
+                       "cached_sweeps": i["cached_sweeps"], "refreshed_entries": i["refreshed_entries"],
+                       "sweep_ms": round(ms, 3), "ms_per_sweep": round(ms / max(sw, 1), 4),
+                       "bytes_per_sweep": b,
+                       "frac": round(b * sw / (ms * 1e-3) / (peak_gbs * 1e9), 4) if ms > 0 else None})
+    tot_b = sum(x["bytes_per_sweep"] * x["sweeps"] for x in levels)
+    tot_ms = sum(x["sweep_ms"] for x in levels)
+    return levels, (tot_b / (tot_ms * 1e-3) / (peak_gbs * 1e9) if tot_ms > 0 else None)
 
 
 def log(*a):
@@ -385,6 +443,142 @@ def serving_leg(args, lvp, graphgen, np, torch):
     return out
 
 
+def golden_check(args, r, lp, g):
+    """Every level of a timed run against the oracle's per-level digests of
+    the benchmark graph (written by tests/golden/make_rmat24_digests.py from
+    the oracle alone).  Exits on a mismatch; None for other graphs."""
+    import json
+
+    if (args.scale, args.edge_factor, args.seed) != (24, 16.0, 2) or not os.path.exists(GOLDEN):
+        return None
+    with open(GOLDEN) as fh:
+        gold = json.load(fh)
+    want = gold["louvain"]
+    bad = []
+    if (g.n, g.nnz) != (gold["n"], gold["nnz"]):
+        bad.append("graph size")
+    if len(r.levels) != len(want["levels"]):
+        bad.append("number of levels")
+    for lvl, (a, b) in enumerate(zip(r.levels, want["levels"])):
+        i = a.info
+        if (i["n"], i["nnz"], i["n_next"], i["q_start"], i["q_end"], bool(i["accepted"])) != \
+                (b["n"], b["nnz"], b["n_next"], b["q_start"], b["q_end"], b["accepted"]):
+            bad.append(f"level {lvl} sizes or Q_int")
+        if a.moves != b["moves"]:
+            bad.append(f"level {lvl} moves")
+    if (r.M, r.q_int) != (want["M"], want["q_int"]) or sha256_i32(r.final_labels) != want["final_labels_sha256"]:
+        bad.append("final labels or Q_int")
+    if lp.moves != gold["lpa"]["moves"] or sha256_i32(lp.labels) != gold["lpa"]["labels_sha256"]:
+        bad.append("LPA")
+    out = {"equal": not bad, "levels": len(want["levels"]), "file": "tests/golden/rmat24_seed2_digests.json",
+           "checked": "per level n, nnz, n_next, Q_start, Q_end, acceptance, per-sweep moves; final labels "
+                      "(SHA-256), Q_int, M; LPA moves and labels (SHA-256)"}
+    log(f"golden digests: {out}")
+    if bad:
+        print(f"timed run differs from the oracle's digests: {bad}", file=sys.stderr, flush=True)
+        sys.exit(1)
+    return out
+
+
+def cpu_baseline(args, oracle, adj, g, graphgen, np):
+    """The CPU oracle as it stands, on this host's cores: one warm-up and
+    `cpu_reps` timed repetitions of `cpu_sweeps` level-0 sweeps over the full
+    benchmark graph (median and mean), and whole Louvain runs with the paper's
+    phases timed apart on the small SBM configuration and a sample of the
+    batch graphs, on all threads and on one (one warm-up, five repetitions)."""
+    def reps(fn, n):
+        fn()
+        ts = []
+        for _ in range(n):
+            t = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t)
+        return float(np.median(ts)), float(np.mean(ts))
+
+    threads = oracle.num_threads()
+    sweeps = max(1, args.cpu_sweeps)
+    med, mean = reps(lambda: oracle.local_move(adj, oracle.LOUVAIN, max_sweeps=sweeps), args.cpu_reps)
+    out = {"value": round(sweeps * g.nnz / med / 1e9, 4), "unit": "GTEPS", "cores": threads, "kind": "oracle",
+           "host_nproc": os.cpu_count(),
+           "sample": f"{sweeps} level-0 synchronous Louvain sweeps of the CPU oracle over the full graph "
+                     f"({sweeps * g.nnz} entries per repetition), 1 warm-up + {args.cpu_reps} repetitions, "
+                     f"median {med:.2f} s, mean {mean:.2f} s",
+           "median_s": round(med, 3), "mean_s": round(mean, 3)}
+
+    def phases(graphs, threads_):
+        oracle.set_threads(threads_)
+        pts = []
+
+        def run():
+            pt = {}
+            for x in graphs:
+                oracle.louvain(x, phase_times=pt)
+            pts.append(pt)
+        med_, mean_ = reps(run, 5)
+        keys = ("local_move", "renumber", "aggregate", "other")
+        ph = {k: round(float(np.median([p[k] for p in pts[1:]])) * 1e3, 3) for k in keys}
+        return {"threads": threads_, "ms_median": round(med_ * 1e3, 3), "ms_mean": round(mean_ * 1e3, 3),
+                "phase_ms_median": ph}
+
+    sbm = graphgen.sbm(4096, 128, 0.05, 0.0005, seed=1)
+    sample = graphgen.batch_mix(args.cpu_batch_sample, seed=4)
+    try:
+        out["phases"] = {
+            "sbm_4096": {"all_threads": phases([sbm], threads), "one_thread": phases([sbm], 1)},
+            "batch_sample": {"graphs": len(sample), "entries": int(sum(x.nnz for x in sample)),
+                             "all_threads": phases(sample, threads), "one_thread": phases(sample, 1)},
+        }
+    finally:
+        oracle.set_threads(threads)
+    log(f"cpu baseline: {out}")
+    return out
+
+
+def workloads_leg(args, lvp, graphgen, np, torch):
+    """The other single-graph configurations: the 4,096-vertex SBM (Louvain)
+    and the LFR-style graph (Louvain and LPA), each device-resident before
+    timing; local-move rate from the levels' sweep events."""
+    out = {}
+
+    def run(name, g, lpa, reps):
+        with lvp.Graph.from_csr(g, validate=False) as dg:
+            def step():
+                r = lvp.louvain(dg, level_labels=False)
+                lp = lvp.lpa(dg) if lpa else None
+                return r, lp
+            step()
+            torch.cuda.synchronize()
+            res, t0 = [], time.perf_counter()
+            for _ in range(reps):
+                res.append(step())
+            torch.cuda.synchronize()
+            wall = (time.perf_counter() - t0) / reps
+        r = res[0][0]
+        e = sum(lv.info["nnz"] * lv.info["sweeps"] for rr, _ in res for lv in rr.levels)
+        ms = sum(lv.info["sweep_ms"] for rr, _ in res for lv in rr.levels)
+        d = {"n": g.n, "nnz": g.nnz, "ms_per_step": round(wall * 1e3, 3), "levels": len(r.accepted), "q": r.q,
+             "local_move_ms": round(ms / reps, 3), "local_move_gteps": round(e / (ms * 1e-3) / 1e9, 3) if ms else None,
+             "sweeps_per_level": [lv.info["sweeps"] for lv in r.levels],
+             "cached_sweeps_per_level": [lv.info["cached_sweeps"] for lv in r.levels],
+             "step": "Louvain, all levels" + (" + LPA" if lpa else "")}
+        if lpa:
+            lms = sum(lp.info["sweep_ms"] for _, lp in res) / reps
+            d["lpa_ms"] = round(lms, 3)
+            d["lpa_sweeps"] = res[0][1].info["sweeps"]
+        log(f"workload {name}: {d}")
+        return d
+
+    out["sbm_4096"] = run("sbm_4096", graphgen.sbm(4096, 128, 0.05, 0.0005, seed=1), False, 20)
+    t = time.time()
+    g, _ = graphgen.lfr(args.lfr_n, seed=3)
+    log(f"LFR n={g.n} nnz={g.nnz} generated in {time.time() - t:.1f}s")
+    out["lfr"] = run("lfr", g, True, 3)
+    out["lfr"]["workload"] = (f"LFR-style, n={g.n}, degree exponent 2.5, mean degree 20, max degree 5,000, "
+                              "community sizes 50-20,000 (exponent 1.5), mixing 0.3, weights 1..8, seed 3")
+    del g
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -393,7 +587,11 @@ def main():
     ap.add_argument("--scale", type=int, default=24)
     ap.add_argument("--edge-factor", type=float, default=16.0)
     ap.add_argument("--seed", type=int, default=2)
-    ap.add_argument("--cpu-sweeps", type=int, default=2, help="oracle sweeps timed for cpu_baseline")
+    ap.add_argument("--cpu-sweeps", type=int, default=2, help="oracle sweeps per timed cpu_baseline repetition")
+    ap.add_argument("--cpu-reps", type=int, default=5, help="timed cpu_baseline repetitions (after one warm-up)")
+    ap.add_argument("--cpu-batch-sample", type=int, default=8, help="batch graphs in the per-phase CPU sample")
+    ap.add_argument("--no-workloads", action="store_true", help="skip the SBM and LFR legs")
+    ap.add_argument("--lfr-n", type=int, default=10_000_000, help="vertices of the LFR leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--batch-graphs", type=int, default=4096, help="graphs in the batch leg (0: skip it)")
@@ -479,6 +677,7 @@ def main():
     del outs
     for r, lp in runs[1:]:
         assert np.array_equal(r.final_labels, runs[0][0].final_labels) and np.array_equal(lp.labels, runs[0][1].labels)
+    golden = golden_check(args, runs[0][0], runs[0][1], g)
 
     # local-move throughput from the phase events of the timed steps
     lm_edges = lm_ms = lpa_edges = lpa_ms = 0.0
@@ -509,8 +708,13 @@ def main():
     assert ri.q_int == runs[0][0].q_int and np.array_equal(ri.final_labels, runs[0][0].final_labels)
     gteps = lm_edges / (lm_ms * 1e-3) / 1e9 if lm_ms > 0 else 0.0
     lpa_gteps = lpa_edges / (lpa_ms * 1e-3) / 1e9 if lpa_ms > 0 else 0.0
-    # dominant kernel: the longest-running single kernel that reads the graph
-    # (the hub partition slot reads only the scatter pass's buckets)
+    levels, all_frac = level_roofline(runs)
+    lpa0 = runs[0][1].info
+    lpa_b = (8 * lpa0["nnz"] + 12 * lpa0["n"]) * lpa0["sweeps"]
+    lpa_frac = lpa_b / (lpa_ms / K * 1e-3) / (HBM_PEAK_GBS * 1e9) if lpa_ms > 0 else None
+    # dominant kernel: the longest-running single move kernel that reads the
+    # graph (the hub partition slot reads only the scatter pass's buckets; the
+    # commit and cache-refresh slots carry no compulsory bytes)
     dom = int(np.argmax(np.where(kern_bytes > 0, kern_ms, -1.0)))
     avg_launch_ms = kern_ms[dom] / max(1, kern_launches[dom])
     bytes_per_launch = kern_bytes[dom] / max(1, kern_launches[dom])
@@ -551,42 +755,28 @@ def main():
         import oracle
 
         adj = oracle.adjacency(g)
-        k, M = oracle.degrees(adj)
-        c = np.arange(g.n, dtype=np.int32)
-        sigma = k.copy()
-        sweeps_done = 0
-        t = time.perf_counter()
-        first = None
-        for s_ in range(1, max(1, args.cpu_sweeps) + 1):
-            c, mv = oracle.sweep(adj, c, sigma, oracle.DOWN if s_ % 2 else oracle.UP)
-            sigma = np.bincount(c, weights=k, minlength=g.n).astype(np.int64)
-            sweeps_done += 1
-            if first is None:
-                first = (c.copy(), mv)
-        cpu_s = time.perf_counter() - t
-        cpu = {"value": round(sweeps_done * g.nnz / cpu_s / 1e9, 4), "unit": "GTEPS",
-               "cores": oracle.num_threads(), "kind": "oracle",
-               "sample": f"{sweeps_done} level-0 synchronous sweeps of the CPU oracle over the full graph "
-                         f"({sweeps_done * g.nnz} entries, {cpu_s:.1f}s, includes Sigma_tot recomputation)"}
-        log(f"cpu baseline: {cpu}")
+        if not args.no_cpu_baseline:
+            cpu = cpu_baseline(args, oracle, adj, g, graphgen, np)
         if not args.no_parity:
             # GPU first sweep (one sweep, one level) vs the oracle's first sweep, renumbered
+            c1, mv1 = oracle.local_move(adj, oracle.LOUVAIN, max_sweeps=1)
             r1 = lvp.louvain(dg, max_sweeps=1, max_levels=1)
-            want_lab, _ = oracle.renumber(first[0])
+            want_lab, _ = oracle.renumber(c1)
             got_lab = r1.levels[0].labels if r1.levels[0].info["accepted"] else None
-            ok = got_lab is not None and np.array_equal(got_lab, want_lab) and r1.levels[0].moves[0] == first[1]
-            parity = {"first_sweep_partition_equal": bool(ok), "first_sweep_moves": int(first[1]),
-                      "labels_checked": int(g.n)}
+            ok = got_lab is not None and np.array_equal(got_lab, want_lab) and r1.levels[0].moves[0] == int(mv1[0])
+            parity = {"first_sweep_partition_equal": bool(ok), "first_sweep_moves": int(mv1[0]),
+                      "labels_checked": int(g.n),
+                      "all_levels_equal_to_golden_digests": None if golden is None else golden["equal"]}
             log(f"parity: {parity}")
             if not ok:
                 print("first-sweep partition differs from the oracle", file=sys.stderr, flush=True)
                 sys.exit(1)
+        del adj
 
     dg.close()
     gn, gnnz = g.n, g.nnz
     del g
-    if not args.no_cpu_baseline or not args.no_parity:
-        del adj, k, c, sigma
+    workloads = None if args.no_workloads else workloads_leg(args, lvp, graphgen, np, torch)
     batch = batch_leg(args, lvp, graphgen, np, torch) if args.batch_graphs > 0 else None
     serving = serving_leg(args, lvp, graphgen, np, torch) if args.serve_jobs > 0 else None
 
@@ -611,10 +801,20 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(lvp.KERNEL_NAMES[dom]) if args.scale == 24 else None,
                      "kernel": lvp.KERNEL_NAMES[dom], "avg_launch_ms": round(float(avg_launch_ms), 4),
-                     "bytes_per_launch": int(bytes_per_launch)},
+                     "bytes_per_launch": int(bytes_per_launch),
+                     "bytes_model": "8 per CSR entry + 36 per vertex of the kernel's rows (per launch)",
+                     "level0_frac": levels[0]["frac"] if levels else None,
+                     "all_levels_frac": round(all_frac, 4) if all_frac is not None else None,
+                     "lpa_frac": round(lpa_frac, 4) if lpa_frac is not None else None,
+                     "level0_ms_per_sweep": levels[0]["ms_per_sweep"] if levels else None,
+                     "sweep_bytes_model": "8E + 36n per sweep (LPA: 8E + 12n)",
+                     "levels": levels},
         "gather_ceiling": gather_ceiling, "stream_copy": stream_copy,
         "cpu_baseline": cpu,
+        "paper_context": PAPER_CONTEXT,
         "parity": parity,
+        "golden": golden,
+        "workloads": workloads,
         "louvain": {"levels": len(r0.accepted), "q": r0.q, "q_int": r0.q_int, "M": r0.M,
                     "sweeps_per_level": [lv.info["sweeps"] for lv in r0.levels],
                     "n_per_level": [lv.info["n"] for lv in r0.levels],

@@ -20,8 +20,9 @@
  *   - a level ends after two consecutive sweeps with no move (LPA: with at
  *     most lpa_threshold moves) or after max_sweeps sweeps;
  *   - communities are renumbered by their smallest member vertex id;
- *   - a Louvain level is kept only if it raises modularity (Section III-B,
- *     "until no further improvement"), at most max_levels levels.
+ *   - a Louvain level is kept only if it raises modularity (Section III-B;
+ *     Algorithm 3 stops once a level brings no gain), at most max_levels
+ *     levels.
  * Every decision is integer arithmetic (int64 products of values < 2^31), so
  * results do not depend on tuning, scheduling or batching.
  *
@@ -52,7 +53,8 @@ typedef enum lv_status {
                             range, or a row not strictly increasing                   */
     LV_E_ASYMMETRIC = 3, /* entry (i,j,w) without a matching (j,i,w)                  */
     LV_E_WEIGHT = 4,     /* a weight < 1                                              */
-    LV_E_OVERFLOW = 5,   /* total volume M = sum_i k_i >= 2^31, or nnz >= 2^31        */
+    LV_E_OVERFLOW = 5,   /* total volume M = sum_i k_i >= 2^31, or more than
+                            LV_MAX_NNZ CSR entries (one graph or a packed set)        */
     LV_E_NOMEM = 6,      /* device allocation failed; the handle stays usable         */
     LV_E_HIP = 7,        /* a HIP runtime call failed                                 */
     LV_E_BUSY = 8,       /* server queue full                                         */
@@ -64,12 +66,20 @@ typedef enum lv_status {
 
 typedef enum lv_memkind { LV_MEM_HOST = 0, LV_MEM_DEVICE = 1 } lv_memkind;
 
+/* Largest number of CSR entries a handle (one graph, or all graphs packed in
+ * one handle or one server step) may hold: 2^31 - 1 - 2^16.  Row loops step
+ * 32-bit entry counters by up to 2^13 past a row's end; the margin keeps every
+ * such counter below 2^31. */
+#define LV_MAX_NNZ (2147483647 - 65536)
+
 /* lv_graph_create_csr flags */
 #define LV_VALIDATE 1u /* check CSR shape, sortedness, symmetry and weights on the device */
 #define LV_KEEP_ORDER 2u  /* create: store the vertices in input order (default: by descending    */
                           /* degree within each graph, for cache locality; results are the same)  */
 #define LV_EDGES_NO_LOOPS 4u /* lv_graph_create_edges: drop loops (u, u)                          */
 #define LV_EDGES_SIMPLE 8u   /* lv_graph_create_edges: a pair listed several times keeps weight 1 */
+#define LV_NO_ENTRY_CACHE 16u /* create: skip the reverse-entry map (int32 per CSR entry); calls on  */
+                              /* the handle then never use the entry cache (see LV_NO_CACHE)         */
                              /* (no weights may be given)                                        */
 
 /* lv_params.flags */
@@ -91,6 +101,14 @@ typedef enum lv_memkind { LV_MEM_HOST = 0, LV_MEM_DEVICE = 1 } lv_memkind;
                           /* scheduling and are not reproducible; every invariant (Sigma_tot sums */
                           /* to M, exact Q_int of the returned labels, level acceptance) holds.  */
                           /* With LV_PRUNE the active set looks one sweep back (Alg. 2).          */
+#define LV_NO_CACHE 64u   /* do not use the entry cache.  By default the sweeps of a handle's input */
+                          /* graph (Louvain's first level, LPA) keep each CSR entry's neighbour     */
+                          /* (community, volume) pair in an int2[nnz] device array once few pairs   */
+                          /* change between sweeps, rewriting after each commit only the entries    */
+                          /* whose pair changed; a sweep then streams the array instead of gathering */
+                          /* one pair per entry at random.  Results are identical either way.       */
+                          /* Needs the handle's reverse-entry map (not LV_NO_ENTRY_CACHE); off with */
+                          /* LV_PRUNE and LV_ASYNC.                                                  */
 
 typedef struct lv_graph lv_graph;   /* device-resident CSR + workspace, library-owned */
 typedef struct lv_result lv_result; /* per-level labels and statistics, library-owned */
@@ -123,6 +141,10 @@ typedef struct lv_tuning {
                         /* level with at most 20 vertices per community (members' rows    */
                         /* laid out by label, each community's entries summed in LDS, the */
                         /* longest sorted), sorting otherwise.  Same coarse graphs.       */
+    int32_t cache_pct;  /* entry cache: the next sweep reads the cache when at most this  */
+                        /* percentage of the level's entries saw their pair change in the */
+                        /* last commit (0 = 10, at most 100); a sweep fills it when at    */
+                        /* most min(100, 2 cache_pct + 5) percent changed                  */
 } lv_tuning;
 
 typedef struct lv_params {
@@ -134,7 +156,7 @@ typedef struct lv_params {
     const lv_tuning* tuning; /* NULL = built-in defaults                                   */
 } lv_params;
 
-#define LV_KERNEL_SLOTS 23
+#define LV_KERNEL_SLOTS 25
 
 /* Per-level statistics; times are milliseconds from HIP events.  sweep_ms,
    renumber_ms and aggregate_ms are always measured (events around each
@@ -153,19 +175,24 @@ typedef struct lv_level_info {
     double renumber_ms;
     double aggregate_ms;
     int64_t move_launches; /* number of move-kernel launches                       */
-    int64_t move_bytes;    /* algorithmic bytes of the move kernels, all sweeps    */
+    int64_t move_bytes;    /* compulsory bytes of the sweeps: (8 nnz + 36 n) each  */
     /* Per move kernel (LV_TIMING): slot 2*(class-1) + (1 for the first sweep
        of a level, where every community is a single vertex); classes 1..10 =
        rows of at most 4, 8, 32, 128, 256, 512, 1024, 2048, 3072 and 8192
        entries (groups of 4 lanes up to 1024-thread workgroups), 11 =
        partition workgroups (with their merge and fallback kernels); slot 22
        = the bucketed mode's scatter pass, which then carries class 11's
-       bytes.  Bytes count each array element a kernel needs once: indices
-       (and weights) of its rows, and 20 bytes per vertex (vertex list, row
-       offset, label, degree, own community volume). */
+       bytes; slot 23 = the commit (labels, volumes, pairs, sweep control);
+       slot 24 = the entry cache's refresh.  Bytes are the compulsory bytes
+       of the kernel's rows: 8 per CSR entry (index and weight) and 36 per
+       vertex (offsets, label, degree and volume read; label and volume
+       written), as for a whole sweep. */
     double kern_ms[LV_KERNEL_SLOTS];
     int64_t kern_launches[LV_KERNEL_SLOTS];
     int64_t kern_bytes[LV_KERNEL_SLOTS];
+    int32_t cached_sweeps;      /* sweeps that read the entry cache (0 without it)        */
+    int32_t reserved;
+    int64_t refreshed_entries;  /* cache entries rewritten after commits, all sweeps      */
 } lv_level_info;
 
 void lv_params_default(lv_params* p);

@@ -299,26 +299,47 @@ class LouvainResult:
         return [lv for lv in self.levels if lv.accepted]
 
 
-def louvain(g, max_sweeps: int = 20, max_levels: int = 32, keep_graphs: bool = False, prune: bool = False):
+def louvain(g, max_sweeps: int = 20, max_levels: int = 32, keep_graphs: bool = False, prune: bool = False,
+            phase_times: Optional[dict] = None):
     """Multi-level Louvain (Alg. 3) under the oracle's deterministic semantics.
 
     Level l: Q_start = Q_int of singletons on G_l; local moving; renumber;
     aggregate to G_{l+1}; Q_end = Q_int of singletons on G_{l+1} (equal to
     Q_int(G_l, labels)).  A level with Q_end <= Q_start is discarded and ends
     the run; otherwise it is accepted and G <- G_{l+1}.
+
+    `phase_times` (a dict, optional) accumulates the wall time in seconds of
+    the phases the paper times apart (Section V-B): "local_move", "renumber"
+    and "aggregate" (the Q_int evaluations go to "other").
     """
+    import time
+
+    pt = phase_times if phase_times is not None else {}
+    for key in ("local_move", "renumber", "aggregate", "other"):
+        pt.setdefault(key, 0.0)
+    t = time.perf_counter()
     adj = adjacency(g)
     n0 = adj.n
     _, M = degrees(adj)
     final = np.arange(n0, dtype=np.int32)
     res = LouvainResult(M=M, q_int=singleton_qint(adj), q=0.0, final_labels=final)
     graphs = [adj]
+    pt["other"] += time.perf_counter() - t
     while True:
+        t0 = time.perf_counter()
         q_start = singleton_qint(adj)
+        t1 = time.perf_counter()
         c, moves = local_move(adj, LOUVAIN, max_sweeps, 0, prune)
+        t2 = time.perf_counter()
         labels, n2 = renumber(c)
+        t3 = time.perf_counter()
         adj2 = aggregate(adj, labels, n2)
+        t4 = time.perf_counter()
         q_end = singleton_qint(adj2)
+        pt["other"] += (t1 - t0) + (time.perf_counter() - t4)
+        pt["local_move"] += t2 - t1
+        pt["renumber"] += t3 - t2
+        pt["aggregate"] += t4 - t3
         accepted = q_end > q_start
         res.levels.append(LevelRecord(adj.n, adj.nnz, q_start, q_end, len(moves), moves, labels, n2,
                                       accepted))

@@ -32,18 +32,21 @@ LV_VALIDATE = 1
 LV_KEEP_ORDER = 2
 LV_EDGES_NO_LOOPS = 4
 LV_EDGES_SIMPLE = 8
+LV_NO_ENTRY_CACHE = 16
 LV_TIMING = 1
 LV_KEEP_GRAPHS = 2
 LV_NO_HIPGRAPH = 4
 LV_AUTOTUNE = 8
 LV_PRUNE = 16
 LV_ASYNC = 32
-KERNEL_SLOTS = 23
-# kernel slot -> name (slot = 2*(class-1) + first-sweep flag; the last slot is
-# the bucketed hub scatter pass, whose partition workgroups are timed as "hub")
+LV_NO_CACHE = 64
+KERNEL_SLOTS = 25
+# kernel slot -> name (slot = 2*(class-1) + first-sweep flag; then the bucketed
+# hub scatter pass, whose partition workgroups are timed as "hub"; the commit
+# with pair refresh and sweep control; the entry cache's refresh)
 KERNEL_NAMES = [f"{c}{'/first' if f else ''}"
                 for c in ("l4", "l8", "l32", "l128", "l256", "l512", "l1k", "l2k", "l3k", "l8k", "hub")
-                for f in (0, 1)] + ["hub/scatter"]
+                for f in (0, 1)] + ["hub/scatter", "commit", "cache/refresh"]
 
 _i32p = ctypes.POINTER(ctypes.c_int32)
 _i64p = ctypes.POINTER(ctypes.c_int64)
@@ -55,7 +58,7 @@ class lv_tuning(ctypes.Structure):
                 ("block_max", ctypes.c_int32), ("part_keys", ctypes.c_int32),
                 ("part_slots", ctypes.c_int32), ("hub_mode", ctypes.c_int32),
                 ("hub_chunk", ctypes.c_int32), ("order_min", ctypes.c_int32),
-                ("agg_sort", ctypes.c_int32)]
+                ("agg_sort", ctypes.c_int32), ("cache_pct", ctypes.c_int32)]
 
 
 class lv_params(ctypes.Structure):
@@ -72,7 +75,8 @@ class lv_level_info(ctypes.Structure):
                 ("renumber_ms", ctypes.c_double), ("aggregate_ms", ctypes.c_double),
                 ("move_launches", ctypes.c_int64), ("move_bytes", ctypes.c_int64),
                 ("kern_ms", ctypes.c_double * KERNEL_SLOTS), ("kern_launches", ctypes.c_int64 * KERNEL_SLOTS),
-                ("kern_bytes", ctypes.c_int64 * KERNEL_SLOTS)]
+                ("kern_bytes", ctypes.c_int64 * KERNEL_SLOTS), ("cached_sweeps", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("refreshed_entries", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         out = {}
@@ -227,7 +231,7 @@ class Graph:
     """Device-resident graph handle (lv_graph_create_csr / lv_graph_destroy)."""
 
     def __init__(self, n: int, offsets, indices, weights=None, validate: bool = True, stream: int = 0,
-                 keep_order: bool = False):
+                 keep_order: bool = False, entry_cache: bool = True):
         lib = load_library()
         po, ko = _ptr(offsets)
         pi, ki = _ptr(indices)
@@ -236,7 +240,8 @@ class Graph:
         if len(kinds) != 1:
             raise ValueError("offsets, indices and weights must live in the same memory")
         h = _vp()
-        flags = (LV_VALIDATE if validate else 0) | (LV_KEEP_ORDER if keep_order else 0)
+        flags = ((LV_VALIDATE if validate else 0) | (LV_KEEP_ORDER if keep_order else 0)
+                 | (0 if entry_cache else LV_NO_ENTRY_CACHE))
         st = lib.lv_graph_create_csr(int(n), po, pi, pw, ko, flags, stream or None, ctypes.byref(h))
         _check(st, "lv_graph_create_csr")
         self._h = h
@@ -249,7 +254,7 @@ class Graph:
         self.sizes = [self.n]
 
     @classmethod
-    def batch(cls, graphs, validate: bool = True, keep_order: bool = False):
+    def batch(cls, graphs, validate: bool = True, keep_order: bool = False, entry_cache: bool = True):
         """Pack several ``graphgen.CSR``-like graphs into one handle
         (lv_graph_create_batch); graph g keeps its own vertex numbering."""
         lib = load_library()
@@ -268,8 +273,8 @@ class Graph:
         h = _vp()
         st = lib.lv_graph_create_batch(cnt, ns.ctypes.data, ctypes.cast(po, _vp), ctypes.cast(pi, _vp),
                                        ctypes.cast(pw, _vp), LV_MEM_HOST,
-                                       (LV_VALIDATE if validate else 0) | (LV_KEEP_ORDER if keep_order else 0), None,
-                                       ctypes.byref(h))
+                                       (LV_VALIDATE if validate else 0) | (LV_KEEP_ORDER if keep_order else 0)
+                                       | (0 if entry_cache else LV_NO_ENTRY_CACHE), None, ctypes.byref(h))
         _check(st, "lv_graph_create_batch")
         self = cls.__new__(cls)
         self._h = h
@@ -282,7 +287,8 @@ class Graph:
         return self
 
     @classmethod
-    def from_csr(cls, g, validate: bool = True, device: bool = False, keep_order: bool = False):
+    def from_csr(cls, g, validate: bool = True, device: bool = False, keep_order: bool = False,
+                 entry_cache: bool = True):
         """From a ``graphgen.CSR``-like object (n, offsets, indices, weights)."""
         off = np.ascontiguousarray(g.offsets, dtype=np.int32)
         idx = np.ascontiguousarray(g.indices, dtype=np.int32)
@@ -293,11 +299,11 @@ class Graph:
             off, idx = torch.from_numpy(off).cuda(), torch.from_numpy(idx).cuda()
             w = None if w is None else torch.from_numpy(w).cuda()
             torch.cuda.synchronize()
-        return cls(g.n, off, idx, w, validate=validate, keep_order=keep_order)
+        return cls(g.n, off, idx, w, validate=validate, keep_order=keep_order, entry_cache=entry_cache)
 
     @classmethod
     def from_edges(cls, n: int, src, dst, weights=None, drop_loops: bool = False, simple: bool = False,
-                   keep_order: bool = False):
+                   keep_order: bool = False, entry_cache: bool = True):
         """lv_graph_create_edges: an undirected edge list (numpy or torch
         int32, all in the same memory), built into a CSR on the device."""
         lib = load_library()
@@ -313,7 +319,7 @@ class Graph:
             raise ValueError("src, dst and weights must live in the same memory")
         m = int(src.shape[0])
         flags = ((LV_EDGES_NO_LOOPS if drop_loops else 0) | (LV_EDGES_SIMPLE if simple else 0)
-                 | (LV_KEEP_ORDER if keep_order else 0))
+                 | (LV_KEEP_ORDER if keep_order else 0) | (0 if entry_cache else LV_NO_ENTRY_CACHE))
         h = _vp()
         _check(lib.lv_graph_create_edges(int(n), m, ps, pd, pw, ks, flags, None, ctypes.byref(h)),
                "lv_graph_create_edges")
@@ -389,12 +395,14 @@ class FinalPartition:
 
 
 def louvain_final(graph: Graph, max_sweeps: int = 20, max_levels: int = 32, tuning: Optional[dict] = None,
-                  autotuned: bool = False, out=None, prune: bool = False, asynchronous: bool = False) -> FinalPartition:
+                  autotuned: bool = False, out=None, prune: bool = False, asynchronous: bool = False,
+                  cache: bool = True) -> FinalPartition:
     """lv_louvain, then only the final labels and modularity of every graph
     (two calls, whatever the number of graphs); `out` may be a numpy or
     torch int32 buffer of the handle's total vertex count."""
     lib = load_library()
-    p, _keep = make_params(max_sweeps, max_levels, 0, _flags(False, False, True, autotuned, prune, asynchronous), tuning)
+    p, _keep = make_params(max_sweeps, max_levels, 0, _flags(False, False, True, autotuned, prune, asynchronous, cache),
+                           tuning)
     r = _vp()
     _check(lib.lv_louvain(graph.handle, ctypes.byref(p), ctypes.byref(r)), "lv_louvain")
     try:
@@ -451,26 +459,27 @@ def _read_graph_result(lib, r, gi: int, n0: int, keep_graphs: bool, level_labels
 
 
 def _flags(timing: bool, keep_graphs: bool = False, hipgraph: bool = True, autotuned: bool = False,
-           prune: bool = False, asynchronous: bool = False) -> int:
+           prune: bool = False, asynchronous: bool = False, cache: bool = True) -> int:
     return ((LV_TIMING if timing else 0) | (LV_KEEP_GRAPHS if keep_graphs else 0) | (0 if hipgraph else LV_NO_HIPGRAPH)
-            | (LV_AUTOTUNE if autotuned else 0) | (LV_PRUNE if prune else 0) | (LV_ASYNC if asynchronous else 0))
+            | (LV_AUTOTUNE if autotuned else 0) | (LV_PRUNE if prune else 0) | (LV_ASYNC if asynchronous else 0)
+            | (0 if cache else LV_NO_CACHE))
 
 
 def louvain(graph: Graph, max_sweeps: int = 20, max_levels: int = 32, timing: bool = False,
             keep_graphs: bool = False, tuning: Optional[dict] = None, hipgraph: bool = True,
             autotuned: bool = False, level_labels: bool = True, prune: bool = False, asynchronous: bool = False,
-            out=None):
+            out=None, cache: bool = True):
     """lv_louvain + result accessors, copied to host numpy.  A packed handle
     (``Graph.batch``) gives one LouvainResult per graph, in order.  With
     level_labels=False only the final labels are copied (levels keep their
     statistics and move counts).  prune=True sets LV_PRUNE, asynchronous=True
-    LV_ASYNC.  `out` (one graph only) takes the final labels instead of a new
+    LV_ASYNC, cache=False LV_NO_CACHE.  `out` (one graph only) takes the final labels instead of a new
     numpy array: a numpy or torch int32 buffer of n entries, host or device."""
     if out is not None and graph.count != 1:
         raise ValueError("out= takes the final labels of a one-graph handle")
     lib = load_library()
     p, _keep = make_params(max_sweeps, max_levels, 0, _flags(timing, keep_graphs, hipgraph, autotuned, prune,
-                                                            asynchronous), tuning)
+                                                            asynchronous, cache), tuning)
     r = _vp()
     _check(lib.lv_louvain(graph.handle, ctypes.byref(p), ctypes.byref(r)), "lv_louvain")
     try:
@@ -490,14 +499,14 @@ class LpaResult:
 
 def lpa(graph: Graph, max_sweeps: int = 20, threshold: int = 0, timing: bool = False, out=None,
         tuning: Optional[dict] = None, hipgraph: bool = True, autotuned: bool = False, prune: bool = False,
-        asynchronous: bool = False) -> LpaResult:
+        asynchronous: bool = False, cache: bool = True) -> LpaResult:
     """lv_lpa; labels land in `out` (numpy or torch int32) or a new numpy array."""
     lib = load_library()
     if graph.count != 1:
         return lpa_batch(graph, max_sweeps, threshold, tuning=tuning, hipgraph=hipgraph, autotuned=autotuned,
-                         prune=prune, asynchronous=asynchronous)
-    p, _keep = make_params(max_sweeps, 32, threshold, _flags(timing, False, hipgraph, autotuned, prune, asynchronous),
-                           tuning)
+                         prune=prune, asynchronous=asynchronous, cache=cache)
+    p, _keep = make_params(max_sweeps, 32, threshold,
+                           _flags(timing, False, hipgraph, autotuned, prune, asynchronous, cache), tuning)
     labels = np.empty(graph.n, dtype=np.int32) if out is None else out
     pl, kind = _ptr(labels)
     info = lv_level_info()
@@ -509,11 +518,11 @@ def lpa(graph: Graph, max_sweeps: int = 20, threshold: int = 0, timing: bool = F
 
 def lpa_batch(graph: Graph, max_sweeps: int = 20, threshold: int = 0, tuning: Optional[dict] = None,
               hipgraph: bool = True, autotuned: bool = False, prune: bool = False,
-              asynchronous: bool = False) -> List[LpaResult]:
+              asynchronous: bool = False, cache: bool = True) -> List[LpaResult]:
     """lv_lpa_batch over a packed handle: one LpaResult per graph (local labels)."""
     lib = load_library()
-    p, _keep = make_params(max_sweeps, 32, threshold, _flags(False, False, hipgraph, autotuned, prune, asynchronous),
-                           tuning)
+    p, _keep = make_params(max_sweeps, 32, threshold,
+                           _flags(False, False, hipgraph, autotuned, prune, asynchronous, cache), tuning)
     G = graph.count
     labels = np.empty(max(graph.n, 1), dtype=np.int32)
     sw = np.zeros(G, dtype=np.int32)

@@ -53,17 +53,40 @@ lv_status from_hip(hipError_t e) { return e == hipErrorOutOfMemory ? LV_E_NOMEM 
         if (s_ != LV_OK) return s_;                                    \
     } while (0)
 
-// Allocation with optional fault injection: LV_FAULT_ALLOC_AT=k makes the
-// k-th device allocation of the process fail with out-of-memory.
-long g_alloc_count = 0;
+// Waits for the stream when it goes out of scope.  Declared after host
+// buffers that are the source or target of asynchronous copies, it keeps
+// every such copy from outliving its buffer when a later call fails and the
+// function returns early (a pending copy into a freed vector or a popped
+// stack slot would corrupt host memory).  Never used inside a captured region.
+struct SyncOnExit {
+    hipStream_t s;
+    ~SyncOnExit() { (void)hipStreamSynchronize(s); }
+};
+
+// Allocation with optional fault injection for tests of the out-of-memory
+// paths: with LV_FAULT_ALLOC_AT=k in the environment, the k-th device or
+// pinned-host allocation made by one entry-point call on the calling thread
+// fails with out-of-memory.  The variable is read at the start of every
+// graph-creation, louvain, lpa and modularity call (FaultScope), so a test may
+// change it between calls.
+thread_local long t_alloc_count = 0;
+thread_local long t_fail_at = 0;
+struct FaultScope {
+    FaultScope()
+    {
+        t_alloc_count = 0;
+        const char* v = std::getenv("LV_FAULT_ALLOC_AT");
+        t_fail_at = v ? std::atol(v) : 0L;
+    }
+};
+bool fault_now()
+{
+    ++t_alloc_count;
+    return t_fail_at > 0 && t_alloc_count == t_fail_at;
+}
 hipError_t dev_alloc(void** p, size_t bytes)
 {
-    ++g_alloc_count;
-    static long fail_at = [] {
-        const char* v = std::getenv("LV_FAULT_ALLOC_AT");
-        return v ? std::atol(v) : 0L;
-    }();
-    if (fail_at > 0 && g_alloc_count == fail_at) { *p = nullptr; return hipErrorOutOfMemory; }
+    if (fault_now()) { *p = nullptr; return hipErrorOutOfMemory; }
     return hipMalloc(p, bytes ? bytes : 1);
 }
 
@@ -105,6 +128,8 @@ struct Workspace {
     DevBuf g_off[2], g_idx[2], g_w[2], g_k[2], g_gid[2];
     DevBuf hub_table, hub_meta, hub_part, hub_rows, hub_cnt, hub_bucket, hub_bucket_w;
     DevBuf rows;  // per-level row descriptors of the class-sorted vertices
+    DevBuf ce;    // entry cache: per CSR entry of the handle's input graph, its neighbour's pair
+    DevBuf chg;   // per listed vertex: its pair changed in the last commit (uint8)
     DevBuf mark;  // active-vertex pruning: last sweep that changed the vertex's neighbourhood
     DevBuf tiles; // aggregation: per key tile its count, first entry and output position
     DevBuf p_off, p_idx, p_w, p_k, p_orig, p_inv;  // a coarse level stored by degree
@@ -181,6 +206,11 @@ struct lv_graph {
     // range, so graph ids by position and by id coincide.
     bool reordered = false;
     DevBuf orig, inv;
+    // Reverse-entry map of the stored input graph: rev[e] = position of the
+    // entry (j, i) for the entry e = (i, j) (a loop entry: itself).  Built at
+    // creation unless LV_NO_ENTRY_CACHE; used to keep the entry cache current.
+    DevBuf rev;
+    bool has_rev = false;
     Workspace ws;
     int32_t* pinned = nullptr;   // host staging area
     size_t pinned_bytes = 0;
@@ -237,6 +267,8 @@ struct Tune {
     int32_t sc_chunk;   // entries per scatter workgroup (bucketed mode)
     int64_t order_min;  // coarse levels with at least this many entries are stored by degree
     int32_t agg_sort;   // 1: aggregation sorts every entry's key (else by community)
+    int32_t cache_read_pct;  // entry cache: read it after a commit that changed at most this % of the pairs
+    int32_t cache_fill_pct;  // ... fill it during a sweep after a commit that changed at most this %
 };
 
 Tune make_tune(const lv_tuning* t)
@@ -251,6 +283,7 @@ Tune make_tune(const lv_tuning* t)
     u.fb_chunk = 4096;
     u.sc_chunk = 1024;
     u.agg_sort = 0;
+    u.cache_read_pct = 10;
     if (t) {
         // sub_max bounds the sub-wavefront classes, wave_max the wavefront
         // class, block_max the workgroup classes; each is clamped to the
@@ -274,7 +307,9 @@ Tune make_tune(const lv_tuning* t)
         if (t->hub_chunk > 0) u.sc_chunk = t->hub_chunk <= 1024 ? 1024 : t->hub_chunk <= 2048 ? 2048 : 4096;
         if (t->order_min > 0) u.order_min = t->order_min;
         u.agg_sort = t->agg_sort == 1 ? 1 : 0;
+        if (t->cache_pct > 0) u.cache_read_pct = std::min(100, t->cache_pct);
     }
+    u.cache_fill_pct = std::max(u.cache_read_pct, std::min(100, 2 * u.cache_read_pct + 5));
     // a single partition must always fit: part_keys <= 3/4 of the slots
     u.part_keys = std::min(u.part_keys, u.part_slots / 4 * 3);
     // keep bounds non-decreasing
@@ -322,10 +357,12 @@ struct LevelGraph {
     std::vector<int32_t> voff;  // [G+1] vertex offsets (host)
     std::vector<int64_t> Mh;    // [G] total volume of each graph (host)
     const int32_t* orig = nullptr;  // vertex id at each position (null: the position)
+    const int32_t* rev = nullptr;   // reverse-entry map (the handle's input graph only; null: none)
 };
 
-// timing slot of the bucketed scatter pass (after the 2 x 7 class slots)
-constexpr int SLOT_HUB_SCATTER = LV_KERNEL_SLOTS - 1;
+// timing slots after the 2 x 11 class slots: the bucketed scatter pass, the
+// commit (labels, volumes, pairs, sweep control) and the entry-cache refresh
+constexpr int SLOT_HUB_SCATTER = 22, SLOT_COMMIT = 23, SLOT_REFRESH = 24;
 
 struct SweepOut {
     std::vector<int32_t> sweeps;   // [G]
@@ -338,6 +375,8 @@ struct SweepOut {
     int64_t kern_launches[LV_KERNEL_SLOTS] = {};
     int64_t kern_bytes[LV_KERNEL_SLOTS] = {};
     int32_t isolated = 0;          // vertices without entries
+    int32_t cached_sweeps = 0;     // sweeps that read the entry cache
+    int64_t refreshed = 0;         // cache entries rewritten after commits
 };
 
 // Hub (partition) layout for one level.
@@ -352,6 +391,7 @@ lv_status ensure_pinned(lv_graph* g, size_t bytes)
     if (g->pinned) (void)hipHostFree(g->pinned);
     g->pinned = nullptr;
     g->pinned_bytes = 0;
+    if (fault_now()) { set_error_msg("hipHostMalloc: injected out-of-memory"); return LV_E_NOMEM; }
     HIP_TRY(hipHostMalloc((void**)&g->pinned, bytes, hipHostMallocDefault));
     g->pinned_bytes = bytes;
     return LV_OK;
@@ -468,6 +508,7 @@ lv_status plan_hubs(lv_graph* g, const LevelGraph& G, const int32_t* hub_verts, 
     const size_t o_sh = put(scan_hub), o_sb = put(scan_beg), o_se = put(scan_end), o_ff = put(fpart_first);
     const size_t o_ch = put(sc_hub), o_cb = put(sc_beg), o_ce = put(sc_end);
     const size_t o_mh = put(mk_hub), o_mb = put(mk_beg), o_me = put(mk_end);
+    SyncOnExit sync_host_vectors{s};
     const size_t b64 = sizeof(int64_t) * (size_t)nhubs;
     HIP_TRY(ws.hub_meta.ensure(b64 + sizeof(int32_t) * pack.size() + 64));
     char* base = ws.hub_meta.as<char>();
@@ -565,7 +606,7 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
     HIP_TRY(ws.gdone.ensure(sizeof(int32_t) * (size_t)G.G));
     HIP_TRY(ws.gsweeps.ensure(sizeof(int32_t) * (size_t)G.G));
     HIP_TRY(ws.gmoves.ensure(sizeof(uint32_t) * (size_t)G.G * (size_t)S));
-    LV_TRY(ensure_pinned(g, std::max<size_t>(4096, (sizeof(int32_t) + sizeof(uint32_t) * S) * (size_t)G.G)));
+    LV_TRY(ensure_pinned(g, std::max<size_t>(4096, (sizeof(int32_t) + sizeof(uint32_t) * S) * (size_t)G.G + 64)));
 
     // degree classes: classify, then one stable radix pass groups vertices by class
     HIP_TRY(launch_classify(n, G.off, p.tune.bounds, ws.cls.as<uint32_t>(), ws.vert.as<int32_t>(), s));
@@ -590,6 +631,36 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
     HubPlan hubs;
     LV_TRY(plan_hubs(g, G, vert_sorted + start[CLS_HUB], n - start[CLS_HUB], p.tune, hubs));
     const bool timing = (p.flags & LV_TIMING) != 0;
+    const bool async = (p.flags & LV_ASYNC) != 0;
+    // Entry cache: on the handle's input graph (its reverse-entry map
+    // exists), for full synchronous sweeps.  The device decides per sweep
+    // whether to read, fill or bypass it (k_sweep_end).
+    const bool use_ec = G.rev && G.nnz > 0 && active > 0 && !(p.flags & (LV_NO_CACHE | LV_PRUNE | LV_ASYNC));
+    if (use_ec) {
+        HIP_TRY(ws.ce.ensure(sizeof(int2) * (size_t)G.nnz));
+        HIP_TRY(ws.chg.ensure((size_t)std::max(active, 1)));
+    }
+    const int64_t ec_read_max = use_ec ? G.nnz * p.tune.cache_read_pct / 100 : -1;
+    const int64_t ec_fill_max = use_ec ? G.nnz * p.tune.cache_fill_pct / 100 : -1;
+    const int32_t nonhub = start[CLS_HUB] - start[CLS_L4];  // listed vertices below the hub class
+    // the refresh's blocks per class: lanes per row as in the move kernels, at most 256
+    RefreshMap rmap{};
+    if (use_ec) {
+        static const int32_t lanes_log2[NUM_CLS] = {0, 2, 3, 4, 5, 6, 7, 8, 8, 8, 8, 8};
+        int32_t blocks = 0;
+        for (int c = CLS_L4; c < CLS_HUB; ++c) {
+            const int32_t cnt = start[c + 1] - start[c];
+            if (cnt <= 0) continue;
+            const int q = rmap.nclass++;
+            rmap.blk_first[q] = blocks;
+            rmap.slot_first[q] = start[c] - start[CLS_L4];
+            rmap.slot_end[q] = start[c + 1] - start[CLS_L4];
+            rmap.lanes_log2[q] = lanes_log2[c];
+            const int32_t per_block = 256 >> lanes_log2[c];
+            blocks += (cnt + per_block - 1) / per_block;
+        }
+        rmap.blk_first[rmap.nclass] = blocks;
+    }
     int64_t cls_entries[NUM_CLS] = {};
     if (timing) {
         int64_t* d_ce = (int64_t*)(ws.small.as<char>() + 3328);
@@ -628,7 +699,7 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
     a.gdone = G.G > 1 ? ws.gdone.as<int32_t>() : nullptr;
     a.ctl = ctl;
     a.mode = mode;
-    const bool async = (p.flags & LV_ASYNC) != 0;
+    a.ce = use_ec ? ws.ce.as<int2>() : nullptr;
     a.live_comm = async ? ws.comm.as<int32_t>() : nullptr;
     a.live_sigma = async ? ws.sigma.as<int32_t>() : nullptr;
     a.gmoves = ws.gmoves.as<uint32_t>();
@@ -652,7 +723,7 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
     // pair refresh, per-graph stopping rule.
     auto launch_sweep = [&](bool singleton, std::vector<hipEvent_t>* e) -> lv_status {
         singleton = singleton && !async;  // an asynchronous sweep changes communities as it runs
-        if (e) { e->assign(2 * NUM_CLS + 4, nullptr); HIP_TRY(tm.mark(&(*e)[2 * NUM_CLS])); }
+        if (e) { e->assign(2 * NUM_CLS + 5, nullptr); HIP_TRY(tm.mark(&(*e)[2 * NUM_CLS])); }
         for (int c = CLS_L4; c < CLS_HUB; ++c) {
             a.verts = vert_sorted + start[c];
             a.rows = ws.rows.as<int4>() + (start[c] - start[CLS_L4]);
@@ -689,13 +760,23 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
         if (!async) {  // asynchronous sweeps have moved already
             HIP_TRY(launch_apply(act_verts, dec_all + start[CLS_L4], active, G.k, a.gid, ws.comm.as<int32_t>(),
                                  ws.sigma.as<int32_t>(), ctl, ws.gmoves.as<uint32_t>(), S, s));
-            HIP_TRY(launch_pairs(active, act_verts, ws.comm.as<int32_t>(), ws.sigma.as<int32_t>(), ws.cs.as<int2>(),
-                                 ctl, s));
+            if (use_ec)
+                HIP_TRY(launch_pairs_changed(active, ws.rows.as<int4>(), ws.comm.as<int32_t>(), ws.sigma.as<int32_t>(),
+                                             ws.cs.as<int2>(), ws.chg.as<uint8_t>(), mode, ctl, s));
+            else
+                HIP_TRY(launch_pairs(active, act_verts, ws.comm.as<int32_t>(), ws.sigma.as<int32_t>(),
+                                     ws.cs.as<int2>(), ctl, s));
         }
         // synchronous sweeps alternate direction, so a level ends after two
         // quiet sweeps; an asynchronous level ends after one (Alg. 2's test)
         HIP_TRY(launch_sweep_end(ctl, G.G, ws.gdone.as<int32_t>(), ws.gsweeps.as<int32_t>(),
-                                 ws.gmoves.as<uint32_t>(), S, theta, async ? 1 : 2, s));
+                                 ws.gmoves.as<uint32_t>(), S, theta, async ? 1 : 2, ec_read_max, ec_fill_max, s));
+        if (e) HIP_TRY(tm.mark(&(*e)[2 * NUM_CLS + 4]));
+        if (use_ec) {  // rewrite the changed entries if the next sweep reads the cache
+            HIP_TRY(launch_cache_refresh(rmap, ws.rows.as<int4>(), ws.chg.as<uint8_t>(), G.idx, G.rev,
+                                         ws.cs.as<int2>(), ws.ce.as<int2>(), ctl, s));
+            if (hubs.nhubs > 0) HIP_TRY(launch_hub_cache_refresh(a, hubs.args, ws.chg.as<uint8_t>() + nonhub, G.rev, s));
+        }
         if (e) HIP_TRY(tm.mark(&(*e)[2 * NUM_CLS + 2]));
         return LV_OK;
     };
@@ -754,15 +835,20 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
     // per-graph sweep and move counts (one host round trip per level)
     uint32_t* h_moves = (uint32_t*)g->pinned;
     int32_t* h_sweeps = (int32_t*)(h_moves + (size_t)G.G * S);
+    SweepCtl* h_ctl = (SweepCtl*)(((uintptr_t)(h_sweeps + G.G) + 15) & ~(uintptr_t)15);
     HIP_TRY(hipMemcpyAsync(h_moves, ws.gmoves.p, sizeof(uint32_t) * (size_t)G.G * S, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(h_sweeps, ws.gsweeps.p, sizeof(int32_t) * (size_t)G.G, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(h_ctl, ws.ctl.p, sizeof(SweepCtl), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    out.cached_sweeps = use_ec ? h_ctl->ec_reads : 0;
+    out.refreshed = use_ec ? (int64_t)h_ctl->refreshed : 0;
     out.moves.assign(h_moves, h_moves + (size_t)G.G * S);
     out.sweeps.assign(h_sweeps, h_sweeps + G.G);
     out.executed = 0;
     for (int32_t q = 0; q < G.G; ++q) out.executed = std::max(out.executed, out.sweeps[q]);
-    const int64_t wbytes = G.w ? 8 : 4;
-    out.bytes = (4 * ((int64_t)n + 1) + wbytes * G.nnz + 12 * (int64_t)n) * out.executed;
+    // compulsory bytes of a sweep: 8 per CSR entry (index and weight) and 36
+    // per vertex (offsets, label, degree and volume read; label and volume written)
+    out.bytes = (8 * G.nnz + 36 * (int64_t)n) * out.executed;
     for (int32_t sw = 1; sw <= out.executed; ++sw) {
         for (int c = CLS_L4; c <= CLS_HUB; ++c) {
             const int32_t nv = start[c + 1] - start[c];
@@ -776,18 +862,25 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
                 // the partition workgroups read the buckets it wrote
                 out.kern_ms[SLOT_HUB_SCATTER] += elapsed(E[2 * c], E[2 * NUM_CLS + 3]);
                 out.kern_launches[SLOT_HUB_SCATTER] += 1;
-                out.kern_bytes[SLOT_HUB_SCATTER] += wbytes * cls_entries[c] + 20 * (int64_t)nv;
+                out.kern_bytes[SLOT_HUB_SCATTER] += 8 * cls_entries[c] + 36 * (int64_t)nv;
                 out.kern_ms[slot] += elapsed(E[2 * NUM_CLS + 3], E[2 * c + 1]);
                 out.kern_launches[slot] += 1;
                 continue;
             }
             out.kern_ms[slot] += elapsed(E[2 * c], E[2 * c + 1]);
             out.kern_launches[slot] += 1;
-            out.kern_bytes[slot] += wbytes * cls_entries[c] + 20 * (int64_t)nv;
+            out.kern_bytes[slot] += 8 * cls_entries[c] + 36 * (int64_t)nv;
         }
         if (timing) {
-            out.move_ms += elapsed(ev[sw - 1][2 * NUM_CLS], ev[sw - 1][2 * NUM_CLS + 1]);
-            out.sweep_ms += elapsed(ev[sw - 1][2 * NUM_CLS], ev[sw - 1][2 * NUM_CLS + 2]);
+            const std::vector<hipEvent_t>& E = ev[sw - 1];
+            out.move_ms += elapsed(E[2 * NUM_CLS], E[2 * NUM_CLS + 1]);
+            out.sweep_ms += elapsed(E[2 * NUM_CLS], E[2 * NUM_CLS + 2]);
+            out.kern_ms[SLOT_COMMIT] += elapsed(E[2 * NUM_CLS + 1], E[2 * NUM_CLS + 4]);
+            out.kern_launches[SLOT_COMMIT] += 1;
+            if (use_ec) {
+                out.kern_ms[SLOT_REFRESH] += elapsed(E[2 * NUM_CLS + 4], E[2 * NUM_CLS + 2]);
+                out.kern_launches[SLOT_REFRESH] += 1;
+            }
         }
     }
     return LV_OK;
@@ -856,6 +949,7 @@ lv_status tile_keys(lv_graph* g, bool agg, int32_t n, const int32_t* off, const 
                               ws.vals_alt.as<int32_t>(), meta, gid, sigma_in, s));
     HIP_TRY(scan_exclusive_i32(meta, pos, tiles, d_tot, ws.tmp.p, ws.tmp.cap, s));
     int32_t tot = 0;
+    SyncOnExit sync_tot{s};
     HIP_TRY(hipMemcpyAsync(&tot, d_tot, sizeof tot, hipMemcpyDeviceToHost, s));
     HIP_TRY(launch_compact_tiles(ws.keys_alt.as<uint64_t>(), ws.vals_alt.as<int32_t>(), meta, pos, tiles,
                                  ws.keys.as<uint64_t>(), ws.vals.as<int32_t>(), s));
@@ -902,7 +996,7 @@ lv_status aggregate_by_community(lv_graph* g, const LevelGraph& G, int32_t n2, i
     int32_t* wt = G.w ? col + E : nullptr;
     int32_t* col2 = (int32_t*)ws.keys_alt.p;
     int32_t* wt2 = col2 + E;
-    HIP_TRY(launch_perm_rows(n, voff, E, mem, G.off, G.idx, G.w, labels, col, wt, s));
+    HIP_TRY(launch_perm_rows(n, voff, E, mem, G.off, G.idx, G.w, labels, col, wt, nullptr, nullptr, s));
     // 5. coarse vertices by segment length, with the local-moving classes'
     // bounds (the tuning's, never above a class's table)
     HIP_TRY(launch_classify(n2, seg, bounds, ws.cls.as<uint32_t>(), ws.vert.as<int32_t>(), s));
@@ -1130,6 +1224,7 @@ lv_status repack(lv_graph* g, const Coarse& co, const std::vector<int32_t>& voff
         next.voff.push_back(nv);
     }
     HIP_TRY(ws.segs.ensure(sizeof(RepackSeg) * segs.size()));
+    SyncOnExit sync_segs{s};
     HIP_TRY(hipMemcpyAsync(ws.segs.p, segs.data(), sizeof(RepackSeg) * segs.size(), hipMemcpyHostToDevice, s));
     HIP_TRY(ws.g_off[dst].ensure(sizeof(int32_t) * ((size_t)nv + 1)));
     HIP_TRY(ws.g_idx[dst].ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(ne, 1)));
@@ -1179,6 +1274,7 @@ LevelGraph level0(lv_graph* g)
     G.voff = g->voff;
     G.Mh = g->M;
     G.orig = g->reordered ? g->orig.as<int32_t>() : nullptr;
+    G.rev = g->has_rev ? g->rev.as<int32_t>() : nullptr;
     return G;
 }
 
@@ -1194,13 +1290,13 @@ lv_status autotune(lv_graph* g, const Params& base, lv_tuning* best, double* bes
     auto cost = [&](const lv_tuning& t, double* ms) -> lv_status {
         Params p = base;
         p.max_sweeps = std::min(3, base.max_sweeps);
-        p.flags = LV_TIMING;
+        p.flags = LV_TIMING | LV_NO_CACHE;  // the class kernels alone, each sweep gathering
         p.tune = make_tune(&t);
         SweepOut so;
         const LevelGraph G = level0(g);
         LV_TRY(run_sweeps(g, G, MODE_LOUVAIN, p, nullptr, so));
         double first = 0.0, later = 0.0;
-        for (int q = 0; q < LV_KERNEL_SLOTS; ++q) {
+        for (int q = 0; q < SLOT_COMMIT; ++q) {
             if (q < 2 * (NUM_CLS - 1) && (q & 1)) first += so.kern_ms[q];
             else later += so.kern_ms[q];
         }
@@ -1261,6 +1357,8 @@ void fill_info(lv_level_info& li, const SweepOut& so, int32_t c, int32_t S)
         li.kern_launches[t] = so.kern_launches[t];
         li.kern_bytes[t] = so.kern_bytes[t];
     }
+    li.cached_sweeps = so.cached_sweeps;
+    li.refreshed_entries = so.refreshed;
     (void)S;
 }
 
@@ -1272,7 +1370,7 @@ void fill_info(lv_level_info& li, const SweepOut& so, int32_t c, int32_t S)
 // indices mapped to positions.  Sorts in ws.keys* / ws.vals*.
 lv_status degree_order(lv_graph* g, int32_t n, int64_t nnz, const int32_t* off, const int32_t* idx, const int32_t* w,
                        const int32_t* k, const int32_t* gid, int32_t G, DevBuf& orig, DevBuf& inv, DevBuf& off2,
-                       DevBuf& idx2, DevBuf& w2, DevBuf& k2)
+                       DevBuf& idx2, DevBuf& w2, DevBuf& k2, const int32_t* rank = nullptr, DevBuf* rev2 = nullptr)
 {
     Workspace& ws = g->ws;
     hipStream_t s = g->stream;
@@ -1304,8 +1402,10 @@ lv_status degree_order(lv_graph* g, int32_t n, int64_t nnz, const int32_t* off, 
     HIP_TRY(k2.ensure(nb));
     HIP_TRY(launch_perm_lengths(orig.as<int32_t>(), n, off, off2.as<int32_t>(), s));
     HIP_TRY(scan_exclusive_i32(off2.as<int32_t>(), off2.as<int32_t>(), n, off2.as<int32_t>() + n, ws.tmp.p, ws.tmp.cap, s));
+    if (rank) HIP_TRY(rev2->ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(nnz, 1)));
     HIP_TRY(launch_perm_rows(n, off2.as<int32_t>(), nnz, orig.as<int32_t>(), off, idx, w, inv.as<int32_t>(),
-                             idx2.as<int32_t>(), w ? w2.as<int32_t>() : nullptr, s));
+                             idx2.as<int32_t>(), w ? w2.as<int32_t>() : nullptr, rank,
+                             rank ? rev2->as<int32_t>() : nullptr, s));
     HIP_TRY(launch_gather_i32(k, orig.as<int32_t>(), n, k2.as<int32_t>(), s));
     HIP_TRY(hipStreamSynchronize(s));
     return LV_OK;
@@ -1545,6 +1645,7 @@ lv_status lpa_impl(lv_graph* g, const Params& p, int32_t* out_dev, SweepOut& so,
     HIP_TRY(launch_sigma_in(G.n, G.off, G.idx, G.w, G.nnz, ws.comm.as<int32_t>(), G.gid, ws.gsum.as<int64_t>(), s));
     HIP_TRY(launch_sum_sq(ws.sigma.as<int32_t>(), G.n, G.gid, ws.gsq.as<int64_t>(), s));
     std::vector<int64_t> sin(G.G), sq(G.G);
+    SyncOnExit sync_sums{s};
     HIP_TRY(hipMemcpyAsync(sin.data(), ws.gsum.p, sizeof(int64_t) * (size_t)G.G, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(sq.data(), ws.gsq.p, sizeof(int64_t) * (size_t)G.G, hipMemcpyDeviceToHost, s));
     // labels numbered within each graph
@@ -1603,13 +1704,14 @@ const char* lv_last_error(void) { return g_last_error.c_str(); }
 // Store the graph by descending degree within each packed graph: the
 // gathered (community, volume) pairs of frequent neighbours then share cache
 // lines.  Ids, and so every decision and label, stay those of the input.
-static lv_status reorder_by_degree(lv_graph* g)
+static lv_status reorder_by_degree(lv_graph* g, const int32_t* rank)
 {
     if (g->n < 2 || g->nnz == 0) return LV_OK;
     DevBuf off2, idx2, w2, k2;
     LV_TRY(degree_order(g, g->n, g->nnz, g->off.as<int32_t>(), g->idx.as<int32_t>(),
                         g->weighted ? g->w.as<int32_t>() : nullptr, g->k.as<int32_t>(),
-                        g->G > 1 ? g->d_gid.as<int32_t>() : nullptr, g->G, g->orig, g->inv, off2, idx2, w2, k2));
+                        g->G > 1 ? g->d_gid.as<int32_t>() : nullptr, g->G, g->orig, g->inv, off2, idx2, w2, k2, rank,
+                        &g->rev));
     g->off.swap(off2);
     g->idx.swap(idx2);
     if (g->weighted) g->w.swap(w2);
@@ -1639,6 +1741,7 @@ static lv_status graph_setup(lv_graph* g, int32_t n, const int32_t* offsets, con
     HIP_TRY(hipMemcpyAsync(&first_last[1], g->off.as<int32_t>() + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (first_last[0] != 0 || first_last[1] < 0) { set_error_msg("offsets[0] must be 0 and offsets[n] >= 0"); return LV_E_CSR; }
+    if ((int64_t)first_last[1] > LV_MAX_NNZ) { set_error_msg("more than LV_MAX_NNZ entries"); return LV_E_OVERFLOW; }
     const int64_t nnz = first_last[1];
     const int32_t G = (int32_t)voff.size() - 1;
     g->n = n;
@@ -1728,7 +1831,26 @@ static lv_status graph_setup(lv_graph* g, int32_t n, const int32_t* offsets, con
         HIP_TRY(hipMemcpyAsync(g->d_M.p, g->M.data(), sizeof(int64_t) * (size_t)G, hipMemcpyHostToDevice, s));
         HIP_TRY(hipStreamSynchronize(s));
     }
-    if (!(flags & LV_KEEP_ORDER)) LV_TRY(reorder_by_degree(g));
+    // reverse-entry ranks while the rows are still sorted by column
+    DevBuf rank;
+    bool rank_ok = false;
+    if (!(flags & LV_NO_ENTRY_CACHE) && nnz > 0) {
+        HIP_TRY(rank.ensure(sizeof(int32_t) * (size_t)nnz));
+        HIP_TRY(hipMemsetAsync(d_err, 0, sizeof(int32_t), s));
+        HIP_TRY(launch_reverse_rank(n, g->off.as<int32_t>(), g->idx.as<int32_t>(), nnz, rank.as<int32_t>(), d_err, s));
+        HIP_TRY(hipMemcpyAsync(&err, d_err, sizeof err, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        rank_ok = (err & 32) == 0;  // an asymmetric graph (not validated) gets no cache
+    }
+    g->rev.release();
+    if (!(flags & LV_KEEP_ORDER)) LV_TRY(reorder_by_degree(g, rank_ok ? rank.as<int32_t>() : nullptr));
+    if (rank_ok && !g->reordered) {
+        HIP_TRY(g->rev.ensure(sizeof(int32_t) * (size_t)nnz));
+        HIP_TRY(launch_reverse_from_rank(n, g->off.as<int32_t>(), g->idx.as<int32_t>(), nnz, rank.as<int32_t>(),
+                                         g->rev.as<int32_t>(), s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    g->has_rev = rank_ok;
     return LV_OK;
 }
 
@@ -1822,6 +1944,7 @@ static lv_status create_from_edges(lv_graph* g, int32_t n, int64_t m, const int3
     const int32_t* us = src;
     const int32_t* vs = dst;
     const int32_t* ws_in = weights;
+    SyncOnExit sync_inputs{s};  // the caller's arrays need to live only for the call
     if (kind == LV_MEM_HOST && m > 0) {
         HIP_TRY(d_src.ensure(sizeof(int32_t) * (size_t)m));
         HIP_TRY(d_dst.ensure(sizeof(int32_t) * (size_t)m));
@@ -1865,12 +1988,13 @@ static lv_status create_from_edges(lv_graph* g, int32_t n, int64_t m, const int3
     release_sort_workspace(g);
     const bool unit = (flags & LV_EDGES_SIMPLE) != 0;
     return graph_setup(g, n, off.as<int32_t>(), idx.as<int32_t>(), unit ? nullptr : w.as<int32_t>(), LV_MEM_DEVICE,
-                       flags & LV_KEEP_ORDER, std::vector<int32_t>{0, n});
+                       flags & (LV_KEEP_ORDER | LV_NO_ENTRY_CACHE), std::vector<int32_t>{0, n});
 }
 
 lv_status lv_graph_create_edges(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, const int32_t* weights,
                                 lv_memkind kind, uint32_t flags, void* stream, lv_graph** out)
 {
+    FaultScope fault_scope;
     if (!out || n < 0 || m < 0 || (m > 0 && (!src || !dst)) || (kind != LV_MEM_HOST && kind != LV_MEM_DEVICE)) {
         set_error_msg("lv_graph_create_edges: null out, n < 0, m < 0, null endpoints or bad memkind");
         return LV_E_ARG;
@@ -1937,12 +2061,14 @@ lv_status lv_graph_csr(lv_graph* g, int32_t* offsets, int32_t* indices, int32_t*
 lv_status lv_graph_create_csr(int32_t n, const int32_t* offsets, const int32_t* indices, const int32_t* weights,
                               lv_memkind kind, uint32_t flags, void* stream, lv_graph** out)
 {
+    FaultScope fault_scope;
     if (!out || n < 0 || !offsets || (kind != LV_MEM_HOST && kind != LV_MEM_DEVICE)) {
         set_error_msg("lv_graph_create_csr: null out/offsets, n < 0 or bad memkind");
         return LV_E_ARG;
     }
     if (n == INT32_MAX) { set_error_msg("n must be < 2^31 - 1"); return LV_E_OVERFLOW; }
     if (kind == LV_MEM_HOST) {
+        if ((int64_t)offsets[n] > LV_MAX_NNZ) { set_error_msg("more than LV_MAX_NNZ entries"); return LV_E_OVERFLOW; }
         if ((int64_t)offsets[n] > 0 && !indices) { set_error_msg("indices is null"); return LV_E_ARG; }
     } else if (!indices) {
         set_error_msg("indices is null");
@@ -1964,6 +2090,7 @@ lv_status lv_graph_create_batch(int32_t count, const int32_t* n, const int32_t* 
                                 const int32_t* const* indices, const int32_t* const* weights, lv_memkind kind,
                                 uint32_t flags, void* stream, lv_graph** out)
 {
+    FaultScope fault_scope;
     if (!out || count < 1 || !n || !offsets || !indices || (kind != LV_MEM_HOST && kind != LV_MEM_DEVICE)) {
         set_error_msg("lv_graph_create_batch: count >= 1 and non-null n/offsets/indices/out required");
         return LV_E_ARG;
@@ -1982,7 +2109,7 @@ lv_status lv_graph_create_batch(int32_t count, const int32_t* n, const int32_t* 
         if (ho[q][n[q]] > 0 && !indices[q]) { set_error_msg("graph " + std::to_string(q) + ": null indices"); return LV_E_ARG; }
         nv += n[q];
         ne += ho[q][n[q]];
-        if (nv >= INT32_MAX || ne >= INT32_MAX) { set_error_msg("packed graphs exceed 2^31 vertices or entries"); return LV_E_OVERFLOW; }
+        if (nv >= INT32_MAX || ne > LV_MAX_NNZ) { set_error_msg("packed graphs exceed 2^31 - 1 vertices or LV_MAX_NNZ entries"); return LV_E_OVERFLOW; }
         voff.push_back((int32_t)nv);
         any_w = any_w || (weights && weights[q]);
     }
@@ -2022,6 +2149,7 @@ lv_status lv_graph_create_batch(int32_t count, const int32_t* n, const int32_t* 
 
 lv_status lv_autotune(lv_graph* g, const lv_params* params, lv_tuning* out, double* est_ms)
 {
+    FaultScope fault_scope;
     if (!g || !out) { set_error_msg("lv_autotune: null graph or out"); return LV_E_ARG; }
     Params p;
     LV_TRY(read_params(params, p));
@@ -2061,6 +2189,7 @@ lv_status lv_graph_count(const lv_graph* g, int32_t* count)
 
 lv_status lv_louvain(lv_graph* g, const lv_params* params, lv_result** out)
 {
+    FaultScope fault_scope;
     if (!g || !out) { set_error_msg("lv_louvain: null graph or out"); return LV_E_ARG; }
     Params p;
     LV_TRY(read_params(params, p));
@@ -2286,11 +2415,13 @@ lv_status lv_probe_copy(lv_graph* g, int32_t reps, double* bytes_per_s)
 
 lv_status lv_modularity(lv_graph* g, const int32_t* labels, lv_memkind kind, int64_t* q_int, int64_t* m, double* q)
 {
+    FaultScope fault_scope;
     if (!g || !labels || (kind != LV_MEM_HOST && kind != LV_MEM_DEVICE)) return LV_E_ARG;
     if (g->G != 1) { set_error_msg("lv_modularity takes a single-graph handle"); return LV_E_STATE; }
     Workspace& ws = g->ws;
     HIP_TRY(ws.small.ensure(4096));
     const int32_t* dl = labels;
+    SyncOnExit sync_labels{g->stream};  // the caller's labels need to live only for the call
     if (kind == LV_MEM_HOST) {
         HIP_TRY(ws.labels.ensure(sizeof(int32_t) * (size_t)std::max(g->n, 1)));
         if (g->n > 0)
@@ -2314,6 +2445,7 @@ lv_status lv_modularity(lv_graph* g, const int32_t* labels, lv_memkind kind, int
 lv_status lv_lpa_batch(lv_graph* g, const lv_params* params, int32_t* labels, lv_memkind kind, int32_t* sweeps,
                        int64_t* q_int, int64_t* m, int64_t* moves, int32_t moves_stride)
 {
+    FaultScope fault_scope;
     if (!g || !labels || (kind != LV_MEM_HOST && kind != LV_MEM_DEVICE) || moves_stride < 0 ||
         (moves && moves_stride == 0))
         return LV_E_ARG;
@@ -2344,6 +2476,7 @@ lv_status lv_lpa_batch(lv_graph* g, const lv_params* params, int32_t* labels, lv
 lv_status lv_lpa(lv_graph* g, const lv_params* params, int32_t* labels, lv_memkind kind, lv_level_info* info,
                  int64_t* moves_out, int32_t moves_cap)
 {
+    FaultScope fault_scope;
     if (!g || !labels || (kind != LV_MEM_HOST && kind != LV_MEM_DEVICE) || moves_cap < 0 || (moves_cap > 0 && !moves_out))
         return LV_E_ARG;
     if (g->G != 1) { set_error_msg("lv_lpa takes a single-graph handle (see lv_lpa_batch)"); return LV_E_STATE; }

@@ -259,13 +259,48 @@ __global__ void k_perm_lengths(const int32_t* perm, int32_t n, const int32_t* of
 __global__ __launch_bounds__(TILE_BS) void k_perm_rows(int32_t n, const int32_t* off_new, int64_t nnz,
                                                         const int32_t* perm, const int32_t* off, const int32_t* idx,
                                                         const int32_t* w, const int32_t* inv, int32_t* idx_new,
-                                                        int32_t* w_new)
+                                                        int32_t* w_new, const int32_t* rank, int32_t* rev_new)
 {
     for_tile_entries_co_at<TILE_BS, TILE_IT>((int64_t)blockIdx.x, off_new, n, nnz, [&](int32_t q, int64_t e) {
         const int64_t src = (int64_t)off[perm[q]] + (e - off_new[q]);
-        idx_new[e] = inv[idx[src]];
+        const int32_t p = inv[idx[src]];
+        idx_new[e] = p;
         if (w) w_new[e] = w[src];
+        // the reverse entry keeps its rank within its (moved) row
+        if (rank) rev_new[e] = off_new[p] + rank[src];
     });
+}
+
+// Reverse-entry ranks of a CSR with sorted rows.  Each unordered pair {i, j}
+// (i != j) is handled once, by its entry in the longer row (ties: the larger
+// row id), which binary-searches the shorter row for the reverse entry and
+// writes both ranks; a loop is its own reverse.
+__global__ __launch_bounds__(TILE_BS) void k_reverse_rank(int32_t n, const int32_t* off, const int32_t* idx,
+                                                           int64_t nnz, int32_t* rank, int32_t* err)
+{
+    for_tile_entries<TILE_BS, TILE_IT>(off, n, nnz, [&](int32_t r, int64_t e) {
+        const int32_t j = idx[e];
+        const int32_t rb = off[r];
+        if (j == r) { rank[e] = (int32_t)(e - rb); return; }
+        const int32_t jb = off[j], je = off[j + 1];
+        const int32_t dr = off[r + 1] - rb, dj = je - jb;
+        if (!(dj < dr || (dj == dr && j < r))) return;
+        int32_t lo = jb, hi = je;
+        while (lo < hi) {
+            const int32_t mid = lo + (hi - lo) / 2;
+            if (idx[mid] < r) lo = mid + 1; else hi = mid;
+        }
+        if (lo >= je || idx[lo] != r) { atomicOr(err, 32); return; }
+        rank[e] = lo - jb;
+        rank[lo] = (int32_t)(e - rb);
+    });
+}
+
+__global__ void k_reverse_from_rank(const int32_t* off, const int32_t* idx, int64_t nnz, const int32_t* rank,
+                                    int32_t* rev)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x)
+        rev[e] = off[idx[e]] + rank[e];
 }
 __global__ void k_scatter_i32(const int32_t* src, const int32_t* idx, int32_t m, int32_t* dst)
 {
@@ -302,10 +337,26 @@ hipError_t launch_perm_lengths(const int32_t* perm, int32_t n, const int32_t* of
 }
 hipError_t launch_perm_rows(int32_t n, const int32_t* off_new, int64_t nnz, const int32_t* perm, const int32_t* off,
                             const int32_t* idx, const int32_t* w, const int32_t* inv, int32_t* idx_new, int32_t* w_new,
-                            hipStream_t s)
+                            const int32_t* rank, int32_t* rev_new, hipStream_t s)
 {
     if (nnz <= 0) return hipSuccess;
-    k_perm_rows<<<tiles_for(n, nnz), TILE_BS, 0, s>>>(n, off_new, nnz, perm, off, idx, w, inv, idx_new, w_new);
+    k_perm_rows<<<tiles_for(n, nnz), TILE_BS, 0, s>>>(n, off_new, nnz, perm, off, idx, w, inv, idx_new, w_new, rank,
+                                                      rev_new);
+    return hipGetLastError();
+}
+hipError_t launch_reverse_rank(int32_t n, const int32_t* off, const int32_t* idx, int64_t nnz, int32_t* rank,
+                               int32_t* err, hipStream_t s)
+{
+    if (nnz <= 0) return hipSuccess;
+    k_reverse_rank<<<tiles_for(n, nnz), TILE_BS, 0, s>>>(n, off, idx, nnz, rank, err);
+    return hipGetLastError();
+}
+hipError_t launch_reverse_from_rank(int32_t n, const int32_t* off, const int32_t* idx, int64_t nnz,
+                                    const int32_t* rank, int32_t* rev, hipStream_t s)
+{
+    if (nnz <= 0) return hipSuccess;
+    (void)n;
+    k_reverse_from_rank<<<LV_GRID(nnz)>>>(off, idx, nnz, rank, rev);
     return hipGetLastError();
 }
 hipError_t launch_scatter_i32(const int32_t* src, const int32_t* idx, int32_t m, int32_t* dst, hipStream_t s)

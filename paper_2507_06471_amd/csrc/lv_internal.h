@@ -44,7 +44,15 @@ constexpr int32_t L8K_SLOTS = 10112;
 struct SweepCtl {
     int32_t sweep;
     int32_t all_done;
+    // Entry cache (see MoveArgs::ce): how the current sweep's move kernels
+    // get each entry's (community, volume) pair: EC_GATHER from cs[idx[e]],
+    // EC_FILL the same and also storing it into ce[e], EC_READ from ce[e].
+    int32_t ec_mode;
+    int32_t ec_reads;                 // sweeps of this level that read the cache
+    unsigned long long chg_entries;   // entries whose pair the last commit changed
+    unsigned long long refreshed;     // entries rewritten by cache refreshes this level
 };
+constexpr int32_t EC_GATHER = 0, EC_FILL = 1, EC_READ = 2;
 
 // Arguments shared by every move kernel.
 struct MoveArgs {
@@ -75,6 +83,13 @@ struct MoveArgs {
     int32_t* live_sigma;
     uint32_t* gmoves;
     int32_t max_sweeps;
+    // Entry cache (null: off).  ce[e] holds the (community, volume) pair of
+    // entry e's neighbour as of the previous sweep ((EMPTY_KEY, 0) for a loop
+    // entry), so a sweep that reads it streams 8 bytes per entry instead of
+    // gathering cs[idx[e]] at random.  Kept current by rewriting, after every
+    // commit, the entries that point at a vertex whose pair changed (through
+    // the reverse-entry map).
+    int2* ce;
 };
 
 // One segment of a packed CSR rebuild (see launch_repack).
@@ -232,6 +247,36 @@ hipError_t launch_mark_movers(const int4* rows, const int32_t* dec, int32_t m, c
 hipError_t launch_hub_mark(const MoveArgs& a, const HubArgs& h, int32_t* mark, hipStream_t s);
 hipError_t launch_pairs(int32_t n, const int32_t* verts, const int32_t* comm, const int32_t* sigma, int2* cs,
                         const SweepCtl* ctl, hipStream_t s);
+// As launch_pairs over the m listed vertices rows[0..m) (class order), also
+// recording in chg[t] whether slot t's pair changed (LPA: its label) and
+// adding the changed rows' entries to ctl->chg_entries.
+hipError_t launch_pairs_changed(int32_t m, const int4* rows, const int32_t* comm, const int32_t* sigma, int2* cs,
+                                uint8_t* chg, int mode, SweepCtl* ctl, hipStream_t s);
+// Entry-cache refresh when the next sweep reads the cache: for every listed
+// vertex v with chg set, ce[rev[e]] = cs[v] for each non-loop entry e of v's
+// row (rows below the hub class, by class; hubs through their 4096-entry
+// chunks).  RefreshMap: per class below the hub class that has rows, in
+// order: its first 256-thread block (blk_first[nclass] = blocks in all), its
+// listed slots [slot_first, slot_end) and log2 of the lanes per row.
+struct RefreshMap {
+    int32_t nclass;
+    int32_t blk_first[NUM_CLS + 1];
+    int32_t slot_first[NUM_CLS];
+    int32_t slot_end[NUM_CLS];
+    int32_t lanes_log2[NUM_CLS];
+};
+hipError_t launch_cache_refresh(const RefreshMap& mp, const int4* rows, const uint8_t* chg, const int32_t* idx,
+                                const int32_t* rev, const int2* cs, int2* ce, SweepCtl* ctl, hipStream_t s);
+hipError_t launch_hub_cache_refresh(const MoveArgs& a, const HubArgs& h, const uint8_t* chg_hub, const int32_t* rev,
+                                    hipStream_t s);
+// Reverse-entry map of a CSR whose rows are sorted: rank[e] = position of
+// entry e's reverse (j, i) within row j.  err |= 32 if some entry has no
+// reverse (an asymmetric graph).
+hipError_t launch_reverse_rank(int32_t n, const int32_t* off, const int32_t* idx, int64_t nnz, int32_t* rank,
+                               int32_t* err, hipStream_t s);
+// rev[e] = off[idx[e]] + rank[e] (rows kept in place)
+hipError_t launch_reverse_from_rank(int32_t n, const int32_t* off, const int32_t* idx, int64_t nnz,
+                                    const int32_t* rank, int32_t* rev, hipStream_t s);
 // commit the decisions dec[0..m) of vertices verts[0..m); per-graph movers into gmoves
 hipError_t launch_apply(const int32_t* verts, const int32_t* dec, int32_t m, const int32_t* k, const int32_t* gid,
                         int32_t* comm, int32_t* sigma, const SweepCtl* ctl, uint32_t* gmoves, int32_t max_sweeps,
@@ -239,8 +284,12 @@ hipError_t launch_apply(const int32_t* verts, const int32_t* dec, int32_t m, con
 // level start: sweep counter 0; gdone[g] = !gactive[g] (gactive null = all run); moves zeroed
 hipError_t launch_ctl_init(SweepCtl* ctl, int32_t G, const int32_t* gactive, int32_t* gdone, int32_t* gsweeps,
                            uint32_t* gmoves, int32_t max_sweeps, hipStream_t s);
+// ec_read_max / ec_fill_max: the next sweep reads the entry cache if it was
+// filled and at most ec_read_max entries changed, else fills it if at most
+// ec_fill_max changed (-1: no cache)
 hipError_t launch_sweep_end(SweepCtl* ctl, int32_t G, int32_t* gdone, int32_t* gsweeps, const uint32_t* gmoves,
-                            int32_t max_sweeps, int64_t theta, int32_t consecutive, hipStream_t s);
+                            int32_t max_sweeps, int64_t theta, int32_t consecutive, int64_t ec_read_max,
+                            int64_t ec_fill_max, hipStream_t s);
 
 // renumber + aggregation
 hipError_t launch_renumber(int32_t n, const int32_t* comm, const int32_t* orig, int32_t* minv, int32_t* flag,
@@ -254,9 +303,11 @@ hipError_t launch_degree_keys(int32_t n, const int32_t* off, const int32_t* gid,
 hipError_t launch_max_degree(int32_t n, const int32_t* off, int32_t* out, hipStream_t s);
 hipError_t launch_inverse(const int32_t* perm, int32_t n, int32_t* inv, hipStream_t s);
 hipError_t launch_perm_lengths(const int32_t* perm, int32_t n, const int32_t* off, int32_t* len, hipStream_t s);
+// rank (may be null): the reverse-entry ranks of the old rows (launch_reverse_rank);
+// then rev_new receives the reverse-entry map of the permuted CSR
 hipError_t launch_perm_rows(int32_t n, const int32_t* off_new, int64_t nnz, const int32_t* perm, const int32_t* off,
                             const int32_t* idx, const int32_t* w, const int32_t* inv, int32_t* idx_new, int32_t* w_new,
-                            hipStream_t s);
+                            const int32_t* rank, int32_t* rev_new, hipStream_t s);
 // dst[idx[t]] = src[t]
 hipError_t launch_scatter_i32(const int32_t* src, const int32_t* idx, int32_t m, int32_t* dst, hipStream_t s);
 // keys = (label(i) << colbits) | label(j); sigma_in[g] += weight inside communities (caller zeroes it)

@@ -196,6 +196,20 @@ __device__ __forceinline__ void decide_store(const MoveArgs& a, int64_t pos, int
     a.dec[pos] = mover ? best_c : -1;
 }
 
+// Entry cache access: 8-byte streaming load / store of entry e's pair.
+__device__ __forceinline__ int2 ce_load(const int2* ce, int64_t e)
+{
+    const long long v = __builtin_nontemporal_load((const long long*)ce + e);
+    return make_int2((int32_t)(uint32_t)(unsigned long long)v, (int32_t)((unsigned long long)v >> 32));
+}
+__device__ __forceinline__ void ce_store(int2* ce, int64_t e, int2 p)
+{
+    const unsigned long long v = ((unsigned long long)(uint32_t)p.y << 32) | (uint32_t)p.x;
+    __builtin_nontemporal_store((long long)v, (long long*)ce + e);
+}
+// How this sweep's kernels get the entries' pairs (EC_GATHER without a cache).
+__device__ __forceinline__ int entry_mode(const MoveArgs& a) { return a.ce ? a.ctl->ec_mode : EC_GATHER; }
+
 // Score every entry of [e_beg, e_end) as its own community (first sweep of a level).
 template <int STRIDE>
 __device__ __forceinline__ void score_entries_singleton(const MoveArgs& a, int32_t i, int64_t ki, int64_t M,
@@ -244,26 +258,46 @@ __device__ __forceinline__ bool lds_insert_bounded(int32_t* key, int32_t* val, i
 // of vertex i into an LDS table, optionally only communities of partition
 // `part` of P.  Returns false if the bounded table had no room (only
 // possible with P > 1).
+// ecm: EC_READ takes each entry's pair from the entry cache, EC_FILL gathers
+// it and also stores it there, EC_GATHER gathers it.
 template <int STRIDE, bool BOUNDED, bool SIG, int U = UNROLL, bool MOD = false>
 __device__ __forceinline__ bool aggregate_entries(const MoveArgs& a, int32_t i, int32_t e_beg, int32_t e_end,
                                                   int32_t* key, int32_t* val, int32_t* sig, uint32_t mask, uint32_t P,
-                                                  uint32_t part)
+                                                  uint32_t part, int ecm)
 {
     bool ok_all = true;
     for (int32_t e0 = e_beg; e0 < e_end; e0 += STRIDE * U) {
-        int32_t jj[U], ww[U];
+        int32_t ww[U];
         int2 cc[U];
+        if (ecm == EC_READ) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int32_t e = e0 + u * STRIDE;
-            const bool ok = e < e_end;
-            jj[u] = ok ? __builtin_nontemporal_load(&a.idx[e]) : i;
-            ww[u] = (ok && a.w) ? __builtin_nontemporal_load(&a.w[e]) : 1;
-        }
+            for (int u = 0; u < U; ++u) {
+                const int32_t e = e0 + u * STRIDE;
+                const bool ok = e < e_end;
+                cc[u] = ok ? ce_load(a.ce, e) : make_int2(EMPTY_KEY, 0);
+                ww[u] = (ok && a.w) ? __builtin_nontemporal_load(&a.w[e]) : 1;
+            }
+        } else {
+            int32_t jj[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if constexpr (SIG) cc[u] = jj[u] != i ? a.cs[jj[u]] : make_int2(EMPTY_KEY, 0);
-            else cc[u] = make_int2(jj[u] != i ? a.comm[jj[u]] : EMPTY_KEY, 0);
+            for (int u = 0; u < U; ++u) {
+                const int32_t e = e0 + u * STRIDE;
+                const bool ok = e < e_end;
+                jj[u] = ok ? __builtin_nontemporal_load(&a.idx[e]) : i;
+                ww[u] = (ok && a.w) ? __builtin_nontemporal_load(&a.w[e]) : 1;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (SIG || ecm == EC_FILL) cc[u] = jj[u] != i ? a.cs[jj[u]] : make_int2(EMPTY_KEY, 0);
+                else cc[u] = make_int2(jj[u] != i ? a.comm[jj[u]] : EMPTY_KEY, 0);
+            }
+            if (ecm == EC_FILL) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int32_t e = e0 + u * STRIDE;
+                    if (e < e_end) ce_store(a.ce, e, cc[u]);
+                }
+            }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -344,20 +378,85 @@ __device__ __forceinline__ void scan_table(const MoveArgs& a, const int32_t* key
     }
 }
 
+// Pairs of the ME entries e_first + u*STRIDE (u < ME) of vertex i's row
+// ending at e_end, by the sweep's entry mode (out of range or a loop: EMPTY_KEY).
+template <int STRIDE, int ME>
+__device__ __forceinline__ void load_pairs(const MoveArgs& a, int32_t i, int32_t e_first, int32_t e_end, int ecm,
+                                           int2 (&cc)[ME], int32_t (&ww)[ME])
+{
+    if (ecm == EC_READ) {
+#pragma unroll
+        for (int u = 0; u < ME; ++u) {
+            const int32_t e = e_first + u * STRIDE;
+            const bool ok = e < e_end;
+            cc[u] = ok ? ce_load(a.ce, e) : make_int2(EMPTY_KEY, 0);
+            ww[u] = (ok && a.w) ? __builtin_nontemporal_load(&a.w[e]) : 1;
+        }
+        return;
+    }
+    int32_t jj[ME];
+#pragma unroll
+    for (int u = 0; u < ME; ++u) {
+        const int32_t e = e_first + u * STRIDE;
+        const bool ok = e < e_end;
+        jj[u] = ok ? __builtin_nontemporal_load(&a.idx[e]) : i;
+        ww[u] = (ok && a.w) ? __builtin_nontemporal_load(&a.w[e]) : 1;
+    }
+#pragma unroll
+    for (int u = 0; u < ME; ++u) cc[u] = jj[u] != i ? a.cs[jj[u]] : make_int2(EMPTY_KEY, 0);
+    if (ecm == EC_FILL) {
+#pragma unroll
+        for (int u = 0; u < ME; ++u) {
+            const int32_t e = e_first + u * STRIDE;
+            if (e < e_end) ce_store(a.ce, e, cc[u]);
+        }
+    }
+}
+
+// Claim-or-add of (C, W) in an LDS table of packed 64-bit slots (community
+// in the high word, weight sum in the low word; EMPTY_SLOT when free) that
+// has room for every key.  Returns the slot if this call claimed it (the
+// claimer later scores the community), else -1 after adding W to the
+// community's sum.  mask: slots - 1 (a power of two), or with MOD the slot
+// count, hashed by a multiply-high reduction.
+constexpr unsigned long long EMPTY_SLOT = 0xFFFFFFFF00000000ull;
+template <bool MOD>
+__device__ __forceinline__ int32_t claim_or_add(unsigned long long* tab, uint32_t mask, int32_t C, int32_t W)
+{
+    const unsigned long long mine = ((unsigned long long)(uint32_t)C << 32) | (uint32_t)W;
+    uint32_t h = MOD ? (uint32_t)(((uint64_t)mix32(C) * mask) >> 32) : (mix32(C) & mask);
+    for (;;) {
+        const unsigned long long prev = atomicCAS(&tab[h], EMPTY_SLOT, mine);
+        if (prev == EMPTY_SLOT) return (int32_t)h;
+        if ((int32_t)(prev >> 32) == C) {
+            atomicAdd(&tab[h], (unsigned long long)(uint32_t)W);
+            return -1;
+        }
+        if constexpr (MOD) h = h + 1 == mask ? 0u : h + 1; else h = (h + 1) & mask;
+    }
+}
+
+// Kinds of the generic move kernel: the first sweep of a level (every
+// community a single vertex: entries scored directly) and an asynchronous
+// sweep (compact table; volumes read live at scan time).  Later synchronous
+// sweeps run k_move_claim.
+constexpr int MK_FIRST = 0, MK_ASYNC = 2;
+
 // One group of G lanes per vertex (G <= BS); LDS table of up to SLOTS slots.
 // (CLS only names the instantiation, so each degree class has its own kernel symbol)
-template <int CLS, int BS, int G, int SLOTS, bool SINGLETON, bool SIG, bool ASYNC = false>
+template <int CLS, int BS, int G, int SLOTS, int KIND>
 __global__ __launch_bounds__(BS) void k_move(MoveArgs a)
 {
     constexpr int NG = BS / G;
-    constexpr int TBL = SINGLETON ? 1 : NG * SLOTS;
-    __shared__ int32_t s_key[TBL];
-    __shared__ int32_t s_val[TBL];
-    __shared__ int32_t s_sig[SIG ? TBL : 1];
+    constexpr int TBL = KIND == MK_FIRST ? 1 : NG * SLOTS;
+    constexpr bool ASYNC = KIND == MK_ASYNC;
+    __shared__ int32_t s_key[ASYNC ? TBL : 1];
+    __shared__ int32_t s_val[ASYNC ? TBL : 1];
     __shared__ int64_t rs[BS / WAVE];
     __shared__ int32_t rc[BS / WAVE], rw[BS / WAVE];
 
     if (a.ctl->all_done) return;
+    const int ecm = entry_mode(a);
     const int g = threadIdx.x / G, lane = threadIdx.x % G;
     const int64_t vi = (int64_t)blockIdx.x * NG + g;
     const bool has = vi < a.nverts;
@@ -371,25 +470,24 @@ __global__ __launch_bounds__(BS) void k_move(MoveArgs a)
     const int64_t M = live ? vertex_M(a, i) : 0;
     int64_t best_s = INT64_MIN;
     int32_t best_c = INT32_MAX, w_own = 0;
+    // a table of up to SLOTS slots sized to the row (a power of two when
+    // SLOTS is one, else 2L + 1 with multiply-high hashing); SLOTS exceeds
+    // every row of the class, so the table never fills
+    constexpr bool POW2 = (SLOTS & (SLOTS - 1)) == 0;
+    const uint32_t T = POW2 ? min((uint32_t)SLOTS, pow2_at_least(2u * (uint32_t)(end - beg)))
+                            : min((uint32_t)SLOTS, 2u * (uint32_t)(end - beg) + 1u);
 
-    if constexpr (SINGLETON) {
+    if constexpr (KIND == MK_FIRST) {
         score_entries_singleton<G>(a, i, ki, M, beg + lane, end, best_s, best_c);
     } else {
         int32_t* key = s_key + g * SLOTS;
         int32_t* val = s_val + g * SLOTS;
-        int32_t* sig = SIG ? s_sig + g * SLOTS : s_sig;
-        // a table of up to SLOTS slots sized to the row (a power of two when
-        // SLOTS is one, else 2L + 1 with multiply-high hashing); SLOTS exceeds
-        // every row of the class, so the table never fills
-        constexpr bool POW2 = (SLOTS & (SLOTS - 1)) == 0;
-        const uint32_t T = POW2 ? min((uint32_t)SLOTS, pow2_at_least(2u * (uint32_t)(end - beg)))
-                                : min((uint32_t)SLOTS, 2u * (uint32_t)(end - beg) + 1u);
         for (uint32_t t = lane; t < T; t += G) { key[t] = EMPTY_KEY; val[t] = 0; }
         group_sync<G>();
-        aggregate_entries<G, false, SIG, (G >= 1024 ? 8 : UNROLL), !POW2>(a, i, beg + lane, end, key, val, sig,
-                                                                          POW2 ? T - 1u : T, 1u, 0u);
+        aggregate_entries<G, false, false, (G >= 1024 ? 8 : UNROLL), !POW2>(a, i, beg + lane, end, key, val, key,
+                                                                           POW2 ? T - 1u : T, 1u, 0u, EC_GATHER);
         group_sync<G>();
-        scan_table<G, SIG>(a, key, val, sig, lane, T, A, ki, M, best_s, best_c, w_own);
+        scan_table<G, false>(a, key, val, key, lane, T, A, ki, M, best_s, best_c, w_own);
     }
 
     if constexpr (G <= WAVE) {
@@ -417,17 +515,92 @@ __global__ __launch_bounds__(BS) void k_move(MoveArgs a)
     if constexpr (ASYNC) block_flush_sums<BS, uint32_t>(a.gmoves, moved ? move_slot(a, i) : -1, moved ? 1u : 0u);
 }
 
-template <int CLS, int BS, int G, int SLOTS, bool SIG>
+// Later synchronous sweeps: one group of G lanes per vertex, an LDS table of
+// up to SLOTS packed slots per group, each community scored by the lane that
+// claimed its slot with the volume that came with the entry's pair (no scan
+// of the table, no volume array).
+template <int CLS, int BS, int G, int SLOTS>
+__global__ __launch_bounds__(BS) void k_move_claim(MoveArgs a)
+{
+    constexpr int NG = BS / G;
+    constexpr int ME = (CLS_CAP[CLS] + G - 1) / G;  // entries per lane (rows of the class have <= CLS_CAP entries)
+    static_assert(ME >= 1 && ME <= 8, "entries per lane");
+    constexpr bool POW2 = (SLOTS & (SLOTS - 1)) == 0;
+    __shared__ unsigned long long s_tab[NG * SLOTS];
+    __shared__ int64_t rs[BS / WAVE];
+    __shared__ int32_t rc[BS / WAVE], rw[BS / WAVE];
+
+    if (a.ctl->all_done) return;
+    const int ecm = entry_mode(a);
+    const int g = threadIdx.x / G, lane = threadIdx.x % G;
+    const int64_t vi = (int64_t)blockIdx.x * NG + g;
+    const bool has = vi < a.nverts;
+    const int4 row = has ? a.rows[vi] : make_int4(0, 0, 0, 0);
+    const int32_t i = row.x;
+    const bool live = has && !vertex_frozen(a, i) && !vertex_skipped(a, i);
+    const int32_t beg = live ? row.y : 0, end = live ? row.z : 0;
+    const int2 self = live ? a.cs[i] : make_int2(0, 0);
+    const int32_t A = self.x;
+    const int64_t ki = live ? row.w : 0;
+    const int64_t M = live ? vertex_M(a, i) : 0;
+    // a table of min(SLOTS, 2L + 1) slots (a power of two when SLOTS is one);
+    // SLOTS exceeds every row of the class, so it never fills
+    const uint32_t L = (uint32_t)(end - beg);
+    const uint32_t T = POW2 ? min((uint32_t)SLOTS, pow2_at_least(2u * L)) : min((uint32_t)SLOTS, 2u * L + 1u);
+    unsigned long long* tab = s_tab + g * SLOTS;
+    for (uint32_t t = lane; t < T; t += G) tab[t] = EMPTY_SLOT;
+    int2 cc[ME];
+    int32_t ww[ME], slot[ME];
+    load_pairs<G, ME>(a, i, beg + lane, end, ecm, cc, ww);
+    group_sync<G>();
+#pragma unroll
+    for (int u = 0; u < ME; ++u)
+        slot[u] = cc[u].x == EMPTY_KEY ? -1 : claim_or_add<!POW2>(tab, POW2 ? T - 1u : T, cc[u].x, ww[u]);
+    group_sync<G>();
+    const bool louvain = a.mode == MODE_LOUVAIN;
+    int64_t best_s = INT64_MIN;
+    int32_t best_c = INT32_MAX, w_own = 0;
+#pragma unroll
+    for (int u = 0; u < ME; ++u) {
+        if (slot[u] < 0) continue;
+        const int32_t W = (int32_t)(uint32_t)tab[slot[u]];
+        const int32_t C = cc[u].x;
+        if (C == A) { w_own = W; continue; }
+        const int64_t sc = louvain ? M * W - ki * (int64_t)cc[u].y : (int64_t)W;
+        if (better(sc, C, best_s, best_c)) { best_s = sc; best_c = C; }
+    }
+    if constexpr (G <= WAVE) {
+        group_reduce<G>(best_s, best_c, w_own);
+    } else {
+        group_reduce<WAVE>(best_s, best_c, w_own);
+        const int wid = threadIdx.x / WAVE;
+        if (lane_id() == 0) { rs[wid] = best_s; rc[wid] = best_c; rw[wid] = w_own; }
+        __syncthreads();
+        if (lane == 0) {
+            constexpr int WPG = G / WAVE;
+            for (int w = 1; w < WPG; ++w) {
+                const int src = g * WPG + w;
+                if (better(rs[src], rc[src], best_s, best_c)) { best_s = rs[src]; best_c = rc[src]; }
+                w_own = max(w_own, rw[src]);
+            }
+        }
+    }
+    if (has && lane == 0) {
+        if (!live) a.dec[vi] = -1;
+        else decide_store(a, vi, A, self.y, ki, M, best_s, best_c, w_own);
+    }
+}
+
+template <int CLS, int BS, int G, int SLOTS>
 hipError_t launch_move_t(bool singleton, bool async, const MoveArgs& a, hipStream_t s)
 {
     static_assert(SLOTS > CLS_CAP[CLS], "a class's table must hold every distinct community of its longest row");
     if (a.nverts <= 0) return hipSuccess;
     constexpr int NG = BS / G;
     const unsigned grid = (unsigned)((a.nverts + NG - 1) / NG);
-    // asynchronous sweeps read volumes live at scan time (compact tables)
-    if (async) k_move<CLS, BS, G, SLOTS, false, false, true><<<grid, BS, 0, s>>>(a);
-    else if (singleton) k_move<CLS, BS, G, SLOTS, true, false><<<grid, BS, 0, s>>>(a);
-    else k_move<CLS, BS, G, SLOTS, false, SIG><<<grid, BS, 0, s>>>(a);
+    if (async) k_move<CLS, BS, G, SLOTS, MK_ASYNC><<<grid, BS, 0, s>>>(a);
+    else if (singleton) k_move<CLS, BS, G, SLOTS, MK_FIRST><<<grid, BS, 0, s>>>(a);
+    else k_move_claim<CLS, BS, G, SLOTS><<<grid, BS, 0, s>>>(a);
     return hipGetLastError();
 }
 
@@ -495,13 +668,112 @@ __global__ __launch_bounds__(BS) void k_hub_part(MoveArgs a, HubArgs h)
             ok = aggregate_bucket<BS>(h.bucket + at, h.bucket_w + at, (int32_t)threadIdx.x, cnt, s_key, s_val, s_sig,
                                       h.part_mask);
         } else {
+            // every partition reads the whole row; partition 0 fills the cache
+            const int ecm = entry_mode(a);
             ok = aggregate_entries<BS, true, SIG>(a, i, beg + (int32_t)threadIdx.x, end, s_key, s_val, s_sig,
-                                                  h.part_mask, P, part);
+                                                  h.part_mask, P, part,
+                                                  (ecm == EC_FILL && part != 0) ? EC_GATHER : ecm);
         }
         if (!ok) s_over = 1;
         __syncthreads();
         over = s_over;
         if (!over) scan_table<BS, SIG>(a, s_key, s_val, s_sig, threadIdx.x, T, A, ki, M, best_s, best_c, w_own);
+    }
+    block_reduce_best<BS>(best_s, best_c, w_own, rs, rc, rw);
+    if (threadIdx.x == 0) {
+        h.part_score[b] = best_s;
+        h.part_comm[b] = best_c;
+        h.part_wown[b] = w_own;
+        h.part_flag[b] = over;
+    }
+}
+
+// As claim_or_add, but gives up (ok = false) after probing every slot.
+__device__ __forceinline__ int32_t claim_or_add_bounded(unsigned long long* tab, uint32_t mask, int32_t C, int32_t W,
+                                                        bool& ok)
+{
+    const unsigned long long mine = ((unsigned long long)(uint32_t)C << 32) | (uint32_t)W;
+    uint32_t h = mix32(C) & mask;
+    for (uint32_t probes = 0; probes <= mask; ++probes) {
+        const unsigned long long prev = atomicCAS(&tab[h], EMPTY_SLOT, mine);
+        if (prev == EMPTY_SLOT) return (int32_t)h;
+        if ((int32_t)(prev >> 32) == C) {
+            atomicAdd(&tab[h], (unsigned long long)(uint32_t)W);
+            return -1;
+        }
+        h = (h + 1) & mask;
+    }
+    ok = false;
+    return -1;
+}
+
+// Later sweeps of the bucketed partition path: one workgroup per (hub,
+// partition).  Its communities come from the partition's bucket (hubs with
+// P > 1) or, for a hub of one partition, from the row itself; each is summed
+// in a packed LDS table and scored by the thread that claimed its slot, with
+// the volume that came with it.  A bucket offered more than it holds, or a
+// table without room, sends the hub to the global-table fallback.
+template <int BS, int SLOTS>
+__global__ __launch_bounds__(BS) void k_hub_part_claim(MoveArgs a, HubArgs h)
+{
+    constexpr int ME = SLOTS / BS;  // records per thread: a bucket holds at most SLOTS, a row of one partition fewer
+    __shared__ unsigned long long s_tab[SLOTS];
+    __shared__ int64_t rs[BS / WAVE];
+    __shared__ int32_t rc[BS / WAVE], rw[BS / WAVE];
+    __shared__ int32_t s_over;
+    if (a.ctl->all_done) return;
+    const int32_t b = xcd_logical((int32_t)blockIdx.x, h.nblk);
+    const int32_t hh = h.blk_hub[b];
+    const uint32_t P = (uint32_t)h.hub_parts[hh];
+    const int32_t i = h.hub_vert[hh];
+    if (vertex_frozen(a, i) || vertex_skipped(a, i)) {
+        if (threadIdx.x == 0) { h.part_score[b] = INT64_MIN; h.part_comm[b] = INT32_MAX; h.part_wown[b] = 0; h.part_flag[b] = 0; }
+        return;
+    }
+    const int32_t A = a.cs[i].x;
+    const int64_t ki = a.k[i];
+    const int64_t M = vertex_M(a, i);
+    const uint32_t T = h.part_mask + 1u;
+    const int32_t cnt = P > 1 ? h.bucket_cnt[b] : -1;
+    for (uint32_t t = threadIdx.x; t < T; t += BS) s_tab[t] = EMPTY_SLOT;
+    if (threadIdx.x == 0) s_over = 0;
+    int2 cc[ME];
+    int32_t ww[ME], slot[ME];
+    bool ok = cnt <= h.bucket_cap;
+    if (cnt >= 0) {
+        const size_t at = (size_t)b * (size_t)h.bucket_cap;
+        const int32_t n = ok ? cnt : 0;
+#pragma unroll
+        for (int u = 0; u < ME; ++u) {
+            const int32_t t = (int32_t)threadIdx.x + u * BS;
+            cc[u] = t < n ? h.bucket[at + t] : make_int2(EMPTY_KEY, 0);
+            ww[u] = t < n ? h.bucket_w[at + t] : 0;
+        }
+    } else {
+        // one partition: the row has at most part_keys <= 3/4 SLOTS entries
+        load_pairs<BS, ME>(a, i, a.off[i] + (int32_t)threadIdx.x, a.off[i + 1], entry_mode(a), cc, ww);
+    }
+    __syncthreads();
+    if (cnt >= 0 && threadIdx.x == 0) h.bucket_cnt[b] = 0;  // every thread has read it
+#pragma unroll
+    for (int u = 0; u < ME; ++u)
+        slot[u] = cc[u].x == EMPTY_KEY ? -1 : claim_or_add_bounded(s_tab, T - 1u, cc[u].x, ww[u], ok);
+    if (!ok) s_over = 1;
+    __syncthreads();
+    const int32_t over = s_over;
+    int64_t best_s = INT64_MIN;
+    int32_t best_c = INT32_MAX, w_own = 0;
+    if (!over) {
+        const bool louvain = a.mode == MODE_LOUVAIN;
+#pragma unroll
+        for (int u = 0; u < ME; ++u) {
+            if (slot[u] < 0) continue;
+            const int32_t W = (int32_t)(uint32_t)s_tab[slot[u]];
+            const int32_t C = cc[u].x;
+            if (C == A) { w_own = W; continue; }
+            const int64_t sc = louvain ? M * W - ki * (int64_t)cc[u].y : (int64_t)W;
+            if (better(sc, C, best_s, best_c)) { best_s = sc; best_c = C; }
+        }
     }
     block_reduce_best<BS>(best_s, best_c, w_own, rs, rc, rw);
     if (threadIdx.x == 0) {
@@ -573,17 +845,36 @@ __global__ __launch_bounds__(SBS) void k_hub_scatter(MoveArgs a, HubArgs h)
     for (uint32_t t = threadIdx.x; t < P; t += SBS) s_cnt[t] = 0;
     __syncthreads();
     {
-        int32_t jj[SC_EPT], ww[SC_EPT];
+        const int ecm = entry_mode(a);
+        int32_t ww[SC_EPT];
         int2 cc[SC_EPT];
+        if (ecm == EC_READ) {
 #pragma unroll
-        for (int u = 0; u < SC_EPT; ++u) {
-            const int32_t e = e0 + u * SBS + (int32_t)threadIdx.x;
-            const bool ok = e < e1;
-            jj[u] = ok ? __builtin_nontemporal_load(&a.idx[e]) : i;
-            ww[u] = (ok && a.w) ? __builtin_nontemporal_load(&a.w[e]) : 1;
+            for (int u = 0; u < SC_EPT; ++u) {
+                const int32_t e = e0 + u * SBS + (int32_t)threadIdx.x;
+                const bool ok = e < e1;
+                cc[u] = ok ? ce_load(a.ce, e) : make_int2(EMPTY_KEY, 0);
+                ww[u] = (ok && a.w) ? __builtin_nontemporal_load(&a.w[e]) : 1;
+            }
+        } else {
+            int32_t jj[SC_EPT];
+#pragma unroll
+            for (int u = 0; u < SC_EPT; ++u) {
+                const int32_t e = e0 + u * SBS + (int32_t)threadIdx.x;
+                const bool ok = e < e1;
+                jj[u] = ok ? __builtin_nontemporal_load(&a.idx[e]) : i;
+                ww[u] = (ok && a.w) ? __builtin_nontemporal_load(&a.w[e]) : 1;
+            }
+#pragma unroll
+            for (int u = 0; u < SC_EPT; ++u) cc[u] = jj[u] != i ? pair_now(a, jj[u]) : make_int2(EMPTY_KEY, 0);
+            if (ecm == EC_FILL) {
+#pragma unroll
+                for (int u = 0; u < SC_EPT; ++u) {
+                    const int32_t e = e0 + u * SBS + (int32_t)threadIdx.x;
+                    if (e < e1) ce_store(a.ce, e, cc[u]);
+                }
+            }
         }
-#pragma unroll
-        for (int u = 0; u < SC_EPT; ++u) cc[u] = jj[u] != i ? pair_now(a, jj[u]) : make_int2(EMPTY_KEY, 0);
         // at most SBS * EPT distinct keys in twice as many slots: always room
 #pragma unroll
         for (int u = 0; u < SC_EPT; ++u)
@@ -855,9 +1146,14 @@ __global__ __launch_bounds__(256) void k_apply(const int32_t* verts, const int32
 // After sweep s (1-based): a running graph stops when s >= 2 and its last two
 // sweeps moved at most theta vertices each, or when s == max_sweeps.  Sets
 // all_done when no graph runs any more, so later sweeps' kernels exit early.
+// With the entry cache (ec_read_max >= 0) it also chooses how the next sweep
+// gets its pairs: from the cache if the cache holds this sweep's pairs and at
+// most ec_read_max entries saw their pair change in this commit (the refresh
+// that follows rewrites them), else by gathering, filling the cache on the way
+// if at most ec_fill_max entries changed (a later sweep may then read it).
 __global__ __launch_bounds__(256) void k_sweep_end(SweepCtl* ctl, int32_t G, int32_t* gdone, int32_t* gsweeps,
                                                    const uint32_t* gmoves, int32_t max_sweeps, int64_t theta,
-                                                   int32_t consecutive)
+                                                   int32_t consecutive, int64_t ec_read_max, int64_t ec_fill_max)
 {
     __shared__ int32_t red[4];
     if (ctl->all_done) return;
@@ -875,6 +1171,19 @@ __global__ __launch_bounds__(256) void k_sweep_end(SweepCtl* ctl, int32_t G, int
     if (threadIdx.x == 0) {
         ctl->sweep = s;
         ctl->all_done = running == 0 ? 1 : 0;
+        if (ec_read_max >= 0) {
+            const unsigned long long chg = ctl->chg_entries;
+            const bool filled = ctl->ec_mode != EC_GATHER;
+            int32_t next = EC_GATHER;
+            if (filled && chg <= (unsigned long long)ec_read_max) next = EC_READ;
+            else if (chg <= (unsigned long long)ec_fill_max) next = EC_FILL;
+            ctl->ec_mode = next;
+            if (next == EC_READ && running > 0) {
+                ctl->ec_reads += 1;
+                ctl->refreshed += chg;
+            }
+            ctl->chg_entries = 0;
+        }
     }
 }
 
@@ -887,7 +1196,14 @@ __global__ void k_ctl_init(SweepCtl* ctl, int32_t G, const int32_t* gactive, int
         gdone[g] = gactive && !gactive[g] ? 1 : 0;
         gsweeps[g] = 0;
     }
-    if (t0 == 0) { ctl->sweep = 0; ctl->all_done = 0; }
+    if (t0 == 0) {
+        ctl->sweep = 0;
+        ctl->all_done = 0;
+        ctl->ec_mode = EC_GATHER;
+        ctl->ec_reads = 0;
+        ctl->chg_entries = 0;
+        ctl->refreshed = 0;
+    }
 }
 
 // cs[v] = (comm[v], Sigma_tot(comm[v])): the pair a move kernel gathers per
@@ -904,7 +1220,98 @@ __global__ void k_pairs(int32_t n, const int32_t* verts, const int32_t* comm, co
     }
 }
 
+// As k_pairs over the listed vertices (class order), recording whether each
+// slot's pair changed (LPA, whose scores ignore volumes: its label) and the
+// entries of the changed rows.
+__global__ __launch_bounds__(256) void k_pairs_changed(int32_t m, const int4* rows, const int32_t* comm,
+                                                       const int32_t* sigma, int2* cs, uint8_t* chg, int mode,
+                                                       SweepCtl* ctl)
+{
+    __shared__ unsigned long long red[4];
+    if (ctl->all_done) return;
+    unsigned long long cnt = 0;
+    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < m; t += (int64_t)gridDim.x * 256) {
+        const int4 r = rows[t];
+        const int32_t c = comm[r.x];
+        const int2 nw = make_int2(c, sigma[c]);
+        const int2 old = cs[r.x];
+        const bool lab = nw.x != old.x, pair = lab || nw.y != old.y;
+        if (pair) cs[r.x] = nw;
+        const bool ch = mode == MODE_LOUVAIN ? pair : lab;
+        if (ch) cnt += (unsigned long long)(r.z - r.y);
+        chg[t] = ch ? 1 : 0;
+    }
+    cnt = block_sum<256>(cnt, red);
+    if (threadIdx.x == 0 && cnt) atomicAdd(&ctl->chg_entries, cnt);
+}
+
+// Entry-cache refresh (only when the next sweep reads the cache): for every
+// listed vertex v whose pair changed, rewrite the cache entry of each of its
+// neighbours u that refers to v (the reverse of v's entry for u).  Like the
+// move kernels, rows of one degree class get a group of lanes each (at most
+// a 256-thread workgroup), so that the work of a block does not depend on how
+// long the changed rows around it are.
+__global__ __launch_bounds__(256) void k_cache_refresh(RefreshMap mp, const int4* __restrict__ rows,
+                                                       const uint8_t* __restrict__ chg,
+                                                       const int32_t* __restrict__ idx,
+                                                       const int32_t* __restrict__ rev, const int2* __restrict__ cs,
+                                                       int2* __restrict__ ce, const SweepCtl* ctl)
+{
+    if (ctl->all_done || ctl->ec_mode != EC_READ) return;
+    const int32_t b = (int32_t)blockIdx.x;
+    int c = 0;
+    while (c + 1 < mp.nclass && mp.blk_first[c + 1] <= b) ++c;
+    const int lg = mp.lanes_log2[c];
+    const int32_t G = 1 << lg, NG = 256 >> lg;
+    const int32_t g = (int32_t)threadIdx.x >> lg, lane = (int32_t)threadIdx.x & (G - 1);
+    const int64_t t = (int64_t)mp.slot_first[c] + (int64_t)(b - mp.blk_first[c]) * NG + g;
+    if (t >= mp.slot_end[c] || !chg[t]) return;
+    const int4 r = rows[t];
+    const int2 p = cs[r.x];
+    for (int32_t e = r.y + lane; e < r.z; e += G) {
+        const int32_t u = __builtin_nontemporal_load(&idx[e]);
+        if (u != r.x) ce[rev[e]] = p;
+    }
+}
+
+// The same for the hubs: workgroup b takes one 4096-entry chunk of a hub's row.
+__global__ __launch_bounds__(256) void k_hub_cache_refresh(MoveArgs a, HubArgs h, const uint8_t* chg_hub,
+                                                           const int32_t* __restrict__ rev)
+{
+    if (a.ctl->all_done || a.ctl->ec_mode != EC_READ) return;
+    const int32_t hh = h.mk_hub[blockIdx.x];
+    if (!chg_hub[hh]) return;
+    const int32_t v = h.hub_vert[hh];
+    const int2 p = a.cs[v];
+    for (int32_t e = h.mk_beg[blockIdx.x] + (int32_t)threadIdx.x; e < h.mk_end[blockIdx.x]; e += 256) {
+        const int32_t u = __builtin_nontemporal_load(&a.idx[e]);
+        if (u != v) a.ce[rev[e]] = p;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_pairs_changed(int32_t m, const int4* rows, const int32_t* comm, const int32_t* sigma, int2* cs,
+                                uint8_t* chg, int mode, SweepCtl* ctl, hipStream_t s)
+{
+    if (m <= 0) return hipSuccess;
+    k_pairs_changed<<<grid_for(m, 256, 8192), 256, 0, s>>>(m, rows, comm, sigma, cs, chg, mode, ctl);
+    return hipGetLastError();
+}
+hipError_t launch_cache_refresh(const RefreshMap& mp, const int4* rows, const uint8_t* chg, const int32_t* idx,
+                                const int32_t* rev, const int2* cs, int2* ce, SweepCtl* ctl, hipStream_t s)
+{
+    if (mp.nclass <= 0 || mp.blk_first[mp.nclass] <= 0) return hipSuccess;
+    k_cache_refresh<<<(unsigned)mp.blk_first[mp.nclass], 256, 0, s>>>(mp, rows, chg, idx, rev, cs, ce, ctl);
+    return hipGetLastError();
+}
+hipError_t launch_hub_cache_refresh(const MoveArgs& a, const HubArgs& h, const uint8_t* chg_hub, const int32_t* rev,
+                                    hipStream_t s)
+{
+    if (h.nmk <= 0) return hipSuccess;
+    k_hub_cache_refresh<<<(unsigned)h.nmk, 256, 0, s>>>(a, h, chg_hub, rev);
+    return hipGetLastError();
+}
 
 hipError_t launch_mark_movers(const int4* rows, const int32_t* dec, int32_t m, const int32_t* idx, int32_t* mark,
                               const SweepCtl* ctl, hipStream_t s)
@@ -936,9 +1343,11 @@ hipError_t launch_ctl_init(SweepCtl* ctl, int32_t G, const int32_t* gactive, int
     return hipGetLastError();
 }
 hipError_t launch_sweep_end(SweepCtl* ctl, int32_t G, int32_t* gdone, int32_t* gsweeps, const uint32_t* gmoves,
-                            int32_t max_sweeps, int64_t theta, int32_t consecutive, hipStream_t s)
+                            int32_t max_sweeps, int64_t theta, int32_t consecutive, int64_t ec_read_max,
+                            int64_t ec_fill_max, hipStream_t s)
 {
-    k_sweep_end<<<1, 256, 0, s>>>(ctl, G, gdone, gsweeps, gmoves, max_sweeps, theta, consecutive);
+    k_sweep_end<<<1, 256, 0, s>>>(ctl, G, gdone, gsweeps, gmoves, max_sweeps, theta, consecutive, ec_read_max,
+                                  ec_fill_max);
     return hipGetLastError();
 }
 
@@ -986,22 +1395,22 @@ hipError_t launch_gather_rows(const int32_t* verts, int32_t m, const int32_t* of
 hipError_t launch_move_class(int cls, bool singleton, bool async, const MoveArgs& a, hipStream_t s)
 {
     switch (cls) {
-    case CLS_L4: return launch_move_t<CLS_L4, 256, 4, 8, true>(singleton, async, a, s);
-    case CLS_L8: return launch_move_t<CLS_L8, 256, 8, 16, true>(singleton, async, a, s);
-    case CLS_L32: return launch_move_t<CLS_L32, 256, 16, 64, true>(singleton, async, a, s);
+    case CLS_L4: return launch_move_t<CLS_L4, 256, 4, 8>(singleton, async, a, s);
+    case CLS_L8: return launch_move_t<CLS_L8, 256, 8, 16>(singleton, async, a, s);
+    case CLS_L32: return launch_move_t<CLS_L32, 256, 16, 64>(singleton, async, a, s);
     // 1664-1696 slots of 12 bytes per 256-thread workgroup (<= 20 KiB), 3392 per
     // 512-thread workgroup (<= 40 KiB): eight wavefronts a SIMD.  Rows of
     // 2049-3072 entries keep 4096 slots (six wavefronts a SIMD): at their load
     // a 3392-slot table probes longer than the extra workgroup gains.
-    case CLS_L128: return launch_move_t<CLS_L128, 256, 32, 208, true>(singleton, async, a, s);
-    case CLS_L256: return launch_move_t<CLS_L256, 256, 64, 424, true>(singleton, async, a, s);
-    case CLS_L512: return launch_move_t<CLS_L512, 256, 128, 848, true>(singleton, async, a, s);
-    case CLS_L1K: return launch_move_t<CLS_L1K, 256, 256, 1696, true>(singleton, async, a, s);
-    case CLS_L2K: return launch_move_t<CLS_L2K, 512, 512, 3392, true>(singleton, async, a, s);
-    case CLS_L3K: return launch_move_t<CLS_L3K, 512, 512, 4096, true>(singleton, async, a, s);
+    case CLS_L128: return launch_move_t<CLS_L128, 256, 32, 208>(singleton, async, a, s);
+    case CLS_L256: return launch_move_t<CLS_L256, 256, 64, 424>(singleton, async, a, s);
+    case CLS_L512: return launch_move_t<CLS_L512, 256, 128, 848>(singleton, async, a, s);
+    case CLS_L1K: return launch_move_t<CLS_L1K, 256, 256, 1696>(singleton, async, a, s);
+    case CLS_L2K: return launch_move_t<CLS_L2K, 512, 512, 3392>(singleton, async, a, s);
+    case CLS_L3K: return launch_move_t<CLS_L3K, 512, 512, 4096>(singleton, async, a, s);
     // 10112 8-byte slots (79 KiB): two workgroups fit a CU's 160 KiB, and every row of the class
     // (at most 8192 entries) leaves free slots
-    case CLS_L8K: return launch_move_t<CLS_L8K, 1024, 1024, L8K_SLOTS, false>(singleton, async, a, s);
+    case CLS_L8K: return launch_move_t<CLS_L8K, 1024, 1024, L8K_SLOTS>(singleton, async, a, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -1034,6 +1443,7 @@ hipError_t launch_hub_sweep(bool singleton, const MoveArgs& a, const HubArgs& h,
     if (h.nhubs <= 0) return hipSuccess;
     if (h.bucketed) {
         if (singleton) k_hub_part<true, false, BBS, 1><<<(unsigned)h.nblk, BBS, 0, s>>>(a, h);
+        else if (!a.live_comm) k_hub_part_claim<BBS, BSLOTS><<<(unsigned)h.nblk, BBS, 0, s>>>(a, h);
         else k_hub_part<false, true, BBS, BSLOTS><<<(unsigned)h.nblk, BBS, 0, s>>>(a, h);
     } else if (singleton) {
         k_hub_part<true, false, PBS, 1><<<(unsigned)h.nblk, PBS, 0, s>>>(a, h);

@@ -3,15 +3,20 @@ benchmark times (captured sweeps, every degree class, the bucketed partition
 path), against the oracle: every label and every per-sweep move count.
 
 - R-MAT 24 (520.8 M entries) and LFR with 10 M vertices: level 0's local
-  moving (all of its sweeps) and LPA.  The oracle's sweeps take a second or
-  two each; its aggregation at these sizes would take minutes, so Louvain
-  stops after level 0.
+  moving (all of its sweeps) and LPA against the oracle run here.
+- R-MAT 24, every level: the complete multi-level Louvain (and LPA) against
+  per-level digests the oracle wrote beforehand (tests/golden/
+  make_rmat24_digests.py; six minutes of CPU): sizes, Q_int, per-sweep move
+  counts, SHA-256 of every level's labels and of every coarse graph.
 - The 4,096-graph batch (about 1.15e9 entries in one handle): complete
   Louvain on the device, twelve evenly spaced graphs against the oracle run
   on each graph alone.
 - The serving pool (32 R-MAT graphs of 10 k to 4 M vertices) through one
   server at once: every job against a one-graph-per-call run, and every job
   of up to 12 M entries against the oracle."""
+import hashlib
+import json
+import os
 import sys
 
 import numpy as np
@@ -56,6 +61,47 @@ def test_rmat24_level0_louvain(rmat24):
     assert np.array_equal(lvl.labels, want)
     assert np.array_equal(got.final_labels, want)
     assert (lvl.info["q_end"], got.M) == (q_want, m_want)
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "rmat24_seed2_digests.json")
+
+
+def sha(*arrays) -> str:
+    h = hashlib.sha256()
+    for a in arrays:
+        h.update(np.ascontiguousarray(a, dtype="<i4").tobytes())
+    return h.hexdigest()
+
+
+@pytest.mark.timeout(900)
+def test_rmat24_every_level_against_golden_digests(rmat24):
+    g, _ = rmat24
+    with open(GOLDEN) as fh:
+        gold = json.load(fh)
+    assert (g.n, g.nnz) == (gold["n"], gold["nnz"])
+    want = gold["louvain"]
+    say(f"GPU: Louvain, every level, coarse graphs kept; {len(want['levels'])} levels in the digests")
+    with lvp.Graph.from_csr(g, validate=False) as dg:
+        got = lvp.louvain(dg, max_sweeps=gold["max_sweeps"], keep_graphs=True)
+        lp = lvp.lpa(dg, max_sweeps=gold["max_sweeps"])
+    assert (got.M, got.q_int) == (want["M"], want["q_int"])
+    assert len(got.levels) == len(want["levels"])
+    for lvl, (a, b) in enumerate(zip(got.levels, want["levels"])):
+        say(f"level {lvl}: n={a.info['n']} nnz={a.info['nnz']} sweeps={a.info['sweeps']} "
+            f"cached={a.info['cached_sweeps']}")
+        i = a.info
+        assert (i["n"], i["nnz"], i["n_next"], i["q_start"], i["q_end"], bool(i["accepted"])) == \
+            (b["n"], b["nnz"], b["n_next"], b["q_start"], b["q_end"], b["accepted"]), f"level {lvl}"
+        assert a.moves == b["moves"], f"level {lvl} moves"
+        if b["accepted"]:
+            assert sha(a.labels) == b["labels_sha256"], f"level {lvl} labels"
+            off, idx, w = a.graph
+            assert len(idx) == b["coarse_nnz"], f"level {lvl} coarse entries"
+            assert sha(off, idx, w) == b["coarse_sha256"], f"level {lvl} coarse graph"
+    assert sha(got.final_labels) == want["final_labels_sha256"]
+    assert lp.moves == gold["lpa"]["moves"]
+    assert sha(lp.labels) == gold["lpa"]["labels_sha256"]
+    assert lp.info["q_end"] == gold["lpa"]["q_int"]
 
 
 @pytest.mark.timeout(600)
