@@ -365,6 +365,22 @@ lv_status lv_probe_copy(lv_graph* g, int32_t reps, double* bytes_per_s);
 lv_status lv_modularity(lv_graph* g, const int32_t* labels, lv_memkind kind, int64_t* q_int,
                         int64_t* m, double* q);
 
+/*
+ * lv_modularity for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * (Q_int, M, Q) for labels int32[n] in DEVICE memory, computed without any
+ * allocation.  Its scratch memory (12 bytes per vertex + 256) is a fixed
+ * device array of LV_NOALLOC_SCRATCH_BYTES that every GPU the library runs
+ * on holds until the process ends, so n is limited to
+ * (LV_NOALLOC_SCRATCH_BYTES - 256) / 12 vertices (LV_E_TOO_LARGE beyond).
+ * Calls on one GPU share that array: calls that overlap on one GPU race (run
+ * them one at a time per device).  The handle's device must be current
+ * (LV_E_STATE otherwise); labels outside [0, n) give LV_E_ARG.  Reads the
+ * three results back with one synchronous copy.
+ */
+#define LV_NOALLOC_SCRATCH_BYTES (64u << 20)
+lv_status lv_modularity_noalloc(lv_graph* g, const int32_t* labels, int64_t* q_int, int64_t* m, double* q);
+
 /* ---------------------------------------------------------------------------
  * Serving loop (continuous batching).  A server owns a worker thread and a
  * stream on the current device.  Jobs (CSR graphs, same conventions as

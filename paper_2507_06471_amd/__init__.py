@@ -156,6 +156,7 @@ SIGNATURES = {
     "lv_graph_csr": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i64p, ctypes.c_int]),
     "lv_probe_gather": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
     "lv_probe_copy": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
+    "lv_modularity_noalloc": (ctypes.c_int, [_vp, _vp, _i64p, _i64p, ctypes.POINTER(ctypes.c_double)]),
 }
 
 _lib = None
@@ -573,6 +574,21 @@ def modularity(graph: Graph, labels):
     qi, m, q = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_double()
     _check(lib.lv_modularity(graph.handle, pl, kind, ctypes.byref(qi), ctypes.byref(m), ctypes.byref(q)),
            "lv_modularity")
+    return qi.value, m.value, q.value
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def modularity_noalloc(graph: Graph, labels):
+    """lv_modularity_noalloc -> (Q_int, M, Q); labels: a device int32 tensor of n entries."""
+    lib = load_library()
+    pl, kind = _ptr(labels)
+    if kind != LV_MEM_DEVICE:
+        raise ValueError("lv_modularity_noalloc takes device labels")
+    qi, m, q = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_double()
+    _check(lib.lv_modularity_noalloc(graph.handle, pl, ctypes.byref(qi), ctypes.byref(m), ctypes.byref(q)),
+           "lv_modularity_noalloc")
     return qi.value, m.value, q.value
 
 

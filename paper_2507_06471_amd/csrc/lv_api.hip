@@ -17,6 +17,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <initializer_list>
@@ -2510,3 +2511,4 @@ lv_status lv_lpa(lv_graph* g, const lv_params* params, int32_t* labels, lv_memki
 }  // extern "C"
 
 #include "lv_server.inc"
+#include "lv_noalloc.inc"
