@@ -783,41 +783,43 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
     };
     const bool use_graph = !timing && !(p.flags & LV_NO_HIPGRAPH);
     if (use_graph) {
-        // capture the first sweep and a later sweep once, then replay: the
-        // kernels read the sweep counter and early-exit flag from the device
-        hipGraph_t gr[2] = {nullptr, nullptr};
-        hipGraphExec_t ex[2] = {nullptr, nullptr};
-        lv_status st = LV_OK;
-        for (int q = 0; q < 2 && st == LV_OK; ++q) {
-            hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
-            if (e != hipSuccess) { set_error("hipStreamBeginCapture", e); st = from_hip(e); break; }
-            st = launch_sweep(q == 0, nullptr);
-            hipGraph_t gq = nullptr;
-            e = hipStreamEndCapture(s, &gq);
-            if (st == LV_OK && e != hipSuccess) { set_error("hipStreamEndCapture", e); st = from_hip(e); }
-            gr[q] = gq;
-            if (st == LV_OK) {
-                e = hipGraphInstantiate(&ex[q], gr[q], nullptr, nullptr, 0);
-                if (e != hipSuccess) { set_error("hipGraphInstantiate", e); st = from_hip(e); }
-            }
-        }
+        // The first sweep (every community a single vertex) is launched
+        // directly; while it runs, a later sweep is captured once and then
+        // replayed up to max_sweeps - 1 times: the kernels read the sweep
+        // counter and early-exit flag from the device.
         Timer ph;
         ph.s = s;
         hipEvent_t p0{}, p1{};
-        if (st == LV_OK) {
-            HIP_TRY(ph.mark(&p0));
-            for (int32_t sw = 1; sw <= S && st == LV_OK; ++sw) {
-                hipError_t e = hipGraphLaunch(ex[sw == 1 ? 0 : 1], s);
+        HIP_TRY(ph.mark(&p0));
+        LV_TRY(launch_sweep(true, nullptr));
+        hipGraph_t gr = nullptr;
+        hipGraphExec_t ex = nullptr;
+        lv_status st = LV_OK;
+        if (S > 1) {
+            hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) { set_error("hipStreamBeginCapture", e); st = from_hip(e); }
+            if (st == LV_OK) {
+                st = launch_sweep(false, nullptr);
+                e = hipStreamEndCapture(s, &gr);
+                if (st == LV_OK && e != hipSuccess) { set_error("hipStreamEndCapture", e); st = from_hip(e); }
+            }
+            if (st == LV_OK) {
+                e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+                if (e != hipSuccess) { set_error("hipGraphInstantiate", e); st = from_hip(e); }
+            }
+            for (int32_t sw = 2; sw <= S && st == LV_OK; ++sw) {
+                e = hipGraphLaunch(ex, s);
                 if (e != hipSuccess) { set_error("hipGraphLaunch", e); st = from_hip(e); }
             }
-            if (st == LV_OK) HIP_TRY(ph.mark(&p1));
+        }
+        if (st == LV_OK) {
+            hipError_t e = ph.mark(&p1);
+            if (e != hipSuccess) { set_error("hipEventRecord", e); st = from_hip(e); }
         }
         hipError_t es = hipStreamSynchronize(s);
         if (st == LV_OK && es == hipSuccess) out.sweep_ms = elapsed(p0, p1);
-        for (int q = 0; q < 2; ++q) {
-            if (ex[q]) (void)hipGraphExecDestroy(ex[q]);
-            if (gr[q]) (void)hipGraphDestroy(gr[q]);
-        }
+        if (ex) (void)hipGraphExecDestroy(ex);
+        if (gr) (void)hipGraphDestroy(gr);
         LV_TRY(st);
         HIP_TRY(es);
     } else {

@@ -819,20 +819,17 @@ __global__ __launch_bounds__(256) void k_hub_finalize(MoveArgs a, HubArgs h)
 }
 
 // Scatter the entries of hubs with P > 1 into their partitions' buckets.  A
-// workgroup takes a chunk of a row, sums its entries per community in LDS
-// (so a community shared by many neighbours costs one bucket entry per
-// chunk), and appends each (community, volume, weight sum) to the bucket of
-// the community's partition.  Positions inside a bucket depend on timing; the
-// sums a partition workgroup forms from them do not.
+// workgroup takes a chunk of a row and sums its entries per community in a
+// packed LDS table (so a community shared by many neighbours costs one bucket
+// entry per chunk); the thread that claimed a community's slot appends
+// (community, volume, weight sum) to the bucket of the community's partition.
+// Positions inside a bucket depend on timing; the sums a partition workgroup
+// forms from them do not.
 template <int SBS, int EPT>
 __global__ __launch_bounds__(SBS) void k_hub_scatter(MoveArgs a, HubArgs h)
 {
-    constexpr int SC_EPT = EPT;
-    constexpr int SC_SLOTS = 2 * SBS * EPT;
-    constexpr int SC_SPT = 2 * EPT;
-    __shared__ int32_t t_key[SC_SLOTS];
-    __shared__ int32_t t_val[SC_SLOTS];
-    __shared__ int32_t t_sig[SC_SLOTS];
+    constexpr int SC_SLOTS = 2 * SBS * EPT;  // at most SBS * EPT keys: always room
+    __shared__ unsigned long long t_tab[SC_SLOTS];
     __shared__ int32_t s_cnt[HUB_PMAX];  // per-partition counts, then bucket bases
     if (a.ctl->all_done) return;
     const int b = blockIdx.x;
@@ -841,57 +838,51 @@ __global__ __launch_bounds__(SBS) void k_hub_scatter(MoveArgs a, HubArgs h)
     if (vertex_frozen(a, i) || vertex_skipped(a, i)) return;
     const uint32_t P = (uint32_t)h.hub_parts[hh];
     const int32_t e0 = h.sc_beg[b], e1 = h.sc_end[b];
-    for (uint32_t t = threadIdx.x; t < (uint32_t)SC_SLOTS; t += SBS) { t_key[t] = EMPTY_KEY; t_val[t] = 0; }
+    for (uint32_t t = threadIdx.x; t < (uint32_t)SC_SLOTS; t += SBS) t_tab[t] = EMPTY_SLOT;
     for (uint32_t t = threadIdx.x; t < P; t += SBS) s_cnt[t] = 0;
-    __syncthreads();
-    {
-        const int ecm = entry_mode(a);
-        int32_t ww[SC_EPT];
-        int2 cc[SC_EPT];
-        if (ecm == EC_READ) {
+    const int ecm = entry_mode(a);
+    int32_t ww[EPT], slot[EPT], rk[EPT];
+    uint32_t pp[EPT];
+    int2 cc[EPT];
+    if (ecm == EC_READ) {
 #pragma unroll
-            for (int u = 0; u < SC_EPT; ++u) {
+        for (int u = 0; u < EPT; ++u) {
+            const int32_t e = e0 + u * SBS + (int32_t)threadIdx.x;
+            const bool ok = e < e1;
+            cc[u] = ok ? ce_load(a.ce, e) : make_int2(EMPTY_KEY, 0);
+            ww[u] = (ok && a.w) ? __builtin_nontemporal_load(&a.w[e]) : 1;
+        }
+    } else {
+        int32_t jj[EPT];
+#pragma unroll
+        for (int u = 0; u < EPT; ++u) {
+            const int32_t e = e0 + u * SBS + (int32_t)threadIdx.x;
+            const bool ok = e < e1;
+            jj[u] = ok ? __builtin_nontemporal_load(&a.idx[e]) : i;
+            ww[u] = (ok && a.w) ? __builtin_nontemporal_load(&a.w[e]) : 1;
+        }
+#pragma unroll
+        for (int u = 0; u < EPT; ++u) cc[u] = jj[u] != i ? pair_now(a, jj[u]) : make_int2(EMPTY_KEY, 0);
+        if (ecm == EC_FILL) {
+#pragma unroll
+            for (int u = 0; u < EPT; ++u) {
                 const int32_t e = e0 + u * SBS + (int32_t)threadIdx.x;
-                const bool ok = e < e1;
-                cc[u] = ok ? ce_load(a.ce, e) : make_int2(EMPTY_KEY, 0);
-                ww[u] = (ok && a.w) ? __builtin_nontemporal_load(&a.w[e]) : 1;
-            }
-        } else {
-            int32_t jj[SC_EPT];
-#pragma unroll
-            for (int u = 0; u < SC_EPT; ++u) {
-                const int32_t e = e0 + u * SBS + (int32_t)threadIdx.x;
-                const bool ok = e < e1;
-                jj[u] = ok ? __builtin_nontemporal_load(&a.idx[e]) : i;
-                ww[u] = (ok && a.w) ? __builtin_nontemporal_load(&a.w[e]) : 1;
-            }
-#pragma unroll
-            for (int u = 0; u < SC_EPT; ++u) cc[u] = jj[u] != i ? pair_now(a, jj[u]) : make_int2(EMPTY_KEY, 0);
-            if (ecm == EC_FILL) {
-#pragma unroll
-                for (int u = 0; u < SC_EPT; ++u) {
-                    const int32_t e = e0 + u * SBS + (int32_t)threadIdx.x;
-                    if (e < e1) ce_store(a.ce, e, cc[u]);
-                }
+                if (e < e1) ce_store(a.ce, e, cc[u]);
             }
         }
-        // at most SBS * EPT distinct keys in twice as many slots: always room
-#pragma unroll
-        for (int u = 0; u < SC_EPT; ++u)
-            if (cc[u].x != EMPTY_KEY) lds_insert<true>(t_key, t_val, t_sig, SC_SLOTS - 1, cc[u].x, ww[u], cc[u].y);
     }
     __syncthreads();
-    uint32_t pp[SC_SPT];
-    int32_t rk[SC_SPT];
 #pragma unroll
-    for (int u = 0; u < SC_SPT; ++u) {
-        const int32_t C = t_key[u * SBS + threadIdx.x];
-        pp[u] = 0;
+    for (int u = 0; u < EPT; ++u)
+        slot[u] = cc[u].x == EMPTY_KEY ? -1 : claim_or_add<false>(t_tab, SC_SLOTS - 1, cc[u].x, ww[u]);
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
         rk[u] = -1;
-        if (C != EMPTY_KEY) {
-            pp[u] = part_of(C, P);
-            rk[u] = atomicAdd(&s_cnt[pp[u]], 1);
-        }
+        if (slot[u] < 0) continue;
+        ww[u] = (int32_t)(uint32_t)t_tab[slot[u]];  // the community's weight sum in this chunk
+        pp[u] = part_of(cc[u].x, P);
+        rk[u] = atomicAdd(&s_cnt[pp[u]], 1);
     }
     __syncthreads();
     int32_t* cnt = h.bucket_cnt + h.hub_first_blk[hh];
@@ -903,14 +894,13 @@ __global__ __launch_bounds__(SBS) void k_hub_scatter(MoveArgs a, HubArgs h)
     const size_t cap = (size_t)h.bucket_cap;
     const size_t first = (size_t)h.hub_first_blk[hh];
 #pragma unroll
-    for (int u = 0; u < SC_SPT; ++u) {
+    for (int u = 0; u < EPT; ++u) {
         if (rk[u] < 0) continue;
         const int32_t pos = s_cnt[pp[u]] + rk[u];
         if (pos >= h.bucket_cap) continue;  // the partition's workgroup flags the overflow
-        const int32_t t = u * SBS + threadIdx.x;
         const size_t at = (first + pp[u]) * cap + (size_t)pos;
-        h.bucket[at] = make_int2(t_key[t], t_sig[t]);
-        h.bucket_w[at] = t_val[t];
+        h.bucket[at] = cc[u];
+        h.bucket_w[at] = ww[u];
     }
 }
 
@@ -1055,15 +1045,16 @@ __global__ __launch_bounds__(256) void k_hub_mark(MoveArgs a, HubArgs h, int32_t
 
 // ------------------------------------------------------------------ commit (K7)
 // Apply the decisions of the m listed vertices: labels and community
-// volumes (LPA's modularity reads the volumes too).  A wavefront sums its
-// volume changes per community (integer sums, so order is irrelevant) and
-// adds them into the workgroup's LDS table; the table is added into the
-// volumes once at the end, so a community that many movers leave or join
-// costs one global atomic per workgroup.  A change that finds no table slot
-// within APPLY_PROBE probes, or arrives once the table holds APPLY_FILL
-// communities (a workgroup whose movers touch many communities gains
-// nothing from it), is added globally at once.  The movers of graph g in this
-// sweep are counted in gmoves[g * max_sweeps + sweep].
+// volumes (LPA's modularity reads the volumes too).  Every mover adds its
+// volume change for the community it leaves and the one it joins into the
+// workgroup's LDS table (integer sums, so order is irrelevant; see
+// peeled_apply); the table is added into the volumes once at the end, so a
+// community that many movers leave or join costs one global atomic per
+// workgroup.  A change that finds no table slot within APPLY_PROBE probes,
+// or is for a community not yet in the table once it holds APPLY_FILL
+// communities (a workgroup whose movers touch many communities gains nothing
+// from more), is added globally at once.  The movers of graph g in this sweep
+// are counted in gmoves[g * max_sweeps + sweep].
 constexpr int APPLY_SLOTS = 4096;
 constexpr int APPLY_PROBE = 16;
 constexpr int APPLY_FILL = APPLY_SLOTS * 3 / 4;
@@ -1071,33 +1062,40 @@ constexpr int APPLY_FILL = APPLY_SLOTS * 3 / 4;
 __device__ __forceinline__ void apply_add(int32_t* key, int32_t* val, int32_t* fill, int32_t* sigma, int32_t C,
                                           int32_t d)
 {
-    if (*(volatile int32_t*)fill < APPLY_FILL) {
-        uint32_t h = mix32(C) & (uint32_t)(APPLY_SLOTS - 1);
-        for (int p = 0; p < APPLY_PROBE; ++p) {
+    // a community already in the table always adds there; a new one takes
+    // a slot only while the table holds fewer than APPLY_FILL communities
+    uint32_t h = mix32(C) & (uint32_t)(APPLY_SLOTS - 1);
+    for (int p = 0; p < APPLY_PROBE; ++p) {
+        const int32_t k = *(volatile int32_t*)&key[h];
+        if (k == C) { atomicAdd(&val[h], d); return; }
+        if (k == EMPTY_KEY) {
+            if (*(volatile int32_t*)fill >= APPLY_FILL) break;
             const int32_t prev = atomicCAS(&key[h], EMPTY_KEY, C);
             if (prev == EMPTY_KEY) atomicAdd(fill, 1);
             if (prev == EMPTY_KEY || prev == C) { atomicAdd(&val[h], d); return; }
-            h = (h + 1) & (uint32_t)(APPLY_SLOTS - 1);
         }
+        h = (h + 1) & (uint32_t)(APPLY_SLOTS - 1);
     }
     atomicAdd(&sigma[C], d);
 }
 
-// As wave_grouped_add, into the LDS table.
-__device__ __forceinline__ void wave_grouped_apply(int32_t* key, int32_t* val, int32_t* fill, int32_t* sigma,
-                                                   int32_t C, int32_t d, bool valid)
+// Add d to community C for every valid lane: the lanes that share the first
+// valid lane's community are summed into one add (movers crowding into one
+// large community), every other lane adds on its own (the LDS atomics sort
+// out any further collisions).  Reached by all lanes of the wavefront.
+__device__ __forceinline__ void peeled_apply(int32_t* key, int32_t* val, int32_t* fill, int32_t* sigma, int32_t C,
+                                             int32_t d, bool valid)
 {
-    uint64_t pending = __ballot(valid);
-    while (pending) {
-        const int leader = __ffsll((unsigned long long)pending) - 1;
-        const int32_t lc = __shfl(C, leader);
-        const uint64_t grp = __ballot(valid && C == lc) & pending;
-        int32_t c = ((grp >> lane_id()) & 1ull) ? d : 0;
+    const uint64_t any = __ballot(valid);
+    if (!any) return;
+    const int leader = __ffsll((unsigned long long)any) - 1;
+    const int32_t lc = __shfl(C, leader);
+    const bool mine = valid && C == lc;
+    int32_t c = mine ? d : 0;
 #pragma unroll
-        for (int m = 32; m >= 1; m >>= 1) c += __shfl_xor(c, m);
-        if ((int)lane_id() == leader && c) apply_add(key, val, fill, sigma, lc, c);
-        pending &= ~grp;
-    }
+    for (int m = 32; m >= 1; m >>= 1) c += __shfl_xor(c, m);
+    if ((int)lane_id() == leader && c) apply_add(key, val, fill, sigma, lc, c);
+    if (valid && !mine && d) apply_add(key, val, fill, sigma, C, d);
 }
 
 __global__ __launch_bounds__(256) void k_apply(const int32_t* verts, const int32_t* dec, int32_t m, const int32_t* k,
@@ -1133,8 +1131,8 @@ __global__ __launch_bounds__(256) void k_apply(const int32_t* verts, const int32
             comm[v] = C;
         }
         if (__ballot(valid)) {
-            wave_grouped_apply(t_key, t_val, &t_fill, sigma, C, kv, valid);
-            wave_grouped_apply(t_key, t_val, &t_fill, sigma, A, -kv, valid);
+            peeled_apply(t_key, t_val, &t_fill, sigma, C, kv, valid);
+            peeled_apply(t_key, t_val, &t_fill, sigma, A, -kv, valid);
         }
     }
     __syncthreads();
