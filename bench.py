@@ -261,14 +261,24 @@ def batch_leg(args, lvp, graphgen, np, torch):
     log(f"batch: packed handle resident in {time.time() - t:.1f}s")
     cfg, est = lvp.autotune(bg)
     log(f"batch: autotuned {cfg} (estimated level-0 {est:.1f} ms)")
-    fp = lvp.louvain_final(bg, autotuned=True)  # warm-up
-    reps = []
-    for _ in range(args.batch_reps):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        fp = lvp.louvain_final(bg, autotuned=True)
-        reps.append(time.perf_counter() - t0)
-    batch_s = float(np.median(reps))
+
+    def timed(**kw):
+        fp_ = lvp.louvain_final(bg, **kw)  # warm-up
+        ts = []
+        for _ in range(args.batch_reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fp_ = lvp.louvain_final(bg, **kw)
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts)), fp_
+
+    # the two ways of launching the later sweeps' classes, at default settings
+    per_class_s, fp_pc = timed(tuning={"fused": 0})
+    fused_s, fp_f = timed(tuning={"fused": 1})
+    launch_cmp = {"per_class_launches_ms": round(per_class_s * 1e3, 2), "fused_persistent_ms": round(fused_s * 1e3, 2),
+                  "same_partitions": bool(np.array_equal(fp_pc.labels, fp_f.labels))}
+    log(f"batch: {launch_cmp}")
+    batch_s, fp = timed(autotuned=True)
     # entries processed by local moving, from a timed run's per-level counts
     # (per graph: sum over levels of entries x sweeps)
     detail = lvp.louvain(bg, autotuned=True)
@@ -297,8 +307,8 @@ def batch_leg(args, lvp, graphgen, np, torch):
                     "unit weights, seed 4",
         "graphs": len(gs), "vertices": V, "entries": E,
         "batched": {"ms": round(batch_s * 1e3, 2), "graphs_per_s": round(len(gs) / batch_s, 1),
-                    "local_move_gteps": round(lm_entries / batch_s / 1e9, 3), "reps": len(reps),
-                    "tuning": cfg},
+                    "local_move_gteps": round(lm_entries / batch_s / 1e9, 3), "reps": args.batch_reps,
+                    "tuning": cfg, "autotune_estimate_ms": round(est, 2), "launch_modes": launch_cmp},
         "one_graph_per_call": {"sample_graphs": len(sample), "ms": round(single_s * 1e3, 2),
                                "graphs_per_s": round(len(sample) / single_s, 1),
                                "local_move_gteps": round(sample_entries / single_s / 1e9, 3)},
@@ -306,7 +316,7 @@ def batch_leg(args, lvp, graphgen, np, torch):
     }
     out["speedup_graphs_per_s"] = round(out["batched"]["graphs_per_s"] / out["one_graph_per_call"]["graphs_per_s"], 2)
     log(f"batch: {out}")
-    if not same:
+    if not same or not launch_cmp["same_partitions"]:
         print("batched partitions differ from one-graph-per-call partitions", file=sys.stderr, flush=True)
         sys.exit(1)
     return out

@@ -145,6 +145,12 @@ typedef struct lv_tuning {
                         /* percentage of the level's entries saw their pair change in the */
                         /* last commit (0 = 10, at most 100); a sweep fills it when at    */
                         /* most min(100, 2 cache_pct + 5) percent changed                  */
+    int32_t fused;      /* later sweeps: 1 = every class below block_max in one persistent */
+                        /* launch (1024-thread workgroups taking blocks of rows of any    */
+                        /* class from a device counter); 0 = one launch per class          */
+    int32_t table_pct;  /* LDS table slots per row of L entries in later sweeps: about    */
+                        /* L * table_pct / 100 + 1, at least L + 1 and at most the        */
+                        /* class's table (0 = 300)                                         */
 } lv_tuning;
 
 typedef struct lv_params {
@@ -156,7 +162,7 @@ typedef struct lv_params {
     const lv_tuning* tuning; /* NULL = built-in defaults                                   */
 } lv_params;
 
-#define LV_KERNEL_SLOTS 25
+#define LV_KERNEL_SLOTS 26
 
 /* Per-level statistics; times are milliseconds from HIP events.  sweep_ms,
    renumber_ms and aggregate_ms are always measured (events around each
@@ -183,7 +189,9 @@ typedef struct lv_level_info {
        partition workgroups (with their merge and fallback kernels); slot 22
        = the bucketed mode's scatter pass, which then carries class 11's
        bytes; slot 23 = the commit (labels, volumes, pairs, sweep control);
-       slot 24 = the entry cache's refresh.  Bytes are the compulsory bytes
+       slot 24 = the entry cache's refresh; slot 25 = the fused persistent
+       kernel of the classes below the hub class (lv_tuning.fused), which
+       then carries their bytes.  Bytes are the compulsory bytes
        of the kernel's rows: 8 per CSR entry (index and weight) and 36 per
        vertex (offsets, label, degree and volume read; label and volume
        written), as for a whole sweep. */

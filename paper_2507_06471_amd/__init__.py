@@ -40,13 +40,14 @@ LV_AUTOTUNE = 8
 LV_PRUNE = 16
 LV_ASYNC = 32
 LV_NO_CACHE = 64
-KERNEL_SLOTS = 25
+KERNEL_SLOTS = 26
 # kernel slot -> name (slot = 2*(class-1) + first-sweep flag; then the bucketed
 # hub scatter pass, whose partition workgroups are timed as "hub"; the commit
-# with pair refresh and sweep control; the entry cache's refresh)
+# with pair refresh and sweep control; the entry cache's refresh; the fused
+# persistent kernel of the classes below the hub class)
 KERNEL_NAMES = [f"{c}{'/first' if f else ''}"
                 for c in ("l4", "l8", "l32", "l128", "l256", "l512", "l1k", "l2k", "l3k", "l8k", "hub")
-                for f in (0, 1)] + ["hub/scatter", "commit", "cache/refresh"]
+                for f in (0, 1)] + ["hub/scatter", "commit", "cache/refresh", "fused"]
 
 _i32p = ctypes.POINTER(ctypes.c_int32)
 _i64p = ctypes.POINTER(ctypes.c_int64)
@@ -58,7 +59,8 @@ class lv_tuning(ctypes.Structure):
                 ("block_max", ctypes.c_int32), ("part_keys", ctypes.c_int32),
                 ("part_slots", ctypes.c_int32), ("hub_mode", ctypes.c_int32),
                 ("hub_chunk", ctypes.c_int32), ("order_min", ctypes.c_int32),
-                ("agg_sort", ctypes.c_int32), ("cache_pct", ctypes.c_int32)]
+                ("agg_sort", ctypes.c_int32), ("cache_pct", ctypes.c_int32), ("fused", ctypes.c_int32),
+                ("table_pct", ctypes.c_int32)]
 
 
 class lv_params(ctypes.Structure):

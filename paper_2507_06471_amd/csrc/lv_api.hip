@@ -268,6 +268,8 @@ struct Tune {
     int32_t sc_chunk;   // entries per scatter workgroup (bucketed mode)
     int64_t order_min;  // coarse levels with at least this many entries are stored by degree
     int32_t agg_sort;   // 1: aggregation sorts every entry's key (else by community)
+    int32_t fused;      // 1: later sweeps of the classes below the hub class in one persistent launch
+    int32_t table_pct;  // later sweeps' LDS tables: about L * table_pct / 100 + 1 slots for L entries
     int32_t cache_read_pct;  // entry cache: read it after a commit that changed at most this % of the pairs
     int32_t cache_fill_pct;  // ... fill it during a sweep after a commit that changed at most this %
 };
@@ -285,6 +287,8 @@ Tune make_tune(const lv_tuning* t)
     u.sc_chunk = 1024;
     u.agg_sort = 0;
     u.cache_read_pct = 10;
+    u.fused = 0;
+    u.table_pct = 300;
     if (t) {
         // sub_max bounds the sub-wavefront classes, wave_max the wavefront
         // class, block_max the workgroup classes; each is clamped to the
@@ -309,6 +313,8 @@ Tune make_tune(const lv_tuning* t)
         if (t->order_min > 0) u.order_min = t->order_min;
         u.agg_sort = t->agg_sort == 1 ? 1 : 0;
         if (t->cache_pct > 0) u.cache_read_pct = std::min(100, t->cache_pct);
+        u.fused = t->fused == 1 ? 1 : 0;
+        if (t->table_pct > 0) u.table_pct = std::min(400, std::max(100, t->table_pct));
     }
     u.cache_fill_pct = std::max(u.cache_read_pct, std::min(100, 2 * u.cache_read_pct + 5));
     // a single partition must always fit: part_keys <= 3/4 of the slots
@@ -363,7 +369,7 @@ struct LevelGraph {
 
 // timing slots after the 2 x 11 class slots: the bucketed scatter pass, the
 // commit (labels, volumes, pairs, sweep control) and the entry-cache refresh
-constexpr int SLOT_HUB_SCATTER = 22, SLOT_COMMIT = 23, SLOT_REFRESH = 24;
+constexpr int SLOT_HUB_SCATTER = 22, SLOT_COMMIT = 23, SLOT_REFRESH = 24, SLOT_FUSED = 25;
 
 struct SweepOut {
     std::vector<int32_t> sweeps;   // [G]
@@ -644,6 +650,24 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
     const int64_t ec_read_max = use_ec ? G.nnz * p.tune.cache_read_pct / 100 : -1;
     const int64_t ec_fill_max = use_ec ? G.nnz * p.tune.cache_fill_pct / 100 : -1;
     const int32_t nonhub = start[CLS_HUB] - start[CLS_L4];  // listed vertices below the hub class
+    // the fused kernel's work items: blocks of rows, longest rows first
+    FusedMap fmap{};
+    const bool fused = p.tune.fused != 0 && !async;
+    if (fused) {
+        static const int32_t rows_per_item[NUM_CLS] = {0, 256, 128, 64, 32, 16, 8, 4, 2, 2, 1, 0};
+        int32_t items = 0;
+        for (int c = CLS_HUB - 1; c >= CLS_L4; --c) {
+            const int32_t cnt = start[c + 1] - start[c];
+            if (cnt <= 0) continue;
+            const int q = fmap.nclass++;
+            fmap.cls[q] = c;
+            fmap.item_first[q] = items;
+            fmap.row_first[q] = start[c] - start[CLS_L4];
+            fmap.row_end[q] = start[c + 1] - start[CLS_L4];
+            items += (cnt + rows_per_item[c] - 1) / rows_per_item[c];
+        }
+        fmap.item_first[fmap.nclass] = items;
+    }
     // the refresh's blocks per class: lanes per row as in the move kernels, at most 256
     RefreshMap rmap{};
     if (use_ec) {
@@ -701,6 +725,7 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
     a.ctl = ctl;
     a.mode = mode;
     a.ce = use_ec ? ws.ce.as<int2>() : nullptr;
+    a.table_pct = p.tune.table_pct;
     a.live_comm = async ? ws.comm.as<int32_t>() : nullptr;
     a.live_sigma = async ? ws.sigma.as<int32_t>() : nullptr;
     a.gmoves = ws.gmoves.as<uint32_t>();
@@ -724,16 +749,26 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
     // pair refresh, per-graph stopping rule.
     auto launch_sweep = [&](bool singleton, std::vector<hipEvent_t>* e) -> lv_status {
         singleton = singleton && !async;  // an asynchronous sweep changes communities as it runs
-        if (e) { e->assign(2 * NUM_CLS + 5, nullptr); HIP_TRY(tm.mark(&(*e)[2 * NUM_CLS])); }
-        for (int c = CLS_L4; c < CLS_HUB; ++c) {
-            a.verts = vert_sorted + start[c];
-            a.rows = ws.rows.as<int4>() + (start[c] - start[CLS_L4]);
-            a.dec = dec_all + start[c];
-            a.nverts = start[c + 1] - start[c];
-            if (a.nverts == 0) continue;
-            if (e) HIP_TRY(tm.mark(&(*e)[2 * c]));
-            HIP_TRY(launch_move_class(c, singleton, async, a, s));
-            if (e) HIP_TRY(tm.mark(&(*e)[2 * c + 1]));
+        if (e) { e->assign(2 * NUM_CLS + 7, nullptr); HIP_TRY(tm.mark(&(*e)[2 * NUM_CLS])); }
+        if (fused && !singleton) {
+            a.verts = vert_sorted + start[CLS_L4];
+            a.rows = ws.rows.as<int4>();
+            a.dec = dec_all + start[CLS_L4];
+            a.nverts = nonhub;
+            if (e) HIP_TRY(tm.mark(&(*e)[2 * NUM_CLS + 5]));
+            HIP_TRY(launch_move_fused(a, fmap, ctl, s));
+            if (e) HIP_TRY(tm.mark(&(*e)[2 * NUM_CLS + 6]));
+        } else {
+            for (int c = CLS_L4; c < CLS_HUB; ++c) {
+                a.verts = vert_sorted + start[c];
+                a.rows = ws.rows.as<int4>() + (start[c] - start[CLS_L4]);
+                a.dec = dec_all + start[c];
+                a.nverts = start[c + 1] - start[c];
+                if (a.nverts == 0) continue;
+                if (e) HIP_TRY(tm.mark(&(*e)[2 * c]));
+                HIP_TRY(launch_move_class(c, singleton, async, a, s));
+                if (e) HIP_TRY(tm.mark(&(*e)[2 * c + 1]));
+            }
         }
         if (hubs.nhubs > 0) {
             const hipStream_t hs = s;
@@ -853,9 +888,21 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
     // per vertex (offsets, label, degree and volume read; label and volume written)
     out.bytes = (8 * G.nnz + 36 * (int64_t)n) * out.executed;
     for (int32_t sw = 1; sw <= out.executed; ++sw) {
+        const bool fused_sweep = fused && sw > 1 && fmap.nclass > 0;  // the classes below the hub class in one launch
+        if (fused_sweep) {
+            out.launches += 1;
+            if (timing) {
+                out.kern_ms[SLOT_FUSED] += elapsed(ev[sw - 1][2 * NUM_CLS + 5], ev[sw - 1][2 * NUM_CLS + 6]);
+                out.kern_launches[SLOT_FUSED] += 1;
+            }
+        }
         for (int c = CLS_L4; c <= CLS_HUB; ++c) {
             const int32_t nv = start[c + 1] - start[c];
             if (nv == 0) continue;
+            if (fused_sweep && c < CLS_HUB) {
+                if (timing) out.kern_bytes[SLOT_FUSED] += 8 * cls_entries[c] + 36 * (int64_t)nv;
+                continue;
+            }
             out.launches += c == CLS_HUB ? (sw == 1 ? 2 : 2 + (hubs.args.bucketed && hubs.args.nsc > 0 ? 1 : 0) + (hubs.args.nins > 0 ? 3 : 0)) : 1;
             if (!timing) continue;
             const int slot = 2 * c + (sw == 1 ? 1 : 0) - 2;
@@ -1299,7 +1346,8 @@ lv_status autotune(lv_graph* g, const Params& base, lv_tuning* best, double* bes
         const LevelGraph G = level0(g);
         LV_TRY(run_sweeps(g, G, MODE_LOUVAIN, p, nullptr, so));
         double first = 0.0, later = 0.0;
-        for (int q = 0; q < SLOT_COMMIT; ++q) {
+        for (int q = 0; q < LV_KERNEL_SLOTS; ++q) {  // the move kernels (not the commit or the cache)
+            if (q == SLOT_COMMIT || q == SLOT_REFRESH) continue;
             if (q < 2 * (NUM_CLS - 1) && (q & 1)) first += so.kern_ms[q];
             else later += so.kern_ms[q];
         }
@@ -1317,6 +1365,9 @@ lv_status autotune(lv_graph* g, const Params& base, lv_tuning* best, double* bes
         {&lv_tuning::hub_mode, {1}},
         {&lv_tuning::part_keys, {512, 1024}},
         {&lv_tuning::hub_chunk, {2048, 4096}},
+        {&lv_tuning::part_slots, {1024}},
+        {&lv_tuning::table_pct, {150, 200, 400}},
+        {&lv_tuning::fused, {1}},
     };
     for (const Knob& kb : knobs) {
         lv_tuning keep = *best;

@@ -51,6 +51,8 @@ struct SweepCtl {
     int32_t ec_reads;                 // sweeps of this level that read the cache
     unsigned long long chg_entries;   // entries whose pair the last commit changed
     unsigned long long refreshed;     // entries rewritten by cache refreshes this level
+    int32_t work_next;                // next work item of the fused sweep kernel
+    int32_t pad;
 };
 constexpr int32_t EC_GATHER = 0, EC_FILL = 1, EC_READ = 2;
 
@@ -90,6 +92,7 @@ struct MoveArgs {
     // commit, the entries that point at a vertex whose pair changed (through
     // the reverse-entry map).
     int2* ce;
+    int32_t table_pct;      // later sweeps' LDS table: about L * table_pct / 100 + 1 slots for L entries
 };
 
 // One segment of a packed CSR rebuild (see launch_repack).
@@ -230,6 +233,20 @@ hipError_t launch_class_entries(const int32_t* verts_sorted, const int32_t* star
 
 // sweep
 hipError_t launch_move_class(int cls, bool singleton, bool async, const MoveArgs& a, hipStream_t s);
+// Later synchronous sweeps of every class below the hub class in one
+// persistent launch (k_move_fused).  Per class q that has rows, in order of
+// decreasing row length: its class id, its first work item (item_first[nclass]
+// = items in all; an item is one block of 1024 threads laid out as the
+// class's own kernel lays out a block) and its listed rows [row_first,
+// row_end) in the MoveArgs' rows/dec arrays.
+struct FusedMap {
+    int32_t nclass;
+    int32_t cls[NUM_CLS];
+    int32_t item_first[NUM_CLS + 1];
+    int32_t row_first[NUM_CLS];
+    int32_t row_end[NUM_CLS];
+};
+hipError_t launch_move_fused(const MoveArgs& a, const FusedMap& fm, SweepCtl* ctl, hipStream_t s);
 hipError_t launch_hub_clear(int32_t* table, int64_t slots, hipStream_t s);
 // bucketed mode, sweeps after the first: scatter the hubs' entries to the partition buckets
 hipError_t launch_hub_scatter(const MoveArgs& a, const HubArgs& h, hipStream_t s);

@@ -515,26 +515,23 @@ __global__ __launch_bounds__(BS) void k_move(MoveArgs a)
     if constexpr (ASYNC) block_flush_sums<BS, uint32_t>(a.gmoves, moved ? move_slot(a, i) : -1, moved ? 1u : 0u);
 }
 
-// Later synchronous sweeps: one group of G lanes per vertex, an LDS table of
-// up to SLOTS packed slots per group, each community scored by the lane that
-// claimed its slot with the volume that came with the entry's pair (no scan
-// of the table, no volume array).
+// Later synchronous sweeps: one group of G lanes per vertex (a block of BS
+// threads holds BS/G groups; group g takes listed row vi_first + g if it is
+// below vi_end), an LDS table of up to SLOTS packed slots per group at
+// tab + g*SLOTS, each community scored by the lane that claimed its slot with
+// the volume that came with the entry's pair (no scan of the table, no volume
+// array).  rs/rc/rw: BS/64 entries for the reduction across wavefronts.
+// Every thread of the block calls it with the same arguments.
 template <int CLS, int BS, int G, int SLOTS>
-__global__ __launch_bounds__(BS) void k_move_claim(MoveArgs a)
+__device__ __forceinline__ void claim_rows(const MoveArgs& a, int ecm, int64_t vi_first, int64_t vi_end,
+                                           unsigned long long* s_tab, int64_t* rs, int32_t* rc, int32_t* rw)
 {
-    constexpr int NG = BS / G;
     constexpr int ME = (CLS_CAP[CLS] + G - 1) / G;  // entries per lane (rows of the class have <= CLS_CAP entries)
     static_assert(ME >= 1 && ME <= 8, "entries per lane");
     constexpr bool POW2 = (SLOTS & (SLOTS - 1)) == 0;
-    __shared__ unsigned long long s_tab[NG * SLOTS];
-    __shared__ int64_t rs[BS / WAVE];
-    __shared__ int32_t rc[BS / WAVE], rw[BS / WAVE];
-
-    if (a.ctl->all_done) return;
-    const int ecm = entry_mode(a);
     const int g = threadIdx.x / G, lane = threadIdx.x % G;
-    const int64_t vi = (int64_t)blockIdx.x * NG + g;
-    const bool has = vi < a.nverts;
+    const int64_t vi = vi_first + g;
+    const bool has = vi < vi_end;
     const int4 row = has ? a.rows[vi] : make_int4(0, 0, 0, 0);
     const int32_t i = row.x;
     const bool live = has && !vertex_frozen(a, i) && !vertex_skipped(a, i);
@@ -543,10 +540,12 @@ __global__ __launch_bounds__(BS) void k_move_claim(MoveArgs a)
     const int32_t A = self.x;
     const int64_t ki = live ? row.w : 0;
     const int64_t M = live ? vertex_M(a, i) : 0;
-    // a table of min(SLOTS, 2L + 1) slots (a power of two when SLOTS is one);
-    // SLOTS exceeds every row of the class, so it never fills
+    // a table of about L * table_pct / 100 + 1 slots, at least L + 1 (a power
+    // of two when SLOTS is one), at most SLOTS, which exceeds every row of the
+    // class: it never fills
     const uint32_t L = (uint32_t)(end - beg);
-    const uint32_t T = POW2 ? min((uint32_t)SLOTS, pow2_at_least(2u * L)) : min((uint32_t)SLOTS, 2u * L + 1u);
+    const uint32_t want = max(L + 1u, (uint32_t)(((uint64_t)L * (uint32_t)a.table_pct) / 100u) + (POW2 ? 0u : 1u));
+    const uint32_t T = POW2 ? min((uint32_t)SLOTS, pow2_at_least(want)) : min((uint32_t)SLOTS, want);
     unsigned long long* tab = s_tab + g * SLOTS;
     for (uint32_t t = lane; t < T; t += G) tab[t] = EMPTY_SLOT;
     int2 cc[ME];
@@ -588,6 +587,72 @@ __global__ __launch_bounds__(BS) void k_move_claim(MoveArgs a)
     if (has && lane == 0) {
         if (!live) a.dec[vi] = -1;
         else decide_store(a, vi, A, self.y, ki, M, best_s, best_c, w_own);
+    }
+}
+
+template <int CLS, int BS, int G, int SLOTS>
+__global__ __launch_bounds__(BS) void k_move_claim(MoveArgs a)
+{
+    __shared__ unsigned long long s_tab[(BS / G) * SLOTS];
+    __shared__ int64_t rs[BS / WAVE];
+    __shared__ int32_t rc[BS / WAVE], rw[BS / WAVE];
+    if (a.ctl->all_done) return;
+    claim_rows<CLS, BS, G, SLOTS>(a, entry_mode(a), (int64_t)blockIdx.x * (BS / G), a.nverts, s_tab, rs, rc, rw);
+}
+
+// Persistent fused sweep kernel (later synchronous sweeps, every class
+// below the hub class in one launch).  Work items are blocks of rows of one
+// class, numbered class by class (item_first[q] is class q's first);
+// 1024-thread workgroups take FUSED_CHUNK items at a time from the counter
+// ctl->work_next until none is left, each item laid out as its class's
+// kernel lays out its block
+// (BS/G groups of G lanes), with its tables carved from one LDS array sized
+// for the largest class.  The counter is reset by k_sweep_end.
+constexpr int FUSED_BS = 1024;
+constexpr int FUSED_SLOTS = L8K_SLOTS;  // the largest (BS/G) * SLOTS of the classes at 1024 threads
+constexpr int FUSED_CHUNK = 16;         // work items a workgroup takes per atomic
+__global__ __launch_bounds__(FUSED_BS) void k_move_fused(MoveArgs a, FusedMap fm, SweepCtl* ctl)
+{
+    __shared__ unsigned long long s_tab[FUSED_SLOTS];
+    __shared__ int64_t rs[FUSED_BS / WAVE];
+    __shared__ int32_t rc[FUSED_BS / WAVE], rw[FUSED_BS / WAVE];
+    __shared__ int32_t s_item;
+    if (ctl->all_done) return;
+    const int ecm = entry_mode(a);
+    const int32_t total = fm.item_first[fm.nclass];
+    int32_t item = 0, chunk_end = 0;
+    for (;;) {
+        if (item >= chunk_end) {  // take the next FUSED_CHUNK items
+            __syncthreads();      // every thread has read s_item
+            if (threadIdx.x == 0) s_item = atomicAdd(&ctl->work_next, FUSED_CHUNK);
+            __syncthreads();
+            item = s_item;
+            chunk_end = item + FUSED_CHUNK;
+        } else {
+            __syncthreads();  // the previous item is done with the tables
+        }
+        if (item >= total) break;
+        int q = 0;
+        while (q + 1 < fm.nclass && fm.item_first[q + 1] <= item) ++q;
+        const int32_t k = item - fm.item_first[q];
+        const int64_t r0 = fm.row_first[q], r1 = fm.row_end[q];
+#define LV_FUSED_CASE(C, G, SL)                                                                                    \
+    case C: claim_rows<C, FUSED_BS, G, SL>(a, ecm, r0 + (int64_t)k * (FUSED_BS / G), r1, s_tab, rs, rc, rw); break;
+        switch (fm.cls[q]) {
+            LV_FUSED_CASE(CLS_L4, 4, 8)
+            LV_FUSED_CASE(CLS_L8, 8, 16)
+            LV_FUSED_CASE(CLS_L32, 16, 64)
+            LV_FUSED_CASE(CLS_L128, 32, 208)
+            LV_FUSED_CASE(CLS_L256, 64, 424)
+            LV_FUSED_CASE(CLS_L512, 128, 848)
+            LV_FUSED_CASE(CLS_L1K, 256, 1696)
+            LV_FUSED_CASE(CLS_L2K, 512, 3392)
+            LV_FUSED_CASE(CLS_L3K, 512, 4096)
+            LV_FUSED_CASE(CLS_L8K, 1024, L8K_SLOTS)
+            default: break;
+        }
+#undef LV_FUSED_CASE
+        ++item;
     }
 }
 
@@ -1169,6 +1234,7 @@ __global__ __launch_bounds__(256) void k_sweep_end(SweepCtl* ctl, int32_t G, int
     if (threadIdx.x == 0) {
         ctl->sweep = s;
         ctl->all_done = running == 0 ? 1 : 0;
+        ctl->work_next = 0;
         if (ec_read_max >= 0) {
             const unsigned long long chg = ctl->chg_entries;
             const bool filled = ctl->ec_mode != EC_GATHER;
@@ -1199,6 +1265,7 @@ __global__ void k_ctl_init(SweepCtl* ctl, int32_t G, const int32_t* gactive, int
         ctl->all_done = 0;
         ctl->ec_mode = EC_GATHER;
         ctl->ec_reads = 0;
+        ctl->work_next = 0;
         ctl->chg_entries = 0;
         ctl->refreshed = 0;
     }
@@ -1387,6 +1454,15 @@ hipError_t launch_gather_rows(const int32_t* verts, int32_t m, const int32_t* of
 {
     if (m <= 0) return hipSuccess;
     k_gather_rows<<<LV_GRID(m)>>>(verts, m, off, beg, len);
+    return hipGetLastError();
+}
+
+hipError_t launch_move_fused(const MoveArgs& a, const FusedMap& fm, SweepCtl* ctl, hipStream_t s)
+{
+    if (fm.nclass <= 0 || fm.item_first[fm.nclass] <= 0) return hipSuccess;
+    // two workgroups fit a CU (LDS of the largest class's table)
+    const int32_t items = fm.item_first[fm.nclass];
+    k_move_fused<<<(unsigned)(items < 512 ? items : 512), FUSED_BS, 0, s>>>(a, fm, ctl);
     return hipGetLastError();
 }
 
