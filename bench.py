@@ -323,11 +323,12 @@ def batch_leg(args, lvp, graphgen, np, torch):
 
 
 def serving_leg(args, lvp, graphgen, np, torch):
-    """Poisson trace of Louvain jobs replayed twice in real time: through a
-    FIFO loop that runs one graph per call (create from host memory, Louvain,
+    """Poisson traces of Louvain jobs replayed in real time, at each load of
+    --serve-loads (arrival rate / one-graph-per-call capacity): through a FIFO
+    loop that runs one graph per call (create from host memory, Louvain,
     final labels) and through the continuous-batching server.  Latency is
     arrival -> result; every job's partition must equal its graph's result
-    alone."""
+    alone.  Then both at saturation (jobs submitted at once)."""
     import threading
 
     t = time.time()
@@ -350,11 +351,8 @@ def serving_leg(args, lvp, graphgen, np, torch):
     J = args.serve_jobs
     which = rng.integers(0, len(pool), size=J)
     mean_svc = float(np.mean([svc[i] for i in which]))
-    rate = args.serve_load / mean_svc
-    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=J))
+    gaps = rng.exponential(1.0, size=J)  # one trace shape, scaled to each load
     entries = [pool[i].nnz for i in which]
-    log(f"serving: {J} jobs, mean one-per-call service {mean_svc * 1e3:.2f} ms, Poisson rate {rate:.1f}/s "
-        f"({args.serve_load:.0%} of one-per-call capacity)")
 
     def summarize(lat, span, same):
         lat = np.asarray(lat) * 1e3
@@ -362,64 +360,75 @@ def serving_leg(args, lvp, graphgen, np, torch):
                 "p99_ms": round(float(np.percentile(lat, 99)), 2), "mean_ms": round(float(lat.mean()), 2),
                 "span_s": round(span, 2), "identical_partitions": same}
 
-    # FIFO, one graph per call
-    same = True
-    lat = np.zeros(J)
-    t0 = time.perf_counter()
-    for i in range(J):
-        now = time.perf_counter()
-        if now < t0 + arrivals[i]:
-            time.sleep(t0 + arrivals[i] - now)
-        with lvp.Graph.from_csr(pool[which[i]]) as h:
-            fp = lvp.louvain_final(h)
-        done = time.perf_counter()
-        lat[i] = done - (t0 + arrivals[i])
-        same &= bool(np.array_equal(fp.labels, alone[which[i]][0])) and int(fp.q_int[0]) == alone[which[i]][1]
-        if i % 200 == 0:
-            log(f"serving: fifo job {i}")
-    fifo = summarize(lat, time.perf_counter() - t0, same)
-    log(f"serving: one graph per call {fifo}")
-
-    # continuous batching server
     srv = lvp.Server(max_jobs=args.serve_max_jobs)
-    tickets = [0] * J
-    submitted = [0.0] * J
-    ready = [threading.Event() for _ in range(J)]
-    t0 = time.perf_counter()
-
-    def submitter():
+    loads = {}
+    for load in args.serve_loads:
+        rate = load / mean_svc
+        arrivals = np.cumsum(gaps / rate)
+        log(f"serving: {J} jobs, mean one-per-call service {mean_svc * 1e3:.2f} ms, Poisson rate {rate:.1f}/s "
+            f"({load:.0%} of one-per-call capacity)")
+        # FIFO, one graph per call
+        same = True
+        lat = np.zeros(J)
+        t0 = time.perf_counter()
         for i in range(J):
             now = time.perf_counter()
             if now < t0 + arrivals[i]:
                 time.sleep(t0 + arrivals[i] - now)
-            submitted[i] = time.perf_counter()
-            tickets[i] = srv.submit(pool[which[i]])
-            ready[i].set()
+            with lvp.Graph.from_csr(pool[which[i]]) as h:
+                fp = lvp.louvain_final(h)
+            done = time.perf_counter()
+            lat[i] = done - (t0 + arrivals[i])
+            same &= bool(np.array_equal(fp.labels, alone[which[i]][0])) and int(fp.q_int[0]) == alone[which[i]][1]
+            if i % 250 == 0:
+                log(f"serving {load:.0%}: fifo job {i}")
+        fifo = summarize(lat, time.perf_counter() - t0, same)
+        log(f"serving {load:.0%}: one graph per call {fifo}")
+        # continuous batching server
+        tickets = [0] * J
+        submitted = [0.0] * J
+        ready = [threading.Event() for _ in range(J)]
+        t0 = time.perf_counter()
 
-    th = threading.Thread(target=submitter)
-    th.start()
-    same = True
-    lat = np.zeros(J)
-    end = 0.0
-    for i in range(J):
-        ready[i].wait()
-        srv.wait(tickets[i])
-        labels, info = srv.result(tickets[i], pool[which[i]].n)
-        fin = submitted[i] + info["total_ms"] * 1e-3
-        end = max(end, fin)
-        lat[i] = fin - (t0 + arrivals[i])
-        same &= bool(np.array_equal(labels, alone[which[i]][0])) and int(info["q_int"]) == alone[which[i]][1]
-        if i % 200 == 0:
-            log(f"serving: server job {i}")
-    th.join()
+        def submitter():
+            for i in range(J):
+                now = time.perf_counter()
+                if now < t0 + arrivals[i]:
+                    time.sleep(t0 + arrivals[i] - now)
+                submitted[i] = time.perf_counter()
+                tickets[i] = srv.submit(pool[which[i]])
+                ready[i].set()
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        same = True
+        lat = np.zeros(J)
+        end = 0.0
+        for i in range(J):
+            ready[i].wait()
+            srv.wait(tickets[i])
+            labels, info = srv.result(tickets[i], pool[which[i]].n)
+            fin = submitted[i] + info["total_ms"] * 1e-3
+            end = max(end, fin)
+            lat[i] = fin - (t0 + arrivals[i])
+            same &= bool(np.array_equal(labels, alone[which[i]][0])) and int(info["q_int"]) == alone[which[i]][1]
+            if i % 250 == 0:
+                log(f"serving {load:.0%}: server job {i}")
+        th.join()
+        batched = summarize(lat, end - t0, same)
+        log(f"serving {load:.0%}: continuous batching {batched}")
+        loads[f"{load:g}"] = {"rate_per_s": round(rate, 2), "one_graph_per_call": fifo, "continuous_batching": batched,
+                              "p50_speedup": round(fifo["p50_ms"] / batched["p50_ms"], 2) if batched["p50_ms"] > 0 else None,
+                              "p99_speedup": round(fifo["p99_ms"] / batched["p99_ms"], 2) if batched["p99_ms"] > 0 else None,
+                              "throughput_speedup": round(batched["jobs_per_s"] / fifo["jobs_per_s"], 2)}
+        if not (fifo["identical_partitions"] and batched["identical_partitions"]):
+            print("a served partition differs from the graph's partition alone", file=sys.stderr, flush=True)
+            sys.exit(1)
     stats = srv.stats()
-    batched = summarize(lat, end - t0, same)
-    batched["max_batch"] = int(stats["max_batch"])
-    batched["packed_levels"] = int(stats["steps"])
-    log(f"serving: continuous batching {batched}")
 
     # capacity: the first jobs of the trace all submitted at once
     C = min(J, args.serve_capacity_jobs)
+    same = True
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(C):
@@ -435,21 +444,22 @@ def serving_leg(args, lvp, graphgen, np, torch):
         same &= bool(np.array_equal(labels, alone[which[i]][0]))
     srv_cap = C / (time.perf_counter() - t0)
     srv.close()
-    batched["identical_partitions"] = same
-    fifo["saturated_jobs_per_s"] = round(fifo_cap, 2)
-    batched["saturated_jobs_per_s"] = round(srv_cap, 2)
     log(f"serving: saturated ({C} jobs at once): one per call {fifo_cap:.2f}/s, server {srv_cap:.2f}/s")
-    out = {"workload": f"{J} Louvain jobs, Poisson arrivals at {args.serve_load:.0%} of one-graph-per-call "
-                       f"capacity ({rate:.1f}/s); graphs from a pool of {len(pool)} R-MAT graphs, n log-uniform "
-                       "in [1e4, 4e6], edge factor uniform in {8..16}, unit weights, seed 5",
-           "mean_entries": round(float(np.mean(entries))), "one_graph_per_call": fifo,
-           "continuous_batching": batched,
-           "p99_speedup": round(fifo["p99_ms"] / batched["p99_ms"], 2) if batched["p99_ms"] > 0 else None,
-           "throughput_speedup": round(batched["jobs_per_s"] / fifo["jobs_per_s"], 2),
-           "saturated_throughput_speedup": round(batched["saturated_jobs_per_s"] / fifo["saturated_jobs_per_s"], 2)}
-    if not (fifo["identical_partitions"] and batched["identical_partitions"]):
+    if not same:
         print("a served partition differs from the graph's partition alone", file=sys.stderr, flush=True)
         sys.exit(1)
+    first = loads[f"{args.serve_loads[0]:g}"]
+    out = {"workload": f"{J} Louvain jobs per trace, Poisson arrivals at {', '.join(f'{x:.0%}' for x in args.serve_loads)} "
+                       f"of one-graph-per-call capacity; graphs from a pool of {len(pool)} R-MAT graphs, n log-uniform "
+                       "in [1e4, 4e6], edge factor uniform in {8..16}, unit weights, seed 5",
+           "mean_entries": round(float(np.mean(entries))), "mean_one_per_call_service_ms": round(mean_svc * 1e3, 2),
+           "loads": loads,
+           "one_graph_per_call": first["one_graph_per_call"], "continuous_batching": first["continuous_batching"],
+           "p99_speedup": first["p99_speedup"], "throughput_speedup": first["throughput_speedup"],
+           "saturated": {"jobs": C, "one_graph_per_call_jobs_per_s": round(fifo_cap, 2),
+                         "server_jobs_per_s": round(srv_cap, 2), "speedup": round(srv_cap / fifo_cap, 2),
+                         "identical_partitions": same},
+           "server_stats": {"max_batch": int(stats["max_batch"]), "packed_levels": int(stats["steps"])}}
     return out
 
 
@@ -609,7 +619,8 @@ def main():
     ap.add_argument("--batch-reps", type=int, default=3)
     ap.add_argument("--serve-jobs", type=int, default=1000, help="jobs in the serving trace (0: skip it)")
     ap.add_argument("--serve-pool", type=int, default=32, help="distinct graphs the jobs draw from")
-    ap.add_argument("--serve-load", type=float, default=0.8, help="arrival rate / one-per-call capacity")
+    ap.add_argument("--serve-loads", type=float, nargs="+", default=[0.8, 0.95],
+                    help="arrival rates / one-per-call capacity, one trace each")
     ap.add_argument("--serve-max-jobs", type=int, default=64)
     ap.add_argument("--serve-capacity-jobs", type=int, default=200, help="jobs of the saturated capacity runs")
     ap.add_argument("--prune-reps", type=int, default=2,

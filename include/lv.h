@@ -390,17 +390,21 @@ lv_status lv_modularity(lv_graph* g, const int32_t* labels, lv_memkind kind, int
 lv_status lv_modularity_noalloc(lv_graph* g, const int32_t* labels, int64_t* q_int, int64_t* m, double* q);
 
 /* ---------------------------------------------------------------------------
- * Serving loop (continuous batching).  A server owns a worker thread and a
- * stream on the current device.  Jobs (CSR graphs, same conventions as
- * lv_graph_create_csr) are submitted at any time and copied to host memory;
- * at every level boundary the worker admits queued jobs in arrival order
- * while their working-set estimates (72 B per entry + 96 B per vertex + 1
- * MiB) fit the memory budget and the in-flight count fits max_jobs, packs
- * the coarse graphs of the jobs that continue together with the level-0
- * graphs of the admitted ones, and runs one Louvain level (Algorithm 3) for
- * all of them in the same launches.  Each job keeps its own M, stopping rule
- * and acceptance, so its partition equals lv_louvain's on its graph alone.
- * Every server call is thread-safe; results are kept until lv_server_result.
+ * Serving loop (continuous batching).  A server owns two threads, each with
+ * a stream of its own on the current device (default priority).  Jobs (CSR
+ * graphs, same conventions as lv_graph_create_csr) are submitted at any time
+ * and copied (host input to host memory, device input to device memory).
+ * The staging thread admits queued jobs in arrival order while their
+ * working-set estimates (72 B per entry + 96 B per vertex + 1 MiB) fit the
+ * memory budget and the in-flight count fits max_jobs, and sets up each
+ * admitted job's graph on the device while the worker runs the current
+ * level.  At every level boundary the worker packs the coarse graphs of the
+ * jobs that continue together with the graphs staged since, and runs one
+ * Louvain level (Algorithm 3) for all of them in the same launches.  Each job
+ * keeps its own M, stopping rule and acceptance, so its partition equals
+ * lv_louvain's on its graph alone.  A device-resident submission's copy is
+ * not counted in the budget.  Every server call is thread-safe; results are
+ * kept until lv_server_result.
  * ------------------------------------------------------------------------- */
 typedef struct lv_server lv_server;
 
@@ -441,9 +445,11 @@ typedef struct lv_server_stats {
 
 /* cfg may be NULL (defaults).  LV_E_STATE if the worker thread cannot start. */
 lv_status lv_server_create(const lv_server_config* cfg, lv_server** out);
-/* Copies the CSR (host or device memory) and queues the job; *ticket names it.
-   LV_E_TOO_LARGE if its estimate alone exceeds the budget.  Malformed input
-   is reported by the job's result (validation happens at admission). */
+/* Copies the CSR (host input to host memory, device input to device memory)
+   and queues the job; *ticket names it.  LV_E_TOO_LARGE if its estimate
+   alone exceeds the budget, LV_E_OVERFLOW above LV_MAX_NNZ entries.
+   Malformed input is reported by the job's result (validation happens at
+   admission). */
 lv_status lv_server_submit(lv_server* s, int32_t n, const int32_t* offsets, const int32_t* indices,
                            const int32_t* weights, lv_memkind kind, uint64_t* ticket);
 /* *state = LV_JOB_QUEUED / RUNNING / DONE; LV_E_NOT_FOUND for an unknown ticket. */

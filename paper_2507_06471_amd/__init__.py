@@ -610,16 +610,27 @@ class Server:
         _check(lib.lv_server_create(ctypes.byref(cfg), ctypes.byref(h)), "lv_server_create")
         self._h = h
 
-    def submit(self, g) -> int:
-        """Queue a ``graphgen.CSR``-like graph (host arrays); returns its ticket."""
+    def submit(self, g, device: bool = False) -> int:
+        """Queue a ``graphgen.CSR``-like graph; returns its ticket.  With
+        device=True its arrays are first put in device memory (torch), and the
+        server copies them device to device."""
         lib = load_library()
         off = np.ascontiguousarray(g.offsets, dtype=np.int32)
         idx = np.ascontiguousarray(g.indices, dtype=np.int32)
         w = None if g.weights is None else np.ascontiguousarray(g.weights, dtype=np.int32)
+        kind = LV_MEM_HOST
+        if device:
+            import torch
+
+            off, idx = torch.from_numpy(off).cuda(), torch.from_numpy(idx).cuda()
+            w = None if w is None else torch.from_numpy(w).cuda()
+            torch.cuda.synchronize()
+            kind = LV_MEM_DEVICE
+        po, _ = _ptr(off)
+        pi, _ = _ptr(idx)
+        pw, _ = _ptr(w)
         t = ctypes.c_uint64()
-        _check(lib.lv_server_submit(self._h, int(g.n), off.ctypes.data, idx.ctypes.data,
-                                    None if w is None else w.ctypes.data, LV_MEM_HOST, ctypes.byref(t)),
-               "lv_server_submit")
+        _check(lib.lv_server_submit(self._h, int(g.n), po, pi, pw, kind, ctypes.byref(t)), "lv_server_submit")
         return t.value
 
     def poll(self, ticket: int) -> int:

@@ -217,6 +217,18 @@ struct lv_graph {
     size_t pinned_bytes = 0;
     bool has_tuned = false;      // LV_AUTOTUNE: the setting chosen on first use
     lv_tuning tuned{};
+    // Set-up frees nothing while set (a free waits for the whole device, and
+    // the server sets graphs up while another stream runs): buffers that set-up
+    // would free are parked here until the handle is destroyed.
+    bool keep_scratch = false;
+    std::vector<std::unique_ptr<DevBuf>> parked;
+    void release_or_park(DevBuf& b)
+    {
+        if (!b.p) return;
+        if (!keep_scratch) { b.release(); return; }
+        parked.push_back(std::make_unique<DevBuf>());
+        parked.back()->swap(b);
+    }
     ~lv_graph()
     {
         if (pinned) (void)hipHostFree(pinned);
@@ -1772,10 +1784,7 @@ static lv_status reorder_by_degree(lv_graph* g, const int32_t* rank)
     g->k.swap(k2);
     g->reordered = true;
     Workspace& ws = g->ws;
-    ws.keys.release();
-    ws.keys_alt.release();
-    ws.vals.release();
-    ws.vals_alt.release();
+    for (DevBuf* b : {&off2, &idx2, &w2, &k2, &ws.keys, &ws.keys_alt, &ws.vals, &ws.vals_alt}) g->release_or_park(*b);
     return LV_OK;
 }
 
@@ -1851,9 +1860,9 @@ static lv_status graph_setup(lv_graph* g, int32_t n, const int32_t* offsets, con
         HIP_TRY(launch_row_sums(n, g->off.as<int32_t>(), g->w.as<int32_t>(), nnz, g->k.as<int32_t>(),
                                 ws.k64.as<int64_t>(), d_tot, s));
         HIP_TRY(hipStreamSynchronize(s));
-        ws.k64.release();
+        g->release_or_park(ws.k64);
     } else {
-        g->w.release();
+        g->release_or_park(g->w);
         HIP_TRY(launch_degree_unit(n, g->off.as<int32_t>(), g->k.as<int32_t>(), s));
     }
     // per-graph M, trace and sum of squared degrees

@@ -131,3 +131,20 @@ def test_too_large_and_destroy_with_pending_jobs():
     for _ in range(5):
         srv.submit(g)
     srv.close()  # must not hang or leak: pending jobs are cancelled
+
+
+def test_device_resident_submissions_and_staging():
+    # jobs submitted from device memory (copied device to device) mixed with
+    # host submissions; every job equals the oracle's result for its graph
+    gs = job_mix(77, 18)
+    with lvp.Server(max_jobs=4) as srv:
+        tickets = [srv.submit(g, device=(i % 2 == 0)) for i, g in enumerate(gs)]
+        for g, t in zip(gs, tickets):
+            assert srv.wait(t, 120000)
+            labels, info = srv.result(t, g.n)
+            assert info["status"] == 0
+            want = oracle.louvain(g)
+            assert np.array_equal(labels, want.final_labels), g.name
+            assert info["q_int"] == want.q_int
+        st = srv.stats()
+        assert st["completed"] == len(gs) and st["in_flight"] == 0 and st["mem_in_use"] == 0
