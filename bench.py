@@ -599,7 +599,133 @@ def workloads_leg(args, lvp, graphgen, np, torch):
     return out
 
 
+def profile_summary(paths, out_dir, command):
+    """Summaries for profiles/ from rocprofv3 databases of
+    `bench.py --steps 1 --warmup 0 ... --copy-probe-mib 1024` (kernel trace,
+    FETCH_SIZE pass, WRITE_SIZE pass, TCC hit/miss pass): per kernel, the
+    dispatches of the instrumented step (Louvain, all levels, and LPA: those
+    between the two marker launches of the copy probe's kernel), averaged;
+    the first launch of that kernel is the 1 GiB calibration copy.
+    Writes <out_dir>/move_kernels_rmat24_kernel_trace.md,
+    move_kernels_rmat24_pmc.md and pmc_rmat24.txt (read by the roofline's
+    `traffic`)."""
+    import re
+    import sqlite3
+
+    def short(n):
+        n = re.sub(r"^void |lv::\(anonymous namespace\)::|lv::", "", n).split("(")[0]
+        return n
+
+    def louvain_dispatches(db):
+        con = sqlite3.connect(db)
+        rows = con.execute("select dispatch_id, name, duration from kernels order by start").fetchall()
+        marks = [i for i, r in enumerate(rows) if "bitwise_not" in r[1]]
+        a, b = marks[-2], marks[-1]
+        return con, rows[a + 1:b], rows[:marks[0] + 1]
+
+    def copy_probe(rows):
+        return [r for r in rows if "bitwise_not" in r[1]]
+
+    names = {}
+    con, sel, _ = louvain_dispatches(paths[0])
+    dur = {}
+    for d, n, t in sel:
+        dur.setdefault(short(n), []).append(t / 1e6)
+    counters = {}
+    for key, db in zip(("fetch", "write", "hit"), paths[1:]):
+        c2, sel2, rows2 = louvain_dispatches(db)
+        ids = {d: short(n) for d, n, _ in sel2}
+        probe_ids = {d for d, _, _ in copy_probe(rows2)}
+        vals, pv = {}, {}
+        for d, cn, v in c2.execute("select dispatch_id, counter_name, value from counters_collection"):
+            if d in ids:
+                vals.setdefault((ids[d], cn), {}).setdefault(d, 0.0)
+                vals[(ids[d], cn)][d] += v
+            if d in probe_ids:
+                pv[cn] = pv.get(cn, 0.0) + v
+        counters[key] = (vals, pv)
+    gib_kib = (1 << 30) / 1024.0
+    fetch_factor = counters["fetch"][1].get("FETCH_SIZE", 0.0) / gib_kib
+    write_factor = counters["write"][1].get("WRITE_SIZE", 0.0) / gib_kib
+
+    def avg(key, kern, cn):
+        d = counters[key][0].get((kern, cn), {})
+        return sum(d.values()) / len(d) if d else None
+
+    src = kernel_source_digest()
+    rows_out = []
+    for kern, ts in sorted(dur.items(), key=lambda kv: -sum(kv[1])):
+        f, w = avg("fetch", kern, "FETCH_SIZE"), avg("write", kern, "WRITE_SIZE")
+        h, m = avg("hit", kern, "TCC_HIT_sum"), avg("hit", kern, "TCC_MISS_sum")
+        rows_out.append((kern, len(ts), sum(ts) / len(ts), sum(ts), f, w, h, m))
+    os.makedirs(out_dir, exist_ok=True)
+    with open(os.path.join(out_dir, "move_kernels_rmat24_kernel_trace.md"), "w") as fh:
+        fh.write("# Kernel trace: R-MAT 24, the instrumented step (Louvain, all levels, and LPA)\n\n")
+        fh.write("Command (run from the repository root on the GPU host, with `cd /tmp && export TMPDIR=/tmp` for the "
+                 "profiler's files):\n\n```\n" + command[0] + "\n```\n\n")
+        fh.write("Dispatches between the two marker launches around the instrumented step, "
+                 "grouped by kernel.  bench.py's roofline takes its dominant kernel's average from HIP events on "
+                 "the same step.\n\n| kernel | dispatches | avg ms | total ms |\n|---|---:|---:|---:|\n")
+        for kern, nd, a, t, *_ in rows_out[:40]:
+            fh.write(f"| `{kern}` | {nd} | {a:.4f} | {t:.3f} |\n")
+    with open(os.path.join(out_dir, "move_kernels_rmat24_pmc.md"), "w") as fh:
+        fh.write("# HBM counters: R-MAT 24, the instrumented step (Louvain and LPA)\n\nThree rocprofv3 passes, one counter "
+                 "group each:\n\n```\n" + "\n".join(command[1:]) + "\n```\n\n")
+        fh.write(f"Calibration: the 1 GiB copy probe (torch bitwise_not: 1 GiB read, 1 GiB written) reads "
+                 f"FETCH_SIZE = {fetch_factor:.4f} x its bytes read and WRITE_SIZE = {write_factor:.4f} x its bytes "
+                 "written (KiB).  Calibrated bytes = FETCH_SIZE / fetch factor + WRITE_SIZE / write factor.  These "
+                 "TCC counters see requests from L2 to the memory fabric: a line served by the Infinity Cache (MALL) "
+                 "is counted like one from HBM, so 'HBM bytes' here is an upper bound on DRAM traffic.\n\n")
+        fh.write("| kernel | dispatches | avg ms | FETCH_SIZE MiB | WRITE_SIZE MiB | calibrated MB | L2 hit % |\n"
+                 "|---|---:|---:|---:|---:|---:|---:|\n")
+        for kern, nd, a, t, f, w, h, m in rows_out[:40]:
+            if f is None or w is None:
+                continue
+            cal = (f / max(fetch_factor, 1e-9) + w / max(write_factor, 1e-9)) * 1024 / 1e6
+            hit = 100.0 * h / (h + m) if h is not None and m and (h + m) > 0 else float("nan")
+            fh.write(f"| `{kern}` | {nd} | {a:.4f} | {f / 1024:.2f} | {w / 1024:.2f} | {cal:.1f} | {hit:.1f} |\n")
+    with open(os.path.join(out_dir, "pmc_rmat24.txt"), "w") as fh:
+        fh.write("# Per-dispatch HBM counters of the move kernels on R-MAT 24 (see move_kernels_rmat24_pmc.md);\n"
+                 "# fetch_kib / write_kib: FETCH_SIZE / WRITE_SIZE averaged over the instrumented step's\n"
+                 "# dispatches of the kernel, copy_*_factor: the counter's reading per byte of a plain 1 GiB copy;\n"
+                 "# src: digest of the kernels' sources when taken.\n")
+        for kern, nd, a, t, f, w, h, m in rows_out:
+            slot = KERNEL_SLOT_OF(kern)
+            if slot is None or f is None or w is None:
+                continue
+            fh.write(f"slot={slot} kernel={kern.replace(' ', '')} dispatches={nd} fetch_kib={f:.1f} write_kib={w:.1f} "
+                     f"copy_fetch_factor={fetch_factor:.4f} copy_write_factor={write_factor:.4f} src={src}\n")
+
+
+def KERNEL_SLOT_OF(kern):
+    """The library's timing-slot name of a profiled kernel symbol (None: not
+    a kernel that a slot times alone)."""
+    import re
+
+    names = ["l4", "l8", "l32", "l128", "l256", "l512", "l1k", "l2k", "l3k", "l8k"]
+    m = re.match(r"k_move_claim<(\d+),", kern)
+    if m and 1 <= int(m.group(1)) <= 10:
+        return names[int(m.group(1)) - 1]
+    m = re.match(r"k_move<(\d+),.*, 0>$", kern)
+    if m and 1 <= int(m.group(1)) <= 10:
+        return names[int(m.group(1)) - 1] + "/first"
+    if kern.startswith("k_hub_scatter"):
+        return "hub/scatter"
+    if kern.startswith("k_hub_part_claim"):
+        return "hub"
+    if kern.startswith("k_hub_part<true"):
+        return "hub/first"
+    if kern.startswith("k_move_fused"):
+        return "fused"
+    return None
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "--profile-summary":
+        # bench.py --profile-summary OUT_DIR KT_DB FETCH_DB WRITE_DB HIT_DB CMD_KT CMD_FETCH CMD_WRITE CMD_HIT
+        a = sys.argv[2:]
+        profile_summary(a[1:5], a[0], a[5:9])
+        return
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
@@ -663,6 +789,14 @@ def main():
         log(f"copy probe: {args.copy_probe_mib} MiB read + {args.copy_probe_mib} MiB written")
         del src, dst
 
+    def profile_marker():
+        # with the copy probe on, a 1 KiB launch of the same kernel before
+        # and after the instrumented step marks its dispatches in a trace
+        if args.copy_probe_mib > 0:
+            torch.cuda.synchronize()
+            torch.bitwise_not(torch.ones(256, dtype=torch.int32, device="cuda"))
+            torch.cuda.synchronize()
+
     def step(timing, out=None):
         # the job's results: final labels and per-level statistics of Louvain,
         # labels of LPA (the per-level labels stay on the device).  With `out`
@@ -720,7 +854,9 @@ def main():
     kern_ms = np.zeros(lvp.KERNEL_SLOTS)
     kern_launches = np.zeros(lvp.KERNEL_SLOTS, dtype=np.int64)
     kern_bytes = np.zeros(lvp.KERNEL_SLOTS, dtype=np.int64)
+    profile_marker()
     ri, _ = step(timing=True)
+    profile_marker()
     for lv in ri.levels:
         i = lv.info
         kern_ms += np.array(i["kern_ms"])
