@@ -18,12 +18,31 @@ namespace {
 // Vertices are stored at positions i; orig[i] is the vertex id (null: i).
 // Community ids are vertex ids, and renumbering goes by the smallest member
 // id, so minv and the first-member flags are indexed by id.
-__global__ void k_minv(int32_t n, const int32_t* comm, const int32_t* orig, int32_t* minv)
+// The lanes of a wavefront that share the first lane's community take one
+// atomic together (a label held by most vertices, as after label
+// propagation, would otherwise see one atomic per member); the others read
+// the current minimum from L2 first and skip the atomic when it is smaller.
+__device__ __forceinline__ void min_if_smaller(int32_t* at, int32_t v)
 {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t c = comm[i];
-        const int32_t id = orig ? orig[i] : (int32_t)i;
-        if (minv[c] > id) atomicMin(&minv[c], id);  // read first: skips most contended atomics
+    if (__hip_atomic_load(at, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > v) atomicMin(at, v);
+}
+__global__ __launch_bounds__(256) void k_minv(int32_t n, const int32_t* comm, const int32_t* orig, int32_t* minv)
+{
+    for (int64_t base = (int64_t)blockIdx.x * 256; base < n; base += (int64_t)gridDim.x * 256) {
+        const int64_t i = base + threadIdx.x;
+        const bool ok = i < n;
+        const int32_t c = ok ? comm[i] : 0;
+        const int32_t id = ok ? (orig ? orig[i] : (int32_t)i) : INT32_MAX;
+        const uint64_t live = __ballot(ok);
+        if (live == 0) continue;
+        const int leader = __ffsll((unsigned long long)live) - 1;
+        const int32_t lc = __shfl(c, leader);
+        const bool with = ok && c == lc;
+        int32_t m = with ? id : INT32_MAX;
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) m = min(m, __shfl_xor(m, d));
+        if ((int)lane_id() == leader) min_if_smaller(&minv[lc], m);
+        if (ok && !with) min_if_smaller(&minv[c], id);
     }
 }
 __global__ void k_first_flag(int32_t n, const int32_t* comm, const int32_t* orig, const int32_t* minv, int32_t* flag)
