@@ -603,9 +603,10 @@ def profile_summary(paths, out_dir, command):
     """Summaries for profiles/ from rocprofv3 databases of
     `bench.py --steps 1 --warmup 0 ... --copy-probe-mib 1024` (kernel trace,
     FETCH_SIZE pass, WRITE_SIZE pass, TCC hit/miss pass): per kernel, the
-    dispatches of the instrumented step (Louvain, all levels, and LPA: those
-    between the two marker launches of the copy probe's kernel), averaged;
-    the first launch of that kernel is the 1 GiB calibration copy.
+    dispatches of the instrumented step's Louvain (all levels: those between
+    the first two of the three marker launches of the copy probe's kernel
+    around its Louvain and LPA), averaged; the first launch of that kernel is
+    the 1 GiB calibration copy.
     Writes <out_dir>/move_kernels_rmat24_kernel_trace.md,
     move_kernels_rmat24_pmc.md and pmc_rmat24.txt (read by the roofline's
     `traffic`)."""
@@ -616,11 +617,11 @@ def profile_summary(paths, out_dir, command):
         n = re.sub(r"^void |lv::\(anonymous namespace\)::|lv::", "", n).split("(")[0]
         return n
 
-    def louvain_dispatches(db):
+    def louvain_dispatches(db, part=0):
         con = sqlite3.connect(db)
         rows = con.execute("select dispatch_id, name, duration from kernels order by start").fetchall()
         marks = [i for i, r in enumerate(rows) if "bitwise_not" in r[1]]
-        a, b = marks[-2], marks[-1]
+        a, b = marks[-3 - part], marks[-2 - part]
         return con, rows[a + 1:b], rows[:marks[0] + 1]
 
     def copy_probe(rows):
@@ -658,18 +659,29 @@ def profile_summary(paths, out_dir, command):
         f, w = avg("fetch", kern, "FETCH_SIZE"), avg("write", kern, "WRITE_SIZE")
         h, m = avg("hit", kern, "TCC_HIT_sum"), avg("hit", kern, "TCC_MISS_sum")
         rows_out.append((kern, len(ts), sum(ts) / len(ts), sum(ts), f, w, h, m))
+    _, sel_lpa, _ = louvain_dispatches(paths[0], part=-1)
+    dur_lpa = {}
+    for d, n, t in sel_lpa:
+        dur_lpa.setdefault(short(n), []).append(t / 1e6)
     os.makedirs(out_dir, exist_ok=True)
     with open(os.path.join(out_dir, "move_kernels_rmat24_kernel_trace.md"), "w") as fh:
-        fh.write("# Kernel trace: R-MAT 24, the instrumented step (Louvain, all levels, and LPA)\n\n")
+        fh.write("# Kernel trace: R-MAT 24, the instrumented step\n\n")
         fh.write("Command (run from the repository root on the GPU host, with `cd /tmp && export TMPDIR=/tmp` for the "
                  "profiler's files):\n\n```\n" + command[0] + "\n```\n\n")
-        fh.write("Dispatches between the two marker launches around the instrumented step, "
+        fh.write("Dispatches between the marker launches around the instrumented step's Louvain (all levels), "
                  "grouped by kernel.  bench.py's roofline takes its dominant kernel's average from HIP events on "
-                 "the same step.\n\n| kernel | dispatches | avg ms | total ms |\n|---|---:|---:|---:|\n")
+                 "the same calls.  Sum of the dispatches: %.3f ms.\n\n| kernel | dispatches | avg ms | total ms |\n"
+                 "|---|---:|---:|---:|\n" % sum(r[3] for r in rows_out))
         for kern, nd, a, t, *_ in rows_out[:40]:
             fh.write(f"| `{kern}` | {nd} | {a:.4f} | {t:.3f} |\n")
+        tot = sum(sum(v) for v in dur_lpa.values())
+        fh.write("\nLPA of the same step (launched for every sweep up to the limit; after the stopping rule a "
+                 "dispatch returns at once): sum of the dispatches %.3f ms.\n\n| kernel | dispatches | avg ms | "
+                 "total ms |\n|---|---:|---:|---:|\n" % tot)
+        for kern, ts in sorted(dur_lpa.items(), key=lambda kv: -sum(kv[1]))[:20]:
+            fh.write(f"| `{kern}` | {len(ts)} | {sum(ts) / len(ts):.4f} | {sum(ts):.3f} |\n")
     with open(os.path.join(out_dir, "move_kernels_rmat24_pmc.md"), "w") as fh:
-        fh.write("# HBM counters: R-MAT 24, the instrumented step (Louvain and LPA)\n\nThree rocprofv3 passes, one counter "
+        fh.write("# HBM counters: R-MAT 24, the instrumented step's Louvain (all levels)\n\nThree rocprofv3 passes, one counter "
                  "group each:\n\n```\n" + "\n".join(command[1:]) + "\n```\n\n")
         fh.write(f"Calibration: the 1 GiB copy probe (torch bitwise_not: 1 GiB read, 1 GiB written) reads "
                  f"FETCH_SIZE = {fetch_factor:.4f} x its bytes read and WRITE_SIZE = {write_factor:.4f} x its bytes "
@@ -686,7 +698,7 @@ def profile_summary(paths, out_dir, command):
             fh.write(f"| `{kern}` | {nd} | {a:.4f} | {f / 1024:.2f} | {w / 1024:.2f} | {cal:.1f} | {hit:.1f} |\n")
     with open(os.path.join(out_dir, "pmc_rmat24.txt"), "w") as fh:
         fh.write("# Per-dispatch HBM counters of the move kernels on R-MAT 24 (see move_kernels_rmat24_pmc.md);\n"
-                 "# fetch_kib / write_kib: FETCH_SIZE / WRITE_SIZE averaged over the instrumented step's\n"
+                 "# fetch_kib / write_kib: FETCH_SIZE / WRITE_SIZE averaged over the instrumented step's Louvain\n"
                  "# dispatches of the kernel, copy_*_factor: the counter's reading per byte of a plain 1 GiB copy;\n"
                  "# src: digest of the kernels' sources when taken.\n")
         for kern, nd, a, t, f, w, h, m in rows_out:
@@ -855,7 +867,9 @@ def main():
     kern_launches = np.zeros(lvp.KERNEL_SLOTS, dtype=np.int64)
     kern_bytes = np.zeros(lvp.KERNEL_SLOTS, dtype=np.int64)
     profile_marker()
-    ri, _ = step(timing=True)
+    ri = lvp.louvain(dg, timing=True, level_labels=False)
+    profile_marker()
+    lvp.lpa(dg, timing=True)
     profile_marker()
     for lv in ri.levels:
         i = lv.info
