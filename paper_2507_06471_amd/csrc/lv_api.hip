@@ -185,6 +185,60 @@ uint64_t next_pow2(uint64_t x)
     return p;
 }
 
+// Device buffers that results hold (level labels, final labels) come from a
+// pool of the handle and go back to it when the result is destroyed, so that
+// repeated calls neither allocate nor free (a free waits for the whole
+// device).  A result may outlive its handle: a buffer whose pool is gone is
+// freed.  The pool keeps what it holds until the handle is destroyed.
+struct BufPool {
+    std::mutex mu;
+    std::vector<std::unique_ptr<DevBuf>> free;
+};
+struct PooledBuf {
+    std::unique_ptr<DevBuf> buf;
+    std::weak_ptr<BufPool> pool;
+    PooledBuf() = default;
+    PooledBuf(const PooledBuf&) = delete;
+    PooledBuf& operator=(const PooledBuf&) = delete;
+    ~PooledBuf() { give_back(); }
+    void give_back()
+    {
+        if (buf && buf->p) {
+            if (std::shared_ptr<BufPool> pl = pool.lock()) {
+                std::lock_guard<std::mutex> lk(pl->mu);
+                pl->free.push_back(std::move(buf));
+            }
+        }
+        buf.reset();
+    }
+    int32_t* i32() const { return buf ? buf->as<int32_t>() : nullptr; }
+};
+// Take the pool's smallest buffer of at least `bytes` (else its largest,
+// grown) into `out`.
+hipError_t pool_take(const std::shared_ptr<BufPool>& pool, size_t bytes, PooledBuf& out)
+{
+    out.give_back();
+    out.pool = pool;
+    {
+        std::lock_guard<std::mutex> lk(pool->mu);
+        const size_t want = (std::max<size_t>(bytes, 1) + 255) & ~(size_t)255;
+        int best = -1;
+        for (int i = 0; i < (int)pool->free.size(); ++i) {
+            const size_t c = pool->free[i]->cap;
+            if (best < 0) { best = i; continue; }
+            const size_t b = pool->free[best]->cap;
+            const bool fits = c >= want, best_fits = b >= want;
+            if (fits ? (!best_fits || c < b) : (!best_fits && c > b)) best = i;
+        }
+        if (best >= 0) {
+            out.buf = std::move(pool->free[best]);
+            pool->free.erase(pool->free.begin() + best);
+        }
+    }
+    if (!out.buf) out.buf = std::make_unique<DevBuf>();
+    return out.buf->ensure(std::max<size_t>(bytes, 1));
+}
+
 }  // namespace
 
 struct lv_graph {
@@ -222,6 +276,7 @@ struct lv_graph {
     // would free are parked here until the handle is destroyed.
     bool keep_scratch = false;
     std::vector<std::unique_ptr<DevBuf>> parked;
+    std::shared_ptr<BufPool> pool = std::make_shared<BufPool>();  // result buffers
     void release_or_park(DevBuf& b)
     {
         if (!b.p) return;
@@ -240,7 +295,7 @@ namespace {
 
 // Labels of one packed level, shared by the graphs that took part in it.
 struct LabelStore {
-    DevBuf labels;
+    PooledBuf labels;
     int32_t n = 0;
 };
 
@@ -266,7 +321,7 @@ struct lv_result {
     int32_t G = 1;
     int32_t n0 = 0;
     std::vector<GraphResult> graphs;
-    DevBuf final_labels;  // packed like the handle's vertices
+    PooledBuf final_labels;  // packed like the handle's vertices
 };
 
 namespace {
@@ -821,7 +876,7 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
                                  ws.gmoves.as<uint32_t>(), S, theta, async ? 1 : 2, ec_read_max, ec_fill_max, s));
         if (e) HIP_TRY(tm.mark(&(*e)[2 * NUM_CLS + 4]));
         if (use_ec) {  // rewrite the changed entries if the next sweep reads the cache
-            HIP_TRY(launch_cache_refresh(rmap, ws.rows.as<int4>(), ws.chg.as<uint8_t>(), G.idx, G.rev,
+            HIP_TRY(launch_cache_refresh(rmap, ws.rows.as<int4>(), ws.chg.as<uint8_t>(), G.rev,
                                          ws.cs.as<int2>(), ws.ce.as<int2>(), ctl, s));
             if (hubs.nhubs > 0) HIP_TRY(launch_hub_cache_refresh(a, hubs.args, ws.chg.as<uint8_t>() + nonhub, G.rev, s));
         }
@@ -1514,15 +1569,15 @@ lv_status louvain_impl(lv_graph* g, const Params& p, bool keep_graphs, lv_result
         gr.M = g->M[q];
         gr.q_int = g->q0[q];
     }
-    HIP_TRY(r->final_labels.ensure(sizeof(int32_t) * (size_t)std::max(g->n, 1)));
+    HIP_TRY(pool_take(g->pool, sizeof(int32_t) * (size_t)std::max(g->n, 1), r->final_labels));
     // final labels start as each vertex's index within its graph
     {
         HIP_TRY(ws.gmeta.ensure(sizeof(int32_t) * ((size_t)G0 + 1)));
         HIP_TRY(hipMemcpyAsync(ws.gmeta.p, g->voff.data(), sizeof(int32_t) * ((size_t)G0 + 1), hipMemcpyHostToDevice, s));
         // (a graph that accepts no level keeps the singleton partition in id order)
-        HIP_TRY(launch_iota(r->final_labels.as<int32_t>(), g->n, s));
-        HIP_TRY(launch_local_labels(g->n, r->final_labels.as<int32_t>(), G0 > 1 ? g->d_gid.as<int32_t>() : nullptr,
-                                    ws.gmeta.as<int32_t>(), r->final_labels.as<int32_t>(), s));
+        HIP_TRY(launch_iota(r->final_labels.i32(), g->n, s));
+        HIP_TRY(launch_local_labels(g->n, r->final_labels.i32(), G0 > 1 ? g->d_gid.as<int32_t>() : nullptr,
+                                    ws.gmeta.as<int32_t>(), r->final_labels.i32(), s));
     }
     LevelGraph G = level0(g);
     std::vector<int64_t> eoff = g->eoff;
@@ -1566,11 +1621,11 @@ lv_status louvain_impl(lv_graph* g, const Params& p, bool keep_graphs, lv_result
         if (any) {
             store = std::make_shared<LabelStore>();
             store->n = G.n;
-            HIP_TRY(store->labels.ensure(sizeof(int32_t) * (size_t)std::max(G.n, 1)));
+            HIP_TRY(pool_take(g->pool, sizeof(int32_t) * (size_t)std::max(G.n, 1), store->labels));
             if (G.orig)  // kept in vertex-id order
-                HIP_TRY(launch_scatter_i32(ws.labels.as<int32_t>(), G.orig, G.n, store->labels.as<int32_t>(), s));
+                HIP_TRY(launch_scatter_i32(ws.labels.as<int32_t>(), G.orig, G.n, store->labels.i32(), s));
             else
-                HIP_TRY(launch_copy_i32(store->labels.as<int32_t>(), ws.labels.as<int32_t>(), G.n, s));
+                HIP_TRY(launch_copy_i32(store->labels.i32(), ws.labels.as<int32_t>(), G.n, s));
         }
         for (int32_t c = 0; c < G.G; ++c) {
             GraphResult& gr = r->graphs[orig[c]];
@@ -1613,9 +1668,9 @@ lv_status louvain_impl(lv_graph* g, const Params& p, bool keep_graphs, lv_result
         // the level's labels in vertex-id order (the store's copy when the
         // level is stored by degree)
         if (any) {
-            const int32_t* lab_id = G.orig ? store->labels.as<int32_t>() : ws.labels.as<int32_t>();
+            const int32_t* lab_id = G.orig ? store->labels.i32() : ws.labels.as<int32_t>();
             if (G0 == 1) {
-                HIP_TRY(launch_compose(g->n, r->final_labels.as<int32_t>(), lab_id, nullptr, nullptr, nullptr, nullptr, s));
+                HIP_TRY(launch_compose(g->n, r->final_labels.i32(), lab_id, nullptr, nullptr, nullptr, nullptr, s));
             } else {
                 std::vector<int32_t> meta((size_t)G0 + 2 * (size_t)G.G, -1);
                 for (int32_t c = 0; c < G.G; ++c) {
@@ -1625,7 +1680,7 @@ lv_status louvain_impl(lv_graph* g, const Params& p, bool keep_graphs, lv_result
                 }
                 HIP_TRY(ws.gmeta.ensure(sizeof(int32_t) * meta.size()));
                 HIP_TRY(hipMemcpyAsync(ws.gmeta.p, meta.data(), sizeof(int32_t) * meta.size(), hipMemcpyHostToDevice, s));
-                HIP_TRY(launch_compose(g->n, r->final_labels.as<int32_t>(), lab_id,
+                HIP_TRY(launch_compose(g->n, r->final_labels.i32(), lab_id,
                                        g->d_gid.as<int32_t>(), ws.gmeta.as<int32_t>(), ws.gmeta.as<int32_t>() + G0,
                                        ws.gmeta.as<int32_t>() + G0 + G.G, s));
                 HIP_TRY(hipStreamSynchronize(s));
@@ -2313,7 +2368,7 @@ lv_status lv_result_graph_level_labels(const lv_result* r, int32_t g, int32_t le
     const int32_t cnt = rec.info.n;
     if (cnt <= 0) return LV_OK;
     std::vector<int32_t> h((size_t)cnt);
-    HIP_TRY(hipMemcpy(h.data(), rec.store->labels.as<int32_t>() + rec.vbase, sizeof(int32_t) * (size_t)cnt,
+    HIP_TRY(hipMemcpy(h.data(), rec.store->labels.i32() + rec.vbase, sizeof(int32_t) * (size_t)cnt,
                       hipMemcpyDeviceToHost));
     for (auto& x : h) x -= rec.nbase;
     HIP_TRY(hipMemcpy(labels, h.data(), sizeof(int32_t) * (size_t)cnt,
@@ -2326,7 +2381,7 @@ lv_status lv_result_graph_final_labels(const lv_result* r, int32_t g, int32_t* l
     const GraphResult* gr = graph_of(r, g);
     if (!r || !labels || (kind != LV_MEM_HOST && kind != LV_MEM_DEVICE)) return LV_E_ARG;
     if (!gr) return LV_E_NOT_FOUND;
-    return copy_out(labels, r->final_labels.as<int32_t>() + gr->fin_base, gr->n0, kind, nullptr);
+    return copy_out(labels, r->final_labels.i32() + gr->fin_base, gr->n0, kind, nullptr);
 }
 
 lv_status lv_result_graph_modularity(const lv_result* r, int32_t g, int64_t* q_int, int64_t* m, double* q)
@@ -2343,7 +2398,7 @@ lv_status lv_result_graph_modularity(const lv_result* r, int32_t g, int64_t* q_i
 lv_status lv_result_final_labels_all(const lv_result* r, int32_t* labels, lv_memkind kind)
 {
     if (!r || !labels || (kind != LV_MEM_HOST && kind != LV_MEM_DEVICE)) return LV_E_ARG;
-    return copy_out(labels, r->final_labels.as<int32_t>(), r->n0, kind, nullptr);
+    return copy_out(labels, r->final_labels.i32(), r->n0, kind, nullptr);
 }
 
 lv_status lv_result_modularity_all(const lv_result* r, int64_t* q_int, int64_t* m, double* q)
@@ -2517,14 +2572,18 @@ lv_status lv_lpa_batch(lv_graph* g, const lv_params* params, int32_t* labels, lv
     LV_TRY(resolve_tuning(g, params, p));
     Workspace& ws = g->ws;
     HIP_TRY(ws.pos.ensure(sizeof(int32_t) * ((size_t)g->n + 1)));
-    DevBuf out;
-    HIP_TRY(out.ensure(sizeof(int32_t) * (size_t)std::max(g->n, 1)));
+    // device-resident output: the labels are written in place; host output
+    // goes through a pooled buffer
+    const bool direct = kind == LV_MEM_DEVICE && g->n > 0;
+    PooledBuf out;
+    if (!direct) HIP_TRY(pool_take(g->pool, sizeof(int32_t) * (size_t)std::max(g->n, 1), out));
+    int32_t* dst = direct ? labels : out.i32();
     SweepOut so;
     std::vector<int32_t> voff2;
     std::vector<int64_t> qi;
     double ren = 0;
-    LV_TRY(lpa_impl(g, p, out.as<int32_t>(), so, voff2, qi, &ren));
-    LV_TRY(copy_out(labels, out.as<int32_t>(), g->n, kind, g->stream));
+    LV_TRY(lpa_impl(g, p, dst, so, voff2, qi, &ren));
+    if (!direct) LV_TRY(copy_out(labels, dst, g->n, kind, g->stream));
     for (int32_t c = 0; c < g->G; ++c) {
         if (sweeps) sweeps[c] = so.sweeps[c];
         if (q_int) q_int[c] = qi[c];

@@ -282,8 +282,8 @@ struct RefreshMap {
     int32_t slot_end[NUM_CLS];
     int32_t lanes_log2[NUM_CLS];
 };
-hipError_t launch_cache_refresh(const RefreshMap& mp, const int4* rows, const uint8_t* chg, const int32_t* idx,
-                                const int32_t* rev, const int2* cs, int2* ce, SweepCtl* ctl, hipStream_t s);
+hipError_t launch_cache_refresh(const RefreshMap& mp, const int4* rows, const uint8_t* chg, const int32_t* rev,
+                                const int2* cs, int2* ce, SweepCtl* ctl, hipStream_t s);
 hipError_t launch_hub_cache_refresh(const MoveArgs& a, const HubArgs& h, const uint8_t* chg_hub, const int32_t* rev,
                                     hipStream_t s);
 // Reverse-entry map of a CSR whose rows are sorted: rank[e] = position of

@@ -1310,32 +1310,36 @@ __global__ __launch_bounds__(256) void k_pairs_changed(int32_t m, const int4* ro
     if (threadIdx.x == 0 && cnt) atomicAdd(&ctl->chg_entries, cnt);
 }
 
+constexpr int32_t REFRESH_GRID = 8192;  // four rounds of resident 256-thread workgroups
+
 // Entry-cache refresh (only when the next sweep reads the cache): for every
 // listed vertex v whose pair changed, rewrite the cache entry of each of its
-// neighbours u that refers to v (the reverse of v's entry for u).  Like the
-// move kernels, rows of one degree class get a group of lanes each (at most
-// a 256-thread workgroup), so that the work of a block does not depend on how
-// long the changed rows around it are.
+// neighbours u that refers to v (the reverse of v's entry for u; a loop is
+// its own reverse and keeps its empty entry).  Like the move kernels, rows of
+// one degree class get a group of lanes each (at most a 256-thread
+// workgroup), so that the work of a block does not depend on how long the
+// changed rows around it are; a capped grid walks the blocks, so that the
+// launch costs little in the sweeps that do not refresh.
 __global__ __launch_bounds__(256) void k_cache_refresh(RefreshMap mp, const int4* __restrict__ rows,
                                                        const uint8_t* __restrict__ chg,
-                                                       const int32_t* __restrict__ idx,
                                                        const int32_t* __restrict__ rev, const int2* __restrict__ cs,
                                                        int2* __restrict__ ce, const SweepCtl* ctl)
 {
     if (ctl->all_done || ctl->ec_mode != EC_READ) return;
-    const int32_t b = (int32_t)blockIdx.x;
-    int c = 0;
-    while (c + 1 < mp.nclass && mp.blk_first[c + 1] <= b) ++c;
-    const int lg = mp.lanes_log2[c];
-    const int32_t G = 1 << lg, NG = 256 >> lg;
-    const int32_t g = (int32_t)threadIdx.x >> lg, lane = (int32_t)threadIdx.x & (G - 1);
-    const int64_t t = (int64_t)mp.slot_first[c] + (int64_t)(b - mp.blk_first[c]) * NG + g;
-    if (t >= mp.slot_end[c] || !chg[t]) return;
-    const int4 r = rows[t];
-    const int2 p = cs[r.x];
-    for (int32_t e = r.y + lane; e < r.z; e += G) {
-        const int32_t u = __builtin_nontemporal_load(&idx[e]);
-        if (u != r.x) ce[rev[e]] = p;
+    for (int32_t b = (int32_t)blockIdx.x; b < mp.blk_first[mp.nclass]; b += (int32_t)gridDim.x) {
+        int c = 0;
+        while (c + 1 < mp.nclass && mp.blk_first[c + 1] <= b) ++c;
+        const int lg = mp.lanes_log2[c];
+        const int32_t G = 1 << lg, NG = 256 >> lg;
+        const int32_t g = (int32_t)threadIdx.x >> lg, lane = (int32_t)threadIdx.x & (G - 1);
+        const int64_t t = (int64_t)mp.slot_first[c] + (int64_t)(b - mp.blk_first[c]) * NG + g;
+        if (t >= mp.slot_end[c] || !chg[t]) continue;
+        const int4 r = rows[t];
+        const int2 p = cs[r.x];
+        for (int32_t e = r.y + lane; e < r.z; e += G) {
+            const int32_t re = __builtin_nontemporal_load(&rev[e]);
+            if (re != e) ce[re] = p;
+        }
     }
 }
 
@@ -1349,8 +1353,8 @@ __global__ __launch_bounds__(256) void k_hub_cache_refresh(MoveArgs a, HubArgs h
     const int32_t v = h.hub_vert[hh];
     const int2 p = a.cs[v];
     for (int32_t e = h.mk_beg[blockIdx.x] + (int32_t)threadIdx.x; e < h.mk_end[blockIdx.x]; e += 256) {
-        const int32_t u = __builtin_nontemporal_load(&a.idx[e]);
-        if (u != v) a.ce[rev[e]] = p;
+        const int32_t re = __builtin_nontemporal_load(&rev[e]);
+        if (re != e) a.ce[re] = p;
     }
 }
 
@@ -1363,11 +1367,12 @@ hipError_t launch_pairs_changed(int32_t m, const int4* rows, const int32_t* comm
     k_pairs_changed<<<grid_for(m, 256, 8192), 256, 0, s>>>(m, rows, comm, sigma, cs, chg, mode, ctl);
     return hipGetLastError();
 }
-hipError_t launch_cache_refresh(const RefreshMap& mp, const int4* rows, const uint8_t* chg, const int32_t* idx,
-                                const int32_t* rev, const int2* cs, int2* ce, SweepCtl* ctl, hipStream_t s)
+hipError_t launch_cache_refresh(const RefreshMap& mp, const int4* rows, const uint8_t* chg, const int32_t* rev,
+                                const int2* cs, int2* ce, SweepCtl* ctl, hipStream_t s)
 {
     if (mp.nclass <= 0 || mp.blk_first[mp.nclass] <= 0) return hipSuccess;
-    k_cache_refresh<<<(unsigned)mp.blk_first[mp.nclass], 256, 0, s>>>(mp, rows, chg, idx, rev, cs, ce, ctl);
+    const unsigned grid = (unsigned)std::min<int32_t>(mp.blk_first[mp.nclass], REFRESH_GRID);
+    k_cache_refresh<<<grid, 256, 0, s>>>(mp, rows, chg, rev, cs, ce, ctl);
     return hipGetLastError();
 }
 hipError_t launch_hub_cache_refresh(const MoveArgs& a, const HubArgs& h, const uint8_t* chg_hub, const int32_t* rev,
