@@ -78,9 +78,9 @@ typedef enum lv_memkind { LV_MEM_HOST = 0, LV_MEM_DEVICE = 1 } lv_memkind;
                           /* degree within each graph, for cache locality; results are the same)  */
 #define LV_EDGES_NO_LOOPS 4u /* lv_graph_create_edges: drop loops (u, u)                          */
 #define LV_EDGES_SIMPLE 8u   /* lv_graph_create_edges: a pair listed several times keeps weight 1 */
+                             /* (no weights may be given)                                        */
 #define LV_NO_ENTRY_CACHE 16u /* create: skip the reverse-entry map (int32 per CSR entry); calls on  */
                               /* the handle then never use the entry cache (see LV_NO_CACHE)         */
-                             /* (no weights may be given)                                        */
 
 /* lv_params.flags */
 #define LV_TIMING 1u      /* record per-kernel HIP event times (see lv_level_info); sweeps */
