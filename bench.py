@@ -599,14 +599,17 @@ def workloads_leg(args, lvp, graphgen, np, torch):
     return out
 
 
-def profile_summary(paths, out_dir, command):
+def profile_summary(paths, out_dir, command, run_log=None):
     """Summaries for profiles/ from rocprofv3 databases of
     `bench.py --steps 1 --warmup 0 ... --copy-probe-mib 1024` (kernel trace,
     FETCH_SIZE pass, WRITE_SIZE pass, TCC hit/miss pass): per kernel, the
     dispatches of the instrumented step's Louvain (all levels: those between
     the first two of the three marker launches of the copy probe's kernel
     around its Louvain and LPA), averaged; the first launch of that kernel is
-    the 1 GiB calibration copy.
+    the 1 GiB calibration copy, the second marks the end of the timed steps
+    (whose GPU idle time is summed).  run_log: the kernel-trace run's output
+    (its JSON line gives the graph's entry count, for the probes'
+    calibration on the gather pattern).
     Writes <out_dir>/move_kernels_rmat24_kernel_trace.md,
     move_kernels_rmat24_pmc.md and pmc_rmat24.txt (read by the roofline's
     `traffic`)."""
@@ -659,6 +662,46 @@ def profile_summary(paths, out_dir, command):
         f, w = avg("fetch", kern, "FETCH_SIZE"), avg("write", kern, "WRITE_SIZE")
         h, m = avg("hit", kern, "TCC_HIT_sum"), avg("hit", kern, "TCC_MISS_sum")
         rows_out.append((kern, len(ts), sum(ts) / len(ts), sum(ts), f, w, h, m))
+    # the timed step (captured sweeps): GPU busy and idle between its first
+    # and last dispatch, from the kernel trace
+    con0 = sqlite3.connect(paths[0])
+    allk = con0.execute("select name, start, end from kernels order by start").fetchall()
+    mk = [i for i, r in enumerate(allk) if "bitwise_not" in r[0]]
+    step = allk[mk[0] + 1:mk[1]]
+    idle = busy = span = 0.0
+    gaps10 = 0
+    if step:
+        edge = step[0][2]
+        busy = (step[0][2] - step[0][1]) / 1e6
+        for nme, st, en in step[1:]:
+            gap = max(0, st - edge) / 1e6
+            idle += gap
+            gaps10 += gap > 0.01
+            busy += max(0, en - max(st, edge)) / 1e6
+            edge = max(edge, en)
+        span = (edge - step[0][1]) / 1e6
+    # the library's probes, on the same graph: a 16-byte copy of the index
+    # array and the pure gather (index stream + one random 8-byte pair per entry)
+    nnz = None
+    if run_log and os.path.exists(run_log):
+        import json
+        for line in open(run_log):
+            if line.startswith("{") and '"metric"' in line:
+                nnz = json.loads(line)["config"]["nnz"]
+
+    def probe_avg(db, name, counter):
+        c = sqlite3.connect(db)
+        ids = {d for d, n in c.execute("select dispatch_id, name from kernels") if name in n}
+        vals = {}
+        for d, cn, v in c.execute("select dispatch_id, counter_name, value from counters_collection"):
+            if d in ids and cn == counter:
+                vals[d] = vals.get(d, 0.0) + v
+        return sum(vals.values()) / len(vals) if vals else None
+
+    probes = {}
+    for pn in ("k_probe_copy", "k_probe_gather"):
+        probes[pn] = (probe_avg(paths[1], pn, "FETCH_SIZE"), probe_avg(paths[2], pn, "WRITE_SIZE"),
+                      probe_avg(paths[3], pn, "TCC_HIT_sum"), probe_avg(paths[3], pn, "TCC_MISS_sum"))
     _, sel_lpa, _ = louvain_dispatches(paths[0], part=-1)
     dur_lpa = {}
     for d, n, t in sel_lpa:
@@ -674,6 +717,9 @@ def profile_summary(paths, out_dir, command):
                  "|---|---:|---:|---:|\n" % sum(r[3] for r in rows_out))
         for kern, nd, a, t, *_ in rows_out[:40]:
             fh.write(f"| `{kern}` | {nd} | {a:.4f} | {t:.3f} |\n")
+        fh.write(f"\nThe timed step before it (captured sweeps, Louvain and LPA): {span:.2f} ms from its first to "
+                 f"its last dispatch, GPU busy {busy:.2f} ms, idle {idle:.2f} ms between dispatches ({gaps10} gaps "
+                 f"over 10 us).\n")
         tot = sum(sum(v) for v in dur_lpa.values())
         fh.write("\nLPA of the same step (launched for every sweep up to the limit; after the stopping rule a "
                  "dispatch returns at once): sum of the dispatches %.3f ms.\n\n| kernel | dispatches | avg ms | "
@@ -688,6 +734,22 @@ def profile_summary(paths, out_dir, command):
                  "written (KiB).  Calibrated bytes = FETCH_SIZE / fetch factor + WRITE_SIZE / write factor.  These "
                  "TCC counters see requests from L2 to the memory fabric: a line served by the Infinity Cache (MALL) "
                  "is counted like one from HBM, so 'HBM bytes' here is an upper bound on DRAM traffic.\n\n")
+        if nnz:
+            fh.write("The library's probes over the same graph's index array (E = %d entries), per dispatch:\n\n"
+                     "| probe | requested bytes | FETCH_SIZE / requested read | WRITE_SIZE / requested write | "
+                     "L2 hit %% |\n|---|---:|---:|---:|---:|\n" % nnz)
+            for pn, rd, wr in (("k_probe_copy", 4 * nnz, 4 * nnz), ("k_probe_gather", 12 * nnz, 0)):
+                f_, w_, h_, m_ = probes[pn]
+                if f_ is None:
+                    continue
+                hit = 100.0 * h_ / (h_ + m_) if h_ is not None and m_ and h_ + m_ > 0 else float("nan")
+                wtxt = f"{w_ * 1024 / wr:.3f}" if wr and w_ is not None else "-"
+                fh.write(f"| `{pn}` | {rd + wr} | {f_ * 1024 / rd:.3f} | {wtxt} | {hit:.1f} |\n")
+            fh.write("\nThe copy probe reads the index array once (4E bytes read, 4E written); the gather probe "
+                     "streams it and gathers one random 8-byte pair per entry from an n-entry table (12E bytes "
+                     "requested).  Its FETCH_SIZE per requested byte, over the copy's, is the line amplification "
+                     "of random 8-byte gathers on this graph (the 134 MB table fits in the Infinity Cache, whose "
+                     "hits these counters cannot tell from HBM reads).\n\n")
         fh.write("| kernel | dispatches | avg ms | FETCH_SIZE MiB | WRITE_SIZE MiB | calibrated MB | L2 hit % |\n"
                  "|---|---:|---:|---:|---:|---:|---:|\n")
         for kern, nd, a, t, f, w, h, m in rows_out[:40]:
@@ -734,9 +796,9 @@ def KERNEL_SLOT_OF(kern):
 
 def main():
     if len(sys.argv) > 1 and sys.argv[1] == "--profile-summary":
-        # bench.py --profile-summary OUT_DIR KT_DB FETCH_DB WRITE_DB HIT_DB CMD_KT CMD_FETCH CMD_WRITE CMD_HIT
+        # bench.py --profile-summary OUT_DIR KT_DB FETCH_DB WRITE_DB HIT_DB CMD_KT CMD_FETCH CMD_WRITE CMD_HIT [KT_LOG]
         a = sys.argv[2:]
-        profile_summary(a[1:5], a[0], a[5:9])
+        profile_summary(a[1:5], a[0], a[5:9], a[9] if len(a) > 9 else None)
         return
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -837,6 +899,7 @@ def main():
         log(f"step {k}: {time.perf_counter() - ts:.3f}s")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    profile_marker()  # after the timed steps (outside the timed region)
     # the labels to host memory, after the timed region
     for r, lp in runs:
         r.final_labels = r.final_labels.cpu().numpy()
