@@ -254,6 +254,7 @@ struct lv_graph {
     std::vector<int64_t> eoff;   // [G+1] entry offset of each graph
     std::vector<int64_t> M;      // [G] total volume
     std::vector<int64_t> q0;     // [G] Q_int of singletons
+    std::vector<int64_t> trace;  // [G] sum of the diagonal entries (loops, doubled)
     DevBuf d_gid, d_M;           // per vertex graph id, per graph M (G > 1)
     // Storage order: vertices are kept by descending degree within each
     // graph (unless LV_KEEP_ORDER); orig[p] = vertex id at position p,
@@ -451,6 +452,7 @@ struct SweepOut {
     int32_t isolated = 0;          // vertices without entries
     int32_t cached_sweeps = 0;     // sweeps that read the entry cache
     int64_t refreshed = 0;         // cache entries rewritten after commits
+    int32_t ec_last = EC_GATHER;   // how the last sweep got its pairs (EC_GATHER without a cache)
 };
 
 // Hub (partition) layout for one level.
@@ -947,6 +949,7 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
     HIP_TRY(hipStreamSynchronize(s));
     out.cached_sweeps = use_ec ? h_ctl->ec_reads : 0;
     out.refreshed = use_ec ? (int64_t)h_ctl->refreshed : 0;
+    out.ec_last = use_ec ? h_ctl->ec_last : EC_GATHER;
     out.moves.assign(h_moves, h_moves + (size_t)G.G * S);
     out.sweeps.assign(h_sweeps, h_sweeps + G.G);
     out.executed = 0;
@@ -1763,7 +1766,16 @@ lv_status lpa_impl(lv_graph* g, const Params& p, int32_t* out_dev, SweepOut& so,
     HIP_TRY(ws.gsq.ensure(sizeof(int64_t) * (size_t)G.G));
     HIP_TRY(hipMemsetAsync(ws.gsum.p, 0, sizeof(int64_t) * (size_t)G.G, s));
     HIP_TRY(hipMemsetAsync(ws.gsq.p, 0, sizeof(int64_t) * (size_t)G.G, s));
-    HIP_TRY(launch_sigma_in(G.n, G.off, G.idx, G.w, G.nnz, ws.comm.as<int32_t>(), G.gid, ws.gsum.as<int64_t>(), s));
+    // One graph whose last sweep read or filled the entry cache and moved no
+    // vertex: the cache holds every entry's neighbour label of the final
+    // labels, so Sigma_in streams it (plus the loops) instead of gathering.
+    const bool cached = G.G == 1 && (int64_t)g->trace.size() == 1 && so.sweeps[0] >= 1 &&
+                        (so.ec_last == EC_READ || so.ec_last == EC_FILL) && so.moves[(size_t)so.sweeps[0] - 1] == 0;
+    if (cached)
+        HIP_TRY(launch_sigma_in_cached(G.n, G.off, ws.ce.as<int2>(), G.w, G.nnz, ws.comm.as<int32_t>(),
+                                       ws.gsum.as<int64_t>(), s));
+    else
+        HIP_TRY(launch_sigma_in(G.n, G.off, G.idx, G.w, G.nnz, ws.comm.as<int32_t>(), G.gid, ws.gsum.as<int64_t>(), s));
     HIP_TRY(launch_sum_sq(ws.sigma.as<int32_t>(), G.n, G.gid, ws.gsq.as<int64_t>(), s));
     std::vector<int64_t> sin(G.G), sq(G.G);
     SyncOnExit sync_sums{s};
@@ -1779,6 +1791,7 @@ lv_status lpa_impl(lv_graph* g, const Params& p, int32_t* out_dev, SweepOut& so,
         HIP_TRY(launch_local_labels(G.n, ws.labels.as<int32_t>(), G.gid, ws.gmeta.as<int32_t>(), out_dev, s));
     }
     HIP_TRY(hipStreamSynchronize(s));
+    if (cached) sin[0] += g->trace[0];
     q_int.resize(G.G);
     for (int32_t c = 0; c < G.G; ++c) q_int[c] = G.Mh[c] * sin[c] - sq[c];
     *ren_ms = tm.on ? elapsed(t0, t1) : 0.0;
@@ -1939,6 +1952,7 @@ static lv_status graph_setup(lv_graph* g, int32_t n, const int32_t* offsets, con
     HIP_TRY(hipStreamSynchronize(s));
     if (err & 16) { set_error_msg("a loop's doubled weight exceeds 2^31 - 1"); return LV_E_OVERFLOW; }
     g->M = Ms;
+    g->trace = tr;
     g->q0.resize(G);
     for (int32_t q = 0; q < G; ++q) {
         if (Ms[q] > (int64_t)INT32_MAX) { set_error_msg("total volume M >= 2^31 (graph " + std::to_string(q) + ")"); return LV_E_OVERFLOW; }

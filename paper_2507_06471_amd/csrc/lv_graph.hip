@@ -193,6 +193,23 @@ __global__ __launch_bounds__(TILE_BS) void k_sigma_in(int32_t n, const int32_t* 
     acc.flush_block(out);
 }
 
+// Sigma_in without gathers: the neighbour's label of every entry is read
+// from the entry cache, in entry order (loop entries, EMPTY_KEY there, are
+// left to the caller).
+__global__ __launch_bounds__(TILE_BS) void k_sigma_in_cached(int32_t n, const int32_t* off, const int2* ce,
+                                                              const int32_t* w, int64_t nnz, const int32_t* labels,
+                                                              unsigned long long* out)
+{
+    GraphAcc acc;
+    const int64_t tiles = ((int64_t)n + nnz + TILE - 1) / TILE;
+    for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x)
+        for_tile_entries_co_at<TILE_BS, TILE_IT>(t, off, n, nnz, [&](int32_t r, int64_t e) {
+            if (__builtin_nontemporal_load(&ce[e].x) == labels[r])
+                acc.add(out, 0, (unsigned long long)(w ? w[e] : 1));
+        });
+    acc.flush_block(out);
+}
+
 // tot[label] += k_i, one atomic per distinct label of a wavefront
 __global__ __launch_bounds__(256) void k_label_volumes(int32_t n, const int32_t* k, const int32_t* labels,
                                                        unsigned long long* tot)
@@ -443,6 +460,14 @@ hipError_t launch_sigma_in(int32_t n, const int32_t* off, const int32_t* idx, co
 {
     if (nnz > 0)
         k_sigma_in<<<std::min(tiles_for(n, nnz), SUM_GRID), TILE_BS, 0, s>>>(n, off, idx, w, nnz, labels, gid, (unsigned long long*)out);
+    return hipGetLastError();
+}
+hipError_t launch_sigma_in_cached(int32_t n, const int32_t* off, const int2* ce, const int32_t* w, int64_t nnz,
+                                  const int32_t* labels, int64_t* out, hipStream_t s)
+{
+    if (nnz > 0)
+        k_sigma_in_cached<<<std::min(tiles_for(n, nnz), SUM_GRID), TILE_BS, 0, s>>>(n, off, ce, w, nnz, labels,
+                                                                                     (unsigned long long*)out);
     return hipGetLastError();
 }
 hipError_t launch_modularity_parts(int32_t n, const int32_t* off, const int32_t* idx, const int32_t* w, int64_t nnz,

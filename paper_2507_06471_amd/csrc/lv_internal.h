@@ -52,7 +52,7 @@ struct SweepCtl {
     unsigned long long chg_entries;   // entries whose pair the last commit changed
     unsigned long long refreshed;     // entries rewritten by cache refreshes this level
     int32_t work_next;                // next work item of the fused sweep kernel
-    int32_t pad;
+    int32_t ec_last;                  // how the last completed sweep got its pairs
 };
 constexpr int32_t EC_GATHER = 0, EC_FILL = 1, EC_READ = 2;
 
@@ -215,6 +215,11 @@ hipError_t launch_fill_gid(const int32_t* voff, int32_t G, int32_t n, int32_t* g
 // out[g] += Sigma_in of labels within graph g
 hipError_t launch_sigma_in(int32_t n, const int32_t* off, const int32_t* idx, const int32_t* w, int64_t nnz,
                            const int32_t* labels, const int32_t* gid, int64_t* out, hipStream_t s);
+// The same for one graph from an entry cache that holds every entry's
+// neighbour label of `labels` (a loop entry holds EMPTY_KEY): *out += the
+// weight of the non-loop entries inside communities; the caller adds the trace.
+hipError_t launch_sigma_in_cached(int32_t n, const int32_t* off, const int2* ce, const int32_t* w, int64_t nnz,
+                                  const int32_t* labels, int64_t* out, hipStream_t s);
 
 // classes
 hipError_t launch_classify(int32_t n, const int32_t* off, const int32_t* bounds, uint32_t* cls,

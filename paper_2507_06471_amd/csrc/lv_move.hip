@@ -456,7 +456,6 @@ __global__ __launch_bounds__(BS) void k_move(MoveArgs a)
     __shared__ int32_t rc[BS / WAVE], rw[BS / WAVE];
 
     if (a.ctl->all_done) return;
-    const int ecm = entry_mode(a);
     const int g = threadIdx.x / G, lane = threadIdx.x % G;
     const int64_t vi = (int64_t)blockIdx.x * NG + g;
     const bool has = vi < a.nverts;
@@ -1236,6 +1235,7 @@ __global__ __launch_bounds__(256) void k_sweep_end(SweepCtl* ctl, int32_t G, int
         ctl->all_done = running == 0 ? 1 : 0;
         ctl->work_next = 0;
         if (ec_read_max >= 0) {
+            ctl->ec_last = ctl->ec_mode;
             const unsigned long long chg = ctl->chg_entries;
             const bool filled = ctl->ec_mode != EC_GATHER;
             int32_t next = EC_GATHER;
@@ -1264,6 +1264,7 @@ __global__ void k_ctl_init(SweepCtl* ctl, int32_t G, const int32_t* gactive, int
         ctl->sweep = 0;
         ctl->all_done = 0;
         ctl->ec_mode = EC_GATHER;
+        ctl->ec_last = EC_GATHER;
         ctl->ec_reads = 0;
         ctl->work_next = 0;
         ctl->chg_entries = 0;
