@@ -133,7 +133,8 @@ typedef struct lv_tuning {
                         /* re-reading the vertex's entries; 0/2 = one scatter pass sums   */
                         /* the entries per community within chunks and appends them to    */
                         /* per-partition buckets that the partition workgroups read       */
-    int32_t hub_chunk;  /* mode 2: entries per scatter workgroup, 1024, 2048 or 4096      */
+    int32_t hub_chunk;  /* mode 2: entries per scatter workgroup, 1024, 2048 (default) or */
+                        /* 4096, summed in passes of 1024 with one bucket allocation      */
     int32_t order_min;  /* coarse levels with at least this many entries are stored by    */
                         /* descending degree, like level 0 (0 = 2^22)                      */
     int32_t agg_sort;   /* aggregation: 1 = always sort and reduce the keys               */

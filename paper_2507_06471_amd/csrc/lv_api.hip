@@ -352,7 +352,7 @@ Tune make_tune(const lv_tuning* t)
     u.bucketed = 1;
     u.order_min = (int64_t)1 << 22;
     u.fb_chunk = 4096;
-    u.sc_chunk = 1024;
+    u.sc_chunk = 2048;
     u.agg_sort = 0;
     u.cache_read_pct = 10;
     u.fused = 0;
@@ -1434,7 +1434,7 @@ lv_status autotune(lv_graph* g, const Params& base, lv_tuning* best, double* bes
         {&lv_tuning::block_max, {3072, 2048}},
         {&lv_tuning::hub_mode, {1}},
         {&lv_tuning::part_keys, {512, 1024}},
-        {&lv_tuning::hub_chunk, {2048, 4096}},
+        {&lv_tuning::hub_chunk, {1024, 4096}},
         {&lv_tuning::part_slots, {1024}},
         {&lv_tuning::table_pct, {150, 200, 400}},
         {&lv_tuning::fused, {1}},

@@ -883,16 +883,19 @@ __global__ __launch_bounds__(256) void k_hub_finalize(MoveArgs a, HubArgs h)
 }
 
 // Scatter the entries of hubs with P > 1 into their partitions' buckets.  A
-// workgroup takes a chunk of a row and sums its entries per community in a
-// packed LDS table (so a community shared by many neighbours costs one bucket
-// entry per chunk); the thread that claimed a community's slot appends
-// (community, volume, weight sum) to the bucket of the community's partition.
+// workgroup takes a chunk of a row in NCH passes of SBS * EPT entries; each
+// pass sums its entries per community in a packed LDS table (so a community
+// shared by many neighbours costs one bucket entry per pass) and the thread
+// that claimed a community's slot keeps (community, volume, weight sum) in
+// registers.  After the last pass the workgroup takes its room in each
+// partition's bucket with one atomic per partition and writes its records.
 // Positions inside a bucket depend on timing; the sums a partition workgroup
 // forms from them do not.
-template <int SBS, int EPT>
+template <int SBS, int EPT, int NCH>
 __global__ __launch_bounds__(SBS) void k_hub_scatter(MoveArgs a, HubArgs h)
 {
-    constexpr int SC_SLOTS = 2 * SBS * EPT;  // at most SBS * EPT keys: always room
+    constexpr int SC_SLOTS = 2 * SBS * EPT;  // at most SBS * EPT keys a pass: always room
+    constexpr int R = EPT * NCH;              // records a thread may hold
     __shared__ unsigned long long t_tab[SC_SLOTS];
     __shared__ int32_t s_cnt[HUB_PMAX];  // per-partition counts, then bucket bases
     if (a.ctl->all_done) return;
@@ -901,54 +904,62 @@ __global__ __launch_bounds__(SBS) void k_hub_scatter(MoveArgs a, HubArgs h)
     const int32_t i = h.hub_vert[hh];
     if (vertex_frozen(a, i) || vertex_skipped(a, i)) return;
     const uint32_t P = (uint32_t)h.hub_parts[hh];
-    const int32_t e0 = h.sc_beg[b], e1 = h.sc_end[b];
-    for (uint32_t t = threadIdx.x; t < (uint32_t)SC_SLOTS; t += SBS) t_tab[t] = EMPTY_SLOT;
+    const int32_t c0 = h.sc_beg[b], c1 = h.sc_end[b];
     for (uint32_t t = threadIdx.x; t < P; t += SBS) s_cnt[t] = 0;
     const int ecm = entry_mode(a);
-    int32_t ww[EPT], slot[EPT], rk[EPT];
-    uint32_t pp[EPT];
-    int2 cc[EPT];
-    if (ecm == EC_READ) {
+    int32_t ww[R], rk[R];
+    uint32_t pp[R];
+    int2 cc[R];
 #pragma unroll
-        for (int u = 0; u < EPT; ++u) {
-            const int32_t e = e0 + u * SBS + (int32_t)threadIdx.x;
-            const bool ok = e < e1;
-            cc[u] = ok ? ce_load(a.ce, e) : make_int2(EMPTY_KEY, 0);
-            ww[u] = (ok && a.w) ? __builtin_nontemporal_load(&a.w[e]) : 1;
-        }
-    } else {
-        int32_t jj[EPT];
-#pragma unroll
-        for (int u = 0; u < EPT; ++u) {
-            const int32_t e = e0 + u * SBS + (int32_t)threadIdx.x;
-            const bool ok = e < e1;
-            jj[u] = ok ? __builtin_nontemporal_load(&a.idx[e]) : i;
-            ww[u] = (ok && a.w) ? __builtin_nontemporal_load(&a.w[e]) : 1;
-        }
-#pragma unroll
-        for (int u = 0; u < EPT; ++u) cc[u] = jj[u] != i ? pair_now(a, jj[u]) : make_int2(EMPTY_KEY, 0);
-        if (ecm == EC_FILL) {
+    for (int q = 0; q < NCH; ++q) {
+        const int32_t e0 = c0 + q * SBS * EPT, e1 = c1;
+        for (uint32_t t = threadIdx.x; t < (uint32_t)SC_SLOTS; t += SBS) t_tab[t] = EMPTY_SLOT;
+        int32_t slot[EPT];
+        if (ecm == EC_READ) {
 #pragma unroll
             for (int u = 0; u < EPT; ++u) {
                 const int32_t e = e0 + u * SBS + (int32_t)threadIdx.x;
-                if (e < e1) ce_store(a.ce, e, cc[u]);
+                const bool ok = e < e1;
+                cc[q * EPT + u] = ok ? ce_load(a.ce, e) : make_int2(EMPTY_KEY, 0);
+                ww[q * EPT + u] = (ok && a.w) ? __builtin_nontemporal_load(&a.w[e]) : 1;
+            }
+        } else {
+            int32_t jj[EPT];
+#pragma unroll
+            for (int u = 0; u < EPT; ++u) {
+                const int32_t e = e0 + u * SBS + (int32_t)threadIdx.x;
+                const bool ok = e < e1;
+                jj[u] = ok ? __builtin_nontemporal_load(&a.idx[e]) : i;
+                ww[q * EPT + u] = (ok && a.w) ? __builtin_nontemporal_load(&a.w[e]) : 1;
+            }
+#pragma unroll
+            for (int u = 0; u < EPT; ++u) cc[q * EPT + u] = jj[u] != i ? pair_now(a, jj[u]) : make_int2(EMPTY_KEY, 0);
+            if (ecm == EC_FILL) {
+#pragma unroll
+                for (int u = 0; u < EPT; ++u) {
+                    const int32_t e = e0 + u * SBS + (int32_t)threadIdx.x;
+                    if (e < e1) ce_store(a.ce, e, cc[q * EPT + u]);
+                }
             }
         }
-    }
-    __syncthreads();
+        __syncthreads();
 #pragma unroll
-    for (int u = 0; u < EPT; ++u)
-        slot[u] = cc[u].x == EMPTY_KEY ? -1 : claim_or_add<false>(t_tab, SC_SLOTS - 1, cc[u].x, ww[u]);
-    __syncthreads();
+        for (int u = 0; u < EPT; ++u)
+            slot[u] = cc[q * EPT + u].x == EMPTY_KEY ? -1
+                                                     : claim_or_add<false>(t_tab, SC_SLOTS - 1, cc[q * EPT + u].x,
+                                                                           ww[q * EPT + u]);
+        __syncthreads();
 #pragma unroll
-    for (int u = 0; u < EPT; ++u) {
-        rk[u] = -1;
-        if (slot[u] < 0) continue;
-        ww[u] = (int32_t)(uint32_t)t_tab[slot[u]];  // the community's weight sum in this chunk
-        pp[u] = part_of(cc[u].x, P);
-        rk[u] = atomicAdd(&s_cnt[pp[u]], 1);
+        for (int u = 0; u < EPT; ++u) {
+            const int r = q * EPT + u;
+            rk[r] = -1;
+            if (slot[u] < 0) continue;
+            ww[r] = (int32_t)(uint32_t)t_tab[slot[u]];  // the community's weight sum in this pass
+            pp[r] = part_of(cc[r].x, P);
+            rk[r] = atomicAdd(&s_cnt[pp[r]], 1);
+        }
+        __syncthreads();  // the table is cleared by the next pass
     }
-    __syncthreads();
     int32_t* cnt = h.bucket_cnt + h.hub_first_blk[hh];
     for (uint32_t t = threadIdx.x; t < P; t += SBS) {
         const int32_t c = s_cnt[t];
@@ -958,13 +969,13 @@ __global__ __launch_bounds__(SBS) void k_hub_scatter(MoveArgs a, HubArgs h)
     const size_t cap = (size_t)h.bucket_cap;
     const size_t first = (size_t)h.hub_first_blk[hh];
 #pragma unroll
-    for (int u = 0; u < EPT; ++u) {
-        if (rk[u] < 0) continue;
-        const int32_t pos = s_cnt[pp[u]] + rk[u];
+    for (int r = 0; r < R; ++r) {
+        if (rk[r] < 0) continue;
+        const int32_t pos = s_cnt[pp[r]] + rk[r];
         if (pos >= h.bucket_cap) continue;  // the partition's workgroup flags the overflow
-        const size_t at = (first + pp[u]) * cap + (size_t)pos;
-        h.bucket[at] = cc[u];
-        h.bucket_w[at] = ww[u];
+        const size_t at = (first + pp[r]) * cap + (size_t)pos;
+        h.bucket[at] = cc[r];
+        h.bucket_w[at] = ww[r];
     }
 }
 
@@ -1512,9 +1523,9 @@ hipError_t launch_hub_clear(int32_t* table, int64_t slots, hipStream_t s)
 hipError_t launch_hub_scatter(const MoveArgs& a, const HubArgs& h, hipStream_t s)
 {
     if (h.nhubs <= 0 || !h.bucketed || h.nsc <= 0) return hipSuccess;
-    if (h.sc_chunk == 1024) k_hub_scatter<256, 4><<<(unsigned)h.nsc, 256, 0, s>>>(a, h);
-    else if (h.sc_chunk == 2048) k_hub_scatter<256, 8><<<(unsigned)h.nsc, 256, 0, s>>>(a, h);
-    else k_hub_scatter<512, 8><<<(unsigned)h.nsc, 512, 0, s>>>(a, h);
+    if (h.sc_chunk == 1024) k_hub_scatter<256, 4, 1><<<(unsigned)h.nsc, 256, 0, s>>>(a, h);
+    else if (h.sc_chunk == 2048) k_hub_scatter<256, 4, 2><<<(unsigned)h.nsc, 256, 0, s>>>(a, h);
+    else k_hub_scatter<256, 4, 4><<<(unsigned)h.nsc, 256, 0, s>>>(a, h);
     return hipGetLastError();
 }
 
