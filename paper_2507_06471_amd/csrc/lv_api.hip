@@ -131,6 +131,7 @@ struct Workspace {
     DevBuf rows;  // per-level row descriptors of the class-sorted vertices
     DevBuf ce;    // entry cache: per CSR entry of the handle's input graph, its neighbour's pair
     DevBuf chg;   // per listed vertex: its pair changed in the last commit (uint8)
+    DevBuf rlist, rcnt;  // per 256-slot tile: its changed rows below the hub class (int4) and their number
     DevBuf mark;  // active-vertex pruning: last sweep that changed the vertex's neighbourhood
     DevBuf tiles; // aggregation: per key tile its count, first entry and output position
     DevBuf p_off, p_idx, p_w, p_k, p_orig, p_inv;  // a coarse level stored by degree
@@ -715,6 +716,9 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
     if (use_ec) {
         HIP_TRY(ws.ce.ensure(sizeof(int2) * (size_t)G.nnz));
         HIP_TRY(ws.chg.ensure((size_t)std::max(active, 1)));
+        const size_t tiles = ((size_t)active + 255) / 256;
+        HIP_TRY(ws.rlist.ensure(sizeof(int4) * 256 * tiles));
+        HIP_TRY(ws.rcnt.ensure(sizeof(int32_t) * tiles));
     }
     const int64_t ec_read_max = use_ec ? G.nnz * p.tune.cache_read_pct / 100 : -1;
     const int64_t ec_fill_max = use_ec ? G.nnz * p.tune.cache_fill_pct / 100 : -1;
@@ -736,24 +740,6 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
             items += (cnt + rows_per_item[c] - 1) / rows_per_item[c];
         }
         fmap.item_first[fmap.nclass] = items;
-    }
-    // the refresh's blocks per class: lanes per row as in the move kernels, at most 256
-    RefreshMap rmap{};
-    if (use_ec) {
-        static const int32_t lanes_log2[NUM_CLS] = {0, 2, 3, 4, 5, 6, 7, 8, 8, 8, 8, 8};
-        int32_t blocks = 0;
-        for (int c = CLS_L4; c < CLS_HUB; ++c) {
-            const int32_t cnt = start[c + 1] - start[c];
-            if (cnt <= 0) continue;
-            const int q = rmap.nclass++;
-            rmap.blk_first[q] = blocks;
-            rmap.slot_first[q] = start[c] - start[CLS_L4];
-            rmap.slot_end[q] = start[c + 1] - start[CLS_L4];
-            rmap.lanes_log2[q] = lanes_log2[c];
-            const int32_t per_block = 256 >> lanes_log2[c];
-            blocks += (cnt + per_block - 1) / per_block;
-        }
-        rmap.blk_first[rmap.nclass] = blocks;
     }
     int64_t cls_entries[NUM_CLS] = {};
     if (timing) {
@@ -866,8 +852,9 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
             HIP_TRY(launch_apply(act_verts, dec_all + start[CLS_L4], active, G.k, a.gid, ws.comm.as<int32_t>(),
                                  ws.sigma.as<int32_t>(), ctl, ws.gmoves.as<uint32_t>(), S, s));
             if (use_ec)
-                HIP_TRY(launch_pairs_changed(active, ws.rows.as<int4>(), ws.comm.as<int32_t>(), ws.sigma.as<int32_t>(),
-                                             ws.cs.as<int2>(), ws.chg.as<uint8_t>(), mode, ctl, s));
+                HIP_TRY(launch_pairs_changed(active, nonhub, ws.rows.as<int4>(), ws.comm.as<int32_t>(),
+                                             ws.sigma.as<int32_t>(), ws.cs.as<int2>(), ws.chg.as<uint8_t>(),
+                                             ws.rlist.as<int4>(), ws.rcnt.as<int32_t>(), mode, ctl, s));
             else
                 HIP_TRY(launch_pairs(active, act_verts, ws.comm.as<int32_t>(), ws.sigma.as<int32_t>(),
                                      ws.cs.as<int2>(), ctl, s));
@@ -878,8 +865,8 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
                                  ws.gmoves.as<uint32_t>(), S, theta, async ? 1 : 2, ec_read_max, ec_fill_max, s));
         if (e) HIP_TRY(tm.mark(&(*e)[2 * NUM_CLS + 4]));
         if (use_ec) {  // rewrite the changed entries if the next sweep reads the cache
-            HIP_TRY(launch_cache_refresh(rmap, ws.rows.as<int4>(), ws.chg.as<uint8_t>(), G.rev,
-                                         ws.cs.as<int2>(), ws.ce.as<int2>(), ctl, s));
+            HIP_TRY(launch_cache_refresh(active, ws.rlist.as<int4>(), ws.rcnt.as<int32_t>(), G.rev,
+                                         ws.ce.as<int2>(), ctl, s));
             if (hubs.nhubs > 0) HIP_TRY(launch_hub_cache_refresh(a, hubs.args, ws.chg.as<uint8_t>() + nonhub, G.rev, s));
         }
         if (e) HIP_TRY(tm.mark(&(*e)[2 * NUM_CLS + 2]));

@@ -271,24 +271,18 @@ hipError_t launch_pairs(int32_t n, const int32_t* verts, const int32_t* comm, co
                         const SweepCtl* ctl, hipStream_t s);
 // As launch_pairs over the m listed vertices rows[0..m) (class order), also
 // recording in chg[t] whether slot t's pair changed (LPA: its label) and
-// adding the changed rows' entries to ctl->chg_entries.
-hipError_t launch_pairs_changed(int32_t m, const int4* rows, const int32_t* comm, const int32_t* sigma, int2* cs,
-                                uint8_t* chg, int mode, SweepCtl* ctl, hipStream_t s);
+// adding the changed rows' entries to ctl->chg_entries.  The changed rows of
+// slots below `nonhub` are listed per 256-slot tile: (row begin, length, new
+// pair) at list[tile * 256 + i] for i < cnt[tile].
+hipError_t launch_pairs_changed(int32_t m, int32_t nonhub, const int4* rows, const int32_t* comm, const int32_t* sigma,
+                                int2* cs, uint8_t* chg, int4* list, int32_t* cnt, int mode, SweepCtl* ctl,
+                                hipStream_t s);
 // Entry-cache refresh when the next sweep reads the cache: for every listed
-// vertex v with chg set, ce[rev[e]] = cs[v] for each non-loop entry e of v's
-// row (rows below the hub class, by class; hubs through their 4096-entry
-// chunks).  RefreshMap: per class below the hub class that has rows, in
-// order: its first 256-thread block (blk_first[nclass] = blocks in all), its
-// listed slots [slot_first, slot_end) and log2 of the lanes per row.
-struct RefreshMap {
-    int32_t nclass;
-    int32_t blk_first[NUM_CLS + 1];
-    int32_t slot_first[NUM_CLS];
-    int32_t slot_end[NUM_CLS];
-    int32_t lanes_log2[NUM_CLS];
-};
-hipError_t launch_cache_refresh(const RefreshMap& mp, const int4* rows, const uint8_t* chg, const int32_t* rev,
-                                const int2* cs, int2* ce, SweepCtl* ctl, hipStream_t s);
+// changed row (list/cnt of launch_pairs_changed over m slots), ce[rev[e]] =
+// its new pair for each non-loop entry e of the row.  Hubs: through their
+// 4096-entry chunks (launch_hub_cache_refresh, from chg).
+hipError_t launch_cache_refresh(int32_t m, const int4* list, const int32_t* cnt, const int32_t* rev, int2* ce,
+                                SweepCtl* ctl, hipStream_t s);
 hipError_t launch_hub_cache_refresh(const MoveArgs& a, const HubArgs& h, const uint8_t* chg_hub, const int32_t* rev,
                                     hipStream_t s);
 // Reverse-entry map of a CSR whose rows are sorted: rank[e] = position of

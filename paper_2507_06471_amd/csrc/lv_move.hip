@@ -1299,27 +1299,49 @@ __global__ void k_pairs(int32_t n, const int32_t* verts, const int32_t* comm, co
 
 // As k_pairs over the listed vertices (class order), recording whether each
 // slot's pair changed (LPA, whose scores ignore volumes: its label) and the
-// entries of the changed rows.
-__global__ __launch_bounds__(256) void k_pairs_changed(int32_t m, const int4* rows, const int32_t* comm,
-                                                       const int32_t* sigma, int2* cs, uint8_t* chg, int mode,
+// entries of the changed rows.  Each 256-slot tile also lists its changed
+// rows below the hub class, (row begin, length, new pair), at the tile's
+// own place in `list`, with their number in cnt[tile]: the refresh reads
+// only those.
+__global__ __launch_bounds__(256) void k_pairs_changed(int32_t m, int32_t nonhub, const int4* rows,
+                                                       const int32_t* comm, const int32_t* sigma, int2* cs,
+                                                       uint8_t* chg, int4* list, int32_t* cnt, int mode,
                                                        SweepCtl* ctl)
 {
     __shared__ unsigned long long red[4];
+    __shared__ int32_t w_cnt[4];
     if (ctl->all_done) return;
-    unsigned long long cnt = 0;
-    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < m; t += (int64_t)gridDim.x * 256) {
-        const int4 r = rows[t];
-        const int32_t c = comm[r.x];
-        const int2 nw = make_int2(c, sigma[c]);
-        const int2 old = cs[r.x];
-        const bool lab = nw.x != old.x, pair = lab || nw.y != old.y;
-        if (pair) cs[r.x] = nw;
-        const bool ch = mode == MODE_LOUVAIN ? pair : lab;
-        if (ch) cnt += (unsigned long long)(r.z - r.y);
-        chg[t] = ch ? 1 : 0;
+    unsigned long long tot = 0;
+    for (int64_t base = (int64_t)blockIdx.x * 256; base < m; base += (int64_t)gridDim.x * 256) {
+        const int64_t t = base + threadIdx.x;
+        bool ch = false;
+        int4 rec = make_int4(0, 0, 0, 0);
+        if (t < m) {
+            const int4 r = rows[t];
+            const int32_t c = comm[r.x];
+            const int2 nw = make_int2(c, sigma[c]);
+            const int2 old = cs[r.x];
+            const bool lab = nw.x != old.x, pair = lab || nw.y != old.y;
+            if (pair) cs[r.x] = nw;
+            ch = mode == MODE_LOUVAIN ? pair : lab;
+            if (ch) tot += (unsigned long long)(r.z - r.y);
+            chg[t] = ch ? 1 : 0;
+            rec = make_int4(r.y, r.z - r.y, nw.x, nw.y);
+        }
+        const bool listed = ch && t < nonhub;
+        const uint64_t bal = __ballot(listed);
+        const int wid = (int)(threadIdx.x / WAVE);
+        if (lane_id() == 0) w_cnt[wid] = __popcll(bal);
+        __syncthreads();
+        int32_t at = 0;
+        for (int w = 0; w < wid; ++w) at += w_cnt[w];
+        const int64_t tile = base / 256;
+        if (listed) list[base + at + (int32_t)lane_rank(bal)] = rec;
+        if (threadIdx.x == 0) cnt[tile] = w_cnt[0] + w_cnt[1] + w_cnt[2] + w_cnt[3];
+        __syncthreads();  // w_cnt is reused by the next tile
     }
-    cnt = block_sum<256>(cnt, red);
-    if (threadIdx.x == 0 && cnt) atomicAdd(&ctl->chg_entries, cnt);
+    tot = block_sum<256>(tot, red);
+    if (threadIdx.x == 0 && tot) atomicAdd(&ctl->chg_entries, tot);
 }
 
 constexpr int32_t REFRESH_GRID = 8192;  // four rounds of resident 256-thread workgroups
@@ -1327,31 +1349,54 @@ constexpr int32_t REFRESH_GRID = 8192;  // four rounds of resident 256-thread wo
 // Entry-cache refresh (only when the next sweep reads the cache): for every
 // listed vertex v whose pair changed, rewrite the cache entry of each of its
 // neighbours u that refers to v (the reverse of v's entry for u; a loop is
-// its own reverse and keeps its empty entry).  Like the move kernels, rows of
-// one degree class get a group of lanes each (at most a 256-thread
-// workgroup), so that the work of a block does not depend on how long the
-// changed rows around it are; a capped grid walks the blocks, so that the
-// launch costs little in the sweeps that do not refresh.
-__global__ __launch_bounds__(256) void k_cache_refresh(RefreshMap mp, const int4* __restrict__ rows,
-                                                       const uint8_t* __restrict__ chg,
-                                                       const int32_t* __restrict__ rev, const int2* __restrict__ cs,
-                                                       int2* __restrict__ ce, const SweepCtl* ctl)
+// its own reverse and keeps its empty entry).  A workgroup takes a tile's
+// list of changed rows (k_pairs_changed), sums their lengths and spreads
+// their entries over its lanes, so that no lane waits on an unchanged row.
+__global__ __launch_bounds__(256) void k_cache_refresh(int32_t tiles, const int4* __restrict__ list,
+                                                       const int32_t* __restrict__ cnt,
+                                                       const int32_t* __restrict__ rev, int2* __restrict__ ce,
+                                                       const SweepCtl* ctl)
 {
+    __shared__ int32_t s_off[257];
+    __shared__ int4 s_row[256];
+    __shared__ int32_t w_sum[4];
     if (ctl->all_done || ctl->ec_mode != EC_READ) return;
-    for (int32_t b = (int32_t)blockIdx.x; b < mp.blk_first[mp.nclass]; b += (int32_t)gridDim.x) {
-        int c = 0;
-        while (c + 1 < mp.nclass && mp.blk_first[c + 1] <= b) ++c;
-        const int lg = mp.lanes_log2[c];
-        const int32_t G = 1 << lg, NG = 256 >> lg;
-        const int32_t g = (int32_t)threadIdx.x >> lg, lane = (int32_t)threadIdx.x & (G - 1);
-        const int64_t t = (int64_t)mp.slot_first[c] + (int64_t)(b - mp.blk_first[c]) * NG + g;
-        if (t >= mp.slot_end[c] || !chg[t]) continue;
-        const int4 r = rows[t];
-        const int2 p = cs[r.x];
-        for (int32_t e = r.y + lane; e < r.z; e += G) {
-            const int32_t re = __builtin_nontemporal_load(&rev[e]);
-            if (re != e) ce[re] = p;
+    for (int32_t tile = (int32_t)blockIdx.x; tile < tiles; tile += (int32_t)gridDim.x) {
+        const int32_t c = cnt[tile];
+        if (c == 0) continue;  // the same for every thread of the workgroup
+        int32_t len = 0;
+        if ((int32_t)threadIdx.x < c) {
+            const int4 r = list[(int64_t)tile * 256 + threadIdx.x];
+            s_row[threadIdx.x] = r;
+            len = r.y;
         }
+        // inclusive scan of the lengths: within each wavefront, then across the four
+        int32_t x = len;
+#pragma unroll
+        for (int d = 1; d < WAVE; d <<= 1) {
+            const int32_t y = __shfl_up(x, d);
+            if ((int)lane_id() >= d) x += y;
+        }
+        const int wid = (int)(threadIdx.x / WAVE);
+        if (lane_id() == WAVE - 1) w_sum[wid] = x;
+        __syncthreads();
+        for (int w = 0; w < wid; ++w) x += w_sum[w];
+        s_off[threadIdx.x + 1] = x;
+        if (threadIdx.x == 0) s_off[0] = 0;
+        __syncthreads();
+        const int32_t total = s_off[c];
+        for (int32_t f = (int32_t)threadIdx.x; f < total; f += 256) {
+            int32_t lo = 0, hi = c - 1;  // the row q with s_off[q] <= f < s_off[q + 1]
+            while (lo < hi) {
+                const int32_t mid = (lo + hi + 1) >> 1;
+                if (s_off[mid] <= f) lo = mid; else hi = mid - 1;
+            }
+            const int4 r = s_row[lo];
+            const int32_t e = r.x + (f - s_off[lo]);
+            const int32_t re = __builtin_nontemporal_load(&rev[e]);
+            if (re != e) ce[re] = make_int2(r.z, r.w);
+        }
+        __syncthreads();  // s_row and s_off are reused by the next tile
     }
 }
 
@@ -1372,19 +1417,21 @@ __global__ __launch_bounds__(256) void k_hub_cache_refresh(MoveArgs a, HubArgs h
 
 }  // namespace
 
-hipError_t launch_pairs_changed(int32_t m, const int4* rows, const int32_t* comm, const int32_t* sigma, int2* cs,
-                                uint8_t* chg, int mode, SweepCtl* ctl, hipStream_t s)
+hipError_t launch_pairs_changed(int32_t m, int32_t nonhub, const int4* rows, const int32_t* comm, const int32_t* sigma,
+                                int2* cs, uint8_t* chg, int4* list, int32_t* cnt, int mode, SweepCtl* ctl,
+                                hipStream_t s)
 {
     if (m <= 0) return hipSuccess;
-    k_pairs_changed<<<grid_for(m, 256, 8192), 256, 0, s>>>(m, rows, comm, sigma, cs, chg, mode, ctl);
+    k_pairs_changed<<<grid_for(m, 256, 8192), 256, 0, s>>>(m, nonhub, rows, comm, sigma, cs, chg, list, cnt, mode,
+                                                           ctl);
     return hipGetLastError();
 }
-hipError_t launch_cache_refresh(const RefreshMap& mp, const int4* rows, const uint8_t* chg, const int32_t* rev,
-                                const int2* cs, int2* ce, SweepCtl* ctl, hipStream_t s)
+hipError_t launch_cache_refresh(int32_t m, const int4* list, const int32_t* cnt, const int32_t* rev, int2* ce,
+                                SweepCtl* ctl, hipStream_t s)
 {
-    if (mp.nclass <= 0 || mp.blk_first[mp.nclass] <= 0) return hipSuccess;
-    const unsigned grid = (unsigned)std::min<int32_t>(mp.blk_first[mp.nclass], REFRESH_GRID);
-    k_cache_refresh<<<grid, 256, 0, s>>>(mp, rows, chg, rev, cs, ce, ctl);
+    const int32_t tiles = (int32_t)(((int64_t)m + 255) / 256);
+    if (tiles <= 0) return hipSuccess;
+    k_cache_refresh<<<(unsigned)std::min(tiles, REFRESH_GRID), 256, 0, s>>>(tiles, list, cnt, rev, ce, ctl);
     return hipGetLastError();
 }
 hipError_t launch_hub_cache_refresh(const MoveArgs& a, const HubArgs& h, const uint8_t* chg_hub, const int32_t* rev,
