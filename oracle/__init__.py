@@ -9,8 +9,8 @@ vertex loop of a sweep); this module marshals arguments and runs the level
 driver of the paper's Algorithm 3 in plain Python:
 
     repeat: local moving (Alg. 2) -> renumber -> aggregate (Alg. 3, Aggregation)
-    until the level does not improve modularity (Section III-B: "until no
-    further improvement in modularity") or max_levels levels were accepted.
+    until a level leaves modularity where it was (the end condition of
+    Section III-B) or max_levels levels were accepted.
 
 Readings of the paper that fix deterministic semantics are stated in
 ``lv_oracle.c``'s header.
