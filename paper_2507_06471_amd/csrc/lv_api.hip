@@ -627,6 +627,8 @@ lv_status plan_hubs(lv_graph* g, const LevelGraph& G, const int32_t* hub_verts, 
     a.mk_end = p32 + o_me;
     a.nmk = (int32_t)mk_hub.size();
     a.sc_chunk = tu.sc_chunk;
+    a.max_parts = 0;
+    for (int32_t h = 0; h < nhubs; ++h) a.max_parts = std::max(a.max_parts, parts[h]);
     a.bucket_cap = tu.part_slots;
     if (tu.bucketed && nsc > 0) {
         const size_t nb = (size_t)nblk * (size_t)tu.part_slots;

@@ -137,6 +137,7 @@ struct HubArgs {
     int2* bucket;                  // [nblk * bucket_cap]
     int32_t* bucket_w;             // [nblk * bucket_cap] weight sums
     int32_t sc_chunk;              // entries per scatter workgroup: 1024, 2048 or 4096
+    int32_t max_parts;             // the largest P among the hubs the scatter pass takes
     const int32_t* sc_hub;         // scatter workgroup b: entries [sc_beg, sc_end) of hub sc_hub
     const int32_t* sc_beg;
     const int32_t* sc_end;
@@ -165,6 +166,7 @@ struct HubArgs {
 
 // partitions per hub in bucketed mode are limited by the scatter kernel's LDS histogram
 constexpr int32_t HUB_PMAX = 4096;
+constexpr int32_t HUB_PSMALL = 1024;  // the scatter pass's per-partition counts fit a smaller LDS array up to here
 
 
 // ---- launchers (lv_kernels.hip) ----

@@ -891,13 +891,13 @@ __global__ __launch_bounds__(256) void k_hub_finalize(MoveArgs a, HubArgs h)
 // partition's bucket with one atomic per partition and writes its records.
 // Positions inside a bucket depend on timing; the sums a partition workgroup
 // forms from them do not.
-template <int SBS, int EPT, int NCH>
+template <int SBS, int EPT, int NCH, int PMAX>
 __global__ __launch_bounds__(SBS) void k_hub_scatter(MoveArgs a, HubArgs h)
 {
     constexpr int SC_SLOTS = 2 * SBS * EPT;  // at most SBS * EPT keys a pass: always room
     constexpr int R = EPT * NCH;              // records a thread may hold
     __shared__ unsigned long long t_tab[SC_SLOTS];
-    __shared__ int32_t s_cnt[HUB_PMAX];  // per-partition counts, then bucket bases
+    __shared__ int32_t s_cnt[PMAX];  // per-partition counts, then bucket bases (P <= PMAX)
     if (a.ctl->all_done) return;
     const int b = blockIdx.x;
     const int32_t hh = h.sc_hub[b];
@@ -1570,9 +1570,19 @@ hipError_t launch_hub_clear(int32_t* table, int64_t slots, hipStream_t s)
 hipError_t launch_hub_scatter(const MoveArgs& a, const HubArgs& h, hipStream_t s)
 {
     if (h.nhubs <= 0 || !h.bucketed || h.nsc <= 0) return hipSuccess;
-    if (h.sc_chunk == 1024) k_hub_scatter<256, 4, 1><<<(unsigned)h.nsc, 256, 0, s>>>(a, h);
-    else if (h.sc_chunk == 2048) k_hub_scatter<256, 4, 2><<<(unsigned)h.nsc, 256, 0, s>>>(a, h);
-    else k_hub_scatter<256, 4, 4><<<(unsigned)h.nsc, 256, 0, s>>>(a, h);
+    // hubs of at most HUB_PSMALL partitions: a 4 KiB count array, so that
+    // eight workgroups fit a CU's LDS instead of five
+    const bool small = h.max_parts <= HUB_PSMALL;
+    if (h.sc_chunk == 1024) {
+        if (small) k_hub_scatter<256, 4, 1, HUB_PSMALL><<<(unsigned)h.nsc, 256, 0, s>>>(a, h);
+        else k_hub_scatter<256, 4, 1, HUB_PMAX><<<(unsigned)h.nsc, 256, 0, s>>>(a, h);
+    } else if (h.sc_chunk == 2048) {
+        if (small) k_hub_scatter<256, 4, 2, HUB_PSMALL><<<(unsigned)h.nsc, 256, 0, s>>>(a, h);
+        else k_hub_scatter<256, 4, 2, HUB_PMAX><<<(unsigned)h.nsc, 256, 0, s>>>(a, h);
+    } else {
+        if (small) k_hub_scatter<256, 4, 4, HUB_PSMALL><<<(unsigned)h.nsc, 256, 0, s>>>(a, h);
+        else k_hub_scatter<256, 4, 4, HUB_PMAX><<<(unsigned)h.nsc, 256, 0, s>>>(a, h);
+    }
     return hipGetLastError();
 }
 

@@ -128,6 +128,28 @@ def test_weighted_bucketed_partitions(tuning):
     compare_lpa(g, tuning=tuning)
 
 
+def hub_star_graph(leaves=40000, seed=61):
+    # vertex 0 joins every leaf; leaves form a ring with random chords, so
+    # communities form along it while the hub row stays 40,000 entries long
+    rng = np.random.default_rng(seed)
+    ring = np.arange(1, leaves + 1)
+    u = np.concatenate([np.zeros(leaves, dtype=np.int64), ring, rng.integers(1, leaves + 1, size=leaves // 2)])
+    v = np.concatenate([ring, np.roll(ring, -1), rng.integers(1, leaves + 1, size=leaves // 2)])
+    keep = u != v
+    return graphgen.from_edges(leaves + 1, u[keep], v[keep], keep_loops=False)
+
+
+@pytest.mark.parametrize("hub_chunk", [1024, 2048, 4096])
+def test_hub_with_more_partitions_than_the_small_count_array(hub_chunk):
+    # part_keys 32 splits the 40,000-entry hub row into 1,250 partitions, more
+    # than the scatter pass's small per-partition count array takes
+    g = hub_star_graph()
+    g = graphgen.CSR(g.n, g.offsets, g.indices, None, "hub star")
+    tuning = {"block_max": 64, "hub_mode": 2, "part_keys": 32, "part_slots": 2048, "hub_chunk": hub_chunk}
+    compare_louvain(g, tuning=tuning)
+    compare_lpa(g, tuning=tuning)
+
+
 def test_device_resident_input():
     pytest.importorskip("torch")
     compare_louvain(graphgen.rmat(12, seed=8), device=True)
