@@ -54,6 +54,7 @@ sys.path.insert(0, ROOT)
 METRIC = "local-move GTEPS + %HBM roofline at exact partitions; batched p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
 GOLDEN = os.path.join(ROOT, "tests", "golden", "rmat24_seed2_digests.json")
+GOLDEN_LFR = os.path.join(ROOT, "tests", "golden", "lfr10m_seed3_digests.json")
 # the paper's own local-moving times (context, not the target): Section V-B,
 # strong scaling on com-livejournal (3,997,962 vertices, 34,681,189 edges)
 PAPER_CONTEXT = {
@@ -463,15 +464,13 @@ def serving_leg(args, lvp, graphgen, np, torch):
     return out
 
 
-def golden_check(args, r, lp, g):
-    """Every level of a timed run against the oracle's per-level digests of
-    the benchmark graph (written by tests/golden/make_rmat24_digests.py from
-    the oracle alone).  Exits on a mismatch; None for other graphs."""
+def digest_check(r, lp, g, path, name):
+    """Every level of a timed run (Louvain result r, LPA result lp, graph g)
+    against the oracle's per-level digests in `path` (written by the scripts
+    in tests/golden/ from the oracle alone).  Exits on a mismatch."""
     import json
 
-    if (args.scale, args.edge_factor, args.seed) != (24, 16.0, 2) or not os.path.exists(GOLDEN):
-        return None
-    with open(GOLDEN) as fh:
+    with open(path) as fh:
         gold = json.load(fh)
     want = gold["louvain"]
     bad = []
@@ -488,16 +487,25 @@ def golden_check(args, r, lp, g):
             bad.append(f"level {lvl} moves")
     if (r.M, r.q_int) != (want["M"], want["q_int"]) or sha256_i32(r.final_labels) != want["final_labels_sha256"]:
         bad.append("final labels or Q_int")
-    if lp.moves != gold["lpa"]["moves"] or sha256_i32(lp.labels) != gold["lpa"]["labels_sha256"]:
+    if lp.moves != gold["lpa"]["moves"] or sha256_i32(lp.labels) != gold["lpa"]["labels_sha256"] or \
+            lp.info["q_end"] != gold["lpa"]["q_int"]:
         bad.append("LPA")
-    out = {"equal": not bad, "levels": len(want["levels"]), "file": "tests/golden/rmat24_seed2_digests.json",
+    out = {"equal": not bad, "levels": len(want["levels"]), "file": os.path.relpath(path, ROOT),
            "checked": "per level n, nnz, n_next, Q_start, Q_end, acceptance, per-sweep moves; final labels "
-                      "(SHA-256), Q_int, M; LPA moves and labels (SHA-256)"}
-    log(f"golden digests: {out}")
+                      "(SHA-256), Q_int, M; LPA moves, labels (SHA-256) and Q_int"}
+    log(f"golden digests ({name}): {out}")
     if bad:
-        print(f"timed run differs from the oracle's digests: {bad}", file=sys.stderr, flush=True)
+        print(f"{name}: timed run differs from the oracle's digests: {bad}", file=sys.stderr, flush=True)
         sys.exit(1)
     return out
+
+
+def golden_check(args, r, lp, g):
+    """The benchmark graph's timed run against its digests
+    (tests/golden/make_rmat24_digests.py); None for other graphs."""
+    if (args.scale, args.edge_factor, args.seed) != (24, 16.0, 2) or not os.path.exists(GOLDEN):
+        return None
+    return digest_check(r, lp, g, GOLDEN, "R-MAT 24")
 
 
 def cpu_baseline(args, oracle, adj, g, graphgen, np):
@@ -560,7 +568,7 @@ def workloads_leg(args, lvp, graphgen, np, torch):
     timing; local-move rate from the levels' sweep events."""
     out = {}
 
-    def run(name, g, lpa, reps):
+    def run(name, g, lpa, reps, golden=None):
         with lvp.Graph.from_csr(g, validate=False) as dg:
             def step():
                 r = lvp.louvain(dg, level_labels=False)
@@ -585,6 +593,8 @@ def workloads_leg(args, lvp, graphgen, np, torch):
             lms = sum(lp.info["sweep_ms"] for _, lp in res) / reps
             d["lpa_ms"] = round(lms, 3)
             d["lpa_sweeps"] = res[0][1].info["sweeps"]
+        if golden and os.path.exists(golden):
+            d["golden"] = digest_check(res[0][0], res[0][1], g, golden, name)
         log(f"workload {name}: {d}")
         return d
 
@@ -592,7 +602,7 @@ def workloads_leg(args, lvp, graphgen, np, torch):
     t = time.time()
     g, _ = graphgen.lfr(args.lfr_n, seed=3)
     log(f"LFR n={g.n} nnz={g.nnz} generated in {time.time() - t:.1f}s")
-    out["lfr"] = run("lfr", g, True, 3)
+    out["lfr"] = run("lfr", g, True, 3, golden=GOLDEN_LFR if args.lfr_n == 10_000_000 else None)
     out["lfr"]["workload"] = (f"LFR-style, n={g.n}, degree exponent 2.5, mean degree 20, max degree 5,000, "
                               "community sizes 50-20,000 (exponent 1.5), mixing 0.3, weights 1..8, seed 3")
     del g

@@ -4,10 +4,11 @@ path), against the oracle: every label and every per-sweep move count.
 
 - R-MAT 24 (520.8 M entries) and LFR with 10 M vertices: level 0's local
   moving (all of its sweeps) and LPA against the oracle run here.
-- R-MAT 24, every level: the complete multi-level Louvain (and LPA) against
-  per-level digests the oracle wrote beforehand (tests/golden/
-  make_rmat24_digests.py; six minutes of CPU): sizes, Q_int, per-sweep move
-  counts, SHA-256 of every level's labels and of every coarse graph.
+- R-MAT 24 and LFR 10 M, every level: the complete multi-level Louvain (and
+  LPA) against per-level digests the oracle wrote beforehand (tests/golden/
+  make_rmat24_digests.py, make_lfr10m_digests.py; minutes of CPU): sizes,
+  Q_int, per-sweep move counts, SHA-256 of every level's labels and of every
+  coarse graph.
 - The 4,096-graph batch (about 1.15e9 entries in one handle): complete
   Louvain on the device, twelve evenly spaced graphs against the oracle run
   on each graph alone.
@@ -64,6 +65,7 @@ def test_rmat24_level0_louvain(rmat24):
 
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "rmat24_seed2_digests.json")
+GOLDEN_LFR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "lfr10m_seed3_digests.json")
 
 
 def sha(*arrays) -> str:
@@ -73,10 +75,8 @@ def sha(*arrays) -> str:
     return h.hexdigest()
 
 
-@pytest.mark.timeout(900)
-def test_rmat24_every_level_against_golden_digests(rmat24):
-    g, _ = rmat24
-    with open(GOLDEN) as fh:
+def check_every_level(g, golden_path):
+    with open(golden_path) as fh:
         gold = json.load(fh)
     assert (g.n, g.nnz) == (gold["n"], gold["nnz"])
     want = gold["louvain"]
@@ -104,6 +104,12 @@ def test_rmat24_every_level_against_golden_digests(rmat24):
     assert lp.info["q_end"] == gold["lpa"]["q_int"]
 
 
+@pytest.mark.timeout(900)
+def test_rmat24_every_level_against_golden_digests(rmat24):
+    g, _ = rmat24
+    check_every_level(g, GOLDEN)
+
+
 @pytest.mark.timeout(600)
 def test_rmat24_lpa(rmat24):
     g, adj = rmat24
@@ -117,12 +123,18 @@ def test_rmat24_lpa(rmat24):
     assert np.array_equal(got.labels, want)
 
 
-@pytest.mark.timeout(600)
-def test_lfr_10m_level0_louvain_and_lpa():
+@pytest.fixture(scope="module")
+def lfr10m():
     # the LFR configuration at full size: 10 M vertices, weights 1..8
     say("generating LFR n=10,000,000 seed 3")
     g, _ = graphgen.lfr(10_000_000, seed=3)
     say(f"generated n={g.n} nnz={g.nnz}")
+    return g
+
+
+@pytest.mark.timeout(600)
+def test_lfr_10m_level0_louvain_and_lpa(lfr10m):
+    g = lfr10m
     adj = oracle.adjacency(g)
     c, moves = oracle.local_move(adj, oracle.LOUVAIN, max_sweeps=SWEEPS)
     want, n2 = oracle.renumber(c)
@@ -139,6 +151,11 @@ def test_lfr_10m_level0_louvain_and_lpa():
     assert (lvl.info["q_end"], got.M) == (q_want, m_want)
     assert got_lpa.moves == [int(x) for x in lpa_moves]
     assert np.array_equal(got_lpa.labels, want_lpa)
+
+
+@pytest.mark.timeout(600)
+def test_lfr_10m_every_level_against_golden_digests(lfr10m):
+    check_every_level(lfr10m, GOLDEN_LFR)
 
 
 @pytest.mark.timeout(600)
