@@ -611,13 +611,13 @@ def workloads_leg(args, lvp, graphgen, np, torch):
 
 def profile_summary(paths, out_dir, command, run_log=None):
     """Summaries for profiles/ from rocprofv3 databases of
-    `bench.py --steps 1 --warmup 0 ... --copy-probe-mib 1024` (kernel trace,
+    `bench.py --steps 1 --warmup 1 ... --copy-probe-mib 1024` (kernel trace,
     FETCH_SIZE pass, WRITE_SIZE pass, TCC hit/miss pass): per kernel, the
     dispatches of the instrumented step's Louvain (all levels: those between
     the first two of the three marker launches of the copy probe's kernel
     around its Louvain and LPA), averaged; the first launch of that kernel is
-    the 1 GiB calibration copy, the second marks the end of the timed steps
-    (whose GPU idle time is summed).  run_log: the kernel-trace run's output
+    the 1 GiB calibration copy, the next two enclose the timed steps (whose
+    GPU idle time is summed).  run_log: the kernel-trace run's output
     (its JSON line gives the graph's entry count, for the probes'
     calibration on the gather pattern).
     Writes <out_dir>/move_kernels_rmat24_kernel_trace.md,
@@ -677,7 +677,7 @@ def profile_summary(paths, out_dir, command, run_log=None):
     con0 = sqlite3.connect(paths[0])
     allk = con0.execute("select name, start, end from kernels order by start").fetchall()
     mk = [i for i, r in enumerate(allk) if "bitwise_not" in r[0]]
-    step = allk[mk[0] + 1:mk[1]]
+    step = allk[mk[1] + 1:mk[2]]  # between the markers around the timed steps
     idle = busy = span = 0.0
     gaps10 = 0
     if step:
@@ -727,8 +727,8 @@ def profile_summary(paths, out_dir, command, run_log=None):
                  "|---|---:|---:|---:|\n" % sum(r[3] for r in rows_out))
         for kern, nd, a, t, *_ in rows_out[:40]:
             fh.write(f"| `{kern}` | {nd} | {a:.4f} | {t:.3f} |\n")
-        fh.write(f"\nThe timed step before it (captured sweeps, Louvain and LPA): {span:.2f} ms from its first to "
-                 f"its last dispatch, GPU busy {busy:.2f} ms, idle {idle:.2f} ms between dispatches ({gaps10} gaps "
+        fh.write(f"\nThe timed steps before it (captured sweeps, Louvain and LPA): {span:.2f} ms from the first to "
+                 f"the last dispatch, GPU busy {busy:.2f} ms, idle {idle:.2f} ms between dispatches ({gaps10} gaps "
                  f"over 10 us).\n")
         tot = sum(sum(v) for v in dur_lpa.values())
         fh.write("\nLPA of the same step (launched for every sweep up to the limit; after the stopping rule a "
@@ -900,6 +900,7 @@ def main():
         log(f"warmup {w}: {time.time() - t:.2f}s, levels {len(r.accepted)}, Q={r.q:.6f}")
 
     # timed steps: the production path (captured sweeps, concurrent classes)
+    profile_marker()  # before the timed steps (outside the timed region)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     runs = []
