@@ -852,7 +852,8 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
         }
         if (!async) {  // asynchronous sweeps have moved already
             HIP_TRY(launch_apply(act_verts, dec_all + start[CLS_L4], active, G.k, a.gid, ws.comm.as<int32_t>(),
-                                 ws.sigma.as<int32_t>(), ctl, ws.gmoves.as<uint32_t>(), S, s));
+                                 mode == MODE_LPA ? nullptr : ws.sigma.as<int32_t>(), ctl, ws.gmoves.as<uint32_t>(),
+                                 S, s));
             if (use_ec)
                 HIP_TRY(launch_pairs_changed(active, nonhub, ws.rows.as<int4>(), ws.comm.as<int32_t>(),
                                              ws.sigma.as<int32_t>(), ws.cs.as<int2>(), ws.chg.as<uint8_t>(),
@@ -927,6 +928,12 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
             HIP_TRY(hipStreamSynchronize(s));
             out.sweep_ms = elapsed(p0, p1);
         }
+    }
+    // LPA's commits leave the volumes alone (its scores never read them):
+    // those of its final labels, for its modularity, are summed here
+    if (mode == MODE_LPA && !async) {
+        HIP_TRY(launch_fill_i32(ws.sigma.as<int32_t>(), 0, n, s));
+        HIP_TRY(launch_volumes(act_verts, active, G.k, ws.comm.as<int32_t>(), ws.sigma.as<int32_t>(), s));
     }
     // per-graph sweep and move counts (one host round trip per level)
     uint32_t* h_moves = (uint32_t*)g->pinned;

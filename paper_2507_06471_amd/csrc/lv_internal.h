@@ -295,10 +295,14 @@ hipError_t launch_reverse_rank(int32_t n, const int32_t* off, const int32_t* idx
 // rev[e] = off[idx[e]] + rank[e] (rows kept in place)
 hipError_t launch_reverse_from_rank(int32_t n, const int32_t* off, const int32_t* idx, int64_t nnz,
                                     const int32_t* rank, int32_t* rev, hipStream_t s);
-// commit the decisions dec[0..m) of vertices verts[0..m); per-graph movers into gmoves
+// commit the decisions dec[0..m) of vertices verts[0..m); per-graph movers into
+// gmoves; sigma null: labels only (LPA)
 hipError_t launch_apply(const int32_t* verts, const int32_t* dec, int32_t m, const int32_t* k, const int32_t* gid,
                         int32_t* comm, int32_t* sigma, const SweepCtl* ctl, uint32_t* gmoves, int32_t max_sweeps,
                         hipStream_t s);
+// sigma[comm[v]] += k[v] for the vertices verts[0..m) (the caller clears sigma)
+hipError_t launch_volumes(const int32_t* verts, int32_t m, const int32_t* k, const int32_t* comm, int32_t* sigma,
+                          hipStream_t s);
 // level start: sweep counter 0; gdone[g] = !gactive[g] (gactive null = all run); moves zeroed
 hipError_t launch_ctl_init(SweepCtl* ctl, int32_t G, const int32_t* gactive, int32_t* gdone, int32_t* gsweeps,
                            uint32_t* gmoves, int32_t max_sweeps, hipStream_t s);

@@ -551,9 +551,29 @@ __device__ __forceinline__ void claim_rows(const MoveArgs& a, int ecm, int64_t v
     int32_t ww[ME], slot[ME];
     load_pairs<G, ME>(a, i, beg + lane, end, ecm, cc, ww);
     group_sync<G>();
+    // LPA gathers a row's entries into few labels once they spread: in a
+    // group of a whole wavefront or more, the lanes holding the first lane's
+    // label sum their weights and make one table add (Louvain's communities
+    // at a vertex are mostly distinct, so it adds entry by entry)
+    const bool merge = G >= WAVE && a.mode == MODE_LPA;
 #pragma unroll
-    for (int u = 0; u < ME; ++u)
-        slot[u] = cc[u].x == EMPTY_KEY ? -1 : claim_or_add<!POW2>(tab, POW2 ? T - 1u : T, cc[u].x, ww[u]);
+    for (int u = 0; u < ME; ++u) {
+        const int32_t C = cc[u].x;
+        if (merge) {
+            const uint64_t live_m = __ballot(C != EMPTY_KEY);
+            const int leader = live_m ? __ffsll((unsigned long long)live_m) - 1 : 0;
+            const int32_t lk = __shfl(C, leader);
+            const bool same = live_m && C != EMPTY_KEY && C == lk;
+            int32_t sw = same ? ww[u] : 0;
+#pragma unroll
+            for (int d = WAVE / 2; d >= 1; d >>= 1) sw += __shfl_xor(sw, d);
+            if (C == EMPTY_KEY) slot[u] = -1;
+            else if (same) slot[u] = (int)lane_id() == leader ? claim_or_add<!POW2>(tab, POW2 ? T - 1u : T, C, sw) : -1;
+            else slot[u] = claim_or_add<!POW2>(tab, POW2 ? T - 1u : T, C, ww[u]);
+        } else {
+            slot[u] = C == EMPTY_KEY ? -1 : claim_or_add<!POW2>(tab, POW2 ? T - 1u : T, C, ww[u]);
+        }
+    }
     group_sync<G>();
     const bool louvain = a.mode == MODE_LOUVAIN;
     int64_t best_s = INT64_MIN;
@@ -1173,6 +1193,10 @@ __device__ __forceinline__ void peeled_apply(int32_t* key, int32_t* val, int32_t
     if (valid && !mine && d) apply_add(key, val, fill, sigma, C, d);
 }
 
+// Commit of one synchronous sweep: every mover takes its new community, and
+// (sigma not null) the community volumes follow.  LPA passes no volumes: its
+// scores never read them, and they are summed once from the final labels
+// (k_volumes).
 __global__ __launch_bounds__(256) void k_apply(const int32_t* verts, const int32_t* dec, int32_t m, const int32_t* k,
                                                const int32_t* gid, int32_t* comm, int32_t* sigma, const SweepCtl* ctl,
                                                uint32_t* gmoves, int32_t max_sweeps)
@@ -1205,15 +1229,43 @@ __global__ __launch_bounds__(256) void k_apply(const int32_t* verts, const int32
             ++my_n;
             comm[v] = C;
         }
-        if (__ballot(valid)) {
+        if (sigma && __ballot(valid)) {
             peeled_apply(t_key, t_val, &t_fill, sigma, C, kv, valid);
             peeled_apply(t_key, t_val, &t_fill, sigma, A, -kv, valid);
         }
     }
     __syncthreads();
+    if (sigma)
+        for (int t = threadIdx.x; t < APPLY_SLOTS; t += 256)
+            if (t_key[t] != EMPTY_KEY && t_val[t] != 0) atomicAdd(&sigma[t_key[t]], t_val[t]);
+    block_flush_sums<256, uint32_t>(moves, my_n ? my_g : -1, my_n);
+}
+
+// sigma[comm[v]] += k[v] over the listed vertices verts[0..m) (sigma cleared
+// by the caller), summed per workgroup in the same LDS table as the commit.
+__global__ __launch_bounds__(256) void k_volumes(const int32_t* verts, int32_t m, const int32_t* k,
+                                                 const int32_t* comm, int32_t* sigma)
+{
+    __shared__ int32_t t_key[APPLY_SLOTS];
+    __shared__ int32_t t_val[APPLY_SLOTS];
+    __shared__ int32_t t_fill;
+    if (threadIdx.x == 0) t_fill = 0;
+    for (int t = threadIdx.x; t < APPLY_SLOTS; t += 256) { t_key[t] = EMPTY_KEY; t_val[t] = 0; }
+    __syncthreads();
+    for (int64_t base = (int64_t)blockIdx.x * 256; base < m; base += (int64_t)gridDim.x * 256) {
+        const int64_t t = base + threadIdx.x;
+        const bool valid = t < m;
+        int32_t C = 0, kv = 0;
+        if (valid) {
+            const int32_t v = verts[t];
+            C = comm[v];
+            kv = k[v];
+        }
+        peeled_apply(t_key, t_val, &t_fill, sigma, C, kv, valid);
+    }
+    __syncthreads();
     for (int t = threadIdx.x; t < APPLY_SLOTS; t += 256)
         if (t_key[t] != EMPTY_KEY && t_val[t] != 0) atomicAdd(&sigma[t_key[t]], t_val[t]);
-    block_flush_sums<256, uint32_t>(moves, my_n ? my_g : -1, my_n);
 }
 
 // After sweep s (1-based): a running graph stops when s >= 2 and its last two
@@ -1614,6 +1666,13 @@ hipError_t launch_apply(const int32_t* verts, const int32_t* dec, int32_t m, con
 {
     if (m <= 0) return hipSuccess;
     k_apply<<<grid_for(m, 256, 2048), 256, 0, s>>>(verts, dec, m, k, gid, comm, sigma, ctl, gmoves, max_sweeps);
+    return hipGetLastError();
+}
+hipError_t launch_volumes(const int32_t* verts, int32_t m, const int32_t* k, const int32_t* comm, int32_t* sigma,
+                          hipStream_t s)
+{
+    if (m <= 0) return hipSuccess;
+    k_volumes<<<grid_for(m, 256, 2048), 256, 0, s>>>(verts, m, k, comm, sigma);
     return hipGetLastError();
 }
 
