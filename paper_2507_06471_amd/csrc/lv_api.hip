@@ -128,6 +128,7 @@ struct Workspace {
     DevBuf keys, keys_alt, vals, vals_alt, head;
     DevBuf g_off[2], g_idx[2], g_w[2], g_k[2], g_gid[2];
     DevBuf hub_table, hub_meta, hub_part, hub_rows, hub_cnt, hub_bucket, hub_bucket_w;
+    bool hub_table_clean = false;  // every slot of hub_table is empty
     DevBuf rows;  // per-level row descriptors of the class-sorted vertices
     DevBuf ce;    // entry cache: per CSR entry of the handle's input graph, its neighbour's pair
     DevBuf chg;   // per listed vertex: its pair changed in the last commit (uint8)
@@ -510,14 +511,13 @@ lv_status plan_hubs(lv_graph* g, const LevelGraph& G, const int32_t* hub_verts, 
     hipStream_t s = g->stream;
     plan.nhubs = nhubs;
     if (nhubs == 0) return LV_OK;
-    // row starts and lengths of the hubs, read back to size the layout
+    // row starts and lengths of the hubs; the lengths are read back to size the layout
     HIP_TRY(ws.hub_rows.ensure(sizeof(int32_t) * 2 * (size_t)nhubs));
     int32_t* d_beg = ws.hub_rows.as<int32_t>();
     int32_t* d_len = d_beg + nhubs;
     HIP_TRY(launch_gather_rows(hub_verts, nhubs, G.off, d_beg, d_len, s));
-    std::vector<int32_t> beg(nhubs), len(nhubs), hv(nhubs);
-    const size_t hb = sizeof(int32_t) * (size_t)nhubs;
-    LV_TRY(read_back(g, {{beg.data(), d_beg, hb}, {len.data(), d_len, hb}, {hv.data(), hub_verts, hb}}));
+    std::vector<int32_t> len(nhubs);
+    LV_TRY(read_back(g, {{len.data(), d_len, sizeof(int32_t) * (size_t)nhubs}}));
     if (tu.bucketed) {
         // the scatter pass histograms at most HUB_PMAX partitions of a vertex:
         // a level with a longer row uses the compact mode instead
@@ -528,72 +528,94 @@ lv_status plan_hubs(lv_graph* g, const LevelGraph& G, const int32_t* hub_verts, 
             tu.part_keys = 8192;
         }
     }
-    std::vector<int32_t> parts(nhubs), first_blk(nhubs + 1), blk_hub, blk_part;
-    std::vector<int64_t> tab_off(nhubs);
-    std::vector<int32_t> tab_cap(nhubs), ins_hub, ins_beg, ins_end, scan_hub, scan_beg, scan_end, fpart_first(nhubs + 1);
-    std::vector<int32_t> sc_hub, sc_beg, sc_end, mk_hub, mk_beg, mk_end;
-    int64_t slots = 0;
+    // Per hub: its partitions, its fallback table, and where its workgroups
+    // start in each per-workgroup list (partition, scatter, fallback insert
+    // and scan, pruning marks).  The lists themselves are expanded on the
+    // device from these prefix counts (k_chunk_list), so the host work and the
+    // upload stay proportional to the number of hubs.
     constexpr int64_t MARK_CHUNK = 4096;  // entries per pruning-mark workgroup
+    std::vector<int32_t> parts(nhubs), tab_cap(nhubs);
+    std::vector<int32_t> first_blk(nhubs + 1), first_sc(nhubs + 1), first_ins(nhubs + 1), first_scan(nhubs + 1),
+        first_mk(nhubs + 1);
+    std::vector<int64_t> tab_off(nhubs);
+    int64_t slots = 0, nblk = 0, nsc = 0, nins = 0, nscan = 0, nmk = 0;
+    auto chunks = [](int64_t n, int64_t c) { return (n + c - 1) / c; };
     for (int32_t h = 0; h < nhubs; ++h) {
-        for (int64_t e = beg[h]; e < (int64_t)beg[h] + len[h]; e += MARK_CHUNK) {
-            mk_hub.push_back(h);
-            mk_beg.push_back((int32_t)e);
-            mk_end.push_back((int32_t)std::min<int64_t>(e + MARK_CHUNK, (int64_t)beg[h] + len[h]));
-        }
-        const int64_t P = std::max<int64_t>(1, ((int64_t)len[h] + tu.part_keys - 1) / tu.part_keys);
+        first_mk[h] = (int32_t)nmk;
+        nmk += chunks(len[h], MARK_CHUNK);
+        const int64_t P = std::max<int64_t>(1, chunks(len[h], tu.part_keys));
         parts[h] = (int32_t)P;
-        first_blk[h] = (int32_t)blk_hub.size();
-        for (int32_t q = 0; q < P; ++q) { blk_hub.push_back(h); blk_part.push_back(q); }
-        fpart_first[h] = (int32_t)scan_hub.size();
+        first_blk[h] = (int32_t)nblk;
+        nblk += P;
+        first_sc[h] = (int32_t)nsc;
+        first_ins[h] = (int32_t)nins;
+        first_scan[h] = (int32_t)nscan;
         tab_off[h] = slots;
         tab_cap[h] = 0;
         if (P == 1) continue;  // one partition of <= part_keys keys always fits its LDS table
-        if (tu.bucketed)
-            for (int64_t e = beg[h]; e < (int64_t)beg[h] + len[h]; e += tu.sc_chunk) {
-                sc_hub.push_back(h);
-                sc_beg.push_back((int32_t)e);
-                sc_end.push_back((int32_t)std::min<int64_t>(e + tu.sc_chunk, (int64_t)beg[h] + len[h]));
-            }
+        if (tu.bucketed) nsc += chunks(len[h], tu.sc_chunk);
         const uint64_t cap = std::max<uint64_t>(64, next_pow2(2ull * (uint64_t)len[h]));
         if (cap > (uint64_t)INT32_MAX) { set_error_msg("hub table too large"); return LV_E_OVERFLOW; }
         tab_cap[h] = (int32_t)cap;
         slots += (int64_t)cap;
-        for (int64_t e = beg[h]; e < (int64_t)beg[h] + len[h]; e += tu.fb_chunk) {
-            ins_hub.push_back(h);
-            ins_beg.push_back((int32_t)e);
-            ins_end.push_back((int32_t)std::min<int64_t>(e + tu.fb_chunk, (int64_t)beg[h] + len[h]));
-        }
-        for (int64_t t = 0; t < (int64_t)cap; t += tu.fb_chunk) {
-            scan_hub.push_back(h);
-            scan_beg.push_back((int32_t)t);
-            scan_end.push_back((int32_t)std::min<int64_t>(t + tu.fb_chunk, (int64_t)cap));
-        }
+        nins += chunks(len[h], tu.fb_chunk);
+        nscan += chunks((int64_t)cap, tu.fb_chunk);
     }
-    first_blk[nhubs] = (int32_t)blk_hub.size();
-    fpart_first[nhubs] = (int32_t)scan_hub.size();
-    const int32_t nblk = (int32_t)blk_hub.size(), nins = (int32_t)ins_hub.size(), nscan = (int32_t)scan_hub.size();
-    const int32_t nsc = (int32_t)sc_hub.size();
-    // metadata: int64 tab_off first, then the int32 arrays
-    std::vector<int32_t> pack;
-    auto put = [&](const std::vector<int32_t>& v) {
-        const size_t at = pack.size();
-        pack.insert(pack.end(), v.begin(), v.end());
-        return at;
-    };
-    const size_t o_hv = put(hv), o_parts = put(parts), o_fb = put(first_blk), o_bh = put(blk_hub), o_bp = put(blk_part);
-    const size_t o_cap = put(tab_cap), o_ih = put(ins_hub), o_ib = put(ins_beg), o_ie = put(ins_end);
-    const size_t o_sh = put(scan_hub), o_sb = put(scan_beg), o_se = put(scan_end), o_ff = put(fpart_first);
-    const size_t o_ch = put(sc_hub), o_cb = put(sc_beg), o_ce = put(sc_end);
-    const size_t o_mh = put(mk_hub), o_mb = put(mk_beg), o_me = put(mk_end);
-    SyncOnExit sync_host_vectors{s};
-    const size_t b64 = sizeof(int64_t) * (size_t)nhubs;
-    HIP_TRY(ws.hub_meta.ensure(b64 + sizeof(int32_t) * pack.size() + 64));
+    if (std::max({nblk, nsc, nins, nscan, nmk}) > (int64_t)INT32_MAX) {
+        set_error_msg("hub workgroup lists too long");
+        return LV_E_OVERFLOW;
+    }
+    first_blk[nhubs] = (int32_t)nblk;
+    first_sc[nhubs] = (int32_t)nsc;
+    first_ins[nhubs] = (int32_t)nins;
+    first_scan[nhubs] = (int32_t)nscan;
+    first_mk[nhubs] = (int32_t)nmk;
+    // device metadata: int64 tab_off, then the per-hub int32 arrays (uploaded
+    // through the pinned staging area), then the per-workgroup lists
+    const size_t H = (size_t)nhubs, H1 = H + 1;
+    const size_t o_hv = 0, o_parts = o_hv + H, o_cap = o_parts + H, o_fb = o_cap + H, o_fsc = o_fb + H1,
+                 o_fins = o_fsc + H1, o_ff = o_fins + H1, o_fmk = o_ff + H1, n_up = o_fmk + H1;
+    const size_t o_bh = n_up, o_bp = o_bh + (size_t)nblk, o_ch = o_bp + (size_t)nblk, o_cb = o_ch + (size_t)nsc,
+                 o_ce = o_cb + (size_t)nsc, o_ih = o_ce + (size_t)nsc, o_ib = o_ih + (size_t)nins,
+                 o_ie = o_ib + (size_t)nins, o_sh = o_ie + (size_t)nins, o_sb = o_sh + (size_t)nscan,
+                 o_se = o_sb + (size_t)nscan, o_mh = o_se + (size_t)nscan, o_mb = o_mh + (size_t)nmk,
+                 o_me = o_mb + (size_t)nmk, n_all = o_me + (size_t)nmk;
+    const size_t b64 = sizeof(int64_t) * H;
+    const size_t up_bytes = b64 + sizeof(int32_t) * n_up;
+    HIP_TRY(ws.hub_meta.ensure(b64 + sizeof(int32_t) * n_all + 64));
     char* base = ws.hub_meta.as<char>();
     int32_t* p32 = (int32_t*)(base + b64);
-    HIP_TRY(hipMemcpyAsync(base, tab_off.data(), b64, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(p32, pack.data(), sizeof(int32_t) * pack.size(), hipMemcpyHostToDevice, s));
+    LV_TRY(ensure_pinned(g, up_bytes));
+    {
+        char* st = (char*)g->pinned;
+        int32_t* u32 = (int32_t*)(st + b64);
+        std::memcpy(st, tab_off.data(), b64);
+        std::memcpy(u32 + o_parts, parts.data(), sizeof(int32_t) * H);
+        std::memcpy(u32 + o_cap, tab_cap.data(), sizeof(int32_t) * H);
+        std::memcpy(u32 + o_fb, first_blk.data(), sizeof(int32_t) * H1);
+        std::memcpy(u32 + o_fsc, first_sc.data(), sizeof(int32_t) * H1);
+        std::memcpy(u32 + o_fins, first_ins.data(), sizeof(int32_t) * H1);
+        std::memcpy(u32 + o_ff, first_scan.data(), sizeof(int32_t) * H1);
+        std::memcpy(u32 + o_fmk, first_mk.data(), sizeof(int32_t) * H1);
+    }
+    // the staging area is reused by the next read-back only after the stream
+    // has drained (every read-back synchronizes first), and this function
+    // synchronizes before it returns
+    HIP_TRY(hipMemcpyAsync(base, g->pinned, up_bytes, hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_copy_i32(p32 + o_hv, hub_verts, nhubs, s));
+    HIP_TRY(launch_chunk_list(p32 + o_fb, nhubs, (int32_t)nblk, nullptr, p32 + o_parts, 1, p32 + o_bh, p32 + o_bp,
+                              nullptr, s));
+    HIP_TRY(launch_chunk_list(p32 + o_fsc, nhubs, (int32_t)nsc, d_beg, d_len, tu.sc_chunk, p32 + o_ch, p32 + o_cb,
+                              p32 + o_ce, s));
+    HIP_TRY(launch_chunk_list(p32 + o_fins, nhubs, (int32_t)nins, d_beg, d_len, tu.fb_chunk, p32 + o_ih, p32 + o_ib,
+                              p32 + o_ie, s));
+    HIP_TRY(launch_chunk_list(p32 + o_ff, nhubs, (int32_t)nscan, nullptr, p32 + o_cap, tu.fb_chunk, p32 + o_sh,
+                              p32 + o_sb, p32 + o_se, s));
+    HIP_TRY(launch_chunk_list(p32 + o_fmk, nhubs, (int32_t)nmk, d_beg, d_len, (int32_t)MARK_CHUNK, p32 + o_mh,
+                              p32 + o_mb, p32 + o_me, s));
     // partial results + flags: [nblk] x (int64 score, int32 comm, wown, flag), [nhubs] fb_flag, [nscan] fallback partials
-    const size_t part_bytes = (size_t)nblk * (8 + 4 * 3) + (size_t)nhubs * 4 + (size_t)std::max(nscan, 1) * (8 + 4 * 2);
+    const size_t part_bytes =
+        (size_t)nblk * (8 + 4 * 3) + (size_t)nhubs * 4 + (size_t)std::max<int64_t>(nscan, 1) * (8 + 4 * 2);
     HIP_TRY(ws.hub_part.ensure(part_bytes + 64));
     char* pb = ws.hub_part.as<char>();
     HubArgs& a = plan.args;
@@ -606,7 +628,7 @@ lv_status plan_hubs(lv_graph* g, const LevelGraph& G, const int32_t* hub_verts, 
     a.hub_first_blk = p32 + o_fb;
     a.blk_hub = p32 + o_bh;
     a.blk_part = p32 + o_bp;
-    a.nblk = nblk;
+    a.nblk = (int32_t)nblk;
     a.part_score = (int64_t*)pb;
     a.part_comm = (int32_t*)(a.part_score + nblk);
     a.part_wown = a.part_comm + nblk;
@@ -614,18 +636,18 @@ lv_status plan_hubs(lv_graph* g, const LevelGraph& G, const int32_t* hub_verts, 
     a.fb_flag = a.part_flag + nblk;
     int64_t* fps = (int64_t*)(((uintptr_t)(a.fb_flag + nhubs) + 7) & ~(uintptr_t)7);
     a.fpart_score = fps;
-    a.fpart_comm = (int32_t*)(fps + std::max(nscan, 1));
-    a.fpart_wown = a.fpart_comm + std::max(nscan, 1);
+    a.fpart_comm = (int32_t*)(fps + std::max<int64_t>(nscan, 1));
+    a.fpart_wown = a.fpart_comm + std::max<int64_t>(nscan, 1);
     a.fpart_first = p32 + o_ff;
     a.tab_off = (const int64_t*)base;
     a.sc_hub = p32 + o_ch;
     a.sc_beg = p32 + o_cb;
     a.sc_end = p32 + o_ce;
-    a.nsc = nsc;
+    a.nsc = (int32_t)nsc;
     a.mk_hub = p32 + o_mh;
     a.mk_beg = p32 + o_mb;
     a.mk_end = p32 + o_me;
-    a.nmk = (int32_t)mk_hub.size();
+    a.nmk = (int32_t)nmk;
     a.sc_chunk = tu.sc_chunk;
     a.max_parts = 0;
     for (int32_t h = 0; h < nhubs; ++h) a.max_parts = std::max(a.max_parts, parts[h]);
@@ -644,16 +666,23 @@ lv_status plan_hubs(lv_graph* g, const LevelGraph& G, const int32_t* hub_verts, 
     a.ins_hub = p32 + o_ih;
     a.ins_beg = p32 + o_ib;
     a.ins_end = p32 + o_ie;
-    a.nins = nins;
+    a.nins = (int32_t)nins;
     a.scan_hub = p32 + o_sh;
     a.scan_beg = p32 + o_sb;
     a.scan_end = p32 + o_se;
-    a.nscan = nscan;
-    HIP_TRY(hipMemsetAsync(a.fb_flag, 0, sizeof(int32_t) * (size_t)nhubs, s));
+    a.nscan = (int32_t)nscan;
+    HIP_TRY(launch_fill_i32(a.fb_flag, 0, nhubs, s));
+    // The fallback tables: every slot starts empty, and the scan pass empties
+    // each slot it reads, so a table that completed its sweeps is clean for
+    // the next level; it is cleared here only when it is new or a level did
+    // not complete (run_sweeps marks it clean at the end of a level).
+    const size_t old_cap = ws.hub_table.cap;
     HIP_TRY(ws.hub_table.ensure(sizeof(int32_t) * 2 * (size_t)std::max<int64_t>(slots, 1)));
     a.table = ws.hub_table.as<int32_t>();
-    HIP_TRY(launch_hub_clear(a.table, slots, s));
-    // the host vectors must outlive the asynchronous copies
+    if (!ws.hub_table_clean || ws.hub_table.cap != old_cap)
+        HIP_TRY(launch_hub_clear(a.table, (int64_t)(ws.hub_table.cap / (2 * sizeof(int32_t))), s));
+    ws.hub_table_clean = false;
+    // the staging area is free again once the upload is done
     HIP_TRY(hipStreamSynchronize(s));
     return LV_OK;
 }
@@ -876,58 +905,51 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
         return LV_OK;
     };
     const bool use_graph = !timing && !(p.flags & LV_NO_HIPGRAPH);
+    // the sweeps' graph lives until the level's results are read back (one
+    // stream synchronization per level); on an early return the stream is
+    // drained before the graph is destroyed
+    struct GraphHolder {
+        hipStream_t s;
+        hipGraph_t gr = nullptr;
+        hipGraphExec_t ex = nullptr;
+        ~GraphHolder()
+        {
+            if (!ex && !gr) return;
+            (void)hipStreamSynchronize(s);
+            if (ex) (void)hipGraphExecDestroy(ex);
+            if (gr) (void)hipGraphDestroy(gr);
+        }
+    } held{s};
+    Timer ph;
+    ph.s = s;
+    hipEvent_t p0{}, p1{};
     if (use_graph) {
         // The first sweep (every community a single vertex) is launched
         // directly; while it runs, a later sweep is captured once and then
         // replayed up to max_sweeps - 1 times: the kernels read the sweep
         // counter and early-exit flag from the device.
-        Timer ph;
-        ph.s = s;
-        hipEvent_t p0{}, p1{};
         HIP_TRY(ph.mark(&p0));
         LV_TRY(launch_sweep(true, nullptr));
-        hipGraph_t gr = nullptr;
-        hipGraphExec_t ex = nullptr;
-        lv_status st = LV_OK;
         if (S > 1) {
             hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
-            if (e != hipSuccess) { set_error("hipStreamBeginCapture", e); st = from_hip(e); }
-            if (st == LV_OK) {
-                st = launch_sweep(false, nullptr);
-                e = hipStreamEndCapture(s, &gr);
-                if (st == LV_OK && e != hipSuccess) { set_error("hipStreamEndCapture", e); st = from_hip(e); }
-            }
-            if (st == LV_OK) {
-                e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
-                if (e != hipSuccess) { set_error("hipGraphInstantiate", e); st = from_hip(e); }
-            }
-            for (int32_t sw = 2; sw <= S && st == LV_OK; ++sw) {
-                e = hipGraphLaunch(ex, s);
-                if (e != hipSuccess) { set_error("hipGraphLaunch", e); st = from_hip(e); }
+            if (e != hipSuccess) { set_error("hipStreamBeginCapture", e); return from_hip(e); }
+            const lv_status st = launch_sweep(false, nullptr);
+            e = hipStreamEndCapture(s, &held.gr);
+            LV_TRY(st);
+            if (e != hipSuccess) { set_error("hipStreamEndCapture", e); return from_hip(e); }
+            e = hipGraphInstantiate(&held.ex, held.gr, nullptr, nullptr, 0);
+            if (e != hipSuccess) { set_error("hipGraphInstantiate", e); return from_hip(e); }
+            for (int32_t sw = 2; sw <= S; ++sw) {
+                e = hipGraphLaunch(held.ex, s);
+                if (e != hipSuccess) { set_error("hipGraphLaunch", e); return from_hip(e); }
             }
         }
-        if (st == LV_OK) {
-            hipError_t e = ph.mark(&p1);
-            if (e != hipSuccess) { set_error("hipEventRecord", e); st = from_hip(e); }
-        }
-        hipError_t es = hipStreamSynchronize(s);
-        if (st == LV_OK && es == hipSuccess) out.sweep_ms = elapsed(p0, p1);
-        if (ex) (void)hipGraphExecDestroy(ex);
-        if (gr) (void)hipGraphDestroy(gr);
-        LV_TRY(st);
-        HIP_TRY(es);
+        HIP_TRY(ph.mark(&p1));
     } else {
         ev.resize(S);
-        Timer ph;
-        ph.s = s;
-        hipEvent_t p0{}, p1{};
         if (!timing) HIP_TRY(ph.mark(&p0));
         for (int32_t sw = 1; sw <= S; ++sw) LV_TRY(launch_sweep(sw == 1, timing ? &ev[sw - 1] : nullptr));
-        if (!timing) {
-            HIP_TRY(ph.mark(&p1));
-            HIP_TRY(hipStreamSynchronize(s));
-            out.sweep_ms = elapsed(p0, p1);
-        }
+        if (!timing) HIP_TRY(ph.mark(&p1));
     }
     // LPA's commits leave the volumes alone (its scores never read them):
     // those of its final labels, for its modularity, are summed here
@@ -943,6 +965,8 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
     HIP_TRY(hipMemcpyAsync(h_sweeps, ws.gsweeps.p, sizeof(int32_t) * (size_t)G.G, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(h_ctl, ws.ctl.p, sizeof(SweepCtl), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    ws.hub_table_clean = true;  // every fallback scan of the level has run
+    if (!timing) out.sweep_ms = elapsed(p0, p1);
     out.cached_sweeps = use_ec ? h_ctl->ec_reads : 0;
     out.refreshed = use_ec ? (int64_t)h_ctl->refreshed : 0;
     out.ec_last = use_ec ? h_ctl->ec_last : EC_GATHER;

@@ -255,6 +255,9 @@ struct FusedMap {
 };
 hipError_t launch_move_fused(const MoveArgs& a, const FusedMap& fm, SweepCtl* ctl, hipStream_t s);
 hipError_t launch_hub_clear(int32_t* table, int64_t slots, hipStream_t s);
+hipError_t launch_chunk_list(const int32_t* first, int32_t nhubs, int32_t total, const int32_t* base,
+                             const int32_t* len, int32_t chunk, int32_t* o_hub, int32_t* o_beg, int32_t* o_end,
+                             hipStream_t s);
 // bucketed mode, sweeps after the first: scatter the hubs' entries to the partition buckets
 hipError_t launch_hub_scatter(const MoveArgs& a, const HubArgs& h, hipStream_t s);
 // partition workgroups, merge and decision, global-table fallback

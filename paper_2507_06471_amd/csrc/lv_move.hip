@@ -1605,6 +1605,39 @@ hipError_t launch_move_class(int cls, bool singleton, bool async, const MoveArgs
     }
 }
 
+// Expands per-hub workgroup counts into a per-workgroup list: workgroup b
+// (of first[nhubs]) belongs to the hub h with first[h] <= b < first[h+1] (the
+// last such h: hubs without workgroups have first[h] == first[h+1]) and is
+// its chunk k = b - first[h], covering [base[h] + k*chunk, min(base[h] +
+// (k+1)*chunk, base[h] + len[h])) (base null: 0).  o_end may be null.
+__global__ __launch_bounds__(256) void k_chunk_list(const int32_t* __restrict__ first, int32_t nhubs, int32_t total,
+                                                    const int32_t* __restrict__ base, const int32_t* __restrict__ len,
+                                                    int32_t chunk, int32_t* __restrict__ o_hub,
+                                                    int32_t* __restrict__ o_beg, int32_t* __restrict__ o_end)
+{
+    const int32_t b = (int32_t)(blockIdx.x * 256 + threadIdx.x);
+    if (b >= total) return;
+    int32_t lo = 0, hi = nhubs - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (first[mid] <= b) lo = mid; else hi = mid - 1;
+    }
+    const int64_t b0 = base ? (int64_t)base[lo] : 0;
+    const int64_t e0 = b0 + (int64_t)(b - first[lo]) * chunk;
+    o_hub[b] = lo;
+    o_beg[b] = (int32_t)e0;
+    if (o_end) o_end[b] = (int32_t)min(e0 + chunk, b0 + (int64_t)len[lo]);
+}
+hipError_t launch_chunk_list(const int32_t* first, int32_t nhubs, int32_t total, const int32_t* base,
+                             const int32_t* len, int32_t chunk, int32_t* o_hub, int32_t* o_beg, int32_t* o_end,
+                             hipStream_t s)
+{
+    if (total <= 0 || nhubs <= 0) return hipSuccess;
+    k_chunk_list<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(first, nhubs, total, base, len, chunk, o_hub, o_beg,
+                                                                  o_end);
+    return hipGetLastError();
+}
+
 __global__ void k_hub_clear(int32_t* table, int64_t slots)
 {
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < slots; t += (int64_t)gridDim.x * blockDim.x) {
