@@ -420,19 +420,55 @@ __device__ __forceinline__ void load_pairs(const MoveArgs& a, int32_t i, int32_t
 // community's sum.  mask: slots - 1 (a power of two), or with MOD the slot
 // count, hashed by a multiply-high reduction.
 constexpr unsigned long long EMPTY_SLOT = 0xFFFFFFFF00000000ull;
+
+// Probe sequence of key C in a claim table (double hashing: start and stride
+// from the key's hash, so that keys landing near each other do not follow
+// one another's runs).  A power-of-two table (mask = slots - 1) takes an odd
+// stride, which visits every slot within `slots` steps; a table of any size
+// (MOD, mask = slots >= 2) takes a stride in [1, slots - 1] for 8 steps and
+// then continues slot by slot, so it too reaches every slot.  Every lane
+// holding key C walks the same sequence, which is all claim-or-add needs:
+// slots only change from empty to a key, so the first lane to claim takes the
+// first empty slot of the sequence and every later one passes the same
+// occupied slots to reach it.
+struct Probe {
+    uint32_t h, st, n;
+};
+template <bool MOD>
+__device__ __forceinline__ Probe probe_start(int32_t C, uint32_t mask)
+{
+    const uint32_t hv = mix32(C);
+    if constexpr (MOD)
+        return Probe{(uint32_t)(((uint64_t)hv * mask) >> 32),
+                     1u + (uint32_t)(((uint64_t)(hv * 0x85EBCA6Bu) * (mask - 1u)) >> 32), 0u};
+    else
+        return Probe{hv & mask, ((hv >> 16) | 1u) & mask, 0u};
+}
+template <bool MOD>
+__device__ __forceinline__ void probe_next(Probe& p, uint32_t mask)
+{
+    if constexpr (MOD) {
+        if (++p.n == 8u) p.st = 1u;
+        p.h += p.st;
+        if (p.h >= mask) p.h -= mask;
+    } else {
+        p.h = (p.h + p.st) & mask;
+    }
+}
+
 template <bool MOD>
 __device__ __forceinline__ int32_t claim_or_add(unsigned long long* tab, uint32_t mask, int32_t C, int32_t W)
 {
     const unsigned long long mine = ((unsigned long long)(uint32_t)C << 32) | (uint32_t)W;
-    uint32_t h = MOD ? (uint32_t)(((uint64_t)mix32(C) * mask) >> 32) : (mix32(C) & mask);
+    Probe p = probe_start<MOD>(C, mask);
     for (;;) {
-        const unsigned long long prev = atomicCAS(&tab[h], EMPTY_SLOT, mine);
-        if (prev == EMPTY_SLOT) return (int32_t)h;
+        const unsigned long long prev = atomicCAS(&tab[p.h], EMPTY_SLOT, mine);
+        if (prev == EMPTY_SLOT) return (int32_t)p.h;
         if ((int32_t)(prev >> 32) == C) {
-            atomicAdd(&tab[h], (unsigned long long)(uint32_t)W);
+            atomicAdd(&tab[p.h], (unsigned long long)(uint32_t)W);
             return -1;
         }
-        if constexpr (MOD) h = h + 1 == mask ? 0u : h + 1; else h = (h + 1) & mask;
+        probe_next<MOD>(p, mask);
     }
 }
 
@@ -777,15 +813,15 @@ __device__ __forceinline__ int32_t claim_or_add_bounded(unsigned long long* tab,
                                                         bool& ok)
 {
     const unsigned long long mine = ((unsigned long long)(uint32_t)C << 32) | (uint32_t)W;
-    uint32_t h = mix32(C) & mask;
+    Probe p = probe_start<false>(C, mask);  // a power-of-two table: odd stride, every slot within mask + 1 probes
     for (uint32_t probes = 0; probes <= mask; ++probes) {
-        const unsigned long long prev = atomicCAS(&tab[h], EMPTY_SLOT, mine);
-        if (prev == EMPTY_SLOT) return (int32_t)h;
+        const unsigned long long prev = atomicCAS(&tab[p.h], EMPTY_SLOT, mine);
+        if (prev == EMPTY_SLOT) return (int32_t)p.h;
         if ((int32_t)(prev >> 32) == C) {
-            atomicAdd(&tab[h], (unsigned long long)(uint32_t)W);
+            atomicAdd(&tab[p.h], (unsigned long long)(uint32_t)W);
             return -1;
         }
-        h = (h + 1) & mask;
+        probe_next<false>(p, mask);
     }
     ok = false;
     return -1;
