@@ -230,6 +230,41 @@ __device__ __forceinline__ void for_tile_entries_co_at(int64_t tile, const int32
     }
 }
 
+// Probe sequence of key C in an LDS table (double hashing: start and stride
+// from the key's hash, so that keys landing near each other do not follow
+// one another's runs).  A power-of-two table (mask = slots - 1) takes an odd
+// stride, which visits every slot within `slots` steps; a table of any size
+// (MOD, mask = slots >= 2) takes a stride in [1, slots - 1] for 8 steps and
+// then continues slot by slot, so it too reaches every slot.  Every lane
+// holding key C walks the same sequence, which is all an insert needs:
+// slots only change from empty to a key, so the first lane to claim takes the
+// first empty slot of the sequence and every later one passes the same
+// occupied slots to reach it.
+struct Probe {
+    uint32_t h, st, n;
+};
+template <bool MOD>
+__device__ __forceinline__ Probe probe_start(int32_t C, uint32_t mask)
+{
+    const uint32_t hv = mix32(C);
+    if constexpr (MOD)
+        return Probe{(uint32_t)(((uint64_t)hv * mask) >> 32),
+                     1u + (uint32_t)(((uint64_t)(hv * 0x85EBCA6Bu) * (mask - 1u)) >> 32), 0u};
+    else
+        return Probe{hv & mask, ((hv >> 16) | 1u) & mask, 0u};
+}
+template <bool MOD>
+__device__ __forceinline__ void probe_next(Probe& p, uint32_t mask)
+{
+    if constexpr (MOD) {
+        if (++p.n == 8u) p.st = 1u;
+        p.h += p.st;
+        if (p.h >= mask) p.h -= mask;
+    } else {
+        p.h = (p.h + p.st) & mask;
+    }
+}
+
 // Insert (C, W) into an LDS open-addressing table that is guaranteed to have
 // room (distinct keys < slots); the thread that claims a slot stores the
 // community's volume S beside it.  The table has mask+1 slots (a power of
@@ -239,12 +274,12 @@ template <bool SIG, bool MOD = false>
 __device__ __forceinline__ void lds_insert(int32_t* key, int32_t* val, int32_t* sig, uint32_t mask, int32_t C,
                                            int32_t W, int32_t S)
 {
-    uint32_t h = MOD ? (uint32_t)(((uint64_t)mix32(C) * mask) >> 32) : (mix32(C) & mask);
+    Probe p = probe_start<MOD>(C, mask);
     for (;;) {
-        const int32_t prev = atomicCAS(&key[h], EMPTY_KEY, C);
-        if constexpr (SIG) if (prev == EMPTY_KEY) sig[h] = S;
-        if (prev == EMPTY_KEY || prev == C) { atomicAdd(&val[h], W); return; }
-        if constexpr (MOD) h = h + 1 == mask ? 0u : h + 1; else h = (h + 1) & mask;
+        const int32_t prev = atomicCAS(&key[p.h], EMPTY_KEY, C);
+        if constexpr (SIG) if (prev == EMPTY_KEY) sig[p.h] = S;
+        if (prev == EMPTY_KEY || prev == C) { atomicAdd(&val[p.h], W); return; }
+        probe_next<MOD>(p, mask);
     }
 }
 

@@ -244,12 +244,12 @@ template <bool SIG>
 __device__ __forceinline__ bool lds_insert_bounded(int32_t* key, int32_t* val, int32_t* sig, uint32_t mask, int32_t C,
                                                    int32_t W, int32_t S)
 {
-    uint32_t h = mix32(C) & mask;
+    Probe p = probe_start<false>(C, mask);  // power of two: every slot within mask + 1 probes
     for (uint32_t probes = 0; probes <= mask; ++probes) {
-        const int32_t prev = atomicCAS(&key[h], EMPTY_KEY, C);
-        if constexpr (SIG) if (prev == EMPTY_KEY) sig[h] = S;
-        if (prev == EMPTY_KEY || prev == C) { atomicAdd(&val[h], W); return true; }
-        h = (h + 1) & mask;
+        const int32_t prev = atomicCAS(&key[p.h], EMPTY_KEY, C);
+        if constexpr (SIG) if (prev == EMPTY_KEY) sig[p.h] = S;
+        if (prev == EMPTY_KEY || prev == C) { atomicAdd(&val[p.h], W); return true; }
+        probe_next<false>(p, mask);
     }
     return false;
 }
@@ -420,41 +420,6 @@ __device__ __forceinline__ void load_pairs(const MoveArgs& a, int32_t i, int32_t
 // community's sum.  mask: slots - 1 (a power of two), or with MOD the slot
 // count, hashed by a multiply-high reduction.
 constexpr unsigned long long EMPTY_SLOT = 0xFFFFFFFF00000000ull;
-
-// Probe sequence of key C in a claim table (double hashing: start and stride
-// from the key's hash, so that keys landing near each other do not follow
-// one another's runs).  A power-of-two table (mask = slots - 1) takes an odd
-// stride, which visits every slot within `slots` steps; a table of any size
-// (MOD, mask = slots >= 2) takes a stride in [1, slots - 1] for 8 steps and
-// then continues slot by slot, so it too reaches every slot.  Every lane
-// holding key C walks the same sequence, which is all claim-or-add needs:
-// slots only change from empty to a key, so the first lane to claim takes the
-// first empty slot of the sequence and every later one passes the same
-// occupied slots to reach it.
-struct Probe {
-    uint32_t h, st, n;
-};
-template <bool MOD>
-__device__ __forceinline__ Probe probe_start(int32_t C, uint32_t mask)
-{
-    const uint32_t hv = mix32(C);
-    if constexpr (MOD)
-        return Probe{(uint32_t)(((uint64_t)hv * mask) >> 32),
-                     1u + (uint32_t)(((uint64_t)(hv * 0x85EBCA6Bu) * (mask - 1u)) >> 32), 0u};
-    else
-        return Probe{hv & mask, ((hv >> 16) | 1u) & mask, 0u};
-}
-template <bool MOD>
-__device__ __forceinline__ void probe_next(Probe& p, uint32_t mask)
-{
-    if constexpr (MOD) {
-        if (++p.n == 8u) p.st = 1u;
-        p.h += p.st;
-        if (p.h >= mask) p.h -= mask;
-    } else {
-        p.h = (p.h + p.st) & mask;
-    }
-}
 
 template <bool MOD>
 __device__ __forceinline__ int32_t claim_or_add(unsigned long long* tab, uint32_t mask, int32_t C, int32_t W)
@@ -1195,17 +1160,18 @@ __device__ __forceinline__ void apply_add(int32_t* key, int32_t* val, int32_t* f
 {
     // a community already in the table always adds there; a new one takes
     // a slot only while the table holds fewer than APPLY_FILL communities
-    uint32_t h = mix32(C) & (uint32_t)(APPLY_SLOTS - 1);
+    constexpr uint32_t AMASK = (uint32_t)(APPLY_SLOTS - 1);
+    Probe pr = probe_start<false>(C, AMASK);
     for (int p = 0; p < APPLY_PROBE; ++p) {
-        const int32_t k = *(volatile int32_t*)&key[h];
-        if (k == C) { atomicAdd(&val[h], d); return; }
+        const int32_t k = *(volatile int32_t*)&key[pr.h];
+        if (k == C) { atomicAdd(&val[pr.h], d); return; }
         if (k == EMPTY_KEY) {
             if (*(volatile int32_t*)fill >= APPLY_FILL) break;
-            const int32_t prev = atomicCAS(&key[h], EMPTY_KEY, C);
+            const int32_t prev = atomicCAS(&key[pr.h], EMPTY_KEY, C);
             if (prev == EMPTY_KEY) atomicAdd(fill, 1);
-            if (prev == EMPTY_KEY || prev == C) { atomicAdd(&val[h], d); return; }
+            if (prev == EMPTY_KEY || prev == C) { atomicAdd(&val[pr.h], d); return; }
         }
-        h = (h + 1) & (uint32_t)(APPLY_SLOTS - 1);
+        probe_next<false>(pr, AMASK);
     }
     atomicAdd(&sigma[C], d);
 }
