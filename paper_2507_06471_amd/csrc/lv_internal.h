@@ -36,7 +36,13 @@ enum MoveClass : int {
 constexpr int32_t CLS_CAP[NUM_CLS] = {0, 4, 8, 32, 128, 256, 512, 1024, 2048, 3072, 8192, INT32_MAX};
 // classes of groups narrower than a wavefront, of one wavefront, of workgroups
 constexpr int CLS_FIRST_WAVE = CLS_L256, CLS_FIRST_BLOCK = CLS_L512;
-// table slots of the L8K class (8-byte slots: key and weight sum)
+// Claim-table slots per row of each class (8-byte slots: key and weight
+// sum), sized so that a CU still holds eight wavefronts a SIMD: at most
+// 20 KiB of tables per 256-thread workgroup, 40 KiB per 512-thread one,
+// 80 KiB per 1024-thread one (two workgroups of the 8192-entry class share a
+// CU's 160 KiB).  Every class's table exceeds its longest row.
+constexpr int32_t L4_SLOTS = 16, L8_SLOTS = 32, L32_SLOTS = 128, L128_SLOTS = 312, L256_SLOTS = 624,
+                  L512_SLOTS = 1248, L1K_SLOTS = 2496, L2K_SLOTS = 5056, L3K_SLOTS = 5056;
 constexpr int32_t L8K_SLOTS = 10112;
 
 // Device-side sweep control of one level: completed sweeps and whether every

@@ -12,23 +12,24 @@
 //
 // Scheduling by the vertex's number of CSR entries L (degree classes): about
 // one lane per four entries, so that a lane keeps four loads in flight and a
-// compute unit holds many vertices.  Table sizes (12-byte slots: community,
-// weight, volume) let every class run 8 wavefronts a SIMD: at most 20 KiB
-// per 256-thread and 40 KiB per 512-thread workgroup.  Sizes that are not a
-// power of two hash by a multiply-high reduction; a row of L entries uses
-// min(slots, 2L + 1) of them, so a table never fills.
-//   L <= 4      4 lanes per vertex, LDS table of 8 slots
-//   L <= 8      8 lanes, 16 slots
-//   L <= 32     16 lanes, 64 slots
-//   L <= 128    32 lanes, 208 slots
-//   L <= 256    a wavefront, 424 slots
-//   L <= 512    128 lanes, 848 slots
-//   L <= 1024   a 256-thread workgroup, 1696 slots
-//   L <= 2048   a 512-thread workgroup, 3392 slots
-//   L <= 3072   a 512-thread workgroup, 4096 slots
-//   L <= 8192   a 1024-thread workgroup, 10112 compact 8-byte slots (79 KiB,
-//               two workgroups a CU; the volume is gathered per distinct
-//               community at scan time)
+// compute unit holds many vertices.  Claim tables (8-byte slots: community
+// and weight sum; the claimer scores with the volume that came with its
+// entry) let every class run 8 wavefronts a SIMD: at most 20 KiB per
+// 256-thread, 40 KiB per 512-thread and 80 KiB per 1024-thread workgroup.
+// Sizes that are not a power of two hash by a multiply-high reduction; keys
+// probe by double hashing; a row of L entries uses about 3L of the slots
+// (table_pct), at least L + 1, so a table never fills.
+//   L <= 4      4 lanes per vertex, LDS table of 16 slots
+//   L <= 8      8 lanes, 32 slots
+//   L <= 32     16 lanes, 128 slots
+//   L <= 128    32 lanes, 312 slots
+//   L <= 256    a wavefront, 624 slots
+//   L <= 512    128 lanes, 1248 slots
+//   L <= 1024   a 256-thread workgroup, 2496 slots
+//   L <= 2048   a 512-thread workgroup, 5056 slots
+//   L <= 3072   a 512-thread workgroup, 5056 slots
+//   L <= 8192   a 1024-thread workgroup, 10112 slots (79 KiB, two
+//               workgroups a CU)
 //   L >  8192   P = ceil(L / part_keys) workgroups per vertex;
 //               workgroup p aggregates the communities of hash partition p in
 //               an LDS table; partial results are merged per vertex, and all P
@@ -657,17 +658,20 @@ __global__ __launch_bounds__(FUSED_BS) void k_move_fused(MoveArgs a, FusedMap fm
         const int32_t k = item - fm.item_first[q];
         const int64_t r0 = fm.row_first[q], r1 = fm.row_end[q];
 #define LV_FUSED_CASE(C, G, SL)                                                                                    \
-    case C: claim_rows<C, FUSED_BS, G, SL>(a, ecm, r0 + (int64_t)k * (FUSED_BS / G), r1, s_tab, rs, rc, rw); break;
+    case C:                                                                                                        \
+        static_assert((FUSED_BS / G) * SL <= FUSED_SLOTS, "the fused kernel's LDS holds every class's tables");    \
+        claim_rows<C, FUSED_BS, G, SL>(a, ecm, r0 + (int64_t)k * (FUSED_BS / G), r1, s_tab, rs, rc, rw);            \
+        break;
         switch (fm.cls[q]) {
-            LV_FUSED_CASE(CLS_L4, 4, 8)
-            LV_FUSED_CASE(CLS_L8, 8, 16)
-            LV_FUSED_CASE(CLS_L32, 16, 64)
-            LV_FUSED_CASE(CLS_L128, 32, 208)
-            LV_FUSED_CASE(CLS_L256, 64, 424)
-            LV_FUSED_CASE(CLS_L512, 128, 848)
-            LV_FUSED_CASE(CLS_L1K, 256, 1696)
-            LV_FUSED_CASE(CLS_L2K, 512, 3392)
-            LV_FUSED_CASE(CLS_L3K, 512, 4096)
+            LV_FUSED_CASE(CLS_L4, 4, L4_SLOTS)
+            LV_FUSED_CASE(CLS_L8, 8, L8_SLOTS)
+            LV_FUSED_CASE(CLS_L32, 16, L32_SLOTS)
+            LV_FUSED_CASE(CLS_L128, 32, L128_SLOTS)
+            LV_FUSED_CASE(CLS_L256, 64, L256_SLOTS)
+            LV_FUSED_CASE(CLS_L512, 128, L512_SLOTS)
+            LV_FUSED_CASE(CLS_L1K, 256, L1K_SLOTS)
+            LV_FUSED_CASE(CLS_L2K, 512, L2K_SLOTS)
+            LV_FUSED_CASE(CLS_L3K, 512, L3K_SLOTS)
             LV_FUSED_CASE(CLS_L8K, 1024, L8K_SLOTS)
             default: break;
         }
@@ -1587,21 +1591,15 @@ hipError_t launch_move_fused(const MoveArgs& a, const FusedMap& fm, SweepCtl* ct
 hipError_t launch_move_class(int cls, bool singleton, bool async, const MoveArgs& a, hipStream_t s)
 {
     switch (cls) {
-    case CLS_L4: return launch_move_t<CLS_L4, 256, 4, 8>(singleton, async, a, s);
-    case CLS_L8: return launch_move_t<CLS_L8, 256, 8, 16>(singleton, async, a, s);
-    case CLS_L32: return launch_move_t<CLS_L32, 256, 16, 64>(singleton, async, a, s);
-    // 1664-1696 slots of 12 bytes per 256-thread workgroup (<= 20 KiB), 3392 per
-    // 512-thread workgroup (<= 40 KiB): eight wavefronts a SIMD.  Rows of
-    // 2049-3072 entries keep 4096 slots (six wavefronts a SIMD): at their load
-    // a 3392-slot table probes longer than the extra workgroup gains.
-    case CLS_L128: return launch_move_t<CLS_L128, 256, 32, 208>(singleton, async, a, s);
-    case CLS_L256: return launch_move_t<CLS_L256, 256, 64, 424>(singleton, async, a, s);
-    case CLS_L512: return launch_move_t<CLS_L512, 256, 128, 848>(singleton, async, a, s);
-    case CLS_L1K: return launch_move_t<CLS_L1K, 256, 256, 1696>(singleton, async, a, s);
-    case CLS_L2K: return launch_move_t<CLS_L2K, 512, 512, 3392>(singleton, async, a, s);
-    case CLS_L3K: return launch_move_t<CLS_L3K, 512, 512, 4096>(singleton, async, a, s);
-    // 10112 8-byte slots (79 KiB): two workgroups fit a CU's 160 KiB, and every row of the class
-    // (at most 8192 entries) leaves free slots
+    case CLS_L4: return launch_move_t<CLS_L4, 256, 4, L4_SLOTS>(singleton, async, a, s);
+    case CLS_L8: return launch_move_t<CLS_L8, 256, 8, L8_SLOTS>(singleton, async, a, s);
+    case CLS_L32: return launch_move_t<CLS_L32, 256, 16, L32_SLOTS>(singleton, async, a, s);
+    case CLS_L128: return launch_move_t<CLS_L128, 256, 32, L128_SLOTS>(singleton, async, a, s);
+    case CLS_L256: return launch_move_t<CLS_L256, 256, 64, L256_SLOTS>(singleton, async, a, s);
+    case CLS_L512: return launch_move_t<CLS_L512, 256, 128, L512_SLOTS>(singleton, async, a, s);
+    case CLS_L1K: return launch_move_t<CLS_L1K, 256, 256, L1K_SLOTS>(singleton, async, a, s);
+    case CLS_L2K: return launch_move_t<CLS_L2K, 512, 512, L2K_SLOTS>(singleton, async, a, s);
+    case CLS_L3K: return launch_move_t<CLS_L3K, 512, 512, L3K_SLOTS>(singleton, async, a, s);
     case CLS_L8K: return launch_move_t<CLS_L8K, 1024, 1024, L8K_SLOTS>(singleton, async, a, s);
     default: return hipErrorInvalidValue;
     }
