@@ -1443,16 +1443,31 @@ __global__ __launch_bounds__(256) void k_cache_refresh(int32_t tiles, const int4
         if (threadIdx.x == 0) s_off[0] = 0;
         __syncthreads();
         const int32_t total = s_off[c];
-        for (int32_t f = (int32_t)threadIdx.x; f < total; f += 256) {
-            int32_t lo = 0, hi = c - 1;  // the row q with s_off[q] <= f < s_off[q + 1]
-            while (lo < hi) {
-                const int32_t mid = (lo + hi + 1) >> 1;
-                if (s_off[mid] <= f) lo = mid; else hi = mid - 1;
+        // RU entries a thread per round: their rows found, then all their
+        // reverse-map loads in flight, then their writes
+        constexpr int RU = 4;
+        for (int32_t f0 = (int32_t)threadIdx.x; f0 < total; f0 += 256 * RU) {
+            int32_t e[RU], re[RU];
+            int2 pr[RU];
+#pragma unroll
+            for (int u = 0; u < RU; ++u) {
+                const int32_t f = f0 + u * 256;
+                e[u] = -1;
+                if (f >= total) continue;
+                int32_t lo = 0, hi = c - 1;  // the row q with s_off[q] <= f < s_off[q + 1]
+                while (lo < hi) {
+                    const int32_t mid = (lo + hi + 1) >> 1;
+                    if (s_off[mid] <= f) lo = mid; else hi = mid - 1;
+                }
+                const int4 r = s_row[lo];
+                e[u] = r.x + (f - s_off[lo]);
+                pr[u] = make_int2(r.z, r.w);
             }
-            const int4 r = s_row[lo];
-            const int32_t e = r.x + (f - s_off[lo]);
-            const int32_t re = __builtin_nontemporal_load(&rev[e]);
-            if (re != e) ce[re] = make_int2(r.z, r.w);
+#pragma unroll
+            for (int u = 0; u < RU; ++u) re[u] = e[u] >= 0 ? __builtin_nontemporal_load(&rev[e[u]]) : -1;
+#pragma unroll
+            for (int u = 0; u < RU; ++u)
+                if (e[u] >= 0 && re[u] != e[u]) ce[re[u]] = pr[u];
         }
         __syncthreads();  // s_row and s_off are reused by the next tile
     }
