@@ -159,6 +159,16 @@ __device__ __forceinline__ int64_t move_slot(const MoveArgs& a, int32_t i)
     return (a.gid ? (int64_t)a.gid[i] * a.max_sweeps : 0) + a.ctl->sweep;
 }
 
+// Louvain's integer score M*W - k_i*Sigma (Eq. 1 up to the factor 2/M^2).
+// Every factor lies in [0, 2^31): weights and volumes are non-negative and
+// the library rejects a total volume of 2^31 or more.  So each product is one
+// 32 x 32 -> 64-bit multiply, exact, where int64 operands would cost a full
+// 64-bit one.
+__device__ __forceinline__ int64_t louvain_score(int64_t M, int64_t W, int64_t ki, int64_t vol)
+{
+    return (int64_t)((uint64_t)(uint32_t)M * (uint32_t)W) - (int64_t)((uint64_t)(uint32_t)ki * (uint32_t)vol);
+}
+
 // Asynchronous decision of vertex i (own community A read when its table was
 // built; only i changes its own label): against the live volume of A, move
 // at once if the best community beats staying (no direction gate), updating
@@ -170,7 +180,7 @@ __device__ __forceinline__ bool decide_apply(const MoveArgs& a, int64_t pos, int
     if (best_c != INT32_MAX) {
         const bool louvain = a.mode == MODE_LOUVAIN;
         const int64_t sA = louvain ? (int64_t)a.live_sigma[A] : 0;
-        const int64_t stay = louvain ? M * w_own - ki * (sA - ki) : (int64_t)w_own;
+        const int64_t stay = louvain ? louvain_score(M, w_own, ki, sA - ki) : (int64_t)w_own;
         mover = best_s > stay;
     }
     if (mover) {
@@ -190,7 +200,7 @@ __device__ __forceinline__ void decide_store(const MoveArgs& a, int64_t pos, int
     bool mover = false;
     if (best_c != INT32_MAX) {
         const bool louvain = a.mode == MODE_LOUVAIN;
-        const int64_t stay = louvain ? M * w_own - ki * ((int64_t)sA - ki) : (int64_t)w_own;
+        const int64_t stay = louvain ? louvain_score(M, w_own, ki, (int64_t)sA - ki) : (int64_t)w_own;
         const bool dir_ok = sweep_dir(a.ctl) == DIR_DOWN ? best_c < A : best_c > A;
         mover = best_s > stay && dir_ok;
     }
@@ -234,7 +244,7 @@ __device__ __forceinline__ void score_entries_singleton(const MoveArgs& a, int32
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
             if (jj[u] == i) continue;
-            const int64_t s = louvain ? M * ww[u] - ki * (int64_t)cc[u].y : (int64_t)ww[u];
+            const int64_t s = louvain ? louvain_score(M, ww[u], ki, cc[u].y) : (int64_t)ww[u];
             if (better(s, cc[u].x, best_s, best_c)) { best_s = s; best_c = cc[u].x; }
         }
     }
@@ -352,7 +362,7 @@ __device__ __forceinline__ void scan_table(const MoveArgs& a, const int32_t* key
             if (C == EMPTY_KEY) continue;
             const int32_t W = val[t];
             if (C == A) { w_own = W; continue; }
-            const int64_t s = louvain ? M * W - ki * (int64_t)sig[t] : (int64_t)W;
+            const int64_t s = louvain ? louvain_score(M, W, ki, sig[t]) : (int64_t)W;
             if (better(s, C, best_s, best_c)) { best_s = s; best_c = C; }
         }
     } else {
@@ -372,7 +382,7 @@ __device__ __forceinline__ void scan_table(const MoveArgs& a, const int32_t* key
             for (int u = 0; u < SU; ++u) {
                 if (Cs[u] == EMPTY_KEY) continue;
                 if (Cs[u] == A) { w_own = Ws[u]; continue; }
-                const int64_t s = louvain ? M * Ws[u] - ki * (int64_t)Ss[u] : (int64_t)Ws[u];
+                const int64_t s = louvain ? louvain_score(M, Ws[u], ki, Ss[u]) : (int64_t)Ws[u];
                 if (better(s, Cs[u], best_s, best_c)) { best_s = s; best_c = Cs[u]; }
             }
         }
@@ -586,7 +596,7 @@ __device__ __forceinline__ void claim_rows(const MoveArgs& a, int ecm, int64_t v
         const int32_t W = (int32_t)(uint32_t)tab[slot[u]];
         const int32_t C = cc[u].x;
         if (C == A) { w_own = W; continue; }
-        const int64_t sc = louvain ? M * W - ki * (int64_t)cc[u].y : (int64_t)W;
+        const int64_t sc = louvain ? louvain_score(M, W, ki, cc[u].y) : (int64_t)W;
         if (better(sc, C, best_s, best_c)) { best_s = sc; best_c = C; }
     }
     if constexpr (G <= WAVE) {
@@ -860,7 +870,7 @@ __global__ __launch_bounds__(BS) void k_hub_part_claim(MoveArgs a, HubArgs h)
             const int32_t W = (int32_t)(uint32_t)s_tab[slot[u]];
             const int32_t C = cc[u].x;
             if (C == A) { w_own = W; continue; }
-            const int64_t sc = louvain ? M * W - ki * (int64_t)cc[u].y : (int64_t)W;
+            const int64_t sc = louvain ? louvain_score(M, W, ki, cc[u].y) : (int64_t)W;
             if (better(sc, C, best_s, best_c)) { best_s = sc; best_c = C; }
         }
     }
@@ -1052,7 +1062,7 @@ __global__ __launch_bounds__(FBS) void k_fb_scan(MoveArgs a, HubArgs h)
         tab[2 * t] = EMPTY_KEY;
         tab[2 * t + 1] = 0;
         if (C == A) { w_own = W; continue; }
-        const int64_t s = louvain ? vertex_M(a, i) * W - ki * (int64_t)a.sigma[C] : (int64_t)W;
+        const int64_t s = louvain ? louvain_score(vertex_M(a, i), W, ki, a.sigma[C]) : (int64_t)W;
         if (better(s, C, best_s, best_c)) { best_s = s; best_c = C; }
     }
     block_reduce_best<FBS>(best_s, best_c, w_own, rs, rc, rw);
