@@ -275,12 +275,14 @@ __device__ __forceinline__ void lds_insert(int32_t* key, int32_t* val, int32_t* 
                                            int32_t W, int32_t S)
 {
     Probe p = probe_start<MOD>(C, mask);
-    for (;;) {
-        const int32_t prev = atomicCAS(&key[p.h], EMPTY_KEY, C);
-        if constexpr (SIG) if (prev == EMPTY_KEY) sig[p.h] = S;
-        if (prev == EMPTY_KEY || prev == C) { atomicAdd(&val[p.h], W); return; }
+    int32_t prev;
+    for (;;) {  // one exit test per probe; the stores after the loop
+        prev = atomicCAS(&key[p.h], EMPTY_KEY, C);
+        if (prev == EMPTY_KEY || prev == C) break;
         probe_next<MOD>(p, mask);
     }
+    if constexpr (SIG) if (prev == EMPTY_KEY) sig[p.h] = S;
+    atomicAdd(&val[p.h], W);
 }
 
 // Make a group's LDS writes visible to the whole group.  A group within one

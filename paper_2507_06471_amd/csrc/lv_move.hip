@@ -437,15 +437,17 @@ __device__ __forceinline__ int32_t claim_or_add(unsigned long long* tab, uint32_
 {
     const unsigned long long mine = ((unsigned long long)(uint32_t)C << 32) | (uint32_t)W;
     Probe p = probe_start<MOD>(C, mask);
+    // one exit test per probe (an empty slot or the key), the add after the
+    // loop: the loop body stays free of nested branches
+    unsigned long long prev;
     for (;;) {
-        const unsigned long long prev = atomicCAS(&tab[p.h], EMPTY_SLOT, mine);
-        if (prev == EMPTY_SLOT) return (int32_t)p.h;
-        if ((int32_t)(prev >> 32) == C) {
-            atomicAdd(&tab[p.h], (unsigned long long)(uint32_t)W);
-            return -1;
-        }
+        prev = atomicCAS(&tab[p.h], EMPTY_SLOT, mine);
+        if (prev == EMPTY_SLOT || (int32_t)(prev >> 32) == C) break;
         probe_next<MOD>(p, mask);
     }
+    if (prev == EMPTY_SLOT) return (int32_t)p.h;
+    atomicAdd(&tab[p.h], (unsigned long long)(uint32_t)W);
+    return -1;
 }
 
 // Kinds of the generic move kernel: the first sweep of a level (every
@@ -793,16 +795,20 @@ __device__ __forceinline__ int32_t claim_or_add_bounded(unsigned long long* tab,
 {
     const unsigned long long mine = ((unsigned long long)(uint32_t)C << 32) | (uint32_t)W;
     Probe p = probe_start<false>(C, mask);  // a power-of-two table: odd stride, every slot within mask + 1 probes
+    unsigned long long prev = 0;
+    bool placed = false;
     for (uint32_t probes = 0; probes <= mask; ++probes) {
-        const unsigned long long prev = atomicCAS(&tab[p.h], EMPTY_SLOT, mine);
-        if (prev == EMPTY_SLOT) return (int32_t)p.h;
-        if ((int32_t)(prev >> 32) == C) {
-            atomicAdd(&tab[p.h], (unsigned long long)(uint32_t)W);
-            return -1;
-        }
+        prev = atomicCAS(&tab[p.h], EMPTY_SLOT, mine);
+        placed = prev == EMPTY_SLOT || (int32_t)(prev >> 32) == C;
+        if (placed) break;
         probe_next<false>(p, mask);
     }
-    ok = false;
+    if (!placed) {
+        ok = false;
+        return -1;
+    }
+    if (prev == EMPTY_SLOT) return (int32_t)p.h;
+    atomicAdd(&tab[p.h], (unsigned long long)(uint32_t)W);
     return -1;
 }
 
