@@ -348,8 +348,8 @@ Tune make_tune(const lv_tuning* t)
 {
     Tune u;
     for (int c = 0; c < NUM_CLS; ++c) u.bounds[c] = CLS_CAP[c];
-    // default partition mode: bucketed, 768 expected communities per 2048-slot table
-    u.part_keys = 768;
+    // default partition mode: bucketed, 1024 expected communities per 2048-slot table
+    u.part_keys = 1024;
     u.part_slots = 2048;
     u.bucketed = 1;
     u.order_min = (int64_t)1 << 22;
@@ -1453,7 +1453,7 @@ lv_status autotune(lv_graph* g, const Params& base, lv_tuning* best, double* bes
         {&lv_tuning::wave_max, {128}},
         {&lv_tuning::block_max, {3072, 2048}},
         {&lv_tuning::hub_mode, {1}},
-        {&lv_tuning::part_keys, {512, 1024}},
+        {&lv_tuning::part_keys, {768, 1536}},
         {&lv_tuning::hub_chunk, {1024, 4096}},
         {&lv_tuning::part_slots, {1024}},
         {&lv_tuning::table_pct, {150, 200, 400}},
