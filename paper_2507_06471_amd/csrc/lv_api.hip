@@ -884,7 +884,7 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
                                  mode == MODE_LPA ? nullptr : ws.sigma.as<int32_t>(), ctl, ws.gmoves.as<uint32_t>(),
                                  S, s));
             if (use_ec)
-                HIP_TRY(launch_pairs_changed(active, nonhub, ws.rows.as<int4>(), ws.comm.as<int32_t>(),
+                HIP_TRY(launch_pairs_changed(active, nonhub, act_verts, G.off, ws.comm.as<int32_t>(),
                                              ws.sigma.as<int32_t>(), ws.cs.as<int2>(), ws.chg.as<uint8_t>(),
                                              ws.rlist.as<int4>(), ws.rcnt.as<int32_t>(), mode, ctl, s));
             else

@@ -280,14 +280,14 @@ hipError_t launch_mark_movers(const int4* rows, const int32_t* dec, int32_t m, c
 hipError_t launch_hub_mark(const MoveArgs& a, const HubArgs& h, int32_t* mark, hipStream_t s);
 hipError_t launch_pairs(int32_t n, const int32_t* verts, const int32_t* comm, const int32_t* sigma, int2* cs,
                         const SweepCtl* ctl, hipStream_t s);
-// As launch_pairs over the m listed vertices rows[0..m) (class order), also
+// As launch_pairs over the m listed vertices verts[0..m) (class order), also
 // recording in chg[t] whether slot t's pair changed (LPA: its label) and
 // adding the changed rows' entries to ctl->chg_entries.  The changed rows of
 // slots below `nonhub` are listed per 256-slot tile: (row begin, length, new
 // pair) at list[tile * 256 + i] for i < cnt[tile].
-hipError_t launch_pairs_changed(int32_t m, int32_t nonhub, const int4* rows, const int32_t* comm, const int32_t* sigma,
-                                int2* cs, uint8_t* chg, int4* list, int32_t* cnt, int mode, SweepCtl* ctl,
-                                hipStream_t s);
+hipError_t launch_pairs_changed(int32_t m, int32_t nonhub, const int32_t* verts, const int32_t* off,
+                                const int32_t* comm, const int32_t* sigma, int2* cs, uint8_t* chg, int4* list,
+                                int32_t* cnt, int mode, SweepCtl* ctl, hipStream_t s);
 // Entry-cache refresh when the next sweep reads the cache: for every listed
 // changed row (list/cnt of launch_pairs_changed over m slots), ce[rev[e]] =
 // its new pair for each non-loop entry e of the row.  Hubs: through their

@@ -1377,10 +1377,12 @@ __global__ void k_pairs(int32_t n, const int32_t* verts, const int32_t* comm, co
 // rows below the hub class, (row begin, length, new pair), at the tile's
 // own place in `list`, with their number in cnt[tile]: the refresh reads
 // only those.
-__global__ __launch_bounds__(256) void k_pairs_changed(int32_t m, int32_t nonhub, const int4* rows,
-                                                       const int32_t* comm, const int32_t* sigma, int2* cs,
-                                                       uint8_t* chg, int4* list, int32_t* cnt, int mode,
-                                                       SweepCtl* ctl)
+// The vertex of slot t is verts[t]; its row bounds are read only if its
+// pair changed.
+__global__ __launch_bounds__(256) void k_pairs_changed(int32_t m, int32_t nonhub, const int32_t* __restrict__ verts,
+                                                       const int32_t* __restrict__ off, const int32_t* comm,
+                                                       const int32_t* sigma, int2* cs, uint8_t* chg, int4* list,
+                                                       int32_t* cnt, int mode, SweepCtl* ctl)
 {
     __shared__ unsigned long long red[4];
     __shared__ int32_t w_cnt[4];
@@ -1391,16 +1393,19 @@ __global__ __launch_bounds__(256) void k_pairs_changed(int32_t m, int32_t nonhub
         bool ch = false;
         int4 rec = make_int4(0, 0, 0, 0);
         if (t < m) {
-            const int4 r = rows[t];
-            const int32_t c = comm[r.x];
+            const int32_t v = verts[t];
+            const int32_t c = comm[v];
             const int2 nw = make_int2(c, sigma[c]);
-            const int2 old = cs[r.x];
+            const int2 old = cs[v];
             const bool lab = nw.x != old.x, pair = lab || nw.y != old.y;
-            if (pair) cs[r.x] = nw;
+            if (pair) cs[v] = nw;
             ch = mode == MODE_LOUVAIN ? pair : lab;
-            if (ch) tot += (unsigned long long)(r.z - r.y);
+            if (ch) {
+                const int32_t b0 = off[v], b1 = off[v + 1];
+                tot += (unsigned long long)(b1 - b0);
+                rec = make_int4(b0, b1 - b0, nw.x, nw.y);
+            }
             chg[t] = ch ? 1 : 0;
-            rec = make_int4(r.y, r.z - r.y, nw.x, nw.y);
         }
         const bool listed = ch && t < nonhub;
         const uint64_t bal = __ballot(listed);
@@ -1506,13 +1511,13 @@ __global__ __launch_bounds__(256) void k_hub_cache_refresh(MoveArgs a, HubArgs h
 
 }  // namespace
 
-hipError_t launch_pairs_changed(int32_t m, int32_t nonhub, const int4* rows, const int32_t* comm, const int32_t* sigma,
-                                int2* cs, uint8_t* chg, int4* list, int32_t* cnt, int mode, SweepCtl* ctl,
-                                hipStream_t s)
+hipError_t launch_pairs_changed(int32_t m, int32_t nonhub, const int32_t* verts, const int32_t* off,
+                                const int32_t* comm, const int32_t* sigma, int2* cs, uint8_t* chg, int4* list,
+                                int32_t* cnt, int mode, SweepCtl* ctl, hipStream_t s)
 {
     if (m <= 0) return hipSuccess;
-    k_pairs_changed<<<grid_for(m, 256, 8192), 256, 0, s>>>(m, nonhub, rows, comm, sigma, cs, chg, list, cnt, mode,
-                                                           ctl);
+    k_pairs_changed<<<grid_for(m, 256, 8192), 256, 0, s>>>(m, nonhub, verts, off, comm, sigma, cs, chg, list, cnt,
+                                                           mode, ctl);
     return hipGetLastError();
 }
 hipError_t launch_cache_refresh(int32_t m, const int4* list, const int32_t* cnt, const int32_t* rev, int2* ce,
