@@ -560,7 +560,13 @@ __device__ __forceinline__ void claim_rows(const MoveArgs& a, int ecm, int64_t v
     const uint32_t want = max(L + 1u, (uint32_t)(((uint64_t)L * (uint32_t)a.table_pct) / 100u) + (POW2 ? 0u : 1u));
     const uint32_t T = POW2 ? min((uint32_t)SLOTS, pow2_at_least(want)) : min((uint32_t)SLOTS, want);
     unsigned long long* tab = s_tab + g * SLOTS;
-    for (uint32_t t = lane; t < T; t += G) tab[t] = EMPTY_SLOT;
+    {  // cleared two slots a store: every group's table starts 16-byte aligned (SLOTS is even), and
+       // ceil(T / 2) pairs stay within its SLOTS (T < SLOTS, or T == SLOTS and even)
+        static_assert(SLOTS % 2 == 0, "claim tables are cleared in pairs of slots");
+        ulonglong2* tab2 = reinterpret_cast<ulonglong2*>(tab);
+        const ulonglong2 empty2 = make_ulonglong2(EMPTY_SLOT, EMPTY_SLOT);
+        for (uint32_t t = lane; t < (T + 1u) / 2u; t += G) tab2[t] = empty2;
+    }
     int2 cc[ME];
     int32_t ww[ME], slot[ME];
     load_pairs<G, ME>(a, i, beg + lane, end, ecm, cc, ww);
@@ -626,7 +632,7 @@ __device__ __forceinline__ void claim_rows(const MoveArgs& a, int ecm, int64_t v
 template <int CLS, int BS, int G, int SLOTS>
 __global__ __launch_bounds__(BS) void k_move_claim(MoveArgs a)
 {
-    __shared__ unsigned long long s_tab[(BS / G) * SLOTS];
+    __shared__ __align__(16) unsigned long long s_tab[(BS / G) * SLOTS];
     __shared__ int64_t rs[BS / WAVE];
     __shared__ int32_t rc[BS / WAVE], rw[BS / WAVE];
     if (a.ctl->all_done) return;
@@ -646,7 +652,7 @@ constexpr int FUSED_SLOTS = L8K_SLOTS;  // the largest (BS/G) * SLOTS of the cla
 constexpr int FUSED_CHUNK = 16;         // work items a workgroup takes per atomic
 __global__ __launch_bounds__(FUSED_BS) void k_move_fused(MoveArgs a, FusedMap fm, SweepCtl* ctl)
 {
-    __shared__ unsigned long long s_tab[FUSED_SLOTS];
+    __shared__ __align__(16) unsigned long long s_tab[FUSED_SLOTS];
     __shared__ int64_t rs[FUSED_BS / WAVE];
     __shared__ int32_t rc[FUSED_BS / WAVE], rw[FUSED_BS / WAVE];
     __shared__ int32_t s_item;
