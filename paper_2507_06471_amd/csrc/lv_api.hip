@@ -714,7 +714,12 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
     HIP_TRY(ws.gdone.ensure(sizeof(int32_t) * (size_t)G.G));
     HIP_TRY(ws.gsweeps.ensure(sizeof(int32_t) * (size_t)G.G));
     HIP_TRY(ws.gmoves.ensure(sizeof(uint32_t) * (size_t)G.G * (size_t)S));
-    LV_TRY(ensure_pinned(g, std::max<size_t>(4096, (sizeof(int32_t) + sizeof(uint32_t) * S) * (size_t)G.G + 64)));
+    // pinned: the per-graph move and sweep counts and the control block read
+    // back at the end, then (at poll_off) the early-exit flag the sweeps of a
+    // large level copy out as they go
+    const size_t poll_off = (((sizeof(int32_t) + sizeof(uint32_t) * S) * (size_t)G.G + 64 + sizeof(SweepCtl)) + 63) &
+                            ~(size_t)63;
+    LV_TRY(ensure_pinned(g, std::max<size_t>(4096, poll_off + 64)));
 
     // degree classes: classify, then one stable radix pass groups vertices by class
     HIP_TRY(launch_classify(n, G.off, p.tune.bounds, ws.cls.as<uint32_t>(), ws.vert.as<int32_t>(), s));
@@ -908,18 +913,27 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
     // the sweeps' graph lives until the level's results are read back (one
     // stream synchronization per level); on an early return the stream is
     // drained before the graph is destroyed
+    constexpr int POLL_LAG = 2;  // replays in flight while the host waits for the oldest
     struct GraphHolder {
         hipStream_t s;
         hipGraph_t gr = nullptr;
         hipGraphExec_t ex = nullptr;
+        hipEvent_t ev[POLL_LAG] = {};
         ~GraphHolder()
         {
-            if (!ex && !gr) return;
-            (void)hipStreamSynchronize(s);
+            if (ex || gr) (void)hipStreamSynchronize(s);
             if (ex) (void)hipGraphExecDestroy(ex);
             if (gr) (void)hipGraphDestroy(gr);
+            for (hipEvent_t e : ev)
+                if (e) (void)hipEventDestroy(e);
         }
     } held{s};
+    const bool poll = use_graph && S > 2 && G.nnz >= ((int64_t)1 << 20);
+    int32_t* h_flag = (int32_t*)((char*)g->pinned + poll_off);
+    if (poll) {
+        *h_flag = 0;
+        for (hipEvent_t& e : held.ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    }
     Timer ph;
     ph.s = s;
     hipEvent_t p0{}, p1{};
@@ -933,15 +947,34 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
         if (S > 1) {
             hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
             if (e != hipSuccess) { set_error("hipStreamBeginCapture", e); return from_hip(e); }
-            const lv_status st = launch_sweep(false, nullptr);
+            // On a large level each replay also copies the early-exit flag to
+            // pinned memory, so that the host stops replaying once the level
+            // has stopped (a stopped level's replays are launches that return
+            // at once, about 0.2 ms each at R-MAT 24's size).
+            lv_status st = launch_sweep(false, nullptr);
+            if (st == LV_OK && poll) {
+                const hipError_t ec = hipMemcpyAsync(h_flag, &ctl->all_done, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+                if (ec != hipSuccess) { set_error("hipMemcpyAsync", ec); st = from_hip(ec); }
+            }
             e = hipStreamEndCapture(s, &held.gr);
             LV_TRY(st);
             if (e != hipSuccess) { set_error("hipStreamEndCapture", e); return from_hip(e); }
             e = hipGraphInstantiate(&held.ex, held.gr, nullptr, nullptr, 0);
             if (e != hipSuccess) { set_error("hipGraphInstantiate", e); return from_hip(e); }
-            for (int32_t sw = 2; sw <= S; ++sw) {
+            // with POLL_LAG replays queued, wait for the oldest and stop once it
+            // found the level stopped: every later replay would return at once
+            for (int32_t sw = 2, launched = 0; sw <= S; ++sw, ++launched) {
+                if (poll && launched >= POLL_LAG) {
+                    e = hipEventSynchronize(held.ev[launched % POLL_LAG]);
+                    if (e != hipSuccess) { set_error("hipEventSynchronize", e); return from_hip(e); }
+                    if (*(volatile int32_t*)h_flag) break;
+                }
                 e = hipGraphLaunch(held.ex, s);
                 if (e != hipSuccess) { set_error("hipGraphLaunch", e); return from_hip(e); }
+                if (poll) {
+                    e = hipEventRecord(held.ev[launched % POLL_LAG], s);
+                    if (e != hipSuccess) { set_error("hipEventRecord", e); return from_hip(e); }
+                }
             }
         }
         HIP_TRY(ph.mark(&p1));
