@@ -998,7 +998,9 @@ lv_status run_sweeps(lv_graph* g, const LevelGraph& G, int mode, const Params& p
     HIP_TRY(hipMemcpyAsync(h_sweeps, ws.gsweeps.p, sizeof(int32_t) * (size_t)G.G, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(h_ctl, ws.ctl.p, sizeof(SweepCtl), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    ws.hub_table_clean = true;  // every fallback scan of the level has run
+    // every fallback scan of this level has run: a table its hubs used is
+    // clean again (a level without hubs leaves the flag as it was)
+    if (hubs.nhubs > 0) ws.hub_table_clean = true;
     if (!timing) out.sweep_ms = elapsed(p0, p1);
     out.cached_sweeps = use_ec ? h_ctl->ec_reads : 0;
     out.refreshed = use_ec ? (int64_t)h_ctl->refreshed : 0;
