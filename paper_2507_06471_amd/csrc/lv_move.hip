@@ -698,6 +698,53 @@ __global__ __launch_bounds__(FUSED_BS) void k_move_fused(MoveArgs a, FusedMap fm
     }
 }
 
+// Later synchronous sweeps of the class of at most ME = 4 entries: one
+// lane per row and no table.  The lane holds its row's pairs in
+// registers; entry u sums the weights of every entry of the row with its
+// community, and the first entry of each community scores it.
+constexpr int REG_BS = 256;
+template <int CLS>
+__global__ __launch_bounds__(REG_BS) void k_move_reg(MoveArgs a)
+{
+    constexpr int ME = CLS_CAP[CLS];
+    static_assert(ME >= 1 && ME <= 4, "rows held in registers");
+    if (a.ctl->all_done) return;
+    const int64_t vi = (int64_t)blockIdx.x * REG_BS + threadIdx.x;
+    if (vi >= a.nverts) return;
+    const int4 row = a.rows[vi];
+    const int32_t i = row.x;
+    if (vertex_frozen(a, i) || vertex_skipped(a, i)) {
+        a.dec[vi] = -1;
+        return;
+    }
+    const int2 self = a.cs[i];
+    const int32_t A = self.x;
+    const int64_t ki = row.w;
+    const int64_t M = vertex_M(a, i);
+    int2 cc[ME];
+    int32_t ww[ME];
+    load_pairs<1, ME>(a, i, row.y, row.z, entry_mode(a), cc, ww);
+    const bool louvain = a.mode == MODE_LOUVAIN;
+    int64_t best_s = INT64_MIN;
+    int32_t best_c = INT32_MAX, w_own = 0;
+#pragma unroll
+    for (int u = 0; u < ME; ++u) {
+        const int32_t C = cc[u].x;
+        bool first = C != EMPTY_KEY;
+        int32_t W = 0;
+#pragma unroll
+        for (int v = 0; v < ME; ++v) {
+            if (cc[v].x == C) W += ww[v];
+            if (v < u && cc[v].x == C) first = false;
+        }
+        if (!first) continue;
+        if (C == A) { w_own = W; continue; }
+        const int64_t sc = louvain ? louvain_score(M, W, ki, cc[u].y) : (int64_t)W;
+        if (better(sc, C, best_s, best_c)) { best_s = sc; best_c = C; }
+    }
+    decide_store(a, vi, A, self.y, ki, M, best_s, best_c, w_own);
+}
+
 template <int CLS, int BS, int G, int SLOTS>
 hipError_t launch_move_t(bool singleton, bool async, const MoveArgs& a, hipStream_t s)
 {
@@ -707,6 +754,8 @@ hipError_t launch_move_t(bool singleton, bool async, const MoveArgs& a, hipStrea
     const unsigned grid = (unsigned)((a.nverts + NG - 1) / NG);
     if (async) k_move<CLS, BS, G, SLOTS, MK_ASYNC><<<grid, BS, 0, s>>>(a);
     else if (singleton) k_move<CLS, BS, G, SLOTS, MK_FIRST><<<grid, BS, 0, s>>>(a);
+    else if constexpr (CLS_CAP[CLS] <= 4)  // the 8-entry class was slower this way on graphs of short rows
+        k_move_reg<CLS><<<(unsigned)((a.nverts + REG_BS - 1) / REG_BS), REG_BS, 0, s>>>(a);
     else k_move_claim<CLS, BS, G, SLOTS><<<grid, BS, 0, s>>>(a);
     return hipGetLastError();
 }
