@@ -19,7 +19,8 @@
 // Sizes that are not a power of two hash by a multiply-high reduction; keys
 // probe by double hashing; a row of L entries uses about 3L of the slots
 // (table_pct), at least L + 1, so a table never fills.
-//   L <= 4      4 lanes per vertex, LDS table of 16 slots
+//   L <= 4      later sweeps: one lane per vertex, no table (k_move_reg);
+//               first sweep: 4 lanes per vertex
 //   L <= 8      8 lanes, 32 slots
 //   L <= 32     16 lanes, 128 slots
 //   L <= 128    32 lanes, 312 slots
