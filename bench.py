@@ -112,14 +112,20 @@ KERNEL_SOURCES = ("lv_device.h", "lv_internal.h", "lv_move.hip")  # where the mo
 
 
 def kernel_source_digest() -> str:
-    """Digest of the move kernels' sources, to tell whether stored counters still describe them."""
+    """Digest of the move kernels' code, to tell whether stored counters still
+    describe them: comments and runs of white space are left out, so that a
+    change of wording alone keeps the record (the sources hold no comment
+    marker inside a string literal)."""
     import hashlib
+    import re
 
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2507_06471_amd", "csrc")
     for f in KERNEL_SOURCES:
-        with open(os.path.join(d, f), "rb") as fh:
-            h.update(f.encode() + b"\0" + fh.read())
+        with open(os.path.join(d, f)) as fh:
+            text = fh.read()
+        code = re.sub(r"//[^\n]*", "", re.sub(r"/\*.*?\*/", "", text, flags=re.S))
+        h.update(f.encode() + b"\0" + " ".join(code.split()).encode())
     return h.hexdigest()[:16]
 
 
@@ -772,7 +778,7 @@ def profile_summary(paths, out_dir, command, run_log=None):
         fh.write("# Per-dispatch HBM counters of the move kernels on R-MAT 24 (see move_kernels_rmat24_pmc.md);\n"
                  "# fetch_kib / write_kib: FETCH_SIZE / WRITE_SIZE averaged over the instrumented step's Louvain\n"
                  "# dispatches of the kernel, copy_*_factor: the counter's reading per byte of a plain 1 GiB copy;\n"
-                 "# src: digest of the kernels' sources when taken.\n")
+                 "# src: digest of the kernels' code (comments and white space left out) when taken.\n")
         for kern, nd, a, t, f, w, h, m in rows_out:
             slot = KERNEL_SLOT_OF(kern)
             if slot is None or f is None or w is None:

@@ -17,16 +17,16 @@ constexpr int DIR_UP = 1;
 // first class whose bound is >= L (L = 0 never moves and is skipped).
 enum MoveClass : int {
     CLS_NONE = 0,  // isolated
-    CLS_L4,        // L <= 4:     4 lanes per vertex, LDS table of 8 slots
-    CLS_L8,        // L <= 8:     8 lanes, 16 slots
-    CLS_L32,       // L <= 32:    16 lanes, 64 slots
-    CLS_L128,      // L <= 128:   32 lanes, 208 slots
-    CLS_L256,      // L <= 256:   one wavefront, 424 slots
-    CLS_L512,      // L <= 512:   128 lanes, 848 slots
-    CLS_L1K,       // L <= 1024:  one 256-thread workgroup, 1696 slots
-    CLS_L2K,       // L <= 2048:  one 512-thread workgroup, 3392 slots
-    CLS_L3K,       // L <= 3072:  one 512-thread workgroup, 4096 slots
-    CLS_L8K,       // L <= 8192:  one 1024-thread workgroup, 10112 compact slots (two workgroups a CU)
+    CLS_L4,        // L <= 4:     first sweep 4 lanes per vertex; later sweeps one lane, no table
+    CLS_L8,        // L <= 8:     8 lanes
+    CLS_L32,       // L <= 32:    8 lanes
+    CLS_L128,      // L <= 128:   32 lanes
+    CLS_L256,      // L <= 256:   one wavefront
+    CLS_L512,      // L <= 512:   128 lanes
+    CLS_L1K,       // L <= 1024:  one 256-thread workgroup
+    CLS_L2K,       // L <= 2048:  one 512-thread workgroup
+    CLS_L3K,       // L <= 3072:  one 512-thread workgroup
+    CLS_L8K,       // L <= 8192:  one 1024-thread workgroup (two workgroups a CU)
     CLS_HUB,       // several partition workgroups per vertex
     NUM_CLS
 };
@@ -41,7 +41,7 @@ constexpr int CLS_FIRST_WAVE = CLS_L256, CLS_FIRST_BLOCK = CLS_L512;
 // 20 KiB of tables per 256-thread workgroup, 40 KiB per 512-thread one,
 // 80 KiB per 1024-thread one (two workgroups of the 8192-entry class share a
 // CU's 160 KiB).  Every class's table exceeds its longest row.
-constexpr int32_t L4_SLOTS = 16, L8_SLOTS = 32, L32_SLOTS = 128, L128_SLOTS = 312, L256_SLOTS = 624,
+constexpr int32_t L4_SLOTS = 16, L8_SLOTS = 32, L32_SLOTS = 64, L128_SLOTS = 312, L256_SLOTS = 624,
                   L512_SLOTS = 1248, L1K_SLOTS = 2496, L2K_SLOTS = 5056, L3K_SLOTS = 5056;
 constexpr int32_t L8K_SLOTS = 10112;
 
