@@ -152,8 +152,7 @@ __global__ __launch_bounds__(TILE_BS) void k_tile_keys(int32_t n, const int32_t*
         int64_t r = lo;
         int64_t rend = off[r + 1];
         uint32_t a = (uint32_t)labels[r];
-#pragma unroll
-        for (int u = 0; u < AG_IT; ++u) {
+        for (int u = 0; u < AG_IT; ++u) {  // left to the compiler: the early exit keeps it rolled
             if (u >= m) break;
             const int64_t e = y0 + q0 + u;
             if (e >= rend) {
