@@ -18,7 +18,7 @@ constexpr int DIR_UP = 1;
 enum MoveClass : int {
     CLS_NONE = 0,  // isolated
     CLS_L4,        // L <= 4:     first sweep 4 lanes per vertex; later sweeps one lane, no table
-    CLS_L8,        // L <= 8:     8 lanes
+    CLS_L8,        // L <= 8:     4 lanes
     CLS_L32,       // L <= 32:    8 lanes
     CLS_L128,      // L <= 128:   32 lanes
     CLS_L256,      // L <= 256:   one wavefront

@@ -21,7 +21,7 @@
 // (table_pct), at least L + 1, so a table never fills.
 //   L <= 4      later sweeps: one lane per vertex, no table (k_move_reg);
 //               first sweep: 4 lanes per vertex
-//   L <= 8      8 lanes, 32 slots
+//   L <= 8      4 lanes, 32 slots
 //   L <= 32     8 lanes, 64 slots
 //   L <= 128    32 lanes, 312 slots
 //   L <= 256    a wavefront, 624 slots
@@ -683,7 +683,7 @@ __global__ __launch_bounds__(FUSED_BS) void k_move_fused(MoveArgs a, FusedMap fm
         break;
         switch (fm.cls[q]) {
             LV_FUSED_CASE(CLS_L4, 4, L4_SLOTS)
-            LV_FUSED_CASE(CLS_L8, 8, L8_SLOTS)
+            LV_FUSED_CASE(CLS_L8, 4, L8_SLOTS)
             LV_FUSED_CASE(CLS_L32, 8, L32_SLOTS)
             LV_FUSED_CASE(CLS_L128, 32, L128_SLOTS)
             LV_FUSED_CASE(CLS_L256, 64, L256_SLOTS)
@@ -1684,7 +1684,7 @@ hipError_t launch_move_class(int cls, bool singleton, bool async, const MoveArgs
 {
     switch (cls) {
     case CLS_L4: return launch_move_t<CLS_L4, 256, 4, L4_SLOTS>(singleton, async, a, s);
-    case CLS_L8: return launch_move_t<CLS_L8, 256, 8, L8_SLOTS>(singleton, async, a, s);
+    case CLS_L8: return launch_move_t<CLS_L8, 256, 4, L8_SLOTS>(singleton, async, a, s);
     case CLS_L32: return launch_move_t<CLS_L32, 256, 8, L32_SLOTS>(singleton, async, a, s);
     case CLS_L128: return launch_move_t<CLS_L128, 256, 32, L128_SLOTS>(singleton, async, a, s);
     case CLS_L256: return launch_move_t<CLS_L256, 256, 64, L256_SLOTS>(singleton, async, a, s);
