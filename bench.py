@@ -849,8 +849,8 @@ def main():
                     help="run one plain device copy of this many MiB before the steps (PMC calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported by this build",
-              file=sys.stderr, flush=True)
+        print(f"bench.py measures one GPU: the library has no multi-GPU path (no sharding, no collectives), "
+              f"so --gpus {args.gpus} is refused", file=sys.stderr, flush=True)
         sys.exit(2)
 
     import numpy as np
