@@ -119,7 +119,7 @@ typedef struct lv_result lv_result; /* per-level labels and statistics, library-
  * Zero fields take the built-in defaults.
  */
 typedef struct lv_tuning {
-    int32_t sub_max;   /* rows up to sub_max entries: groups of 4..32 lanes (<= 128)      */
+    int32_t sub_max;   /* rows up to sub_max entries: groups of 1..32 lanes (<= 128)      */
     int32_t wave_max;  /* rows up to wave_max entries: one wavefront (<= 256)              */
     int32_t block_max; /* rows up to block_max entries: 128..1024-thread groups (<= 8192)  */
                        /* L >  block_max: ceil(L / part_keys) workgroups per vertex, each  */
@@ -186,7 +186,7 @@ typedef struct lv_level_info {
     /* Per move kernel (LV_TIMING): slot 2*(class-1) + (1 for the first sweep
        of a level, where every community is a single vertex); classes 1..10 =
        rows of at most 4, 8, 32, 128, 256, 512, 1024, 2048, 3072 and 8192
-       entries (groups of 4 lanes up to 1024-thread workgroups), 11 =
+       entries (from one lane a row up to 1024-thread workgroups), 11 =
        partition workgroups (with their merge and fallback kernels); slot 22
        = the bucketed mode's scatter pass, which then carries class 11's
        bytes; slot 23 = the commit (labels, volumes, pairs, sweep control);
