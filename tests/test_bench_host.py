@@ -34,3 +34,26 @@ def test_digest_ignores_comments_not_code(tmp_path, monkeypatch):
     assert "L4_SLOTS = 16" in text
     p.write_text(text.replace("L4_SLOTS = 16", "L4_SLOTS = 32"))
     assert bench.kernel_source_digest() != base
+
+
+def test_measured_traffic_scales_by_the_copy_factors(tmp_path, monkeypatch):
+    src = bench.kernel_source_digest()
+    f = tmp_path / "pmc.txt"
+    f.write_text("# header line\n"
+                 f"slot=hub/scatter kernel=k fetch_kib=1000.0 write_kib=300.0 copy_fetch_factor=0.5000 "
+                 f"copy_write_factor=1.0000 src={src}\n"
+                 f"slot=l8k kernel=k2 fetch_kib=10.0 write_kib=0.0 copy_fetch_factor=0.5000 "
+                 f"copy_write_factor=1.0000 src=0000000000000000\n")
+    monkeypatch.setattr(bench, "PMC_FILE", str(f))
+    # (1000 / 0.5 + 300 / 1.0) KiB
+    assert bench.measured_traffic("hub/scatter") == (2000 + 300) * 1024
+    # a record taken from other kernel code, or no record, gives no figure
+    assert bench.measured_traffic("l8k") is None
+    assert bench.measured_traffic("l1k") is None
+    monkeypatch.setattr(bench, "PMC_FILE", str(tmp_path / "absent.txt"))
+    assert bench.measured_traffic("hub/scatter") is None
+
+
+def test_committed_counters_describe_the_current_kernels():
+    # the stored record of the dominant kernel matches the sources it is read with
+    assert bench.measured_traffic("hub/scatter") is not None
